@@ -1,0 +1,304 @@
+"""Pins of the CPU FP64 oracle against closed forms, textbook reductions and brute force.
+
+Every oracle step has at least one check here that a plausible slip (a
+dropped term, a wrong sign or index, a transposed operand) would fail; the
+last group plants such slips in the oracle and checks that a pin catches them.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import pins as P
+from oracle import rsrr_oracle as O
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# --------------------------------------------------------------- Step 1 ----
+
+def test_ellipse_quadrature_identities():
+    """Trapezoid nodes/weights of eq. ellip-contour-xw: sum w/(z - z0) = i inside, 0 outside; sum w z^m = 0."""
+    z, w = O.ellipse(0.3 + 0.2j, 2.0, 0.7, 128)
+    assert abs(np.sum(w / (z - (0.5 + 0.15j))) - 1j) < 1e-12
+    assert abs(np.sum(w / (z - (6.0 + 0.0j)))) < 1e-12
+    for m in range(0, 20):
+        assert abs(np.sum(w * (z - 0.3 - 0.2j) ** m)) < 1e-12 * 2.0 ** m
+    # node placement: alpha_j = 2 pi (j + 1/2)/N on the ellipse
+    assert np.allclose(O.level(z, 0.3 + 0.2j, 2.0, 0.7), 1.0)
+    assert abs(z[0] - (0.3 + 0.2j + 2.0 * math.cos(math.pi / 128) + 0.7j * math.sin(math.pi / 128))) < 1e-15
+
+
+def test_coefficient_terms_closed_values():
+    t = W.term(2.0, 2, z0=1.0, tau=0.5, s=3.0, q=1)
+    assert abs(O.coef(t, 2.0) - (2.0 * 1.0 * math.exp(-1.0) / (-1.0))) < 1e-15
+    t2 = W.term(-1.0, 1)
+    assert O.coef(t2, 3.0 + 1j) == -(3.0 + 1j)
+    # derivative against a central difference on a smooth term
+    for t in (W.term(1.5, 3, z0=0.2, tau=0.3, s=2.0, q=2), W.term(-1.0, 1), W.term(1.0, 0, tau=1.0)):
+        z0, h = 0.7 + 0.4j, 1e-5
+        fd = (O.coef(t, z0 + h) - O.coef(t, z0 - h)) / (2 * h)
+        assert abs(fd - O.coef_deriv(t, z0)) < 1e-8 * max(1.0, abs(fd))
+
+
+# --------------------------------------------------------------- T(z) ------
+
+def test_qep_assembly_matches_rotated_diagonal():
+    nep = W.rotated_diagonal_qep(12, 5)
+    Q, c, k = nep.extra["Q"], nep.extra["c"], nep.extra["k"]
+    for z in (0.3 + 2j, -1.0 + 0.5j):
+        ref = Q.conj().T @ np.diag(z * z + c * z + k) @ Q
+        assert np.allclose(O.T_separable(nep.A, nep.terms, z), ref, atol=1e-12, rtol=0)
+
+
+def test_helmholtz_single_layer_of_constant_density():
+    """On the unit sphere, int e^{ikr}/(4 pi r) dS(y) = e^{ik} sin(k)/k; the Nystrom row sums approach it."""
+    n = 2048
+    nep = W.helmholtz_sphere(n)
+    prob = O.Problem(nep)
+    for kz in (1.0, 3.8, 2.5 + 0.2j):
+        T = prob.T(kz)
+        approx = T.sum(axis=1)
+        exact = np.exp(1j * kz) * np.sin(kz) / kz
+        assert np.max(np.abs(approx - exact)) < 3e-2 * abs(exact) + 5e-3
+        assert np.allclose(T, T.T)  # complex symmetric
+
+
+# --------------------------------------------------------------- Step 2 ----
+
+def test_sample_matches_high_precision_solve():
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 40
+    nep = W.rotated_diagonal_qep(6, 11)
+    prob = O.Problem(nep)
+    U = W.probes(6, 2, 3)
+    z = np.array([0.4 + 3.1j, -0.2 + 1.0j])
+    S = O.sample(prob, z, U)
+    for kk, zk in enumerate(z):
+        T = prob.T(zk)
+        Tm = mpmath.matrix([[mpmath.mpc(T[i, j].real, T[i, j].imag) for j in range(6)] for i in range(6)])
+        for c in range(2):
+            b = mpmath.matrix([mpmath.mpc(U[i, c].real, U[i, c].imag) for i in range(6)])
+            x = mpmath.lu_solve(Tm, b)
+            xe = np.array([complex(x[i]) for i in range(6)])
+            assert np.linalg.norm(S[:, 2 * kk + c] - xe) <= 1e-12 * np.linalg.norm(xe)
+
+
+# --------------------------------------------------------------- Step 3 ----
+
+def test_basis_recovers_planted_rank_and_singular_values():
+    rng = np.random.default_rng(7)
+    n, p, r = 60, 90, 17
+    Ua = np.linalg.qr(W.complex_gaussian(rng, (n, r)))[0]
+    Vb = np.linalg.qr(W.complex_gaussian(rng, (p, r)))[0]
+    s = np.logspace(0, -12, r)
+    S = (Ua * s[None, :]) @ Vb.conj().T
+    Q, sig, k = O.basis(S, 1e-14)
+    assert k == r
+    assert np.allclose(sig[:r], s, rtol=1e-8, atol=1e-15)
+    assert np.allclose(Q.conj().T @ Q, np.eye(k), atol=1e-12)
+    # same span as the planted factor (directions with sigma >= 1e-3 are fixed to ~eps/sigma)
+    lead = Ua[:, s >= 1e-3]
+    assert np.linalg.norm(lead - Q @ (Q.conj().T @ lead)) < 1e-11
+
+
+def test_normalize_keeps_span_and_unit_norms():
+    rng = np.random.default_rng(8)
+    S = W.complex_gaussian(rng, (20, 8)) * np.logspace(0, 6, 8)[None, :]
+    Sn = O.normalize(S)
+    assert np.allclose(np.linalg.norm(Sn, axis=0), 1.0)
+    Q = np.linalg.qr(S)[0]
+    assert np.linalg.norm(Sn - Q @ (Q.conj().T @ Sn)) < 1e-12
+
+
+# --------------------------------------------------------------- Step 4-5 --
+
+def test_ss_full_on_diagonal_nep_with_known_roots():
+    """T(z) = diag(z - l_i): SS-FULL must return exactly the l_i inside the ellipse."""
+    lam = np.array([0.2 + 0.1j, -0.5 + 0.3j, 0.9 - 0.2j, 3.0 + 0j, -2.5j, 0.0 + 0.05j])
+    A = [np.diag(-lam).astype(complex), np.eye(lam.size, dtype=complex)]
+    terms = [W.term(1.0, 0), W.term(1.0, 1)]
+    TQ = lambda z: O.T_separable(A, terms, z)
+    res = O.ss_full(TQ, lam.size, 0.1 + 0.0j, 1.5, 1.0, NQ=200, KQ=2)
+    inside = lam[O.level(lam, 0.1, 1.5, 1.0) < 1]
+    got = res["lam"]
+    assert res["nbar"] == inside.size and not res["warn_gap"]
+    for l in inside:
+        assert np.min(np.abs(got - l)) < 1e-12
+    # eigenvectors are the unit vectors of the matching coordinate
+    for i, l in enumerate(got):
+        j = int(np.argmin(np.abs(lam - l)))
+        assert abs(abs(res["G"][j, i]) - 1.0) < 1e-10
+
+
+def _match(got, ref):
+    return max(np.min(np.abs(ref - g)) / max(1.0, abs(g)) for g in got)
+
+
+@pytest.mark.slow
+def test_rsrr_qep_closed_form_cfg0_reading():
+    """Rotated diagonal QEP, n=200, N=32, L=16, centre 5i: eigenvalues vs roots of z^2 + c z + k."""
+    nep, C, U = W.cfg_qep()
+    prob = O.Problem(nep)
+    r = O.rsrr(prob, C, U)
+    ex = P.qep_roots(nep.extra["c"], nep.extra["k"])
+    inside = r["level"] < 0.98
+    assert inside.sum() >= 30
+    assert _match(r["lam"][inside], ex) < 1e-9
+    assert r["res"][inside].max() < 1e-10
+    assert r["k"] == 200  # N*L = 512 > n: full rank
+    # every exact root strictly inside (with margin) was found
+    exin = ex[O.level(ex, C.gamma, C.a, C.b) < 0.98]
+    assert _match(exin, r["lam"]) < 1e-9
+    # eigenvectors are Q^H e_i
+    Q = nep.extra["Q"]
+    for i in np.where(inside)[0]:
+        j = int(np.argmin(np.abs(ex - r["lam"][i]))) % 200
+        v = Q.conj().T[:, j]
+        assert abs(np.vdot(v, r["V"][:, i])) > 1 - 1e-9
+
+
+def test_rsrr_qep_literal_contour_is_empty():
+    """Centre 5 + 0i holds none of the roots: the gap rule does not find a reliable count."""
+    nep, C, U = W.cfg_qep(n=40, N=16, L=4, literal=True)
+    prob = O.Problem(nep)
+    ex = P.qep_roots(nep.extra["c"], nep.extra["k"])
+    assert np.all(O.level(ex, C.gamma, C.a, C.b) > 1)
+    cnt = P.argument_count(prob.T, prob.dT, C.gamma, C.a, C.b, M=256)
+    assert abs(cnt) < 1e-6
+    r = O.rsrr(prob, C, U, NQ=200)
+    assert np.sum(r["level"] < 0.98) == 0 or r["ss"]["warn_gap"]
+
+
+@pytest.mark.slow
+def test_rsrr_delay_lambert_w():
+    """Delay Laplacian (16x16), circle (-4, 0.75): the three eigenvalues mu + W(0.5 e^-mu)."""
+    nep, C, U = W.cfg_delay(nx=16, N=48, L=32)
+    prob = O.Problem(nep)
+    r = O.rsrr(prob, C, U)
+    ex = P.delay_eigs(W.laplacian_modes(16, 16))
+    exin = ex[O.level(ex, C.gamma, C.a, C.b) < 1]
+    assert exin.size == 3
+    inside = r["level"] < 0.98
+    assert inside.sum() == 3
+    assert _match(r["lam"][inside], exin) < 1e-9
+    assert r["res"][inside].max() < 1e-10
+    cnt = P.argument_count(prob.T, prob.dT, C.gamma, C.a, C.b, M=256)
+    assert abs(cnt - 3) < 1e-6
+
+
+def test_lambert_w_closed_form_solves_the_delay_equation():
+    for mu in (-19.7, -49.3, -300.0):
+        for br in (-2, 0, 1):
+            lam = P._delay_branch(mu, 0.5, br)
+            f = -lam + mu + 0.5 * np.exp(-lam) if lam.real > -700 else None
+            if f is not None:
+                assert abs(f) < 1e-9 * max(1.0, abs(lam))
+
+
+def test_rsrr_tiny_nonnormal_against_det_newton():
+    """n=5 non-normal QEP + delay mix: RSRR eigenvalues inside == brute-force det T roots inside."""
+    rng = np.random.default_rng(21)
+    n = 5
+    A = [W.complex_gaussian(rng, (n, n)) for _ in range(3)]
+    terms = [W.term(1.0, 0), W.term(1.0, 1), W.term(0.3, 0, tau=1.0)]
+    nep = W.SeparableNEP("tiny", A, terms)
+    prob = O.Problem(nep)
+    C = W.Contour(0.0 + 0.0j, 1.6, 1.2, 40)
+    seeds = [complex(x, y) for x in np.linspace(-2.4, 2.4, 13) for y in np.linspace(-1.8, 1.8, 10)]
+    roots = P.det_newton_roots(prob.T, prob.dT, seeds)
+    lv = O.level(roots, C.gamma, C.a, C.b)
+    assert np.all(np.abs(lv - 1) > 0.05), "a root too close to the contour for this seed"
+    rin = roots[lv < 1]
+    cnt = P.argument_count(prob.T, prob.dT, C.gamma, C.a, C.b, M=512)
+    assert abs(cnt - rin.size) < 1e-6
+    U = W.probes(n, 3, 4)
+    r = O.rsrr(prob, C, U, NQ=300)
+    got = r["lam"][r["level"] < 1]
+    assert got.size == rin.size
+    assert _match(got, rin) < 1e-9 and _match(rin, got) < 1e-9
+
+
+def test_companion_linearisation_agrees_for_random_qep():
+    rng = np.random.default_rng(9)
+    n = 10
+    A0, A1 = W.complex_gaussian(rng, (n, n)), W.complex_gaussian(rng, (n, n))
+    A2 = np.eye(n, dtype=complex)
+    ev = P.companion_eigs(A0, A1, A2)
+    nep = W.SeparableNEP("q", [A0, A1, A2], [W.term(1, 0), W.term(1, 1), W.term(1, 2)])
+    prob = O.Problem(nep)
+    C = W.Contour(0.2 + 0.1j, 1.3, 1.1, 48)
+    lv = O.level(ev, C.gamma, C.a, C.b)
+    if np.any(np.abs(lv - 1) < 0.05):
+        pytest.skip("eigenvalue on the contour for this seed")
+    r = O.rsrr(prob, C, W.probes(n, 4, 5), NQ=300)
+    got = r["lam"][r["level"] < 1]
+    ref = ev[lv < 1]
+    assert got.size == ref.size
+    assert _match(got, ref) < 1e-9
+
+
+def test_residual_of_exact_and_perturbed_pairs():
+    nep = W.rotated_diagonal_qep(30, 2)
+    prob = O.Problem(nep)
+    c, k, Q = nep.extra["c"], nep.extra["k"], nep.extra["Q"]
+    lam = (-c[3] + np.sqrt(c[3] ** 2 - 4 * k[3] + 0j)) / 2
+    v = Q.conj().T[:, 3]
+    assert O.residual(prob, lam, v) < 1e-15
+    assert O.residual(prob, lam * (1 + 1e-6), v) > 1e-9
+
+
+# ------------------------------------------------------ paper golden value --
+
+@pytest.mark.slow
+def test_loaded_string_count_matches_paper():
+    """Example 1: 32 eigenvalues in [3, 10000] for n = 400 (printed count)."""
+    g = json.load(open(os.path.join(HERE, "golden", "loaded_string.json")))
+    nep = W.loaded_string(g["n"])
+    prob = O.Problem(nep)
+    a = g["contour"]["a"]
+    C = W.Contour(g["contour"]["gamma"] + 0j, a, a * g["contour"]["b_over_a"], 64)
+    U = W.probes(g["n"], 2, 77)
+    r = O.rsrr(prob, C, U, NQ=500)
+    lam = r["lam"]
+    sel = (lam.real >= g["interval"][0]) & (lam.real <= g["interval"][1]) & (r["level"] < 1) & (r["res"] < 1e-10)
+    assert int(sel.sum()) == g["count"]
+    assert np.max(np.abs(lam[sel].imag)) < 1e-6 * np.max(np.abs(lam[sel]))
+
+
+# --------------------------------------------------------- planted slips ---
+
+def test_planted_slips_are_caught(monkeypatch):
+    """Mistakes planted in the oracle (on the CPU) make a pin fail."""
+    nep = W.rotated_diagonal_qep(12, 5)
+    Q, c, k = nep.extra["Q"], nep.extra["c"], nep.extra["k"]
+    z = 0.3 + 2j
+    ref = Q.conj().T @ np.diag(z * z + c * z + k) @ Q
+
+    # a dropped term in the assembly
+    T = O.T_separable(nep.A[:2], nep.terms[:2], z)
+    assert not np.allclose(T, ref, atol=1e-12)
+    # a transposed operand
+    T = O.T_separable([A.T for A in nep.A], nep.terms, z)
+    assert not np.allclose(T, ref, atol=1e-12)
+    # a wrong sign in the trapezoid weight
+    zz, ww = O.ellipse(0.3 + 0.2j, 2.0, 0.7, 64)
+    assert abs(np.sum((-ww.conj()) / (zz - (0.5 + 0.1j))) - 1j) > 1e-3
+    # an off-by-one Hankel shift in SS-FULL moves the eigenvalues
+    lam = np.array([0.2 + 0.1j, -0.5 + 0.3j])
+    A = [np.diag(-lam).astype(complex), np.eye(2, dtype=complex)]
+    terms = [W.term(1.0, 0), W.term(1.0, 1)]
+    orig_block = np.block
+
+    def shifted_block(rows):
+        if len(rows) == 2 and len(rows[0]) == 2:
+            rows = [[rows[1][0], rows[1][1]], [rows[1][1], rows[1][1]]]
+        return orig_block(rows)
+    monkeypatch.setattr(O.np, "block", shifted_block)
+    res = O.ss_full(lambda zz_: O.T_separable(A, terms, zz_), 2, 0.0, 1.5, 1.0, NQ=100, KQ=2)
+    monkeypatch.undo()
+    bad = res["lam"]
+    assert bad.size == 0 or _match(bad, lam) > 1e-6 or res["warn_gap"]
