@@ -1,0 +1,210 @@
+/*
+ * rsrr.h -- C ABI of the MI355X resolvent-sampling library (RSRR hot path).
+ *
+ * Method: the resolvent sampling based Rayleigh-Ritz method of Xiao, Zhang,
+ * Huang and Sakurai for the nonlinear eigenvalue problem T(lambda) v = 0
+ * (Sec. 1, eq. gnep).  The library owns the steps of the RSRR algorithm
+ * (Sec. 4.3) that follow the choice of contour, points and probes:
+ *
+ *   rsrr_sample   Step 2 and eq. hatS: S = [T(z_0)^-1 U, ..., T(z_{N-1})^-1 U]
+ *   rsrr_basis    Step 3: normalise the columns of S (Sec. 4.2) and keep the
+ *                 left singular vectors with sigma > delta*sigma_1
+ *   rsrr_project  Step 4, first half / eq. Ts-NEP: T_Q(z) = Q^H T(z) Q
+ *   rsrr_solve    Step 4, second half, and Step 5: SS-FULL (Sec. 3.3) on the
+ *                 projected NEP, lift v = Q g, residuals
+ *
+ * plus rsrr_contour for the ellipse nodes and trapezoid weights of Sec. 5.1
+ * (eq. ellip-contour, eq. ellip-contour-xw).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Complex numbers are interleaved pairs of doubles (re, im).  Matrices are
+ *   column-major with an explicit leading dimension counted in complex
+ *   elements.
+ * - "device" pointers are HIP device memory on the context's device; "host"
+ *   pointers are ordinary host memory.  Every buffer is owned by the caller;
+ *   the library never frees or keeps a caller pointer after a call returns.
+ * - Work is enqueued on the context's stream.  Calls that return host
+ *   results (point info, k, sigma, eigenvalues) synchronise that stream
+ *   before returning; device outputs are complete when the call returns.
+ * - Return value: RSRR_OK (0); a negative value -i names the i-th argument
+ *   (1-based) as invalid, and nothing was enqueued; a positive value is a
+ *   numerical or runtime condition listed below.
+ * - One context per host thread.  Calls on one context must not overlap.
+ */
+#ifndef RSRR_H
+#define RSRR_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define RSRR_API __attribute__((visibility("default")))
+#else
+#define RSRR_API
+#endif
+
+typedef int rsrr_status;
+
+enum {
+    RSRR_OK = 0,
+    RSRR_ESINGULAR = 1,      /* an exact zero pivot: T(z_k) singular in working precision      */
+    RSRR_WARN_FALLBACK = 2,  /* refinement stalled at some point; that point was redone in FP64 */
+    RSRR_WARN_GAP = 3,       /* SS-FULL: largest singular-value gap below tol_gap (eq. gap)     */
+    RSRR_ENOMEM = 4,         /* device allocation of workspace failed                         */
+    RSRR_EDEVICE = 5,        /* a HIP runtime call failed                                      */
+    RSRR_ENOTCONV = 6,       /* an iterative eigen/singular-value solve did not converge        */
+    RSRR_ENAN = 7            /* a NaN or Inf reached a pivot                                   */
+};
+
+/* Kinds of T(z).  SEPARABLE: T(z) = sum_j f_j(z) A_j (the form of every
+ * example of Sec. 2.1 except the boundary-element kernels).  HELMHOLTZ: the
+ * single-layer Nystrom matrix of a point set on a surface (kernel G of
+ * eq. nyes): T_ij = w e^{i z r_ij} / (4 pi r_ij), T_ii = sqrt(w/pi)/2 + i z w/(4 pi). */
+enum { RSRR_T_SEPARABLE = 0, RSRR_T_HELMHOLTZ = 1 };
+
+/* Arithmetic of the sampling step.  C128: complex FP64 LU and solves.
+ * C64_IR: complex FP32 LU on the matrix cores, then iterative refinement
+ * against FP64 residuals until FP64 backward error; a point that does not
+ * converge is redone with the C128 path (flagged in rsrr_point_info). */
+enum { RSRR_PREC_C128 = 0, RSRR_PREC_C64_IR = 1 };
+
+/* One scalar coefficient f(z) = c (z - z0)^p exp(-tau z) / (z - s)^q. */
+typedef struct {
+    double c_re, c_im;
+    int p;
+    double z0_re, z0_im;
+    double tau;
+    double s_re, s_im;
+    int q;
+} rsrr_term;
+
+/* The NEP T(z).
+ * SEPARABLE: n, J, A (device, J matrices n x n, matrix j at A + 2*j*lda*n
+ *            doubles), lda >= n, terms (host, J entries).
+ * HELMHOLTZ: n, points (device, n x 3 doubles, x y z of point i at
+ *            points + 3*i), w (quadrature weight per point). */
+typedef struct {
+    int kind;
+    int n;
+    int J;
+    const double *A;
+    int lda;
+    const rsrr_term *terms;
+    const double *points;
+    double w;
+} rsrr_nep;
+
+/* Per sampling point diagnostics of rsrr_sample. */
+typedef struct {
+    int info;          /* 0, or i+1 when U(i,i) == 0 exactly (getrf semantics)       */
+    int ir_iters;      /* refinement corrections applied (0 for C128)               */
+    int fallback;      /* 1 when the point was redone on the C128 path               */
+    int pad;
+    double resid;      /* max over columns of ||u_c - T(z_k) x_c||_2 / ||u_c||_2, FP64 */
+} rsrr_point_info;
+
+/* Diagnostics of rsrr_solve. */
+typedef struct {
+    int nbar;          /* eigenvalue count from the gap rule (eq. gap)    */
+    int warn_gap;      /* 1 when g_max < tol_gap                          */
+    double gmax;       /* largest sigma_j / sigma_{j+1} of H              */
+    int n_sigma;       /* number of singular values of H written         */
+    int pad;
+} rsrr_solve_info;
+
+typedef struct rsrr_ctx rsrr_ctx;
+
+/* Create a context on HIP device `device` that enqueues on `stream` (a
+ * hipStream_t; NULL = the null stream).  Workspace is allocated lazily and
+ * owned by the context.  Errors: -1 ctx NULL, -2 bad device, RSRR_EDEVICE. */
+RSRR_API rsrr_status rsrr_create(rsrr_ctx **ctx, int device, void *stream);
+
+/* Release the context and its workspace.  Errors: -1 ctx NULL. */
+RSRR_API rsrr_status rsrr_destroy(rsrr_ctx *ctx);
+
+/* Ellipse nodes and trapezoid weights (Sec. 5.1, eq. ellip-contour-xw):
+ * z_j = gamma + a cos(t_j) + i b sin(t_j), w_j = (-a sin t_j + i b cos t_j)/N,
+ * t_j = 2 pi (j + 1/2)/N.  z, w: host, 2N doubles each (w may be NULL).
+ * Errors: -3/-4 a, b <= 0; -5 N < 1; -6 z NULL. */
+RSRR_API rsrr_status rsrr_contour(double gamma_re, double gamma_im, double a, double b, int N,
+                         double *z, double *w);
+
+/* Resolvent sampling (RSRR Step 2, eq. hatS).  For each of the N points z_k
+ * (host, 2N doubles): assemble T(z_k), factor it by blocked LU with partial
+ * pivoting, and solve for the L probe columns U (device, n x L, ldu >= n).
+ * Block k of S (device, n x N*L, lds >= n) receives X_k = T(z_k)^-1 U in
+ * columns k*L .. k*L+L-1.  info: host, N entries (may be NULL).
+ * prec: RSRR_PREC_C128 or RSRR_PREC_C64_IR.
+ * Status: RSRR_ESINGULAR if any point had an exact zero pivot (its block of S
+ * is then not meaningful), RSRR_WARN_FALLBACK if any point was redone in FP64.
+ * Errors: -2 nep invalid, -3 N < 1, -4 z NULL, -5 U NULL, -6 L < 1, -7 ldu < n,
+ * -8 prec, -9 S NULL, -10 lds < n. */
+RSRR_API rsrr_status rsrr_sample(rsrr_ctx *ctx, const rsrr_nep *nep, int N, const double *z,
+                        const double *U, int L, int ldu, int prec,
+                        double *S, int lds, rsrr_point_info *info);
+
+/* Basis (RSRR Step 3, Sec. 4.2-4.3).  S (device, n x NL, lds) is normalised
+ * in place to unit column norms, then its singular values sigma (host,
+ * min(n, NL) doubles, descending; may be NULL) and the number k of them above
+ * delta*sigma_1 are computed in FP64; the first min(k, kmax) left singular
+ * vectors are written to Q (device, n x kmax, ldq >= n).  *k (host) receives
+ * k even when k > kmax.
+ * Errors: -2 n < 1, -3 NL < 1, -4 S NULL, -5 lds < n, -6 delta not in (0,1),
+ * -7 Q NULL, -8 ldq < n, -9 kmax < 1, -10 k NULL.  RSRR_ENOTCONV if the
+ * one-sided Jacobi SVD did not converge. */
+RSRR_API rsrr_status rsrr_basis(rsrr_ctx *ctx, int n, int NL, double *S, int lds, double delta,
+                       double *Q, int ldq, int kmax, int *k, double *sigma);
+
+/* Projection (RSRR Step 4, eq. Ts-NEP): T_Q(z) = Q^H T(z) Q with Q (device,
+ * n x k, ldq).  SEPARABLE: AQ_j = Q^H A_j Q for each j and the same terms.
+ * HELMHOLTZ: T(z) is expanded about gamma (host, 2 doubles) in powers of
+ * (z - gamma), with the degree chosen so that the remainder is below 1e-17
+ * relative for |z - gamma| <= radius; AQ_p = Q^H T_p Q, term p = (z-gamma)^p.
+ * AQ: device, max_terms matrices k x k (matrix j at AQ + 2*j*k*k doubles).
+ * J_eff (host) receives the number of matrices written; terms_out (host,
+ * max_terms entries) their coefficients.
+ * Errors: -2 nep, -3 Q NULL, -4 ldq < n, -5 k < 1, -6 gamma NULL,
+ * -7 radius <= 0, -8 AQ NULL, -9 max_terms too small, -10 J_eff NULL,
+ * -11 terms_out NULL. */
+RSRR_API rsrr_status rsrr_project(rsrr_ctx *ctx, const rsrr_nep *nep, const double *Q, int ldq, int k,
+                         const double *gamma, double radius, double *AQ, int max_terms,
+                         int *J_eff, rsrr_term *terms_out);
+
+/* Projected NEP solve (RSRR Steps 4-5 via SS-FULL, Sec. 3.3).  T_Q(z) =
+ * sum_j f_j(z) AQ_j (device AQ, J_eff matrices k x k; host terms).  SS-FULL
+ * on the ellipse (gamma, a, b) with NQ trapezoid nodes and KQ moment blocks:
+ * moments of T_Q^-1 in zeta = (z - gamma)/max(a, b), block Hankel H and H^<
+ * (eq. HH), SVD of H, count by the largest gap (eq. gap), reduced matrix
+ * (eq. A), its eigenpairs, lift g = M W0 Sigma0^-1 b and v = Q g.
+ * Outputs: count (host) eigenvalues lambda (host, 2*max_eigs doubles),
+ * eigenvectors V (device, n x max_eigs, ldv >= n, unit 2-norm; may be NULL),
+ * residuals resid (host, max_eigs; ||T(lambda)v||_2 / (||T(lambda)||_1 ||v||_2)
+ * in FP64 against the full nep; may be NULL only if V is NULL), the level of
+ * each eigenvalue is for the caller to compute.  sigma_H (host, KQ*k doubles,
+ * may be NULL) receives the singular values of H.  sinfo (host, may be NULL).
+ * Status RSRR_WARN_GAP when g_max < tol_gap (results are best effort).
+ * Errors: -2 nep, -3 k < 1, -4 AQ NULL, -5 J_eff < 1, -6 terms NULL,
+ * -7 Q NULL, -8 ldq, -9 gamma NULL, -10 a, -11 b, -12 NQ < 2*KQ+1,
+ * -13 KQ < 1, -14 tol_gap, -15 max_eigs < 1, -16 lambda NULL, -17 ldv,
+ * -18 count NULL. */
+RSRR_API rsrr_status rsrr_solve(rsrr_ctx *ctx, const rsrr_nep *nep, int k, const double *AQ, int J_eff,
+                       const rsrr_term *terms, const double *Q, int ldq,
+                       const double *gamma, double a, double b, int NQ, int KQ, double tol_gap,
+                       int max_eigs, double *lambda, double *V, int ldv, double *resid,
+                       int *count, double *sigma_H, rsrr_solve_info *sinfo);
+
+/* Phase timings (milliseconds, device events) of the last rsrr_sample call:
+ * t[0] assembly, t[1] LU factorisation, t[2] solves (getrs, all iterations),
+ * t[3] FP64 residuals, t[4] total.  t: host, 5 doubles.  Errors: -2 t NULL. */
+RSRR_API rsrr_status rsrr_last_timings(rsrr_ctx *ctx, double *t);
+
+/* Library version string (static storage). */
+RSRR_API const char *rsrr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSRR_H */

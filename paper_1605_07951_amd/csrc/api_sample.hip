@@ -1,0 +1,458 @@
+// C ABI: context, contour nodes and resolvent sampling (RSRR Steps 1-2).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "ctx.h"
+#include "kernels.h"
+
+using namespace rsrr;
+
+void* ws_get(rsrr_ctx* c, int s, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    if (c->ws_size[s] >= bytes) return c->ws[s];
+    if (c->ws[s]) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(c->ws[s]);
+        c->ws[s] = nullptr;
+        c->ws_size[s] = 0;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    c->ws[s] = p;
+    c->ws_size[s] = bytes;
+    return p;
+}
+
+zd term_eval(const rsrr_term& t, zd z)
+{
+    zd v(t.c_re, t.c_im);
+    if (t.p) v *= std::pow(z - zd(t.z0_re, t.z0_im), t.p);
+    if (t.tau != 0.0) v *= std::exp(-t.tau * z);
+    if (t.q) v /= std::pow(z - zd(t.s_re, t.s_im), t.q);
+    return v;
+}
+
+extern "C" {
+
+const char* rsrr_version(void) { return "rsrr-mi355x 0.1 (gfx950)"; }
+
+rsrr_status rsrr_create(rsrr_ctx** ctx, int device, void* stream)
+{
+    if (!ctx) return -1;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess) return RSRR_EDEVICE;
+    if (device < 0 || device >= ndev) return -2;
+    RSRR_HIP(hipSetDevice(device));
+    rsrr_ctx* c = new rsrr_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    for (auto& e : c->ev)
+        if (hipEventCreate(&e) != hipSuccess) { delete c; return RSRR_EDEVICE; }
+    *ctx = c;
+    return RSRR_OK;
+}
+
+rsrr_status rsrr_destroy(rsrr_ctx* c)
+{
+    if (!c) return -1;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (int s = 0; s < WS_COUNT; ++s)
+        if (c->ws[s]) (void)hipFree(c->ws[s]);
+    for (auto& e : c->ev) (void)hipEventDestroy(e);
+    delete c;
+    return RSRR_OK;
+}
+
+rsrr_status rsrr_contour(double gre, double gim, double a, double b, int N, double* z, double* w)
+{
+    if (!(a > 0)) return -3;
+    if (!(b > 0)) return -4;
+    if (N < 1) return -5;
+    if (!z) return -6;
+    for (int j = 0; j < N; ++j) {
+        const double t = 2.0 * M_PI * (j + 0.5) / N;
+        z[2 * j] = gre + a * std::cos(t);
+        z[2 * j + 1] = gim + b * std::sin(t);
+        if (w) {
+            w[2 * j] = -a * std::sin(t) / N;
+            w[2 * j + 1] = b * std::cos(t) / N;
+        }
+    }
+    return RSRR_OK;
+}
+
+rsrr_status rsrr_last_timings(rsrr_ctx* c, double* t)
+{
+    if (!c) return -1;
+    if (!t) return -2;
+    for (int i = 0; i < 5; ++i) t[i] = c->timings[i];
+    return RSRR_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// sampling driver
+// ---------------------------------------------------------------------------
+
+namespace {
+
+static int ld_pad(int n) { return (n + 63) / 64 * 64; }
+
+struct PhaseTimer {
+    rsrr_ctx* c;
+    hipEvent_t a, b;
+    double* acc;
+    PhaseTimer(rsrr_ctx* c_, double* acc_) : c(c_), acc(acc_)
+    {
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+        (void)hipEventRecord(a, c->stream);
+    }
+    void stop()
+    {
+        (void)hipEventRecord(b, c->stream);
+        (void)hipEventSynchronize(b);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        *acc += ms;
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        a = b = nullptr;
+    }
+    ~PhaseTimer()
+    {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+struct SampleBufs {
+    void* Tlu; double2* Tres; int* ipiv; int2* perm; int2* tperm; int* info; double2* coef; double* frobp;
+    double* frob; float2* D64; double2* R; double* norms; int* active; double2* zdev;
+    int ld, np; long sT, sP, sPerm, sTP, nparts;
+};
+
+// Per-point bytes of the sampling buffers.
+static size_t per_point_bytes(int n, int L, int prec)
+{
+    const size_t ld = ld_pad(n);
+    const size_t np = (n + MAX_NB - 1) / MAX_NB;
+    size_t b = ld * n * 16;                         // FP64 copy for residuals
+    b += ld * n * (prec == RSRR_PREC_C128 ? 16 : 8);  // LU input
+    b += (size_t)n * 4 + np * 2 * MAX_NB * 8 + 8 * 2 * MAX_NB * 8 + 16;
+    b += ((size_t)n * n + 255) / 256 * 8 + 8;
+    b += (size_t)ld * L * (8 + 16) + (size_t)L * 16;
+    return b;
+}
+
+static rsrr_status alloc_bufs(rsrr_ctx* c, int n, int L, int J, int prec, int B, SampleBufs& s)
+{
+    s.ld = ld_pad(n);
+    s.np = (n + MAX_NB - 1) / MAX_NB;
+    s.sT = (long)s.ld * n;
+    s.sP = n;
+    s.sPerm = (long)s.np * 2 * MAX_NB;
+    s.sTP = 8L * 2 * MAX_NB;
+    s.nparts = ((long)n * n + 255) / 256;
+    const size_t esz = prec == RSRR_PREC_C128 ? 16 : 8;
+    s.Tlu = ws_get(c, WS_TLU, (size_t)B * s.sT * esz);
+    s.Tres = (double2*)ws_get(c, WS_TRES, (size_t)B * s.sT * 16);
+    s.ipiv = (int*)ws_get(c, WS_IPIV, (size_t)B * s.sP * 4);
+    s.perm = (int2*)ws_get(c, WS_PERM, (size_t)B * s.sPerm * 8);
+    s.tperm = (int2*)ws_get(c, WS_TPERM, (size_t)B * s.sTP * 8);
+    s.info = (int*)ws_get(c, WS_INFO, (size_t)B * 4);
+    s.coef = (double2*)ws_get(c, WS_COEF, (size_t)std::max(J, 1) * B * 16);
+    s.frobp = (double*)ws_get(c, WS_FROBP, (size_t)B * s.nparts * 8);
+    s.frob = (double*)ws_get(c, WS_FROB, (size_t)B * 8);
+    s.D64 = (float2*)ws_get(c, WS_D64, (size_t)B * s.ld * L * 8);
+    s.R = (double2*)ws_get(c, WS_R, (size_t)B * s.ld * L * 16);
+    s.norms = (double*)ws_get(c, WS_NORM, (size_t)3 * B * L * 8);
+    s.active = (int*)ws_get(c, WS_ACTIVE, (size_t)B * 4);
+    s.zdev = (double2*)ws_get(c, WS_Z, (size_t)B * 16);
+    if (!s.Tlu || !s.Tres || !s.ipiv || !s.perm || !s.tperm || !s.info || !s.coef || !s.frobp || !s.frob ||
+        !s.D64 || !s.R || !s.norms || !s.active || !s.zdev)
+        return RSRR_ENOMEM;
+    return RSRR_OK;
+}
+
+// Assemble T(z_k) for the batch into the LU buffer (c64 or c128) and the FP64 copy.
+static rsrr_status assemble_batch(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, int B, int prec, SampleBufs& s)
+{
+    const int n = nep->n;
+    float2* T64 = prec == RSRR_PREC_C64_IR ? (float2*)s.Tlu : nullptr;
+    double2* Tlu128 = prec == RSRR_PREC_C128 ? (double2*)s.Tlu : nullptr;
+    if (nep->kind == RSRR_T_SEPARABLE) {
+        std::vector<double2> cf((size_t)nep->J * B);
+        for (int j = 0; j < nep->J; ++j)
+            for (int k = 0; k < B; ++k) {
+                zd f = term_eval(nep->terms[j], z[k]);
+                cf[(size_t)j * B + k] = make_double2(f.real(), f.imag());
+            }
+        RSRR_HIP(hipMemcpyAsync(s.coef, cf.data(), cf.size() * 16, hipMemcpyHostToDevice, c->stream));
+        RSRR_HIP(hipStreamSynchronize(c->stream));
+        RSRR_HIP(assemble_separable(c->stream, n, nep->J, (const double2*)nep->A, nep->lda, s.coef, B, T64, s.ld,
+                                    s.sT, s.Tres, s.ld, s.sT, s.frobp, s.frob));
+        if (Tlu128) RSRR_HIP(copy_c128(c->stream, n, n, s.Tres, s.ld, s.sT, Tlu128, s.ld, s.sT, B));
+    } else {
+        std::vector<double2> zz(B);
+        for (int k = 0; k < B; ++k) zz[k] = make_double2(z[k].real(), z[k].imag());
+        RSRR_HIP(hipMemcpyAsync(s.zdev, zz.data(), (size_t)B * 16, hipMemcpyHostToDevice, c->stream));
+        RSRR_HIP(hipStreamSynchronize(c->stream));
+        RSRR_HIP(assemble_helmholtz(c->stream, n, nep->points, nep->w, s.zdev, B, T64, s.ld, s.sT, s.Tres, s.ld, s.sT,
+                                    s.frobp, s.frob));
+        if (Tlu128) RSRR_HIP(copy_c128(c->stream, n, n, s.Tres, s.ld, s.sT, Tlu128, s.ld, s.sT, B));
+    }
+    return RSRR_OK;
+}
+
+// R_k = U - T_k X_k (FP64) and the column norms of R_k and X_k (host copies).
+static rsrr_status residual_batch(rsrr_ctx* c, int n, int L, const double2* U, int ldu, double2* X, int ldx, long sX,
+                                  int B, SampleBufs& s, std::vector<double>& rn, std::vector<double>& xn)
+{
+    RSRR_HIP(bcast_c128(c->stream, n, L, U, ldu, s.R, s.ld, (long)s.ld * L, B));
+    RSRR_HIP(zgemm(c->stream, 0, 0, n, L, n, -1.0, s.Tres, s.ld, s.sT, X, ldx, sX, 1.0, s.R, s.ld, (long)s.ld * L, B));
+    RSRR_HIP(colnorms(c->stream, n, L, s.R, s.ld, (long)s.ld * L, s.norms, B));
+    RSRR_HIP(colnorms(c->stream, n, L, X, ldx, sX, s.norms + (size_t)B * L, B));
+    rn.resize((size_t)B * L);
+    xn.resize((size_t)B * L);
+    RSRR_HIP(hipMemcpyAsync(rn.data(), s.norms, (size_t)B * L * 8, hipMemcpyDeviceToHost, c->stream));
+    RSRR_HIP(hipMemcpyAsync(xn.data(), s.norms + (size_t)B * L, (size_t)B * L * 8, hipMemcpyDeviceToHost, c->stream));
+    RSRR_HIP(hipStreamSynchronize(c->stream));
+    return RSRR_OK;
+}
+
+static rsrr_status sample_batch(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, int B, const double2* U, int L, int ldu,
+                                const std::vector<double>& un, int prec, double2* S, int lds,
+                                rsrr_point_info* info, int* any_singular, int* any_fallback, int* any_nan)
+{
+    const int n = nep->n;
+    SampleBufs s;
+    rsrr_status st = alloc_bufs(c, n, L, nep->J, prec, B, s);
+    if (st) return st;
+    const long sX = (long)L * lds;
+    double* tm = c->timings;
+
+    {
+        PhaseTimer t(c, &tm[0]);
+        st = assemble_batch(c, nep, z, B, prec, s);
+        if (st) return st;
+        t.stop();
+    }
+    std::vector<int> hinfo(B);
+    {
+        PhaseTimer t(c, &tm[1]);
+        RSRR_HIP(hipMemsetAsync(s.info, 0, (size_t)B * 4, c->stream));
+        if (prec == RSRR_PREC_C128)
+            RSRR_HIP(getrf_batched<double>(c->stream, (double2*)s.Tlu, s.sT, s.ld, n, c->nb_c128, s.ipiv, s.sP, s.perm,
+                                           s.sPerm, s.info, s.tperm, s.sTP, nullptr, B));
+        else
+            RSRR_HIP(getrf_batched<float>(c->stream, (float2*)s.Tlu, s.sT, s.ld, n, c->nb_c64, s.ipiv, s.sP, s.perm,
+                                          s.sPerm, s.info, s.tperm, s.sTP, nullptr, B));
+        t.stop();
+        RSRR_HIP(hipMemcpyAsync(hinfo.data(), s.info, (size_t)B * 4, hipMemcpyDeviceToHost, c->stream));
+        RSRR_HIP(hipStreamSynchronize(c->stream));
+    }
+    std::vector<int> act(B, 1);
+    for (int k = 0; k < B; ++k) {
+        if (info) {
+            info[k].info = hinfo[k];
+            info[k].ir_iters = 0;
+            info[k].fallback = 0;
+            info[k].resid = 0.0;
+        }
+        if (hinfo[k] > 0) { *any_singular = 1; act[k] = 0; }
+        if (hinfo[k] < 0) { *any_nan = 1; act[k] = 0; }
+    }
+    RSRR_HIP(hipMemcpyAsync(s.active, act.data(), (size_t)B * 4, hipMemcpyHostToDevice, c->stream));
+
+    std::vector<double> rn, xn, fro(B);
+    RSRR_HIP(hipMemcpyAsync(fro.data(), s.frob, (size_t)B * 8, hipMemcpyDeviceToHost, c->stream));
+
+    if (prec == RSRR_PREC_C128) {
+        {
+            PhaseTimer t(c, &tm[2]);
+            RSRR_HIP(bcast_c128(c->stream, n, L, U, ldu, S, lds, sX, B));
+            RSRR_HIP(getrs_batched<double>(c->stream, (const double2*)s.Tlu, s.sT, s.ld, n, c->nb_c128, s.perm, s.sPerm,
+                                           S, sX, lds, L, s.active, B));
+            t.stop();
+        }
+        {
+            PhaseTimer t(c, &tm[3]);
+            st = residual_batch(c, n, L, U, ldu, S, lds, sX, B, s, rn, xn);
+            if (st) return st;
+            t.stop();
+        }
+        for (int k = 0; k < B; ++k) {
+            double r = 0;
+            for (int cc = 0; cc < L; ++cc) r = std::max(r, rn[(size_t)k * L + cc] / un[cc]);
+            if (info) info[k].resid = r;
+        }
+        return RSRR_OK;
+    }
+
+    // mixed path: X0 = getrs_c64(U), then refinement with FP64 residuals
+    {
+        PhaseTimer t(c, &tm[2]);
+        RSRR_HIP(bcast_to_c64(c->stream, n, L, U, ldu, s.D64, s.ld, (long)s.ld * L, B));
+        RSRR_HIP(getrs_batched<float>(c->stream, (const float2*)s.Tlu, s.sT, s.ld, n, c->nb_c64, s.perm, s.sPerm,
+                                      s.D64, (long)s.ld * L, s.ld, L, s.active, B));
+        RSRR_HIP(widen(c->stream, n, L, s.D64, s.ld, (long)s.ld * L, S, lds, sX, B));
+        t.stop();
+    }
+    const double eps = 1.1102230246251565e-16;
+    const double tol_be = 4.0 * eps * std::sqrt((double)n);
+    std::vector<double> prev(B, 1e300), resid(B, 0.0), scl((size_t)B * L), inv((size_t)B * L);
+    std::vector<int> done(B, 0), iters(B, 0);
+    for (int k = 0; k < B; ++k) done[k] = act[k] ? 0 : 1;
+    for (int it = 0;; ++it) {
+        {
+            PhaseTimer t(c, &tm[3]);
+            st = residual_batch(c, n, L, U, ldu, S, lds, sX, B, s, rn, xn);
+            if (st) return st;
+            t.stop();
+        }
+        int live = 0;
+        for (int k = 0; k < B; ++k) {
+            double r = 0, eta = 0;
+            for (int cc = 0; cc < L; ++cc) {
+                const double rr = rn[(size_t)k * L + cc];
+                r = std::max(r, rr / un[cc]);
+                eta = std::max(eta, rr / (fro[k] * xn[(size_t)k * L + cc] + un[cc]));
+            }
+            if (!done[k]) {
+                resid[k] = r;
+                iters[k] = it;
+                const bool conv = eta <= tol_be;
+                const bool stall = r > 0.5 * prev[k];
+                if (conv || stall || it >= c->ir_max_iters || !(r == r)) done[k] = 1;
+                prev[k] = r;
+            }
+            act[k] = done[k] ? 0 : 1;
+            live += act[k];
+            for (int cc = 0; cc < L; ++cc) {
+                const double rr = rn[(size_t)k * L + cc];
+                scl[(size_t)k * L + cc] = rr;
+                inv[(size_t)k * L + cc] = rr > 0 ? 1.0 / rr : 0.0;
+            }
+        }
+        if (!live) break;
+        {
+            PhaseTimer t(c, &tm[2]);
+            RSRR_HIP(hipMemcpyAsync(s.active, act.data(), (size_t)B * 4, hipMemcpyHostToDevice, c->stream));
+            RSRR_HIP(hipMemcpyAsync(s.norms + (size_t)2 * B * L, inv.data(), (size_t)B * L * 8, hipMemcpyHostToDevice,
+                                    c->stream));
+            RSRR_HIP(scale_narrow(c->stream, n, L, s.R, s.ld, (long)s.ld * L, s.norms + (size_t)2 * B * L, s.D64, s.ld,
+                                  (long)s.ld * L, s.active, B));
+            RSRR_HIP(getrs_batched<float>(c->stream, (const float2*)s.Tlu, s.sT, s.ld, n, c->nb_c64, s.perm, s.sPerm,
+                                          s.D64, (long)s.ld * L, s.ld, L, s.active, B));
+            RSRR_HIP(hipMemcpyAsync(s.norms + (size_t)2 * B * L, scl.data(), (size_t)B * L * 8, hipMemcpyHostToDevice,
+                                    c->stream));
+            RSRR_HIP(axpy_widen(c->stream, n, L, s.D64, s.ld, (long)s.ld * L, s.norms + (size_t)2 * B * L, S, lds, sX,
+                                s.active, B));
+            t.stop();
+        }
+    }
+    for (int k = 0; k < B; ++k) {
+        if (info) {
+            info[k].ir_iters = iters[k];
+            info[k].resid = resid[k];
+        }
+    }
+    // fallback: points whose refinement did not reach 1e-10 are redone in FP64
+    for (int k = 0; k < B; ++k) {
+        if (hinfo[k] != 0) continue;
+        if (resid[k] <= 1e-10) continue;
+        rsrr_point_info pi;
+        int sing = 0, fb = 0, nan = 0;
+        st = sample_batch(c, nep, z + k, 1, U, L, ldu, un, RSRR_PREC_C128, S + (size_t)k * sX, lds, &pi, &sing, &fb,
+                          &nan);
+        if (st) return st;
+        *any_fallback = 1;
+        if (info) {
+            info[k].fallback = 1;
+            info[k].resid = pi.resid;
+            info[k].info = pi.info;
+        }
+        if (sing) *any_singular = 1;
+        if (nan) *any_nan = 1;
+    }
+    return RSRR_OK;
+}
+
+}  // namespace
+
+extern "C" rsrr_status rsrr_sample(rsrr_ctx* c, const rsrr_nep* nep, int N, const double* z, const double* U, int L,
+                                   int ldu, int prec, double* S, int lds, rsrr_point_info* info)
+{
+    if (!c) return -1;
+    if (!nep || nep->n < 1 || nep->n > 8192) return -2;
+    if (nep->kind == RSRR_T_SEPARABLE) {
+        if (nep->J < 1 || nep->J > 16 || !nep->A || nep->lda < nep->n || !nep->terms) return -2;
+    } else if (nep->kind == RSRR_T_HELMHOLTZ) {
+        if (!nep->points || !(nep->w > 0)) return -2;
+    } else {
+        return -2;
+    }
+    if (N < 1) return -3;
+    if (!z) return -4;
+    if (!U) return -5;
+    if (L < 1) return -6;
+    if (ldu < nep->n) return -7;
+    if (prec != RSRR_PREC_C128 && prec != RSRR_PREC_C64_IR) return -8;
+    if (!S) return -9;
+    if (lds < nep->n) return -10;
+    RSRR_HIP(hipSetDevice(c->device));
+    const int n = nep->n;
+    for (int i = 0; i < 5; ++i) c->timings[i] = 0.0;
+    RSRR_HIP(hipEventRecord(c->ev[0], c->stream));
+
+    // probe column norms (for relative residuals)
+    double* dn = (double*)ws_get(c, WS_B7, (size_t)L * 8);
+    if (!dn) return RSRR_ENOMEM;
+    RSRR_HIP(colnorms(c->stream, n, L, (const double2*)U, ldu, 0, dn, 1));
+    std::vector<double> un(L);
+    RSRR_HIP(hipMemcpyAsync(un.data(), dn, (size_t)L * 8, hipMemcpyDeviceToHost, c->stream));
+    RSRR_HIP(hipStreamSynchronize(c->stream));
+    for (auto& v : un)
+        if (!(v > 0)) v = 1.0;
+
+    // batch size from the workspace budget
+    size_t budget = c->ws_budget;
+    if (!budget) {
+        size_t fr = 0, tot = 0;
+        RSRR_HIP(hipMemGetInfo(&fr, &tot));
+        budget = fr / 2;
+    }
+    const size_t ppb = per_point_bytes(n, L, prec);
+    int Bp = (int)std::min<size_t>((size_t)N, std::max<size_t>(1, budget / ppb));
+
+    std::vector<zd> zz(N);
+    for (int k = 0; k < N; ++k) zz[k] = zd(z[2 * k], z[2 * k + 1]);
+    int sing = 0, fb = 0, nan = 0;
+    for (int k0 = 0; k0 < N; k0 += Bp) {
+        const int B = std::min(Bp, N - k0);
+        rsrr_status st = sample_batch(c, nep, zz.data() + k0, B, (const double2*)U, L, ldu, un, prec,
+                                      (double2*)S + (size_t)k0 * L * lds, lds, info ? info + k0 : nullptr, &sing, &fb,
+                                      &nan);
+        if (st) return st;
+    }
+    RSRR_HIP(hipEventRecord(c->ev[1], c->stream));
+    RSRR_HIP(hipEventSynchronize(c->ev[1]));
+    float ms = 0.f;
+    RSRR_HIP(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+    c->timings[4] = ms;
+    if (nan) return RSRR_ENAN;
+    if (sing) return RSRR_ESINGULAR;
+    if (fb) return RSRR_WARN_FALLBACK;
+    return RSRR_OK;
+}

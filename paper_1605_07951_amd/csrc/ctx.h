@@ -1,0 +1,44 @@
+// Library context: device, stream, grow-only workspace and phase timers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <vector>
+
+#include "rsrr.h"
+
+typedef std::complex<double> zd;
+
+// Workspace slots (each a grow-only device allocation owned by the context).
+enum WsSlot {
+    WS_TLU = 0, WS_TRES, WS_IPIV, WS_PERM, WS_TPERM, WS_INFO, WS_COEF, WS_FROBP, WS_FROB,
+    WS_D64, WS_R, WS_NORM, WS_ACTIVE, WS_Z,
+    WS_B0, WS_B1, WS_B2, WS_B3, WS_B4, WS_B5, WS_B6, WS_B7,
+    WS_COUNT
+};
+
+struct rsrr_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    void* ws[WS_COUNT] = {};
+    size_t ws_size[WS_COUNT] = {};
+    hipEvent_t ev[2] = {};
+    double timings[5] = {0, 0, 0, 0, 0};
+    int nb_c64 = 64;       // outer LU panel width, complex FP32 path
+    int nb_c128 = 64;      // outer LU panel width, complex FP64 path
+    int ir_max_iters = 10;
+    size_t ws_budget = 0;  // bytes for the per-point sampling buffers (0 = half of free memory)
+};
+
+// Grow workspace slot `s` to at least `bytes`; returns nullptr on failure.
+void* ws_get(rsrr_ctx* c, int s, size_t bytes);
+
+// f(z) = c (z - z0)^p exp(-tau z) / (z - s)^q
+zd term_eval(const rsrr_term& t, zd z);
+
+#define RSRR_HIP(call)                                  \
+    do {                                                \
+        hipError_t _e = (call);                         \
+        if (_e != hipSuccess) return RSRR_EDEVICE;      \
+    } while (0)

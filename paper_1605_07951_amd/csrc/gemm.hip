@@ -1,0 +1,354 @@
+// Batched complex GEMMs on the CDNA4 matrix cores.
+//
+// A complex product C += A*B is computed as real MFMA products by splitting
+// the complex inner index k into two real indices k' = 2k + c (c = 0 real
+// part, c = 1 imaginary part):
+//     Re C(i,j) = sum_k' A'(i,k') Br'(k',j),   A'(i,2k+c) = c ? Im A : Re A,
+//     Im C(i,j) = sum_k' A'(i,k') Bi'(k',j),   Br'(2k+c,j) = c ? -Im B : Re B,
+//                                              Bi'(2k+c,j) = c ?  Re B : Im B.
+// (4 real multiplies per complex multiply-add, the "4M" form.)  A' is the
+// interleaved complex storage read one float per lane, so the operands come
+// straight from the interleaved layout staged in LDS.  The MFMA operand
+// slots are swapped (the MFMA "A" operand carries B' and its "B" operand
+// carries A'), which makes the output lane index run along rows i: 32 (or 16)
+// consecutive lanes then store one contiguous column segment of C.
+#include "common.h"
+#include "kernels.h"
+
+namespace rsrr {
+
+// ----------------------------------------------------------------------------
+// complex FP32: v_mfma_f32_32x32x2f32, WG tile 128x128, 4 waves of 64x64.
+// ----------------------------------------------------------------------------
+constexpr int CG_BM = 128, CG_BN = 128, CG_KT = 16, CG_NT = 256;
+
+template <bool VEC>
+__global__ __launch_bounds__(CG_NT, 2) void cgemm_mfma_kernel(
+    int M, int N, int K, float alpha,
+    const float2* __restrict__ A, int lda, long sA,
+    const float2* __restrict__ B, int ldb, long sB,
+    float beta, float2* __restrict__ C, int ldc, long sC,
+    int tilesM, int tilesN, int batch, long total_padded)
+{
+    __shared__ __attribute__((aligned(16))) float As[2][CG_KT][2 * CG_BM];
+    __shared__ __attribute__((aligned(16))) float2 Bs[2][CG_KT][CG_BN];
+
+    const long tile = xcd_remap(blockIdx.x, total_padded);
+    const long per = (long)tilesM * tilesN;
+    const long b = tile / per;
+    if (b >= batch) return;
+    const int t = (int)(tile - b * per);
+    const int i0 = (t % tilesM) * CG_BM;
+    const int j0 = (t / tilesM) * CG_BN;
+    const float2* Ab = A + b * sA;
+    const float2* Bb = B + b * sB;
+    float2* Cb = C + b * sC;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wi = wave & 1, wj = wave >> 1;
+    const int li = lane & 31, half = lane >> 5;
+
+    floatx16 accR[2][2], accI[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) { accR[x][y][r] = 0.f; accI[x][y][r] = 0.f; }
+
+    floatx4 ra[4], rb[4];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int p = tid + CG_NT * q;
+            // A: 64 row-pairs x 16 k
+            {
+                int k = p >> 6, ip = (p & 63) << 1;
+                int gi = i0 + ip, gk = k0 + k;
+                floatx4 v = {0.f, 0.f, 0.f, 0.f};
+                if (gk < K) {
+                    const float2* src = Ab + gi + (long)gk * lda;
+                    if (VEC && gi + 1 < M) {
+                        v = *reinterpret_cast<const floatx4*>(src);
+                    } else {
+                        if (gi < M) { float2 e = src[0]; v[0] = e.x; v[1] = e.y; }
+                        if (gi + 1 < M) { float2 e = src[1]; v[2] = e.x; v[3] = e.y; }
+                    }
+                }
+                ra[q] = v;
+            }
+            // B: 128 columns x 8 k-pairs
+            {
+                int j = p >> 3, kp = (p & 7) << 1;
+                int gj = j0 + j, gk = k0 + kp;
+                floatx4 v = {0.f, 0.f, 0.f, 0.f};
+                if (gj < N) {
+                    const float2* src = Bb + gk + (long)gj * ldb;
+                    if (VEC && gk + 1 < K) {
+                        v = *reinterpret_cast<const floatx4*>(src);
+                    } else {
+                        if (gk < K) { float2 e = src[0]; v[0] = e.x; v[1] = e.y; }
+                        if (gk + 1 < K) { float2 e = src[1]; v[2] = e.x; v[3] = e.y; }
+                    }
+                }
+                rb[q] = v;
+            }
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int p = tid + CG_NT * q;
+            {
+                int k = p >> 6, ip = (p & 63) << 1;
+                *reinterpret_cast<floatx4*>(&As[buf][k][2 * ip]) = ra[q];
+            }
+            {
+                int j = p >> 3, kp = (p & 7) << 1;
+                Bs[buf][kp][j] = make_float2(rb[q][0], rb[q][1]);
+                Bs[buf][kp + 1][j] = make_float2(rb[q][2], rb[q][3]);
+            }
+        }
+    };
+
+    const int nst = (K + CG_KT - 1) / CG_KT;
+    if (nst > 0) {
+        gload(0);
+        sstore(0);
+        __syncthreads();
+    }
+    for (int s = 0; s < nst; ++s) {
+        const int buf = s & 1;
+        if (s + 1 < nst) gload((s + 1) * CG_KT);
+#pragma unroll 4
+        for (int k = 0; k < CG_KT; ++k) {
+            float a[2], br[2], bi[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x) a[x] = As[buf][k][2 * (wi * 64 + x * 32 + li) + half];
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                float2 bv = Bs[buf][k][wj * 64 + y * 32 + li];
+                br[y] = half ? -bv.y : bv.x;
+                bi[y] = half ? bv.x : bv.y;
+            }
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) {
+                    accR[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(br[y], a[x], accR[x][y], 0, 0, 0);
+                    accI[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(bi[y], a[x], accI[x][y], 0, 0, 0);
+                }
+        }
+        if (s + 1 < nst) sstore(buf ^ 1);
+        __syncthreads();
+    }
+
+    // epilogue: lane li holds row i; register r holds column 8(r/4) + 4 half + r%4.
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+        const int i = i0 + wi * 64 + x * 32 + li;
+        if (i >= M) continue;
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int j = j0 + wj * 64 + y * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                if (j < N) {
+                    float2* dst = Cb + i + (long)j * ldc;
+                    float2 o;
+                    o.x = alpha * accR[x][y][r];
+                    o.y = alpha * accI[x][y][r];
+                    if (beta != 0.f) {
+                        float2 c = *dst;
+                        o.x += beta * c.x;
+                        o.y += beta * c.y;
+                    }
+                    *dst = o;
+                }
+            }
+    }
+}
+
+hipError_t cgemm(hipStream_t st, int M, int N, int K, float alpha,
+                 const float2* A, int lda, long sA, const float2* B, int ldb, long sB,
+                 float beta, float2* C, int ldc, long sC, int batch)
+{
+    if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+    const int tm = (M + CG_BM - 1) / CG_BM, tn = (N + CG_BN - 1) / CG_BN;
+    const long total = round_up_l((long)tm * tn * batch, 8);
+    const bool vec = ((((uintptr_t)A) | ((uintptr_t)B)) & 15) == 0 && (lda % 2 == 0) && (ldb % 2 == 0)
+                     && (sA % 2 == 0) && (sB % 2 == 0);
+    if (vec)
+        hipLaunchKernelGGL(cgemm_mfma_kernel<true>, dim3((unsigned)total), dim3(CG_NT), 0, st,
+                           M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, tm, tn, batch, total);
+    else
+        hipLaunchKernelGGL(cgemm_mfma_kernel<false>, dim3((unsigned)total), dim3(CG_NT), 0, st,
+                           M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, tm, tn, batch, total);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// complex FP64: v_mfma_f64_16x16x4f64, WG tile 64x64, 4 waves of 32x32.
+// op(A) = A or A^H, op(B) = B or B^H.
+// ----------------------------------------------------------------------------
+constexpr int ZG_BM = 64, ZG_BN = 64, ZG_KT = 16, ZG_NT = 256;
+
+template <bool CA, bool CB>
+__global__ __launch_bounds__(ZG_NT, 2) void zgemm_mfma_kernel(
+    int M, int N, int K, double alpha,
+    const double2* __restrict__ A, int lda, long sA,
+    const double2* __restrict__ B, int ldb, long sB,
+    double beta, double2* __restrict__ C, int ldc, long sC,
+    int tilesM, int tilesN, int batch, long total_padded)
+{
+    __shared__ __attribute__((aligned(16))) double2 As[2][ZG_KT][ZG_BM];
+    __shared__ __attribute__((aligned(16))) double2 Bs[2][ZG_KT][ZG_BN];
+
+    const long tile = xcd_remap(blockIdx.x, total_padded);
+    const long per = (long)tilesM * tilesN;
+    const long b = tile / per;
+    if (b >= batch) return;
+    const int t = (int)(tile - b * per);
+    const int i0 = (t % tilesM) * ZG_BM;
+    const int j0 = (t / tilesM) * ZG_BN;
+    const double2* Ab = A + b * sA;
+    const double2* Bb = B + b * sB;
+    double2* Cb = C + b * sC;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wi = wave & 1, wj = wave >> 1;
+    const int li = lane & 15, kq = lane >> 4;       // kq = 2*kc + part
+    const int kc = kq >> 1, part = kq & 1;
+
+    doublex4 accR[2][2], accI[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) { accR[x][y][r] = 0.0; accI[x][y][r] = 0.0; }
+
+    double2 ra[4], rb[4];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int p = tid + ZG_NT * q;   // 0..1023
+            double2 v = make_double2(0.0, 0.0);
+            if (!CA) {
+                int k = p >> 6, i = p & 63;
+                int gi = i0 + i, gk = k0 + k;
+                if (gi < M && gk < K) v = Ab[gi + (long)gk * lda];
+            } else {
+                int i = p >> 4, k = p & 15;
+                int gi = i0 + i, gk = k0 + k;
+                if (gi < M && gk < K) { v = Ab[gk + (long)gi * lda]; v.y = -v.y; }
+            }
+            ra[q] = v;
+            double2 w = make_double2(0.0, 0.0);
+            if (!CB) {
+                int j = p >> 4, k = p & 15;
+                int gj = j0 + j, gk = k0 + k;
+                if (gj < N && gk < K) w = Bb[gk + (long)gj * ldb];
+            } else {
+                int k = p >> 6, j = p & 63;
+                int gj = j0 + j, gk = k0 + k;
+                if (gj < N && gk < K) { w = Bb[gj + (long)gk * ldb]; w.y = -w.y; }
+            }
+            rb[q] = w;
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int p = tid + ZG_NT * q;
+            if (!CA) As[buf][p >> 6][p & 63] = ra[q];
+            else As[buf][p & 15][p >> 4] = ra[q];
+            if (!CB) Bs[buf][p & 15][p >> 4] = rb[q];
+            else Bs[buf][p >> 6][p & 63] = rb[q];
+        }
+    };
+
+    const int nst = (K + ZG_KT - 1) / ZG_KT;
+    if (nst > 0) {
+        gload(0);
+        sstore(0);
+        __syncthreads();
+    }
+    for (int s = 0; s < nst; ++s) {
+        const int buf = s & 1;
+        if (s + 1 < nst) gload((s + 1) * ZG_KT);
+#pragma unroll 2
+        for (int kk = 0; kk < ZG_KT; kk += 2) {
+            double a[2], br[2], bi[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                double2 av = As[buf][kk + kc][wi * 32 + x * 16 + li];
+                a[x] = part ? av.y : av.x;
+            }
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                double2 bv = Bs[buf][kk + kc][wj * 32 + y * 16 + li];
+                br[y] = part ? -bv.y : bv.x;
+                bi[y] = part ? bv.x : bv.y;
+            }
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) {
+                    accR[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(br[y], a[x], accR[x][y], 0, 0, 0);
+                    accI[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(bi[y], a[x], accI[x][y], 0, 0, 0);
+                }
+        }
+        if (s + 1 < nst) sstore(buf ^ 1);
+        __syncthreads();
+    }
+
+    // epilogue: lane li holds row i; register r holds column lane/16 + 4*r
+    // (the f64 MFMA interleaves its four output groups by register).
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+        const int i = i0 + wi * 32 + x * 16 + li;
+        if (i >= M) continue;
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = j0 + wj * 32 + y * 16 + kq + 4 * r;
+                if (j < N) {
+                    double2* dst = Cb + i + (long)j * ldc;
+                    double2 o;
+                    o.x = alpha * accR[x][y][r];
+                    o.y = alpha * accI[x][y][r];
+                    if (beta != 0.0) {
+                        double2 c = *dst;
+                        o.x += beta * c.x;
+                        o.y += beta * c.y;
+                    }
+                    *dst = o;
+                }
+            }
+    }
+}
+
+hipError_t zgemm(hipStream_t st, int opA, int opB, int M, int N, int K, double alpha,
+                 const double2* A, int lda, long sA, const double2* B, int ldb, long sB,
+                 double beta, double2* C, int ldc, long sC, int batch)
+{
+    if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+    const int tm = (M + ZG_BM - 1) / ZG_BM, tn = (N + ZG_BN - 1) / ZG_BN;
+    const long total = round_up_l((long)tm * tn * batch, 8);
+    dim3 g((unsigned)total), blk(ZG_NT);
+#define ZG_LAUNCH(CA, CB)                                                                        \
+    hipLaunchKernelGGL((zgemm_mfma_kernel<CA, CB>), g, blk, 0, st, M, N, K, alpha, A, lda, sA, B, \
+                       ldb, sB, beta, C, ldc, sC, tm, tn, batch, total)
+    if (!opA && !opB) ZG_LAUNCH(false, false);
+    else if (opA && !opB) ZG_LAUNCH(true, false);
+    else if (!opA && opB) ZG_LAUNCH(false, true);
+    else ZG_LAUNCH(true, true);
+#undef ZG_LAUNCH
+    return hipGetLastError();
+}
+
+}  // namespace rsrr

@@ -1,0 +1,174 @@
+// Element-wise and reduction kernels of the mixed-precision refinement
+// (complex FP32 solves, FP64 residuals) and of the probe/solution copies.
+// All operate on a batch of n x L column blocks (stride per point).
+#include "common.h"
+#include "kernels.h"
+
+namespace rsrr {
+
+constexpr int EW_NT = 256;
+
+// D_k = (c64) U for every point k.
+__global__ __launch_bounds__(EW_NT) void bcast_to_c64_kernel(int n, int L, const double2* __restrict__ U, int ldu,
+                                                              float2* __restrict__ D, int ldd, long sD)
+{
+    const int k = blockIdx.y;
+    const int e = blockIdx.x * EW_NT + threadIdx.x;
+    if (e >= n * L) return;
+    const int i = e % n, c = e / n;
+    D[k * sD + i + (long)c * ldd] = to_c64(U[i + (long)c * ldu]);
+}
+
+// R_k = U for every point k (FP64).
+__global__ __launch_bounds__(EW_NT) void bcast_c128_kernel(int n, int L, const double2* __restrict__ U, int ldu,
+                                                            double2* __restrict__ R, int ldr, long sR)
+{
+    const int k = blockIdx.y;
+    const int e = blockIdx.x * EW_NT + threadIdx.x;
+    if (e >= n * L) return;
+    const int i = e % n, c = e / n;
+    R[k * sR + i + (long)c * ldr] = U[i + (long)c * ldu];
+}
+
+// X_k = (c128) D_k.
+__global__ __launch_bounds__(EW_NT) void widen_kernel(int n, int L, const float2* __restrict__ D, int ldd, long sD,
+                                                       double2* __restrict__ X, int ldx, long sX)
+{
+    const int k = blockIdx.y;
+    const int e = blockIdx.x * EW_NT + threadIdx.x;
+    if (e >= n * L) return;
+    const int i = e % n, c = e / n;
+    X[k * sX + i + (long)c * ldx] = to_c128(D[k * sD + i + (long)c * ldd]);
+}
+
+// out[k*L + c] = ||X_k(:, c)||_2 (FP64, fixed summation order).
+__global__ __launch_bounds__(EW_NT) void colnorm_kernel(int n, int L, const double2* __restrict__ X, int ldx, long sX,
+                                                         double* __restrict__ out)
+{
+    __shared__ double red[EW_NT / 64];
+    const int c = blockIdx.x, k = blockIdx.y;
+    const double2* col = X + k * sX + (long)c * ldx;
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += EW_NT) {
+        const double2 a = col[i];
+        v += a.x * a.x + a.y * a.y;
+    }
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < EW_NT / 64; ++w) s += red[w];
+        out[(long)k * L + c] = sqrt(s);
+    }
+}
+
+// D_k(:, c) = (c64) (R_k(:, c) * inv[k*L + c]) for active points.
+__global__ __launch_bounds__(EW_NT) void scale_narrow_kernel(int n, int L, const double2* __restrict__ R, int ldr,
+                                                              long sR, const double* __restrict__ inv,
+                                                              float2* __restrict__ D, int ldd, long sD,
+                                                              const int* __restrict__ active)
+{
+    const int k = blockIdx.y;
+    if (active && !active[k]) return;
+    const int e = blockIdx.x * EW_NT + threadIdx.x;
+    if (e >= n * L) return;
+    const int i = e % n, c = e / n;
+    const double s = inv[(long)k * L + c];
+    const double2 r = R[k * sR + i + (long)c * ldr];
+    D[k * sD + i + (long)c * ldd] = make_float2((float)(r.x * s), (float)(r.y * s));
+}
+
+// X_k(:, c) += scale[k*L + c] * D_k(:, c) for active points.
+__global__ __launch_bounds__(EW_NT) void axpy_widen_kernel(int n, int L, const float2* __restrict__ D, int ldd,
+                                                            long sD, const double* __restrict__ scale,
+                                                            double2* __restrict__ X, int ldx, long sX,
+                                                            const int* __restrict__ active)
+{
+    const int k = blockIdx.y;
+    if (active && !active[k]) return;
+    const int e = blockIdx.x * EW_NT + threadIdx.x;
+    if (e >= n * L) return;
+    const int i = e % n, c = e / n;
+    const double s = scale[(long)k * L + c];
+    const float2 d = D[k * sD + i + (long)c * ldd];
+    double2* x = X + k * sX + i + (long)c * ldx;
+    double2 v = *x;
+    v.x += s * (double)d.x;
+    v.y += s * (double)d.y;
+    *x = v;
+}
+
+// Copy n x m (c128) blocks: Y_k = X_k.
+__global__ __launch_bounds__(EW_NT) void copy_c128_kernel(int n, int m, const double2* __restrict__ X, int ldx,
+                                                           long sX, double2* __restrict__ Y, int ldy, long sY)
+{
+    const int k = blockIdx.y;
+    const long e = (long)blockIdx.x * EW_NT + threadIdx.x;
+    if (e >= (long)n * m) return;
+    const int i = (int)(e % n), c = (int)(e / n);
+    Y[k * sY + i + (long)c * ldy] = X[k * sX + i + (long)c * ldx];
+}
+
+// Scale each column c of X (n x m) by s[c] (in place, FP64).
+__global__ __launch_bounds__(EW_NT) void scale_cols_kernel(int n, int m, double2* __restrict__ X, int ldx,
+                                                            const double* __restrict__ s)
+{
+    const long e = (long)blockIdx.x * EW_NT + threadIdx.x;
+    if (e >= (long)n * m) return;
+    const int i = (int)(e % n), c = (int)(e / n);
+    double2* x = X + i + (long)c * ldx;
+    const double f = s[c];
+    x->x *= f;
+    x->y *= f;
+}
+
+static dim3 ew_grid(long elems, int B) { return dim3((unsigned)((elems + EW_NT - 1) / EW_NT), B); }
+
+hipError_t bcast_to_c64(hipStream_t st, int n, int L, const double2* U, int ldu, float2* D, int ldd, long sD, int B)
+{
+    hipLaunchKernelGGL(bcast_to_c64_kernel, ew_grid((long)n * L, B), dim3(EW_NT), 0, st, n, L, U, ldu, D, ldd, sD);
+    return hipGetLastError();
+}
+hipError_t bcast_c128(hipStream_t st, int n, int L, const double2* U, int ldu, double2* R, int ldr, long sR, int B)
+{
+    hipLaunchKernelGGL(bcast_c128_kernel, ew_grid((long)n * L, B), dim3(EW_NT), 0, st, n, L, U, ldu, R, ldr, sR);
+    return hipGetLastError();
+}
+hipError_t widen(hipStream_t st, int n, int L, const float2* D, int ldd, long sD, double2* X, int ldx, long sX, int B)
+{
+    hipLaunchKernelGGL(widen_kernel, ew_grid((long)n * L, B), dim3(EW_NT), 0, st, n, L, D, ldd, sD, X, ldx, sX);
+    return hipGetLastError();
+}
+hipError_t colnorms(hipStream_t st, int n, int L, const double2* X, int ldx, long sX, double* out, int B)
+{
+    hipLaunchKernelGGL(colnorm_kernel, dim3(L, B), dim3(EW_NT), 0, st, n, L, X, ldx, sX, out);
+    return hipGetLastError();
+}
+hipError_t scale_narrow(hipStream_t st, int n, int L, const double2* R, int ldr, long sR, const double* inv,
+                        float2* D, int ldd, long sD, const int* active, int B)
+{
+    hipLaunchKernelGGL(scale_narrow_kernel, ew_grid((long)n * L, B), dim3(EW_NT), 0, st, n, L, R, ldr, sR, inv, D,
+                       ldd, sD, active);
+    return hipGetLastError();
+}
+hipError_t axpy_widen(hipStream_t st, int n, int L, const float2* D, int ldd, long sD, const double* scale,
+                      double2* X, int ldx, long sX, const int* active, int B)
+{
+    hipLaunchKernelGGL(axpy_widen_kernel, ew_grid((long)n * L, B), dim3(EW_NT), 0, st, n, L, D, ldd, sD, scale, X,
+                       ldx, sX, active);
+    return hipGetLastError();
+}
+hipError_t copy_c128(hipStream_t st, int n, int m, const double2* X, int ldx, long sX, double2* Y, int ldy, long sY,
+                     int B)
+{
+    hipLaunchKernelGGL(copy_c128_kernel, ew_grid((long)n * m, B), dim3(EW_NT), 0, st, n, m, X, ldx, sX, Y, ldy, sY);
+    return hipGetLastError();
+}
+hipError_t scale_cols(hipStream_t st, int n, int m, double2* X, int ldx, const double* s)
+{
+    hipLaunchKernelGGL(scale_cols_kernel, ew_grid((long)n * m, 1), dim3(EW_NT), 0, st, n, m, X, ldx, s);
+    return hipGetLastError();
+}
+
+}  // namespace rsrr

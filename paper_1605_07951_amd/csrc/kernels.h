@@ -1,0 +1,65 @@
+// Host-side entry points of the device kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace rsrr {
+
+// Widest LU panel (columns) the solve/interchange kernels stage in LDS.
+constexpr int MAX_NB = 64;
+
+// C = beta*C + alpha*A*B, complex single on v_mfma_f32_32x32x2f32.
+hipError_t cgemm(hipStream_t st, int M, int N, int K, float alpha,
+                 const float2* A, int lda, long sA, const float2* B, int ldb, long sB,
+                 float beta, float2* C, int ldc, long sC, int batch);
+
+// C = beta*C + alpha*op(A)*op(B), complex double on v_mfma_f64_16x16x4f64;
+// op = conjugate transpose when the flag is set.
+hipError_t zgemm(hipStream_t st, int opA, int opB, int M, int N, int K, double alpha,
+                 const double2* A, int lda, long sA, const double2* B, int ldb, long sB,
+                 double beta, double2* C, int ldc, long sC, int batch);
+
+// Blocked LU with partial pivoting of `batch` n x n matrices (stride sA).
+// ipiv: n ints per matrix (stride sP).  perm: ceil(n/nb)*2*MAX_NB int2 per
+// matrix (stride sPerm), one composed permutation per panel, used by
+// getrs_batched.  tperm: 8*2*MAX_NB int2 scratch per matrix (stride sTP).
+// info: one int per matrix, must be zero on entry.  active: optional mask.
+template <typename R>
+hipError_t getrf_batched(hipStream_t st, typename cpx<R>::T* A,
+                         long sA, int lda, int n, int nb, int* ipiv, long sP, int2* perm, long sPerm, int* info,
+                         int2* tperm, long sTP, const int* active, int batch);
+
+template <typename R>
+hipError_t getrs_batched(hipStream_t st, const typename cpx<R>::T* LU,
+                         long sLU, int lda, int n, int nb, const int2* perm, long sPerm,
+                         typename cpx<R>::T* X, long sX, int ldx,
+                         int nrhs, const int* active, int batch);
+
+// ---- assembly (assemble.hip) ----
+// T64/T128 may be null (not written); batch strides s64/s128 in elements.
+// frob_part: B * ceil(n*n/256) doubles of scratch; frob: B doubles (||T_k||_F).
+hipError_t assemble_separable(hipStream_t st, int n, int J, const double2* A, int lda, const double2* coef, int B,
+                              float2* T64, int ld64, long s64, double2* T128, int ld128, long s128,
+                              double* frob_part, double* frob);
+hipError_t assemble_helmholtz(hipStream_t st, int n, const double* pts, double w, const double2* z, int B,
+                              float2* T64, int ld64, long s64, double2* T128, int ld128, long s128,
+                              double* frob_part, double* frob);
+hipError_t helmholtz_taylor(hipStream_t st, int n, const double* pts, double w, double gre, double gim, int p,
+                            double2* Tp, int ld);
+
+// ---- element-wise helpers (ir.hip) ----
+hipError_t bcast_to_c64(hipStream_t st, int n, int L, const double2* U, int ldu, float2* D, int ldd, long sD, int B);
+hipError_t bcast_c128(hipStream_t st, int n, int L, const double2* U, int ldu, double2* R, int ldr, long sR, int B);
+hipError_t widen(hipStream_t st, int n, int L, const float2* D, int ldd, long sD, double2* X, int ldx, long sX, int B);
+hipError_t colnorms(hipStream_t st, int n, int L, const double2* X, int ldx, long sX, double* out, int B);
+hipError_t scale_narrow(hipStream_t st, int n, int L, const double2* R, int ldr, long sR, const double* inv,
+                        float2* D, int ldd, long sD, const int* active, int B);
+hipError_t axpy_widen(hipStream_t st, int n, int L, const float2* D, int ldd, long sD, const double* scale,
+                      double2* X, int ldx, long sX, const int* active, int B);
+hipError_t copy_c128(hipStream_t st, int n, int m, const double2* X, int ldx, long sX, double2* Y, int ldy, long sY,
+                     int B);
+hipError_t scale_cols(hipStream_t st, int n, int m, double2* X, int ldx, const double* s);
+
+}  // namespace rsrr

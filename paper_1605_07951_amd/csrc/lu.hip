@@ -1,0 +1,468 @@
+// Batched dense complex LU with partial pivoting and the matching solves.
+//
+// Factorisation (right-looking, blocked, RSRR Step 2 needs one LU per
+// sampling point): for each outer panel of nb columns
+//   1. the panel (all rows below the diagonal) is factored by a recursive
+//      split into halves down to a register-resident base kernel;
+//   2. the panel's row interchanges are composed into a permutation of at
+//      most 2*nb rows (perm_build) and applied to the columns right of the
+//      panel together with the unit-lower triangular solve U12 = L11^-1 A12;
+//   3. the trailing matrix is updated on the matrix cores, A22 -= L21 U12.
+// Columns left of the panel are never interchanged ("lazy" left swaps): the
+// solve applies each panel's permutation just before that panel's forward
+// elimination step, which reproduces the elimination order exactly.  Inside
+// one panel the interchanges are applied to every panel column, so the
+// solve can work at panel granularity.
+//
+// Pivot: largest |Re| + |Im| in the column, lowest row index on ties
+// (LAPACK's choice).  info = first column (1-based) whose pivot is exactly
+// zero; the factorisation continues past it, as getrf does.
+#include <climits>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace rsrr {
+
+// ----------------------------------------------------------------------------
+// Panel base: rows [c0, n) x columns [c0, c0+jb) of one matrix per workgroup,
+// held in registers (thread t owns local rows t, t+NT, ...).
+// ----------------------------------------------------------------------------
+template <typename R, int NT, int RPT, int JB>
+__global__ __launch_bounds__(NT) void panel_base_kernel(
+    typename cpx<R>::T* __restrict__ A, long sA, int lda, int n, int c0, int jb,
+    int* __restrict__ ipiv, long sP, int* __restrict__ info, const int* __restrict__ active)
+{
+    typedef typename cpx<R>::T C;
+    const int b = blockIdx.x;
+    if (active && !active[b]) return;
+    C* Ab = A + (long)b * sA;
+    int* pv = ipiv + (long)b * sP;
+    const int m = n - c0;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    constexpr int NW = NT / 64;
+
+    __shared__ R red_v[NW];
+    __shared__ int red_i[NW];
+    __shared__ int s_piv;
+    __shared__ C prow[JB], crow[JB];
+
+    C v[RPT][JB];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int lr = tid + NT * q;
+#pragma unroll
+        for (int c = 0; c < JB; ++c) {
+            C e = czero<C>();
+            if (lr < m && c < jb) e = Ab[(c0 + lr) + (long)(c0 + c) * lda];
+            v[q][c] = e;
+        }
+    }
+
+#pragma unroll
+    for (int c = 0; c < JB; ++c) {
+        if (c >= jb) break;
+        // ---- pivot search: per-thread, wavefront shuffle, then LDS ----
+        R best = (R)-1;
+        int bi = INT_MAX;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int lr = tid + NT * q;
+            if (lr >= c && lr < m) {
+                R a = cabs1(v[q][c]);
+                if (a != a) a = (R)INFINITY;  // a NaN wins, so it is reported
+                if (a > best) { best = a; bi = lr; }
+            }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            R ob = __shfl_xor(best, off);
+            int oi = __shfl_xor(bi, off);
+            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        if (lane == 0) { red_v[wave] = best; red_i[wave] = bi; }
+        __syncthreads();
+        if (wave == 0) {
+            R bb = lane < NW ? red_v[lane] : (R)-1;
+            int ii = lane < NW ? red_i[lane] : INT_MAX;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                R ob = __shfl_xor(bb, off);
+                int oi = __shfl_xor(ii, off);
+                if (ob > bb || (ob == bb && oi < ii)) { bb = ob; ii = oi; }
+            }
+            if (lane == 0) s_piv = (ii == INT_MAX) ? c : ii;
+        }
+        __syncthreads();
+        const int p = s_piv;
+        // ---- interchange rows c and p (panel columns only) ----
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int lr = tid + NT * q;
+            if (lr == p) {
+#pragma unroll
+                for (int cc = 0; cc < JB; ++cc) prow[cc] = v[q][cc];
+            }
+            if (lr == c) {
+#pragma unroll
+                for (int cc = 0; cc < JB; ++cc) crow[cc] = v[q][cc];
+            }
+        }
+        __syncthreads();
+        if (p != c) {
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int lr = tid + NT * q;
+                if (lr == c) {
+#pragma unroll
+                    for (int cc = 0; cc < JB; ++cc) v[q][cc] = prow[cc];
+                }
+                if (lr == p) {
+#pragma unroll
+                    for (int cc = 0; cc < JB; ++cc) v[q][cc] = crow[cc];
+                }
+            }
+        }
+        const C piv = prow[c];
+        const bool zero = (piv.x == (R)0 && piv.y == (R)0);
+        const bool bad = !(isfinite(piv.x) && isfinite(piv.y));
+        if (tid == 0) {
+            pv[c0 + c] = c0 + p;
+            if (info[b] == 0) {
+                if (bad) info[b] = -(c0 + c + 1);
+                else if (zero) info[b] = c0 + c + 1;
+            }
+        }
+        const C rp = zero ? czero<C>() : crecip(piv);
+        // ---- scale the column and update the rest of the panel ----
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int lr = tid + NT * q;
+            if (lr > c && lr < m) {
+                if (!zero) v[q][c] = cmul(v[q][c], rp);
+                const C l = v[q][c];
+#pragma unroll
+                for (int cc = c + 1; cc < JB; ++cc)
+                    if (cc < jb) v[q][cc] = cfms(v[q][cc], l, prow[cc]);
+            }
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int lr = tid + NT * q;
+        if (lr < m) {
+#pragma unroll
+            for (int c = 0; c < JB; ++c)
+                if (c < jb) Ab[(c0 + lr) + (long)(c0 + c) * lda] = v[q][c];
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Compose the interchanges ipiv[k1 .. k1+jb) (applied in order) into a
+// permutation of the affected rows: after the swaps, row dst[s] holds the
+// old row src[s].  Slots 0..jb-1 are rows k1..k1+jb-1; later slots are the
+// distinct rows below that were swapped in; unused slots hold (-1, -1).
+// One wavefront per matrix; lane 0 replays the swaps, the wave searches.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void perm_build_kernel(const int* __restrict__ ipiv, long sP, int k1, int jb,
+                                                          int2* __restrict__ perm, long sPerm,
+                                                          const int* __restrict__ active)
+{
+    const int b = blockIdx.x;
+    if (active && !active[b]) return;
+    const int* pv = ipiv + (long)b * sP;
+    int2* pm = perm + (long)b * sPerm;
+    const int lane = threadIdx.x;
+    __shared__ int rowid[2 * MAX_NB], content[2 * MAX_NB];
+    for (int s = lane; s < 2 * jb; s += 64) {
+        rowid[s] = (s < jb) ? k1 + s : -1;
+        content[s] = (s < jb) ? k1 + s : -1;
+    }
+    __syncthreads();
+    int nout = 0;
+    for (int i = 0; i < jb; ++i) {
+        const int p = pv[k1 + i];
+        int slot;
+        if (p < k1 + jb) {
+            slot = p - k1;
+        } else {
+            int found = INT_MAX;
+            for (int base = 0; base < nout; base += 64) {
+                const int s = base + lane;
+                const bool hit = (s < nout) && rowid[jb + s] == p;
+                const unsigned long long m = __ballot(hit);
+                if (m) { found = base + __ffsll((long long)m) - 1; break; }
+            }
+            if (found == INT_MAX) {
+                slot = jb + nout;
+                if (lane == 0) { rowid[slot] = p; content[slot] = p; }
+                ++nout;
+            } else {
+                slot = jb + found;
+            }
+        }
+        __syncthreads();
+        if (lane == 0 && slot != i) {
+            const int t = content[i];
+            content[i] = content[slot];
+            content[slot] = t;
+        }
+        __syncthreads();
+    }
+    for (int s = lane; s < 2 * jb; s += 64) pm[s] = make_int2(rowid[s], content[s]);
+}
+
+// ----------------------------------------------------------------------------
+// Row permutation + triangular solve on a block of columns.
+// X: rows indexed like the factored matrix; columns [0, ncols).
+// mode 0: permute only.  mode 1: permute, then X[c0:c0+jb] = L11^-1 X[...]
+// with L11 the unit-lower diagonal block of LU at (c0, c0).
+// mode 2: no permutation, X[c0:c0+jb] = U11^-1 X[...] (non-unit upper).
+// ----------------------------------------------------------------------------
+constexpr int TS_NT = 256, TS_TC = 32;
+
+template <typename R>
+__global__ __launch_bounds__(TS_NT) void perm_trsm_kernel(
+    const typename cpx<R>::T* __restrict__ LU, long sLU, int ldl,
+    const int2* __restrict__ perm, long sPerm,
+    typename cpx<R>::T* __restrict__ X, long sX, int ldx,
+    int c0, int jb, int ncols, int mode, const int* __restrict__ active)
+{
+    typedef typename cpx<R>::T C;
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    const C* Lb = LU + (long)b * sLU;
+    C* Xb = X + (long)b * sX;
+    const int tid = threadIdx.x;
+    const int col = tid % TS_TC, grp = tid / TS_TC;  // 8 groups
+    constexpr int NG = TS_NT / TS_TC;
+    const int gcol = blockIdx.x * TS_TC + col;
+    const bool colok = gcol < ncols;
+
+    __shared__ C top[MAX_NB][TS_TC + 1];
+    __shared__ C Ld[MAX_NB][MAX_NB + 1];
+    __shared__ int2 pm[2 * MAX_NB];
+
+    if (mode != 2) {
+        const int2* pb = perm + (long)b * sPerm;
+        for (int s = tid; s < 2 * jb; s += TS_NT) pm[s] = pb[s];
+    }
+    if (mode != 0) {
+        // triangle into LDS (column-major read, coalesced along rows)
+        for (int e = tid; e < jb * jb; e += TS_NT) {
+            const int r = e % jb, c = e / jb;
+            Ld[r][c] = Lb[(c0 + r) + (long)(c0 + c) * ldl];
+        }
+    }
+    __syncthreads();
+
+    if (mode != 2) {
+        // gather every affected row (reads first, writes after the barrier)
+        constexpr int MAXQ = (2 * MAX_NB + NG - 1) / NG;
+        C val[MAXQ];
+#pragma unroll
+        for (int q = 0; q < MAXQ; ++q) {
+            const int s = grp + NG * q;
+            C e = czero<C>();
+            if (s < 2 * jb && colok) {
+                const int src = pm[s].y;
+                if (src >= 0) e = Xb[src + (long)gcol * ldx];
+            }
+            val[q] = e;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < MAXQ; ++q) {
+            const int s = grp + NG * q;
+            if (s < jb) {
+                top[s][col] = val[q];
+            } else if (s < 2 * jb && colok) {
+                const int dst = pm[s].x;
+                if (dst >= 0) Xb[dst + (long)gcol * ldx] = val[q];
+            }
+        }
+    } else {
+        for (int s = grp; s < jb; s += NG)
+            top[s][col] = colok ? Xb[(c0 + s) + (long)gcol * ldx] : czero<C>();
+    }
+    __syncthreads();
+
+    if (mode == 1) {
+        for (int l = 0; l < jb; ++l) {
+            const C xl = top[l][col];
+            for (int i = l + 1 + grp; i < jb; i += NG) top[i][col] = cfms(top[i][col], Ld[i][l], xl);
+            __syncthreads();
+        }
+    } else if (mode == 2) {
+        for (int l = jb - 1; l >= 0; --l) {
+            if (grp == 0) {
+                const C d = Ld[l][l];
+                top[l][col] = (d.x == (R)0 && d.y == (R)0) ? top[l][col] : cmul(top[l][col], crecip(d));
+            }
+            __syncthreads();
+            const C xl = top[l][col];
+            for (int i = grp; i < l; i += NG) top[i][col] = cfms(top[i][col], Ld[i][l], xl);
+            __syncthreads();
+        }
+    }
+
+    if (colok)
+        for (int s = grp; s < jb; s += NG) Xb[(c0 + s) + (long)gcol * ldx] = top[s][col];
+}
+
+// ----------------------------------------------------------------------------
+// host drivers
+// ----------------------------------------------------------------------------
+
+// Base width of the register-resident panel kernel for m rows.
+template <typename R> static int base_width(int m);
+template <> int base_width<float>(int m) { return m <= 4096 ? 8 : 4; }
+template <> int base_width<double>(int m) { return m <= 2048 ? 8 : (m <= 4096 ? 4 : 2); }
+
+template <typename R, int NT, int RPT, int JB>
+static void launch_base(hipStream_t st, typename cpx<R>::T* A, long sA, int lda, int n, int c0, int jb,
+                        int* ipiv, long sP, int* info, const int* active, int batch)
+{
+    hipLaunchKernelGGL((panel_base_kernel<R, NT, RPT, JB>), dim3(batch), dim3(NT), 0, st,
+                       A, sA, lda, n, c0, jb, ipiv, sP, info, active);
+}
+
+template <typename R>
+static void panel_base(hipStream_t st, typename cpx<R>::T* A, long sA, int lda, int n, int c0, int jb,
+                       int* ipiv, long sP, int* info, const int* active, int batch)
+{
+    const int m = n - c0;
+#define PB(NT, RPT, JB) launch_base<R, NT, RPT, JB>(st, A, sA, lda, n, c0, jb, ipiv, sP, info, active, batch)
+    if (m <= 256) {
+        PB(256, 1, 8);
+    } else if (m <= 512) {
+        PB(256, 2, 8);
+    } else if (m <= 1024) {
+        PB(256, 4, 8);
+    } else if (m <= 2048) {
+        PB(1024, 2, 8);
+    } else if (m <= 4096) {
+        if (sizeof(R) == 4) PB(1024, 4, 8); else PB(1024, 4, 4);
+    } else {
+        if (sizeof(R) == 4) PB(1024, 8, 4); else PB(1024, 8, 2);
+    }
+#undef PB
+}
+
+template <typename R>
+static void perm_trsm(hipStream_t st, const typename cpx<R>::T* LU, long sLU, int ldl, const int2* perm, long sPerm,
+                      typename cpx<R>::T* X, long sX, int ldx, int c0, int jb, int ncols, int mode,
+                      const int* active, int batch)
+{
+    if (ncols <= 0 || jb <= 0) return;
+    dim3 g((ncols + TS_TC - 1) / TS_TC, batch);
+    hipLaunchKernelGGL(perm_trsm_kernel<R>, g, dim3(TS_NT), 0, st, LU, sLU, ldl, perm, sPerm, X, sX, ldx, c0, jb,
+                       ncols, mode, active);
+}
+
+template <typename R>
+static hipError_t gemm_sub(hipStream_t st, int M, int N, int K, const typename cpx<R>::T* A, int lda, long sA,
+                           const typename cpx<R>::T* B, int ldb, long sB, typename cpx<R>::T* Cm, int ldc, long sC,
+                           int batch);
+template <>
+hipError_t gemm_sub<float>(hipStream_t st, int M, int N, int K, const float2* A, int lda, long sA, const float2* B,
+                           int ldb, long sB, float2* Cm, int ldc, long sC, int batch)
+{
+    return cgemm(st, M, N, K, -1.f, A, lda, sA, B, ldb, sB, 1.f, Cm, ldc, sC, batch);
+}
+template <>
+hipError_t gemm_sub<double>(hipStream_t st, int M, int N, int K, const double2* A, int lda, long sA,
+                            const double2* B, int ldb, long sB, double2* Cm, int ldc, long sC, int batch)
+{
+    return zgemm(st, 0, 0, M, N, K, -1.0, A, lda, sA, B, ldb, sB, 1.0, Cm, ldc, sC, batch);
+}
+
+// Recursive panel factorisation of columns [c0, c0+w) (rows c0..n-1).
+template <typename R>
+static void factor_panel(hipStream_t st, typename cpx<R>::T* A, long sA, int lda, int n, int c0, int w,
+                         int* ipiv, long sP, int* info, int2* tperm, long sTP, int depth, const int* active,
+                         int batch)
+{
+    const int m = n - c0;
+    const int jbase = base_width<R>(m);
+    if (w <= jbase) {
+        panel_base<R>(st, A, sA, lda, n, c0, w, ipiv, sP, info, active, batch);
+        return;
+    }
+    int w1 = (w / 2) / jbase * jbase;
+    if (w1 < jbase) w1 = jbase;
+    const int w2 = w - w1;
+    int2* pm = tperm + (long)depth * 2 * MAX_NB;
+    factor_panel<R>(st, A, sA, lda, n, c0, w1, ipiv, sP, info, tperm, sTP, depth + 1, active, batch);
+    // right half: interchanges of the left half, U12 = L11^-1 A12, A22 -= L21 U12
+    hipLaunchKernelGGL(perm_build_kernel, dim3(batch), dim3(64), 0, st, ipiv, sP, c0, w1, pm, sTP, active);
+    typename cpx<R>::T* Ar = A + (long)(c0 + w1) * lda;
+    perm_trsm<R>(st, A, sA, lda, pm, sTP, Ar, sA, lda, c0, w1, w2, 1, active, batch);
+    (void)gemm_sub<R>(st, m - w1, w2, w1, A + (c0 + w1) + (long)c0 * lda, lda, sA, A + c0 + (long)(c0 + w1) * lda, lda, sA,
+                A + (c0 + w1) + (long)(c0 + w1) * lda, lda, sA, batch);
+    factor_panel<R>(st, A, sA, lda, n, c0 + w1, w2, ipiv, sP, info, tperm, sTP, depth + 1, active, batch);
+    // left half receives the interchanges of the right half
+    hipLaunchKernelGGL(perm_build_kernel, dim3(batch), dim3(64), 0, st, ipiv, sP, c0 + w1, w2, pm, sTP, active);
+    perm_trsm<R>(st, A, sA, lda, pm, sTP, A + (long)c0 * lda, sA, lda, c0 + w1, w2, w1, 0, active, batch);
+}
+
+template <typename R>
+hipError_t getrf_batched(hipStream_t st, typename cpx<R>::T* A, long sA, int lda, int n, int nb, int* ipiv, long sP,
+                         int2* perm, long sPerm, int* info, int2* tperm, long sTP, const int* active, int batch)
+{
+    if (nb > MAX_NB) nb = MAX_NB;
+    for (int c0 = 0; c0 < n; c0 += nb) {
+        const int jb = (n - c0 < nb) ? n - c0 : nb;
+        factor_panel<R>(st, A, sA, lda, n, c0, jb, ipiv, sP, info, tperm, sTP, 0, active, batch);
+        int2* pm = perm + (long)(c0 / nb) * 2 * MAX_NB;
+        hipLaunchKernelGGL(perm_build_kernel, dim3(batch), dim3(64), 0, st, ipiv, sP, c0, jb, pm, sPerm, active);
+        const int rest = n - c0 - jb;
+        if (rest > 0) {
+            perm_trsm<R>(st, A, sA, lda, pm, sPerm, A + (long)(c0 + jb) * lda, sA, lda, c0, jb, rest, 1, active,
+                         batch);
+            (void)gemm_sub<R>(st, rest, rest, jb, A + (c0 + jb) + (long)c0 * lda, lda, sA, A + c0 + (long)(c0 + jb) * lda,
+                        lda, sA, A + (c0 + jb) + (long)(c0 + jb) * lda, lda, sA, batch);
+        }
+    }
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t getrs_batched(hipStream_t st, const typename cpx<R>::T* LU, long sLU, int lda, int n, int nb,
+                         const int2* perm, long sPerm, typename cpx<R>::T* X, long sX, int ldx, int nrhs,
+                         const int* active, int batch)
+{
+    if (nb > MAX_NB) nb = MAX_NB;
+    const int np = (n + nb - 1) / nb;
+    for (int p = 0; p < np; ++p) {
+        const int c0 = p * nb, jb = (n - c0 < nb) ? n - c0 : nb;
+        perm_trsm<R>(st, LU, sLU, lda, perm + (long)p * 2 * MAX_NB, sPerm, X, sX, ldx, c0, jb, nrhs, 1, active,
+                     batch);
+        const int rest = n - c0 - jb;
+        if (rest > 0)
+            (void)gemm_sub<R>(st, rest, nrhs, jb, LU + (c0 + jb) + (long)c0 * lda, lda, sLU, X + c0, ldx, sX, X + c0 + jb,
+                        ldx, sX, batch);
+    }
+    for (int p = np - 1; p >= 0; --p) {
+        const int c0 = p * nb, jb = (n - c0 < nb) ? n - c0 : nb;
+        perm_trsm<R>(st, LU, sLU, lda, nullptr, 0, X, sX, ldx, c0, jb, nrhs, 2, active, batch);
+        if (c0 > 0)
+            (void)gemm_sub<R>(st, c0, nrhs, jb, LU + (long)c0 * lda, lda, sLU, X + c0, ldx, sX, X, ldx, sX, batch);
+    }
+    return hipGetLastError();
+}
+
+template hipError_t getrf_batched<float>(hipStream_t, float2*, long, int, int, int, int*, long, int2*, long, int*,
+                                         int2*, long, const int*, int);
+template hipError_t getrf_batched<double>(hipStream_t, double2*, long, int, int, int, int*, long, int2*, long, int*,
+                                          int2*, long, const int*, int);
+template hipError_t getrs_batched<float>(hipStream_t, const float2*, long, int, int, int, const int2*, long, float2*,
+                                         long, int, int, const int*, int);
+template hipError_t getrs_batched<double>(hipStream_t, const double2*, long, int, int, int, const int2*, long,
+                                          double2*, long, int, int, const int*, int);
+
+}  // namespace rsrr

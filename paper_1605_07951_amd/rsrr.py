@@ -1,0 +1,309 @@
+"""Thin Python binding of the C ABI in include/rsrr.h (argument marshalling only).
+
+Every computation runs in the HIP library ``librsrr.so``; this module only
+converts NumPy/PyTorch arguments to pointers and sizes, and raises when the
+library is missing or a call fails.  Device memory is held in PyTorch CUDA
+(HIP) tensors; matrices are column-major, which a row-major PyTorch tensor
+of shape (cols, rows) provides (``colmajor``/``from_colmajor``).
+
+Names follow the C ABI: ``rsrr_create``, ``rsrr_sample``, ``rsrr_basis``,
+``rsrr_project``, ``rsrr_solve``, ``rsrr_contour``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librsrr.so")
+
+RSRR_OK = 0
+RSRR_ESINGULAR = 1
+RSRR_WARN_FALLBACK = 2
+RSRR_WARN_GAP = 3
+RSRR_ENOMEM = 4
+RSRR_EDEVICE = 5
+RSRR_ENOTCONV = 6
+RSRR_ENAN = 7
+RSRR_T_SEPARABLE = 0
+RSRR_T_HELMHOLTZ = 1
+RSRR_PREC_C128 = 0
+RSRR_PREC_C64_IR = 1
+
+STATUS_NAMES = {0: "OK", 1: "ESINGULAR", 2: "WARN_FALLBACK", 3: "WARN_GAP", 4: "ENOMEM", 5: "EDEVICE",
+                6: "ENOTCONV", 7: "ENAN"}
+
+EXPORTS = ["rsrr_create", "rsrr_destroy", "rsrr_contour", "rsrr_sample", "rsrr_basis", "rsrr_project",
+           "rsrr_solve", "rsrr_last_timings", "rsrr_version"]
+
+
+class RsrrTerm(C.Structure):
+    _fields_ = [("c_re", C.c_double), ("c_im", C.c_double), ("p", C.c_int), ("z0_re", C.c_double),
+                ("z0_im", C.c_double), ("tau", C.c_double), ("s_re", C.c_double), ("s_im", C.c_double),
+                ("q", C.c_int)]
+
+
+class RsrrNep(C.Structure):
+    _fields_ = [("kind", C.c_int), ("n", C.c_int), ("J", C.c_int), ("A", C.c_void_p), ("lda", C.c_int),
+                ("terms", C.POINTER(RsrrTerm)), ("points", C.c_void_p), ("w", C.c_double)]
+
+
+class RsrrPointInfo(C.Structure):
+    _fields_ = [("info", C.c_int), ("ir_iters", C.c_int), ("fallback", C.c_int), ("pad", C.c_int),
+                ("resid", C.c_double)]
+
+
+class RsrrSolveInfo(C.Structure):
+    _fields_ = [("nbar", C.c_int), ("warn_gap", C.c_int), ("gmax", C.c_double), ("n_sigma", C.c_int),
+                ("pad", C.c_int)]
+
+
+class RsrrError(RuntimeError):
+    def __init__(self, fn, code):
+        name = STATUS_NAMES.get(code, f"invalid argument {-code}" if code < 0 else str(code))
+        super().__init__(f"{fn} failed: {name} ({code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load librsrr.so (built in-tree); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    missing = [f for f in EXPORTS if not hasattr(L, f)]
+    if missing:
+        raise RuntimeError(f"{LIB_PATH} does not export {missing}")
+    dp, ip, vp = C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_void_p
+    L.rsrr_create.argtypes = [C.POINTER(vp), C.c_int, vp]
+    L.rsrr_destroy.argtypes = [vp]
+    L.rsrr_contour.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, dp, dp]
+    L.rsrr_sample.argtypes = [vp, C.POINTER(RsrrNep), C.c_int, dp, vp, C.c_int, C.c_int, C.c_int, vp, C.c_int,
+                              C.POINTER(RsrrPointInfo)]
+    L.rsrr_basis.argtypes = [vp, C.c_int, C.c_int, vp, C.c_int, C.c_double, vp, C.c_int, C.c_int, ip, dp]
+    L.rsrr_project.argtypes = [vp, C.POINTER(RsrrNep), vp, C.c_int, C.c_int, dp, C.c_double, vp, C.c_int, ip,
+                               C.POINTER(RsrrTerm)]
+    L.rsrr_solve.argtypes = [vp, C.POINTER(RsrrNep), C.c_int, vp, C.c_int, C.POINTER(RsrrTerm), vp, C.c_int, dp,
+                             C.c_double, C.c_double, C.c_int, C.c_int, C.c_double, C.c_int, dp, vp, C.c_int, dp,
+                             ip, dp, C.POINTER(RsrrSolveInfo)]
+    L.rsrr_last_timings.argtypes = [vp, dp]
+    L.rsrr_version.restype = C.c_char_p
+    for f in EXPORTS:
+        if f != "rsrr_version":
+            getattr(L, f).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(fn, code, ok=(RSRR_OK,)):
+    if code not in ok:
+        raise RsrrError(fn, code)
+    return code
+
+
+def _torch():
+    import torch
+    return torch
+
+
+# ----------------------------------------------------------------------------- layout helpers
+
+def colmajor(M, device="cuda"):
+    """Host (rows, cols) complex array -> device tensor holding it column-major; returns (tensor, ld)."""
+    torch = _torch()
+    M = np.asarray(M, dtype=np.complex128)
+    if M.ndim == 1:
+        M = M[:, None]
+    t = torch.from_numpy(np.ascontiguousarray(M.T)).to(device)
+    return t, M.shape[0]
+
+
+def from_colmajor(t, rows=None):
+    """Device tensor of shape (cols, ld) -> host (rows, cols) complex array."""
+    a = t.detach().cpu().numpy()
+    if rows is None:
+        rows = a.shape[1]
+    return np.ascontiguousarray(a[:, :rows].T)
+
+
+def term_struct(t):
+    return RsrrTerm(t["c"].real, t["c"].imag, int(t["p"]), t["z0"].real, t["z0"].imag, float(t["tau"]),
+                    t["s"].real, t["s"].imag, int(t["q"]))
+
+
+def terms_array(terms):
+    arr = (RsrrTerm * len(terms))()
+    for i, t in enumerate(terms):
+        arr[i] = term_struct(t)
+    return arr
+
+
+def term_from_struct(s):
+    return {"c": complex(s.c_re, s.c_im), "p": s.p, "z0": complex(s.z0_re, s.z0_im), "tau": s.tau,
+            "s": complex(s.s_re, s.s_im), "q": s.q}
+
+
+class DeviceNEP:
+    """A NEP whose data lives on the GPU, with the rsrr_nep descriptor pointing at it."""
+
+    def __init__(self, nep, device="cuda"):
+        torch = _torch()
+        self.host = nep
+        if hasattr(nep, "A"):
+            self.kind = RSRR_T_SEPARABLE
+            self.n = nep.A[0].shape[0]
+            stack = np.stack([np.ascontiguousarray(np.asarray(A, dtype=np.complex128).T) for A in nep.A])
+            self.A = torch.from_numpy(stack).to(device)
+            self.terms = list(nep.terms)
+            self._terms = terms_array(self.terms)
+            self.desc = RsrrNep(RSRR_T_SEPARABLE, self.n, len(nep.A), self.A.data_ptr(), self.n,
+                                C.cast(self._terms, C.POINTER(RsrrTerm)), None, 0.0)
+        else:
+            self.kind = RSRR_T_HELMHOLTZ
+            self.n = nep.points.shape[0]
+            self.points = torch.from_numpy(np.ascontiguousarray(nep.points, dtype=np.float64)).to(device)
+            self.w = float(nep.w)
+            self._terms = None
+            self.desc = RsrrNep(RSRR_T_HELMHOLTZ, self.n, 0, None, self.n, None, self.points.data_ptr(), self.w)
+
+
+class Context:
+    """An rsrr_ctx bound to a device and a HIP stream (default: torch's current stream)."""
+
+    def __init__(self, device=0, stream=None):
+        torch = _torch()
+        L = lib()
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        self.stream = stream
+        self.device = device
+        self.h = C.c_void_p()
+        _check("rsrr_create", L.rsrr_create(C.byref(self.h), device, C.c_void_p(stream)))
+
+    def close(self):
+        if self.h:
+            lib().rsrr_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def timings(self):
+        t = (C.c_double * 5)()
+        _check("rsrr_last_timings", lib().rsrr_last_timings(self.h, t))
+        return {"assemble_ms": t[0], "lu_ms": t[1], "solve_ms": t[2], "residual_ms": t[3], "total_ms": t[4]}
+
+
+def rsrr_create(device=0, stream=None):
+    return Context(device, stream)
+
+
+def rsrr_contour(gamma, a, b, N):
+    """Ellipse nodes and trapezoid weights (host, computed by the library)."""
+    z = (C.c_double * (2 * N))()
+    w = (C.c_double * (2 * N))()
+    g = complex(gamma)
+    _check("rsrr_contour", lib().rsrr_contour(g.real, g.imag, float(a), float(b), int(N), z, w))
+    za = np.frombuffer(z, dtype=np.float64).view(np.complex128).copy()
+    wa = np.frombuffer(w, dtype=np.float64).view(np.complex128).copy()
+    return za, wa
+
+
+def _zbuf(z):
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.complex128))
+    return z, z.view(np.float64).ctypes.data_as(C.POINTER(C.c_double))
+
+
+def rsrr_sample(ctx, dnep, z, U, prec=RSRR_PREC_C64_IR, S=None, ok=(RSRR_OK, RSRR_WARN_FALLBACK)):
+    """S = [T(z_k)^-1 U]_k on the GPU.  U: device tensor (L, n) (column-major n x L) or host array.
+
+    Returns (S tensor of shape (N*L, n) = column-major n x N*L, info list, status).
+    """
+    torch = _torch()
+    n = dnep.n
+    if not torch.is_tensor(U):
+        U, _ = colmajor(U)
+    L = U.shape[0]
+    ldu = U.shape[1]
+    zc, zp = _zbuf(z)
+    N = zc.size
+    if S is None:
+        S = torch.empty((N * L, n), dtype=torch.complex128, device=U.device)
+    lds = S.shape[1]
+    info = (RsrrPointInfo * N)()
+    code = lib().rsrr_sample(ctx.h, C.byref(dnep.desc), N, zp, U.data_ptr(), L, ldu, int(prec), S.data_ptr(), lds,
+                             info)
+    _check("rsrr_sample", code, ok)
+    infos = [{"info": i.info, "ir_iters": i.ir_iters, "fallback": i.fallback, "resid": i.resid} for i in info]
+    return S, infos, code
+
+
+def rsrr_basis(ctx, S, n, delta=1e-14, kmax=None):
+    """Normalise S in place, truncated SVD basis.  Returns (Q tensor (kmax, n), k, sigma)."""
+    torch = _torch()
+    NL = S.shape[0]
+    lds = S.shape[1]
+    m = min(n, NL)
+    kmax = m if kmax is None else kmax
+    Q = torch.zeros((kmax, n), dtype=torch.complex128, device=S.device)
+    k = C.c_int(0)
+    sig = (C.c_double * m)()
+    _check("rsrr_basis", lib().rsrr_basis(ctx.h, n, NL, S.data_ptr(), lds, float(delta), Q.data_ptr(), n, kmax,
+                                          C.byref(k), sig))
+    return Q, k.value, np.frombuffer(sig, dtype=np.float64).copy()
+
+
+def rsrr_project(ctx, dnep, Q, k, gamma, radius, max_terms=64):
+    """Projected coefficients Q^H A_j Q (device tensor (J_eff, k, k) column-major) and their terms."""
+    torch = _torch()
+    n = dnep.n
+    ldq = Q.shape[1]
+    AQ = torch.zeros((max_terms, k, k), dtype=torch.complex128, device=Q.device)
+    J = C.c_int(0)
+    tout = (RsrrTerm * max_terms)()
+    g = (C.c_double * 2)(complex(gamma).real, complex(gamma).imag)
+    _check("rsrr_project", lib().rsrr_project(ctx.h, C.byref(dnep.desc), Q.data_ptr(), ldq, k, g, float(radius),
+                                              AQ.data_ptr(), max_terms, C.byref(J), tout))
+    terms = [term_from_struct(tout[i]) for i in range(J.value)]
+    return AQ[:J.value], terms
+
+
+def rsrr_solve(ctx, dnep, Q, k, AQ, terms, gamma, a, b, NQ=500, KQ=2, tol_gap=1e3, max_eigs=None,
+               ok=(RSRR_OK, RSRR_WARN_GAP)):
+    """SS-FULL on the projected NEP and lift.  Returns dict with lam, V (host), resid, info, status."""
+    torch = _torch()
+    n = dnep.n
+    ldq = Q.shape[1]
+    max_eigs = max_eigs or min(k * KQ, 512)
+    lam = (C.c_double * (2 * max_eigs))()
+    V = torch.zeros((max_eigs, n), dtype=torch.complex128, device=Q.device)
+    res = (C.c_double * max_eigs)()
+    cnt = C.c_int(0)
+    sigH = (C.c_double * (KQ * k))()
+    sinfo = RsrrSolveInfo()
+    tarr = terms_array(terms)
+    g = (C.c_double * 2)(complex(gamma).real, complex(gamma).imag)
+    code = lib().rsrr_solve(ctx.h, C.byref(dnep.desc), k, AQ.data_ptr(), len(terms),
+                            C.cast(tarr, C.POINTER(RsrrTerm)), Q.data_ptr(), ldq, g, float(a), float(b), int(NQ),
+                            int(KQ), float(tol_gap), max_eigs, lam, V.data_ptr(), n, res, C.byref(cnt), sigH,
+                            C.byref(sinfo))
+    _check("rsrr_solve", code, ok)
+    m = cnt.value
+    lam_np = np.frombuffer(lam, dtype=np.float64).view(np.complex128)[:m].copy()
+    return {"lam": lam_np, "V": from_colmajor(V[:m], n), "resid": np.frombuffer(res, dtype=np.float64)[:m].copy(),
+            "nbar": sinfo.nbar, "warn_gap": bool(sinfo.warn_gap), "gmax": sinfo.gmax,
+            "sigma_H": np.frombuffer(sigH, dtype=np.float64)[:sinfo.n_sigma].copy(), "status": code}
+
+
+def rsrr_version():
+    return lib().rsrr_version().decode()
