@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Benchmark of the RSRR resolvent-sampling hot path on one MI355X.
+
+Workload (default): the dense BEM-like Helmholtz NEP on the unit sphere,
+n = 4096 Fibonacci collocation points, ellipse (3.8; 1.4, 0.3), N = 64
+sampling points, L = 64 complex Gaussian probes; complex-FP32 LU on the
+matrix cores with FP64 iterative refinement.  Inputs are synthetic and
+seeded and live in HBM before the timed region starts.
+
+One step = rsrr_sample over all N points (assembly, LU, solves, refinement)
+followed by rsrr_basis (normalisation + truncated SVD) and rsrr_project when
+those are available.  value = N * steps / elapsed (resolvent solves/s).
+
+Prints one JSON line (see the repository's benchmark contract), with a
+"roofline" object for the LU trailing-update kernel (HIP events around every
+launch inside the timed region) and a "cpu_baseline" object (the CPU oracle
+timed on a bounded sample of the same workload).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "resolvent solves/sec (n=4096, L=64) & % MFMA peak; p50/p99 NEP latency"
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_FP64_MFMA_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="helmholtz", choices=["helmholtz", "delay", "qep"])
+    ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--N", type=int, default=None)
+    ap.add_argument("--L", type=int, default=None)
+    ap.add_argument("--prec", default="mixed", choices=["mixed", "c128"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-points", type=int, default=None, help="sampling points in the CPU sample")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison run")
+    ap.add_argument("--sample-only", action="store_true", help="time rsrr_sample only")
+    return ap.parse_args()
+
+
+def build_workload(args):
+    import workloads as W
+    if args.workload == "helmholtz":
+        n = args.n or 4096
+        nep, C, U = W.cfg_helmholtz(n=n, N=args.N or 64, L=args.L or 64)
+        desc = f"helmholtz_sphere n={n} N={C.N} L={U.shape[1]} ellipse(3.8;1.4,0.3)"
+    elif args.workload == "delay":
+        nx = int(round(math.sqrt(args.n or 1024)))
+        nep, C, U = W.cfg_delay(nx=nx, N=args.N or 48, L=args.L or 32, parity=False)
+        desc = f"delay_laplacian n={nep.n} N={C.N} L={U.shape[1]} circle(-20,15)"
+    else:
+        nep, C, U = W.cfg_qep(n=args.n or 200, N=args.N or 32, L=args.L or 16)
+        desc = f"rotated_diag_qep n={nep.n} N={C.N} L={U.shape[1]} ellipse(5i;4,1)"
+    return nep, C, U, desc
+
+
+def cpu_baseline(nep, C, U, npts):
+    """Time the CPU oracle's sampling on npts points of the same workload."""
+    from oracle import rsrr_oracle as O
+    threads = os.cpu_count() or 1
+    try:
+        from threadpoolctl import threadpool_info
+        info = threadpool_info()
+        if info:
+            threads = max(int(i.get("num_threads", 1)) for i in info)
+    except Exception:
+        pass
+    prob = O.Problem(nep)
+    z, _ = O.ellipse(C.gamma, C.a, C.b, C.N)
+    pts = z[:npts]
+    t0 = time.perf_counter()
+    O.sample(prob, pts, U)
+    dt = time.perf_counter() - t0
+    return {"value": npts / dt, "unit": "resolvent solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"{npts} of {C.N} sampling points of the same workload (assembly + zgetrf + zgetrs, "
+                      f"FP64, NumPy/SciPy LAPACK), {dt:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1",
+                          "n_gpus_requested": args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_1605_07951_amd import rsrr as R
+
+    nep, C, U_host, desc = build_workload(args)
+    n, L, N = nep.n, U_host.shape[1], C.N
+    dev = torch.device("cuda:0")
+    ctx = R.rsrr_create(0)
+    dnep = R.DeviceNEP(nep)
+    U, _ = R.colmajor(U_host)
+    z, _ = R.rsrr_contour(C.gamma, C.a, C.b, N)
+    prec = R.RSRR_PREC_C64_IR if args.prec == "mixed" else R.RSRR_PREC_C128
+    S = torch.empty((N * L, n), dtype=torch.complex128, device=dev)
+    have_basis = not args.sample_only
+    kmax = min(n, N * L)
+    radius = max(C.a, C.b)
+
+    def step():
+        _, info, _ = R.rsrr_sample(ctx, dnep, z, U, prec=prec, S=S)
+        out = {"info": info}
+        if have_basis:
+            Q, k, sig = R.rsrr_basis(ctx, S, n, 1e-14, kmax=kmax)
+            out["k"] = k
+            R.rsrr_project(ctx, dnep, Q, k, C.gamma, radius)
+        return out
+
+    # probe whether basis/project are implemented
+    if have_basis:
+        try:
+            step()
+        except R.RsrrError:
+            have_basis = False
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    R.rsrr_update_stats(ctx, enable=True, reset=True)
+    sample_ms = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = None
+    for _ in range(args.steps):
+        last = step()
+        sample_ms += ctx.timings()["total_ms"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = R.rsrr_update_stats(ctx, enable=False)
+    tm = ctx.timings()
+
+    value = N * args.steps / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+    peak = PEAK_FP32_MFMA_TFLOPS if prec == R.RSRR_PREC_C64_IR else PEAK_FP64_MFMA_TFLOPS
+    avg_ms = st["ms"] / max(1, st["launches"])
+    achieved = (st["flops"] / (st["ms"] * 1e-3) / 1e12) if st["ms"] > 0 else 0.0
+    info = last["info"]
+    res = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "resolvent solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 LU (f32 MFMA) + f64 refinement" if prec == R.RSRR_PREC_C64_IR else "c128 (f64 MFMA)",
+        "data": "synthetic (seeded Fibonacci-sphere Helmholtz single-layer NEP, complex Gaussian probes)",
+        "config": {"workload": desc, "n": n, "N": N, "L": L, "precision": args.prec,
+                   "step": "rsrr_sample" + (" + rsrr_basis + rsrr_project" if have_basis else "")},
+        "roofline": {"bound": "mfma", "kernel": "LU trailing update (cgemm_mfma_kernel<*,1>)"
+                     if prec == R.RSRR_PREC_C64_IR else "LU trailing update (zgemm_mfma_kernel<0,0,1>)",
+                     "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "launches": st["launches"], "avg_launch_ms": round(avg_ms, 4),
+                     "flops_per_launch": st["flops"] / max(1, st["launches"])},
+        "sample_solves_per_s": round(N * args.steps / (sample_ms * 1e-3), 3) if sample_ms > 0 else None,
+        "phase_ms_last_step": {k: round(v, 3) for k, v in tm.items()},
+        "ir_iters_max": max(i["ir_iters"] for i in info),
+        "resid_max": max(i["resid"] for i in info),
+        "fallbacks": sum(i["fallback"] for i in info),
+    }
+    if have_basis and last and "k" in last:
+        res["basis_k"] = last["k"]
+
+    if not args.no_plain and prec == R.RSRR_PREC_C64_IR:
+        # plain FP64 path on the same inputs for the mixed/plain speedup
+        R.rsrr_sample(ctx, dnep, z, U, prec=R.RSRR_PREC_C128, S=S)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        R.rsrr_sample(ctx, dnep, z, U, prec=R.RSRR_PREC_C128, S=S)
+        torch.cuda.synchronize()
+        dtp = time.perf_counter() - t1
+        res["plain_c128_sample_solves_per_s"] = round(N / dtp, 3)
+        if res["sample_solves_per_s"]:
+            res["mixed_over_plain_speedup"] = round(res["sample_solves_per_s"] / (N / dtp), 3)
+
+    if not args.no_cpu:
+        npts = args.cpu_points or (4 if n >= 2048 else min(N, 16))
+        res["cpu_baseline"] = cpu_baseline(nep, C, U_host, npts)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -200,6 +200,15 @@ RSRR_API rsrr_status rsrr_solve(rsrr_ctx *ctx, const rsrr_nep *nep, int k, const
  * t[3] FP64 residuals, t[4] total.  t: host, 5 doubles.  Errors: -2 t NULL. */
 RSRR_API rsrr_status rsrr_last_timings(rsrr_ctx *ctx, double *t);
 
+/* Device-event statistics of the LU trailing-update kernel (A22 -= L21 U12,
+ * the matrix-core hot loop of rsrr_sample).  enable = 1 starts recording a
+ * pair of events around every trailing-update launch of later rsrr_sample
+ * calls, 0 stops; reset = 1 clears the totals.  out (host, 4 doubles, may be
+ * NULL): launches timed, summed kernel time in ms, algorithmic flops of the
+ * timed launches (8 m^2 k per complex m x m x k update and matrix), launches
+ * not timed (event pool exhausted).  Errors: -1 ctx NULL. */
+RSRR_API rsrr_status rsrr_update_stats(rsrr_ctx *ctx, int enable, int reset, double *out);
+
 /* Library version string (static storage). */
 RSRR_API const char *rsrr_version(void);
 

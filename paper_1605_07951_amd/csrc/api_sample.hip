@@ -31,6 +31,22 @@ void* ws_get(rsrr_ctx* c, int s, size_t bytes)
     return p;
 }
 
+void rec_collect(rsrr_ctx* c)
+{
+    if (!c->rec.ev) return;
+    for (int i = 0; i < c->rec.used; ++i) {
+        (void)hipEventSynchronize(c->rec.ev[2 * i + 1]);
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->rec.ev[2 * i], c->rec.ev[2 * i + 1]) == hipSuccess) c->upd_ms += ms;
+    }
+    c->upd_launches += c->rec.used;
+    c->upd_flops += c->rec.flops;
+    c->upd_dropped += c->rec.dropped;
+    c->rec.used = 0;
+    c->rec.flops = 0.0;
+    c->rec.dropped = 0;
+}
+
 zd term_eval(const rsrr_term& t, zd z)
 {
     zd v(t.c_re, t.c_im);
@@ -68,6 +84,10 @@ rsrr_status rsrr_destroy(rsrr_ctx* c)
     for (int s = 0; s < WS_COUNT; ++s)
         if (c->ws[s]) (void)hipFree(c->ws[s]);
     for (auto& e : c->ev) (void)hipEventDestroy(e);
+    if (c->rec.ev) {
+        for (int i = 0; i < 2 * c->rec.cap; ++i) (void)hipEventDestroy(c->rec.ev[i]);
+        delete[] c->rec.ev;
+    }
     delete c;
     return RSRR_OK;
 }
@@ -86,6 +106,30 @@ rsrr_status rsrr_contour(double gre, double gim, double a, double b, int N, doub
             w[2 * j] = -a * std::sin(t) / N;
             w[2 * j + 1] = b * std::cos(t) / N;
         }
+    }
+    return RSRR_OK;
+}
+
+rsrr_status rsrr_update_stats(rsrr_ctx* c, int enable, int reset, double* out)
+{
+    if (!c) return -1;
+    RSRR_HIP(hipSetDevice(c->device));
+    if (enable && !c->rec.ev) {
+        const int cap = 8192;
+        c->rec.ev = new hipEvent_t[2 * cap];
+        for (int i = 0; i < 2 * cap; ++i) RSRR_HIP(hipEventCreate(&c->rec.ev[i]));
+        c->rec.cap = cap;
+    }
+    c->rec_on = enable != 0;
+    if (reset) {
+        c->upd_ms = c->upd_flops = 0.0;
+        c->upd_launches = c->upd_dropped = 0;
+    }
+    if (out) {
+        out[0] = (double)c->upd_launches;
+        out[1] = c->upd_ms;
+        out[2] = c->upd_flops;
+        out[3] = (double)c->upd_dropped;
     }
     return RSRR_OK;
 }
@@ -254,11 +298,14 @@ static rsrr_status sample_batch(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, i
         RSRR_HIP(hipMemsetAsync(s.info, 0, (size_t)B * 4, c->stream));
         if (prec == RSRR_PREC_C128)
             RSRR_HIP(getrf_batched<double>(c->stream, (double2*)s.Tlu, s.sT, s.ld, n, c->nb_c128, s.ipiv, s.sP, s.perm,
-                                           s.sPerm, s.info, s.tperm, s.sTP, nullptr, B));
+                                           s.sPerm, s.info, s.tperm, s.sTP, nullptr, B,
+                                           c->rec_on ? &c->rec : nullptr));
         else
             RSRR_HIP(getrf_batched<float>(c->stream, (float2*)s.Tlu, s.sT, s.ld, n, c->nb_c64, s.ipiv, s.sP, s.perm,
-                                          s.sPerm, s.info, s.tperm, s.sTP, nullptr, B));
+                                          s.sPerm, s.info, s.tperm, s.sTP, nullptr, B,
+                                          c->rec_on ? &c->rec : nullptr));
         t.stop();
+        if (c->rec_on) rec_collect(c);
         RSRR_HIP(hipMemcpyAsync(hinfo.data(), s.info, (size_t)B * 4, hipMemcpyDeviceToHost, c->stream));
         RSRR_HIP(hipStreamSynchronize(c->stream));
     }
@@ -390,6 +437,38 @@ static rsrr_status sample_batch(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, i
 }
 
 }  // namespace
+
+rsrr_status assemble_c128(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, int B, double2* T, int ld, long sT,
+                          double* frob)
+{
+    const int n = nep->n;
+    const long nparts = ((long)n * n + 255) / 256;
+    double* frobp = (double*)ws_get(c, WS_FROBP, (size_t)B * nparts * 8);
+    if (!frobp) return RSRR_ENOMEM;
+    if (nep->kind == RSRR_T_SEPARABLE) {
+        double2* coef = (double2*)ws_get(c, WS_COEF, (size_t)nep->J * B * 16);
+        if (!coef) return RSRR_ENOMEM;
+        std::vector<double2> cf((size_t)nep->J * B);
+        for (int j = 0; j < nep->J; ++j)
+            for (int k = 0; k < B; ++k) {
+                zd f = term_eval(nep->terms[j], z[k]);
+                cf[(size_t)j * B + k] = make_double2(f.real(), f.imag());
+            }
+        RSRR_HIP(hipMemcpyAsync(coef, cf.data(), cf.size() * 16, hipMemcpyHostToDevice, c->stream));
+        RSRR_HIP(hipStreamSynchronize(c->stream));
+        RSRR_HIP(assemble_separable(c->stream, n, nep->J, (const double2*)nep->A, nep->lda, coef, B, nullptr, 0, 0, T,
+                                    ld, sT, frobp, frob));
+    } else {
+        double2* zdev = (double2*)ws_get(c, WS_Z, (size_t)B * 16);
+        if (!zdev) return RSRR_ENOMEM;
+        std::vector<double2> zz(B);
+        for (int k = 0; k < B; ++k) zz[k] = make_double2(z[k].real(), z[k].imag());
+        RSRR_HIP(hipMemcpyAsync(zdev, zz.data(), (size_t)B * 16, hipMemcpyHostToDevice, c->stream));
+        RSRR_HIP(hipStreamSynchronize(c->stream));
+        RSRR_HIP(assemble_helmholtz(c->stream, n, nep->points, nep->w, zdev, B, nullptr, 0, 0, T, ld, sT, frobp, frob));
+    }
+    return RSRR_OK;
+}
 
 extern "C" rsrr_status rsrr_sample(rsrr_ctx* c, const rsrr_nep* nep, int N, const double* z, const double* U, int L,
                                    int ldu, int prec, double* S, int lds, rsrr_point_info* info)

@@ -6,6 +6,7 @@
 #include <complex>
 #include <vector>
 
+#include "kernels.h"
 #include "rsrr.h"
 
 typedef std::complex<double> zd;
@@ -29,10 +30,28 @@ struct rsrr_ctx {
     int nb_c128 = 64;      // outer LU panel width, complex FP64 path
     int ir_max_iters = 10;
     size_t ws_budget = 0;  // bytes for the per-point sampling buffers (0 = half of free memory)
+    // trailing-update statistics (rsrr_update_stats)
+    bool rec_on = false;
+    rsrr::UpdateRecorder rec;
+    double upd_ms = 0.0, upd_flops = 0.0;
+    long upd_launches = 0, upd_dropped = 0;
 };
+
+// Fold the recorded update events into the running statistics (syncs the events).
+void rec_collect(rsrr_ctx* c);
 
 // Grow workspace slot `s` to at least `bytes`; returns nullptr on failure.
 void* ws_get(rsrr_ctx* c, int s, size_t bytes);
+
+// Assemble T(z_k) in complex FP64 for B host points into T (ld, stride sT);
+// frob (device, B doubles) receives ||T(z_k)||_F.  Uses workspace slots
+// WS_COEF, WS_Z and WS_FROBP.
+rsrr_status assemble_c128(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, int B, double2* T, int ld, long sT,
+                          double* frob);
+
+// One-sided Jacobi SVD (api_basis): see jacobi_round.  Returns sweeps or -1.
+int jacobi_svd(rsrr_ctx* c, double2* A, int lda, int m, int m_apply, int p, int max_sweeps, double tol,
+               rsrr_status* st);
 
 // f(z) = c (z - z0)^p exp(-tau z) / (z - s)^q
 zd term_eval(const rsrr_term& t, zd z);

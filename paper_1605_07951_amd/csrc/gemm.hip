@@ -22,7 +22,8 @@ namespace rsrr {
 // ----------------------------------------------------------------------------
 constexpr int CG_BM = 128, CG_BN = 128, CG_KT = 16, CG_NT = 256;
 
-template <bool VEC>
+// TAG only distinguishes kernel symbols (1 = LU trailing update) for profilers.
+template <bool VEC, int TAG>
 __global__ __launch_bounds__(CG_NT, 2) void cgemm_mfma_kernel(
     int M, int N, int K, float alpha,
     const float2* __restrict__ A, int lda, long sA,
@@ -172,19 +173,22 @@ __global__ __launch_bounds__(CG_NT, 2) void cgemm_mfma_kernel(
 
 hipError_t cgemm(hipStream_t st, int M, int N, int K, float alpha,
                  const float2* A, int lda, long sA, const float2* B, int ldb, long sB,
-                 float beta, float2* C, int ldc, long sC, int batch)
+                 float beta, float2* C, int ldc, long sC, int batch, int tag)
 {
     if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
     const int tm = (M + CG_BM - 1) / CG_BM, tn = (N + CG_BN - 1) / CG_BN;
     const long total = round_up_l((long)tm * tn * batch, 8);
     const bool vec = ((((uintptr_t)A) | ((uintptr_t)B)) & 15) == 0 && (lda % 2 == 0) && (ldb % 2 == 0)
                      && (sA % 2 == 0) && (sB % 2 == 0);
-    if (vec)
-        hipLaunchKernelGGL(cgemm_mfma_kernel<true>, dim3((unsigned)total), dim3(CG_NT), 0, st,
-                           M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, tm, tn, batch, total);
-    else
-        hipLaunchKernelGGL(cgemm_mfma_kernel<false>, dim3((unsigned)total), dim3(CG_NT), 0, st,
-                           M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, tm, tn, batch, total);
+#define CG_LAUNCH(V, T)                                                                                       \
+    hipLaunchKernelGGL((cgemm_mfma_kernel<V, T>), dim3((unsigned)total), dim3(CG_NT), 0, st, M, N, K, alpha, A, lda, \
+                       sA, B, ldb, sB, beta, C, ldc, sC, tm, tn, batch, total)
+    if (vec) {
+        if (tag == 1) CG_LAUNCH(true, 1); else CG_LAUNCH(true, 0);
+    } else {
+        if (tag == 1) CG_LAUNCH(false, 1); else CG_LAUNCH(false, 0);
+    }
+#undef CG_LAUNCH
     return hipGetLastError();
 }
 
@@ -194,7 +198,7 @@ hipError_t cgemm(hipStream_t st, int M, int N, int K, float alpha,
 // ----------------------------------------------------------------------------
 constexpr int ZG_BM = 64, ZG_BN = 64, ZG_KT = 16, ZG_NT = 256;
 
-template <bool CA, bool CB>
+template <bool CA, bool CB, int TAG>
 __global__ __launch_bounds__(ZG_NT, 2) void zgemm_mfma_kernel(
     int M, int N, int K, double alpha,
     const double2* __restrict__ A, int lda, long sA,
@@ -334,16 +338,19 @@ __global__ __launch_bounds__(ZG_NT, 2) void zgemm_mfma_kernel(
 
 hipError_t zgemm(hipStream_t st, int opA, int opB, int M, int N, int K, double alpha,
                  const double2* A, int lda, long sA, const double2* B, int ldb, long sB,
-                 double beta, double2* C, int ldc, long sC, int batch)
+                 double beta, double2* C, int ldc, long sC, int batch, int tag)
 {
     if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
     const int tm = (M + ZG_BM - 1) / ZG_BM, tn = (N + ZG_BN - 1) / ZG_BN;
     const long total = round_up_l((long)tm * tn * batch, 8);
     dim3 g((unsigned)total), blk(ZG_NT);
-#define ZG_LAUNCH(CA, CB)                                                                        \
-    hipLaunchKernelGGL((zgemm_mfma_kernel<CA, CB>), g, blk, 0, st, M, N, K, alpha, A, lda, sA, B, \
+#define ZG_LAUNCH(CA, CB)                                                                              \
+    hipLaunchKernelGGL((zgemm_mfma_kernel<CA, CB, 0>), g, blk, 0, st, M, N, K, alpha, A, lda, sA, B,       \
                        ldb, sB, beta, C, ldc, sC, tm, tn, batch, total)
-    if (!opA && !opB) ZG_LAUNCH(false, false);
+    if (tag == 1 && !opA && !opB)
+        hipLaunchKernelGGL((zgemm_mfma_kernel<false, false, 1>), g, blk, 0, st, M, N, K, alpha, A, lda, sA, B,
+                           ldb, sB, beta, C, ldc, sC, tm, tn, batch, total);
+    else if (!opA && !opB) ZG_LAUNCH(false, false);
     else if (opA && !opB) ZG_LAUNCH(true, false);
     else if (!opA && opB) ZG_LAUNCH(false, true);
     else ZG_LAUNCH(true, true);

@@ -11,15 +11,25 @@ namespace rsrr {
 constexpr int MAX_NB = 64;
 
 // C = beta*C + alpha*A*B, complex single on v_mfma_f32_32x32x2f32.
+// tag 1 launches a separately named instance (the LU trailing update).
 hipError_t cgemm(hipStream_t st, int M, int N, int K, float alpha,
                  const float2* A, int lda, long sA, const float2* B, int ldb, long sB,
-                 float beta, float2* C, int ldc, long sC, int batch);
+                 float beta, float2* C, int ldc, long sC, int batch, int tag = 0);
 
 // C = beta*C + alpha*op(A)*op(B), complex double on v_mfma_f64_16x16x4f64;
 // op = conjugate transpose when the flag is set.
 hipError_t zgemm(hipStream_t st, int opA, int opB, int M, int N, int K, double alpha,
                  const double2* A, int lda, long sA, const double2* B, int ldb, long sB,
-                 double beta, double2* C, int ldc, long sC, int batch);
+                 double beta, double2* C, int ldc, long sC, int batch, int tag = 0);
+
+// Event recorder around the LU trailing-update launches (optional).
+struct UpdateRecorder {
+    hipEvent_t* ev = nullptr;   // pool of 2*cap events
+    int cap = 0;
+    int used = 0;               // pairs recorded
+    double flops = 0.0;         // algorithmic flops of the recorded launches (8 m n k)
+    long dropped = 0;           // launches beyond the pool (not timed)
+};
 
 // Blocked LU with partial pivoting of `batch` n x n matrices (stride sA).
 // ipiv: n ints per matrix (stride sP).  perm: ceil(n/nb)*2*MAX_NB int2 per
@@ -29,7 +39,7 @@ hipError_t zgemm(hipStream_t st, int opA, int opB, int M, int N, int K, double a
 template <typename R>
 hipError_t getrf_batched(hipStream_t st, typename cpx<R>::T* A,
                          long sA, int lda, int n, int nb, int* ipiv, long sP, int2* perm, long sPerm, int* info,
-                         int2* tperm, long sTP, const int* active, int batch);
+                         int2* tperm, long sTP, const int* active, int batch, UpdateRecorder* rec = nullptr);
 
 template <typename R>
 hipError_t getrs_batched(hipStream_t st, const typename cpx<R>::T* LU,
@@ -61,5 +71,19 @@ hipError_t axpy_widen(hipStream_t st, int n, int L, const float2* D, int ldd, lo
 hipError_t copy_c128(hipStream_t st, int n, int m, const double2* X, int ldx, long sX, double2* Y, int ldy, long sY,
                      int B);
 hipError_t scale_cols(hipStream_t st, int n, int m, double2* X, int ldx, const double* s);
+
+// ---- block one-sided Jacobi SVD (basis.hip) ----
+int jacobi_blocks(int p);  // number of column blocks (even) for p columns
+hipError_t jacobi_round(hipStream_t st, double2* A, int lda, int m, int m_apply, int p, int round, int inner,
+                        double tol, double* offmax);
+hipError_t gather_scale(hipStream_t st, const double2* A, int lda, int m, const int* order, const double* inv,
+                        double2* Q, int ldq, int k);
+
+// ---- SS-FULL helpers (ssfull.hip) ----
+hipError_t hankel(hipStream_t st, const double2* mom, int k, int K, int shift, double2* H, int ldh);
+hipError_t eye(hipStream_t st, double2* X, int ldx, int r0, int p);
+hipError_t norm1(hipStream_t st, const double2* T, int ld, long sT, int n, double* out, int B);
+hipError_t small_eig(hipStream_t st, const double2* A, int n, double2* H, double2* Z, double2* lam, double2* Bv,
+                     int* status);
 
 }  // namespace rsrr

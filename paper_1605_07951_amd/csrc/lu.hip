@@ -367,18 +367,18 @@ static void perm_trsm(hipStream_t st, const typename cpx<R>::T* LU, long sLU, in
 template <typename R>
 static hipError_t gemm_sub(hipStream_t st, int M, int N, int K, const typename cpx<R>::T* A, int lda, long sA,
                            const typename cpx<R>::T* B, int ldb, long sB, typename cpx<R>::T* Cm, int ldc, long sC,
-                           int batch);
+                           int batch, int tag = 0);
 template <>
 hipError_t gemm_sub<float>(hipStream_t st, int M, int N, int K, const float2* A, int lda, long sA, const float2* B,
-                           int ldb, long sB, float2* Cm, int ldc, long sC, int batch)
+                           int ldb, long sB, float2* Cm, int ldc, long sC, int batch, int tag)
 {
-    return cgemm(st, M, N, K, -1.f, A, lda, sA, B, ldb, sB, 1.f, Cm, ldc, sC, batch);
+    return cgemm(st, M, N, K, -1.f, A, lda, sA, B, ldb, sB, 1.f, Cm, ldc, sC, batch, tag);
 }
 template <>
 hipError_t gemm_sub<double>(hipStream_t st, int M, int N, int K, const double2* A, int lda, long sA,
-                            const double2* B, int ldb, long sB, double2* Cm, int ldc, long sC, int batch)
+                            const double2* B, int ldb, long sB, double2* Cm, int ldc, long sC, int batch, int tag)
 {
-    return zgemm(st, 0, 0, M, N, K, -1.0, A, lda, sA, B, ldb, sB, 1.0, Cm, ldc, sC, batch);
+    return zgemm(st, 0, 0, M, N, K, -1.0, A, lda, sA, B, ldb, sB, 1.0, Cm, ldc, sC, batch, tag);
 }
 
 // Recursive panel factorisation of columns [c0, c0+w) (rows c0..n-1).
@@ -412,7 +412,8 @@ static void factor_panel(hipStream_t st, typename cpx<R>::T* A, long sA, int lda
 
 template <typename R>
 hipError_t getrf_batched(hipStream_t st, typename cpx<R>::T* A, long sA, int lda, int n, int nb, int* ipiv, long sP,
-                         int2* perm, long sPerm, int* info, int2* tperm, long sTP, const int* active, int batch)
+                         int2* perm, long sPerm, int* info, int2* tperm, long sTP, const int* active, int batch,
+                         UpdateRecorder* rec)
 {
     if (nb > MAX_NB) nb = MAX_NB;
     for (int c0 = 0; c0 < n; c0 += nb) {
@@ -424,8 +425,17 @@ hipError_t getrf_batched(hipStream_t st, typename cpx<R>::T* A, long sA, int lda
         if (rest > 0) {
             perm_trsm<R>(st, A, sA, lda, pm, sPerm, A + (long)(c0 + jb) * lda, sA, lda, c0, jb, rest, 1, active,
                          batch);
+            const bool timed = rec && rec->used < rec->cap;
+            if (timed) (void)hipEventRecord(rec->ev[2 * rec->used], st);
             (void)gemm_sub<R>(st, rest, rest, jb, A + (c0 + jb) + (long)c0 * lda, lda, sA, A + c0 + (long)(c0 + jb) * lda,
-                        lda, sA, A + (c0 + jb) + (long)(c0 + jb) * lda, lda, sA, batch);
+                        lda, sA, A + (c0 + jb) + (long)(c0 + jb) * lda, lda, sA, batch, 1);
+            if (timed) {
+                (void)hipEventRecord(rec->ev[2 * rec->used + 1], st);
+                rec->used++;
+                rec->flops += 8.0 * rest * (double)rest * jb * batch;
+            } else if (rec) {
+                rec->dropped++;
+            }
         }
     }
     return hipGetLastError();
@@ -457,9 +467,9 @@ hipError_t getrs_batched(hipStream_t st, const typename cpx<R>::T* LU, long sLU,
 }
 
 template hipError_t getrf_batched<float>(hipStream_t, float2*, long, int, int, int, int*, long, int2*, long, int*,
-                                         int2*, long, const int*, int);
+                                         int2*, long, const int*, int, UpdateRecorder*);
 template hipError_t getrf_batched<double>(hipStream_t, double2*, long, int, int, int, int*, long, int2*, long, int*,
-                                          int2*, long, const int*, int);
+                                          int2*, long, const int*, int, UpdateRecorder*);
 template hipError_t getrs_batched<float>(hipStream_t, const float2*, long, int, int, int, const int2*, long, float2*,
                                          long, int, int, const int*, int);
 template hipError_t getrs_batched<double>(hipStream_t, const double2*, long, int, int, int, const int2*, long,

@@ -36,7 +36,7 @@ STATUS_NAMES = {0: "OK", 1: "ESINGULAR", 2: "WARN_FALLBACK", 3: "WARN_GAP", 4: "
                 6: "ENOTCONV", 7: "ENAN"}
 
 EXPORTS = ["rsrr_create", "rsrr_destroy", "rsrr_contour", "rsrr_sample", "rsrr_basis", "rsrr_project",
-           "rsrr_solve", "rsrr_last_timings", "rsrr_version"]
+           "rsrr_solve", "rsrr_last_timings", "rsrr_update_stats", "rsrr_version"]
 
 
 class RsrrTerm(C.Structure):
@@ -94,6 +94,7 @@ def lib():
                              C.c_double, C.c_double, C.c_int, C.c_int, C.c_double, C.c_int, dp, vp, C.c_int, dp,
                              ip, dp, C.POINTER(RsrrSolveInfo)]
     L.rsrr_last_timings.argtypes = [vp, dp]
+    L.rsrr_update_stats.argtypes = [vp, C.c_int, C.c_int, dp]
     L.rsrr_version.restype = C.c_char_p
     for f in EXPORTS:
         if f != "rsrr_version":
@@ -202,6 +203,13 @@ class Context:
         t = (C.c_double * 5)()
         _check("rsrr_last_timings", lib().rsrr_last_timings(self.h, t))
         return {"assemble_ms": t[0], "lu_ms": t[1], "solve_ms": t[2], "residual_ms": t[3], "total_ms": t[4]}
+
+
+def rsrr_update_stats(ctx, enable=True, reset=False):
+    """Trailing-update kernel statistics: dict(launches, ms, flops, untimed)."""
+    out = (C.c_double * 4)()
+    _check("rsrr_update_stats", lib().rsrr_update_stats(ctx.h, int(enable), int(reset), out))
+    return {"launches": int(out[0]), "ms": out[1], "flops": out[2], "untimed": int(out[3])}
 
 
 def rsrr_create(device=0, stream=None):

@@ -1,0 +1,175 @@
+"""GPU parity of rsrr_basis, rsrr_project and rsrr_solve (RSRR Steps 3-5).
+
+Bars: singular values of the normalised S within 1e-13*sigma_1 of the oracle's
+SVD; leading subspaces (sigma > 1e-6 sigma_1) with principal-angle sines
+<= 1e-9; projected matrices within 1e-12 (relative); eigenvalues within 1e-9
+(relative) of the oracle and of the closed forms; eigen-residuals
+||T(lambda)v|| / (||T(lambda)||_1 ||v||) <= 1e-10 (computed on the CPU from
+the returned pairs).  Eigenvalues are compared inside the contour with a
+margin (elliptic level < 0.98); several correct answers differ outside it.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import pins as P
+from oracle import rsrr_oracle as O
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1605_07951_amd import rsrr
+    rsrr.lib()
+    return rsrr
+
+
+@pytest.fixture(scope="module")
+def ctx(R):
+    return R.rsrr_create(0)
+
+
+def _sin_angle(A, B):
+    """Largest sine of the principal angles between span(A) and span(B) (orthonormal columns)."""
+    s = np.linalg.svd(A.conj().T @ B, compute_uv=False)
+    return float(np.sqrt(max(0.0, 1.0 - min(s) ** 2))) if s.size else 0.0
+
+
+@pytest.mark.parametrize("shape", [(60, 90, 17), (200, 64, 64), (97, 130, 40), (33, 20, 20)])
+def test_basis_planted_spectrum(R, ctx, shape):
+    n, p, r = shape
+    rng = np.random.default_rng(n + p)
+    Ua = np.linalg.qr(W.complex_gaussian(rng, (n, r)))[0]
+    Vb = np.linalg.qr(W.complex_gaussian(rng, (p, r)))[0]
+    s = np.logspace(0, -12, r)
+    S = (Ua * s[None, :]) @ Vb.conj().T
+    Sd, _ = R.colmajor(S)
+    Q, k, sig = R.rsrr_basis(ctx, Sd, n, 1e-14)
+    Qh = R.from_colmajor(Q[:k], n)
+    Qo, sigo, ko = O.basis(O.normalize(S), 1e-14)
+    assert k == ko
+    m = min(n, p)
+    assert np.max(np.abs(sig[:m] - sigo[:m])) <= 1e-13 * sigo[0]
+    assert np.allclose(Qh.conj().T @ Qh, np.eye(k), atol=1e-12)
+    lead = sigo[:k] > 1e-6 * sigo[0]
+    assert _sin_angle(Qh[:, lead], Qo[:, lead]) <= 1e-9
+
+
+def test_basis_of_sampled_matrix_wide(R, ctx):
+    """cfg0 reading: S is n x N*L = 200 x 512 (N*L > n): full rank k = n."""
+    nep, C, U = W.cfg_qep()
+    z, _ = O.ellipse(C.gamma, C.a, C.b, C.N)
+    S, _, _ = R.rsrr_sample(ctx, R.DeviceNEP(nep), z, U, prec=1)
+    Sh = R.from_colmajor(S, 200)
+    Q, k, sig = R.rsrr_basis(ctx, S, 200, 1e-14)
+    Qo, sigo, ko = O.basis(O.normalize(Sh), 1e-14)
+    assert k == ko == 200
+    assert np.max(np.abs(sig[:200] - sigo[:200])) <= 1e-12 * sigo[0]
+
+
+def test_project_separable_matches_oracle(R, ctx):
+    nep = W.rotated_diagonal_qep(150, 3)
+    rng = np.random.default_rng(1)
+    Qh = np.linalg.qr(W.complex_gaussian(rng, (150, 37)))[0]
+    Qd, _ = R.colmajor(Qh)
+    dnep = R.DeviceNEP(nep)
+    AQ, terms = R.rsrr_project(ctx, dnep, Qd, 37, 0.0, 1.0)
+    assert len(terms) == 3
+    for j in range(3):
+        ref = Qh.conj().T @ nep.A[j] @ Qh
+        got = R.from_colmajor(AQ[j], 37)
+        assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_project_helmholtz_taylor_matches_direct(R, ctx):
+    """Taylor-expanded projection: sum_p (z - gamma)^p AQ_p == Q^H T(z) Q for |z - gamma| <= radius."""
+    n, k = 400, 25
+    nep = W.helmholtz_sphere(n)
+    prob = O.Problem(nep)
+    rng = np.random.default_rng(2)
+    Qh = np.linalg.qr(W.complex_gaussian(rng, (n, k)))[0]
+    Qd, _ = R.colmajor(Qh)
+    gamma, radius = 3.8 + 0j, 1.4
+    AQ, terms = R.rsrr_project(ctx, R.DeviceNEP(nep), Qd, k, gamma, radius)
+    mats = [R.from_colmajor(AQ[p], k) for p in range(len(terms))]
+    for z in (3.8 + 1.4j * 0.2, 2.5 + 0.1j, 5.1 - 0.3j):
+        ref = Qh.conj().T @ prob.T(z) @ Qh
+        got = sum(O.coef(t, z) * M for t, M in zip(terms, mats))
+        assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def _pipeline(R, ctx, nep, C, U, NQ=500, KQ=2, prec=1):
+    dnep = R.DeviceNEP(nep)
+    n = dnep.n
+    z, _ = R.rsrr_contour(C.gamma, C.a, C.b, C.N)
+    S, info, _ = R.rsrr_sample(ctx, dnep, z, U, prec=prec)
+    Q, k, sig = R.rsrr_basis(ctx, S, n, 1e-14)
+    AQ, terms = R.rsrr_project(ctx, dnep, Q, k, C.gamma, max(C.a, C.b))
+    out = R.rsrr_solve(ctx, dnep, Q, k, AQ, terms, C.gamma, C.a, C.b, NQ=NQ, KQ=KQ)
+    out["k"] = k
+    out["level"] = O.level(out["lam"], C.gamma, C.a, C.b)
+    return out
+
+
+def _match(got, ref):
+    return max(np.min(np.abs(ref - g)) / max(1.0, abs(g)) for g in got)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_pipeline_qep_closed_form(R, ctx, prec):
+    nep, C, U = W.cfg_qep()
+    out = _pipeline(R, ctx, nep, C, U, prec=prec)
+    prob = O.Problem(nep)
+    ex = P.qep_roots(nep.extra["c"], nep.extra["k"])
+    ins = out["level"] < 0.98
+    exin = ex[O.level(ex, C.gamma, C.a, C.b) < 0.98]
+    assert ins.sum() == exin.size
+    assert _match(out["lam"][ins], ex) < 1e-9
+    assert _match(exin, out["lam"]) < 1e-9
+    assert out["resid"][ins].max() <= 1e-10
+    # residuals recomputed on the CPU from the returned pairs
+    for i in np.where(ins)[0]:
+        assert O.residual(prob, out["lam"][i], out["V"][:, i]) <= 1e-10
+    # eigenvalues also agree with the oracle's RSRR on the same inputs
+    ro = O.rsrr(prob, C, U)
+    oin = ro["lam"][ro["level"] < 0.98]
+    assert _match(out["lam"][ins], oin) < 1e-9 and _match(oin, out["lam"][ins]) < 1e-9
+
+
+def test_pipeline_delay_lambert_w(R, ctx):
+    nep, C, U = W.cfg_delay(nx=16, N=48, L=32)
+    out = _pipeline(R, ctx, nep, C, U)
+    ex = P.delay_eigs(W.laplacian_modes(16, 16))
+    exin = ex[O.level(ex, C.gamma, C.a, C.b) < 1]
+    ins = out["level"] < 0.98
+    assert ins.sum() == 3 and exin.size == 3
+    assert _match(out["lam"][ins], exin) < 1e-9
+    assert out["resid"][ins].max() <= 1e-10
+    # the double eigenvalue: the two eigenvectors span the oracle's 2-dim eigenspace
+    prob = O.Problem(nep)
+    for i in np.where(ins)[0]:
+        assert O.residual(prob, out["lam"][i], out["V"][:, i]) <= 1e-10
+
+
+def test_pipeline_helmholtz_vs_oracle(R, ctx):
+    nep, C, U = W.cfg_helmholtz(n=300, N=32, L=16)
+    out = _pipeline(R, ctx, nep, C, U, NQ=200)
+    prob = O.Problem(nep)
+    ro = O.rsrr(prob, C, U, NQ=200)
+    oin = ro["lam"][ro["level"] < 0.98]
+    ins = out["level"] < 0.98
+    assert ins.sum() == oin.size == 4
+    assert _match(out["lam"][ins], oin) < 1e-9 and _match(oin, out["lam"][ins]) < 1e-9
+    assert out["resid"][ins].max() <= 1e-10
+    for i in np.where(ins)[0]:
+        assert O.residual(prob, out["lam"][i], out["V"][:, i]) <= 1e-10
+
+
+def test_solve_literal_empty_contour_warns(R, ctx):
+    nep, C, U = W.cfg_qep(n=60, N=16, L=4, literal=True)
+    out = _pipeline(R, ctx, nep, C, U, NQ=200)
+    assert out["warn_gap"] or np.sum(out["level"] < 0.98) == 0
