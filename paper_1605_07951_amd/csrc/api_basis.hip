@@ -12,18 +12,35 @@
 using namespace rsrr;
 
 // One-sided Jacobi SVD of A (rows 0..m-1 form the Gram; rows m..m_apply-1 are
-// rotated along).  Returns the number of sweeps, or -1 if not converged.
+// rotated along).  Columns whose norm is below eps*||A||_F count as zero.
+// Stops when a sweep measures every pair below tol, or when the measure has
+// stalled below 1e-13 for two sweeps.  Returns the number of sweeps, or -1.
 int jacobi_svd(rsrr_ctx* c, double2* A, int lda, int m, int m_apply, int p, int max_sweeps, double tol,
                rsrr_status* st)
 {
     const int nb = jacobi_blocks(p);
     const int rounds = nb - 1, pairs = nb / 2;
-    double* off = (double*)ws_get(c, WS_B6, (size_t)rounds * pairs * 8);
+    double* off = (double*)ws_get(c, WS_B6, (size_t)rounds * pairs * 8 + (size_t)p * 8);
     if (!off) { *st = RSRR_ENOMEM; return -1; }
-    std::vector<double> h((size_t)rounds * pairs);
+    double* cn = off + (size_t)rounds * pairs;
+    // ||A||_F^2 (invariant under the rotations) sets the zero-column threshold
+    if (colnorms(c->stream, m, p, A, lda, 0, cn, 1) != hipSuccess) { *st = RSRR_EDEVICE; return -1; }
+    std::vector<double> h((size_t)rounds * pairs), hc(p);
+    if (hipMemcpyAsync(hc.data(), cn, (size_t)p * 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        *st = RSRR_EDEVICE;
+        return -1;
+    }
+    double fro2 = 0.0;
+    for (double v : hc) fro2 += v * v;
+    const double eps = 2.220446049250313e-16;
+    const double zthr2 = eps * eps * fro2;
+    double prev = 1e300;
+    int stall = 0;
     for (int sw = 0; sw < max_sweeps; ++sw) {
         for (int r = 0; r < rounds; ++r) {
-            if (jacobi_round(c->stream, A, lda, m, m_apply, p, r, 2, tol, off + (size_t)r * pairs) != hipSuccess) {
+            if (jacobi_round(c->stream, A, lda, m, m_apply, p, r, 2, tol, zthr2, off + (size_t)r * pairs) !=
+                hipSuccess) {
                 *st = RSRR_EDEVICE;
                 return -1;
             }
@@ -37,6 +54,9 @@ int jacobi_svd(rsrr_ctx* c, double2* A, int lda, int m, int m_apply, int p, int 
         for (double v : h) mx = std::max(mx, v);
         if (!(mx == mx)) { *st = RSRR_ENAN; return -1; }
         if (mx <= tol) { *st = RSRR_OK; return sw + 1; }
+        stall = (mx <= 1e-13 && mx >= 0.5 * prev) ? stall + 1 : 0;
+        if (stall >= 2) { *st = RSRR_OK; return sw + 1; }
+        prev = mx;
     }
     *st = RSRR_ENOTCONV;
     return -1;
@@ -72,9 +92,9 @@ extern "C" rsrr_status rsrr_basis(rsrr_ctx* c, int n, int NL, double* S, int lds
     RSRR_HIP(hipStreamSynchronize(c->stream));
 
     // one-sided Jacobi: S V = U Sigma
-    const double tol = std::max(1.0, std::sqrt((double)n)) * 2.220446049250313e-16;
+    const double tol = 4.0 * std::max(1.0, std::sqrt((double)n)) * 2.220446049250313e-16;
     rsrr_status st = RSRR_OK;
-    if (jacobi_svd(c, A, lds, n, n, NL, 60, tol, &st) < 0) return st;
+    if (jacobi_svd(c, A, lds, n, n, NL, 80, tol, &st) < 0) return st;
 
     // singular values = column norms, sorted descending
     RSRR_HIP(colnorms(c->stream, n, NL, A, lds, 0, nrm, 1));

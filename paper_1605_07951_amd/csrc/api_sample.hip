@@ -476,7 +476,7 @@ extern "C" rsrr_status rsrr_sample(rsrr_ctx* c, const rsrr_nep* nep, int N, cons
     if (!c) return -1;
     if (!nep || nep->n < 1 || nep->n > 8192) return -2;
     if (nep->kind == RSRR_T_SEPARABLE) {
-        if (nep->J < 1 || nep->J > 16 || !nep->A || nep->lda < nep->n || !nep->terms) return -2;
+        if (nep->J < 1 || nep->J > 64 || !nep->A || nep->lda < nep->n || !nep->terms) return -2;
     } else if (nep->kind == RSRR_T_HELMHOLTZ) {
         if (!nep->points || !(nep->w > 0)) return -2;
     } else {

@@ -29,7 +29,7 @@ extern "C" rsrr_status rsrr_solve(rsrr_ctx* c, const rsrr_nep* nep, int k, const
     if (nep->kind == RSRR_T_HELMHOLTZ && (!nep->points || !(nep->w > 0))) return -2;
     if (k < 1 || k > nep->n) return -3;
     if (!AQp) return -4;
-    if (J_eff < 1 || J_eff > 256) return -5;
+    if (J_eff < 1 || J_eff > 64) return -5;
     if (!terms) return -6;
     if (!Qp) return -7;
     if (ldq < nep->n) return -8;
@@ -122,8 +122,8 @@ extern "C" rsrr_status rsrr_solve(rsrr_ctx* c, const rsrr_nep* nep, int k, const
     RSRR_HIP(eye(c->stream, Hx, 2 * Kk, Kk, Kk));
     RSRR_HIP(hankel(c->stream, mom, k, KQ, 1, Hs, Kk));
     rsrr_status st = RSRR_OK;
-    const double tol = std::max(1.0, std::sqrt((double)Kk)) * 2.220446049250313e-16;
-    if (jacobi_svd(c, Hx, 2 * Kk, Kk, 2 * Kk, Kk, 60, tol, &st) < 0) return st;
+    const double tol = 4.0 * std::max(1.0, std::sqrt((double)Kk)) * 2.220446049250313e-16;
+    if (jacobi_svd(c, Hx, 2 * Kk, Kk, 2 * Kk, Kk, 80, tol, &st) < 0) return st;
 
     // ---- singular values, gap rule ----
     double* nrm = (double*)ws_get(c, WS_B5, (size_t)Kk * 8);

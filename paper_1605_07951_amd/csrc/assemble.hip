@@ -20,7 +20,7 @@ namespace rsrr {
 
 constexpr int AS_NT = 256;
 constexpr int AS_PG = 8;      // points per thread pass
-constexpr int AS_MAXJ = 16;   // separable terms held in LDS
+constexpr int AS_MAXJ = 64;   // separable terms held in LDS
 
 // element e of a column-major n x n matrix: (e % n, e / n)
 template <bool O64, bool O128>

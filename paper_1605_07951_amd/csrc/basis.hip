@@ -7,7 +7,9 @@
 //   1. forms the Gram matrix G = [A_I A_J]^H [A_I A_J] (2B x 2B) by
 //      streaming the rows through LDS,
 //   2. records max |G_pq| / sqrt(G_pp G_qq) over p != q (the convergence
-//      measure of one-sided Jacobi),
+//      measure of one-sided Jacobi); columns with |a|^2 <= zthr2 (rounding
+//      level relative to ||A||_F) count as zero and are neither measured
+//      nor rotated, so exactly rank-deficient inputs converge,
 //   3. diagonalises G with cyclic two-sided Jacobi rotations (parallel
 //      ordering) accumulating the unitary V,
 //   4. replaces [A_I A_J] by [A_I A_J] V (rows streamed through LDS).
@@ -30,7 +32,7 @@ RSRR_DEV int rr_block(int pos, int r, int nb) { return pos == 0 ? 0 : ((pos - 1 
 // to (rows m..m_apply-1 accumulate the right singular vectors when they start as I).
 __global__ __launch_bounds__(JB_NT) void jacobi_pair_kernel(double2* __restrict__ A, int lda, int m, int m_apply,
                                                              int p, int nb, int round, int inner_sweeps, double tol,
-                                                             double* __restrict__ offmax)
+                                                             double zthr2, double* __restrict__ offmax)
 {
     __shared__ double2 tile[JB_RC][JB_W + 1];
     __shared__ double2 G[JB_W][JB_W + 1];
@@ -81,7 +83,7 @@ __global__ __launch_bounds__(JB_NT) void jacobi_pair_kernel(double2* __restrict_
         const int q = gq0 + u;
         if (q != gp) {
             const double dp = G[gp][gp].x, dq = G[q][q].x;
-            if (dp > 0.0 && dq > 0.0) {
+            if (dp > zthr2 && dq > zthr2) {
                 const double2 g = G[gp][q];
                 off = fmax(off, sqrt(g.x * g.x + g.y * g.y) / sqrt(dp * dq));
             }
@@ -115,7 +117,7 @@ __global__ __launch_bounds__(JB_NT) void jacobi_pair_kernel(double2* __restrict_
                 int on = 0;
                 double c = 1.0, s = 0.0;
                 double2 e = make_double2(1.0, 0.0);
-                if (h > 0.0 && h > 1e-300 && h > 0.25 * tol * sqrt(fmax(dA, 0.0) * fmax(dB, 0.0))) {
+                if (dA > zthr2 && dB > zthr2 && h > 0.25 * tol * sqrt(dA * dB)) {
                     const double zeta = (dB - dA) / (2.0 * h);
                     const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                     c = 1.0 / sqrt(1.0 + t * t);
@@ -204,11 +206,11 @@ __global__ __launch_bounds__(256) void gather_scale_kernel(const double2* __rest
 int jacobi_blocks(int p) { int nb = (p + JB_B - 1) / JB_B; return nb + (nb & 1); }
 
 hipError_t jacobi_round(hipStream_t st, double2* A, int lda, int m, int m_apply, int p, int round, int inner,
-                        double tol, double* offmax)
+                        double tol, double zthr2, double* offmax)
 {
     const int nb = jacobi_blocks(p);
     hipLaunchKernelGGL(jacobi_pair_kernel, dim3(nb / 2), dim3(JB_NT), 0, st, A, lda, m, m_apply, p, nb, round, inner,
-                       tol, offmax);
+                       tol, zthr2, offmax);
     return hipGetLastError();
 }
 

@@ -75,7 +75,7 @@ hipError_t scale_cols(hipStream_t st, int n, int m, double2* X, int ldx, const d
 // ---- block one-sided Jacobi SVD (basis.hip) ----
 int jacobi_blocks(int p);  // number of column blocks (even) for p columns
 hipError_t jacobi_round(hipStream_t st, double2* A, int lda, int m, int m_apply, int p, int round, int inner,
-                        double tol, double* offmax);
+                        double tol, double zthr2, double* offmax);
 hipError_t gather_scale(hipStream_t st, const double2* A, int lda, int m, const int* order, const double* inv,
                         double2* Q, int ldq, int k);
 
