@@ -182,27 +182,44 @@ struct PhaseTimer {
 
 struct SampleBufs {
     void* Tlu; double2* Tres; int* ipiv; int2* perm; int2* tperm; int* info; double2* coef; double* frobp;
-    double* frob; float2* D64; double2* R; double* norms; int* active; double2* zdev;
-    int ld, np; long sT, sP, sPerm, sTP, nparts;
+    double* frob; float2* D64; double2* R; double* norms; int* active; double2* zdev; void* inv; void* tmp;
+    int ld, np, nb; long sT, sP, sPerm, sTP, nparts, sInv, sTmp;
+    LUWork lu(const int* act, UpdateRecorder* rec) const
+    {
+        LUWork w;
+        w.ipiv = ipiv; w.sP = sP; w.perm = perm; w.sPerm = sPerm; w.tperm = tperm; w.sTP = sTP; w.info = info;
+        w.inv = inv; w.sInv = sInv; w.tmp = tmp; w.sTmp = sTmp; w.active = act; w.rec = rec;
+        return w;
+    }
 };
 
 // Per-point bytes of the sampling buffers.
 static size_t per_point_bytes(int n, int L, int prec)
 {
     const size_t ld = ld_pad(n);
-    const size_t np = (n + MAX_NB - 1) / MAX_NB;
+    const size_t np = perm_panels(n);
     size_t b = ld * n * 16;                         // FP64 copy for residuals
     b += ld * n * (prec == RSRR_PREC_C128 ? 16 : 8);  // LU input
     b += (size_t)n * 4 + np * 2 * MAX_NB * 8 + 8 * 2 * MAX_NB * 8 + 16;
     b += ((size_t)n * n + 255) / 256 * 8 + 8;
     b += (size_t)ld * L * (8 + 16) + (size_t)L * 16;
+    if (prec == RSRR_PREC_C64_IR) {
+        b += (size_t)np * 2 * 128 * 128 * 8 / 2;          // diagonal-block inverses (nb = 128: n/128 panels)
+        b += (size_t)128 * std::max(n, L) * 8;            // scratch rows
+    }
     return b;
 }
 
 static rsrr_status alloc_bufs(rsrr_ctx* c, int n, int L, int J, int prec, int B, SampleBufs& s)
 {
     s.ld = ld_pad(n);
-    s.np = (n + MAX_NB - 1) / MAX_NB;
+    s.np = perm_panels(n);
+    s.nb = prec == RSRR_PREC_C64_IR ? std::min(c->nb_c64, max_panel<float>()) : std::min(c->nb_c128, max_panel<double>());
+    s.sInv = prec == RSRR_PREC_C64_IR ? (long)((n + s.nb - 1) / s.nb) * 2 * s.nb * s.nb : 0;
+    s.sTmp = prec == RSRR_PREC_C64_IR ? (long)s.nb * std::max(n, L) : 0;
+    s.inv = prec == RSRR_PREC_C64_IR ? ws_get(c, WS_B0, (size_t)B * s.sInv * 8) : nullptr;
+    s.tmp = prec == RSRR_PREC_C64_IR ? ws_get(c, WS_B1, (size_t)B * s.sTmp * 8) : nullptr;
+    if (prec == RSRR_PREC_C64_IR && (!s.inv || !s.tmp)) return RSRR_ENOMEM;
     s.sT = (long)s.ld * n;
     s.sP = n;
     s.sPerm = (long)s.np * 2 * MAX_NB;
@@ -297,13 +314,11 @@ static rsrr_status sample_batch(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, i
         PhaseTimer t(c, &tm[1]);
         RSRR_HIP(hipMemsetAsync(s.info, 0, (size_t)B * 4, c->stream));
         if (prec == RSRR_PREC_C128)
-            RSRR_HIP(getrf_batched<double>(c->stream, (double2*)s.Tlu, s.sT, s.ld, n, c->nb_c128, s.ipiv, s.sP, s.perm,
-                                           s.sPerm, s.info, s.tperm, s.sTP, nullptr, B,
-                                           c->rec_on ? &c->rec : nullptr));
+            RSRR_HIP(getrf_batched<double>(c->stream, (double2*)s.Tlu, s.sT, s.ld, n, s.nb,
+                                           s.lu(nullptr, c->rec_on ? &c->rec : nullptr), B));
         else
-            RSRR_HIP(getrf_batched<float>(c->stream, (float2*)s.Tlu, s.sT, s.ld, n, c->nb_c64, s.ipiv, s.sP, s.perm,
-                                          s.sPerm, s.info, s.tperm, s.sTP, nullptr, B,
-                                          c->rec_on ? &c->rec : nullptr));
+            RSRR_HIP(getrf_batched<float>(c->stream, (float2*)s.Tlu, s.sT, s.ld, n, s.nb,
+                                          s.lu(nullptr, c->rec_on ? &c->rec : nullptr), B));
         t.stop();
         if (c->rec_on) rec_collect(c);
         RSRR_HIP(hipMemcpyAsync(hinfo.data(), s.info, (size_t)B * 4, hipMemcpyDeviceToHost, c->stream));
@@ -329,8 +344,8 @@ static rsrr_status sample_batch(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, i
         {
             PhaseTimer t(c, &tm[2]);
             RSRR_HIP(bcast_c128(c->stream, n, L, U, ldu, S, lds, sX, B));
-            RSRR_HIP(getrs_batched<double>(c->stream, (const double2*)s.Tlu, s.sT, s.ld, n, c->nb_c128, s.perm, s.sPerm,
-                                           S, sX, lds, L, s.active, B));
+            RSRR_HIP(getrs_batched<double>(c->stream, (const double2*)s.Tlu, s.sT, s.ld, n, s.nb,
+                                           s.lu(s.active, nullptr), S, sX, lds, L, B));
             t.stop();
         }
         {
@@ -351,8 +366,8 @@ static rsrr_status sample_batch(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, i
     {
         PhaseTimer t(c, &tm[2]);
         RSRR_HIP(bcast_to_c64(c->stream, n, L, U, ldu, s.D64, s.ld, (long)s.ld * L, B));
-        RSRR_HIP(getrs_batched<float>(c->stream, (const float2*)s.Tlu, s.sT, s.ld, n, c->nb_c64, s.perm, s.sPerm,
-                                      s.D64, (long)s.ld * L, s.ld, L, s.active, B));
+        RSRR_HIP(getrs_batched<float>(c->stream, (const float2*)s.Tlu, s.sT, s.ld, n, s.nb, s.lu(s.active, nullptr),
+                                      s.D64, (long)s.ld * L, s.ld, L, B));
         RSRR_HIP(widen(c->stream, n, L, s.D64, s.ld, (long)s.ld * L, S, lds, sX, B));
         t.stop();
     }
@@ -400,8 +415,8 @@ static rsrr_status sample_batch(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, i
                                     c->stream));
             RSRR_HIP(scale_narrow(c->stream, n, L, s.R, s.ld, (long)s.ld * L, s.norms + (size_t)2 * B * L, s.D64, s.ld,
                                   (long)s.ld * L, s.active, B));
-            RSRR_HIP(getrs_batched<float>(c->stream, (const float2*)s.Tlu, s.sT, s.ld, n, c->nb_c64, s.perm, s.sPerm,
-                                          s.D64, (long)s.ld * L, s.ld, L, s.active, B));
+            RSRR_HIP(getrs_batched<float>(c->stream, (const float2*)s.Tlu, s.sT, s.ld, n, s.nb,
+                                          s.lu(s.active, nullptr), s.D64, (long)s.ld * L, s.ld, L, B));
             RSRR_HIP(hipMemcpyAsync(s.norms + (size_t)2 * B * L, scl.data(), (size_t)B * L * 8, hipMemcpyHostToDevice,
                                     c->stream));
             RSRR_HIP(axpy_widen(c->stream, n, L, s.D64, s.ld, (long)s.ld * L, s.norms + (size_t)2 * B * L, S, lds, sX,

@@ -60,7 +60,7 @@ extern "C" rsrr_status rsrr_solve(rsrr_ctx* c, const rsrr_nep* nep, int k, const
     const size_t per_pt = (size_t)kk * 16 * 2 + (size_t)k * 4 + 64 * 1024;
     const int Mc = (int)std::max<size_t>(1, std::min<size_t>((size_t)std::min(NQ, 256), (size_t)(8ull << 30) / per_pt));
     const int nb = 64;
-    const int np = (k + MAX_NB - 1) / MAX_NB;
+    const int np = perm_panels(k);
     double2* T = (double2*)ws_get(c, WS_TLU, (size_t)Mc * kk * 16);
     double2* X = (double2*)ws_get(c, WS_TRES, (size_t)Mc * kk * 16);
     int* ipiv = (int*)ws_get(c, WS_IPIV, (size_t)Mc * k * 4);
@@ -99,11 +99,12 @@ extern "C" rsrr_status rsrr_solve(rsrr_ctx* c, const rsrr_nep* nep, int k, const
         RSRR_HIP(hipMemcpyAsync(cw, hcw.data(), (size_t)twoK * B * 16, hipMemcpyHostToDevice, c->stream));
         RSRR_HIP(assemble_separable(c->stream, k, J_eff, AQ, k, coef, B, nullptr, 0, 0, T, k, kk, frobp, frob));
         RSRR_HIP(hipMemsetAsync(info, 0, (size_t)B * 4, c->stream));
-        RSRR_HIP(getrf_batched<double>(c->stream, T, kk, k, k, nb, ipiv, k, perm, (long)np * 2 * MAX_NB, info, tperm,
-                                       8L * 2 * MAX_NB, nullptr, B));
+        LUWork w;
+        w.ipiv = ipiv; w.sP = k; w.perm = perm; w.sPerm = (long)np * 2 * MAX_NB; w.tperm = tperm;
+        w.sTP = 8L * 2 * MAX_NB; w.info = info;
+        RSRR_HIP(getrf_batched<double>(c->stream, T, kk, k, k, nb, w, B));
         RSRR_HIP(bcast_c128(c->stream, k, k, I, k, X, k, kk, B));
-        RSRR_HIP(getrs_batched<double>(c->stream, T, kk, k, k, nb, perm, (long)np * 2 * MAX_NB, X, kk, k, k, nullptr,
-                                       B));
+        RSRR_HIP(getrs_batched<double>(c->stream, T, kk, k, k, nb, w, X, kk, k, k, B));
         // mom(:, alpha) += sum_m X_m cw(m, alpha): one GEMM over the stacked vec(X_m)
         RSRR_HIP(zgemm(c->stream, 0, 0, (int)kk, twoK, B, 1.0, X, (int)kk, 0, cw, B, 0, 1.0, mom, (int)kk, 0, 1));
         RSRR_HIP(hipMemcpyAsync(hinfo.data(), info, (size_t)B * 4, hipMemcpyDeviceToHost, c->stream));

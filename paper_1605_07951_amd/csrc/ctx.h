@@ -26,7 +26,7 @@ struct rsrr_ctx {
     size_t ws_size[WS_COUNT] = {};
     hipEvent_t ev[2] = {};
     double timings[5] = {0, 0, 0, 0, 0};
-    int nb_c64 = 64;       // outer LU panel width, complex FP32 path
+    int nb_c64 = 128;      // outer LU panel width, complex FP32 path
     int nb_c128 = 64;      // outer LU panel width, complex FP64 path
     int ir_max_iters = 10;
     size_t ws_budget = 0;  // bytes for the per-point sampling buffers (0 = half of free memory)

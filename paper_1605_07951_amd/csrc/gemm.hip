@@ -18,12 +18,17 @@
 namespace rsrr {
 
 // ----------------------------------------------------------------------------
-// complex FP32: v_mfma_f32_32x32x2f32, WG tile 128x128, 4 waves of 64x64.
+// complex FP32: v_mfma_f32_32x32x2f32.  The workgroup has WR x WC waves; each
+// wave owns BR x BC blocks of 32x32 outputs, so the WG tile is
+// (32 WR BR) x (32 WC BC).  Shapes: 128x128 (2x2 waves of 2x2 blocks) for the
+// trailing update, 128x64 and 128x32 for the narrow products of the panel
+// recursion and the solves.  beta*C is loaded into the accumulators before
+// the k loop (its latency overlaps the first LDS stage), alpha is folded
+// into the A operand, and the epilogue only stores.
 // ----------------------------------------------------------------------------
-constexpr int CG_BM = 128, CG_BN = 128, CG_KT = 16, CG_NT = 256;
+constexpr int CG_KT = 16, CG_NT = 256;
 
-// TAG only distinguishes kernel symbols (1 = LU trailing update) for profilers.
-template <bool VEC, int TAG>
+template <int WR, int WC, int BR, int BC, bool VEC, int TAG>
 __global__ __launch_bounds__(CG_NT, 2) void cgemm_mfma_kernel(
     int M, int N, int K, float alpha,
     const float2* __restrict__ A, int lda, long sA,
@@ -31,85 +36,97 @@ __global__ __launch_bounds__(CG_NT, 2) void cgemm_mfma_kernel(
     float beta, float2* __restrict__ C, int ldc, long sC,
     int tilesM, int tilesN, int batch, long total_padded)
 {
-    __shared__ __attribute__((aligned(16))) float As[2][CG_KT][2 * CG_BM];
-    __shared__ __attribute__((aligned(16))) float2 Bs[2][CG_KT][CG_BN];
+    constexpr int BM = 32 * WR * BR, BN = 32 * WC * BC;
+    constexpr int AQ = BM * CG_KT / 2 / CG_NT;   // float4 (2 complex) A loads per thread per stage
+    constexpr int BQ = BN * CG_KT / 2 / CG_NT;   // float4 B loads per thread per stage
+    static_assert(AQ >= 1 && BQ >= 1, "tile too small for the loader");
+    __shared__ __attribute__((aligned(16))) float As[2][CG_KT][2 * BM];
+    __shared__ __attribute__((aligned(16))) float2 Bs[2][CG_KT][BN];
 
     const long tile = xcd_remap(blockIdx.x, total_padded);
     const long per = (long)tilesM * tilesN;
     const long b = tile / per;
     if (b >= batch) return;
     const int t = (int)(tile - b * per);
-    const int i0 = (t % tilesM) * CG_BM;
-    const int j0 = (t / tilesM) * CG_BN;
+    const int i0 = (t % tilesM) * BM;
+    const int j0 = (t / tilesM) * BN;
     const float2* Ab = A + b * sA;
     const float2* Bb = B + b * sB;
     float2* Cb = C + b * sC;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int wi = wave & 1, wj = wave >> 1;
+    const int wi = wave % WR, wj = wave / WR;
     const int li = lane & 31, half = lane >> 5;
+    const int wrow = i0 + wi * BR * 32, wcol = j0 + wj * BC * 32;
 
-    floatx16 accR[2][2], accI[2][2];
+    // ---- prologue: acc = beta * C (output layout: lane li = row, reg r = column 8(r/4)+4 half+r%4) ----
+    floatx16 accR[BR][BC], accI[BR][BC];
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < BR; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+        for (int y = 0; y < BC; ++y) {
+            const int i = wrow + x * 32 + li;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) { accR[x][y][r] = 0.f; accI[x][y][r] = 0.f; }
+            for (int r = 0; r < 16; ++r) {
+                const int j = wcol + y * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                float2 c = make_float2(0.f, 0.f);
+                if (beta != 0.f && i < M && j < N) c = Cb[i + (long)j * ldc];
+                accR[x][y][r] = beta * c.x;
+                accI[x][y][r] = beta * c.y;
+            }
+        }
 
-    floatx4 ra[4], rb[4];
+    floatx4 ra[AQ], rb[BQ];
     auto gload = [&](int k0) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            int p = tid + CG_NT * q;
-            // A: 64 row-pairs x 16 k
-            {
-                int k = p >> 6, ip = (p & 63) << 1;
-                int gi = i0 + ip, gk = k0 + k;
-                floatx4 v = {0.f, 0.f, 0.f, 0.f};
-                if (gk < K) {
-                    const float2* src = Ab + gi + (long)gk * lda;
-                    if (VEC && gi + 1 < M) {
-                        v = *reinterpret_cast<const floatx4*>(src);
-                    } else {
-                        if (gi < M) { float2 e = src[0]; v[0] = e.x; v[1] = e.y; }
-                        if (gi + 1 < M) { float2 e = src[1]; v[2] = e.x; v[3] = e.y; }
-                    }
+        for (int q = 0; q < AQ; ++q) {
+            const int p = tid + CG_NT * q;
+            const int k = p / (BM / 2), ip = (p % (BM / 2)) * 2;
+            const int gi = i0 + ip, gk = k0 + k;
+            floatx4 v = {0.f, 0.f, 0.f, 0.f};
+            if (gk < K) {
+                const float2* src = Ab + gi + (long)gk * lda;
+                if (VEC && gi + 1 < M) {
+                    v = *reinterpret_cast<const floatx4*>(src);
+                } else {
+                    if (gi < M) { float2 e = src[0]; v[0] = e.x; v[1] = e.y; }
+                    if (gi + 1 < M) { float2 e = src[1]; v[2] = e.x; v[3] = e.y; }
                 }
-                ra[q] = v;
             }
-            // B: 128 columns x 8 k-pairs
-            {
-                int j = p >> 3, kp = (p & 7) << 1;
-                int gj = j0 + j, gk = k0 + kp;
-                floatx4 v = {0.f, 0.f, 0.f, 0.f};
-                if (gj < N) {
-                    const float2* src = Bb + gk + (long)gj * ldb;
-                    if (VEC && gk + 1 < K) {
-                        v = *reinterpret_cast<const floatx4*>(src);
-                    } else {
-                        if (gk < K) { float2 e = src[0]; v[0] = e.x; v[1] = e.y; }
-                        if (gk + 1 < K) { float2 e = src[1]; v[2] = e.x; v[3] = e.y; }
-                    }
+            ra[q] = v;
+        }
+#pragma unroll
+        for (int q = 0; q < BQ; ++q) {
+            const int p = tid + CG_NT * q;
+            const int j = p / (CG_KT / 2), kp = (p % (CG_KT / 2)) * 2;
+            const int gj = j0 + j, gk = k0 + kp;
+            floatx4 v = {0.f, 0.f, 0.f, 0.f};
+            if (gj < N) {
+                const float2* src = Bb + gk + (long)gj * ldb;
+                if (VEC && gk + 1 < K) {
+                    v = *reinterpret_cast<const floatx4*>(src);
+                } else {
+                    if (gk < K) { float2 e = src[0]; v[0] = e.x; v[1] = e.y; }
+                    if (gk + 1 < K) { float2 e = src[1]; v[2] = e.x; v[3] = e.y; }
                 }
-                rb[q] = v;
             }
+            rb[q] = v;
         }
     };
     auto sstore = [&](int buf) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            int p = tid + CG_NT * q;
-            {
-                int k = p >> 6, ip = (p & 63) << 1;
-                *reinterpret_cast<floatx4*>(&As[buf][k][2 * ip]) = ra[q];
-            }
-            {
-                int j = p >> 3, kp = (p & 7) << 1;
-                Bs[buf][kp][j] = make_float2(rb[q][0], rb[q][1]);
-                Bs[buf][kp + 1][j] = make_float2(rb[q][2], rb[q][3]);
-            }
+        for (int q = 0; q < AQ; ++q) {
+            const int p = tid + CG_NT * q;
+            const int k = p / (BM / 2), ip = (p % (BM / 2)) * 2;
+            *reinterpret_cast<floatx4*>(&As[buf][k][2 * ip]) = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < BQ; ++q) {
+            const int p = tid + CG_NT * q;
+            const int j = p / (CG_KT / 2), kp = (p % (CG_KT / 2)) * 2;
+            Bs[buf][kp][j] = make_float2(rb[q][0], rb[q][1]);
+            Bs[buf][kp + 1][j] = make_float2(rb[q][2], rb[q][3]);
         }
     };
 
@@ -124,19 +141,19 @@ __global__ __launch_bounds__(CG_NT, 2) void cgemm_mfma_kernel(
         if (s + 1 < nst) gload((s + 1) * CG_KT);
 #pragma unroll 4
         for (int k = 0; k < CG_KT; ++k) {
-            float a[2], br[2], bi[2];
+            float a[BR], br[BC], bi[BC];
 #pragma unroll
-            for (int x = 0; x < 2; ++x) a[x] = As[buf][k][2 * (wi * 64 + x * 32 + li) + half];
+            for (int x = 0; x < BR; ++x) a[x] = alpha * As[buf][k][2 * (wi * BR * 32 + x * 32 + li) + half];
 #pragma unroll
-            for (int y = 0; y < 2; ++y) {
-                float2 bv = Bs[buf][k][wj * 64 + y * 32 + li];
+            for (int y = 0; y < BC; ++y) {
+                const float2 bv = Bs[buf][k][wj * BC * 32 + y * 32 + li];
                 br[y] = half ? -bv.y : bv.x;
                 bi[y] = half ? bv.x : bv.y;
             }
 #pragma unroll
-            for (int x = 0; x < 2; ++x)
+            for (int x = 0; x < BR; ++x)
 #pragma unroll
-                for (int y = 0; y < 2; ++y) {
+                for (int y = 0; y < BC; ++y) {
                     accR[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(br[y], a[x], accR[x][y], 0, 0, 0);
                     accI[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(bi[y], a[x], accI[x][y], 0, 0, 0);
                 }
@@ -145,30 +162,38 @@ __global__ __launch_bounds__(CG_NT, 2) void cgemm_mfma_kernel(
         __syncthreads();
     }
 
-    // epilogue: lane li holds row i; register r holds column 8(r/4) + 4 half + r%4.
+    // ---- epilogue: store ----
 #pragma unroll
-    for (int x = 0; x < 2; ++x) {
-        const int i = i0 + wi * 64 + x * 32 + li;
+    for (int x = 0; x < BR; ++x) {
+        const int i = wrow + x * 32 + li;
         if (i >= M) continue;
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+        for (int y = 0; y < BC; ++y)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int j = j0 + wj * 64 + y * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-                if (j < N) {
-                    float2* dst = Cb + i + (long)j * ldc;
-                    float2 o;
-                    o.x = alpha * accR[x][y][r];
-                    o.y = alpha * accI[x][y][r];
-                    if (beta != 0.f) {
-                        float2 c = *dst;
-                        o.x += beta * c.x;
-                        o.y += beta * c.y;
-                    }
-                    *dst = o;
-                }
+                const int j = wcol + y * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                if (j < N) Cb[i + (long)j * ldc] = make_float2(accR[x][y][r], accI[x][y][r]);
             }
     }
+}
+
+template <int WR, int WC, int BR, int BC>
+static void cgemm_launch(hipStream_t st, int M, int N, int K, float alpha, const float2* A, int lda, long sA,
+                         const float2* B, int ldb, long sB, float beta, float2* C, int ldc, long sC, int batch,
+                         int tag, bool vec)
+{
+    constexpr int BM = 32 * WR * BR, BN = 32 * WC * BC;
+    const int tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
+    const long total = round_up_l((long)tm * tn * batch, 8);
+#define CG_L(V, T)                                                                                                    \
+    hipLaunchKernelGGL((cgemm_mfma_kernel<WR, WC, BR, BC, V, T>), dim3((unsigned)total), dim3(CG_NT), 0, st, M, N, K, \
+                       alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, tm, tn, batch, total)
+    if (vec) {
+        if (tag == 1) CG_L(true, 1); else CG_L(true, 0);
+    } else {
+        if (tag == 1) CG_L(false, 1); else CG_L(false, 0);
+    }
+#undef CG_L
 }
 
 hipError_t cgemm(hipStream_t st, int M, int N, int K, float alpha,
@@ -176,19 +201,14 @@ hipError_t cgemm(hipStream_t st, int M, int N, int K, float alpha,
                  float beta, float2* C, int ldc, long sC, int batch, int tag)
 {
     if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-    const int tm = (M + CG_BM - 1) / CG_BM, tn = (N + CG_BN - 1) / CG_BN;
-    const long total = round_up_l((long)tm * tn * batch, 8);
     const bool vec = ((((uintptr_t)A) | ((uintptr_t)B)) & 15) == 0 && (lda % 2 == 0) && (ldb % 2 == 0)
                      && (sA % 2 == 0) && (sB % 2 == 0);
-#define CG_LAUNCH(V, T)                                                                                       \
-    hipLaunchKernelGGL((cgemm_mfma_kernel<V, T>), dim3((unsigned)total), dim3(CG_NT), 0, st, M, N, K, alpha, A, lda, \
-                       sA, B, ldb, sB, beta, C, ldc, sC, tm, tn, batch, total)
-    if (vec) {
-        if (tag == 1) CG_LAUNCH(true, 1); else CG_LAUNCH(true, 0);
-    } else {
-        if (tag == 1) CG_LAUNCH(false, 1); else CG_LAUNCH(false, 0);
-    }
-#undef CG_LAUNCH
+    if (N <= 32)
+        cgemm_launch<4, 1, 1, 1>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tag, vec);
+    else if (N <= 64)
+        cgemm_launch<4, 1, 1, 2>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tag, vec);
+    else
+        cgemm_launch<2, 2, 2, 2>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tag, vec);
     return hipGetLastError();
 }
 
@@ -226,13 +246,23 @@ __global__ __launch_bounds__(ZG_NT, 2) void zgemm_mfma_kernel(
     const int li = lane & 15, kq = lane >> 4;       // kq = 2*kc + part
     const int kc = kq >> 1, part = kq & 1;
 
+    // acc = beta * C; lane li holds row i, register r holds column lane/16 + 4*r
+    // (the f64 MFMA interleaves its four output groups by register)
     doublex4 accR[2][2], accI[2][2];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+        for (int y = 0; y < 2; ++y) {
+            const int i = i0 + wi * 32 + x * 16 + li;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) { accR[x][y][r] = 0.0; accI[x][y][r] = 0.0; }
+            for (int r = 0; r < 4; ++r) {
+                const int j = j0 + wj * 32 + y * 16 + kq + 4 * r;
+                double2 c = make_double2(0.0, 0.0);
+                if (beta != 0.0 && i < M && j < N) c = Cb[i + (long)j * ldc];
+                accR[x][y][r] = beta * c.x;
+                accI[x][y][r] = beta * c.y;
+            }
+        }
 
     double2 ra[4], rb[4];
     auto gload = [&](int k0) {
@@ -289,7 +319,7 @@ __global__ __launch_bounds__(ZG_NT, 2) void zgemm_mfma_kernel(
 #pragma unroll
             for (int x = 0; x < 2; ++x) {
                 double2 av = As[buf][kk + kc][wi * 32 + x * 16 + li];
-                a[x] = part ? av.y : av.x;
+                a[x] = alpha * (part ? av.y : av.x);
             }
 #pragma unroll
             for (int y = 0; y < 2; ++y) {
@@ -309,8 +339,7 @@ __global__ __launch_bounds__(ZG_NT, 2) void zgemm_mfma_kernel(
         __syncthreads();
     }
 
-    // epilogue: lane li holds row i; register r holds column lane/16 + 4*r
-    // (the f64 MFMA interleaves its four output groups by register).
+    // epilogue: store
 #pragma unroll
     for (int x = 0; x < 2; ++x) {
         const int i = i0 + wi * 32 + x * 16 + li;
@@ -320,18 +349,7 @@ __global__ __launch_bounds__(ZG_NT, 2) void zgemm_mfma_kernel(
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int j = j0 + wj * 32 + y * 16 + kq + 4 * r;
-                if (j < N) {
-                    double2* dst = Cb + i + (long)j * ldc;
-                    double2 o;
-                    o.x = alpha * accR[x][y][r];
-                    o.y = alpha * accI[x][y][r];
-                    if (beta != 0.0) {
-                        double2 c = *dst;
-                        o.x += beta * c.x;
-                        o.y += beta * c.y;
-                    }
-                    *dst = o;
-                }
+                if (j < N) Cb[i + (long)j * ldc] = make_double2(accR[x][y][r], accI[x][y][r]);
             }
     }
 }

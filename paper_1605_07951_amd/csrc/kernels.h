@@ -7,8 +7,13 @@
 
 namespace rsrr {
 
-// Widest LU panel (columns) the solve/interchange kernels stage in LDS.
-constexpr int MAX_NB = 64;
+// Widest LU panel (columns): permutation slots and scratch are sized for it.
+// The LDS triangle of the solve kernel holds 128 columns for complex FP32 and
+// 64 for complex FP64 (panel widths are capped accordingly).
+constexpr int MAX_NB = 128;
+template <typename R> constexpr int max_panel() { return sizeof(R) == 4 ? 128 : 64; }
+// Panel slots of the per-matrix permutation store (enough for the narrowest panel, 64).
+inline int perm_panels(int n) { return (n + 63) / 64; }
 
 // C = beta*C + alpha*A*B, complex single on v_mfma_f32_32x32x2f32.
 // tag 1 launches a separately named instance (the LU trailing update).
@@ -31,21 +36,34 @@ struct UpdateRecorder {
     long dropped = 0;           // launches beyond the pool (not timed)
 };
 
-// Blocked LU with partial pivoting of `batch` n x n matrices (stride sA).
-// ipiv: n ints per matrix (stride sP).  perm: ceil(n/nb)*2*MAX_NB int2 per
-// matrix (stride sPerm), one composed permutation per panel, used by
-// getrs_batched.  tperm: 8*2*MAX_NB int2 scratch per matrix (stride sTP).
-// info: one int per matrix, must be zero on entry.  active: optional mask.
-template <typename R>
-hipError_t getrf_batched(hipStream_t st, typename cpx<R>::T* A,
-                         long sA, int lda, int n, int nb, int* ipiv, long sP, int2* perm, long sPerm, int* info,
-                         int2* tperm, long sTP, const int* active, int batch, UpdateRecorder* rec = nullptr);
+// Workspace of the batched LU (per-matrix strides in elements).
+//  ipiv  : n ints                          (stride sP)
+//  perm  : perm_panels(n)*2*MAX_NB int2     (stride sPerm), composed interchanges per panel
+//  tperm : 8*2*MAX_NB int2                 (stride sTP), recursion scratch
+//  info  : 1 int, zero on entry            (getrf semantics; < 0: NaN/Inf pivot)
+//  inv   : complex-FP32 path only: panels*2*nb*nb complex (stride sInv), L11^-1, U11^-1
+//  tmp   : complex-FP32 path only: nb*max(n, nrhs) complex (stride sTmp)
+//  active: optional per-matrix mask; rec: optional trailing-update event recorder
+struct LUWork {
+    int* ipiv = nullptr; long sP = 0;
+    int2* perm = nullptr; long sPerm = 0;
+    int2* tperm = nullptr; long sTP = 0;
+    int* info = nullptr;
+    void* inv = nullptr; long sInv = 0;
+    void* tmp = nullptr; long sTmp = 0;
+    const int* active = nullptr;
+    UpdateRecorder* rec = nullptr;
+};
 
+// Blocked LU with partial pivoting of `batch` n x n matrices (stride sA).
 template <typename R>
-hipError_t getrs_batched(hipStream_t st, const typename cpx<R>::T* LU,
-                         long sLU, int lda, int n, int nb, const int2* perm, long sPerm,
-                         typename cpx<R>::T* X, long sX, int ldx,
-                         int nrhs, const int* active, int batch);
+hipError_t getrf_batched(hipStream_t st, typename cpx<R>::T* A, long sA, int lda, int n, int nb, const LUWork& w,
+                         int batch);
+
+// X <- T^-1 X for the factors of getrf_batched (same nb and workspace).
+template <typename R>
+hipError_t getrs_batched(hipStream_t st, const typename cpx<R>::T* LU, long sLU, int lda, int n, int nb,
+                         const LUWork& w, typename cpx<R>::T* X, long sX, int ldx, int nrhs, int batch);
 
 // ---- assembly (assemble.hip) ----
 // T64/T128 may be null (not written); batch strides s64/s128 in elements.

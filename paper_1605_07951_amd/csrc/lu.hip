@@ -218,36 +218,39 @@ __global__ __launch_bounds__(64) void perm_build_kernel(const int* __restrict__ 
 
 // ----------------------------------------------------------------------------
 // Row permutation + triangular solve on a block of columns.
-// X: rows indexed like the factored matrix; columns [0, ncols).
+// X: rows indexed like the factored matrix (row r at X[r - xr0]); columns [0, ncols).
 // mode 0: permute only.  mode 1: permute, then X[c0:c0+jb] = L11^-1 X[...]
 // with L11 the unit-lower diagonal block of LU at (c0, c0).
 // mode 2: no permutation, X[c0:c0+jb] = U11^-1 X[...] (non-unit upper).
+// mode 4 / 5: X[c0:c0+jb, 0:jb] = L11^-1 / U11^-1 (the solve applied to I).
 // ----------------------------------------------------------------------------
-constexpr int TS_NT = 256, TS_TC = 32;
+constexpr int TS_NT = 256;
 
-template <typename R>
+// MJB: widest diagonal block staged in LDS; TC: columns per workgroup.
+template <typename R, int MJB, int TC>
 __global__ __launch_bounds__(TS_NT) void perm_trsm_kernel(
     const typename cpx<R>::T* __restrict__ LU, long sLU, int ldl,
     const int2* __restrict__ perm, long sPerm,
-    typename cpx<R>::T* __restrict__ X, long sX, int ldx,
+    typename cpx<R>::T* __restrict__ X, long sX, int ldx, int xr0,
     int c0, int jb, int ncols, int mode, const int* __restrict__ active)
 {
     typedef typename cpx<R>::T C;
     const int b = blockIdx.y;
     if (active && !active[b]) return;
     const C* Lb = LU + (long)b * sLU;
-    C* Xb = X + (long)b * sX;
+    C* Xb = X + (long)b * sX - xr0;
     const int tid = threadIdx.x;
-    const int col = tid % TS_TC, grp = tid / TS_TC;  // 8 groups
-    constexpr int NG = TS_NT / TS_TC;
-    const int gcol = blockIdx.x * TS_TC + col;
+    const int col = tid % TC, grp = tid / TC;
+    constexpr int NG = TS_NT / TC;
+    const int gcol = blockIdx.x * TC + col;
     const bool colok = gcol < ncols;
 
-    __shared__ C top[MAX_NB][TS_TC + 1];
-    __shared__ C Ld[MAX_NB][MAX_NB + 1];
-    __shared__ int2 pm[2 * MAX_NB];
+    __shared__ C top[MJB][TC + 1];
+    __shared__ C Ld[MJB][MJB + 1];
+    __shared__ int2 pm[2 * MJB];
 
-    if (mode != 2) {
+    const bool permute = mode == 0 || mode == 1;
+    if (permute) {
         const int2* pb = perm + (long)b * sPerm;
         for (int s = tid; s < 2 * jb; s += TS_NT) pm[s] = pb[s];
     }
@@ -260,9 +263,9 @@ __global__ __launch_bounds__(TS_NT) void perm_trsm_kernel(
     }
     __syncthreads();
 
-    if (mode != 2) {
+    if (permute) {
         // gather every affected row (reads first, writes after the barrier)
-        constexpr int MAXQ = (2 * MAX_NB + NG - 1) / NG;
+        constexpr int MAXQ = (2 * MJB + NG - 1) / NG;
         C val[MAXQ];
 #pragma unroll
         for (int q = 0; q < MAXQ; ++q) {
@@ -285,19 +288,21 @@ __global__ __launch_bounds__(TS_NT) void perm_trsm_kernel(
                 if (dst >= 0) Xb[dst + (long)gcol * ldx] = val[q];
             }
         }
+    } else if (mode >= 4) {
+        for (int s = grp; s < jb; s += NG) top[s][col] = mk((R)(s == gcol ? 1 : 0), (R)0);
     } else {
         for (int s = grp; s < jb; s += NG)
             top[s][col] = colok ? Xb[(c0 + s) + (long)gcol * ldx] : czero<C>();
     }
     __syncthreads();
 
-    if (mode == 1) {
+    if (mode == 1 || mode == 4) {
         for (int l = 0; l < jb; ++l) {
             const C xl = top[l][col];
             for (int i = l + 1 + grp; i < jb; i += NG) top[i][col] = cfms(top[i][col], Ld[i][l], xl);
             __syncthreads();
         }
-    } else if (mode == 2) {
+    } else if (mode == 2 || mode == 5) {
         for (int l = jb - 1; l >= 0; --l) {
             if (grp == 0) {
                 const C d = Ld[l][l];
@@ -312,6 +317,46 @@ __global__ __launch_bounds__(TS_NT) void perm_trsm_kernel(
 
     if (colok)
         for (int s = grp; s < jb; s += NG) Xb[(c0 + s) + (long)gcol * ldx] = top[s][col];
+}
+
+// ----------------------------------------------------------------------------
+// Row permutation of a block of columns without a solve (LDS only for the
+// permutation).  Column by column, 2*jb threads gather the affected rows and
+// then scatter them; rows c0..c0+jb-1 go to T (jb x ncols, ldt) when T is
+// given, otherwise back into X.  perm == nullptr: identity (copy the block
+// rows to T).
+// ----------------------------------------------------------------------------
+constexpr int PR_TC = 32;
+
+template <typename R>
+__global__ __launch_bounds__(2 * MAX_NB) void perm_rows_kernel(
+    const int2* __restrict__ perm, long sPerm, typename cpx<R>::T* __restrict__ X, long sX, int ldx,
+    typename cpx<R>::T* __restrict__ T, long sT, int ldt, int c0, int jb, int ncols, const int* __restrict__ active)
+{
+    typedef typename cpx<R>::T C;
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    C* Xb = X + (long)b * sX;
+    C* Tb = T ? T + (long)b * sT : nullptr;
+    const int s = threadIdx.x;
+    int2 e = make_int2(-1, -1);
+    if (s < 2 * jb) {
+        if (perm) e = perm[(long)b * sPerm + s];
+        else if (s < jb) e = make_int2(c0 + s, c0 + s);
+    }
+    for (int cc = 0; cc < PR_TC; ++cc) {
+        const int gcol = blockIdx.x * PR_TC + cc;
+        if (gcol >= ncols) break;
+        C v = czero<C>();
+        if (e.y >= 0) v = Xb[e.y + (long)gcol * ldx];
+        __syncthreads();
+        if (s < jb) {
+            if (Tb) Tb[s + (long)gcol * ldt] = v;
+            else Xb[(c0 + s) + (long)gcol * ldx] = v;
+        } else if (e.x >= 0) {
+            Xb[e.x + (long)gcol * ldx] = v;
+        }
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -356,29 +401,52 @@ static void panel_base(hipStream_t st, typename cpx<R>::T* A, long sA, int lda, 
 template <typename R>
 static void perm_trsm(hipStream_t st, const typename cpx<R>::T* LU, long sLU, int ldl, const int2* perm, long sPerm,
                       typename cpx<R>::T* X, long sX, int ldx, int c0, int jb, int ncols, int mode,
-                      const int* active, int batch)
+                      const int* active, int batch, int xr0 = 0)
 {
     if (ncols <= 0 || jb <= 0) return;
-    dim3 g((ncols + TS_TC - 1) / TS_TC, batch);
-    hipLaunchKernelGGL(perm_trsm_kernel<R>, g, dim3(TS_NT), 0, st, LU, sLU, ldl, perm, sPerm, X, sX, ldx, c0, jb,
-                       ncols, mode, active);
+    if (jb <= 64) {
+        constexpr int TC = 32;
+        dim3 g((ncols + TC - 1) / TC, batch);
+        hipLaunchKernelGGL((perm_trsm_kernel<R, 64, TC>), g, dim3(TS_NT), 0, st, LU, sLU, ldl, perm, sPerm, X, sX, ldx,
+                           xr0, c0, jb, ncols, mode, active);
+    } else {
+        constexpr int MJB = max_panel<R>();
+        constexpr int TC = 16;
+        dim3 g((ncols + TC - 1) / TC, batch);
+        hipLaunchKernelGGL((perm_trsm_kernel<R, MJB, TC>), g, dim3(TS_NT), 0, st, LU, sLU, ldl, perm, sPerm, X, sX,
+                           ldx, xr0, c0, jb, ncols, mode, active);
+    }
 }
 
 template <typename R>
+static void perm_rows(hipStream_t st, const int2* perm, long sPerm, typename cpx<R>::T* X, long sX, int ldx,
+                      typename cpx<R>::T* T, long sT, int ldt, int c0, int jb, int ncols, const int* active, int batch)
+{
+    if (ncols <= 0 || jb <= 0) return;
+    dim3 g((ncols + PR_TC - 1) / PR_TC, batch);
+    hipLaunchKernelGGL(perm_rows_kernel<R>, g, dim3(2 * MAX_NB), 0, st, perm, sPerm, X, sX, ldx, T, sT, ldt, c0, jb,
+                       ncols, active);
+}
+
+// C = beta C - alpha A B (defaults alpha = beta = 1: C -= A B).  The products
+// C = A B with the diagonal-block inverses use alpha = -1, beta = 0.
+template <typename R>
 static hipError_t gemm_sub(hipStream_t st, int M, int N, int K, const typename cpx<R>::T* A, int lda, long sA,
                            const typename cpx<R>::T* B, int ldb, long sB, typename cpx<R>::T* Cm, int ldc, long sC,
-                           int batch, int tag = 0);
+                           int batch, int tag = 0, double alpha = 1.0, double beta = 1.0);
 template <>
 hipError_t gemm_sub<float>(hipStream_t st, int M, int N, int K, const float2* A, int lda, long sA, const float2* B,
-                           int ldb, long sB, float2* Cm, int ldc, long sC, int batch, int tag)
+                           int ldb, long sB, float2* Cm, int ldc, long sC, int batch, int tag, double alpha,
+                           double beta)
 {
-    return cgemm(st, M, N, K, -1.f, A, lda, sA, B, ldb, sB, 1.f, Cm, ldc, sC, batch, tag);
+    return cgemm(st, M, N, K, (float)-alpha, A, lda, sA, B, ldb, sB, (float)beta, Cm, ldc, sC, batch, tag);
 }
 template <>
 hipError_t gemm_sub<double>(hipStream_t st, int M, int N, int K, const double2* A, int lda, long sA,
-                            const double2* B, int ldb, long sB, double2* Cm, int ldc, long sC, int batch, int tag)
+                            const double2* B, int ldb, long sB, double2* Cm, int ldc, long sC, int batch, int tag,
+                            double alpha, double beta)
 {
-    return zgemm(st, 0, 0, M, N, K, -1.0, A, lda, sA, B, ldb, sB, 1.0, Cm, ldc, sC, batch, tag);
+    return zgemm(st, 0, 0, M, N, K, -alpha, A, lda, sA, B, ldb, sB, beta, Cm, ldc, sC, batch, tag);
 }
 
 // Recursive panel factorisation of columns [c0, c0+w) (rows c0..n-1).
@@ -410,25 +478,50 @@ static void factor_panel(hipStream_t st, typename cpx<R>::T* A, long sA, int lda
     perm_trsm<R>(st, A, sA, lda, pm, sTP, A + (long)c0 * lda, sA, lda, c0 + w1, w2, w1, 0, active, batch);
 }
 
+// Diagonal-block inverses of panel p (complex-FP32 path): L11^-1 at
+// inv + (2p) nb^2, U11^-1 at inv + (2p+1) nb^2, ld nb.
 template <typename R>
-hipError_t getrf_batched(hipStream_t st, typename cpx<R>::T* A, long sA, int lda, int n, int nb, int* ipiv, long sP,
-                         int2* perm, long sPerm, int* info, int2* tperm, long sTP, const int* active, int batch,
-                         UpdateRecorder* rec)
+static typename cpx<R>::T* panel_inv(const LUWork& w, int p, int nb, int which)
 {
-    if (nb > MAX_NB) nb = MAX_NB;
+    return (typename cpx<R>::T*)w.inv + (long)(2 * p + which) * nb * nb;
+}
+
+template <typename R>
+hipError_t getrf_batched(hipStream_t st, typename cpx<R>::T* A, long sA, int lda, int n, int nb, const LUWork& w,
+                         int batch)
+{
+    typedef typename cpx<R>::T C;
+    constexpr bool use_inv = sizeof(R) == 4;
+    if (nb > max_panel<R>()) nb = max_panel<R>();
+    UpdateRecorder* rec = w.rec;
     for (int c0 = 0; c0 < n; c0 += nb) {
         const int jb = (n - c0 < nb) ? n - c0 : nb;
-        factor_panel<R>(st, A, sA, lda, n, c0, jb, ipiv, sP, info, tperm, sTP, 0, active, batch);
-        int2* pm = perm + (long)(c0 / nb) * 2 * MAX_NB;
-        hipLaunchKernelGGL(perm_build_kernel, dim3(batch), dim3(64), 0, st, ipiv, sP, c0, jb, pm, sPerm, active);
+        const int p = c0 / nb;
+        factor_panel<R>(st, A, sA, lda, n, c0, jb, w.ipiv, w.sP, w.info, w.tperm, w.sTP, 0, w.active, batch);
+        int2* pm = w.perm + (long)p * 2 * MAX_NB;
+        hipLaunchKernelGGL(perm_build_kernel, dim3(batch), dim3(64), 0, st, w.ipiv, w.sP, c0, jb, pm, w.sPerm, w.active);
         const int rest = n - c0 - jb;
+        if (use_inv) {
+            // L11^-1 and U11^-1 of this panel (also used by the solves)
+            perm_trsm<R>(st, A, sA, lda, (const int2*)nullptr, 0, panel_inv<R>(w, p, nb, 0), w.sInv, nb, c0, jb, jb, 4,
+                         w.active, batch, c0);
+            perm_trsm<R>(st, A, sA, lda, (const int2*)nullptr, 0, panel_inv<R>(w, p, nb, 1), w.sInv, nb, c0, jb, jb, 5,
+                         w.active, batch, c0);
+        }
         if (rest > 0) {
-            perm_trsm<R>(st, A, sA, lda, pm, sPerm, A + (long)(c0 + jb) * lda, sA, lda, c0, jb, rest, 1, active,
-                         batch);
+            C* Ar = A + (long)(c0 + jb) * lda;
+            if (use_inv) {
+                // interchanges on the right block (top rows to the scratch), then U12 = L11^-1 A12 on MFMA
+                perm_rows<R>(st, pm, w.sPerm, Ar, sA, lda, (C*)w.tmp, w.sTmp, nb, c0, jb, rest, w.active, batch);
+                (void)gemm_sub<R>(st, jb, rest, jb, panel_inv<R>(w, p, nb, 0), nb, w.sInv, (const C*)w.tmp, nb,
+                                  w.sTmp, Ar + c0, lda, sA, batch, 0, -1.0, 0.0);
+            } else {
+                perm_trsm<R>(st, A, sA, lda, pm, w.sPerm, Ar, sA, lda, c0, jb, rest, 1, w.active, batch);
+            }
             const bool timed = rec && rec->used < rec->cap;
             if (timed) (void)hipEventRecord(rec->ev[2 * rec->used], st);
-            (void)gemm_sub<R>(st, rest, rest, jb, A + (c0 + jb) + (long)c0 * lda, lda, sA, A + c0 + (long)(c0 + jb) * lda,
-                        lda, sA, A + (c0 + jb) + (long)(c0 + jb) * lda, lda, sA, batch, 1);
+            (void)gemm_sub<R>(st, rest, rest, jb, A + (c0 + jb) + (long)c0 * lda, lda, sA, Ar + c0, lda, sA,
+                              Ar + c0 + jb, lda, sA, batch, 1);
             if (timed) {
                 (void)hipEventRecord(rec->ev[2 * rec->used + 1], st);
                 rec->used++;
@@ -443,36 +536,47 @@ hipError_t getrf_batched(hipStream_t st, typename cpx<R>::T* A, long sA, int lda
 
 template <typename R>
 hipError_t getrs_batched(hipStream_t st, const typename cpx<R>::T* LU, long sLU, int lda, int n, int nb,
-                         const int2* perm, long sPerm, typename cpx<R>::T* X, long sX, int ldx, int nrhs,
-                         const int* active, int batch)
+                         const LUWork& w, typename cpx<R>::T* X, long sX, int ldx, int nrhs, int batch)
 {
-    if (nb > MAX_NB) nb = MAX_NB;
+    typedef typename cpx<R>::T C;
+    constexpr bool use_inv = sizeof(R) == 4;
+    if (nb > max_panel<R>()) nb = max_panel<R>();
     const int np = (n + nb - 1) / nb;
     for (int p = 0; p < np; ++p) {
         const int c0 = p * nb, jb = (n - c0 < nb) ? n - c0 : nb;
-        perm_trsm<R>(st, LU, sLU, lda, perm + (long)p * 2 * MAX_NB, sPerm, X, sX, ldx, c0, jb, nrhs, 1, active,
-                     batch);
+        const int2* pm = w.perm + (long)p * 2 * MAX_NB;
+        if (use_inv) {
+            perm_rows<R>(st, pm, w.sPerm, X, sX, ldx, (C*)w.tmp, w.sTmp, nb, c0, jb, nrhs, w.active, batch);
+            (void)gemm_sub<R>(st, jb, nrhs, jb, panel_inv<R>(w, p, nb, 0), nb, w.sInv, (const C*)w.tmp, nb, w.sTmp,
+                              X + c0, ldx, sX, batch, 0, -1.0, 0.0);
+        } else {
+            perm_trsm<R>(st, LU, sLU, lda, pm, w.sPerm, X, sX, ldx, c0, jb, nrhs, 1, w.active, batch);
+        }
         const int rest = n - c0 - jb;
         if (rest > 0)
-            (void)gemm_sub<R>(st, rest, nrhs, jb, LU + (c0 + jb) + (long)c0 * lda, lda, sLU, X + c0, ldx, sX, X + c0 + jb,
-                        ldx, sX, batch);
+            (void)gemm_sub<R>(st, rest, nrhs, jb, LU + (c0 + jb) + (long)c0 * lda, lda, sLU, X + c0, ldx, sX,
+                              X + c0 + jb, ldx, sX, batch);
     }
     for (int p = np - 1; p >= 0; --p) {
         const int c0 = p * nb, jb = (n - c0 < nb) ? n - c0 : nb;
-        perm_trsm<R>(st, LU, sLU, lda, nullptr, 0, X, sX, ldx, c0, jb, nrhs, 2, active, batch);
+        if (use_inv) {
+            perm_rows<R>(st, nullptr, 0, X, sX, ldx, (C*)w.tmp, w.sTmp, nb, c0, jb, nrhs, w.active, batch);
+            (void)gemm_sub<R>(st, jb, nrhs, jb, panel_inv<R>(w, p, nb, 1), nb, w.sInv, (const C*)w.tmp, nb, w.sTmp,
+                              X + c0, ldx, sX, batch, 0, -1.0, 0.0);
+        } else {
+            perm_trsm<R>(st, LU, sLU, lda, nullptr, 0, X, sX, ldx, c0, jb, nrhs, 2, w.active, batch);
+        }
         if (c0 > 0)
             (void)gemm_sub<R>(st, c0, nrhs, jb, LU + (long)c0 * lda, lda, sLU, X + c0, ldx, sX, X, ldx, sX, batch);
     }
     return hipGetLastError();
 }
 
-template hipError_t getrf_batched<float>(hipStream_t, float2*, long, int, int, int, int*, long, int2*, long, int*,
-                                         int2*, long, const int*, int, UpdateRecorder*);
-template hipError_t getrf_batched<double>(hipStream_t, double2*, long, int, int, int, int*, long, int2*, long, int*,
-                                          int2*, long, const int*, int, UpdateRecorder*);
-template hipError_t getrs_batched<float>(hipStream_t, const float2*, long, int, int, int, const int2*, long, float2*,
-                                         long, int, int, const int*, int);
-template hipError_t getrs_batched<double>(hipStream_t, const double2*, long, int, int, int, const int2*, long,
-                                          double2*, long, int, int, const int*, int);
+template hipError_t getrf_batched<float>(hipStream_t, float2*, long, int, int, int, const LUWork&, int);
+template hipError_t getrf_batched<double>(hipStream_t, double2*, long, int, int, int, const LUWork&, int);
+template hipError_t getrs_batched<float>(hipStream_t, const float2*, long, int, int, int, const LUWork&, float2*, long,
+                                         int, int, int);
+template hipError_t getrs_batched<double>(hipStream_t, const double2*, long, int, int, int, const LUWork&, double2*,
+                                          long, int, int, int);
 
 }  // namespace rsrr
