@@ -72,6 +72,13 @@ rsrr_status rsrr_create(rsrr_ctx** ctx, int device, void* stream)
     c->stream = (hipStream_t)stream;
     for (auto& e : c->ev)
         if (hipEventCreate(&e) != hipSuccess) { delete c; return RSRR_EDEVICE; }
+    if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->offset, hipEventDisableTiming) != hipSuccess) {
+        delete c;
+        return RSRR_EDEVICE;
+    }
     *ctx = c;
     return RSRR_OK;
 }
@@ -84,6 +91,10 @@ rsrr_status rsrr_destroy(rsrr_ctx* c)
     for (int s = 0; s < WS_COUNT; ++s)
         if (c->ws[s]) (void)hipFree(c->ws[s]);
     for (auto& e : c->ev) (void)hipEventDestroy(e);
+    if (c->aux) (void)hipStreamDestroy(c->aux);
+    if (c->fork) (void)hipEventDestroy(c->fork);
+    if (c->join) (void)hipEventDestroy(c->join);
+    if (c->offset) (void)hipEventDestroy(c->offset);
     if (c->rec.ev) {
         for (int i = 0; i < 2 * c->rec.cap; ++i) (void)hipEventDestroy(c->rec.ev[i]);
         delete[] c->rec.ev;
@@ -292,6 +303,43 @@ static rsrr_status residual_batch(rsrr_ctx* c, int n, int L, const double2* U, i
     return RSRR_OK;
 }
 
+// Offset a workspace view to the matrices starting at b0.
+static LUWork lu_offset(const LUWork& w, long b0)
+{
+    LUWork o = w;
+    o.ipiv = w.ipiv + b0 * w.sP;
+    o.perm = w.perm + b0 * w.sPerm;
+    o.tperm = w.tperm + b0 * w.sTP;
+    o.info = w.info + b0;
+    if (w.inv) o.inv = (char*)w.inv + b0 * w.sInv * 8;
+    if (w.tmp) o.tmp = (char*)w.tmp + b0 * w.sTmp * 8;
+    if (w.active) o.active = w.active + b0;
+    return o;
+}
+
+// Run f(stream, b0, count, offset_event) for the point groups, group 0 on the
+// context stream and group 1 on the auxiliary stream, joined back into the
+// context stream.  When group 0 records `offset_event` (the factorisation does
+// after its first panel), group 1 starts only then, so the two groups' panel
+// phases interleave with each other's trailing updates instead of coinciding.
+template <typename F>
+static rsrr_status split_groups(rsrr_ctx* c, int B, F f, bool stagger = false)
+{
+    const int G = (B >= 8 && c->groups > 1) ? 2 : 1;
+    if (G == 1) return f(c->stream, 0, B, (hipEvent_t) nullptr);
+    RSRR_HIP(hipEventRecord(c->fork, c->stream));
+    RSRR_HIP(hipStreamWaitEvent(c->aux, c->fork, 0));
+    const int h = B / 2;
+    rsrr_status st = f(c->stream, 0, h, stagger ? c->offset : (hipEvent_t) nullptr);
+    if (st) return st;
+    if (stagger) RSRR_HIP(hipStreamWaitEvent(c->aux, c->offset, 0));
+    st = f(c->aux, h, B - h, (hipEvent_t) nullptr);
+    if (st) return st;
+    RSRR_HIP(hipEventRecord(c->join, c->aux));
+    RSRR_HIP(hipStreamWaitEvent(c->stream, c->join, 0));
+    return RSRR_OK;
+}
+
 static rsrr_status sample_batch(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, int B, const double2* U, int L, int ldu,
                                 const std::vector<double>& un, int prec, double2* S, int lds,
                                 rsrr_point_info* info, int* any_singular, int* any_fallback, int* any_nan)
@@ -313,12 +361,20 @@ static rsrr_status sample_batch(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, i
     {
         PhaseTimer t(c, &tm[1]);
         RSRR_HIP(hipMemsetAsync(s.info, 0, (size_t)B * 4, c->stream));
-        if (prec == RSRR_PREC_C128)
-            RSRR_HIP(getrf_batched<double>(c->stream, (double2*)s.Tlu, s.sT, s.ld, n, s.nb,
-                                           s.lu(nullptr, c->rec_on ? &c->rec : nullptr), B));
-        else
-            RSRR_HIP(getrf_batched<float>(c->stream, (float2*)s.Tlu, s.sT, s.ld, n, s.nb,
-                                          s.lu(nullptr, c->rec_on ? &c->rec : nullptr), B));
+        const LUWork w = s.lu(nullptr, c->rec_on ? &c->rec : nullptr);
+        st = split_groups(
+            c, B,
+            [&](hipStream_t sm, int b0, int nbg, hipEvent_t ev) -> rsrr_status {
+                LUWork wg = lu_offset(w, b0);
+                wg.first_panel = ev;
+                if (prec == RSRR_PREC_C128)
+                    RSRR_HIP(getrf_batched<double>(sm, (double2*)s.Tlu + b0 * s.sT, s.sT, s.ld, n, s.nb, wg, nbg));
+                else
+                    RSRR_HIP(getrf_batched<float>(sm, (float2*)s.Tlu + b0 * s.sT, s.sT, s.ld, n, s.nb, wg, nbg));
+                return RSRR_OK;
+            },
+            true);
+        if (st) return st;
         t.stop();
         if (c->rec_on) rec_collect(c);
         RSRR_HIP(hipMemcpyAsync(hinfo.data(), s.info, (size_t)B * 4, hipMemcpyDeviceToHost, c->stream));
@@ -344,8 +400,13 @@ static rsrr_status sample_batch(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, i
         {
             PhaseTimer t(c, &tm[2]);
             RSRR_HIP(bcast_c128(c->stream, n, L, U, ldu, S, lds, sX, B));
-            RSRR_HIP(getrs_batched<double>(c->stream, (const double2*)s.Tlu, s.sT, s.ld, n, s.nb,
-                                           s.lu(s.active, nullptr), S, sX, lds, L, B));
+            const LUWork w = s.lu(s.active, nullptr);
+            st = split_groups(c, B, [&](hipStream_t sm, int b0, int nbg, hipEvent_t) -> rsrr_status {
+                RSRR_HIP(getrs_batched<double>(sm, (const double2*)s.Tlu + b0 * s.sT, s.sT, s.ld, n, s.nb,
+                                               lu_offset(w, b0), S + b0 * sX, sX, lds, L, nbg));
+                return RSRR_OK;
+            });
+            if (st) return st;
             t.stop();
         }
         {
@@ -366,8 +427,13 @@ static rsrr_status sample_batch(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, i
     {
         PhaseTimer t(c, &tm[2]);
         RSRR_HIP(bcast_to_c64(c->stream, n, L, U, ldu, s.D64, s.ld, (long)s.ld * L, B));
-        RSRR_HIP(getrs_batched<float>(c->stream, (const float2*)s.Tlu, s.sT, s.ld, n, s.nb, s.lu(s.active, nullptr),
-                                      s.D64, (long)s.ld * L, s.ld, L, B));
+        const LUWork w = s.lu(s.active, nullptr);
+        st = split_groups(c, B, [&](hipStream_t sm, int b0, int nbg, hipEvent_t) -> rsrr_status {
+            RSRR_HIP(getrs_batched<float>(sm, (const float2*)s.Tlu + b0 * s.sT, s.sT, s.ld, n, s.nb, lu_offset(w, b0),
+                                          s.D64 + b0 * (long)s.ld * L, (long)s.ld * L, s.ld, L, nbg));
+            return RSRR_OK;
+        });
+        if (st) return st;
         RSRR_HIP(widen(c->stream, n, L, s.D64, s.ld, (long)s.ld * L, S, lds, sX, B));
         t.stop();
     }
@@ -415,8 +481,14 @@ static rsrr_status sample_batch(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, i
                                     c->stream));
             RSRR_HIP(scale_narrow(c->stream, n, L, s.R, s.ld, (long)s.ld * L, s.norms + (size_t)2 * B * L, s.D64, s.ld,
                                   (long)s.ld * L, s.active, B));
-            RSRR_HIP(getrs_batched<float>(c->stream, (const float2*)s.Tlu, s.sT, s.ld, n, s.nb,
-                                          s.lu(s.active, nullptr), s.D64, (long)s.ld * L, s.ld, L, B));
+            const LUWork w = s.lu(s.active, nullptr);
+            st = split_groups(c, B, [&](hipStream_t sm, int b0, int nbg, hipEvent_t) -> rsrr_status {
+                RSRR_HIP(getrs_batched<float>(sm, (const float2*)s.Tlu + b0 * s.sT, s.sT, s.ld, n, s.nb,
+                                              lu_offset(w, b0), s.D64 + b0 * (long)s.ld * L, (long)s.ld * L, s.ld,
+                                              L, nbg));
+                return RSRR_OK;
+            });
+            if (st) return st;
             RSRR_HIP(hipMemcpyAsync(s.norms + (size_t)2 * B * L, scl.data(), (size_t)B * L * 8, hipMemcpyHostToDevice,
                                     c->stream));
             RSRR_HIP(axpy_widen(c->stream, n, L, s.D64, s.ld, (long)s.ld * L, s.norms + (size_t)2 * B * L, S, lds, sX,

@@ -22,6 +22,9 @@ enum WsSlot {
 struct rsrr_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    hipStream_t aux = nullptr;       // second stream (default priority) for the second point group
+    hipEvent_t fork = nullptr, join = nullptr, offset = nullptr;
+    int groups = 1;                  // point groups factored on separate streams (1 = off; measured no overlap)
     void* ws[WS_COUNT] = {};
     size_t ws_size[WS_COUNT] = {};
     hipEvent_t ev[2] = {};

@@ -53,6 +53,7 @@ struct LUWork {
     void* tmp = nullptr; long sTmp = 0;
     const int* active = nullptr;
     UpdateRecorder* rec = nullptr;
+    hipEvent_t first_panel = nullptr;  // recorded once the first panel and its row block are done
 };
 
 // Blocked LU with partial pivoting of `batch` n x n matrices (stride sA).

@@ -518,6 +518,7 @@ hipError_t getrf_batched(hipStream_t st, typename cpx<R>::T* A, long sA, int lda
             } else {
                 perm_trsm<R>(st, A, sA, lda, pm, w.sPerm, Ar, sA, lda, c0, jb, rest, 1, w.active, batch);
             }
+            if (c0 == 0 && w.first_panel) (void)hipEventRecord(w.first_panel, st);
             const bool timed = rec && rec->used < rec->cap;
             if (timed) (void)hipEventRecord(rec->ev[2 * rec->used], st);
             (void)gemm_sub<R>(st, rest, rest, jb, A + (c0 + jb) + (long)c0 * lda, lda, sA, Ar + c0, lda, sA,
