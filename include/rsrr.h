@@ -200,6 +200,42 @@ RSRR_API rsrr_status rsrr_solve(rsrr_ctx *ctx, const rsrr_nep *nep, int k, const
  * t[3] FP64 residuals, t[4] total.  t: host, 5 doubles.  Errors: -2 t NULL. */
 RSRR_API rsrr_status rsrr_last_timings(rsrr_ctx *ctx, double *t);
 
+/* One NEP instance of a ragged batch: T(z) (nep), N sampling points z (host,
+ * 2N doubles), probes U (device, n x L, ldu >= n) and the output S (device,
+ * n x N*L, lds >= n; block k = T(z_k)^-1 U). */
+typedef struct {
+    rsrr_nep nep;
+    int N;
+    const double *z;
+    const double *U;
+    int L;
+    int ldu;
+    double *S;
+    int lds;
+} rsrr_instance;
+
+/* Flags of rsrr_sample_batched. */
+enum {
+    RSRR_BATCH_GRAPH = 1,     /* capture each size bucket's work in a hipGraph; replay it when the
+                                 same batch (same buffers, sizes and points) is submitted again   */
+    RSRR_BATCH_AUTOTUNE = 2   /* time the LU panel widths on the first call for each size bucket */
+};
+
+/* Resolvent sampling for a ragged batch of instances (RSRR Step 2, eq. hatS,
+ * for many NEPs at once).  Instances are grouped by n rounded up to 64; each
+ * group runs as one batch of padded matrices diag(T(z_k), I) (the padded
+ * solve returns T(z_k)^-1 U exactly).  With C64_IR the refinement runs on the
+ * device with at most 3 corrections; points above 1e-10 relative residual
+ * are redone on the FP64 path.  info: host, sum of N entries in instance
+ * order (may be NULL).  The library keeps per-bucket buffers (and graphs) in
+ * the context until rsrr_destroy.  Panel widths chosen by the autotuner are
+ * cached per (bucket, precision) and, when the environment variable
+ * RSRR_TUNE_FILE names a file, read from and written to it.
+ * Status as rsrr_sample.  Errors: -2 count < 1, -3 an instance is invalid,
+ * -4 prec. */
+RSRR_API rsrr_status rsrr_sample_batched(rsrr_ctx *ctx, int count, const rsrr_instance *inst, int prec, int flags,
+                                         rsrr_point_info *info);
+
 /* Device-event statistics of the LU trailing-update kernel (A22 -= L21 U12,
  * the matrix-core hot loop of rsrr_sample).  enable = 1 starts recording a
  * pair of events around every trailing-update launch of later rsrr_sample

@@ -1,0 +1,454 @@
+// C ABI: resolvent sampling for a ragged batch of NEP instances (RSRR Step 2
+// for many problems at once).
+//
+// Instances are grouped in size buckets P = n rounded up to 64.  Inside a
+// bucket every (instance, point) pair is one P x P matrix: T(z_k) occupies the
+// leading n x n block and the identity the rest, so the LU stays block
+// diagonal (no pivot is ever taken from the identity part, whose entries in
+// the leading columns are zero) and the solve with [U; 0] returns
+// [T^-1 U; 0].  The bucket is then one uniform batch for the LU, solve and
+// refinement kernels.  Refinement decisions are taken on the device (fixed
+// budget of corrections, per-point masks), so a bucket's work has no host
+// synchronisation and can be captured once in a hipGraph and replayed.
+// The panel width of each bucket is picked by timing the factorisation with
+// each candidate (autotune) and is cached per (P, precision), optionally in a
+// text file (RSRR_TUNE_FILE).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <vector>
+
+#include "ctx.h"
+#include "kernels.h"
+
+using namespace rsrr;
+
+namespace {
+
+constexpr int BUCKET = 64;
+constexpr int MAXIT_BATCHED = 3;
+
+struct GraphEntry {
+    std::vector<unsigned long long> key;
+    hipGraphExec_t exec = nullptr;
+    std::vector<double2> coef_host;   // host staging referenced by the captured copies
+    std::vector<int> nk_host;
+};
+
+struct BatchedState {
+    std::map<long, int> tuned;                    // (P*2 + prec) -> nb
+    std::map<long, std::unique_ptr<GraphEntry>> graphs;  // bucket P*2+prec -> captured graph
+    std::vector<void*> bufs;
+    std::vector<size_t> sizes;
+    bool file_loaded = false;
+};
+
+std::map<rsrr_ctx*, std::unique_ptr<BatchedState>>& states()
+{
+    static std::map<rsrr_ctx*, std::unique_ptr<BatchedState>> m;
+    return m;
+}
+
+BatchedState& state_of(rsrr_ctx* c)
+{
+    auto& m = states();
+    auto it = m.find(c);
+    if (it == m.end()) it = m.emplace(c, std::make_unique<BatchedState>()).first;
+    return *it->second;
+}
+
+void* bget(BatchedState& S, int slot, size_t bytes, hipStream_t st)
+{
+    if ((int)S.bufs.size() <= slot) {
+        S.bufs.resize(slot + 1, nullptr);
+        S.sizes.resize(slot + 1, 0);
+    }
+    if (bytes == 0) bytes = 256;
+    if (S.sizes[slot] >= bytes) return S.bufs[slot];
+    if (S.bufs[slot]) {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(S.bufs[slot]);
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        S.bufs[slot] = nullptr;
+        S.sizes[slot] = 0;
+        return nullptr;
+    }
+    S.bufs[slot] = p;
+    S.sizes[slot] = bytes;
+    return p;
+}
+
+void load_tune_file(BatchedState& S)
+{
+    if (S.file_loaded) return;
+    S.file_loaded = true;
+    const char* f = std::getenv("RSRR_TUNE_FILE");
+    if (!f) return;
+    FILE* fp = std::fopen(f, "r");
+    if (!fp) return;
+    long key;
+    int nb;
+    while (std::fscanf(fp, "%ld %d", &key, &nb) == 2) S.tuned[key] = nb;
+    std::fclose(fp);
+}
+
+void save_tune_file(const BatchedState& S)
+{
+    const char* f = std::getenv("RSRR_TUNE_FILE");
+    if (!f) return;
+    FILE* fp = std::fopen(f, "w");
+    if (!fp) return;
+    for (auto& kv : S.tuned) std::fprintf(fp, "%ld %d\n", kv.first, kv.second);
+    std::fclose(fp);
+}
+
+struct BucketBufs {
+    void* T; double2* T128; double2* Ub; double2* Xb; double2* R; float2* D64; int* ipiv; int2* perm; int2* tperm;
+    int* info; void* inv; void* tmp; int* nk; double2* coef; double* frobp; double* frob; double* un; double* rn;
+    double* xn; double* inv_s; double* scl; int* active; double* prev; double* resid; int* iters; double* ones;
+    long sT, sU, sP, sPerm, sTP, sInv, sTmp;
+};
+
+// Everything a bucket does on the device, in stream order (capturable).
+rsrr_status run_bucket(rsrr_ctx* c, hipStream_t sm, const rsrr_instance* inst, const std::vector<int>& ids,
+                       const std::vector<long>& off, int P, int Lmax, long M, int prec, int nb, BucketBufs& b,
+                       const double2* coef_host, const int* nk_host, int maxit)
+{
+    const bool mixed = prec == RSRR_PREC_C64_IR;
+    // per-matrix sizes and the identity padding
+    RSRR_HIP(hipMemcpyAsync(b.nk, nk_host, (size_t)M * 4, hipMemcpyHostToDevice, sm));
+    RSRR_HIP(pad_identity(sm, mixed ? (float2*)b.T : nullptr, b.T128, P, b.sT, P, b.nk, (int)M));
+    if (!mixed) RSRR_HIP(pad_identity(sm, nullptr, (double2*)b.T, P, b.sT, P, b.nk, (int)M));
+    // assembly of every instance's points (FP64 sums, c64 and c128 copies)
+    long coff = 0;
+    for (size_t q = 0; q < ids.size(); ++q) {
+        const rsrr_instance& in = inst[ids[q]];
+        const int n = in.nep.n;
+        const long nparts = ((long)n * n + 255) / 256;
+        if (in.nep.kind == RSRR_T_SEPARABLE) {
+            const long cnt = (long)in.nep.J * in.N;
+            RSRR_HIP(hipMemcpyAsync(b.coef + coff, coef_host + coff, (size_t)cnt * 16, hipMemcpyHostToDevice, sm));
+            RSRR_HIP(assemble_separable(sm, n, in.nep.J, (const double2*)in.nep.A, in.nep.lda, b.coef + coff, in.N,
+                                        mixed ? (float2*)b.T + off[q] * b.sT : nullptr, P, b.sT,
+                                        b.T128 + off[q] * b.sT, P, b.sT, b.frobp + off[q] * nparts, b.frob + off[q]));
+            coff += cnt;
+        } else {
+            const long cnt = in.N;
+            RSRR_HIP(hipMemcpyAsync(b.coef + coff, coef_host + coff, (size_t)cnt * 16, hipMemcpyHostToDevice, sm));
+            RSRR_HIP(assemble_helmholtz(sm, n, in.nep.points, in.nep.w, b.coef + coff, in.N,
+                                        mixed ? (float2*)b.T + off[q] * b.sT : nullptr, P, b.sT,
+                                        b.T128 + off[q] * b.sT, P, b.sT, b.frobp + off[q] * nparts, b.frob + off[q]));
+            coff += cnt;
+        }
+        if (!mixed)
+            RSRR_HIP(copy_c128(sm, n, n, b.T128 + off[q] * b.sT, P, b.sT, (double2*)b.T + off[q] * b.sT, P, b.sT,
+                               in.N));
+    }
+    // padded right-hand sides [U; 0]
+    RSRR_HIP(zero_c128(sm, P, Lmax, b.Ub, P, b.sU, (int)M));
+    for (size_t q = 0; q < ids.size(); ++q) {
+        const rsrr_instance& in = inst[ids[q]];
+        RSRR_HIP(bcast_c128(sm, in.nep.n, in.L, (const double2*)in.U, in.ldu, b.Ub + off[q] * b.sU, P, b.sU, in.N));
+    }
+    RSRR_HIP(colnorms(sm, P, Lmax, b.Ub, P, b.sU, b.un, (int)M));
+    // factorisation
+    RSRR_HIP(zero_int(sm, b.info, (int)M));
+    LUWork w;
+    w.ipiv = b.ipiv; w.sP = b.sP; w.perm = b.perm; w.sPerm = b.sPerm; w.tperm = b.tperm; w.sTP = b.sTP;
+    w.info = b.info; w.inv = b.inv; w.sInv = b.sInv; w.tmp = b.tmp; w.sTmp = b.sTmp;
+    if (mixed) RSRR_HIP(getrf_batched<float>(sm, (float2*)b.T, b.sT, P, P, nb, w, (int)M));
+    else RSRR_HIP(getrf_batched<double>(sm, (double2*)b.T, b.sT, P, P, nb, w, (int)M));
+    RSRR_HIP(ir_init(sm, (int)M, b.info, b.active, b.prev, b.resid, b.iters));
+    w.active = b.active;
+    // first solve
+    if (mixed) {
+        RSRR_HIP(scale_narrow(sm, P, Lmax, b.Ub, P, b.sU, b.ones, b.D64, P, b.sU, nullptr, (int)M));
+        RSRR_HIP(getrs_batched<float>(sm, (const float2*)b.T, b.sT, P, P, nb, w, b.D64, b.sU, P, Lmax, (int)M));
+        RSRR_HIP(widen(sm, P, Lmax, b.D64, P, b.sU, b.Xb, P, b.sU, (int)M));
+    } else {
+        RSRR_HIP(copy_c128(sm, P, Lmax, b.Ub, P, b.sU, b.Xb, P, b.sU, (int)M));
+        RSRR_HIP(getrs_batched<double>(sm, (const double2*)b.T, b.sT, P, P, nb, w, b.Xb, b.sU, P, Lmax, (int)M));
+    }
+    // refinement with FP64 residuals, decisions on the device
+    const double tol_be = 4.0 * 1.1102230246251565e-16 * std::sqrt((double)P);
+    const int iters = mixed ? maxit : 0;
+    for (int it = 0; it <= iters; ++it) {
+        RSRR_HIP(copy_c128(sm, P, Lmax, b.Ub, P, b.sU, b.R, P, b.sU, (int)M));
+        RSRR_HIP(zgemm(sm, 0, 0, P, Lmax, P, -1.0, b.T128, P, b.sT, b.Xb, P, b.sU, 1.0, b.R, P, b.sU, (int)M));
+        RSRR_HIP(colnorms(sm, P, Lmax, b.R, P, b.sU, b.rn, (int)M));
+        RSRR_HIP(colnorms(sm, P, Lmax, b.Xb, P, b.sU, b.xn, (int)M));
+        RSRR_HIP(ir_decide(sm, (int)M, Lmax, b.rn, b.xn, b.un, b.frob, tol_be, it, iters, b.active, b.prev, b.resid,
+                           b.iters, b.inv_s, b.scl));
+        if (it == iters) break;
+        RSRR_HIP(scale_narrow(sm, P, Lmax, b.R, P, b.sU, b.inv_s, b.D64, P, b.sU, b.active, (int)M));
+        RSRR_HIP(getrs_batched<float>(sm, (const float2*)b.T, b.sT, P, P, nb, w, b.D64, b.sU, P, Lmax, (int)M));
+        RSRR_HIP(axpy_widen(sm, P, Lmax, b.D64, P, b.sU, b.scl, b.Xb, P, b.sU, b.active, (int)M));
+    }
+    // results into each instance's S
+    for (size_t q = 0; q < ids.size(); ++q) {
+        const rsrr_instance& in = inst[ids[q]];
+        RSRR_HIP(copy_c128(sm, in.nep.n, in.L, b.Xb + off[q] * b.sU, P, b.sU, (double2*)in.S, in.lds,
+                           (long)in.L * in.lds, in.N));
+    }
+    return RSRR_OK;
+}
+
+}  // namespace
+
+void batched_release(rsrr_ctx* c)
+{
+    auto& m = states();
+    auto it = m.find(c);
+    if (it == m.end()) return;
+    for (auto& g : it->second->graphs)
+        if (g.second && g.second->exec) (void)hipGraphExecDestroy(g.second->exec);
+    for (void* p : it->second->bufs)
+        if (p) (void)hipFree(p);
+    m.erase(it);
+}
+
+extern "C" rsrr_status rsrr_sample_batched(rsrr_ctx* c, int count, const rsrr_instance* inst, int prec, int flags,
+                                           rsrr_point_info* info)
+{
+    if (!c) return -1;
+    if (count < 1) return -2;
+    if (!inst) return -3;
+    if (prec != RSRR_PREC_C128 && prec != RSRR_PREC_C64_IR) return -4;
+    for (int i = 0; i < count; ++i) {
+        const rsrr_instance& in = inst[i];
+        const rsrr_nep& e = in.nep;
+        if (e.n < 1 || e.n > 8192) return -3;
+        if (e.kind == RSRR_T_SEPARABLE) {
+            if (e.J < 1 || e.J > 64 || !e.A || e.lda < e.n || !e.terms) return -3;
+        } else if (e.kind == RSRR_T_HELMHOLTZ) {
+            if (!e.points || !(e.w > 0)) return -3;
+        } else {
+            return -3;
+        }
+        if (in.N < 1 || !in.z || !in.U || in.L < 1 || in.ldu < e.n || !in.S || in.lds < e.n) return -3;
+    }
+    RSRR_HIP(hipSetDevice(c->device));
+    BatchedState& S = state_of(c);
+    load_tune_file(S);
+    const bool use_graph = (flags & RSRR_BATCH_GRAPH) != 0;
+    const bool autotune = (flags & RSRR_BATCH_AUTOTUNE) != 0;
+    const bool mixed = prec == RSRR_PREC_C64_IR;
+
+    // point offsets of the instances in the caller's order (for info)
+    std::vector<long> pbase(count + 1, 0);
+    for (int i = 0; i < count; ++i) pbase[i + 1] = pbase[i] + inst[i].N;
+
+    // buckets
+    std::map<int, std::vector<int>> buckets;
+    for (int i = 0; i < count; ++i) buckets[(inst[i].nep.n + BUCKET - 1) / BUCKET * BUCKET].push_back(i);
+
+    int any_sing = 0, any_fb = 0, any_nan = 0;
+    for (auto& kv : buckets) {
+        const int P = kv.first;
+        const std::vector<int>& ids = kv.second;
+        std::vector<long> off(ids.size() + 1, 0);
+        int Lmax = 0, maxn = 0;
+        for (size_t q = 0; q < ids.size(); ++q) {
+            off[q + 1] = off[q] + inst[ids[q]].N;
+            Lmax = std::max(Lmax, inst[ids[q]].L);
+            maxn = std::max(maxn, inst[ids[q]].nep.n);
+        }
+        const long M = off.back();
+        // host tables: per-matrix n and the coefficient / point tables
+        std::vector<int> nk(M);
+        std::vector<double2> coef;
+        for (size_t q = 0; q < ids.size(); ++q) {
+            const rsrr_instance& in = inst[ids[q]];
+            for (long k = off[q]; k < off[q + 1]; ++k) nk[k] = in.nep.n;
+            if (in.nep.kind == RSRR_T_SEPARABLE) {
+                for (int j = 0; j < in.nep.J; ++j)
+                    for (int k = 0; k < in.N; ++k) {
+                        const zd f = term_eval(in.nep.terms[j], zd(in.z[2 * k], in.z[2 * k + 1]));
+                        coef.push_back(make_double2(f.real(), f.imag()));
+                    }
+            } else {
+                for (int k = 0; k < in.N; ++k) coef.push_back(make_double2(in.z[2 * k], in.z[2 * k + 1]));
+            }
+        }
+        // buffers
+        const int npan = perm_panels(P);
+        const int nbmax = mixed ? max_panel<float>() : max_panel<double>();
+        BucketBufs b{};
+        b.sT = (long)P * P;
+        b.sU = (long)P * Lmax;
+        b.sP = P;
+        b.sPerm = (long)npan * 2 * MAX_NB;
+        b.sTP = 8L * 2 * MAX_NB;
+        b.sInv = mixed ? (long)npan * 2 * nbmax * nbmax : 0;
+        b.sTmp = mixed ? (long)nbmax * std::max(P, Lmax) : 0;
+        const size_t esz = mixed ? 8 : 16;
+        long nparts_max = ((long)maxn * maxn + 255) / 256;
+        hipStream_t sm = c->stream;
+        int s = (P / BUCKET) * 32;  // every bucket size has its own buffers (graphs keep pointing at them)
+        b.T = bget(S, s++, (size_t)M * b.sT * esz, sm);
+        b.T128 = (double2*)bget(S, s++, (size_t)M * b.sT * 16, sm);
+        b.Ub = (double2*)bget(S, s++, (size_t)M * b.sU * 16, sm);
+        b.Xb = (double2*)bget(S, s++, (size_t)M * b.sU * 16, sm);
+        b.R = (double2*)bget(S, s++, (size_t)M * b.sU * 16, sm);
+        b.D64 = (float2*)bget(S, s++, (size_t)M * b.sU * 8, sm);
+        b.ipiv = (int*)bget(S, s++, (size_t)M * b.sP * 4, sm);
+        b.perm = (int2*)bget(S, s++, (size_t)M * b.sPerm * 8, sm);
+        b.tperm = (int2*)bget(S, s++, (size_t)M * b.sTP * 8, sm);
+        b.info = (int*)bget(S, s++, (size_t)M * 4, sm);
+        b.inv = mixed ? bget(S, s++, (size_t)M * b.sInv * 8, sm) : (void*)(s++, nullptr);
+        b.tmp = mixed ? bget(S, s++, (size_t)M * b.sTmp * 8, sm) : (void*)(s++, nullptr);
+        b.nk = (int*)bget(S, s++, (size_t)M * 4, sm);
+        b.coef = (double2*)bget(S, s++, coef.size() * 16, sm);
+        b.frobp = (double*)bget(S, s++, (size_t)M * nparts_max * 8, sm);
+        b.frob = (double*)bget(S, s++, (size_t)M * 8, sm);
+        b.un = (double*)bget(S, s++, (size_t)M * Lmax * 8, sm);
+        b.rn = (double*)bget(S, s++, (size_t)M * Lmax * 8, sm);
+        b.xn = (double*)bget(S, s++, (size_t)M * Lmax * 8, sm);
+        b.inv_s = (double*)bget(S, s++, (size_t)M * Lmax * 8, sm);
+        b.scl = (double*)bget(S, s++, (size_t)M * Lmax * 8, sm);
+        b.active = (int*)bget(S, s++, (size_t)M * 4, sm);
+        b.prev = (double*)bget(S, s++, (size_t)M * 8, sm);
+        b.resid = (double*)bget(S, s++, (size_t)M * 8, sm);
+        b.iters = (int*)bget(S, s++, (size_t)M * 4, sm);
+        b.ones = (double*)bget(S, s++, (size_t)M * Lmax * 8, sm);
+        if (!b.T || !b.T128 || !b.Ub || !b.Xb || !b.R || !b.D64 || !b.ipiv || !b.perm || !b.tperm || !b.info ||
+            (mixed && (!b.inv || !b.tmp)) || !b.nk || !b.coef || !b.frobp || !b.frob || !b.un || !b.rn || !b.xn ||
+            !b.inv_s || !b.scl || !b.active || !b.prev || !b.resid || !b.iters || !b.ones)
+            return RSRR_ENOMEM;
+        // the first solve narrows U with scale 1: ones in scl
+        {
+            std::vector<double> ones((size_t)M * Lmax, 1.0);
+            RSRR_HIP(hipMemcpyAsync(b.ones, ones.data(), ones.size() * 8, hipMemcpyHostToDevice, sm));
+            RSRR_HIP(hipStreamSynchronize(sm));
+        }
+
+        // panel width: tuned (timed over the candidates on this bucket) or default
+        const long tkey = (long)P * 2 + (mixed ? 1 : 0);
+        int nb = mixed ? std::min(c->nb_c64, nbmax) : std::min(c->nb_c128, nbmax);
+        auto tu = S.tuned.find(tkey);
+        if (tu != S.tuned.end()) {
+            nb = tu->second;
+        } else if (autotune) {
+            std::vector<int> cand = mixed ? std::vector<int>{32, 64, 128} : std::vector<int>{32, 64};
+            float best = 1e30f;
+            int bestnb = nb;
+            hipEvent_t e0, e1;
+            RSRR_HIP(hipEventCreate(&e0));
+            RSRR_HIP(hipEventCreate(&e1));
+            for (int cb : cand) {
+                if (cb > nbmax) continue;
+                // one full bucket pass (assembly, LU, one solve, one residual) per candidate
+                RSRR_HIP(hipEventRecord(e0, sm));
+                rsrr_status st = run_bucket(c, sm, inst, ids, off, P, Lmax, M, prec, cb, b, coef.data(), nk.data(), 0);
+                if (st) return st;
+                RSRR_HIP(hipEventRecord(e1, sm));
+                RSRR_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                RSRR_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) { best = ms; bestnb = cb; }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            nb = bestnb;
+            S.tuned[tkey] = nb;
+            save_tune_file(S);
+        }
+
+        const int maxit = MAXIT_BATCHED;
+        if (use_graph) {
+            // key: everything the captured work depends on
+            std::vector<unsigned long long> key;
+            key.push_back((unsigned long long)P);
+            key.push_back((unsigned long long)prec);
+            key.push_back((unsigned long long)nb);
+            key.push_back((unsigned long long)M);
+            for (int id : ids) {
+                const rsrr_instance& in = inst[id];
+                key.push_back((unsigned long long)(uintptr_t)in.nep.A);
+                key.push_back((unsigned long long)(uintptr_t)in.nep.points);
+                key.push_back((unsigned long long)(uintptr_t)in.U);
+                key.push_back((unsigned long long)(uintptr_t)in.S);
+                key.push_back(((unsigned long long)in.nep.n << 32) | (unsigned)in.N);
+                key.push_back(((unsigned long long)in.L << 32) | (unsigned)in.lds);
+            }
+            auto& slot = S.graphs[tkey];
+            const bool hit = slot && slot->key == key && slot->coef_host.size() == coef.size() &&
+                             std::memcmp(slot->coef_host.data(), coef.data(), coef.size() * 16) == 0;
+            if (!hit) {
+                if (slot && slot->exec) (void)hipGraphExecDestroy(slot->exec);
+                slot = std::make_unique<GraphEntry>();
+                slot->key = key;
+                slot->coef_host = coef;
+                slot->nk_host = nk;
+                RSRR_HIP(hipEventRecord(c->fork, c->stream));
+                RSRR_HIP(hipStreamWaitEvent(c->aux, c->fork, 0));
+                RSRR_HIP(hipStreamBeginCapture(c->aux, hipStreamCaptureModeThreadLocal));
+                rsrr_status st = run_bucket(c, c->aux, inst, ids, off, P, Lmax, M, prec, nb, b,
+                                            slot->coef_host.data(), slot->nk_host.data(), maxit);
+                hipGraph_t g = nullptr;
+                const hipError_t ce = hipStreamEndCapture(c->aux, &g);
+                if (st) { if (g) (void)hipGraphDestroy(g); slot.reset(); return st; }
+                if (ce != hipSuccess || !g) { slot.reset(); return RSRR_EDEVICE; }
+                const hipError_t ie = hipGraphInstantiate(&slot->exec, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (ie != hipSuccess) { slot.reset(); return RSRR_EDEVICE; }
+            } else {
+                RSRR_HIP(hipEventRecord(c->fork, c->stream));
+                RSRR_HIP(hipStreamWaitEvent(c->aux, c->fork, 0));
+            }
+            RSRR_HIP(hipGraphLaunch(slot->exec, c->aux));
+            RSRR_HIP(hipEventRecord(c->join, c->aux));
+            RSRR_HIP(hipStreamWaitEvent(c->stream, c->join, 0));
+        } else {
+            rsrr_status st = run_bucket(c, c->stream, inst, ids, off, P, Lmax, M, prec, nb, b, coef.data(), nk.data(),
+                                        maxit);
+            if (st) return st;
+        }
+
+        // diagnostics back to the host
+        std::vector<int> hinfo(M), hit(M);
+        std::vector<double> hres(M);
+        RSRR_HIP(hipMemcpyAsync(hinfo.data(), b.info, (size_t)M * 4, hipMemcpyDeviceToHost, c->stream));
+        RSRR_HIP(hipMemcpyAsync(hit.data(), b.iters, (size_t)M * 4, hipMemcpyDeviceToHost, c->stream));
+        RSRR_HIP(hipMemcpyAsync(hres.data(), b.resid, (size_t)M * 8, hipMemcpyDeviceToHost, c->stream));
+        RSRR_HIP(hipStreamSynchronize(c->stream));
+        for (size_t q = 0; q < ids.size(); ++q) {
+            const rsrr_instance& in = inst[ids[q]];
+            for (int k = 0; k < in.N; ++k) {
+                const long m = off[q] + k;
+                rsrr_point_info pi{};
+                pi.info = hinfo[m];
+                pi.ir_iters = hit[m];
+                pi.resid = hres[m];
+                if (hinfo[m] > 0) any_sing = 1;
+                if (hinfo[m] < 0) any_nan = 1;
+                if (hinfo[m] == 0 && !(hres[m] <= 1e-10)) {
+                    // redo this point on the FP64 path
+                    rsrr_point_info fpi;
+                    const rsrr_status st = rsrr_sample(c, &in.nep, 1, in.z + 2 * k, in.U, in.L, in.ldu,
+                                                       RSRR_PREC_C128, in.S + 2 * (size_t)k * in.L * in.lds, in.lds,
+                                                       &fpi);
+                    if (st < 0 || st == RSRR_EDEVICE || st == RSRR_ENOMEM) return st;
+                    pi.fallback = 1;
+                    pi.resid = fpi.resid;
+                    pi.info = fpi.info;
+                    any_fb = 1;
+                }
+                if (info) info[pbase[ids[q]] + k] = pi;
+            }
+        }
+    }
+    if (any_nan) return RSRR_ENAN;
+    if (any_sing) return RSRR_ESINGULAR;
+    if (any_fb) return RSRR_WARN_FALLBACK;
+    return RSRR_OK;
+}

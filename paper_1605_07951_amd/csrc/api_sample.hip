@@ -88,6 +88,8 @@ rsrr_status rsrr_destroy(rsrr_ctx* c)
     if (!c) return -1;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
+    if (c->aux) (void)hipStreamSynchronize(c->aux);
+    batched_release(c);
     for (int s = 0; s < WS_COUNT; ++s)
         if (c->ws[s]) (void)hipFree(c->ws[s]);
     for (auto& e : c->ev) (void)hipEventDestroy(e);

@@ -40,6 +40,9 @@ struct rsrr_ctx {
     long upd_launches = 0, upd_dropped = 0;
 };
 
+// Release the ragged-batch buffers and graphs of a context.
+void batched_release(rsrr_ctx* c);
+
 // Fold the recorded update events into the running statistics (syncs the events).
 void rec_collect(rsrr_ctx* c);
 

@@ -123,7 +123,128 @@ __global__ __launch_bounds__(EW_NT) void scale_cols_kernel(int n, int m, double2
     x->y *= f;
 }
 
+// ---- ragged-batch helpers ----
+
+// Identity outside the leading nk x nk block of each P x P matrix (both copies
+// may be null); the leading block is written by the assembly afterwards.
+template <typename C>
+__global__ __launch_bounds__(EW_NT) void pad_identity_kernel(C* __restrict__ T, int ld, long sT, int P,
+                                                              const int* __restrict__ nk)
+{
+    const int k = blockIdx.y;
+    const long e = (long)blockIdx.x * EW_NT + threadIdx.x;
+    if (e >= (long)P * P) return;
+    const int i = (int)(e % P), j = (int)(e / P);
+    const int n = nk[k];
+    if (i < n && j < n) return;
+    C v;
+    v.x = (i == j) ? 1 : 0;
+    v.y = 0;
+    T[k * sT + i + (long)j * ld] = v;
+}
+
+// Fill n x m (c128) blocks with zeros (graph-safe replacement of a memset).
+__global__ __launch_bounds__(EW_NT) void zero_c128_kernel(int n, int m, double2* __restrict__ X, int ldx, long sX)
+{
+    const int k = blockIdx.y;
+    const long e = (long)blockIdx.x * EW_NT + threadIdx.x;
+    if (e >= (long)n * m) return;
+    X[k * sX + (e % n) + (long)(e / n) * ldx] = make_double2(0.0, 0.0);
+}
+
+__global__ __launch_bounds__(EW_NT) void zero_int_kernel(int* __restrict__ p, int n)
+{
+    const int e = blockIdx.x * EW_NT + threadIdx.x;
+    if (e < n) p[e] = 0;
+}
+
+// Per-point refinement state: active = (getrf info == 0), prev = +inf.
+__global__ __launch_bounds__(EW_NT) void ir_init_kernel(int M, const int* __restrict__ info, int* __restrict__ active,
+                                                         double* __restrict__ prev, double* __restrict__ resid,
+                                                         int* __restrict__ iters)
+{
+    const int k = blockIdx.x * EW_NT + threadIdx.x;
+    if (k >= M) return;
+    active[k] = info[k] == 0 ? 1 : 0;
+    prev[k] = INFINITY;
+    resid[k] = 0.0;
+    iters[k] = 0;
+}
+
+// Device-side refinement decision for iteration `it` (one thread per point):
+// rn, xn: column norms of R_k and X_k (M x Lmax); un: probe column norms
+// (M x Lmax, zero for padding columns); frob: ||T_k||_F.  A point stops when
+// its backward error max_c ||r_c|| / (||T||_F ||x_c|| + ||u_c||) <= tol_be,
+// when the residual did not halve, or at it == maxit.  Writes the scaling
+// of the next correction (inv = 1/||r_c||, scl = ||r_c||).
+__global__ __launch_bounds__(EW_NT) void ir_decide_kernel(int M, int Lmax, const double* __restrict__ rn,
+                                                           const double* __restrict__ xn,
+                                                           const double* __restrict__ un,
+                                                           const double* __restrict__ frob, double tol_be, int it,
+                                                           int maxit, int* __restrict__ active,
+                                                           double* __restrict__ prev, double* __restrict__ resid,
+                                                           int* __restrict__ iters, double* __restrict__ inv,
+                                                           double* __restrict__ scl)
+{
+    const int k = blockIdx.x * EW_NT + threadIdx.x;
+    if (k >= M) return;
+    if (!active[k]) return;
+    double r = 0.0, eta = 0.0;
+    bool nan = false;
+    for (int c = 0; c < Lmax; ++c) {
+        const double u = un[(long)k * Lmax + c];
+        if (!(u > 0.0)) continue;
+        const double rr = rn[(long)k * Lmax + c];
+        if (!(rr == rr)) nan = true;
+        r = fmax(r, rr / u);
+        eta = fmax(eta, rr / (frob[k] * xn[(long)k * Lmax + c] + u));
+    }
+    resid[k] = nan ? INFINITY : r;
+    iters[k] = it;
+    const bool stop = nan || eta <= tol_be || r > 0.5 * prev[k] || it >= maxit;
+    prev[k] = r;
+    if (stop) { active[k] = 0; return; }
+    for (int c = 0; c < Lmax; ++c) {
+        const double rr = rn[(long)k * Lmax + c];
+        inv[(long)k * Lmax + c] = rr > 0.0 ? 1.0 / rr : 0.0;
+        scl[(long)k * Lmax + c] = rr;
+    }
+}
+
 static dim3 ew_grid(long elems, int B) { return dim3((unsigned)((elems + EW_NT - 1) / EW_NT), B); }
+
+hipError_t pad_identity(hipStream_t st, float2* T64, double2* T128, int ld, long sT, int P, const int* nk, int M)
+{
+    if (T64) hipLaunchKernelGGL(pad_identity_kernel<float2>, ew_grid((long)P * P, M), dim3(EW_NT), 0, st, T64, ld, sT,
+                                P, nk);
+    if (T128) hipLaunchKernelGGL(pad_identity_kernel<double2>, ew_grid((long)P * P, M), dim3(EW_NT), 0, st, T128, ld,
+                                 sT, P, nk);
+    return hipGetLastError();
+}
+hipError_t zero_c128(hipStream_t st, int n, int m, double2* X, int ldx, long sX, int B)
+{
+    hipLaunchKernelGGL(zero_c128_kernel, ew_grid((long)n * m, B), dim3(EW_NT), 0, st, n, m, X, ldx, sX);
+    return hipGetLastError();
+}
+hipError_t zero_int(hipStream_t st, int* p, int n)
+{
+    hipLaunchKernelGGL(zero_int_kernel, dim3((n + EW_NT - 1) / EW_NT), dim3(EW_NT), 0, st, p, n);
+    return hipGetLastError();
+}
+hipError_t ir_init(hipStream_t st, int M, const int* info, int* active, double* prev, double* resid, int* iters)
+{
+    hipLaunchKernelGGL(ir_init_kernel, dim3((M + EW_NT - 1) / EW_NT), dim3(EW_NT), 0, st, M, info, active, prev,
+                       resid, iters);
+    return hipGetLastError();
+}
+hipError_t ir_decide(hipStream_t st, int M, int Lmax, const double* rn, const double* xn, const double* un,
+                     const double* frob, double tol_be, int it, int maxit, int* active, double* prev, double* resid,
+                     int* iters, double* inv, double* scl)
+{
+    hipLaunchKernelGGL(ir_decide_kernel, dim3((M + EW_NT - 1) / EW_NT), dim3(EW_NT), 0, st, M, Lmax, rn, xn, un, frob,
+                       tol_be, it, maxit, active, prev, resid, iters, inv, scl);
+    return hipGetLastError();
+}
 
 hipError_t bcast_to_c64(hipStream_t st, int n, int L, const double2* U, int ldu, float2* D, int ldd, long sD, int B)
 {

@@ -90,6 +90,13 @@ hipError_t axpy_widen(hipStream_t st, int n, int L, const float2* D, int ldd, lo
 hipError_t copy_c128(hipStream_t st, int n, int m, const double2* X, int ldx, long sX, double2* Y, int ldy, long sY,
                      int B);
 hipError_t scale_cols(hipStream_t st, int n, int m, double2* X, int ldx, const double* s);
+hipError_t pad_identity(hipStream_t st, float2* T64, double2* T128, int ld, long sT, int P, const int* nk, int M);
+hipError_t zero_c128(hipStream_t st, int n, int m, double2* X, int ldx, long sX, int B);
+hipError_t zero_int(hipStream_t st, int* p, int n);
+hipError_t ir_init(hipStream_t st, int M, const int* info, int* active, double* prev, double* resid, int* iters);
+hipError_t ir_decide(hipStream_t st, int M, int Lmax, const double* rn, const double* xn, const double* un,
+                     const double* frob, double tol_be, int it, int maxit, int* active, double* prev, double* resid,
+                     int* iters, double* inv, double* scl);
 
 // ---- block one-sided Jacobi SVD (basis.hip) ----
 int jacobi_blocks(int p);  // number of column blocks (even) for p columns

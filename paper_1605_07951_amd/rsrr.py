@@ -35,8 +35,10 @@ RSRR_PREC_C64_IR = 1
 STATUS_NAMES = {0: "OK", 1: "ESINGULAR", 2: "WARN_FALLBACK", 3: "WARN_GAP", 4: "ENOMEM", 5: "EDEVICE",
                 6: "ENOTCONV", 7: "ENAN"}
 
-EXPORTS = ["rsrr_create", "rsrr_destroy", "rsrr_contour", "rsrr_sample", "rsrr_basis", "rsrr_project",
-           "rsrr_solve", "rsrr_last_timings", "rsrr_update_stats", "rsrr_version"]
+EXPORTS = ["rsrr_create", "rsrr_destroy", "rsrr_contour", "rsrr_sample", "rsrr_sample_batched", "rsrr_basis",
+           "rsrr_project", "rsrr_solve", "rsrr_last_timings", "rsrr_update_stats", "rsrr_version"]
+RSRR_BATCH_GRAPH = 1
+RSRR_BATCH_AUTOTUNE = 2
 
 
 class RsrrTerm(C.Structure):
@@ -48,6 +50,11 @@ class RsrrTerm(C.Structure):
 class RsrrNep(C.Structure):
     _fields_ = [("kind", C.c_int), ("n", C.c_int), ("J", C.c_int), ("A", C.c_void_p), ("lda", C.c_int),
                 ("terms", C.POINTER(RsrrTerm)), ("points", C.c_void_p), ("w", C.c_double)]
+
+
+class RsrrInstance(C.Structure):
+    _fields_ = [("nep", RsrrNep), ("N", C.c_int), ("z", C.POINTER(C.c_double)), ("U", C.c_void_p), ("L", C.c_int),
+                ("ldu", C.c_int), ("S", C.c_void_p), ("lds", C.c_int)]
 
 
 class RsrrPointInfo(C.Structure):
@@ -87,6 +94,8 @@ def lib():
     L.rsrr_contour.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, dp, dp]
     L.rsrr_sample.argtypes = [vp, C.POINTER(RsrrNep), C.c_int, dp, vp, C.c_int, C.c_int, C.c_int, vp, C.c_int,
                               C.POINTER(RsrrPointInfo)]
+    L.rsrr_sample_batched.argtypes = [vp, C.c_int, C.POINTER(RsrrInstance), C.c_int, C.c_int,
+                                      C.POINTER(RsrrPointInfo)]
     L.rsrr_basis.argtypes = [vp, C.c_int, C.c_int, vp, C.c_int, C.c_double, vp, C.c_int, C.c_int, ip, dp]
     L.rsrr_project.argtypes = [vp, C.POINTER(RsrrNep), vp, C.c_int, C.c_int, dp, C.c_double, vp, C.c_int, ip,
                                C.POINTER(RsrrTerm)]
@@ -254,6 +263,43 @@ def rsrr_sample(ctx, dnep, z, U, prec=RSRR_PREC_C64_IR, S=None, ok=(RSRR_OK, RSR
     _check("rsrr_sample", code, ok)
     infos = [{"info": i.info, "ir_iters": i.ir_iters, "fallback": i.fallback, "resid": i.resid} for i in info]
     return S, infos, code
+
+
+class BatchItem:
+    """One instance of a ragged batch: a DeviceNEP, its points (host), probes and output (device)."""
+
+    def __init__(self, dnep, z, U, S=None):
+        torch = _torch()
+        self.dnep = dnep
+        self.z = np.ascontiguousarray(np.asarray(z, dtype=np.complex128))
+        if not torch.is_tensor(U):
+            U, _ = colmajor(U)
+        self.U = U
+        L = U.shape[0]
+        if S is None:
+            S = torch.empty((self.z.size * L, dnep.n), dtype=torch.complex128, device=U.device)
+        self.S = S
+
+
+def rsrr_sample_batched(ctx, items, prec=RSRR_PREC_C64_IR, flags=0, ok=(RSRR_OK, RSRR_WARN_FALLBACK)):
+    """Ragged batch of sampling problems.  Returns (per-item info lists, status)."""
+    arr = (RsrrInstance * len(items))()
+    keep = []
+    for i, it in enumerate(items):
+        zp = it.z.view(np.float64).ctypes.data_as(C.POINTER(C.c_double))
+        keep.append(it.z)
+        arr[i] = RsrrInstance(it.dnep.desc, it.z.size, zp, it.U.data_ptr(), it.U.shape[0], it.U.shape[1],
+                              it.S.data_ptr(), it.S.shape[1])
+    total = sum(it.z.size for it in items)
+    info = (RsrrPointInfo * total)()
+    code = lib().rsrr_sample_batched(ctx.h, len(items), arr, int(prec), int(flags), info)
+    _check("rsrr_sample_batched", code, ok)
+    out, p = [], 0
+    for it in items:
+        out.append([{"info": info[p + k].info, "ir_iters": info[p + k].ir_iters, "fallback": info[p + k].fallback,
+                     "resid": info[p + k].resid} for k in range(it.z.size)])
+        p += it.z.size
+    return out, code
 
 
 def rsrr_basis(ctx, S, n, delta=1e-14, kmax=None):
