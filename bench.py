@@ -7,9 +7,10 @@ sampling points, L = 64 complex Gaussian probes; complex-FP32 LU on the
 matrix cores with FP64 iterative refinement.  Inputs are synthetic and
 seeded and live in HBM before the timed region starts.
 
-One step = rsrr_sample over all N points (assembly, LU, solves, refinement)
-followed by rsrr_basis (normalisation + truncated SVD) and rsrr_project when
-those are available.  value = N * steps / elapsed (resolvent solves/s).
+One step = rsrr_sample over all N points (assembly, LU, solves, refinement):
+value = N * steps / elapsed (resolvent solves/s).  Unless --sample-only, the
+rest of the method (rsrr_basis, rsrr_project, rsrr_solve) then runs once on
+the sampled S and its times and eigenvalue diagnostics are reported.
 
 Prints one JSON line (see the repository's benchmark contract), with a
 "roofline" object for the LU trailing-update kernel (HIP events around every
@@ -48,7 +49,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-points", type=int, default=None, help="sampling points in the CPU sample")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison run")
-    ap.add_argument("--sample-only", action="store_true", help="time rsrr_sample only")
+    ap.add_argument("--sample-only", action="store_true", help="skip the basis/projection/SS-FULL pass")
+    ap.add_argument("--nq", type=int, default=500, help="SS-FULL quadrature nodes")
     return ap.parse_args()
 
 
@@ -108,25 +110,13 @@ def main():
     z, _ = R.rsrr_contour(C.gamma, C.a, C.b, N)
     prec = R.RSRR_PREC_C64_IR if args.prec == "mixed" else R.RSRR_PREC_C128
     S = torch.empty((N * L, n), dtype=torch.complex128, device=dev)
-    have_basis = not args.sample_only
     kmax = min(n, N * L)
     radius = max(C.a, C.b)
 
     def step():
         _, info, _ = R.rsrr_sample(ctx, dnep, z, U, prec=prec, S=S)
-        out = {"info": info}
-        if have_basis:
-            Q, k, sig = R.rsrr_basis(ctx, S, n, 1e-14, kmax=kmax)
-            out["k"] = k
-            R.rsrr_project(ctx, dnep, Q, k, C.gamma, radius)
-        return out
+        return {"info": info}
 
-    # probe whether basis/project are implemented
-    if have_basis:
-        try:
-            step()
-        except R.RsrrError:
-            have_basis = False
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -164,7 +154,7 @@ def main():
         "dtype": "c64 LU (f32 MFMA) + f64 refinement" if prec == R.RSRR_PREC_C64_IR else "c128 (f64 MFMA)",
         "data": "synthetic (seeded Fibonacci-sphere Helmholtz single-layer NEP, complex Gaussian probes)",
         "config": {"workload": desc, "n": n, "N": N, "L": L, "precision": args.prec,
-                   "step": "rsrr_sample" + (" + rsrr_basis + rsrr_project" if have_basis else "")},
+                   "step": "rsrr_sample over all N points (assembly, LU, solves, refinement)"},
         "roofline": {"bound": "mfma", "kernel": "LU trailing update (cgemm_mfma_kernel<*,1>)"
                      if prec == R.RSRR_PREC_C64_IR else "LU trailing update (zgemm_mfma_kernel<0,0,1>)",
                      "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
@@ -177,8 +167,27 @@ def main():
         "resid_max": max(i["resid"] for i in info),
         "fallbacks": sum(i["fallback"] for i in info),
     }
-    if have_basis and last and "k" in last:
-        res["basis_k"] = last["k"]
+    if not args.sample_only:
+        # the rest of the method on the sampled S: basis, projection, SS-FULL (timed once, reported)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        Q, k, sig = R.rsrr_basis(ctx, S, n, 1e-14, kmax=kmax)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        AQ, terms = R.rsrr_project(ctx, dnep, Q, k, C.gamma, radius)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        sol = R.rsrr_solve(ctx, dnep, Q, k, AQ, terms, C.gamma, C.a, C.b, NQ=args.nq, KQ=2)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        d = sol["lam"] - complex(C.gamma)
+        lv = (d.real / C.a) ** 2 + (d.imag / C.b) ** 2   # elliptic level: < 1 inside the contour
+        ins = lv < 1
+        res["rest_of_method"] = {"basis_ms": round(1e3 * (t2 - t1), 1), "project_ms": round(1e3 * (t3 - t2), 1),
+                                 "solve_ms": round(1e3 * (t4 - t3), 1), "k": k, "terms": len(terms),
+                                 "nbar": sol["nbar"], "gmax": sol["gmax"], "eigs_inside": int(ins.sum()),
+                                 "eig_resid_max_inside": float(sol["resid"][ins].max()) if ins.any() else None,
+                                 "lambda_inside": [[float(l.real), float(l.imag)] for l in sol["lam"][ins]]}
 
     if not args.no_plain and prec == R.RSRR_PREC_C64_IR:
         # plain FP64 path on the same inputs for the mixed/plain speedup

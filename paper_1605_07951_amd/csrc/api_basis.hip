@@ -91,32 +91,95 @@ extern "C" rsrr_status rsrr_basis(rsrr_ctx* c, int n, int NL, double* S, int lds
     RSRR_HIP(scale_cols(c->stream, n, NL, A, lds, inv));
     RSRR_HIP(hipStreamSynchronize(c->stream));
 
-    // one-sided Jacobi: S V = U Sigma
-    const double tol = 4.0 * std::max(1.0, std::sqrt((double)n)) * 2.220446049250313e-16;
-    rsrr_status st = RSRR_OK;
-    if (jacobi_svd(c, A, lds, n, n, NL, 80, tol, &st) < 0) return st;
-
-    // singular values = column norms, sorted descending
-    RSRR_HIP(colnorms(c->stream, n, NL, A, lds, 0, nrm, 1));
-    RSRR_HIP(hipMemcpyAsync(h.data(), nrm, (size_t)NL * 8, hipMemcpyDeviceToHost, c->stream));
-    RSRR_HIP(hipStreamSynchronize(c->stream));
-    std::vector<int> o(NL);
-    std::iota(o.begin(), o.end(), 0);
-    std::stable_sort(o.begin(), o.end(), [&](int a, int b) { return h[a] > h[b]; });
+    // Range sketch + BCGS2 + one-sided Jacobi on the small factor.
+    //   Y = S Omega (Omega: NL x l seeded Gaussian), Q_Y = BCGS2(Y) with the r
+    //   numerically independent columns kept, X = [S^H Q_Y; I_r]: Jacobi
+    //   rotations J on the columns make the top part V Sigma (right singular
+    //   vectors of B = Q_Y^H S) and the bottom part J = W, the left singular
+    //   vectors of B; S's left singular vectors are Q_Y W.
+    // When l = min(n, NL) the sketch spans range(S) and this is the SVD of S.  A
+    // smaller l is accepted when the sketch came out rank deficient (r < l) or its
+    // smallest singular value is at the rounding floor (<= 1e-15 sigma_1);
+    // otherwise l doubles.
     const int m = std::min(n, NL);
-    const double s1 = h[o[0]];
+    int l = std::min(m, 1024);
+    const double tol = 4.0 * std::max(1.0, std::sqrt((double)NL)) * 2.220446049250313e-16;
+    rsrr_status st = RSRR_OK;
+    std::vector<int> o, idx;
+    std::vector<double> sv, hq;
+    double2* Yu = nullptr;
+    double2* X = nullptr;
+    int r = 0;
+    for (;;) {
+        double2* Y = (double2*)ws_get(c, WS_TLU, (size_t)n * l * 16);
+        double2* Om = (double2*)ws_get(c, WS_TRES, (size_t)std::max((long)NL * l, (long)n * l) * 16);
+        double2* Wb = (double2*)ws_get(c, WS_D64, (size_t)l * 32 * 16);
+        double* n0 = (double*)ws_get(c, WS_B7, (size_t)l * 8);
+        if (!Y || !Om || !Wb || !n0) return RSRR_ENOMEM;
+        if (l >= NL) {
+            // no sketch needed: orthonormalise S itself (l == NL)
+            RSRR_HIP(copy_c128(c->stream, n, NL, A, lds, 0, Y, n, 0, 1));
+        } else {
+            RSRR_HIP(gaussian(c->stream, Om, NL, l, NL, 0x5eed5eedull + (unsigned long long)l));
+            RSRR_HIP(zgemm(c->stream, 0, 0, n, l, NL, 1.0, A, lds, 0, Om, NL, 0, 0.0, Y, n, 0, 1));
+        }
+        RSRR_HIP(bcgs2(c->stream, Y, n, n, l, Wb, n0));
+        // keep the nonzero (independent) columns of Q_Y
+        RSRR_HIP(colnorms(c->stream, n, l, Y, n, 0, n0, 1));
+        hq.assign(l, 0.0);
+        RSRR_HIP(hipMemcpyAsync(hq.data(), n0, (size_t)l * 8, hipMemcpyDeviceToHost, c->stream));
+        RSRR_HIP(hipStreamSynchronize(c->stream));
+        idx.clear();
+        for (int i = 0; i < l; ++i)
+            if (hq[i] > 0.5) idx.push_back(i);
+        r = (int)idx.size();
+        if (r == 0) break;
+        Yu = Y;
+        if (r < l) {
+            // Omega is dead: its buffer takes the compacted Q_Y
+            std::vector<double> ones(r, 1.0);
+            RSRR_HIP(hipMemcpyAsync(ord, idx.data(), (size_t)r * 4, hipMemcpyHostToDevice, c->stream));
+            RSRR_HIP(hipMemcpyAsync(inv, ones.data(), (size_t)r * 8, hipMemcpyHostToDevice, c->stream));
+            RSRR_HIP(gather_scale(c->stream, Y, n, n, ord, inv, Om, n, r));
+            RSRR_HIP(hipStreamSynchronize(c->stream));
+            Yu = Om;
+        }
+        X = (double2*)ws_get(c, WS_R, (size_t)(NL + r) * r * 16);
+        if (!X) return RSRR_ENOMEM;
+        RSRR_HIP(zgemm(c->stream, 1, 0, NL, r, n, 1.0, A, lds, 0, Yu, n, 0, 0.0, X, NL + r, 0, 1));
+        RSRR_HIP(eye(c->stream, X, NL + r, NL, r));
+        if (jacobi_svd(c, X, NL + r, NL, NL + r, r, 80, tol, &st) < 0) return st;
+        double* cn = (double*)ws_get(c, WS_B5, (size_t)r * 8);
+        if (!cn) return RSRR_ENOMEM;
+        RSRR_HIP(colnorms(c->stream, NL, r, X, NL + r, 0, cn, 1));
+        sv.assign(r, 0.0);
+        RSRR_HIP(hipMemcpyAsync(sv.data(), cn, (size_t)r * 8, hipMemcpyDeviceToHost, c->stream));
+        RSRR_HIP(hipStreamSynchronize(c->stream));
+        o.resize(r);
+        std::iota(o.begin(), o.end(), 0);
+        std::stable_sort(o.begin(), o.end(), [&](int x, int y) { return sv[x] > sv[y]; });
+        const double s1 = sv[o[0]], sl = sv[o[r - 1]];
+        if (l >= m || r < l || !(s1 > 0.0) || sl <= 1e-15 * s1) break;
+        l = std::min(m, 2 * l);
+    }
+    const double s1 = r > 0 ? sv[o[0]] : 0.0;
     int kk = 0;
-    for (int i = 0; i < m; ++i)
-        if (s1 > 0.0 && h[o[i]] > delta * s1) ++kk;
+    for (int i = 0; i < r; ++i)
+        if (s1 > 0.0 && sv[o[i]] > delta * s1) ++kk;
     if (sigma)
-        for (int i = 0; i < m; ++i) sigma[i] = h[o[i]];
+        for (int i = 0; i < m; ++i) sigma[i] = i < r ? sv[o[i]] : 0.0;
     *k = kk;
     const int kw = std::min(kk, kmax);
-    std::vector<double> iv(kw);
-    for (int i = 0; i < kw; ++i) iv[i] = 1.0 / h[o[i]];
-    RSRR_HIP(hipMemcpyAsync(ord, o.data(), (size_t)kw * 4, hipMemcpyHostToDevice, c->stream));
-    RSRR_HIP(hipMemcpyAsync(inv, iv.data(), (size_t)kw * 8, hipMemcpyHostToDevice, c->stream));
-    RSRR_HIP(gather_scale(c->stream, A, lds, n, ord, inv, (double2*)Q, ldq, kw));
+    if (kw > 0) {
+        // W sorted by singular value (bottom r rows of X), then Q = Q_Y W
+        std::vector<double> ones(kw, 1.0);
+        double2* Ws = (double2*)ws_get(c, WS_B2, (size_t)r * kw * 16);
+        if (!Ws) return RSRR_ENOMEM;
+        RSRR_HIP(hipMemcpyAsync(ord, o.data(), (size_t)kw * 4, hipMemcpyHostToDevice, c->stream));
+        RSRR_HIP(hipMemcpyAsync(inv, ones.data(), (size_t)kw * 8, hipMemcpyHostToDevice, c->stream));
+        RSRR_HIP(gather_scale(c->stream, X + NL, NL + r, r, ord, inv, Ws, r, kw));
+        RSRR_HIP(zgemm(c->stream, 0, 0, n, kw, r, 1.0, Yu, n, 0, Ws, r, 0, 0.0, (double2*)Q, ldq, 0, 1));
+    }
     RSRR_HIP(hipStreamSynchronize(c->stream));
     return RSRR_OK;
 }

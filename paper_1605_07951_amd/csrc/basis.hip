@@ -203,6 +203,134 @@ __global__ __launch_bounds__(256) void gather_scale_kernel(const double2* __rest
     Q[i + (long)c * ldq] = make_double2(a.x * s, a.y * s);
 }
 
+// ----------------------------------------------------------------------------
+// Seeded complex Gaussian matrix (n x m, ld n): entry e uses the counter-based
+// generator splitmix64(seed, e) -> two uniforms -> Box-Muller.  Deterministic.
+// ----------------------------------------------------------------------------
+RSRR_DEV unsigned long long splitmix64(unsigned long long x)
+{
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+__global__ __launch_bounds__(256) void gaussian_kernel(double2* __restrict__ X, int n, int m, int ld,
+                                                        unsigned long long seed)
+{
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (long)n * m) return;
+    const int i = (int)(e % n), j = (int)(e / n);
+    const unsigned long long h1 = splitmix64(seed ^ splitmix64((unsigned long long)e * 2ull));
+    const unsigned long long h2 = splitmix64(seed ^ splitmix64((unsigned long long)e * 2ull + 1ull));
+    const double u1 = ((h1 >> 11) + 1.0) * (1.0 / 9007199254740993.0);  // (0, 1]
+    const double u2 = (h2 >> 11) * (1.0 / 9007199254740992.0);         // [0, 1)
+    const double r = sqrt(-2.0 * log(u1)) * 0.70710678118654752;
+    double sn, cs;
+    sincos(6.283185307179586 * u2, &sn, &cs);
+    X[i + (long)j * ld] = make_double2(r * cs, r * sn);
+}
+
+// ----------------------------------------------------------------------------
+// Classical Gram-Schmidt with reorthogonalisation inside one block of bw <= 32
+// columns (column c against columns 0..c-1 of the block, twice, then
+// normalised).  One workgroup; the block stays in global memory (L2).
+// A column whose remaining norm is at most thr * ref[c] (ref = nullptr: 1) is
+// numerically dependent on the columns before it and is set to zero: what
+// remains of it is rounding noise, and normalising noise would break the
+// orthogonality of everything after it.
+// ----------------------------------------------------------------------------
+constexpr int CG_BW = 32;
+
+__global__ __launch_bounds__(256) void block_cgs2_kernel(double2* __restrict__ Y, int ld, int n, int bw,
+                                                          const double* __restrict__ ref, double thr)
+{
+    __shared__ double2 red[4][CG_BW];
+    __shared__ double2 coef[CG_BW];
+    __shared__ double nred[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int c = 0; c < bw; ++c) {
+        double2* y = Y + (long)c * ld;
+        for (int pass = 0; pass < 2 && c > 0; ++pass) {
+            double2 acc[CG_BW];
+#pragma unroll
+            for (int j = 0; j < CG_BW; ++j) acc[j] = make_double2(0.0, 0.0);
+            for (int r = tid; r < n; r += 256) {
+                const double2 v = y[r];
+#pragma unroll
+                for (int j = 0; j < CG_BW; ++j)
+                    if (j < c) acc[j] = cfma_cj(acc[j], Y[r + (long)j * ld], v);
+            }
+#pragma unroll
+            for (int j = 0; j < CG_BW; ++j) {
+                if (j >= c) break;
+                double2 a = acc[j];
+                for (int o = 32; o >= 1; o >>= 1) { a.x += __shfl_xor(a.x, o); a.y += __shfl_xor(a.y, o); }
+                if (lane == 0) red[wave][j] = a;
+            }
+            __syncthreads();
+            if (tid < c) coef[tid] = cadd(cadd(red[0][tid], red[1][tid]), cadd(red[2][tid], red[3][tid]));
+            __syncthreads();
+            for (int r = tid; r < n; r += 256) {
+                double2 v = y[r];
+                for (int j = 0; j < c; ++j) v = cfms(v, Y[r + (long)j * ld], coef[j]);
+                y[r] = v;
+            }
+            __syncthreads();
+        }
+        double s2 = 0.0;
+        for (int r = tid; r < n; r += 256) { const double2 v = y[r]; s2 += v.x * v.x + v.y * v.y; }
+        for (int o = 32; o >= 1; o >>= 1) s2 += __shfl_xor(s2, o);
+        if (lane == 0) nred[wave] = s2;
+        __syncthreads();
+        const double nn = sqrt(nred[0] + nred[1] + nred[2] + nred[3]);
+        const double inv = nn > thr * (ref ? ref[c] : 1.0) ? 1.0 / nn : 0.0;
+        for (int r = tid; r < n; r += 256) { const double2 v = y[r]; y[r] = make_double2(v.x * inv, v.y * inv); }
+        __syncthreads();
+    }
+}
+
+hipError_t gaussian(hipStream_t st, double2* X, int n, int m, int ld, unsigned long long seed)
+{
+    const long e = (long)n * m;
+    hipLaunchKernelGGL(gaussian_kernel, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, st, X, n, m, ld, seed);
+    return hipGetLastError();
+}
+
+// Block classical Gram-Schmidt with reorthogonalisation (BCGS2) of Y (n x m,
+// ld): each block of 32 columns is projected against the finished blocks (FP64
+// MFMA GEMMs) and orthonormalised inside the block, twice.  Columns found
+// dependent (remaining norm <= 4 eps sqrt(n) times their original norm) come
+// out as zero columns, so Q^H Q is the identity on the nonzero columns.
+// W: scratch of m*32 complex; n0: scratch of m doubles.
+hipError_t bcgs2(hipStream_t st, double2* Y, int ld, int n, int m, double2* W, double* n0)
+{
+    const double thr = 4.0 * 2.220446049250313e-16 * sqrt((double)n);
+    hipError_t e = colnorms(st, n, m, Y, ld, 0, n0, 1);
+    if (e != hipSuccess) return e;
+    for (int j0 = 0; j0 < m; j0 += CG_BW) {
+        const int bw = (m - j0 < CG_BW) ? m - j0 : CG_BW;
+        double2* Yj = Y + (long)j0 * ld;
+        // two full passes (project on the finished blocks, then orthonormalise inside the
+        // block): the second pass sees a block that is already well conditioned, which is
+        // what makes the reorthogonalisation effective when S is nearly rank deficient
+        for (int pass = 0; pass < 2; ++pass) {
+            if (j0 > 0) {
+                e = zgemm(st, 1, 0, j0, bw, n, 1.0, Y, ld, 0, Yj, ld, 0, 0.0, W, j0, 0, 1);
+                if (e != hipSuccess) return e;
+                e = zgemm(st, 0, 0, n, bw, j0, -1.0, Y, ld, 0, W, j0, 0, 1.0, Yj, ld, 0, 1);
+                if (e != hipSuccess) return e;
+            }
+            hipLaunchKernelGGL(block_cgs2_kernel, dim3(1), dim3(256), 0, st, Yj, ld, n, bw,
+                               pass == 0 ? n0 + j0 : (const double*)nullptr, thr);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            if (j0 == 0) break;
+        }
+    }
+    return hipSuccess;
+}
+
 int jacobi_blocks(int p) { int nb = (p + JB_B - 1) / JB_B; return nb + (nb & 1); }
 
 hipError_t jacobi_round(hipStream_t st, double2* A, int lda, int m, int m_apply, int p, int round, int inner,

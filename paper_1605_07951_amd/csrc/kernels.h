@@ -104,6 +104,8 @@ hipError_t jacobi_round(hipStream_t st, double2* A, int lda, int m, int m_apply,
                         double tol, double zthr2, double* offmax);
 hipError_t gather_scale(hipStream_t st, const double2* A, int lda, int m, const int* order, const double* inv,
                         double2* Q, int ldq, int k);
+hipError_t gaussian(hipStream_t st, double2* X, int n, int m, int ld, unsigned long long seed);
+hipError_t bcgs2(hipStream_t st, double2* Y, int ld, int n, int m, double2* W, double* n0);
 
 // ---- SS-FULL helpers (ssfull.hip) ----
 hipError_t hankel(hipStream_t st, const double2* mom, int k, int K, int shift, double2* H, int ldh);
