@@ -12,6 +12,9 @@
  *   rsrr_project  Step 4, first half / eq. Ts-NEP: T_Q(z) = Q^H T(z) Q
  *   rsrr_solve    Step 4, second half, and Step 5: SS-FULL (Sec. 3.3) on the
  *                 projected NEP, lift v = Q g, residuals
+ *   rsrr_sample_batched   Step 2 for a ragged batch of NEP instances
+ *   rsrr_server_* a request loop that runs all of the above for many NEPs at
+ *                 once (continuous batching of their sampling points)
  *
  * plus rsrr_contour for the ellipse nodes and trapezoid weights of Sec. 5.1
  * (eq. ellip-contour, eq. ellip-contour-xw).
@@ -31,6 +34,8 @@
  *   (1-based) as invalid, and nothing was enqueued; a positive value is a
  *   numerical or runtime condition listed below.
  * - One context per host thread.  Calls on one context must not overlap.
+ * - Exception: a server (rsrr_server_*) keeps the caller's request buffers
+ *   until the request has finished (rsrr_server_wait returned it).
  */
 #ifndef RSRR_H
 #define RSRR_H
@@ -55,7 +60,8 @@ enum {
     RSRR_ENOMEM = 4,         /* device allocation of workspace failed                         */
     RSRR_EDEVICE = 5,        /* a HIP runtime call failed                                      */
     RSRR_ENOTCONV = 6,       /* an iterative eigen/singular-value solve did not converge        */
-    RSRR_ENAN = 7            /* a NaN or Inf reached a pivot                                   */
+    RSRR_ENAN = 7,           /* a NaN or Inf reached a pivot                                   */
+    RSRR_ETIMEOUT = 8        /* rsrr_server_wait: the request had not finished in time          */
 };
 
 /* Kinds of T(z).  SEPARABLE: T(z) = sum_j f_j(z) A_j (the form of every
@@ -235,6 +241,106 @@ enum {
  * -4 prec. */
 RSRR_API rsrr_status rsrr_sample_batched(rsrr_ctx *ctx, int count, const rsrr_instance *inst, int prec, int flags,
                                          rsrr_point_info *info);
+
+/* ---------------------------------------------------------------------------
+ * Serving: a request loop for many NEP solves on one device.
+ *
+ * Each request is the whole method of Sec. 4.3 for one NEP: contour nodes
+ * (eq. ellip-contour-xw), resolvent sampling (Step 2), basis (Step 3),
+ * projection and SS-FULL (Steps 4-5).  A request is admitted when a slot is
+ * free and its S block (16 n N L bytes) fits in the server's HBM arena
+ * (first come, first served).  The sampling points of every admitted request
+ * are batched together: each sampling launch takes points from all admitted
+ * requests in admission order, up to batch_bytes of LU workspace, grouped by
+ * (n rounded up to 64, L), so points that arrive while others are on the GPU
+ * join the next launch.  A second host thread with its own stream runs basis,
+ * projection and SS-FULL of requests whose sampling has finished, overlapping
+ * the next sampling launches on the device.  The factors of a launch stay in
+ * HBM from factorisation through refinement and the FP64 fallback.
+ * Per-point work (tile shapes, panel width, refinement) depends only on
+ * (n, L, precision), never on what else is in the launch, so a request's
+ * results do not depend on the mix it ran in.
+ * ------------------------------------------------------------------------- */
+typedef struct rsrr_server rsrr_server;
+
+typedef struct {
+    int device;
+    int prec;                 /* RSRR_PREC_C128 or RSRR_PREC_C64_IR                        */
+    int max_slots;            /* requests admitted at the same time (>= 1)                 */
+    int flags;                /* RSRR_SERVE_*                                               */
+    unsigned long long arena_bytes;  /* HBM for the admitted requests' S blocks            */
+    unsigned long long batch_bytes;  /* HBM cap of one sampling launch's LU workspace      */
+} rsrr_server_config;
+
+enum {
+    RSRR_SERVE_NO_BATCH = 1,  /* one request's points per sampling launch (no mixing)      */
+    RSRR_SERVE_SERIAL = 2     /* no second thread: basis/projection/solve run between the
+                                 sampling launches, on the sampling stream                */
+};
+
+/* One request.  nep device data, U (device, n x L, ldu >= n) and the host
+ * output arrays stay owned by the caller and must stay valid until
+ * rsrr_server_wait has returned this request.  Outputs: lambda (host,
+ * 2*max_eigs doubles), resid (host, max_eigs; ||T(lambda)v|| / (||T(lambda)||_1
+ * ||v||)), V (host, n x max_eigs column-major with ld n, unit 2-norm columns;
+ * may be NULL). */
+typedef struct {
+    rsrr_nep nep;
+    double gamma_re, gamma_im;   /* ellipse centre */
+    double a, b;                 /* ellipse semi-axes (real, imaginary) */
+    int N;                       /* sampling points */
+    int L;                       /* probe columns */
+    const double *U;
+    int ldu;
+    int NQ;                      /* SS-FULL quadrature nodes (0: 500)  */
+    int KQ;                      /* SS-FULL moment blocks (0: 2)       */
+    double delta;                /* rank truncation (0: 1e-14)         */
+    int max_eigs;
+    double *lambda;
+    double *resid;
+    double *V;
+} rsrr_request;
+
+/* Result of one request; times are seconds on the server's steady clock
+ * (0 = server creation). */
+typedef struct {
+    int id;
+    rsrr_status status;          /* RSRR_OK or the first failing step's status           */
+    int count;                   /* eigenpairs written (eigenvalues inside or near C)    */
+    int k;                       /* rank of S kept by the basis                          */
+    int nbar;                    /* SS-FULL eigenvalue count                             */
+    int fallbacks;               /* sampling points redone on the FP64 path              */
+    int ir_iters_max;
+    int launches;                /* sampling launches that carried this request's points */
+    double sample_resid_max;     /* max relative residual of the refined solves          */
+    double t_submit, t_admit, t_sampled, t_done;
+} rsrr_result;
+
+/* Create a server (two host threads, two non-blocking streams on cfg->device)
+ * and allocate its arena.  Errors: -1 srv NULL, -2 cfg invalid,
+ * RSRR_ENOMEM, RSRR_EDEVICE. */
+RSRR_API rsrr_status rsrr_server_create(rsrr_server **srv, const rsrr_server_config *cfg);
+
+/* Queue a request (thread safe, does not block on the GPU).  *id receives its
+ * id.  Errors: -1 srv, -2 request invalid, -3 id NULL; RSRR_ENOMEM when its S
+ * block alone exceeds the arena. */
+RSRR_API rsrr_status rsrr_server_submit(rsrr_server *srv, const rsrr_request *req, int *id);
+
+/* Wait until request id has finished (timeout_s < 0: no limit) and fill out.
+ * Each id can be waited for once.  Errors: -1 srv, -2 unknown id, -4 out NULL;
+ * RSRR_ETIMEOUT. */
+RSRR_API rsrr_status rsrr_server_wait(rsrr_server *srv, int id, double timeout_s, rsrr_result *out);
+
+/* Server counters (host, 10 doubles): requests finished, points sampled,
+ * sampling launches, arena bytes in use at peak, largest launch (points),
+ * seconds the sampling thread was busy, seconds the solve thread was busy,
+ * peak device memory in use (bytes, from hipMemGetInfo), current server
+ * time, requests waiting for admission.  Errors: -1 srv, -2 out NULL. */
+RSRR_API rsrr_status rsrr_server_stats(rsrr_server *srv, double *out);
+
+/* Finish every submitted request, stop the threads and free the server.
+ * Errors: -1 srv NULL. */
+RSRR_API rsrr_status rsrr_server_destroy(rsrr_server *srv);
 
 /* Device-event statistics of the LU trailing-update kernel (A22 -= L21 U12,
  * the matrix-core hot loop of rsrr_sample).  enable = 1 starts recording a

@@ -22,6 +22,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "ctx.h"
@@ -55,8 +56,17 @@ std::map<rsrr_ctx*, std::unique_ptr<BatchedState>>& states()
     return m;
 }
 
+// contexts of different host threads (a server's sampling thread and the
+// caller's) look up their state concurrently
+std::mutex& states_mu()
+{
+    static std::mutex mu;
+    return mu;
+}
+
 BatchedState& state_of(rsrr_ctx* c)
 {
+    std::lock_guard<std::mutex> lk(states_mu());
     auto& m = states();
     auto it = m.find(c);
     if (it == m.end()) it = m.emplace(c, std::make_unique<BatchedState>()).first;
@@ -206,6 +216,7 @@ rsrr_status run_bucket(rsrr_ctx* c, hipStream_t sm, const rsrr_instance* inst, c
 
 void batched_release(rsrr_ctx* c)
 {
+    std::lock_guard<std::mutex> lk(states_mu());
     auto& m = states();
     auto it = m.find(c);
     if (it == m.end()) return;
@@ -293,7 +304,9 @@ extern "C" rsrr_status rsrr_sample_batched(rsrr_ctx* c, int count, const rsrr_in
         const size_t esz = mixed ? 8 : 16;
         long nparts_max = ((long)maxn * maxn + 255) / 256;
         hipStream_t sm = c->stream;
-        int s = (P / BUCKET) * 32;  // every bucket size has its own buffers (graphs keep pointing at them)
+        // with graphs every bucket size has its own buffers (the graphs keep pointing at
+        // them); otherwise the buckets of a call run one after the other and share them
+        int s = use_graph ? (P / BUCKET) * 32 : 0;
         b.T = bget(S, s++, (size_t)M * b.sT * esz, sm);
         b.T128 = (double2*)bget(S, s++, (size_t)M * b.sT * 16, sm);
         b.Ub = (double2*)bget(S, s++, (size_t)M * b.sU * 16, sm);

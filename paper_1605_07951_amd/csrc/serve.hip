@@ -1,0 +1,557 @@
+// C ABI: a request loop that runs the whole RSRR method (Sec. 4.3) for many
+// NEPs on one device, with continuous batching of their sampling points.
+//
+// Two host threads, each with its own rsrr_ctx on its own non-blocking
+// stream:
+//   sampler  admits queued requests (free slot + room for S in the arena, first
+//            come first served), then repeatedly takes sampling points from all
+//            admitted requests in admission order, up to batch_bytes of LU
+//            workspace, and runs them as one rsrr_sample_batched call per
+//            probe count L (inside it, one uniform batch per size bucket).
+//            Requests that arrive meanwhile join the next launch.
+//   solver   runs basis, projection and SS-FULL of each request whose points
+//            are all sampled, copies the eigenpairs to the caller's host
+//            arrays and frees the request's arena block (which may admit the
+//            next request).  Its kernels overlap the next sampling launches.
+// The arena is one hipMalloc'd block sub-allocated first-fit, so admission
+// decides on real HBM and the loop never calls hipMalloc/hipFree per request.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "ctx.h"
+#include "kernels.h"
+
+using namespace rsrr;
+
+namespace {
+
+constexpr int DEFAULT_NQ = 500;
+constexpr int DEFAULT_KQ = 2;
+constexpr double DEFAULT_DELTA = 1e-14;
+constexpr double TOL_GAP = 1e3;
+constexpr int MAX_TERMS = 64;
+constexpr size_t ALIGN = 256;
+
+// First-fit sub-allocator over [0, size).
+struct Arena {
+    std::map<size_t, size_t> free_;  // offset -> length
+    size_t size = 0, used = 0, peak = 0;
+    void init(size_t s)
+    {
+        size = s;
+        free_.clear();
+        if (s) free_[0] = s;
+    }
+    long alloc(size_t bytes)
+    {
+        bytes = (bytes + ALIGN - 1) / ALIGN * ALIGN;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            const size_t off = it->first, len = it->second;
+            free_.erase(it);
+            if (len > bytes) free_[off + bytes] = len - bytes;
+            used += bytes;
+            peak = std::max(peak, used);
+            return (long)off;
+        }
+        return -1;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        bytes = (bytes + ALIGN - 1) / ALIGN * ALIGN;
+        used -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+enum ReqState { QUEUED, ADMITTED, SAMPLED, DONE };
+
+struct Req {
+    int id = 0;
+    rsrr_request r{};
+    std::vector<rsrr_term> terms;  // copy of the caller's term table
+    std::vector<double> z;         // contour nodes (2N)
+    size_t s_off = 0, s_bytes = 0;
+    double* S = nullptr;           // n x N*L in the arena
+    int next = 0;                  // first point not yet handed to a launch
+    int sampled = 0;               // points finished
+    int last_launch = -1;
+    ReqState state = QUEUED;
+    rsrr_result res{};
+};
+
+struct Chunk {
+    Req* q;
+    int k0, cnt;
+};
+
+double now_s(std::chrono::steady_clock::time_point t0)
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+bool is_error(rsrr_status s) { return s < 0 || s == RSRR_ENOMEM || s == RSRR_EDEVICE || s == RSRR_ENOTCONV || s == RSRR_ENAN || s == RSRR_ESINGULAR; }
+
+// LU workspace of one point in a sampling launch (the bucket buffers of
+// rsrr_sample_batched), bytes.
+size_t point_bytes(int n, int L, bool mixed)
+{
+    const size_t P = (size_t)(n + 63) / 64 * 64;
+    const size_t npan = (P + 63) / 64;
+    size_t b = P * P * (mixed ? 8 + 16 : 16 + 16);           // T and its FP64 copy
+    b += P * (size_t)L * (3 * 16 + 8) + P * 4;               // U, X, R, narrow RHS, pivots
+    b += npan * 2 * MAX_NB * 8 + 8 * 2 * MAX_NB * 8;         // permutations
+    if (mixed) b += npan * 2 * MAX_NB * MAX_NB * 8 + MAX_NB * std::max(P, (size_t)L) * 8;  // inverses, scratch
+    b += (P * P + 255) / 256 * 8 + (size_t)L * 6 * 8 + 64;   // norms and refinement state
+    return b;
+}
+
+}  // namespace
+
+struct rsrr_server {
+    rsrr_server_config cfg{};
+    std::chrono::steady_clock::time_point t0;
+    hipStream_t st_s = nullptr, st_p = nullptr;
+    rsrr_ctx* cs = nullptr;
+    rsrr_ctx* cp = nullptr;
+    void* arena_base = nullptr;
+    Arena arena;
+
+    std::mutex mu;
+    std::condition_variable cv_work;  // sampler: new request / freed slot / stop
+    std::condition_variable cv_post;  // solver: sampled request / stop
+    std::condition_variable cv_done;  // waiters
+    std::map<int, std::unique_ptr<Req>> reqs;
+    std::deque<Req*> queue;           // waiting for admission
+    std::vector<Req*> admitted;       // points left to sample, admission order
+    std::deque<Req*> post;            // sampled, waiting for basis/projection/solve
+    int active = 0;                   // admitted and not finished
+    int next_id = 1;
+    bool stop = false;
+    int posting = 0;                  // requests inside the solve step
+
+    // post-step device buffers (grown on demand, owned by the thread doing the post step)
+    void* q_buf = nullptr;  size_t q_cap = 0;
+    void* aq_buf = nullptr; size_t aq_cap = 0;
+    void* v_buf = nullptr;  size_t v_cap = 0;
+
+    // counters
+    long finished = 0, points = 0, launches = 0, max_launch = 0;
+    double busy_s = 0.0, busy_p = 0.0;
+    size_t mem_peak = 0;
+
+    std::thread th_s, th_p;
+};
+
+namespace {
+
+void* grow(void*& p, size_t& cap, size_t bytes)
+{
+    if (bytes <= cap && p) return p;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+        return nullptr;
+    }
+    cap = bytes;
+    return p;
+}
+
+void note_status(rsrr_result& r, rsrr_status s)
+{
+    if (s == RSRR_OK) return;
+    if (r.status == RSRR_OK || (!is_error(r.status) && is_error(s))) r.status = s;
+}
+
+// Basis, projection, SS-FULL and the copy of the eigenpairs to the host (RSRR
+// Steps 3-5) for one sampled request, on context c.
+void finish_request(rsrr_server* s, rsrr_ctx* c, hipStream_t st, Req* q)
+{
+    rsrr_result& res = q->res;
+    if (is_error(res.status) && res.status != RSRR_ESINGULAR) return;
+    const rsrr_request& r = q->r;
+    const int n = r.nep.n, NL = r.N * r.L, kmax = std::min(n, NL);
+    double2* Q = (double2*)grow(s->q_buf, s->q_cap, (size_t)n * kmax * 16);
+    if (!Q) { note_status(res, RSRR_ENOMEM); return; }
+    int k = 0;
+    rsrr_status e = rsrr_basis(c, n, NL, q->S, n, r.delta > 0 ? r.delta : DEFAULT_DELTA, (double*)Q, n, kmax, &k,
+                               nullptr);
+    note_status(res, e);
+    if (is_error(e)) return;
+    res.k = k;
+    if (k < 1) return;
+    const int maxt = r.nep.kind == RSRR_T_SEPARABLE ? r.nep.J : MAX_TERMS;
+    double2* AQ = (double2*)grow(s->aq_buf, s->aq_cap, (size_t)maxt * k * k * 16);
+    double2* V = r.V ? (double2*)grow(s->v_buf, s->v_cap, (size_t)n * r.max_eigs * 16) : nullptr;
+    if (!AQ || (r.V && !V)) { note_status(res, RSRR_ENOMEM); return; }
+    std::vector<rsrr_term> tout(maxt);
+    int J_eff = 0;
+    const double gam[2] = {r.gamma_re, r.gamma_im};
+    e = rsrr_project(c, &r.nep, (const double*)Q, n, k, gam, std::max(r.a, r.b), (double*)AQ, maxt, &J_eff,
+                     tout.data());
+    note_status(res, e);
+    if (is_error(e)) return;
+    int count = 0;
+    rsrr_solve_info si{};
+    std::vector<double> resid(r.max_eigs, 0.0);
+    e = rsrr_solve(c, &r.nep, k, (const double*)AQ, J_eff, tout.data(), (const double*)Q, n, gam, r.a, r.b,
+                   r.NQ > 0 ? r.NQ : DEFAULT_NQ, r.KQ > 0 ? r.KQ : DEFAULT_KQ, TOL_GAP, r.max_eigs, r.lambda,
+                   (double*)V, n, r.resid ? r.resid : resid.data(), &count, nullptr, &si);
+    note_status(res, e);
+    if (is_error(e)) return;
+    res.count = count;
+    res.nbar = si.nbar;
+    if (r.V && count > 0) {
+        if (hipMemcpyAsync(r.V, V, (size_t)n * count * 16, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            note_status(res, RSRR_EDEVICE);
+    }
+}
+
+// Called with s->mu held: admit queued requests while a slot and arena room exist.
+void admit_locked(rsrr_server* s)
+{
+    while (!s->queue.empty() && s->active < s->cfg.max_slots) {
+        Req* q = s->queue.front();
+        const long off = s->arena.alloc(q->s_bytes);
+        if (off < 0) break;  // first come first served: wait for room
+        s->queue.pop_front();
+        q->s_off = (size_t)off;
+        q->S = (double*)((char*)s->arena_base + off);
+        q->state = ADMITTED;
+        q->res.t_admit = now_s(s->t0);
+        s->admitted.push_back(q);
+        ++s->active;
+    }
+}
+
+// Called with s->mu held: the next launch's points.
+std::vector<Chunk> pick_locked(rsrr_server* s)
+{
+    std::vector<Chunk> out;
+    const bool mixed = s->cfg.prec == RSRR_PREC_C64_IR;
+    size_t used = 0;
+    for (Req* q : s->admitted) {
+        if (q->next >= q->r.N) continue;
+        const size_t bp = point_bytes(q->r.nep.n, q->r.L, mixed);
+        long room = used < s->cfg.batch_bytes ? (long)((s->cfg.batch_bytes - used) / bp) : 0;
+        if (room <= 0) {
+            if (!out.empty()) break;
+            room = 1;  // a point larger than the cap still runs, alone
+        }
+        const int cnt = (int)std::min<long>(q->r.N - q->next, room);
+        out.push_back({q, q->next, cnt});
+        q->next += cnt;
+        used += (size_t)cnt * bp;
+        if (s->cfg.flags & RSRR_SERVE_NO_BATCH) break;
+    }
+    return out;
+}
+
+// One sampling launch: rsrr_sample_batched per probe count L.
+void run_launch(rsrr_server* s, const std::vector<Chunk>& ch, std::vector<std::vector<rsrr_point_info>>& infos,
+                std::vector<rsrr_status>& codes)
+{
+    infos.assign(ch.size(), {});
+    codes.assign(ch.size(), RSRR_OK);
+    std::map<int, std::vector<int>> byL;
+    for (size_t i = 0; i < ch.size(); ++i) byL[ch[i].q->r.L].push_back((int)i);
+    for (auto& kv : byL) {
+        std::vector<rsrr_instance> inst;
+        long tot = 0;
+        for (int i : kv.second) {
+            const Chunk& c = ch[i];
+            const rsrr_request& r = c.q->r;
+            rsrr_instance in{};
+            in.nep = r.nep;
+            in.nep.terms = c.q->terms.empty() ? nullptr : c.q->terms.data();
+            in.N = c.cnt;
+            in.z = c.q->z.data() + 2 * (size_t)c.k0;
+            in.U = r.U;
+            in.L = r.L;
+            in.ldu = r.ldu;
+            in.S = c.q->S + 2 * (size_t)c.k0 * r.L * r.nep.n;
+            in.lds = r.nep.n;
+            inst.push_back(in);
+            tot += c.cnt;
+        }
+        std::vector<rsrr_point_info> pi(tot);
+        const rsrr_status e = rsrr_sample_batched(s->cs, (int)inst.size(), inst.data(), s->cfg.prec, 0, pi.data());
+        long p = 0;
+        for (int i : kv.second) {
+            infos[i].assign(pi.begin() + p, pi.begin() + p + ch[i].cnt);
+            p += ch[i].cnt;
+            if (e < 0 || e == RSRR_ENOMEM || e == RSRR_EDEVICE || e == RSRR_ENAN) {
+                codes[i] = e;
+            } else {
+                // per request: ESINGULAR only where one of its own points had a zero pivot
+                for (const auto& x : infos[i]) {
+                    if (x.info > 0) codes[i] = RSRR_ESINGULAR;
+                    else if (x.fallback && codes[i] == RSRR_OK) codes[i] = RSRR_WARN_FALLBACK;
+                }
+            }
+        }
+    }
+}
+
+void complete_locked(rsrr_server* s, Req* q)
+{
+    s->arena.release(q->s_off, q->s_bytes);
+    q->S = nullptr;
+    q->state = DONE;
+    q->res.t_done = now_s(s->t0);
+    --s->active;
+    ++s->finished;
+    s->cv_done.notify_all();
+    s->cv_work.notify_all();
+}
+
+void post_one(rsrr_server* s, rsrr_ctx* c, hipStream_t st, std::unique_lock<std::mutex>& lk)
+{
+    Req* q = s->post.front();
+    s->post.pop_front();
+    ++s->posting;
+    lk.unlock();
+    const auto t = std::chrono::steady_clock::now();
+    finish_request(s, c, st, q);
+    const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t).count();
+    lk.lock();
+    s->busy_p += dt;
+    --s->posting;
+    complete_locked(s, q);
+}
+
+void sampler_main(rsrr_server* s)
+{
+    (void)hipSetDevice(s->cfg.device);
+    const bool serial = (s->cfg.flags & RSRR_SERVE_SERIAL) != 0;
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        if (serial && !s->post.empty()) {
+            post_one(s, s->cs, s->st_s, lk);
+            continue;
+        }
+        admit_locked(s);
+        std::vector<Chunk> ch = pick_locked(s);
+        if (ch.empty()) {
+            if (s->stop && s->queue.empty() && s->admitted.empty()) break;
+            s->cv_work.wait(lk);
+            continue;
+        }
+        const int launch_id = (int)s->launches++;
+        long pts = 0;
+        for (auto& c : ch) pts += c.cnt;
+        s->max_launch = std::max(s->max_launch, pts);
+        lk.unlock();
+        const auto t = std::chrono::steady_clock::now();
+        std::vector<std::vector<rsrr_point_info>> infos;
+        std::vector<rsrr_status> codes;
+        run_launch(s, ch, infos, codes);
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) { (void)hipGetLastError(); fr = tot; }
+        const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t).count();
+        lk.lock();
+        s->busy_s += dt;
+        s->points += pts;
+        s->mem_peak = std::max(s->mem_peak, tot - fr);
+        for (size_t i = 0; i < ch.size(); ++i) {
+            Req* q = ch[i].q;
+            rsrr_result& r = q->res;
+            note_status(r, codes[i]);
+            if (q->last_launch != launch_id) { ++r.launches; q->last_launch = launch_id; }
+            for (const auto& x : infos[i]) {
+                r.fallbacks += x.fallback;
+                r.ir_iters_max = std::max(r.ir_iters_max, x.ir_iters);
+                if (x.resid > r.sample_resid_max) r.sample_resid_max = x.resid;
+            }
+            q->sampled += ch[i].cnt;
+            if (q->sampled == q->r.N) {
+                q->state = SAMPLED;
+                r.t_sampled = now_s(s->t0);
+                s->admitted.erase(std::find(s->admitted.begin(), s->admitted.end(), q));
+                s->post.push_back(q);
+                s->cv_post.notify_one();
+            }
+        }
+    }
+}
+
+void solver_main(rsrr_server* s)
+{
+    (void)hipSetDevice(s->cfg.device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        if (!s->post.empty()) {
+            post_one(s, s->cp, s->st_p, lk);
+            continue;
+        }
+        if (s->stop && s->queue.empty() && s->admitted.empty()) break;
+        s->cv_post.wait(lk);
+    }
+}
+
+}  // namespace
+
+extern "C" rsrr_status rsrr_server_create(rsrr_server** out, const rsrr_server_config* cfg)
+{
+    if (!out) return -1;
+    if (!cfg || cfg->max_slots < 1 || cfg->arena_bytes == 0 || cfg->batch_bytes == 0 ||
+        (cfg->prec != RSRR_PREC_C128 && cfg->prec != RSRR_PREC_C64_IR))
+        return -2;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess) return RSRR_EDEVICE;
+    if (cfg->device < 0 || cfg->device >= ndev) return -2;
+    RSRR_HIP(hipSetDevice(cfg->device));
+    std::unique_ptr<rsrr_server> s(new rsrr_server());
+    s->cfg = *cfg;
+    s->t0 = std::chrono::steady_clock::now();
+    if (hipStreamCreateWithFlags(&s->st_s, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&s->st_p, hipStreamNonBlocking) != hipSuccess)
+        return RSRR_EDEVICE;
+    rsrr_status e = rsrr_create(&s->cs, cfg->device, s->st_s);
+    if (e) return e;
+    e = rsrr_create(&s->cp, cfg->device, s->st_p);
+    if (e) return e;
+    if (hipMalloc(&s->arena_base, cfg->arena_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        rsrr_destroy(s->cs);
+        rsrr_destroy(s->cp);
+        return RSRR_ENOMEM;
+    }
+    s->arena.init(cfg->arena_bytes);
+    rsrr_server* p = s.release();
+    p->th_s = std::thread(sampler_main, p);
+    if (!(cfg->flags & RSRR_SERVE_SERIAL)) p->th_p = std::thread(solver_main, p);
+    *out = p;
+    return RSRR_OK;
+}
+
+extern "C" rsrr_status rsrr_server_submit(rsrr_server* s, const rsrr_request* r, int* id)
+{
+    if (!s) return -1;
+    if (!r) return -2;
+    if (!id) return -3;
+    const rsrr_nep& e = r->nep;
+    if (e.n < 1 || e.n > 8192) return -2;
+    if (e.kind == RSRR_T_SEPARABLE) {
+        if (e.J < 1 || e.J > MAX_TERMS || !e.A || e.lda < e.n || !e.terms) return -2;
+    } else if (e.kind == RSRR_T_HELMHOLTZ) {
+        if (!e.points || !(e.w > 0)) return -2;
+    } else {
+        return -2;
+    }
+    if (!(r->a > 0) || !(r->b > 0) || r->N < 1 || r->L < 1 || !r->U || r->ldu < e.n || r->max_eigs < 1 ||
+        !r->lambda || r->NQ < 0 || r->KQ < 0 || (r->NQ > 0 && r->NQ < 2 * std::max(r->KQ, 1) + 1) ||
+        !(r->delta >= 0 && r->delta < 1))
+        return -2;
+    std::unique_ptr<Req> q(new Req());
+    q->r = *r;
+    if (e.kind == RSRR_T_SEPARABLE) q->terms.assign(e.terms, e.terms + e.J);
+    q->r.nep.terms = q->terms.empty() ? nullptr : q->terms.data();
+    q->z.resize(2 * (size_t)r->N);
+    const rsrr_status ce = rsrr_contour(r->gamma_re, r->gamma_im, r->a, r->b, r->N, q->z.data(), nullptr);
+    if (ce) return -2;
+    q->s_bytes = (size_t)e.n * r->N * r->L * 16;
+    if ((q->s_bytes + ALIGN - 1) / ALIGN * ALIGN > s->cfg.arena_bytes) return RSRR_ENOMEM;
+    std::lock_guard<std::mutex> lk(s->mu);
+    q->id = s->next_id++;
+    q->res.id = q->id;
+    q->res.t_submit = now_s(s->t0);
+    *id = q->id;
+    s->queue.push_back(q.get());
+    s->reqs[q->id] = std::move(q);
+    s->cv_work.notify_all();
+    return RSRR_OK;
+}
+
+extern "C" rsrr_status rsrr_server_wait(rsrr_server* s, int id, double timeout_s, rsrr_result* out)
+{
+    if (!s) return -1;
+    if (!out) return -4;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(id);
+    if (it == s->reqs.end()) return -2;
+    Req* q = it->second.get();
+    auto done = [&] { return q->state == DONE; };
+    if (timeout_s < 0) {
+        s->cv_done.wait(lk, done);
+    } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done)) {
+        return RSRR_ETIMEOUT;
+    }
+    *out = q->res;
+    s->reqs.erase(it);
+    return RSRR_OK;
+}
+
+extern "C" rsrr_status rsrr_server_stats(rsrr_server* s, double* out)
+{
+    if (!s) return -1;
+    if (!out) return -2;
+    std::lock_guard<std::mutex> lk(s->mu);
+    out[0] = (double)s->finished;
+    out[1] = (double)s->points;
+    out[2] = (double)s->launches;
+    out[3] = (double)s->arena.peak;
+    out[4] = (double)s->max_launch;
+    out[5] = s->busy_s;
+    out[6] = s->busy_p;
+    out[7] = (double)s->mem_peak;
+    out[8] = now_s(s->t0);
+    out[9] = (double)s->queue.size();
+    return RSRR_OK;
+}
+
+extern "C" rsrr_status rsrr_server_destroy(rsrr_server* s)
+{
+    if (!s) return -1;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->cv_work.notify_all();
+        s->cv_post.notify_all();
+    }
+    // the sampler leaves once nothing is queued or admitted; the solver once it has also
+    // drained the sampled requests
+    if (s->th_s.joinable()) s->th_s.join();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->cv_post.notify_all();
+    }
+    if (s->th_p.joinable()) s->th_p.join();
+    (void)hipSetDevice(s->cfg.device);
+    rsrr_destroy(s->cs);
+    rsrr_destroy(s->cp);
+    if (s->arena_base) (void)hipFree(s->arena_base);
+    if (s->q_buf) (void)hipFree(s->q_buf);
+    if (s->aq_buf) (void)hipFree(s->aq_buf);
+    if (s->v_buf) (void)hipFree(s->v_buf);
+    (void)hipStreamDestroy(s->st_s);
+    (void)hipStreamDestroy(s->st_p);
+    delete s;
+    return RSRR_OK;
+}

@@ -27,18 +27,23 @@ RSRR_ENOMEM = 4
 RSRR_EDEVICE = 5
 RSRR_ENOTCONV = 6
 RSRR_ENAN = 7
+RSRR_ETIMEOUT = 8
 RSRR_T_SEPARABLE = 0
 RSRR_T_HELMHOLTZ = 1
 RSRR_PREC_C128 = 0
 RSRR_PREC_C64_IR = 1
 
 STATUS_NAMES = {0: "OK", 1: "ESINGULAR", 2: "WARN_FALLBACK", 3: "WARN_GAP", 4: "ENOMEM", 5: "EDEVICE",
-                6: "ENOTCONV", 7: "ENAN"}
+                6: "ENOTCONV", 7: "ENAN", 8: "ETIMEOUT"}
 
 EXPORTS = ["rsrr_create", "rsrr_destroy", "rsrr_contour", "rsrr_sample", "rsrr_sample_batched", "rsrr_basis",
-           "rsrr_project", "rsrr_solve", "rsrr_last_timings", "rsrr_update_stats", "rsrr_version"]
+           "rsrr_project", "rsrr_solve", "rsrr_last_timings", "rsrr_update_stats", "rsrr_version",
+           "rsrr_server_create", "rsrr_server_submit", "rsrr_server_wait", "rsrr_server_stats",
+           "rsrr_server_destroy"]
 RSRR_BATCH_GRAPH = 1
 RSRR_BATCH_AUTOTUNE = 2
+RSRR_SERVE_NO_BATCH = 1
+RSRR_SERVE_SERIAL = 2
 
 
 class RsrrTerm(C.Structure):
@@ -65,6 +70,26 @@ class RsrrPointInfo(C.Structure):
 class RsrrSolveInfo(C.Structure):
     _fields_ = [("nbar", C.c_int), ("warn_gap", C.c_int), ("gmax", C.c_double), ("n_sigma", C.c_int),
                 ("pad", C.c_int)]
+
+
+class RsrrServerConfig(C.Structure):
+    _fields_ = [("device", C.c_int), ("prec", C.c_int), ("max_slots", C.c_int), ("flags", C.c_int),
+                ("arena_bytes", C.c_ulonglong), ("batch_bytes", C.c_ulonglong)]
+
+
+class RsrrRequest(C.Structure):
+    _fields_ = [("nep", RsrrNep), ("gamma_re", C.c_double), ("gamma_im", C.c_double), ("a", C.c_double),
+                ("b", C.c_double), ("N", C.c_int), ("L", C.c_int), ("U", C.c_void_p), ("ldu", C.c_int),
+                ("NQ", C.c_int), ("KQ", C.c_int), ("delta", C.c_double), ("max_eigs", C.c_int),
+                ("lambda_", C.POINTER(C.c_double)), ("resid", C.POINTER(C.c_double)),
+                ("V", C.POINTER(C.c_double))]
+
+
+class RsrrResult(C.Structure):
+    _fields_ = [("id", C.c_int), ("status", C.c_int), ("count", C.c_int), ("k", C.c_int), ("nbar", C.c_int),
+                ("fallbacks", C.c_int), ("ir_iters_max", C.c_int), ("launches", C.c_int),
+                ("sample_resid_max", C.c_double), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_sampled", C.c_double), ("t_done", C.c_double)]
 
 
 class RsrrError(RuntimeError):
@@ -104,6 +129,11 @@ def lib():
                              ip, dp, C.POINTER(RsrrSolveInfo)]
     L.rsrr_last_timings.argtypes = [vp, dp]
     L.rsrr_update_stats.argtypes = [vp, C.c_int, C.c_int, dp]
+    L.rsrr_server_create.argtypes = [C.POINTER(vp), C.POINTER(RsrrServerConfig)]
+    L.rsrr_server_submit.argtypes = [vp, C.POINTER(RsrrRequest), ip]
+    L.rsrr_server_wait.argtypes = [vp, C.c_int, C.c_double, C.POINTER(RsrrResult)]
+    L.rsrr_server_stats.argtypes = [vp, dp]
+    L.rsrr_server_destroy.argtypes = [vp]
     L.rsrr_version.restype = C.c_char_p
     for f in EXPORTS:
         if f != "rsrr_version":
@@ -361,3 +391,70 @@ def rsrr_solve(ctx, dnep, Q, k, AQ, terms, gamma, a, b, NQ=500, KQ=2, tol_gap=1e
 
 def rsrr_version():
     return lib().rsrr_version().decode()
+
+
+# ----------------------------------------------------------------------------- serving
+
+
+class Server:
+    """rsrr_server_*: a request loop running the whole method for many NEPs with
+    continuous batching of their sampling points.  The binding keeps every
+    buffer of a request alive until wait() has returned it."""
+
+    def __init__(self, device=0, prec=RSRR_PREC_C64_IR, max_slots=8, arena_bytes=16 << 30,
+                 batch_bytes=24 << 30, flags=0):
+        L = lib()
+        self.cfg = RsrrServerConfig(device, int(prec), int(max_slots), int(flags), int(arena_bytes),
+                                    int(batch_bytes))
+        self.h = C.c_void_p()
+        _check("rsrr_server_create", L.rsrr_server_create(C.byref(self.h), C.byref(self.cfg)))
+        self._live = {}
+
+    def submit(self, dnep, U, gamma, a, b, N, max_eigs=64, NQ=0, KQ=0, delta=0.0, want_V=False):
+        """U: device tensor (L, n) holding the n x L probes column-major.  Returns the request id."""
+        n = dnep.n
+        L = U.shape[0]
+        lam = (C.c_double * (2 * max_eigs))()
+        res = (C.c_double * max_eigs)()
+        V = np.zeros((max_eigs, n), dtype=np.complex128) if want_V else None
+        vptr = V.ctypes.data_as(C.POINTER(C.c_double)) if want_V else None
+        g = complex(gamma)
+        req = RsrrRequest(dnep.desc, g.real, g.imag, float(a), float(b), int(N), int(L), U.data_ptr(),
+                          U.shape[1], int(NQ), int(KQ), float(delta), int(max_eigs),
+                          C.cast(lam, C.POINTER(C.c_double)), C.cast(res, C.POINTER(C.c_double)), vptr)
+        rid = C.c_int(0)
+        _check("rsrr_server_submit", lib().rsrr_server_submit(self.h, C.byref(req), C.byref(rid)))
+        self._live[rid.value] = (dnep, U, lam, res, V, req)
+        return rid.value
+
+    def wait(self, rid, timeout=-1.0):
+        """Block until request rid has finished; returns its eigenpairs and timings."""
+        out = RsrrResult()
+        _check("rsrr_server_wait", lib().rsrr_server_wait(self.h, int(rid), float(timeout), C.byref(out)))
+        dnep, U, lam, res, V, req = self._live.pop(rid)
+        m = out.count
+        r = {f: getattr(out, f) for f, _ in RsrrResult._fields_}
+        r["lam"] = np.frombuffer(lam, dtype=np.float64).view(np.complex128)[:m].copy()
+        r["resid"] = np.frombuffer(res, dtype=np.float64)[:m].copy()
+        r["V"] = np.ascontiguousarray(V[:m].T) if V is not None else None
+        return r
+
+    def stats(self):
+        out = (C.c_double * 10)()
+        _check("rsrr_server_stats", lib().rsrr_server_stats(self.h, out))
+        keys = ["finished", "points", "launches", "arena_peak_bytes", "max_launch_points", "sampler_busy_s",
+                "solver_busy_s", "device_mem_peak_bytes", "now_s", "queued"]
+        return dict(zip(keys, list(out)))
+
+    def close(self):
+        if self.h:
+            lib().rsrr_server_destroy(self.h)
+            self.h = C.c_void_p()
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

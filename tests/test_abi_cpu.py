@@ -63,3 +63,38 @@ def test_argument_errors_without_device(lib):
     assert lib.rsrr_last_timings(None, None) == -1
     assert lib.rsrr_update_stats(None, 0, 0, None) == -1
     assert b"gfx950" in lib.rsrr_version()
+
+
+def test_server_argument_errors_without_device(lib):
+    from paper_1605_07951_amd import rsrr
+    cfg = rsrr.RsrrServerConfig(0, 1, 0, 0, 1 << 20, 1 << 20)  # max_slots = 0
+    h = C.c_void_p()
+    assert lib.rsrr_server_create(None, C.byref(cfg)) == -1
+    assert lib.rsrr_server_create(C.byref(h), None) == -2
+    assert lib.rsrr_server_create(C.byref(h), C.byref(cfg)) == -2
+    cfg = rsrr.RsrrServerConfig(0, 7, 1, 0, 1 << 20, 1 << 20)  # bad precision
+    assert lib.rsrr_server_create(C.byref(h), C.byref(cfg)) == -2
+    cfg = rsrr.RsrrServerConfig(0, 1, 1, 0, 0, 1 << 20)  # empty arena
+    assert lib.rsrr_server_create(C.byref(h), C.byref(cfg)) == -2
+    rid = C.c_int(0)
+    assert lib.rsrr_server_submit(None, None, C.byref(rid)) == -1
+    assert lib.rsrr_server_wait(None, 1, 0.0, None) == -1
+    assert lib.rsrr_server_stats(None, None) == -1
+    assert lib.rsrr_server_destroy(None) == -1
+
+
+def test_server_structs_match_header(lib):
+    """ctypes mirrors of the serving structs have the C sizes (compiled here with gcc)."""
+    import subprocess
+    import tempfile
+    from paper_1605_07951_amd import rsrr
+    src = ('#include <stdio.h>\n#include "rsrr.h"\nint main(void){printf("%zu %zu %zu %zu %zu\\n", '
+           'sizeof(rsrr_request), sizeof(rsrr_result), sizeof(rsrr_server_config), sizeof(rsrr_nep), '
+           'sizeof(rsrr_instance)); return 0;}\n')
+    with tempfile.TemporaryDirectory() as d:
+        cpath, exe = os.path.join(d, "sz.c"), os.path.join(d, "sz")
+        open(cpath, "w").write(src)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), cpath, "-o", exe], check=True)
+        got = [int(x) for x in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
+    assert got == [C.sizeof(rsrr.RsrrRequest), C.sizeof(rsrr.RsrrResult), C.sizeof(rsrr.RsrrServerConfig),
+                   C.sizeof(rsrr.RsrrNep), C.sizeof(rsrr.RsrrInstance)]

@@ -1,0 +1,156 @@
+"""GPU tests of the serving loop (rsrr_server_*): every request's eigenpairs
+meet the parity bars (eigenvalues within 1e-9 relative of the closed forms /
+the oracle inside the contour, eigen-residuals <= 1e-10); a request's results
+are the same alone and in a mix of concurrent requests (bitwise: per-point
+work depends only on (n, L, precision)); admission respects the HBM arena."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import pins as P
+from oracle import rsrr_oracle as O
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1605_07951_amd import rsrr
+    rsrr.lib()
+    return rsrr
+
+
+def _match(got, ref):
+    return max(np.min(np.abs(ref - g)) / max(1.0, abs(g)) for g in got) if len(got) else 0.0
+
+
+def _qep(R, seed=0, n=200):
+    nep, C, U = W.cfg_qep(n=n, seed=seed)
+    return nep, C, R.DeviceNEP(nep), R.colmajor(U)[0]
+
+
+def _check_qep(res, nep, C):
+    ex = P.qep_roots(nep.extra["c"], nep.extra["k"])
+    lv = O.level(res["lam"], C.gamma, C.a, C.b)
+    ins = lv < 0.98
+    exin = ex[O.level(ex, C.gamma, C.a, C.b) < 0.98]
+    assert res["status"] == 0, res["status"]
+    assert ins.sum() == exin.size
+    assert _match(res["lam"][ins], ex) < 1e-9 and _match(exin, res["lam"]) < 1e-9
+    assert res["resid"][ins].max() <= 1e-10
+
+
+def test_serve_requests_meet_parity(R):
+    srv = R.Server(prec=R.RSRR_PREC_C64_IR, max_slots=4, arena_bytes=1 << 30, batch_bytes=1 << 30)
+    try:
+        reqs = []
+        for seed in (0, 1):
+            nep, C, dn, U = _qep(R, seed)
+            reqs.append(("qep", nep, C, srv.submit(dn, U, C.gamma, C.a, C.b, C.N, max_eigs=64, want_V=True)))
+        nep, C, U = W.cfg_delay(nx=16, N=48, L=32)
+        reqs.append(("delay", nep, C, srv.submit(R.DeviceNEP(nep), R.colmajor(U)[0], C.gamma, C.a, C.b, C.N,
+                                                 max_eigs=32, want_V=True)))
+        for kind, nep, C, rid in reqs:
+            res = srv.wait(rid, timeout=120.0)
+            prob = O.Problem(nep)
+            if kind == "qep":
+                _check_qep(res, nep, C)
+            else:
+                ex = P.delay_eigs(W.laplacian_modes(16, 16))
+                exin = ex[O.level(ex, C.gamma, C.a, C.b) < 1]
+                ins = O.level(res["lam"], C.gamma, C.a, C.b) < 0.98
+                assert ins.sum() == exin.size == 3
+                assert _match(res["lam"][ins], exin) < 1e-9
+            # residuals recomputed on the CPU from the returned eigenvectors
+            ins = O.level(res["lam"], C.gamma, C.a, C.b) < 0.98
+            for i in np.where(ins)[0]:
+                assert O.residual(prob, res["lam"][i], res["V"][:, i]) <= 1e-10
+            assert res["t_submit"] <= res["t_admit"] <= res["t_sampled"] <= res["t_done"]
+        st = srv.stats()
+        assert st["finished"] == 3 and st["points"] == 32 + 32 + 48
+    finally:
+        srv.close()
+
+
+def test_serve_alone_equals_mix(R):
+    """The same request alone and inside a mix of six concurrent requests (shared launches)."""
+    nep, C, dn, U = _qep(R, 5)
+    alone_srv = R.Server(max_slots=1, arena_bytes=1 << 30, batch_bytes=1 << 30)
+    try:
+        alone = alone_srv.wait(alone_srv.submit(dn, U, C.gamma, C.a, C.b, C.N, max_eigs=64, want_V=True), 120.0)
+    finally:
+        alone_srv.close()
+    _check_qep(alone, nep, C)
+    # about 3.2 MB of LU workspace per n=200 point (padded to 256, complex FP32 with FP64
+    # copies): a launch holds about 40 points, so the 32-point requests share launches
+    mix_srv = R.Server(max_slots=6, arena_bytes=1 << 30, batch_bytes=40 * 3_200_000)
+    try:
+        others = []
+        for seed in (6, 7):
+            _, Co, dno, Uo = _qep(R, seed)
+            others.append((dno, Uo, mix_srv.submit(dno, Uo, Co.gamma, Co.a, Co.b, Co.N, max_eigs=64)))
+        rid = mix_srv.submit(dn, U, C.gamma, C.a, C.b, C.N, max_eigs=64, want_V=True)
+        nd, Cd, Ud = W.cfg_delay(nx=16, N=48, L=32)
+        dnd = R.DeviceNEP(nd)
+        others.append((dnd, None, mix_srv.submit(dnd, R.colmajor(Ud)[0], Cd.gamma, Cd.a, Cd.b, Cd.N, max_eigs=32)))
+        for seed in (8, 9):
+            _, Co, dno, Uo = _qep(R, seed)
+            others.append((dno, Uo, mix_srv.submit(dno, Uo, Co.gamma, Co.a, Co.b, Co.N, max_eigs=64)))
+        mixed = mix_srv.wait(rid, 120.0)
+        for _, _, o in others:
+            assert mix_srv.wait(o, 120.0)["status"] in (0, 3)
+        st = mix_srv.stats()
+    finally:
+        mix_srv.close()
+    assert mixed["launches"] >= 2          # its points were split over launches shared with others
+    assert st["max_launch_points"] > 32    # some launch carried points of more than one request
+    assert mixed["count"] == alone["count"] and mixed["k"] == alone["k"]
+    assert np.array_equal(mixed["lam"], alone["lam"])
+    assert np.array_equal(mixed["V"], alone["V"])
+    assert np.array_equal(mixed["resid"], alone["resid"])
+
+
+def test_serve_admission_by_arena(R):
+    """An arena that holds one request's S at a time admits the next only after the first is done."""
+    nep, C, dn, U = _qep(R, 0, n=128)
+    s_bytes = 128 * C.N * 16 * 16
+    srv = R.Server(max_slots=4, arena_bytes=s_bytes + 1024, batch_bytes=1 << 30)
+    try:
+        ids = [srv.submit(dn, U, C.gamma, C.a, C.b, C.N, max_eigs=64) for _ in range(3)]
+        res = [srv.wait(i, 120.0) for i in ids]
+        st = srv.stats()
+    finally:
+        srv.close()
+    for a, b in zip(res, res[1:]):
+        assert b["t_admit"] >= a["t_done"]
+        assert np.array_equal(a["lam"], b["lam"])
+    assert st["arena_peak_bytes"] <= s_bytes + 1024
+
+
+def test_serve_rejects_oversized_and_unknown(R):
+    nep, C, dn, U = _qep(R, 0, n=128)
+    srv = R.Server(max_slots=1, arena_bytes=(1 << 20) - 4096, batch_bytes=1 << 30)
+    try:
+        with pytest.raises(R.RsrrError) as e:
+            srv.submit(dn, U, C.gamma, C.a, C.b, C.N)   # S is 128*32*16*16 B = 1 MiB
+        assert e.value.code == R.RSRR_ENOMEM
+        with pytest.raises(R.RsrrError) as e:
+            srv.wait(12345, 0.0)
+        assert e.value.code == -2
+    finally:
+        srv.close()
+
+
+def test_serve_sequential_plain_fp64_matches(R):
+    """No batching, one slot, serial post step, FP64 LU: the sequential baseline gives the same eigenvalues."""
+    nep, C, dn, U = _qep(R, 3)
+    srv = R.Server(prec=R.RSRR_PREC_C128, max_slots=1, arena_bytes=1 << 30, batch_bytes=1 << 30,
+                   flags=R.RSRR_SERVE_NO_BATCH | R.RSRR_SERVE_SERIAL)
+    try:
+        res = srv.wait(srv.submit(dn, U, C.gamma, C.a, C.b, C.N, max_eigs=64), 120.0)
+    finally:
+        srv.close()
+    _check_qep(res, nep, C)
