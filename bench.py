@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="helmholtz", choices=["helmholtz", "delay", "qep"])
+    ap.add_argument("--workload", default="helmholtz", choices=["helmholtz", "delay", "qep", "serve"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--N", type=int, default=None)
     ap.add_argument("--L", type=int, default=None)
@@ -51,6 +51,12 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--sample-only", action="store_true", help="skip the basis/projection/SS-FULL pass")
     ap.add_argument("--nq", type=int, default=500, help="SS-FULL quadrature nodes")
+    ap.add_argument("--requests", type=int, default=24, help="serve: requests taken from the stream")
+    ap.add_argument("--rate", type=float, default=20.0, help="serve: Poisson arrival rate (1/s)")
+    ap.add_argument("--slots", type=int, default=8, help="serve: requests admitted at once")
+    ap.add_argument("--arena-gb", type=int, default=32, help="serve: HBM arena for S blocks (GiB)")
+    ap.add_argument("--batch-gb", type=int, default=48, help="serve: LU workspace cap per launch (GiB)")
+    ap.add_argument("--solvers", type=int, default=0, help="serve: solve threads (0: library default)")
     return ap.parse_args()
 
 
@@ -92,12 +98,120 @@ def cpu_baseline(nep, C, U, npts):
                       f"FP64, NumPy/SciPy LAPACK), {dt:.2f} s"}
 
 
+
+def _pct(x, q):
+    return float(np.percentile(np.asarray(x), q)) if len(x) else None
+
+
+def run_serve(args):
+    """Serving stream: requests arrive (Poisson), the server batches their sampling points.
+
+    Latency = result on the host minus submission (at the arrival time).  The
+    same stream is then replayed through a sequential plain-FP64 server (one
+    slot, no batching, no overlap) for comparison."""
+    import threading
+    import torch
+    import workloads as W
+    from paper_1605_07951_amd import rsrr as R
+
+    stream = W.cfg_serving_stream(count=args.requests, rate=args.rate)
+    items = []
+    for q in stream:
+        items.append((q, R.DeviceNEP(W.serving_nep(q)), R.colmajor(W.probes(q["n"], q["L"], q["seed"]))[0]))
+    torch.cuda.synchronize()
+    print(f"[serve] {len(items)} requests ready", file=sys.stderr, flush=True)
+
+    def run(label, prec, flags, slots):
+        srv = R.Server(prec=prec, max_slots=slots, arena_bytes=args.arena_gb << 30,
+                       batch_bytes=args.batch_gb << 30, flags=flags, solvers=args.solvers)
+        ids = [None] * len(items)
+        t0 = time.perf_counter()
+
+        def feeder():
+            for i, (q, dn, U) in enumerate(items):
+                dt = q["t"] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                ids[i] = srv.submit(dn, U, q["gamma"], q["a"], q["b"], q["N"], max_eigs=64)
+
+        th = threading.Thread(target=feeder)
+        th.start()
+        th.join()
+        res = []
+        for i in range(len(items)):
+            res.append(srv.wait(ids[i]))
+            r = res[-1]
+            print(f"[serve {label}] {i + 1}/{len(items)} {items[i][0]['kind']} n={items[i][0]['n']} "
+                  f"latency {r['t_done'] - r['t_submit']:.3f}s status {r['status']}", file=sys.stderr, flush=True)
+        elapsed = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        lat = [r["t_done"] - r["t_submit"] for r in res]
+        t_first = min(r["t_submit"] for r in res)
+        makespan = max(r["t_done"] for r in res) - t_first
+        solves = sum(q["N"] for q, _, _ in items)
+        worst, n_inside = 0.0, 0
+        for (q, _, _), r in zip(items, res):
+            d = r["lam"] - complex(q["gamma"])
+            ins = (d.real / q["a"]) ** 2 + (d.imag / q["b"]) ** 2 < 0.98
+            n_inside += int(ins.sum())
+            if ins.any():
+                worst = max(worst, float(r["resid"][ins].max()))
+        out = {"p50_latency_s": round(_pct(lat, 50), 4), "p99_latency_s": round(_pct(lat, 99), 4),
+               "mean_latency_s": round(float(np.mean(lat)), 4), "makespan_s": round(makespan, 3),
+               "mean_wait_admit_s": round(float(np.mean([r["t_admit"] - r["t_submit"] for r in res])), 4),
+               "mean_sampling_s": round(float(np.mean([r["t_sampled"] - r["t_admit"] for r in res])), 4),
+               "mean_post_s": round(float(np.mean([r["t_done"] - r["t_sampled"] for r in res])), 4),
+               "req_per_s": round(len(items) / makespan, 3), "solves_per_s": round(solves / makespan, 3),
+               "wall_s": round(elapsed, 3), "launches": int(st["launches"]),
+               "max_launch_points": int(st["max_launch_points"]), "sampler_busy_s": round(st["sampler_busy_s"], 3),
+               "solver_busy_s": round(st["solver_busy_s"], 3), "arena_peak_gb": round(st["arena_peak_bytes"] / 2**30, 3),
+               "device_mem_peak_gb": round(st["device_mem_peak_bytes"] / 2**30, 2),
+               "statuses": {str(k): int(v) for k, v in zip(*np.unique([r["status"] for r in res], return_counts=True))},
+               "eigs_inside": n_inside,
+               "eig_resid_max_inside": worst, "fallback_points": int(sum(r["fallbacks"] for r in res))}
+        return out, solves
+
+    served, solves = run("mixed", R.RSRR_PREC_C64_IR, 0, args.slots)
+    res = {
+        "metric": METRIC,
+        "value": served["solves_per_s"],
+        "unit": "resolvent solves/s",
+        "n_gpus": 1,
+        "steps": len(items),
+        "warmup": 0,
+        "ms_per_step": round(1e3 * served["makespan_s"] / len(items), 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 LU (f32 MFMA) + f64 refinement",
+        "data": "synthetic (seeded serving stream: delay Laplacian and Helmholtz sphere NEPs, Gaussian probes)",
+        "config": {"workload": f"serving stream: first {len(items)} of the seeded 2000-request stream, Poisson "
+                               f"{args.rate}/s, 50/50 delay (n 512/1024/2048, N=48, L=32) / Helmholtz "
+                               f"(n 2048/4096/8192, N=64, L=64)",
+                   "slots": args.slots, "arena_gb": args.arena_gb, "batch_gb": args.batch_gb,
+                   "step": "one request: contour, sampling, basis, projection, SS-FULL, eigenpairs on the host"},
+        "roofline": None,
+        "serving": served,
+    }
+    if not args.no_plain:
+        seq, _ = run("fp64-seq", R.RSRR_PREC_C128, R.RSRR_SERVE_NO_BATCH | R.RSRR_SERVE_SERIAL, 1)
+        res["sequential_plain_fp64"] = seq
+        res["speedup_vs_sequential_fp64"] = {
+            "solves_per_s": round(served["solves_per_s"] / seq["solves_per_s"], 3),
+            "p50_latency": round(seq["p50_latency_s"] / served["p50_latency_s"], 3),
+            "p99_latency": round(seq["p99_latency_s"] / served["p99_latency_s"], 3)}
+    print(json.dumps(res), flush=True)
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1",
                           "n_gpus_requested": args.gpus}))
         sys.exit(2)
+    if args.workload == "serve":
+        run_serve(args)
+        return
     import torch
     from paper_1605_07951_amd import rsrr as R
 

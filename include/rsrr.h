@@ -253,9 +253,9 @@ RSRR_API rsrr_status rsrr_sample_batched(rsrr_ctx *ctx, int count, const rsrr_in
  * are batched together: each sampling launch takes points from all admitted
  * requests in admission order, up to batch_bytes of LU workspace, grouped by
  * (n rounded up to 64, L), so points that arrive while others are on the GPU
- * join the next launch.  A second host thread with its own stream runs basis,
+ * join the next launch.  Solve threads, each with its own stream, run basis,
  * projection and SS-FULL of requests whose sampling has finished, overlapping
- * the next sampling launches on the device.  The factors of a launch stay in
+ * each other and the next sampling launches on the device.  The factors of a launch stay in
  * HBM from factorisation through refinement and the FP64 fallback.
  * Per-point work (tile shapes, panel width, refinement) depends only on
  * (n, L, precision), never on what else is in the launch, so a request's
@@ -268,13 +268,15 @@ typedef struct {
     int prec;                 /* RSRR_PREC_C128 or RSRR_PREC_C64_IR                        */
     int max_slots;            /* requests admitted at the same time (>= 1)                 */
     int flags;                /* RSRR_SERVE_*                                               */
+    int solvers;              /* solve threads, each with its own stream (0: 2; at most 8)  */
+    int pad;
     unsigned long long arena_bytes;  /* HBM for the admitted requests' S blocks            */
     unsigned long long batch_bytes;  /* HBM cap of one sampling launch's LU workspace      */
 } rsrr_server_config;
 
 enum {
     RSRR_SERVE_NO_BATCH = 1,  /* one request's points per sampling launch (no mixing)      */
-    RSRR_SERVE_SERIAL = 2     /* no second thread: basis/projection/solve run between the
+    RSRR_SERVE_SERIAL = 2     /* no solve threads: basis/projection/solve run between the
                                  sampling launches, on the sampling stream                */
 };
 
@@ -316,8 +318,8 @@ typedef struct {
     double t_submit, t_admit, t_sampled, t_done;
 } rsrr_result;
 
-/* Create a server (two host threads, two non-blocking streams on cfg->device)
- * and allocate its arena.  Errors: -1 srv NULL, -2 cfg invalid,
+/* Create a server (a sampling thread and cfg->solvers solve threads, each on
+ * its own non-blocking stream on cfg->device) and allocate its arena.  Errors: -1 srv NULL, -2 cfg invalid,
  * RSRR_ENOMEM, RSRR_EDEVICE. */
 RSRR_API rsrr_status rsrr_server_create(rsrr_server **srv, const rsrr_server_config *cfg);
 

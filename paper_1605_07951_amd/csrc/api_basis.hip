@@ -23,6 +23,8 @@ int jacobi_svd(rsrr_ctx* c, double2* A, int lda, int m, int m_apply, int p, int 
     double* off = (double*)ws_get(c, WS_B6, (size_t)rounds * pairs * 8 + (size_t)p * 8);
     if (!off) { *st = RSRR_ENOMEM; return -1; }
     double* cn = off + (size_t)rounds * pairs;
+    void* work = ws_get(c, WS_JAC, jacobi_work_bytes(m, m_apply, p));
+    if (!work) { *st = RSRR_ENOMEM; return -1; }
     // ||A||_F^2 (invariant under the rotations) sets the zero-column threshold
     if (colnorms(c->stream, m, p, A, lda, 0, cn, 1) != hipSuccess) { *st = RSRR_EDEVICE; return -1; }
     std::vector<double> h((size_t)rounds * pairs), hc(p);
@@ -39,7 +41,7 @@ int jacobi_svd(rsrr_ctx* c, double2* A, int lda, int m, int m_apply, int p, int 
     int stall = 0;
     for (int sw = 0; sw < max_sweeps; ++sw) {
         for (int r = 0; r < rounds; ++r) {
-            if (jacobi_round(c->stream, A, lda, m, m_apply, p, r, 2, tol, zthr2, off + (size_t)r * pairs) !=
+            if (jacobi_round(c->stream, A, lda, m, m_apply, p, r, 2, tol, zthr2, off + (size_t)r * pairs, work) !=
                 hipSuccess) {
                 *st = RSRR_EDEVICE;
                 return -1;
@@ -113,7 +115,7 @@ extern "C" rsrr_status rsrr_basis(rsrr_ctx* c, int n, int NL, double* S, int lds
     for (;;) {
         double2* Y = (double2*)ws_get(c, WS_TLU, (size_t)n * l * 16);
         double2* Om = (double2*)ws_get(c, WS_TRES, (size_t)std::max((long)NL * l, (long)n * l) * 16);
-        double2* Wb = (double2*)ws_get(c, WS_D64, (size_t)l * 32 * 16);
+        void* Wb = ws_get(c, WS_D64, bcgs2_work_bytes(n, l));
         double* n0 = (double*)ws_get(c, WS_B7, (size_t)l * 8);
         if (!Y || !Om || !Wb || !n0) return RSRR_ENOMEM;
         if (l >= NL) {

@@ -218,7 +218,8 @@ extern "C" rsrr_status rsrr_solve(rsrr_ctx* c, const rsrr_nep* nep, int k, const
             double2* Rv = (double2*)ws_get(c, WS_R, (size_t)Bc * n * 16);
             double* rn = (double*)ws_get(c, WS_B5, (size_t)2 * Bc * 8);
             double* fr = (double*)ws_get(c, WS_FROB, (size_t)Bc * 8);
-            if (!Tb || !Rv || !rn || !fr) return RSRR_ENOMEM;
+            double* part = (double*)ws_get(c, WS_N1, (size_t)Bc * norm1_parts(n) * 8);
+            if (!Tb || !Rv || !rn || !fr || !part) return RSRR_ENOMEM;
             std::vector<double> hr(2 * Bc);
             for (int i0 = 0; i0 < ne; i0 += Bc) {
                 const int B = std::min(Bc, ne - i0);
@@ -227,7 +228,7 @@ extern "C" rsrr_status rsrr_solve(rsrr_ctx* c, const rsrr_nep* nep, int k, const
                 RSRR_HIP(zgemm(c->stream, 0, 0, n, 1, n, 1.0, Tb, n, (long)n * n, V + (size_t)i0 * ldv, ldv, ldv, 0.0,
                                Rv, n, n, B));
                 RSRR_HIP(colnorms(c->stream, n, 1, Rv, n, n, rn, B));
-                RSRR_HIP(norm1(c->stream, Tb, n, (long)n * n, n, rn + Bc, B));
+                RSRR_HIP(norm1(c->stream, Tb, n, (long)n * n, n, rn + Bc, B, part));
                 RSRR_HIP(hipMemcpyAsync(hr.data(), rn, (size_t)2 * Bc * 8, hipMemcpyDeviceToHost, c->stream));
                 RSRR_HIP(hipStreamSynchronize(c->stream));
                 for (int i = 0; i < B; ++i) resid[i0 + i] = hr[Bc + i] > 0 ? hr[i] / hr[Bc + i] : hr[i];

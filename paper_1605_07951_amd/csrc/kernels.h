@@ -101,16 +101,19 @@ hipError_t ir_decide(hipStream_t st, int M, int Lmax, const double* rn, const do
 // ---- block one-sided Jacobi SVD (basis.hip) ----
 int jacobi_blocks(int p);  // number of column blocks (even) for p columns
 hipError_t jacobi_round(hipStream_t st, double2* A, int lda, int m, int m_apply, int p, int round, int inner,
-                        double tol, double zthr2, double* offmax);
+                        double tol, double zthr2, double* offmax, void* work);
+size_t jacobi_work_bytes(int m, int m_apply, int p);  // bytes of `work` for jacobi_round
 hipError_t gather_scale(hipStream_t st, const double2* A, int lda, int m, const int* order, const double* inv,
                         double2* Q, int ldq, int k);
 hipError_t gaussian(hipStream_t st, double2* X, int n, int m, int ld, unsigned long long seed);
-hipError_t bcgs2(hipStream_t st, double2* Y, int ld, int n, int m, double2* W, double* n0);
+hipError_t bcgs2(hipStream_t st, double2* Y, int ld, int n, int m, void* work, double* n0);
+size_t bcgs2_work_bytes(int n, int m);
 
 // ---- SS-FULL helpers (ssfull.hip) ----
 hipError_t hankel(hipStream_t st, const double2* mom, int k, int K, int shift, double2* H, int ldh);
 hipError_t eye(hipStream_t st, double2* X, int ldx, int r0, int p);
-hipError_t norm1(hipStream_t st, const double2* T, int ld, long sT, int n, double* out, int B);
+hipError_t norm1(hipStream_t st, const double2* T, int ld, long sT, int n, double* out, int B, double* part);
+int norm1_parts(int n);  // doubles of `part` per matrix
 hipError_t small_eig(hipStream_t st, const double2* A, int n, double2* H, double2* Z, double2* lam, double2* Bv,
                      int* status);
 

@@ -130,12 +130,22 @@ size_t point_bytes(int n, int L, bool mixed)
 
 }  // namespace
 
+// A host thread's device context: its stream, rsrr_ctx and the post-step
+// buffers it grows on demand.
+struct Worker {
+    hipStream_t st = nullptr;
+    rsrr_ctx* c = nullptr;
+    void* q_buf = nullptr;  size_t q_cap = 0;
+    void* aq_buf = nullptr; size_t aq_cap = 0;
+    void* v_buf = nullptr;  size_t v_cap = 0;
+    std::thread th;
+};
+
 struct rsrr_server {
     rsrr_server_config cfg{};
     std::chrono::steady_clock::time_point t0;
-    hipStream_t st_s = nullptr, st_p = nullptr;
-    rsrr_ctx* cs = nullptr;
-    rsrr_ctx* cp = nullptr;
+    Worker ws;                        // sampling thread
+    std::vector<std::unique_ptr<Worker>> wp;  // solve threads
     void* arena_base = nullptr;
     Arena arena;
 
@@ -152,17 +162,11 @@ struct rsrr_server {
     bool stop = false;
     int posting = 0;                  // requests inside the solve step
 
-    // post-step device buffers (grown on demand, owned by the thread doing the post step)
-    void* q_buf = nullptr;  size_t q_cap = 0;
-    void* aq_buf = nullptr; size_t aq_cap = 0;
-    void* v_buf = nullptr;  size_t v_cap = 0;
-
     // counters
     long finished = 0, points = 0, launches = 0, max_launch = 0;
     double busy_s = 0.0, busy_p = 0.0;
     size_t mem_peak = 0;
 
-    std::thread th_s, th_p;
 };
 
 namespace {
@@ -190,13 +194,15 @@ void note_status(rsrr_result& r, rsrr_status s)
 
 // Basis, projection, SS-FULL and the copy of the eigenpairs to the host (RSRR
 // Steps 3-5) for one sampled request, on context c.
-void finish_request(rsrr_server* s, rsrr_ctx* c, hipStream_t st, Req* q)
+void finish_request(Worker* w, Req* q)
 {
+    rsrr_ctx* c = w->c;
+    hipStream_t st = w->st;
     rsrr_result& res = q->res;
     if (is_error(res.status) && res.status != RSRR_ESINGULAR) return;
     const rsrr_request& r = q->r;
     const int n = r.nep.n, NL = r.N * r.L, kmax = std::min(n, NL);
-    double2* Q = (double2*)grow(s->q_buf, s->q_cap, (size_t)n * kmax * 16);
+    double2* Q = (double2*)grow(w->q_buf, w->q_cap, (size_t)n * kmax * 16);
     if (!Q) { note_status(res, RSRR_ENOMEM); return; }
     int k = 0;
     rsrr_status e = rsrr_basis(c, n, NL, q->S, n, r.delta > 0 ? r.delta : DEFAULT_DELTA, (double*)Q, n, kmax, &k,
@@ -206,9 +212,10 @@ void finish_request(rsrr_server* s, rsrr_ctx* c, hipStream_t st, Req* q)
     res.k = k;
     if (k < 1) return;
     const int maxt = r.nep.kind == RSRR_T_SEPARABLE ? r.nep.J : MAX_TERMS;
-    double2* AQ = (double2*)grow(s->aq_buf, s->aq_cap, (size_t)maxt * k * k * 16);
-    double2* V = r.V ? (double2*)grow(s->v_buf, s->v_cap, (size_t)n * r.max_eigs * 16) : nullptr;
-    if (!AQ || (r.V && !V)) { note_status(res, RSRR_ENOMEM); return; }
+    double2* AQ = (double2*)grow(w->aq_buf, w->aq_cap, (size_t)maxt * k * k * 16);
+    // eigenvectors are always lifted on the device: the residuals need them
+    double2* V = (double2*)grow(w->v_buf, w->v_cap, (size_t)n * r.max_eigs * 16);
+    if (!AQ || !V) { note_status(res, RSRR_ENOMEM); return; }
     std::vector<rsrr_term> tout(maxt);
     int J_eff = 0;
     const double gam[2] = {r.gamma_re, r.gamma_im};
@@ -301,7 +308,7 @@ void run_launch(rsrr_server* s, const std::vector<Chunk>& ch, std::vector<std::v
             tot += c.cnt;
         }
         std::vector<rsrr_point_info> pi(tot);
-        const rsrr_status e = rsrr_sample_batched(s->cs, (int)inst.size(), inst.data(), s->cfg.prec, 0, pi.data());
+        const rsrr_status e = rsrr_sample_batched(s->ws.c, (int)inst.size(), inst.data(), s->cfg.prec, 0, pi.data());
         long p = 0;
         for (int i : kv.second) {
             infos[i].assign(pi.begin() + p, pi.begin() + p + ch[i].cnt);
@@ -331,14 +338,14 @@ void complete_locked(rsrr_server* s, Req* q)
     s->cv_work.notify_all();
 }
 
-void post_one(rsrr_server* s, rsrr_ctx* c, hipStream_t st, std::unique_lock<std::mutex>& lk)
+void post_one(rsrr_server* s, Worker* w, std::unique_lock<std::mutex>& lk)
 {
     Req* q = s->post.front();
     s->post.pop_front();
     ++s->posting;
     lk.unlock();
     const auto t = std::chrono::steady_clock::now();
-    finish_request(s, c, st, q);
+    finish_request(w, q);
     const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t).count();
     lk.lock();
     s->busy_p += dt;
@@ -353,7 +360,7 @@ void sampler_main(rsrr_server* s)
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         if (serial && !s->post.empty()) {
-            post_one(s, s->cs, s->st_s, lk);
+            post_one(s, &s->ws, lk);
             continue;
         }
         admit_locked(s);
@@ -401,13 +408,13 @@ void sampler_main(rsrr_server* s)
     }
 }
 
-void solver_main(rsrr_server* s)
+void solver_main(rsrr_server* s, Worker* w)
 {
     (void)hipSetDevice(s->cfg.device);
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         if (!s->post.empty()) {
-            post_one(s, s->cp, s->st_p, lk);
+            post_one(s, w, lk);
             continue;
         }
         if (s->stop && s->queue.empty() && s->admitted.empty()) break;
@@ -417,37 +424,69 @@ void solver_main(rsrr_server* s)
 
 }  // namespace
 
+static rsrr_status worker_init(Worker* w, int device)
+{
+    if (hipStreamCreateWithFlags(&w->st, hipStreamNonBlocking) != hipSuccess) {
+        w->st = nullptr;
+        return RSRR_EDEVICE;
+    }
+    const rsrr_status e = rsrr_create(&w->c, device, w->st);
+    if (e) w->c = nullptr;
+    return e;
+}
+
+static void worker_free(Worker* w)
+{
+    if (w->c) rsrr_destroy(w->c);
+    if (w->q_buf) (void)hipFree(w->q_buf);
+    if (w->aq_buf) (void)hipFree(w->aq_buf);
+    if (w->v_buf) (void)hipFree(w->v_buf);
+    if (w->st) (void)hipStreamDestroy(w->st);
+    *w = Worker();
+}
+
+static void server_free(rsrr_server* s)
+{
+    (void)hipSetDevice(s->cfg.device);
+    worker_free(&s->ws);
+    for (auto& w : s->wp) worker_free(w.get());
+    if (s->arena_base) (void)hipFree(s->arena_base);
+    delete s;
+}
+
 extern "C" rsrr_status rsrr_server_create(rsrr_server** out, const rsrr_server_config* cfg)
 {
     if (!out) return -1;
-    if (!cfg || cfg->max_slots < 1 || cfg->arena_bytes == 0 || cfg->batch_bytes == 0 ||
-        (cfg->prec != RSRR_PREC_C128 && cfg->prec != RSRR_PREC_C64_IR))
+    if (!cfg || cfg->max_slots < 1 || cfg->arena_bytes == 0 || cfg->batch_bytes == 0 || cfg->solvers < 0 ||
+        cfg->solvers > 8 || (cfg->prec != RSRR_PREC_C128 && cfg->prec != RSRR_PREC_C64_IR))
         return -2;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess) return RSRR_EDEVICE;
     if (cfg->device < 0 || cfg->device >= ndev) return -2;
     RSRR_HIP(hipSetDevice(cfg->device));
-    std::unique_ptr<rsrr_server> s(new rsrr_server());
+    rsrr_server* s = new rsrr_server();
     s->cfg = *cfg;
+    if (s->cfg.solvers == 0) s->cfg.solvers = 2;
     s->t0 = std::chrono::steady_clock::now();
-    if (hipStreamCreateWithFlags(&s->st_s, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&s->st_p, hipStreamNonBlocking) != hipSuccess)
-        return RSRR_EDEVICE;
-    rsrr_status e = rsrr_create(&s->cs, cfg->device, s->st_s);
-    if (e) return e;
-    e = rsrr_create(&s->cp, cfg->device, s->st_p);
-    if (e) return e;
-    if (hipMalloc(&s->arena_base, cfg->arena_bytes) != hipSuccess) {
+    rsrr_status e = worker_init(&s->ws, cfg->device);
+    const int nsolve = (cfg->flags & RSRR_SERVE_SERIAL) ? 0 : s->cfg.solvers;
+    for (int i = 0; i < nsolve && !e; ++i) {
+        s->wp.emplace_back(new Worker());
+        e = worker_init(s->wp.back().get(), cfg->device);
+    }
+    if (!e && hipMalloc(&s->arena_base, cfg->arena_bytes) != hipSuccess) {
         (void)hipGetLastError();
-        rsrr_destroy(s->cs);
-        rsrr_destroy(s->cp);
-        return RSRR_ENOMEM;
+        s->arena_base = nullptr;
+        e = RSRR_ENOMEM;
+    }
+    if (e) {
+        server_free(s);
+        return e;
     }
     s->arena.init(cfg->arena_bytes);
-    rsrr_server* p = s.release();
-    p->th_s = std::thread(sampler_main, p);
-    if (!(cfg->flags & RSRR_SERVE_SERIAL)) p->th_p = std::thread(solver_main, p);
-    *out = p;
+    s->ws.th = std::thread(sampler_main, s);
+    for (auto& w : s->wp) w->th = std::thread(solver_main, s, w.get());
+    *out = s;
     return RSRR_OK;
 }
 
@@ -535,23 +574,15 @@ extern "C" rsrr_status rsrr_server_destroy(rsrr_server* s)
         s->cv_work.notify_all();
         s->cv_post.notify_all();
     }
-    // the sampler leaves once nothing is queued or admitted; the solver once it has also
-    // drained the sampled requests
-    if (s->th_s.joinable()) s->th_s.join();
+    // the sampler leaves once nothing is queued or admitted; the solve threads once they
+    // have also drained the sampled requests
+    if (s->ws.th.joinable()) s->ws.th.join();
     {
         std::lock_guard<std::mutex> lk(s->mu);
         s->cv_post.notify_all();
     }
-    if (s->th_p.joinable()) s->th_p.join();
-    (void)hipSetDevice(s->cfg.device);
-    rsrr_destroy(s->cs);
-    rsrr_destroy(s->cp);
-    if (s->arena_base) (void)hipFree(s->arena_base);
-    if (s->q_buf) (void)hipFree(s->q_buf);
-    if (s->aq_buf) (void)hipFree(s->aq_buf);
-    if (s->v_buf) (void)hipFree(s->v_buf);
-    (void)hipStreamDestroy(s->st_s);
-    (void)hipStreamDestroy(s->st_p);
-    delete s;
+    for (auto& w : s->wp)
+        if (w->th.joinable()) w->th.join();
+    server_free(s);
     return RSRR_OK;
 }

@@ -43,33 +43,54 @@ hipError_t eye(hipStream_t st, double2* X, int ldx, int r0, int p)
 }
 
 // ||T_b||_1 (largest column sum of |t_ij|) for a batch of n x n matrices.
-__global__ __launch_bounds__(256) void norm1_kernel(const double2* __restrict__ T, int ld, long sT, int n,
-                                                     double* __restrict__ out)
+// Pass 1: one wave per column (coalesced along the column), each workgroup of
+// four waves writes the largest of its four sums.  Pass 2: one workgroup per
+// matrix takes the maximum of those partial results.
+constexpr int N1_COLS = 4;
+
+__global__ __launch_bounds__(256) void norm1_cols_kernel(const double2* __restrict__ T, int ld, long sT, int n,
+                                                          double* __restrict__ part)
+{
+    __shared__ double red[N1_COLS];
+    const int b = blockIdx.y, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = blockIdx.x * N1_COLS + wave;
+    double s = 0.0;
+    if (j < n) {
+        const double2* col = T + b * sT + (long)j * ld;
+        for (int i = lane; i < n; i += 64) {
+            const double2 a = col[i];
+            s += sqrt(a.x * a.x + a.y * a.y);
+        }
+    }
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) red[wave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        part[(long)b * gridDim.x + blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+__global__ __launch_bounds__(256) void norm1_max_kernel(const double* __restrict__ part, int G,
+                                                         double* __restrict__ out)
 {
     __shared__ double red[4];
     const int b = blockIdx.x;
-    const double2* Tb = T + b * sT;
-    double best = 0.0;
-    for (int j = 0; j < n; ++j) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < n; i += 256) {
-            const double2 a = Tb[i + (long)j * ld];
-            s += sqrt(a.x * a.x + a.y * a.y);
-        }
-        for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) best = fmax(best, red[0] + red[1] + red[2] + red[3]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[b] = best;
+    double m = 0.0;
+    for (int g = threadIdx.x; g < G; g += 256) m = fmax(m, part[(long)b * G + g]);
+    for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) out[b] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
-hipError_t norm1(hipStream_t st, const double2* T, int ld, long sT, int n, double* out, int B)
+hipError_t norm1(hipStream_t st, const double2* T, int ld, long sT, int n, double* out, int B, double* part)
 {
-    hipLaunchKernelGGL(norm1_kernel, dim3(B), dim3(256), 0, st, T, ld, sT, n, out);
+    const int G = (n + N1_COLS - 1) / N1_COLS;
+    hipLaunchKernelGGL(norm1_cols_kernel, dim3(G, B), dim3(256), 0, st, T, ld, sT, n, part);
+    hipLaunchKernelGGL(norm1_max_kernel, dim3(B), dim3(256), 0, st, part, G, out);
     return hipGetLastError();
 }
+
+int norm1_parts(int n) { return (n + N1_COLS - 1) / N1_COLS; }
 
 // ---------------------------------------------------------------------------
 // Eigenpairs of a small general complex matrix (n x n, column-major, ld n):

@@ -74,7 +74,8 @@ class RsrrSolveInfo(C.Structure):
 
 class RsrrServerConfig(C.Structure):
     _fields_ = [("device", C.c_int), ("prec", C.c_int), ("max_slots", C.c_int), ("flags", C.c_int),
-                ("arena_bytes", C.c_ulonglong), ("batch_bytes", C.c_ulonglong)]
+                ("solvers", C.c_int), ("pad", C.c_int), ("arena_bytes", C.c_ulonglong),
+                ("batch_bytes", C.c_ulonglong)]
 
 
 class RsrrRequest(C.Structure):
@@ -402,10 +403,10 @@ class Server:
     buffer of a request alive until wait() has returned it."""
 
     def __init__(self, device=0, prec=RSRR_PREC_C64_IR, max_slots=8, arena_bytes=16 << 30,
-                 batch_bytes=24 << 30, flags=0):
+                 batch_bytes=24 << 30, flags=0, solvers=0):
         L = lib()
-        self.cfg = RsrrServerConfig(device, int(prec), int(max_slots), int(flags), int(arena_bytes),
-                                    int(batch_bytes))
+        self.cfg = RsrrServerConfig(device, int(prec), int(max_slots), int(flags), int(solvers), 0,
+                                    int(arena_bytes), int(batch_bytes))
         self.h = C.c_void_p()
         _check("rsrr_server_create", L.rsrr_server_create(C.byref(self.h), C.byref(self.cfg)))
         self._live = {}

@@ -67,14 +67,16 @@ def test_argument_errors_without_device(lib):
 
 def test_server_argument_errors_without_device(lib):
     from paper_1605_07951_amd import rsrr
-    cfg = rsrr.RsrrServerConfig(0, 1, 0, 0, 1 << 20, 1 << 20)  # max_slots = 0
+    cfg = rsrr.RsrrServerConfig(0, 1, 0, 0, 0, 0, 1 << 20, 1 << 20)  # max_slots = 0
     h = C.c_void_p()
     assert lib.rsrr_server_create(None, C.byref(cfg)) == -1
     assert lib.rsrr_server_create(C.byref(h), None) == -2
     assert lib.rsrr_server_create(C.byref(h), C.byref(cfg)) == -2
-    cfg = rsrr.RsrrServerConfig(0, 7, 1, 0, 1 << 20, 1 << 20)  # bad precision
+    cfg = rsrr.RsrrServerConfig(0, 7, 1, 0, 0, 0, 1 << 20, 1 << 20)  # bad precision
     assert lib.rsrr_server_create(C.byref(h), C.byref(cfg)) == -2
-    cfg = rsrr.RsrrServerConfig(0, 1, 1, 0, 0, 1 << 20)  # empty arena
+    cfg = rsrr.RsrrServerConfig(0, 1, 1, 0, 0, 0, 0, 1 << 20)  # empty arena
+    assert lib.rsrr_server_create(C.byref(h), C.byref(cfg)) == -2
+    cfg = rsrr.RsrrServerConfig(0, 1, 1, 0, 9, 0, 1 << 20, 1 << 20)  # too many solve threads
     assert lib.rsrr_server_create(C.byref(h), C.byref(cfg)) == -2
     rid = C.c_int(0)
     assert lib.rsrr_server_submit(None, None, C.byref(rid)) == -1

@@ -230,3 +230,44 @@ def cfg_batched_sizes(count=256, lo=64, hi=1024, seed=3000):
     """Per-instance sizes of the ragged batch: n ~ U{lo..hi} inclusive."""
     rng = np.random.default_rng(seed)
     return rng.integers(lo, hi + 1, size=count)
+
+
+DELAY_GRIDS = {512: (16, 32), 1024: (32, 32), 2048: (32, 64)}
+
+
+def cfg_serving_stream(count=2000, rate=20.0, seed=4000):
+    """Seeded request stream of the serving workload.
+
+    Poisson arrivals (rate per second), half delay NEPs (n in {512, 1024,
+    2048}, grids 16x32, 32x32, 32x64; N=48, L=32) and half Helmholtz sphere
+    NEPs (n in {2048, 4096, 8192}; N=64, L=64).  Contours are jittered by up to
+    +-10% around the delay parity circle (-4, 0.75) and the Helmholtz ellipse
+    (3.8; 1.4, 0.3).  Each entry: t (arrival, s), kind, n, grid, gamma, a, b,
+    N, L, seed (of its probes).  Draw order per request: kind, size, three
+    jitters; arrivals are drawn first for the whole stream.
+    """
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, count))
+    out = []
+    for i in range(count):
+        delay = rng.random() < 0.5
+        if delay:
+            n = int(rng.choice([512, 1024, 2048]))
+            j = rng.uniform(-0.1, 0.1, 3)
+            out.append({"t": float(t[i]), "kind": "delay", "n": n, "grid": DELAY_GRIDS[n],
+                        "gamma": -4.0 * (1 + j[0]) + 0j, "a": 0.75 * (1 + j[1]), "b": 0.75 * (1 + j[1]),
+                        "N": 48, "L": 32, "seed": seed + 1 + i})
+        else:
+            n = int(rng.choice([2048, 4096, 8192]))
+            j = rng.uniform(-0.1, 0.1, 3)
+            out.append({"t": float(t[i]), "kind": "helmholtz", "n": n, "grid": None,
+                        "gamma": 3.8 * (1 + j[0]) + 0j, "a": 1.4 * (1 + j[1]), "b": 0.3 * (1 + j[2]),
+                        "N": 64, "L": 64, "seed": seed + 1 + i})
+    return out
+
+
+def serving_nep(req):
+    """The NEP of one serving-stream entry."""
+    if req["kind"] == "delay":
+        return delay_laplacian(*req["grid"])
+    return helmholtz_sphere(req["n"])
