@@ -299,7 +299,8 @@ extern "C" rsrr_status rsrr_sample_batched(rsrr_ctx* c, int count, const rsrr_in
         b.sP = P;
         b.sPerm = (long)npan * 2 * MAX_NB;
         b.sTP = 8L * 2 * MAX_NB;
-        b.sInv = mixed ? (long)npan * 2 * nbmax * nbmax : 0;
+        // ceil(P/nb) panels of 2 nb^2 for any nb <= nbmax: at most 2 nbmax (P + nbmax)
+        b.sInv = mixed ? 2L * nbmax * (P + nbmax) : 0;
         b.sTmp = mixed ? (long)nbmax * std::max(P, Lmax) : 0;
         const size_t esz = mixed ? 8 : 16;
         long nparts_max = ((long)maxn * maxn + 255) / 256;

@@ -13,7 +13,10 @@ namespace rsrr {
 constexpr int MAX_NB = 128;
 template <typename R> constexpr int max_panel() { return sizeof(R) == 4 ? 128 : 64; }
 // Panel slots of the per-matrix permutation store (enough for the narrowest panel, 64).
-inline int perm_panels(int n) { return (n + 63) / 64; }
+// Panel widths of the LU are at least MIN_NB columns; storage per panel is
+// sized for that many panels.
+constexpr int MIN_NB = 32;
+inline int perm_panels(int n) { return (n + MIN_NB - 1) / MIN_NB; }
 
 // C = beta*C + alpha*A*B, complex single on v_mfma_f32_32x32x2f32.
 // tag 1 launches a separately named instance (the LU trailing update).

@@ -493,6 +493,7 @@ hipError_t getrf_batched(hipStream_t st, typename cpx<R>::T* A, long sA, int lda
     typedef typename cpx<R>::T C;
     constexpr bool use_inv = sizeof(R) == 4;
     if (nb > max_panel<R>()) nb = max_panel<R>();
+    if (nb < MIN_NB) nb = MIN_NB;  // perm/inv storage holds perm_panels(n) panels
     UpdateRecorder* rec = w.rec;
     for (int c0 = 0; c0 < n; c0 += nb) {
         const int jb = (n - c0 < nb) ? n - c0 : nb;
@@ -542,6 +543,7 @@ hipError_t getrs_batched(hipStream_t st, const typename cpx<R>::T* LU, long sLU,
     typedef typename cpx<R>::T C;
     constexpr bool use_inv = sizeof(R) == 4;
     if (nb > max_panel<R>()) nb = max_panel<R>();
+    if (nb < MIN_NB) nb = MIN_NB;
     const int np = (n + nb - 1) / nb;
     for (int p = 0; p < np; ++p) {
         const int c0 = p * nb, jb = (n - c0 < nb) ? n - c0 : nb;

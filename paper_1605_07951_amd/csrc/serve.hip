@@ -119,11 +119,11 @@ bool is_error(rsrr_status s) { return s < 0 || s == RSRR_ENOMEM || s == RSRR_EDE
 size_t point_bytes(int n, int L, bool mixed)
 {
     const size_t P = (size_t)(n + 63) / 64 * 64;
-    const size_t npan = (P + 63) / 64;
+    const size_t npan = (size_t)perm_panels((int)P);
     size_t b = P * P * (mixed ? 8 + 16 : 16 + 16);           // T and its FP64 copy
     b += P * (size_t)L * (3 * 16 + 8) + P * 4;               // U, X, R, narrow RHS, pivots
     b += npan * 2 * MAX_NB * 8 + 8 * 2 * MAX_NB * 8;         // permutations
-    if (mixed) b += npan * 2 * MAX_NB * MAX_NB * 8 + MAX_NB * std::max(P, (size_t)L) * 8;  // inverses, scratch
+    if (mixed) b += 2 * MAX_NB * (P + MAX_NB) * 8 + MAX_NB * std::max(P, (size_t)L) * 8;  // inverses, scratch
     b += (P * P + 255) / 256 * 8 + (size_t)L * 6 * 8 + 64;   // norms and refinement state
     return b;
 }

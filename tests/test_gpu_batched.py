@@ -45,6 +45,9 @@ def _check(R, items, hosts, infos, tol=1e-10):
             X = S[:, k * L:(k + 1) * L]
             assert np.linalg.norm(X - Xo) <= tol * np.linalg.norm(Xo), (nep.n, k)
             assert inf[k]["resid"] <= 1e-10
+            # these points are well conditioned: the factorisation itself must be right
+            # (a redo on the FP64 path would hide a wrong LU)
+            assert inf[k]["fallback"] == 0 and inf[k]["info"] == 0, (nep.n, k, inf[k])
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -102,4 +105,19 @@ def test_batched_matches_single_instance_calls(R):
     torch.cuda.synchronize()
     for it, m in zip(items, mixed):
         assert torch.equal(it.S, m)
+    ctx.close()
+
+
+@pytest.mark.parametrize("nb", [32, 64, 128])
+def test_batched_every_panel_width(R, tmp_path, monkeypatch, nb):
+    """Each panel width the autotuner may pick, forced through the cache file, on buckets whose
+    size is and is not a multiple of it (P = 128, 192, 256, 320)."""
+    f = tmp_path / "tune.txt"
+    f.write_text("".join(f"{P * 2 + 1} {nb}\n" for P in (128, 192, 256, 320)))
+    monkeypatch.setenv("RSRR_TUNE_FILE", str(f))
+    ctx = R.rsrr_create(0)
+    items, hosts = _items(R, [100, 150, 250, 300], N=4, L=3, seed=7000 + nb)
+    infos, code = R.rsrr_sample_batched(ctx, items, prec=1)
+    assert code == R.RSRR_OK
+    _check(R, items, hosts, infos)
     ctx.close()
