@@ -12,6 +12,8 @@
  *   rsrr_project  Step 4, first half / eq. Ts-NEP: T_Q(z) = Q^H T(z) Q
  *   rsrr_solve    Step 4, second half, and Step 5: SS-FULL (Sec. 3.3) on the
  *                 projected NEP, lift v = Q g, residuals
+ *   rsrr_two_stage        the two-stage strategy of Sec. 5.2-5.3: stage-1
+ *                 eigenvalue estimates become extra sampling points
  *   rsrr_sample_batched   Step 2 for a ragged batch of NEP instances
  *   rsrr_server_* a request loop that runs all of the above for many NEPs at
  *                 once (continuous batching of their sampling points)
@@ -241,6 +243,35 @@ enum {
  * -4 prec. */
 RSRR_API rsrr_status rsrr_sample_batched(rsrr_ctx *ctx, int count, const rsrr_instance *inst, int prec, int flags,
                                          rsrr_point_info *info);
+
+/* Diagnostics of rsrr_two_stage. */
+typedef struct {
+    int k1, count1, nbar1;   /* stage 1: rank of S, eigenvalues returned, SS-FULL count   */
+    int n_new;               /* distinct stage-1 estimates inside C, sampled in stage 2   */
+    int k2, nbar2;           /* stage 2: rank of S, SS-FULL count                         */
+    double resid1_max;       /* largest stage-1 eigen-residual inside C                   */
+} rsrr_two_stage_info;
+
+/* Two-stage sampling (Sec. 5.2, Example 2; Sec. 5.3).  Stage 1: RSRR (Steps
+ * 2-5) with N1 points on the ellipse (gamma, a, b).  The distinct stage-1
+ * eigenvalue estimates inside the ellipse (elliptic level < 1; estimates within
+ * 1e-6 max(1, |lambda|) of an earlier one are dropped; at most max_new) become
+ * extra sampling points: their blocks T(z)^-1 U are appended to S after the N1
+ * stage-1 blocks, which are reused, and Steps 3-5 run again on all
+ * (N1 + n_new) L columns.
+ * S: device, n x (N1 + max_new) L, lds >= n (caller-owned; normalised in place).
+ * z_new: host, 2 max_new doubles (the points added).  The outputs lambda,
+ * V (device, required: the residuals need it), resid and count are those of
+ * rsrr_solve for stage 2; tinfo (host, may be NULL) gets both stages' figures.
+ * Errors: -2 nep, -3 gamma NULL, -4 a, -5 b, -6 N1, -7 U, -8 L, -9 ldu,
+ * -10 prec, -11 S, -12 lds, -13 max_new < 0, -14 delta, -15 NQ/KQ,
+ * -17 tol_gap, -18 max_eigs, -19 lambda, -20 V, -21 ldv, -22 resid,
+ * -23 count, -24 z_new NULL with max_new > 0. */
+RSRR_API rsrr_status rsrr_two_stage(rsrr_ctx *ctx, const rsrr_nep *nep, const double *gamma, double a, double b,
+                                    int N1, const double *U, int L, int ldu, int prec, double *S, int lds,
+                                    int max_new, double delta, int NQ, int KQ, double tol_gap, int max_eigs,
+                                    double *lambda, double *V, int ldv, double *resid, int *count, double *z_new,
+                                    rsrr_two_stage_info *tinfo);
 
 /* ---------------------------------------------------------------------------
  * Serving: a request loop for many NEP solves on one device.

@@ -26,6 +26,11 @@ Steps and the passages they follow
                        eq. HH, truncated SVD eq. svdH with the gap rule eq. gap,
                        the reduced matrix eq. A and the lift eq. eigens.
 * ``rsrr``             the five steps of Sec. 4.3 chained together.
+* ``two_stage``        the two-stage strategy of Sec. 5.2 (Example 2) and
+                       Sec. 5.3: RSRR on a few contour points, then the
+                       distinct eigenvalue estimates inside the contour become
+                       extra sampling points; the first-stage columns of S are
+                       kept and RSRR runs again on all of them.
 * ``residual``         the relative residual of an eigenpair (Sec. 3.3 and
                        Sec. 5.1: ||T(lambda) v||_2 / ||v||_2), here further
                        divided by ||T(lambda)||_1.
@@ -347,3 +352,27 @@ def rsrr(prob, contour, U, delta=1e-14, NQ=500, KQ=2, tol_gap=1e3, S=None):
     res = np.array([residual(prob, l, V[:, i]) for i, l in enumerate(ss["lam"])])
     return {"lam": ss["lam"], "V": V, "level": level(ss["lam"], contour.gamma, contour.a, contour.b),
             "res": res, "k": k, "sigma_S": sigS, "ss": ss, "z": z, "S": S, "Q": Q}
+
+
+def distinct_inside(lam, gamma, a, b, rel=1e-6):
+    """Eigenvalue estimates inside the ellipse (level < 1), in the given order, without
+    those closer than rel*max(1, |lambda|) to one already taken (reading: the paper
+    keeps the mutually different estimates)."""
+    out = []
+    for l in lam[level(lam, gamma, a, b) < 1]:
+        if all(abs(l - m) > rel * max(1.0, abs(l)) for m in out):
+            out.append(l)
+    return np.array(out, dtype=np.complex128)
+
+
+def two_stage(prob, contour, U, delta=1e-14, NQ=500, KQ=2, tol_gap=1e3):
+    """Two-stage RSRR (Sec. 5.2, Example 2; Sec. 5.3): stage 1 on contour.N points,
+    stage 2 with the stage-1 estimates inside the contour appended as sampling points
+    (their T(z)^-1 U appended to the stage-1 S, which is reused)."""
+    r1 = rsrr(prob, contour, U, delta=delta, NQ=NQ, KQ=KQ, tol_gap=tol_gap)
+    znew = distinct_inside(r1["lam"], contour.gamma, contour.a, contour.b)
+    S2 = np.hstack([r1["S"], sample(prob, znew, U)]) if znew.size else r1["S"]
+    r2 = rsrr(prob, contour, U, delta=delta, NQ=NQ, KQ=KQ, tol_gap=tol_gap, S=S2)
+    r2["z"] = np.concatenate([r1["z"], znew])
+    return r1, r2, znew
+

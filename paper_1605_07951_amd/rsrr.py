@@ -38,7 +38,7 @@ STATUS_NAMES = {0: "OK", 1: "ESINGULAR", 2: "WARN_FALLBACK", 3: "WARN_GAP", 4: "
 
 EXPORTS = ["rsrr_create", "rsrr_destroy", "rsrr_contour", "rsrr_sample", "rsrr_sample_batched", "rsrr_basis",
            "rsrr_project", "rsrr_solve", "rsrr_last_timings", "rsrr_update_stats", "rsrr_version",
-           "rsrr_server_create", "rsrr_server_submit", "rsrr_server_wait", "rsrr_server_stats",
+           "rsrr_two_stage", "rsrr_server_create", "rsrr_server_submit", "rsrr_server_wait", "rsrr_server_stats",
            "rsrr_server_destroy"]
 RSRR_BATCH_GRAPH = 1
 RSRR_BATCH_AUTOTUNE = 2
@@ -70,6 +70,11 @@ class RsrrPointInfo(C.Structure):
 class RsrrSolveInfo(C.Structure):
     _fields_ = [("nbar", C.c_int), ("warn_gap", C.c_int), ("gmax", C.c_double), ("n_sigma", C.c_int),
                 ("pad", C.c_int)]
+
+
+class RsrrTwoStageInfo(C.Structure):
+    _fields_ = [("k1", C.c_int), ("count1", C.c_int), ("nbar1", C.c_int), ("n_new", C.c_int), ("k2", C.c_int),
+                ("nbar2", C.c_int), ("resid1_max", C.c_double)]
 
 
 class RsrrServerConfig(C.Structure):
@@ -130,6 +135,9 @@ def lib():
                              ip, dp, C.POINTER(RsrrSolveInfo)]
     L.rsrr_last_timings.argtypes = [vp, dp]
     L.rsrr_update_stats.argtypes = [vp, C.c_int, C.c_int, dp]
+    L.rsrr_two_stage.argtypes = [vp, C.POINTER(RsrrNep), dp, C.c_double, C.c_double, C.c_int, vp, C.c_int, C.c_int,
+                                 C.c_int, vp, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, C.c_double, C.c_int,
+                                 dp, vp, C.c_int, dp, ip, dp, C.POINTER(RsrrTwoStageInfo)]
     L.rsrr_server_create.argtypes = [C.POINTER(vp), C.POINTER(RsrrServerConfig)]
     L.rsrr_server_submit.argtypes = [vp, C.POINTER(RsrrRequest), ip]
     L.rsrr_server_wait.argtypes = [vp, C.c_int, C.c_double, C.POINTER(RsrrResult)]
@@ -388,6 +396,37 @@ def rsrr_solve(ctx, dnep, Q, k, AQ, terms, gamma, a, b, NQ=500, KQ=2, tol_gap=1e
     return {"lam": lam_np, "V": from_colmajor(V[:m], n), "resid": np.frombuffer(res, dtype=np.float64)[:m].copy(),
             "nbar": sinfo.nbar, "warn_gap": bool(sinfo.warn_gap), "gmax": sinfo.gmax,
             "sigma_H": np.frombuffer(sigH, dtype=np.float64)[:sinfo.n_sigma].copy(), "status": code}
+
+
+def rsrr_two_stage(ctx, dnep, gamma, a, b, N1, U, prec=RSRR_PREC_C64_IR, max_new=64, delta=1e-14, NQ=500, KQ=2,
+                   tol_gap=1e3, max_eigs=256, ok=(RSRR_OK, RSRR_WARN_FALLBACK, RSRR_WARN_GAP)):
+    """Two-stage sampling.  Returns dict with the stage-2 lam, V (host), resid, the added points z_new,
+    the stage figures (k1, count1, nbar1, n_new, k2, nbar2, resid1_max) and the status."""
+    torch = _torch()
+    n = dnep.n
+    if not torch.is_tensor(U):
+        U, _ = colmajor(U)
+    L = U.shape[0]
+    S = torch.empty(((N1 + max_new) * L, n), dtype=torch.complex128, device=U.device)
+    V = torch.zeros((max_eigs, n), dtype=torch.complex128, device=U.device)
+    lam = (C.c_double * (2 * max_eigs))()
+    res = (C.c_double * max_eigs)()
+    zn = (C.c_double * (2 * max(1, max_new)))()
+    cnt = C.c_int(0)
+    ti = RsrrTwoStageInfo()
+    g = (C.c_double * 2)(complex(gamma).real, complex(gamma).imag)
+    code = lib().rsrr_two_stage(ctx.h, C.byref(dnep.desc), g, float(a), float(b), int(N1), U.data_ptr(), L, U.shape[1],
+                                int(prec), S.data_ptr(), n, int(max_new), float(delta), int(NQ), int(KQ),
+                                float(tol_gap), int(max_eigs), lam, V.data_ptr(), n, res, C.byref(cnt), zn,
+                                C.byref(ti))
+    _check("rsrr_two_stage", code, ok)
+    m = cnt.value
+    out = {f: getattr(ti, f) for f, _ in RsrrTwoStageInfo._fields_}
+    out.update({"lam": np.frombuffer(lam, dtype=np.float64).view(np.complex128)[:m].copy(),
+                "V": from_colmajor(V[:m], n), "resid": np.frombuffer(res, dtype=np.float64)[:m].copy(),
+                "z_new": np.frombuffer(zn, dtype=np.float64).view(np.complex128)[:ti.n_new].copy(),
+                "status": code})
+    return out
 
 
 def rsrr_version():

@@ -302,3 +302,28 @@ def test_planted_slips_are_caught(monkeypatch):
     monkeypatch.undo()
     bad = res["lam"]
     assert bad.size == 0 or _match(bad, lam) > 1e-6 or res["warn_gap"]
+
+
+def test_distinct_inside_keeps_first_of_close_estimates():
+    lam = np.array([1.0 + 0.1j, 1.0 + 0.1j + 5e-7, 3.0 + 0j, 0.2 - 0.05j, 1.0 + 0.1j + 2e-6])
+    got = O.distinct_inside(lam, 1.0 + 0j, 1.5, 0.5)  # 3.0 lies outside (level 1.78)
+    assert np.allclose(got, [1.0 + 0.1j, 0.2 - 0.05j, 1.0 + 0.1j + 2e-6])
+
+
+def test_two_stage_points_at_estimates_sharpen_the_eigenvalues():
+    """Sec. 5.2-5.3: stage 1 on six contour points is rough; adding its estimates inside as
+    sampling points gives every eigenvalue inside to 1e-9 of the closed form and cuts the
+    eigen-residuals by orders of magnitude."""
+    nep, C, U = W.cfg_qep(n=60, N=6, L=4)
+    prob = O.Problem(nep)
+    ex = P.qep_roots(nep.extra["c"], nep.extra["k"])
+    r1, r2, znew = O.two_stage(prob, C, U, NQ=300)
+    exin = ex[O.level(ex, C.gamma, C.a, C.b) < 0.98]
+    in1, in2 = r1["level"] < 0.98, r2["level"] < 0.98
+    assert exin.size == 5 and in2.sum() == 5
+    assert _match(r1["lam"][in1], ex) > 1e-3              # stage 1 is rough
+    assert _match(r2["lam"][in2], ex) < 1e-9 and _match(exin, r2["lam"]) < 1e-9
+    assert r2["res"][in2].max() < 1e-4 * r1["res"][in1].max()
+    # the new points are the stage-1 estimates inside, and S keeps the stage-1 columns
+    assert znew.size == np.sum(r1["level"] < 1)
+    assert np.array_equal(r2["S"][:, :C.N * 4], r1["S"])
