@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="helmholtz", choices=["helmholtz", "delay", "qep", "serve", "batched", "adaptive"])
+    ap.add_argument("--workload", default="helmholtz", choices=["helmholtz", "delay", "qep", "serve", "batched", "adaptive", "moments"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--N", type=int, default=None)
     ap.add_argument("--L", type=int, default=None)
@@ -55,6 +55,7 @@ def parse():
                     help="run one plain 1 GiB device copy before the timed region (counter calibration)")
     ap.add_argument("--instances", type=int, default=256, help="batched: QEP instances")
     ap.add_argument("--n1", type=int, default=6, help="adaptive: stage-1 contour points")
+    ap.add_argument("--K", type=str, default="4,16", help="moments: moment counts K to compare")
     ap.add_argument("--requests", type=int, default=24, help="serve: requests taken from the stream")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: Poisson arrival rate (1/s)")
     ap.add_argument("--slots", type=int, default=8, help="serve: requests admitted at once")
@@ -365,6 +366,65 @@ def run_adaptive(args):
     }
     print(json.dumps(res), flush=True)
 
+
+def run_moments(args):
+    """Sampling scheme vs moment scheme on the same S (Helmholtz sphere n=4096, N=64, L=64):
+    M = S Z for several K, then Steps 3-5 on S and on each M; reports the rank kept, the
+    eigen-residuals inside the contour and the time of M = S Z (one batched FP64 GEMM)."""
+    import torch
+    import workloads as W
+    from paper_1605_07951_amd import rsrr as R
+
+    n = args.n or 4096
+    nep, C, U_host = W.cfg_helmholtz(n=n, N=args.N or 64, L=args.L or 64)
+    dnep = R.DeviceNEP(nep)
+    U, _ = R.colmajor(U_host)
+    L, N = U_host.shape[1], C.N
+    ctx = R.rsrr_create(0)
+    z, _ = R.rsrr_contour(C.gamma, C.a, C.b, N)
+    S, _, _ = R.rsrr_sample(ctx, dnep, z, U)
+    rho = max(C.a, C.b)
+    cap = (C.a + C.b) / (2 * rho)
+
+    def steps(X):
+        t0 = time.perf_counter()
+        Q, k, sig = R.rsrr_basis(ctx, X.clone(), n, 1e-14)
+        AQ, terms = R.rsrr_project(ctx, dnep, Q, k, C.gamma, rho)
+        out = R.rsrr_solve(ctx, dnep, Q, k, AQ, terms, C.gamma, C.a, C.b)
+        torch.cuda.synchronize()
+        d = out["lam"] - complex(C.gamma)
+        ins = (d.real / C.a) ** 2 + (d.imag / C.b) ** 2 < 1
+        return {"k": k, "eigs_inside": int(ins.sum()),
+                "resid_max_inside": float(out["resid"][ins].max()) if ins.any() else None,
+                "sigma_ratio_at_64": float(sig[min(63, sig.size - 1)] / sig[0]),
+                "steps_3_5_s": round(time.perf_counter() - t0, 3)}
+
+    res_s = steps(S)
+    rows = {}
+    for K in [int(x) for x in args.K.split(",")]:
+        K = min(K, N)
+        R.rsrr_moments(ctx, S, n, z, L, K, C.gamma, rho, cap)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        M = R.rsrr_moments(ctx, S, n, z, L, K, C.gamma, rho, cap)
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - t0
+        r = steps(M)
+        r["moments_ms"] = round(1e3 * tm, 3)
+        r["moments_tflops"] = round(8.0 * n * N * K * L / tm / 1e12, 3)
+        rows[f"K={K}"] = r
+    res = {
+        "metric": METRIC, "value": None, "unit": "resolvent solves/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic (seeded Fibonacci-sphere Helmholtz single-layer NEP, complex Gaussian probes)",
+        "config": {"workload": f"sampling vs moment scheme on one S: helmholtz_sphere n={n} N={N} L={L}",
+                   "step": "M = S Z and Steps 3-5 on S and on M"},
+        "roofline": None,
+        "sampling_scheme": res_s,
+        "moment_scheme": rows,
+    }
+    print(json.dumps(res), flush=True)
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -379,6 +439,9 @@ def main():
         return
     if args.workload == "adaptive":
         run_adaptive(args)
+        return
+    if args.workload == "moments":
+        run_moments(args)
         return
     import torch
     from paper_1605_07951_amd import rsrr as R

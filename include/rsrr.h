@@ -12,6 +12,7 @@
  *   rsrr_project  Step 4, first half / eq. Ts-NEP: T_Q(z) = Q^H T(z) Q
  *   rsrr_solve    Step 4, second half, and Step 5: SS-FULL (Sec. 3.3) on the
  *                 projected NEP, lift v = Q g, residuals
+ *   rsrr_moments  the moment matrix M = S Z of the moment scheme (Sec. 4.1)
  *   rsrr_two_stage        the two-stage strategy of Sec. 5.2-5.3: stage-1
  *                 eigenvalue estimates become extra sampling points
  *   rsrr_sample_batched   Step 2 for a ragged batch of NEP instances
@@ -243,6 +244,22 @@ enum {
  * -4 prec. */
 RSRR_API rsrr_status rsrr_sample_batched(rsrr_ctx *ctx, int count, const rsrr_instance *inst, int prec, int flags,
                                          rsrr_point_info *info);
+
+/* Moment matrix of the resolvent moment scheme (Sec. 4.1, eq. Malpha,
+ * eq. M-pr) from the sampling matrix: M = S Z (eq. MS), i.e.
+ * M_alpha = sum_i omega_i zeta_i^alpha X_i for alpha = 0 .. K-1, where X_i is
+ * block i of S (columns i L .. i L + L - 1), zeta_i = (z_i - gamma)/rho and
+ * omega_i = 1 / prod_{j != i} ((zeta_i - zeta_j)/C) are the barycentric
+ * weights (eq. bary-wt) with every factor divided by the capacity C
+ * (Sec. 3.4; for an ellipse of semi-axes a, b and rho = max(a, b):
+ * C = (a + b) / (2 rho)).  Block alpha of M is columns alpha L .. alpha L + L - 1.
+ * S: device, n x N L, lds; z: host, 2N doubles (the points of S's blocks);
+ * gamma: host, 2 doubles; M: device, n x K L, ldm (caller-owned).  The moment
+ * variant of SS-RR runs rsrr_basis, rsrr_project and rsrr_solve on M.
+ * Errors: -2 n, -3 N, -4 L, -5 S, -6 lds, -7 z NULL or two equal points,
+ * -8 gamma, -9 rho, -10 capacity, -11 K not in [1, N], -12 M, -13 ldm. */
+RSRR_API rsrr_status rsrr_moments(rsrr_ctx *ctx, int n, int N, int L, const double *S, int lds, const double *z,
+                                  const double *gamma, double rho, double capacity, int K, double *M, int ldm);
 
 /* Diagnostics of rsrr_two_stage. */
 typedef struct {

@@ -26,6 +26,16 @@ Steps and the passages they follow
                        eq. HH, truncated SVD eq. svdH with the gap rule eq. gap,
                        the reduced matrix eq. A and the lift eq. eigens.
 * ``rsrr``             the five steps of Sec. 4.3 chained together.
+* ``barycentric_weights``, ``chebyshev_points``, ``chebyshev_weights``
+                       eq. bary-wt (with each factor divided by a capacity C, the
+                       scaling Sec. 3.4 suggests against under- and overflow),
+                       eq. Chebyshev-pts and eq. Chebyshev-wts.
+* ``moments``          the resolvent moment scheme, Sec. 4.1: M_alpha =
+                       sum_i omega_i zeta_i^alpha T(z_i)^-1 U (eq. Malpha) for
+                       alpha < K, collected as M = [M_0 ... M_{K-1}] (eq. M-pr),
+                       i.e. M = S Z (eq. MS).
+* ``rsrr_moment``      SS-RR with M in place of S (the variant Sec. 4.3 describes
+                       in its closing remark).
 * ``two_stage``        the two-stage strategy of Sec. 5.2 (Example 2) and
                        Sec. 5.3: RSRR on a few contour points, then the
                        distinct eigenvalue estimates inside the contour become
@@ -375,4 +385,57 @@ def two_stage(prob, contour, U, delta=1e-14, NQ=500, KQ=2, tol_gap=1e3):
     r2 = rsrr(prob, contour, U, delta=delta, NQ=NQ, KQ=KQ, tol_gap=tol_gap, S=S2)
     r2["z"] = np.concatenate([r1["z"], znew])
     return r1, r2, znew
+
+
+# ---------------------------------------------------------------------------
+# Interpolation weights and the moment scheme
+# ---------------------------------------------------------------------------
+
+def barycentric_weights(z, capacity=1.0):
+    """omega_i = 1 / prod_{j != i} ((z_i - z_j) / C) (eq. bary-wt with every factor scaled by
+    1/C), the product taken as a sum of logarithms."""
+    z = np.asarray(z, dtype=np.complex128)
+    w = np.empty(z.size, dtype=np.complex128)
+    for i in range(z.size):
+        d = np.delete(z[i] - z, i) / capacity
+        w[i] = np.exp(-np.sum(np.log(d)))
+    return w
+
+
+def chebyshev_points(N):
+    """Chebyshev points of the first kind on [-1, 1] (eq. Chebyshev-pts)."""
+    i = np.arange(N)
+    return np.cos((2 * i + 1) * np.pi / (2 * N))
+
+
+def chebyshev_weights(N):
+    """Their simplified barycentric weights (eq. Chebyshev-wts)."""
+    i = np.arange(N)
+    return (-1.0) ** i * np.sin((2 * i + 1) * np.pi / (2 * N))
+
+
+def moments(S, z, L, K, gamma, rho, capacity):
+    """M = [M_0 ... M_{K-1}], M_alpha = sum_i omega_i zeta_i^alpha X_i with X_i the i-th block
+    of S, zeta = (z - gamma)/rho and omega the barycentric weights of the zeta_i
+    (eq. Malpha, eq. M-pr; reading: the shifted and scaled variable as for SS-FULL)."""
+    zeta = (np.asarray(z) - gamma) / rho
+    w = barycentric_weights(zeta, capacity)
+    n = S.shape[0]
+    M = np.zeros((n, K * L), dtype=np.complex128)
+    for a in range(K):
+        for i, zi in enumerate(zeta):
+            M[:, a * L:(a + 1) * L] += w[i] * zi ** a * S[:, i * L:(i + 1) * L]
+    return M
+
+
+def rsrr_moment(prob, contour, U, K, delta=1e-14, NQ=500, KQ=2, tol_gap=1e3):
+    """SS-RR with the moment matrix M in place of S (Steps 3-5 on M)."""
+    z, _ = ellipse(contour.gamma, contour.a, contour.b, contour.N)
+    S = sample(prob, z, U)
+    rho = max(contour.a, contour.b)
+    M = moments(S, z, U.shape[1], K, contour.gamma, rho, (contour.a + contour.b) / (2 * rho))
+    r = rsrr(prob, contour, U, delta=delta, NQ=NQ, KQ=KQ, tol_gap=tol_gap, S=M)
+    r["M"] = M
+    r["S_sampled"] = S
+    return r
 

@@ -38,7 +38,7 @@ STATUS_NAMES = {0: "OK", 1: "ESINGULAR", 2: "WARN_FALLBACK", 3: "WARN_GAP", 4: "
 
 EXPORTS = ["rsrr_create", "rsrr_destroy", "rsrr_contour", "rsrr_sample", "rsrr_sample_batched", "rsrr_basis",
            "rsrr_project", "rsrr_solve", "rsrr_last_timings", "rsrr_update_stats", "rsrr_version",
-           "rsrr_two_stage", "rsrr_server_create", "rsrr_server_submit", "rsrr_server_wait", "rsrr_server_stats",
+           "rsrr_two_stage", "rsrr_moments", "rsrr_server_create", "rsrr_server_submit", "rsrr_server_wait", "rsrr_server_stats",
            "rsrr_server_destroy"]
 RSRR_BATCH_GRAPH = 1
 RSRR_BATCH_AUTOTUNE = 2
@@ -138,6 +138,8 @@ def lib():
     L.rsrr_two_stage.argtypes = [vp, C.POINTER(RsrrNep), dp, C.c_double, C.c_double, C.c_int, vp, C.c_int, C.c_int,
                                  C.c_int, vp, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, C.c_double, C.c_int,
                                  dp, vp, C.c_int, dp, ip, dp, C.POINTER(RsrrTwoStageInfo)]
+    L.rsrr_moments.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp, C.c_int, dp, dp, C.c_double, C.c_double, C.c_int,
+                               vp, C.c_int]
     L.rsrr_server_create.argtypes = [C.POINTER(vp), C.POINTER(RsrrServerConfig)]
     L.rsrr_server_submit.argtypes = [vp, C.POINTER(RsrrRequest), ip]
     L.rsrr_server_wait.argtypes = [vp, C.c_int, C.c_double, C.POINTER(RsrrResult)]
@@ -427,6 +429,19 @@ def rsrr_two_stage(ctx, dnep, gamma, a, b, N1, U, prec=RSRR_PREC_C64_IR, max_new
                 "z_new": np.frombuffer(zn, dtype=np.float64).view(np.complex128)[:ti.n_new].copy(),
                 "status": code})
     return out
+
+
+def rsrr_moments(ctx, S, n, z, L, K, gamma, rho, capacity):
+    """M = S Z of the moment scheme.  S: device tensor (N*L, n); z: the N points of its blocks.
+    Returns the device tensor (K*L, n) holding M column-major."""
+    torch = _torch()
+    zc, zp = _zbuf(z)
+    N = zc.size
+    M = torch.empty((K * L, n), dtype=torch.complex128, device=S.device)
+    g = (C.c_double * 2)(complex(gamma).real, complex(gamma).imag)
+    _check("rsrr_moments", lib().rsrr_moments(ctx.h, n, N, L, S.data_ptr(), S.shape[1], zp, g, float(rho),
+                                              float(capacity), int(K), M.data_ptr(), n))
+    return M
 
 
 def rsrr_version():

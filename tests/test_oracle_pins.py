@@ -327,3 +327,44 @@ def test_two_stage_points_at_estimates_sharpen_the_eigenvalues():
     # the new points are the stage-1 estimates inside, and S keeps the stage-1 columns
     assert znew.size == np.sum(r1["level"] < 1)
     assert np.array_equal(r2["S"][:, :C.N * 4], r1["S"])
+
+
+def test_barycentric_weights_take_leading_coefficients():
+    """eq. bary-wt / eq. fa1: sum_i omega_i p(z_i) is the leading coefficient of the degree N-1
+    interpolant, so sum_i omega_i z_i^a = 0 for a < N-1 and 1 for a = N-1; scaling every
+    factor by 1/C multiplies the weights by C^(N-1)."""
+    rng = np.random.default_rng(0)
+    z = rng.standard_normal(9) + 1j * rng.standard_normal(9)
+    w = O.barycentric_weights(z)
+    for a in range(8):
+        assert abs(np.sum(w * z ** a)) < 1e-12
+    assert abs(np.sum(w * z ** 8) - 1) < 1e-12
+    wc = O.barycentric_weights(z, capacity=2.5)
+    assert np.allclose(wc, w * 2.5 ** 8, rtol=1e-12)
+
+
+def test_chebyshev_weights_are_the_simplified_barycentric_weights():
+    for N in (5, 12, 40):
+        r = O.barycentric_weights(O.chebyshev_points(N)) / O.chebyshev_weights(N)
+        assert np.allclose(r, r[0], rtol=1e-11)
+
+
+def test_moment_scheme_span_and_robustness():
+    """M = S Z (eq. MS) lies in span(S) (eq. ms).  With K L = 128 columns the moment scheme
+    finds the QEP roots inside; with K = 4 (64 columns for 32 eigenvalues) it does not,
+    while the sampling scheme on the same S does (the paper's robustness argument)."""
+    nep, C, U = W.cfg_qep(n=200, N=32, L=16)
+    prob = O.Problem(nep)
+    ex = P.qep_roots(nep.extra["c"], nep.extra["k"])
+    rm = O.rsrr_moment(prob, C, U, K=8, NQ=300)
+    M, S = rm["M"], rm["S_sampled"]
+    Qs, _, ks = O.basis(O.normalize(S), 1e-14)
+    assert np.linalg.norm(M - Qs @ (Qs.conj().T @ M)) <= 1e-10 * np.linalg.norm(M)
+    ins = rm["level"] < 0.98
+    assert ins.sum() == 32 and _match(rm["lam"][ins], ex) < 1e-9
+    assert rm["k"] <= 8 * 16
+    r4 = O.rsrr_moment(prob, C, U, K=4, NQ=300)
+    rs = O.rsrr(prob, C, U, NQ=300, S=S)
+    i4, i_s = r4["level"] < 0.98, rs["level"] < 0.98
+    assert _match(r4["lam"][i4], ex) > 1e-6
+    assert _match(rs["lam"][i_s], ex) < 1e-9
