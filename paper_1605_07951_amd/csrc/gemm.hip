@@ -40,8 +40,10 @@ __global__ __launch_bounds__(CG_NT, 2) void cgemm_mfma_kernel(
     constexpr int AQ = BM * CG_KT / 2 / CG_NT;   // float4 (2 complex) A loads per thread per stage
     constexpr int BQ = BN * CG_KT / 2 / CG_NT;   // float4 B loads per thread per stage
     static_assert(AQ >= 1 && BQ >= 1, "tile too small for the loader");
+    // B rows padded by 4 complex (32 B): the staging stores write 8 k-rows of one
+    // column per wave, which then fall on different LDS banks
     __shared__ __attribute__((aligned(16))) float As[2][CG_KT][2 * BM];
-    __shared__ __attribute__((aligned(16))) float2 Bs[2][CG_KT][BN];
+    __shared__ __attribute__((aligned(16))) float2 Bs[2][CG_KT][BN + 4];
 
     const long tile = xcd_remap(blockIdx.x, total_padded);
     const long per = (long)tilesM * tilesN;
@@ -226,8 +228,9 @@ __global__ __launch_bounds__(ZG_NT, 2) void zgemm_mfma_kernel(
     double beta, double2* __restrict__ C, int ldc, long sC,
     int tilesM, int tilesN, int batch, long total_padded)
 {
-    __shared__ __attribute__((aligned(16))) double2 As[2][ZG_KT][ZG_BM];
-    __shared__ __attribute__((aligned(16))) double2 Bs[2][ZG_KT][ZG_BN];
+    // rows padded by one complex (16 B) so that column-wise staging stores spread over the banks
+    __shared__ __attribute__((aligned(16))) double2 As[2][ZG_KT][ZG_BM + 1];
+    __shared__ __attribute__((aligned(16))) double2 Bs[2][ZG_KT][ZG_BN + 1];
 
     const long tile = xcd_remap(blockIdx.x, total_padded);
     const long per = (long)tilesM * tilesN;
