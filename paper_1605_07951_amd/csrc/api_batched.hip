@@ -192,8 +192,14 @@ rsrr_status run_bucket(rsrr_ctx* c, hipStream_t sm, const rsrr_instance* inst, c
     const double tol_be = 4.0 * 1.1102230246251565e-16 * std::sqrt((double)P);
     const int iters = mixed ? maxit : 0;
     for (int it = 0; it <= iters; ++it) {
-        RSRR_HIP(copy_c128(sm, P, Lmax, b.Ub, P, b.sU, b.R, P, b.sU, (int)M));
-        RSRR_HIP(zgemm(sm, 0, 0, P, Lmax, P, -1.0, b.T128, P, b.sT, b.Xb, P, b.sU, 1.0, b.R, P, b.sU, (int)M));
+        if (resid_skinny_ok(Lmax)) {
+            // skinny: stream T once; points already decided are skipped
+            RSRR_HIP(resid_skinny(sm, P, Lmax, b.T128, P, b.sT, b.Xb, P, b.sU, b.Ub, P, b.sU, b.R, P, b.sU,
+                                  it == 0 ? nullptr : b.active, (int)M));
+        } else {
+            RSRR_HIP(copy_c128(sm, P, Lmax, b.Ub, P, b.sU, b.R, P, b.sU, (int)M));
+            RSRR_HIP(zgemm(sm, 0, 0, P, Lmax, P, -1.0, b.T128, P, b.sT, b.Xb, P, b.sU, 1.0, b.R, P, b.sU, (int)M));
+        }
         RSRR_HIP(colnorms(sm, P, Lmax, b.R, P, b.sU, b.rn, (int)M));
         RSRR_HIP(colnorms(sm, P, Lmax, b.Xb, P, b.sU, b.xn, (int)M));
         RSRR_HIP(ir_decide(sm, (int)M, Lmax, b.rn, b.xn, b.un, b.frob, tol_be, it, iters, b.active, b.prev, b.resid,

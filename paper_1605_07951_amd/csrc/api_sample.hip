@@ -293,8 +293,14 @@ static rsrr_status assemble_batch(rsrr_ctx* c, const rsrr_nep* nep, const zd* z,
 static rsrr_status residual_batch(rsrr_ctx* c, int n, int L, const double2* U, int ldu, double2* X, int ldx, long sX,
                                   int B, SampleBufs& s, std::vector<double>& rn, std::vector<double>& xn)
 {
-    RSRR_HIP(bcast_c128(c->stream, n, L, U, ldu, s.R, s.ld, (long)s.ld * L, B));
-    RSRR_HIP(zgemm(c->stream, 0, 0, n, L, n, -1.0, s.Tres, s.ld, s.sT, X, ldx, sX, 1.0, s.R, s.ld, (long)s.ld * L, B));
+    if (resid_skinny_ok(L)) {
+        RSRR_HIP(resid_skinny(c->stream, n, L, s.Tres, s.ld, s.sT, X, ldx, sX, U, ldu, 0, s.R, s.ld, (long)s.ld * L,
+                              nullptr, B));
+    } else {
+        RSRR_HIP(bcast_c128(c->stream, n, L, U, ldu, s.R, s.ld, (long)s.ld * L, B));
+        RSRR_HIP(zgemm(c->stream, 0, 0, n, L, n, -1.0, s.Tres, s.ld, s.sT, X, ldx, sX, 1.0, s.R, s.ld, (long)s.ld * L,
+                       B));
+    }
     RSRR_HIP(colnorms(c->stream, n, L, s.R, s.ld, (long)s.ld * L, s.norms, B));
     RSRR_HIP(colnorms(c->stream, n, L, X, ldx, sX, s.norms + (size_t)B * L, B));
     rn.resize((size_t)B * L);

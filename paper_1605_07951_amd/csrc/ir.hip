@@ -211,6 +211,60 @@ __global__ __launch_bounds__(EW_NT) void ir_decide_kernel(int M, int Lmax, const
     }
 }
 
+
+// R_b = U_b - T_b X_b in FP64 for at most RS_LC right-hand sides: the product is
+// skinny, so it is a stream over T (HBM bound) rather than an MFMA GEMM.  One
+// workgroup per 256 rows of one matrix; a chunk of 64 rows of X is staged in LDS
+// and read by broadcast; each thread keeps its row's L sums in registers and
+// walks k in order (deterministic).  Matrices with active[b] == 0 are skipped.
+// RW rows (= threads) per workgroup: 64 for small matrices, so that there are
+// enough workgroups, 256 otherwise.
+template <int LC, int RW>
+__global__ __launch_bounds__(RW) void resid_skinny_kernel(int n, int L, const double2* __restrict__ T, int ldt,
+                                                            long sT, const double2* __restrict__ X, int ldx, long sX,
+                                                            const double2* __restrict__ U, int ldu, long sU,
+                                                            double2* __restrict__ R, int ldr, long sR,
+                                                            const int* __restrict__ active)
+{
+    constexpr int KC = 64;
+    __shared__ double2 xs[KC][LC];
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    const int row = blockIdx.x * RW + threadIdx.x;
+    const double2* Tb = T + b * sT;
+    const double2* Xb = X + b * sX;
+    double2 acc[LC];
+#pragma unroll
+    for (int c = 0; c < LC; ++c) acc[c] = make_double2(0.0, 0.0);
+    for (int k0 = 0; k0 < n; k0 += KC) {
+        for (int e = threadIdx.x; e < KC * LC; e += RW) {
+            const int kk = e % KC, c = e / KC;
+            xs[kk][c] = (k0 + kk < n && c < L) ? Xb[(k0 + kk) + (long)c * ldx] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        if (row < n) {
+            const int kend = min(KC, n - k0);
+            const double2* tp = Tb + row + (long)k0 * ldt;
+#pragma unroll 8
+            for (int kk = 0; kk < kend; ++kk) {
+                const double2 t = tp[(long)kk * ldt];
+#pragma unroll
+                for (int c = 0; c < LC; ++c) acc[c] = cfma(acc[c], t, xs[kk][c]);
+            }
+        }
+        __syncthreads();
+    }
+    if (row >= n) return;
+    const double2* Ub = U + b * sU;
+    double2* Rb = R + b * sR;
+#pragma unroll
+    for (int c = 0; c < LC; ++c)
+        if (c < L) {
+            const double2 u = Ub[row + (long)c * ldu];
+            Rb[row + (long)c * ldr] = make_double2(u.x - acc[c].x, u.y - acc[c].y);
+        }
+}
+
 static dim3 ew_grid(long elems, int B) { return dim3((unsigned)((elems + EW_NT - 1) / EW_NT), B); }
 
 hipError_t pad_identity(hipStream_t st, float2* T64, double2* T128, int ld, long sT, int P, const int* nk, int M)
@@ -289,6 +343,26 @@ hipError_t copy_c128(hipStream_t st, int n, int m, const double2* X, int ldx, lo
 hipError_t scale_cols(hipStream_t st, int n, int m, double2* X, int ldx, const double* s)
 {
     hipLaunchKernelGGL(scale_cols_kernel, ew_grid((long)n * m, 1), dim3(EW_NT), 0, st, n, m, X, ldx, s);
+    return hipGetLastError();
+}
+
+
+bool resid_skinny_ok(int L) { return L >= 1 && L <= 16; }
+
+hipError_t resid_skinny(hipStream_t st, int n, int L, const double2* T, int ldt, long sT, const double2* X, int ldx,
+                        long sX, const double2* U, int ldu, long sU, double2* R, int ldr, long sR, const int* active,
+                        int B)
+{
+#define RS_L(LC, RW)                                                                                                 \
+    hipLaunchKernelGGL((resid_skinny_kernel<LC, RW>), dim3((unsigned)((n + RW - 1) / RW), (unsigned)B), dim3(RW), 0, \
+                       st, n, L, T, ldt, sT, X, ldx, sX, U, ldu, sU, R, ldr, sR, active)
+    const bool small = n <= 1024;
+    if (L <= 8) {
+        if (small) RS_L(8, 64); else RS_L(8, 256);
+    } else {
+        if (small) RS_L(16, 64); else RS_L(16, 256);
+    }
+#undef RS_L
     return hipGetLastError();
 }
 

@@ -86,6 +86,12 @@ hipError_t bcast_to_c64(hipStream_t st, int n, int L, const double2* U, int ldu,
 hipError_t bcast_c128(hipStream_t st, int n, int L, const double2* U, int ldu, double2* R, int ldr, long sR, int B);
 hipError_t widen(hipStream_t st, int n, int L, const float2* D, int ldd, long sD, double2* X, int ldx, long sX, int B);
 hipError_t colnorms(hipStream_t st, int n, int L, const double2* X, int ldx, long sX, double* out, int B);
+// R_b = U_b - T_b X_b (FP64) for L <= 16 columns, matrices with active[b] == 0
+// skipped (active may be null); resid_skinny_ok(L) tells whether it applies.
+bool resid_skinny_ok(int L);
+hipError_t resid_skinny(hipStream_t st, int n, int L, const double2* T, int ldt, long sT, const double2* X, int ldx,
+                        long sX, const double2* U, int ldu, long sU, double2* R, int ldr, long sR, const int* active,
+                        int B);
 hipError_t scale_narrow(hipStream_t st, int n, int L, const double2* R, int ldr, long sR, const double* inv,
                         float2* D, int ldd, long sD, const int* active, int B);
 hipError_t axpy_widen(hipStream_t st, int n, int L, const float2* D, int ldd, long sD, const double* scale,

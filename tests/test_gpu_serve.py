@@ -84,23 +84,25 @@ def test_serve_alone_equals_mix(R):
     finally:
         alone_srv.close()
     _check_qep(alone, nep, C)
-    # about 3.2 MB of LU workspace per n=200 point (padded to 256, complex FP32 with FP64
-    # copies): a launch holds about 40 points, so the 32-point requests share launches
+    # about 2.9 MB of LU workspace per n=200 point (padded to 256, complex FP32 with FP64
+    # copies): a 128 MB launch holds about 44 points, so the 32-point requests share
+    # launches; all inputs are on the device before the first submission, so the six submissions take
+    # microseconds while a launch takes milliseconds: the queue is full when launches start
+    q6, q7, q8, q9 = (_qep(R, s) for s in (6, 7, 8, 9))
+    nd, Cd, Ud = W.cfg_delay(nx=16, N=48, L=32)
+    dnd, Udd = R.DeviceNEP(nd), R.colmajor(Ud)[0]
+    torch.cuda.synchronize()
     mix_srv = R.Server(max_slots=6, arena_bytes=1 << 30, batch_bytes=40 * 3_200_000)
     try:
         others = []
-        for seed in (6, 7):
-            _, Co, dno, Uo = _qep(R, seed)
-            others.append((dno, Uo, mix_srv.submit(dno, Uo, Co.gamma, Co.a, Co.b, Co.N, max_eigs=64)))
+        for (_, Co, dno, Uo) in (q6, q7):
+            others.append(mix_srv.submit(dno, Uo, Co.gamma, Co.a, Co.b, Co.N, max_eigs=64))
         rid = mix_srv.submit(dn, U, C.gamma, C.a, C.b, C.N, max_eigs=64, want_V=True)
-        nd, Cd, Ud = W.cfg_delay(nx=16, N=48, L=32)
-        dnd = R.DeviceNEP(nd)
-        others.append((dnd, None, mix_srv.submit(dnd, R.colmajor(Ud)[0], Cd.gamma, Cd.a, Cd.b, Cd.N, max_eigs=32)))
-        for seed in (8, 9):
-            _, Co, dno, Uo = _qep(R, seed)
-            others.append((dno, Uo, mix_srv.submit(dno, Uo, Co.gamma, Co.a, Co.b, Co.N, max_eigs=64)))
+        others.append(mix_srv.submit(dnd, Udd, Cd.gamma, Cd.a, Cd.b, Cd.N, max_eigs=32))
+        for (_, Co, dno, Uo) in (q8, q9):
+            others.append(mix_srv.submit(dno, Uo, Co.gamma, Co.a, Co.b, Co.N, max_eigs=64))
         mixed = mix_srv.wait(rid, 120.0)
-        for _, _, o in others:
+        for o in others:
             assert mix_srv.wait(o, 120.0)["status"] in (0, 3)
         st = mix_srv.stats()
     finally:
