@@ -41,7 +41,7 @@ int jacobi_svd(rsrr_ctx* c, double2* A, int lda, int m, int m_apply, int p, int 
     int stall = 0;
     for (int sw = 0; sw < max_sweeps; ++sw) {
         for (int r = 0; r < rounds; ++r) {
-            if (jacobi_round(c->stream, A, lda, m, m_apply, p, r, 2, tol, zthr2, off + (size_t)r * pairs, work) !=
+            if (jacobi_round(c->stream, A, lda, m, m_apply, p, r, 1, tol, zthr2, off + (size_t)r * pairs, work) !=
                 hipSuccess) {
                 *st = RSRR_EDEVICE;
                 return -1;
