@@ -143,3 +143,23 @@ def test_sample_argument_errors(R, ctx):
     with pytest.raises(R.RsrrError) as e:
         R.rsrr_sample(ctx, dnep, np.array([0.5 + 0j]), U, prec=7)
     assert e.value.code == -8
+
+
+def test_sample_empty_and_degenerate_arguments(R, ctx):
+    """Empty inputs are argument errors (nothing enqueued): no points, no probe columns,
+    leading dimensions below n; the basis of a one-column S keeps one direction."""
+    import ctypes as C
+    nep = W.rotated_diagonal_qep(10, 1)
+    dnep = R.DeviceNEP(nep)
+    U, ldu = R.colmajor(W.probes(10, 2, 1))
+    S = torch.zeros((2, 10), dtype=torch.complex128, device="cuda")
+    z = (C.c_double * 2)(0.5, 0.0)
+    L = R.lib()
+    args = lambda N, Lc, lu, ls: (ctx.h, C.byref(dnep.desc), N, z, U.data_ptr(), Lc, lu, 1, S.data_ptr(), ls, None)
+    assert L.rsrr_sample(*args(0, 2, 10, 10)) == -3
+    assert L.rsrr_sample(*args(1, 0, 10, 10)) == -6
+    assert L.rsrr_sample(*args(1, 2, 9, 10)) == -7
+    assert L.rsrr_sample(*args(1, 2, 10, 9)) == -10
+    Sd, _, _ = R.rsrr_sample(ctx, dnep, np.array([0.5 + 0j]), W.probes(10, 1, 3))
+    Q, k, sig = R.rsrr_basis(ctx, Sd, 10, 1e-14)
+    assert k == 1 and abs(np.linalg.norm(R.from_colmajor(Q[:1], 10)) - 1) < 1e-14
