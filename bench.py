@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="helmholtz", choices=["helmholtz", "delay", "qep", "serve", "batched", "adaptive", "moments"])
+    ap.add_argument("--workload", default="helmholtz", choices=["helmholtz", "delay", "qep", "serve", "batched", "adaptive", "moments", "real"])
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--N", type=int, default=None)
     ap.add_argument("--L", type=int, default=None)
@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--instances", type=int, default=256, help="batched: QEP instances")
     ap.add_argument("--n1", type=int, default=6, help="adaptive: stage-1 contour points")
     ap.add_argument("--K", type=str, default="4,16", help="moments: moment counts K to compare")
+    ap.add_argument("--real-nep", default="delay", choices=["delay", "string"], help="real: the real NEP")
+    ap.add_argument("--interval", type=str, default=None, help="real: sampling interval lo,hi")
     ap.add_argument("--requests", type=int, default=24, help="serve: requests taken from the stream")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: Poisson arrival rate (1/s)")
     ap.add_argument("--slots", type=int, default=8, help="serve: requests admitted at once")
@@ -425,6 +427,73 @@ def run_moments(args):
     }
     print(json.dumps(res), flush=True)
 
+
+def run_real(args):
+    """Real sampling of a real NEP at N Chebyshev points of a real interval, L real probes.
+    Default: the delay Laplacian on a 64x64 grid (n=4096), interval [-9, -4] (it holds real
+    eigenvalues), N=64, L=16; --real-nep string: the loaded string of Example 1 on [3, 10000].
+    value = resolvent solves/s of the real FP32 LU path (R32_IR); the complex FP32 and FP64
+    paths run on the same inputs."""
+    import torch
+    import workloads as W
+    from paper_1605_07951_amd import rsrr as R
+
+    N = args.N or 64
+    L = args.L or 16
+    if args.real_nep == "string":
+        n = args.n or 4096
+        nep = W.loaded_string(n)
+        lo, hi = 3.0, 10000.0
+    else:
+        nx = int(round(math.sqrt(args.n or 4096)))
+        nep = W.delay_laplacian(nx)
+        n = nep.n
+        lo, hi = -9.0, -4.0
+    if args.interval:
+        lo, hi = (float(v) for v in args.interval.split(","))
+    dnep = R.DeviceNEP(nep)
+    z = W.interval_points(lo, hi, N)
+    U, _ = R.colmajor(W.real_probes(n, L, 78))
+    ctx = R.rsrr_create(0)
+    S = torch.empty((N * L, n), dtype=torch.complex128, device="cuda")
+    out = {}
+    for name, prec in (("r32", R.RSRR_PREC_R32_IR), ("c64", R.RSRR_PREC_C64_IR), ("c128", R.RSRR_PREC_C128)):
+        for _ in range(args.warmup):
+            R.rsrr_sample(ctx, dnep, z, U, prec=prec, S=S)
+        torch.cuda.synchronize()
+        R.rsrr_update_stats(ctx, enable=True, reset=True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, info, _ = R.rsrr_sample(ctx, dnep, z, U, prec=prec, S=S)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        st = R.rsrr_update_stats(ctx, enable=False)
+        out[name] = {"solves_per_s": round(N / dt, 3), "ms_per_step": round(1e3 * dt, 3),
+                     "update_tflops": round(st["flops"] / (st["ms"] * 1e-3) / 1e12, 3) if st["ms"] > 0 else None,
+                     "update_launches": st["launches"],
+                     "resid_max": max(i["resid"] for i in info), "fallbacks": sum(i["fallback"] for i in info),
+                     "ir_iters_max": max(i["ir_iters"] for i in info)}
+    r32 = out["r32"]
+    achieved = r32["update_tflops"] or 0.0
+    res = {
+        "metric": METRIC,
+        "value": r32["solves_per_s"],
+        "unit": "resolvent solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 LU (f32 MFMA) + f64 refinement",
+        "data": f"synthetic ({nep.name}, real Gaussian probes)",
+        "config": {"workload": f"real sampling, {nep.name} n={n}, N={N} Chebyshev points of [{lo}, {hi}], L={L}",
+                   "step": "rsrr_sample over all N points (assembly, real LU, solves, refinement)"},
+        "roofline": {"bound": "mfma", "kernel": "LU trailing update, real (sgemm_mfma_kernel<*,1>)",
+                     "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None},
+        "paths": out,
+        "r32_over_c64": round(out["r32"]["solves_per_s"] / out["c64"]["solves_per_s"], 3),
+        "r32_over_c128": round(out["r32"]["solves_per_s"] / out["c128"]["solves_per_s"], 3),
+    }
+    print(json.dumps(res), flush=True)
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -442,6 +511,9 @@ def main():
         return
     if args.workload == "moments":
         run_moments(args)
+        return
+    if args.workload == "real":
+        run_real(args)
         return
     import torch
     from paper_1605_07951_amd import rsrr as R

@@ -76,8 +76,13 @@ enum { RSRR_T_SEPARABLE = 0, RSRR_T_HELMHOLTZ = 1 };
 /* Arithmetic of the sampling step.  C128: complex FP64 LU and solves.
  * C64_IR: complex FP32 LU on the matrix cores, then iterative refinement
  * against FP64 residuals until FP64 backward error; a point that does not
- * converge is redone with the C128 path (flagged in rsrr_point_info). */
-enum { RSRR_PREC_C128 = 0, RSRR_PREC_C64_IR = 1 };
+ * converge is redone with the C128 path (flagged in rsrr_point_info).
+ * R32_IR (rsrr_sample only): real sampling for a real NEP (Sec. 4.3 and
+ * Sec. 5: real points, e.g. Chebyshev points of an interval): real FP32 LU
+ * and solves, refined against the FP64 residual of the complex problem as
+ * given; requires a SEPARABLE nep and real points.  A T(z_k) or U that is not
+ * real makes the refinement stall, and the point is redone on the C128 path. */
+enum { RSRR_PREC_C128 = 0, RSRR_PREC_C64_IR = 1, RSRR_PREC_R32_IR = 2 };
 
 /* One scalar coefficient f(z) = c (z - z0)^p exp(-tau z) / (z - s)^q. */
 typedef struct {
@@ -148,7 +153,8 @@ RSRR_API rsrr_status rsrr_contour(double gamma_re, double gamma_im, double a, do
  * prec: RSRR_PREC_C128 or RSRR_PREC_C64_IR.
  * Status: RSRR_ESINGULAR if any point had an exact zero pivot (its block of S
  * is then not meaningful), RSRR_WARN_FALLBACK if any point was redone in FP64.
- * Errors: -2 nep invalid, -3 N < 1, -4 z NULL, -5 U NULL, -6 L < 1, -7 ldu < n,
+ * Errors: -2 nep invalid (or not SEPARABLE with R32_IR), -3 N < 1, -4 z NULL
+ * (or a point off the real axis with R32_IR), -5 U NULL, -6 L < 1, -7 ldu < n,
  * -8 prec, -9 S NULL, -10 lds < n. */
 RSRR_API rsrr_status rsrr_sample(rsrr_ctx *ctx, const rsrr_nep *nep, int N, const double *z,
                         const double *U, int L, int ldu, int prec,

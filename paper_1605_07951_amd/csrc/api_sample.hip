@@ -216,7 +216,7 @@ static size_t per_point_bytes(int n, int L, int prec)
     b += (size_t)n * 4 + np * 2 * MAX_NB * 8 + 8 * 2 * MAX_NB * 8 + 16;
     b += ((size_t)n * n + 255) / 256 * 8 + 8;
     b += (size_t)ld * L * (8 + 16) + (size_t)L * 16;
-    if (prec == RSRR_PREC_C64_IR) {
+    if (prec != RSRR_PREC_C128) {
         b += (size_t)np * 2 * 128 * 128 * 8 / 2;          // diagonal-block inverses (nb = 128: n/128 panels)
         b += (size_t)128 * std::max(n, L) * 8;            // scratch rows
     }
@@ -227,12 +227,14 @@ static rsrr_status alloc_bufs(rsrr_ctx* c, int n, int L, int J, int prec, int B,
 {
     s.ld = ld_pad(n);
     s.np = perm_panels(n);
-    s.nb = prec == RSRR_PREC_C64_IR ? std::min(c->nb_c64, max_panel<float>()) : std::min(c->nb_c128, max_panel<double>());
-    s.sInv = prec == RSRR_PREC_C64_IR ? (long)((n + s.nb - 1) / s.nb) * 2 * s.nb * s.nb : 0;
-    s.sTmp = prec == RSRR_PREC_C64_IR ? (long)s.nb * std::max(n, L) : 0;
-    s.inv = prec == RSRR_PREC_C64_IR ? ws_get(c, WS_B0, (size_t)B * s.sInv * 8) : nullptr;
-    s.tmp = prec == RSRR_PREC_C64_IR ? ws_get(c, WS_B1, (size_t)B * s.sTmp * 8) : nullptr;
-    if (prec == RSRR_PREC_C64_IR && (!s.inv || !s.tmp)) return RSRR_ENOMEM;
+    // the real FP32 path (R32_IR) uses the complex FP32 layout with real elements (half the bytes)
+    const bool fp32 = prec != RSRR_PREC_C128;
+    s.nb = fp32 ? std::min(c->nb_c64, max_panel<float>()) : std::min(c->nb_c128, max_panel<double>());
+    s.sInv = fp32 ? (long)((n + s.nb - 1) / s.nb) * 2 * s.nb * s.nb : 0;
+    s.sTmp = fp32 ? (long)s.nb * std::max(n, L) : 0;
+    s.inv = fp32 ? ws_get(c, WS_B0, (size_t)B * s.sInv * 8) : nullptr;
+    s.tmp = fp32 ? ws_get(c, WS_B1, (size_t)B * s.sTmp * 8) : nullptr;
+    if (fp32 && (!s.inv || !s.tmp)) return RSRR_ENOMEM;
     s.sT = (long)s.ld * n;
     s.sP = n;
     s.sPerm = (long)s.np * 2 * MAX_NB;
@@ -277,6 +279,7 @@ static rsrr_status assemble_batch(rsrr_ctx* c, const rsrr_nep* nep, const zd* z,
         RSRR_HIP(assemble_separable(c->stream, n, nep->J, (const double2*)nep->A, nep->lda, s.coef, B, T64, s.ld,
                                     s.sT, s.Tres, s.ld, s.sT, s.frobp, s.frob));
         if (Tlu128) RSRR_HIP(copy_c128(c->stream, n, n, s.Tres, s.ld, s.sT, Tlu128, s.ld, s.sT, B));
+        if (prec == RSRR_PREC_R32_IR) RSRR_HIP(narrow_real(c->stream, n, s.Tres, s.ld, s.sT, (float*)s.Tlu, s.ld, s.sT, B));
     } else {
         std::vector<double2> zz(B);
         for (int k = 0; k < B; ++k) zz[k] = make_double2(z[k].real(), z[k].imag());
@@ -312,15 +315,15 @@ static rsrr_status residual_batch(rsrr_ctx* c, int n, int L, const double2* U, i
 }
 
 // Offset a workspace view to the matrices starting at b0.
-static LUWork lu_offset(const LUWork& w, long b0)
+static LUWork lu_offset(const LUWork& w, long b0, int esz = 8)
 {
     LUWork o = w;
     o.ipiv = w.ipiv + b0 * w.sP;
     o.perm = w.perm + b0 * w.sPerm;
     o.tperm = w.tperm + b0 * w.sTP;
     o.info = w.info + b0;
-    if (w.inv) o.inv = (char*)w.inv + b0 * w.sInv * 8;
-    if (w.tmp) o.tmp = (char*)w.tmp + b0 * w.sTmp * 8;
+    if (w.inv) o.inv = (char*)w.inv + b0 * w.sInv * esz;
+    if (w.tmp) o.tmp = (char*)w.tmp + b0 * w.sTmp * esz;
     if (w.active) o.active = w.active + b0;
     return o;
 }
@@ -373,10 +376,12 @@ static rsrr_status sample_batch(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, i
         st = split_groups(
             c, B,
             [&](hipStream_t sm, int b0, int nbg, hipEvent_t ev) -> rsrr_status {
-                LUWork wg = lu_offset(w, b0);
+                LUWork wg = lu_offset(w, b0, prec == RSRR_PREC_R32_IR ? 4 : 8);
                 wg.first_panel = ev;
                 if (prec == RSRR_PREC_C128)
                     RSRR_HIP(getrf_batched<double>(sm, (double2*)s.Tlu + b0 * s.sT, s.sT, s.ld, n, s.nb, wg, nbg));
+                else if (prec == RSRR_PREC_R32_IR)
+                    RSRR_HIP(getrf_real_batched(sm, (float*)s.Tlu + b0 * s.sT, s.sT, s.ld, n, s.nb, wg, nbg));
                 else
                     RSRR_HIP(getrf_batched<float>(sm, (float2*)s.Tlu + b0 * s.sT, s.sT, s.ld, n, s.nb, wg, nbg));
                 return RSRR_OK;
@@ -434,15 +439,29 @@ static rsrr_status sample_batch(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, i
     // mixed path: X0 = getrs_c64(U), then refinement with FP64 residuals
     {
         PhaseTimer t(c, &tm[2]);
-        RSRR_HIP(bcast_to_c64(c->stream, n, L, U, ldu, s.D64, s.ld, (long)s.ld * L, B));
         const LUWork w = s.lu(s.active, nullptr);
-        st = split_groups(c, B, [&](hipStream_t sm, int b0, int nbg, hipEvent_t) -> rsrr_status {
-            RSRR_HIP(getrs_batched<float>(sm, (const float2*)s.Tlu + b0 * s.sT, s.sT, s.ld, n, s.nb, lu_offset(w, b0),
-                                          s.D64 + b0 * (long)s.ld * L, (long)s.ld * L, s.ld, L, nbg));
-            return RSRR_OK;
-        });
-        if (st) return st;
-        RSRR_HIP(widen(c->stream, n, L, s.D64, s.ld, (long)s.ld * L, S, lds, sX, B));
+        if (prec == RSRR_PREC_R32_IR) {
+            float* D = (float*)s.D64;
+            RSRR_HIP(scale_narrow_real(c->stream, n, L, U, ldu, 0, nullptr, D, s.ld, (long)s.ld * L, nullptr, B));
+            st = split_groups(c, B, [&](hipStream_t sm, int b0, int nbg, hipEvent_t) -> rsrr_status {
+                RSRR_HIP(getrs_real_batched(sm, (const float*)s.Tlu + b0 * s.sT, s.sT, s.ld, n, s.nb,
+                                            lu_offset(w, b0, 4), D + b0 * (long)s.ld * L, (long)s.ld * L, s.ld, L,
+                                            nbg));
+                return RSRR_OK;
+            });
+            if (st) return st;
+            RSRR_HIP(axpy_widen_real(c->stream, n, L, D, s.ld, (long)s.ld * L, nullptr, S, lds, sX, nullptr, B));
+        } else {
+            RSRR_HIP(bcast_to_c64(c->stream, n, L, U, ldu, s.D64, s.ld, (long)s.ld * L, B));
+            st = split_groups(c, B, [&](hipStream_t sm, int b0, int nbg, hipEvent_t) -> rsrr_status {
+                RSRR_HIP(getrs_batched<float>(sm, (const float2*)s.Tlu + b0 * s.sT, s.sT, s.ld, n, s.nb,
+                                              lu_offset(w, b0), s.D64 + b0 * (long)s.ld * L, (long)s.ld * L, s.ld,
+                                              L, nbg));
+                return RSRR_OK;
+            });
+            if (st) return st;
+            RSRR_HIP(widen(c->stream, n, L, s.D64, s.ld, (long)s.ld * L, S, lds, sX, B));
+        }
         t.stop();
     }
     const double eps = 1.1102230246251565e-16;
@@ -487,20 +506,34 @@ static rsrr_status sample_batch(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, i
             RSRR_HIP(hipMemcpyAsync(s.active, act.data(), (size_t)B * 4, hipMemcpyHostToDevice, c->stream));
             RSRR_HIP(hipMemcpyAsync(s.norms + (size_t)2 * B * L, inv.data(), (size_t)B * L * 8, hipMemcpyHostToDevice,
                                     c->stream));
-            RSRR_HIP(scale_narrow(c->stream, n, L, s.R, s.ld, (long)s.ld * L, s.norms + (size_t)2 * B * L, s.D64, s.ld,
-                                  (long)s.ld * L, s.active, B));
             const LUWork w = s.lu(s.active, nullptr);
-            st = split_groups(c, B, [&](hipStream_t sm, int b0, int nbg, hipEvent_t) -> rsrr_status {
-                RSRR_HIP(getrs_batched<float>(sm, (const float2*)s.Tlu + b0 * s.sT, s.sT, s.ld, n, s.nb,
-                                              lu_offset(w, b0), s.D64 + b0 * (long)s.ld * L, (long)s.ld * L, s.ld,
-                                              L, nbg));
-                return RSRR_OK;
-            });
-            if (st) return st;
-            RSRR_HIP(hipMemcpyAsync(s.norms + (size_t)2 * B * L, scl.data(), (size_t)B * L * 8, hipMemcpyHostToDevice,
-                                    c->stream));
-            RSRR_HIP(axpy_widen(c->stream, n, L, s.D64, s.ld, (long)s.ld * L, s.norms + (size_t)2 * B * L, S, lds, sX,
-                                s.active, B));
+            double* sc = s.norms + (size_t)2 * B * L;
+            if (prec == RSRR_PREC_R32_IR) {
+                float* D = (float*)s.D64;
+                RSRR_HIP(scale_narrow_real(c->stream, n, L, s.R, s.ld, (long)s.ld * L, sc, D, s.ld, (long)s.ld * L,
+                                           s.active, B));
+                st = split_groups(c, B, [&](hipStream_t sm, int b0, int nbg, hipEvent_t) -> rsrr_status {
+                    RSRR_HIP(getrs_real_batched(sm, (const float*)s.Tlu + b0 * s.sT, s.sT, s.ld, n, s.nb,
+                                                lu_offset(w, b0, 4), D + b0 * (long)s.ld * L, (long)s.ld * L, s.ld,
+                                                L, nbg));
+                    return RSRR_OK;
+                });
+                if (st) return st;
+                RSRR_HIP(hipMemcpyAsync(sc, scl.data(), (size_t)B * L * 8, hipMemcpyHostToDevice, c->stream));
+                RSRR_HIP(axpy_widen_real(c->stream, n, L, D, s.ld, (long)s.ld * L, sc, S, lds, sX, s.active, B));
+            } else {
+                RSRR_HIP(scale_narrow(c->stream, n, L, s.R, s.ld, (long)s.ld * L, sc, s.D64, s.ld, (long)s.ld * L,
+                                      s.active, B));
+                st = split_groups(c, B, [&](hipStream_t sm, int b0, int nbg, hipEvent_t) -> rsrr_status {
+                    RSRR_HIP(getrs_batched<float>(sm, (const float2*)s.Tlu + b0 * s.sT, s.sT, s.ld, n, s.nb,
+                                                  lu_offset(w, b0), s.D64 + b0 * (long)s.ld * L, (long)s.ld * L,
+                                                  s.ld, L, nbg));
+                    return RSRR_OK;
+                });
+                if (st) return st;
+                RSRR_HIP(hipMemcpyAsync(sc, scl.data(), (size_t)B * L * 8, hipMemcpyHostToDevice, c->stream));
+                RSRR_HIP(axpy_widen(c->stream, n, L, s.D64, s.ld, (long)s.ld * L, sc, S, lds, sX, s.active, B));
+            }
             t.stop();
         }
     }
@@ -582,7 +615,13 @@ extern "C" rsrr_status rsrr_sample(rsrr_ctx* c, const rsrr_nep* nep, int N, cons
     if (!U) return -5;
     if (L < 1) return -6;
     if (ldu < nep->n) return -7;
-    if (prec != RSRR_PREC_C128 && prec != RSRR_PREC_C64_IR) return -8;
+    if (prec != RSRR_PREC_C128 && prec != RSRR_PREC_C64_IR && prec != RSRR_PREC_R32_IR) return -8;
+    if (prec == RSRR_PREC_R32_IR) {
+        // real arithmetic needs a separable NEP and real points
+        if (nep->kind != RSRR_T_SEPARABLE) return -2;
+        for (int k = 0; k < N; ++k)
+            if (z[2 * k + 1] != 0.0) return -4;
+    }
     if (!S) return -9;
     if (lds < nep->n) return -10;
     RSRR_HIP(hipSetDevice(c->device));

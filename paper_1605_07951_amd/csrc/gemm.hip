@@ -215,6 +215,193 @@ hipError_t cgemm(hipStream_t st, int M, int N, int K, float alpha,
 }
 
 // ----------------------------------------------------------------------------
+// real FP32 (the LU of a real NEP at real points): v_mfma_f32_32x32x2f32 with
+// the instruction's K = 2 over two consecutive k (lanes 0-31: k, lanes 32-63:
+// k + 1).  Same wave/block shapes and output layout as the complex kernel.
+// LDS rows are padded so that the staging stores and the two-row operand
+// reads spread over the banks.
+// ----------------------------------------------------------------------------
+constexpr int SG_KT = 16;
+
+template <int WR, int WC, int BR, int BC, bool VEC, int TAG>
+__global__ __launch_bounds__(CG_NT, 2) void sgemm_mfma_kernel(
+    int M, int N, int K, float alpha,
+    const float* __restrict__ A, int lda, long sA,
+    const float* __restrict__ B, int ldb, long sB,
+    float beta, float* __restrict__ C, int ldc, long sC,
+    int tilesM, int tilesN, int batch, long total_padded)
+{
+    constexpr int BM = 32 * WR * BR, BN = 32 * WC * BC;
+    constexpr int AQ = BM * SG_KT / 4 / CG_NT;   // float4 (4 rows) A loads per thread per stage
+    constexpr int BLD = BN * SG_KT / 4;            // float4 (4 k) B loads per stage
+    constexpr int BQ = (BLD + CG_NT - 1) / CG_NT;  // ... per thread (the last round may be partial)
+    static_assert(AQ >= 1 && AQ * 4 * CG_NT == BM * SG_KT, "A tile must split evenly over the threads");
+    __shared__ __attribute__((aligned(16))) float As[2][SG_KT][BM + 32];
+    __shared__ __attribute__((aligned(16))) float Bs[2][SG_KT][BN + 36];
+
+    const long tile = xcd_remap(blockIdx.x, total_padded);
+    const long per = (long)tilesM * tilesN;
+    const long b = tile / per;
+    if (b >= batch) return;
+    const int t = (int)(tile - b * per);
+    const int i0 = (t % tilesM) * BM;
+    const int j0 = (t / tilesM) * BN;
+    const float* Ab = A + b * sA;
+    const float* Bb = B + b * sB;
+    float* Cb = C + b * sC;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wi = wave % WR, wj = wave / WR;
+    const int li = lane & 31, half = lane >> 5;
+    const int wrow = i0 + wi * BR * 32, wcol = j0 + wj * BC * 32;
+
+    floatx16 acc[BR][BC];
+#pragma unroll
+    for (int x = 0; x < BR; ++x)
+#pragma unroll
+        for (int y = 0; y < BC; ++y) {
+            const int i = wrow + x * 32 + li;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int j = wcol + y * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                acc[x][y][r] = (beta != 0.f && i < M && j < N) ? beta * Cb[i + (long)j * ldc] : 0.f;
+            }
+        }
+
+    floatx4 ra[AQ], rb[BQ];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < AQ; ++q) {
+            const int p = tid + CG_NT * q;
+            const int k = p / (BM / 4), i4 = (p % (BM / 4)) * 4;
+            const int gi = i0 + i4, gk = k0 + k;
+            floatx4 v = {0.f, 0.f, 0.f, 0.f};
+            if (gk < K) {
+                const float* src = Ab + gi + (long)gk * lda;
+                if (VEC && gi + 3 < M) {
+                    v = *reinterpret_cast<const floatx4*>(src);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (gi + e < M) v[e] = src[e];
+                }
+            }
+            ra[q] = v;
+        }
+#pragma unroll
+        for (int q = 0; q < BQ; ++q) {
+            const int p = tid + CG_NT * q;
+            const int j = p / (SG_KT / 4), k4 = (p % (SG_KT / 4)) * 4;
+            const int gj = j0 + j, gk = k0 + k4;
+            floatx4 v = {0.f, 0.f, 0.f, 0.f};
+            if (p < BLD && j < BN && gj < N) {
+                const float* src = Bb + gk + (long)gj * ldb;
+                if (VEC && gk + 3 < K) {
+                    v = *reinterpret_cast<const floatx4*>(src);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (gk + e < K) v[e] = src[e];
+                }
+            }
+            rb[q] = v;
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < AQ; ++q) {
+            const int p = tid + CG_NT * q;
+            const int k = p / (BM / 4), i4 = (p % (BM / 4)) * 4;
+            *reinterpret_cast<floatx4*>(&As[buf][k][i4]) = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < BQ; ++q) {
+            const int p = tid + CG_NT * q;
+            const int j = p / (SG_KT / 4), k4 = (p % (SG_KT / 4)) * 4;
+            if (p < BLD) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) Bs[buf][k4 + e][j] = rb[q][e];
+            }
+        }
+    };
+
+    const int nst = (K + SG_KT - 1) / SG_KT;
+    if (nst > 0) {
+        gload(0);
+        sstore(0);
+        __syncthreads();
+    }
+    for (int s = 0; s < nst; ++s) {
+        const int buf = s & 1;
+        if (s + 1 < nst) gload((s + 1) * SG_KT);
+#pragma unroll 4
+        for (int kp = 0; kp < SG_KT / 2; ++kp) {
+            const int k = 2 * kp + half;
+            float a[BR], bb[BC];
+#pragma unroll
+            for (int x = 0; x < BR; ++x) a[x] = alpha * As[buf][k][wi * BR * 32 + x * 32 + li];
+#pragma unroll
+            for (int y = 0; y < BC; ++y) bb[y] = Bs[buf][k][wj * BC * 32 + y * 32 + li];
+#pragma unroll
+            for (int x = 0; x < BR; ++x)
+#pragma unroll
+                for (int y = 0; y < BC; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(bb[y], a[x], acc[x][y], 0, 0, 0);
+        }
+        if (s + 1 < nst) sstore(buf ^ 1);
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int x = 0; x < BR; ++x) {
+        const int i = wrow + x * 32 + li;
+        if (i >= M) continue;
+#pragma unroll
+        for (int y = 0; y < BC; ++y)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int j = wcol + y * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                if (j < N) Cb[i + (long)j * ldc] = acc[x][y][r];
+            }
+    }
+}
+
+template <int WR, int WC, int BR, int BC>
+static void sgemm_launch(hipStream_t st, int M, int N, int K, float alpha, const float* A, int lda, long sA,
+                         const float* B, int ldb, long sB, float beta, float* C, int ldc, long sC, int batch, int tag,
+                         bool vec)
+{
+    constexpr int BM = 32 * WR * BR, BN = 32 * WC * BC;
+    const int tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
+    const long total = round_up_l((long)tm * tn * batch, 8);
+#define SG_L(V, T)                                                                                                    \
+    hipLaunchKernelGGL((sgemm_mfma_kernel<WR, WC, BR, BC, V, T>), dim3((unsigned)total), dim3(CG_NT), 0, st, M, N, K, \
+                       alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, tm, tn, batch, total)
+    if (vec) {
+        if (tag == 1) SG_L(true, 1); else SG_L(true, 0);
+    } else {
+        if (tag == 1) SG_L(false, 1); else SG_L(false, 0);
+    }
+#undef SG_L
+}
+
+hipError_t sgemm(hipStream_t st, int M, int N, int K, float alpha, const float* A, int lda, long sA,
+                 const float* B, int ldb, long sB, float beta, float* C, int ldc, long sC, int batch, int tag)
+{
+    if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+    const bool vec = ((((uintptr_t)A) | ((uintptr_t)B)) & 15) == 0 && (lda % 4 == 0) && (ldb % 4 == 0) &&
+                     (sA % 4 == 0) && (sB % 4 == 0);
+    if (N <= 32)
+        sgemm_launch<4, 1, 1, 1>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tag, vec);
+    else if (N <= 64)
+        sgemm_launch<4, 1, 1, 2>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tag, vec);
+    else
+        sgemm_launch<2, 2, 2, 2>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tag, vec);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
 // complex FP64: v_mfma_f64_16x16x4f64, WG tile 64x64, 4 waves of 32x32.
 // op(A) = A or A^H, op(B) = B or B^H.
 // ----------------------------------------------------------------------------

@@ -99,6 +99,61 @@ __global__ __launch_bounds__(EW_NT) void axpy_widen_kernel(int n, int L, const f
     *x = v;
 }
 
+// ---- real FP32 correction solves (a real NEP at real points) ----
+// The FP64 residual stays complex (its imaginary part is exactly zero for a
+// real problem); the real FP32 LU solves with its real part.  If the problem
+// is not real after all, the refinement stalls and the point is redone on the
+// FP64 complex path.
+
+// Tr_k = (float) Re T_k.
+__global__ __launch_bounds__(EW_NT) void narrow_real_kernel(int n, const double2* __restrict__ T, int ldt, long sT,
+                                                             float* __restrict__ Tr, int ldr, long sTr)
+{
+    const int k = blockIdx.y;
+    const long e = (long)blockIdx.x * EW_NT + threadIdx.x;
+    if (e >= (long)n * n) return;
+    const int i = (int)(e % n), c = (int)(e / n);
+    Tr[k * sTr + i + (long)c * ldr] = (float)T[k * sT + i + (long)c * ldt].x;
+}
+
+// D_k(:, c) = (float) (Re R_k(:, c) * inv[k*L + c]) (inv = null: 1) for active points.
+__global__ __launch_bounds__(EW_NT) void scale_narrow_real_kernel(int n, int L, const double2* __restrict__ R, int ldr,
+                                                                   long sR, const double* __restrict__ inv,
+                                                                   float* __restrict__ D, int ldd, long sD,
+                                                                   const int* __restrict__ active)
+{
+    const int k = blockIdx.y;
+    if (active && !active[k]) return;
+    const int e = blockIdx.x * EW_NT + threadIdx.x;
+    if (e >= n * L) return;
+    const int i = e % n, c = e / n;
+    const double s = inv ? inv[(long)k * L + c] : 1.0;
+    D[k * sD + i + (long)c * ldd] = (float)(R[k * sR + i + (long)c * ldr].x * s);
+}
+
+// X_k(:, c) = (D_k(:, c), 0) when scale is null, else Re X_k(:, c) += scale[k*L + c] * D_k(:, c),
+// for active points.
+__global__ __launch_bounds__(EW_NT) void axpy_widen_real_kernel(int n, int L, const float* __restrict__ D, int ldd,
+                                                                 long sD, const double* __restrict__ scale,
+                                                                 double2* __restrict__ X, int ldx, long sX,
+                                                                 const int* __restrict__ active)
+{
+    const int k = blockIdx.y;
+    if (active && !active[k]) return;
+    const int e = blockIdx.x * EW_NT + threadIdx.x;
+    if (e >= n * L) return;
+    const int i = e % n, c = e / n;
+    const double d = (double)D[k * sD + i + (long)c * ldd];
+    double2* x = X + k * sX + i + (long)c * ldx;
+    if (!scale) {
+        *x = make_double2(d, 0.0);
+    } else {
+        double2 v = *x;
+        v.x += scale[(long)k * L + c] * d;
+        *x = v;
+    }
+}
+
 // Copy n x m (c128) blocks: Y_k = X_k.
 __global__ __launch_bounds__(EW_NT) void copy_c128_kernel(int n, int m, const double2* __restrict__ X, int ldx,
                                                            long sX, double2* __restrict__ Y, int ldy, long sY)
@@ -363,6 +418,27 @@ hipError_t resid_skinny(hipStream_t st, int n, int L, const double2* T, int ldt,
         if (small) RS_L(16, 64); else RS_L(16, 256);
     }
 #undef RS_L
+    return hipGetLastError();
+}
+
+hipError_t narrow_real(hipStream_t st, int n, const double2* T, int ldt, long sT, float* Tr, int ldr, long sTr,
+                       int B)
+{
+    hipLaunchKernelGGL(narrow_real_kernel, ew_grid((long)n * n, B), dim3(EW_NT), 0, st, n, T, ldt, sT, Tr, ldr, sTr);
+    return hipGetLastError();
+}
+hipError_t scale_narrow_real(hipStream_t st, int n, int L, const double2* R, int ldr, long sR, const double* inv,
+                             float* D, int ldd, long sD, const int* active, int B)
+{
+    hipLaunchKernelGGL(scale_narrow_real_kernel, ew_grid((long)n * L, B), dim3(EW_NT), 0, st, n, L, R, ldr, sR, inv,
+                       D, ldd, sD, active);
+    return hipGetLastError();
+}
+hipError_t axpy_widen_real(hipStream_t st, int n, int L, const float* D, int ldd, long sD, const double* scale,
+                           double2* X, int ldx, long sX, const int* active, int B)
+{
+    hipLaunchKernelGGL(axpy_widen_real_kernel, ew_grid((long)n * L, B), dim3(EW_NT), 0, st, n, L, D, ldd, sD, scale,
+                       X, ldx, sX, active);
     return hipGetLastError();
 }
 

@@ -69,6 +69,16 @@ template <typename R>
 hipError_t getrs_batched(hipStream_t st, const typename cpx<R>::T* LU, long sLU, int lda, int n, int nb,
                          const LUWork& w, typename cpx<R>::T* X, long sX, int ldx, int nrhs, int batch);
 
+// The same for real FP32 matrices (a real NEP at real points); workspace as
+// for complex FP32 (inv/tmp hold real values, half the bytes used).
+hipError_t getrf_real_batched(hipStream_t st, float* A, long sA, int lda, int n, int nb, const LUWork& w, int batch);
+hipError_t getrs_real_batched(hipStream_t st, const float* LU, long sLU, int lda, int n, int nb, const LUWork& w,
+                              float* X, long sX, int ldx, int nrhs, int batch);
+
+// C = beta*C + alpha*A*B, real single on v_mfma_f32_32x32x2f32.
+hipError_t sgemm(hipStream_t st, int M, int N, int K, float alpha, const float* A, int lda, long sA,
+                 const float* B, int ldb, long sB, float beta, float* C, int ldc, long sC, int batch, int tag = 0);
+
 // ---- assembly (assemble.hip) ----
 // T64/T128 may be null (not written); batch strides s64/s128 in elements.
 // frob_part: B * ceil(n*n/256) doubles of scratch; frob: B doubles (||T_k||_F).
@@ -89,6 +99,15 @@ hipError_t colnorms(hipStream_t st, int n, int L, const double2* X, int ldx, lon
 // R_b = U_b - T_b X_b (FP64) for L <= 16 columns, matrices with active[b] == 0
 // skipped (active may be null); resid_skinny_ok(L) tells whether it applies.
 bool resid_skinny_ok(int L);
+// Real FP32 corrections for a real NEP at real points: Tr = (float) Re T;
+// D = (float)(Re R * inv) (inv may be null: 1); X = (D, 0) (scale null) or
+// Re X += scale * D.
+hipError_t narrow_real(hipStream_t st, int n, const double2* T, int ldt, long sT, float* Tr, int ldr, long sTr,
+                       int B);
+hipError_t scale_narrow_real(hipStream_t st, int n, int L, const double2* R, int ldr, long sR, const double* inv,
+                             float* D, int ldd, long sD, const int* active, int B);
+hipError_t axpy_widen_real(hipStream_t st, int n, int L, const float* D, int ldd, long sD, const double* scale,
+                           double2* X, int ldx, long sX, const int* active, int B);
 hipError_t resid_skinny(hipStream_t st, int n, int L, const double2* T, int ldt, long sT, const double2* X, int ldx,
                         long sX, const double2* U, int ldu, long sU, double2* R, int ldr, long sR, const int* active,
                         int B);

@@ -28,12 +28,12 @@ namespace rsrr {
 // Panel base: rows [c0, n) x columns [c0, c0+jb) of one matrix per workgroup,
 // held in registers (thread t owns local rows t, t+NT, ...).
 // ----------------------------------------------------------------------------
-template <typename R, int NT, int RPT, int JB>
+template <typename C, int NT, int RPT, int JB>
 __global__ __launch_bounds__(NT) void panel_base_kernel(
-    typename cpx<R>::T* __restrict__ A, long sA, int lda, int n, int c0, int jb,
+    C* __restrict__ A, long sA, int lda, int n, int c0, int jb,
     int* __restrict__ ipiv, long sP, int* __restrict__ info, const int* __restrict__ active)
 {
-    typedef typename cpx<R>::T C;
+    typedef real_t<C> R;
     const int b = blockIdx.x;
     if (active && !active[b]) return;
     C* Ab = A + (long)b * sA;
@@ -125,8 +125,8 @@ __global__ __launch_bounds__(NT) void panel_base_kernel(
             }
         }
         const C piv = prow[c];
-        const bool zero = (piv.x == (R)0 && piv.y == (R)0);
-        const bool bad = !(isfinite(piv.x) && isfinite(piv.y));
+        const bool zero = is_zero(piv);
+        const bool bad = !all_finite(piv);
         if (tid == 0) {
             pv[c0 + c] = c0 + p;
             if (info[b] == 0) {
@@ -227,14 +227,14 @@ __global__ __launch_bounds__(64) void perm_build_kernel(const int* __restrict__ 
 constexpr int TS_NT = 256;
 
 // MJB: widest diagonal block staged in LDS; TC: columns per workgroup.
-template <typename R, int MJB, int TC>
+template <typename C, int MJB, int TC>
 __global__ __launch_bounds__(TS_NT) void perm_trsm_kernel(
-    const typename cpx<R>::T* __restrict__ LU, long sLU, int ldl,
+    const C* __restrict__ LU, long sLU, int ldl,
     const int2* __restrict__ perm, long sPerm,
-    typename cpx<R>::T* __restrict__ X, long sX, int ldx, int xr0,
+    C* __restrict__ X, long sX, int ldx, int xr0,
     int c0, int jb, int ncols, int mode, const int* __restrict__ active)
 {
-    typedef typename cpx<R>::T C;
+    typedef real_t<C> R;
     const int b = blockIdx.y;
     if (active && !active[b]) return;
     const C* Lb = LU + (long)b * sLU;
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(TS_NT) void perm_trsm_kernel(
             }
         }
     } else if (mode >= 4) {
-        for (int s = grp; s < jb; s += NG) top[s][col] = mk((R)(s == gcol ? 1 : 0), (R)0);
+        for (int s = grp; s < jb; s += NG) top[s][col] = from_real<C>((R)(s == gcol ? 1 : 0));
     } else {
         for (int s = grp; s < jb; s += NG)
             top[s][col] = colok ? Xb[(c0 + s) + (long)gcol * ldx] : czero<C>();
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(TS_NT) void perm_trsm_kernel(
         for (int l = jb - 1; l >= 0; --l) {
             if (grp == 0) {
                 const C d = Ld[l][l];
-                top[l][col] = (d.x == (R)0 && d.y == (R)0) ? top[l][col] : cmul(top[l][col], crecip(d));
+                top[l][col] = is_zero(d) ? top[l][col] : cmul(top[l][col], crecip(d));
             }
             __syncthreads();
             const C xl = top[l][col];
@@ -328,12 +328,12 @@ __global__ __launch_bounds__(TS_NT) void perm_trsm_kernel(
 // ----------------------------------------------------------------------------
 constexpr int PR_TC = 32;
 
-template <typename R>
+template <typename C>
 __global__ __launch_bounds__(2 * MAX_NB) void perm_rows_kernel(
-    const int2* __restrict__ perm, long sPerm, typename cpx<R>::T* __restrict__ X, long sX, int ldx,
-    typename cpx<R>::T* __restrict__ T, long sT, int ldt, int c0, int jb, int ncols, const int* __restrict__ active)
+    const int2* __restrict__ perm, long sPerm, C* __restrict__ X, long sX, int ldx,
+    C* __restrict__ T, long sT, int ldt, int c0, int jb, int ncols, const int* __restrict__ active)
 {
-    typedef typename cpx<R>::T C;
+    typedef real_t<C> R;
     const int b = blockIdx.y;
     if (active && !active[b]) return;
     C* Xb = X + (long)b * sX;
@@ -368,20 +368,21 @@ template <typename R> static int base_width(int m);
 template <> int base_width<float>(int m) { return m <= 4096 ? 8 : 4; }
 template <> int base_width<double>(int m) { return m <= 2048 ? 8 : (m <= 4096 ? 4 : 2); }
 
-template <typename R, int NT, int RPT, int JB>
-static void launch_base(hipStream_t st, typename cpx<R>::T* A, long sA, int lda, int n, int c0, int jb,
+template <typename C, int NT, int RPT, int JB>
+static void launch_base(hipStream_t st, C* A, long sA, int lda, int n, int c0, int jb,
                         int* ipiv, long sP, int* info, const int* active, int batch)
 {
-    hipLaunchKernelGGL((panel_base_kernel<R, NT, RPT, JB>), dim3(batch), dim3(NT), 0, st,
+    hipLaunchKernelGGL((panel_base_kernel<C, NT, RPT, JB>), dim3(batch), dim3(NT), 0, st,
                        A, sA, lda, n, c0, jb, ipiv, sP, info, active);
 }
 
-template <typename R>
-static void panel_base(hipStream_t st, typename cpx<R>::T* A, long sA, int lda, int n, int c0, int jb,
+template <typename C>
+static void panel_base(hipStream_t st, C* A, long sA, int lda, int n, int c0, int jb,
                        int* ipiv, long sP, int* info, const int* active, int batch)
 {
+    typedef real_t<C> R;
     const int m = n - c0;
-#define PB(NT, RPT, JB) launch_base<R, NT, RPT, JB>(st, A, sA, lda, n, c0, jb, ipiv, sP, info, active, batch)
+#define PB(NT, RPT, JB) launch_base<C, NT, RPT, JB>(st, A, sA, lda, n, c0, jb, ipiv, sP, info, active, batch)
     if (m <= 256) {
         PB(256, 1, 8);
     } else if (m <= 512) {
@@ -398,99 +399,109 @@ static void panel_base(hipStream_t st, typename cpx<R>::T* A, long sA, int lda, 
 #undef PB
 }
 
-template <typename R>
-static void perm_trsm(hipStream_t st, const typename cpx<R>::T* LU, long sLU, int ldl, const int2* perm, long sPerm,
-                      typename cpx<R>::T* X, long sX, int ldx, int c0, int jb, int ncols, int mode,
+template <typename C>
+static void perm_trsm(hipStream_t st, const C* LU, long sLU, int ldl, const int2* perm, long sPerm,
+                      C* X, long sX, int ldx, int c0, int jb, int ncols, int mode,
                       const int* active, int batch, int xr0 = 0)
 {
+    typedef real_t<C> R;
     if (ncols <= 0 || jb <= 0) return;
     if (jb <= 64) {
         constexpr int TC = 32;
         dim3 g((ncols + TC - 1) / TC, batch);
-        hipLaunchKernelGGL((perm_trsm_kernel<R, 64, TC>), g, dim3(TS_NT), 0, st, LU, sLU, ldl, perm, sPerm, X, sX, ldx,
+        hipLaunchKernelGGL((perm_trsm_kernel<C, 64, TC>), g, dim3(TS_NT), 0, st, LU, sLU, ldl, perm, sPerm, X, sX, ldx,
                            xr0, c0, jb, ncols, mode, active);
     } else {
         constexpr int MJB = max_panel<R>();
         constexpr int TC = 16;
         dim3 g((ncols + TC - 1) / TC, batch);
-        hipLaunchKernelGGL((perm_trsm_kernel<R, MJB, TC>), g, dim3(TS_NT), 0, st, LU, sLU, ldl, perm, sPerm, X, sX,
+        hipLaunchKernelGGL((perm_trsm_kernel<C, MJB, TC>), g, dim3(TS_NT), 0, st, LU, sLU, ldl, perm, sPerm, X, sX,
                            ldx, xr0, c0, jb, ncols, mode, active);
     }
 }
 
-template <typename R>
-static void perm_rows(hipStream_t st, const int2* perm, long sPerm, typename cpx<R>::T* X, long sX, int ldx,
-                      typename cpx<R>::T* T, long sT, int ldt, int c0, int jb, int ncols, const int* active, int batch)
+template <typename C>
+static void perm_rows(hipStream_t st, const int2* perm, long sPerm, C* X, long sX, int ldx,
+                      C* T, long sT, int ldt, int c0, int jb, int ncols, const int* active, int batch)
 {
     if (ncols <= 0 || jb <= 0) return;
     dim3 g((ncols + PR_TC - 1) / PR_TC, batch);
-    hipLaunchKernelGGL(perm_rows_kernel<R>, g, dim3(2 * MAX_NB), 0, st, perm, sPerm, X, sX, ldx, T, sT, ldt, c0, jb,
+    hipLaunchKernelGGL(perm_rows_kernel<C>, g, dim3(2 * MAX_NB), 0, st, perm, sPerm, X, sX, ldx, T, sT, ldt, c0, jb,
                        ncols, active);
 }
 
 // C = beta C - alpha A B (defaults alpha = beta = 1: C -= A B).  The products
 // C = A B with the diagonal-block inverses use alpha = -1, beta = 0.
-template <typename R>
-static hipError_t gemm_sub(hipStream_t st, int M, int N, int K, const typename cpx<R>::T* A, int lda, long sA,
-                           const typename cpx<R>::T* B, int ldb, long sB, typename cpx<R>::T* Cm, int ldc, long sC,
+template <typename C>
+static hipError_t gemm_sub(hipStream_t st, int M, int N, int K, const C* A, int lda, long sA,
+                           const C* B, int ldb, long sB, C* Cm, int ldc, long sC,
                            int batch, int tag = 0, double alpha = 1.0, double beta = 1.0);
 template <>
-hipError_t gemm_sub<float>(hipStream_t st, int M, int N, int K, const float2* A, int lda, long sA, const float2* B,
+hipError_t gemm_sub<float2>(hipStream_t st, int M, int N, int K, const float2* A, int lda, long sA, const float2* B,
                            int ldb, long sB, float2* Cm, int ldc, long sC, int batch, int tag, double alpha,
                            double beta)
 {
     return cgemm(st, M, N, K, (float)-alpha, A, lda, sA, B, ldb, sB, (float)beta, Cm, ldc, sC, batch, tag);
 }
 template <>
-hipError_t gemm_sub<double>(hipStream_t st, int M, int N, int K, const double2* A, int lda, long sA,
+hipError_t gemm_sub<double2>(hipStream_t st, int M, int N, int K, const double2* A, int lda, long sA,
                             const double2* B, int ldb, long sB, double2* Cm, int ldc, long sC, int batch, int tag,
                             double alpha, double beta)
 {
     return zgemm(st, 0, 0, M, N, K, -alpha, A, lda, sA, B, ldb, sB, beta, Cm, ldc, sC, batch, tag);
 }
 
+template <>
+hipError_t gemm_sub<float>(hipStream_t st, int M, int N, int K, const float* A, int lda, long sA, const float* B,
+                           int ldb, long sB, float* Cm, int ldc, long sC, int batch, int tag, double alpha,
+                           double beta)
+{
+    return sgemm(st, M, N, K, (float)-alpha, A, lda, sA, B, ldb, sB, (float)beta, Cm, ldc, sC, batch, tag);
+}
+
 // Recursive panel factorisation of columns [c0, c0+w) (rows c0..n-1).
-template <typename R>
-static void factor_panel(hipStream_t st, typename cpx<R>::T* A, long sA, int lda, int n, int c0, int w,
+template <typename C>
+static void factor_panel(hipStream_t st, C* A, long sA, int lda, int n, int c0, int w,
                          int* ipiv, long sP, int* info, int2* tperm, long sTP, int depth, const int* active,
                          int batch)
 {
+    typedef real_t<C> R;
     const int m = n - c0;
     const int jbase = base_width<R>(m);
     if (w <= jbase) {
-        panel_base<R>(st, A, sA, lda, n, c0, w, ipiv, sP, info, active, batch);
+        panel_base<C>(st, A, sA, lda, n, c0, w, ipiv, sP, info, active, batch);
         return;
     }
     int w1 = (w / 2) / jbase * jbase;
     if (w1 < jbase) w1 = jbase;
     const int w2 = w - w1;
     int2* pm = tperm + (long)depth * 2 * MAX_NB;
-    factor_panel<R>(st, A, sA, lda, n, c0, w1, ipiv, sP, info, tperm, sTP, depth + 1, active, batch);
+    factor_panel<C>(st, A, sA, lda, n, c0, w1, ipiv, sP, info, tperm, sTP, depth + 1, active, batch);
     // right half: interchanges of the left half, U12 = L11^-1 A12, A22 -= L21 U12
     hipLaunchKernelGGL(perm_build_kernel, dim3(batch), dim3(64), 0, st, ipiv, sP, c0, w1, pm, sTP, active);
-    typename cpx<R>::T* Ar = A + (long)(c0 + w1) * lda;
-    perm_trsm<R>(st, A, sA, lda, pm, sTP, Ar, sA, lda, c0, w1, w2, 1, active, batch);
-    (void)gemm_sub<R>(st, m - w1, w2, w1, A + (c0 + w1) + (long)c0 * lda, lda, sA, A + c0 + (long)(c0 + w1) * lda, lda, sA,
+    C* Ar = A + (long)(c0 + w1) * lda;
+    perm_trsm<C>(st, A, sA, lda, pm, sTP, Ar, sA, lda, c0, w1, w2, 1, active, batch);
+    (void)gemm_sub<C>(st, m - w1, w2, w1, A + (c0 + w1) + (long)c0 * lda, lda, sA, A + c0 + (long)(c0 + w1) * lda, lda, sA,
                 A + (c0 + w1) + (long)(c0 + w1) * lda, lda, sA, batch);
-    factor_panel<R>(st, A, sA, lda, n, c0 + w1, w2, ipiv, sP, info, tperm, sTP, depth + 1, active, batch);
+    factor_panel<C>(st, A, sA, lda, n, c0 + w1, w2, ipiv, sP, info, tperm, sTP, depth + 1, active, batch);
     // left half receives the interchanges of the right half
     hipLaunchKernelGGL(perm_build_kernel, dim3(batch), dim3(64), 0, st, ipiv, sP, c0 + w1, w2, pm, sTP, active);
-    perm_trsm<R>(st, A, sA, lda, pm, sTP, A + (long)c0 * lda, sA, lda, c0 + w1, w2, w1, 0, active, batch);
+    perm_trsm<C>(st, A, sA, lda, pm, sTP, A + (long)c0 * lda, sA, lda, c0 + w1, w2, w1, 0, active, batch);
 }
 
 // Diagonal-block inverses of panel p (complex-FP32 path): L11^-1 at
 // inv + (2p) nb^2, U11^-1 at inv + (2p+1) nb^2, ld nb.
-template <typename R>
-static typename cpx<R>::T* panel_inv(const LUWork& w, int p, int nb, int which)
+template <typename C>
+static C* panel_inv(const LUWork& w, int p, int nb, int which)
 {
-    return (typename cpx<R>::T*)w.inv + (long)(2 * p + which) * nb * nb;
+    return (C*)w.inv + (long)(2 * p + which) * nb * nb;
 }
 
-template <typename R>
-hipError_t getrf_batched(hipStream_t st, typename cpx<R>::T* A, long sA, int lda, int n, int nb, const LUWork& w,
+template <typename C>
+static hipError_t getrf_impl(hipStream_t st, C* A, long sA, int lda, int n, int nb, const LUWork& w,
                          int batch)
 {
-    typedef typename cpx<R>::T C;
+    typedef real_t<C> R;
     constexpr bool use_inv = sizeof(R) == 4;
     if (nb > max_panel<R>()) nb = max_panel<R>();
     if (nb < MIN_NB) nb = MIN_NB;  // perm/inv storage holds perm_panels(n) panels
@@ -498,36 +509,36 @@ hipError_t getrf_batched(hipStream_t st, typename cpx<R>::T* A, long sA, int lda
     for (int c0 = 0; c0 < n; c0 += nb) {
         const int jb = (n - c0 < nb) ? n - c0 : nb;
         const int p = c0 / nb;
-        factor_panel<R>(st, A, sA, lda, n, c0, jb, w.ipiv, w.sP, w.info, w.tperm, w.sTP, 0, w.active, batch);
+        factor_panel<C>(st, A, sA, lda, n, c0, jb, w.ipiv, w.sP, w.info, w.tperm, w.sTP, 0, w.active, batch);
         int2* pm = w.perm + (long)p * 2 * MAX_NB;
         hipLaunchKernelGGL(perm_build_kernel, dim3(batch), dim3(64), 0, st, w.ipiv, w.sP, c0, jb, pm, w.sPerm, w.active);
         const int rest = n - c0 - jb;
         if (use_inv) {
             // L11^-1 and U11^-1 of this panel (also used by the solves)
-            perm_trsm<R>(st, A, sA, lda, (const int2*)nullptr, 0, panel_inv<R>(w, p, nb, 0), w.sInv, nb, c0, jb, jb, 4,
+            perm_trsm<C>(st, A, sA, lda, (const int2*)nullptr, 0, panel_inv<C>(w, p, nb, 0), w.sInv, nb, c0, jb, jb, 4,
                          w.active, batch, c0);
-            perm_trsm<R>(st, A, sA, lda, (const int2*)nullptr, 0, panel_inv<R>(w, p, nb, 1), w.sInv, nb, c0, jb, jb, 5,
+            perm_trsm<C>(st, A, sA, lda, (const int2*)nullptr, 0, panel_inv<C>(w, p, nb, 1), w.sInv, nb, c0, jb, jb, 5,
                          w.active, batch, c0);
         }
         if (rest > 0) {
             C* Ar = A + (long)(c0 + jb) * lda;
             if (use_inv) {
                 // interchanges on the right block (top rows to the scratch), then U12 = L11^-1 A12 on MFMA
-                perm_rows<R>(st, pm, w.sPerm, Ar, sA, lda, (C*)w.tmp, w.sTmp, nb, c0, jb, rest, w.active, batch);
-                (void)gemm_sub<R>(st, jb, rest, jb, panel_inv<R>(w, p, nb, 0), nb, w.sInv, (const C*)w.tmp, nb,
+                perm_rows<C>(st, pm, w.sPerm, Ar, sA, lda, (C*)w.tmp, w.sTmp, nb, c0, jb, rest, w.active, batch);
+                (void)gemm_sub<C>(st, jb, rest, jb, panel_inv<C>(w, p, nb, 0), nb, w.sInv, (const C*)w.tmp, nb,
                                   w.sTmp, Ar + c0, lda, sA, batch, 0, -1.0, 0.0);
             } else {
-                perm_trsm<R>(st, A, sA, lda, pm, w.sPerm, Ar, sA, lda, c0, jb, rest, 1, w.active, batch);
+                perm_trsm<C>(st, A, sA, lda, pm, w.sPerm, Ar, sA, lda, c0, jb, rest, 1, w.active, batch);
             }
             if (c0 == 0 && w.first_panel) (void)hipEventRecord(w.first_panel, st);
             const bool timed = rec && rec->used < rec->cap;
             if (timed) (void)hipEventRecord(rec->ev[2 * rec->used], st);
-            (void)gemm_sub<R>(st, rest, rest, jb, A + (c0 + jb) + (long)c0 * lda, lda, sA, Ar + c0, lda, sA,
+            (void)gemm_sub<C>(st, rest, rest, jb, A + (c0 + jb) + (long)c0 * lda, lda, sA, Ar + c0, lda, sA,
                               Ar + c0 + jb, lda, sA, batch, 1);
             if (timed) {
                 (void)hipEventRecord(rec->ev[2 * rec->used + 1], st);
                 rec->used++;
-                rec->flops += 8.0 * rest * (double)rest * jb * batch;
+                rec->flops += (elem_traits<C>::complex ? 8.0 : 2.0) * rest * (double)rest * jb * batch;
             } else if (rec) {
                 rec->dropped++;
             }
@@ -536,11 +547,11 @@ hipError_t getrf_batched(hipStream_t st, typename cpx<R>::T* A, long sA, int lda
     return hipGetLastError();
 }
 
-template <typename R>
-hipError_t getrs_batched(hipStream_t st, const typename cpx<R>::T* LU, long sLU, int lda, int n, int nb,
-                         const LUWork& w, typename cpx<R>::T* X, long sX, int ldx, int nrhs, int batch)
+template <typename C>
+static hipError_t getrs_impl(hipStream_t st, const C* LU, long sLU, int lda, int n, int nb,
+                         const LUWork& w, C* X, long sX, int ldx, int nrhs, int batch)
 {
-    typedef typename cpx<R>::T C;
+    typedef real_t<C> R;
     constexpr bool use_inv = sizeof(R) == 4;
     if (nb > max_panel<R>()) nb = max_panel<R>();
     if (nb < MIN_NB) nb = MIN_NB;
@@ -549,37 +560,63 @@ hipError_t getrs_batched(hipStream_t st, const typename cpx<R>::T* LU, long sLU,
         const int c0 = p * nb, jb = (n - c0 < nb) ? n - c0 : nb;
         const int2* pm = w.perm + (long)p * 2 * MAX_NB;
         if (use_inv) {
-            perm_rows<R>(st, pm, w.sPerm, X, sX, ldx, (C*)w.tmp, w.sTmp, nb, c0, jb, nrhs, w.active, batch);
-            (void)gemm_sub<R>(st, jb, nrhs, jb, panel_inv<R>(w, p, nb, 0), nb, w.sInv, (const C*)w.tmp, nb, w.sTmp,
+            perm_rows<C>(st, pm, w.sPerm, X, sX, ldx, (C*)w.tmp, w.sTmp, nb, c0, jb, nrhs, w.active, batch);
+            (void)gemm_sub<C>(st, jb, nrhs, jb, panel_inv<C>(w, p, nb, 0), nb, w.sInv, (const C*)w.tmp, nb, w.sTmp,
                               X + c0, ldx, sX, batch, 0, -1.0, 0.0);
         } else {
-            perm_trsm<R>(st, LU, sLU, lda, pm, w.sPerm, X, sX, ldx, c0, jb, nrhs, 1, w.active, batch);
+            perm_trsm<C>(st, LU, sLU, lda, pm, w.sPerm, X, sX, ldx, c0, jb, nrhs, 1, w.active, batch);
         }
         const int rest = n - c0 - jb;
         if (rest > 0)
-            (void)gemm_sub<R>(st, rest, nrhs, jb, LU + (c0 + jb) + (long)c0 * lda, lda, sLU, X + c0, ldx, sX,
+            (void)gemm_sub<C>(st, rest, nrhs, jb, LU + (c0 + jb) + (long)c0 * lda, lda, sLU, X + c0, ldx, sX,
                               X + c0 + jb, ldx, sX, batch);
     }
     for (int p = np - 1; p >= 0; --p) {
         const int c0 = p * nb, jb = (n - c0 < nb) ? n - c0 : nb;
         if (use_inv) {
-            perm_rows<R>(st, nullptr, 0, X, sX, ldx, (C*)w.tmp, w.sTmp, nb, c0, jb, nrhs, w.active, batch);
-            (void)gemm_sub<R>(st, jb, nrhs, jb, panel_inv<R>(w, p, nb, 1), nb, w.sInv, (const C*)w.tmp, nb, w.sTmp,
+            perm_rows<C>(st, nullptr, 0, X, sX, ldx, (C*)w.tmp, w.sTmp, nb, c0, jb, nrhs, w.active, batch);
+            (void)gemm_sub<C>(st, jb, nrhs, jb, panel_inv<C>(w, p, nb, 1), nb, w.sInv, (const C*)w.tmp, nb, w.sTmp,
                               X + c0, ldx, sX, batch, 0, -1.0, 0.0);
         } else {
-            perm_trsm<R>(st, LU, sLU, lda, nullptr, 0, X, sX, ldx, c0, jb, nrhs, 2, w.active, batch);
+            perm_trsm<C>(st, LU, sLU, lda, nullptr, 0, X, sX, ldx, c0, jb, nrhs, 2, w.active, batch);
         }
         if (c0 > 0)
-            (void)gemm_sub<R>(st, c0, nrhs, jb, LU + (long)c0 * lda, lda, sLU, X + c0, ldx, sX, X, ldx, sX, batch);
+            (void)gemm_sub<C>(st, c0, nrhs, jb, LU + (long)c0 * lda, lda, sLU, X + c0, ldx, sX, X, ldx, sX, batch);
     }
     return hipGetLastError();
 }
 
-template hipError_t getrf_batched<float>(hipStream_t, float2*, long, int, int, int, const LUWork&, int);
-template hipError_t getrf_batched<double>(hipStream_t, double2*, long, int, int, int, const LUWork&, int);
-template hipError_t getrs_batched<float>(hipStream_t, const float2*, long, int, int, int, const LUWork&, float2*, long,
-                                         int, int, int);
-template hipError_t getrs_batched<double>(hipStream_t, const double2*, long, int, int, int, const LUWork&, double2*,
-                                          long, int, int, int);
+template <>
+hipError_t getrf_batched<float>(hipStream_t st, float2* A, long sA, int lda, int n, int nb, const LUWork& w, int batch)
+{
+    return getrf_impl<float2>(st, A, sA, lda, n, nb, w, batch);
+}
+template <>
+hipError_t getrf_batched<double>(hipStream_t st, double2* A, long sA, int lda, int n, int nb, const LUWork& w,
+                                 int batch)
+{
+    return getrf_impl<double2>(st, A, sA, lda, n, nb, w, batch);
+}
+template <>
+hipError_t getrs_batched<float>(hipStream_t st, const float2* LU, long sLU, int lda, int n, int nb, const LUWork& w,
+                                float2* X, long sX, int ldx, int nrhs, int batch)
+{
+    return getrs_impl<float2>(st, LU, sLU, lda, n, nb, w, X, sX, ldx, nrhs, batch);
+}
+template <>
+hipError_t getrs_batched<double>(hipStream_t st, const double2* LU, long sLU, int lda, int n, int nb,
+                                 const LUWork& w, double2* X, long sX, int ldx, int nrhs, int batch)
+{
+    return getrs_impl<double2>(st, LU, sLU, lda, n, nb, w, X, sX, ldx, nrhs, batch);
+}
+hipError_t getrf_real_batched(hipStream_t st, float* A, long sA, int lda, int n, int nb, const LUWork& w, int batch)
+{
+    return getrf_impl<float>(st, A, sA, lda, n, nb, w, batch);
+}
+hipError_t getrs_real_batched(hipStream_t st, const float* LU, long sLU, int lda, int n, int nb, const LUWork& w,
+                              float* X, long sX, int ldx, int nrhs, int batch)
+{
+    return getrs_impl<float>(st, LU, sLU, lda, n, nb, w, X, sX, ldx, nrhs, batch);
+}
 
 }  // namespace rsrr

@@ -32,6 +32,7 @@ RSRR_T_SEPARABLE = 0
 RSRR_T_HELMHOLTZ = 1
 RSRR_PREC_C128 = 0
 RSRR_PREC_C64_IR = 1
+RSRR_PREC_R32_IR = 2
 
 STATUS_NAMES = {0: "OK", 1: "ESINGULAR", 2: "WARN_FALLBACK", 3: "WARN_GAP", 4: "ENOMEM", 5: "EDEVICE",
                 6: "ENOTCONV", 7: "ENAN", 8: "ETIMEOUT"}

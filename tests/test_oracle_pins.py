@@ -368,3 +368,24 @@ def test_moment_scheme_span_and_robustness():
     i4, i_s = r4["level"] < 0.98, rs["level"] < 0.98
     assert _match(r4["lam"][i4], ex) > 1e-6
     assert _match(rs["lam"][i_s], ex) < 1e-9
+
+
+def test_real_sampling_on_chebyshev_points_finds_the_string_eigenvalues():
+    """Real sampling (Sec. 5.1, Example 1): Chebyshev points of the interval [3, 10000] and
+    real probes make S real; SS-RR on it finds the 32 eigenvalues of the loaded string in
+    the interval (the paper's count) with residuals below 1e-10."""
+    g = json.load(open(os.path.join(HERE, "golden", "loaded_string.json")))
+    nep = W.loaded_string(g["n"])
+    prob = O.Problem(nep)
+    lo, hi = g["interval"]
+    z = W.interval_points(lo, hi, 48)
+    assert np.all(z.imag == 0) and np.allclose(np.sort(z.real), np.sort((lo + hi) / 2 + (hi - lo) / 2 * O.chebyshev_points(48)))
+    U = W.real_probes(g["n"], 2, 78)
+    S = O.sample(prob, z, U)
+    assert np.max(np.abs(S.imag)) == 0.0
+    a = g["contour"]["a"]
+    C = W.Contour(g["contour"]["gamma"] + 0j, a, a * g["contour"]["b_over_a"], 64)
+    r = O.rsrr(prob, C, U, NQ=500, S=S)
+    lam = r["lam"]
+    sel = (lam.real >= lo) & (lam.real <= hi) & (r["level"] < 1) & (r["res"] < 1e-10)
+    assert int(sel.sum()) == g["count"]

@@ -196,6 +196,19 @@ def probes(n, L, seed):
     return np.asfortranarray(complex_gaussian(rng, (n, L)))
 
 
+def real_probes(n, L, seed):
+    """Real probe matrix (standard normal) for real sampling of a real NEP, stored complex."""
+    rng = np.random.default_rng(seed)
+    return np.asfortranarray(rng.standard_normal((n, L)).astype(np.complex128))
+
+
+def interval_points(lo, hi, N):
+    """Chebyshev points of the first kind mapped to the real interval [lo, hi] (complex dtype)."""
+    i = np.arange(N)
+    x = np.cos((2 * i + 1) * np.pi / (2 * N))
+    return ((lo + hi) / 2 + (hi - lo) / 2 * x).astype(np.complex128)
+
+
 # ---------------------------------------------------------------------------
 # The benchmark configurations, with the readings of the paper-silent details.
 # ---------------------------------------------------------------------------
