@@ -16,6 +16,8 @@
  *   rsrr_two_stage        the two-stage strategy of Sec. 5.2-5.3: stage-1
  *                 eigenvalue estimates become extra sampling points
  *   rsrr_sample_batched   Step 2 for a ragged batch of NEP instances
+ *   rsrr_sample_gmres     Step 2 with an iterative solver: flexible GMRES,
+ *                 preconditioned by LU factors reused across points
  *   rsrr_server_* a request loop that runs all of the above for many NEPs at
  *                 once (continuous batching of their sampling points)
  *
@@ -132,7 +134,11 @@ typedef struct rsrr_ctx rsrr_ctx;
 
 /* Create a context on HIP device `device` that enqueues on `stream` (a
  * hipStream_t; NULL = the null stream).  Workspace is allocated lazily and
- * owned by the context.  Errors: -1 ctx NULL, -2 bad device, RSRR_EDEVICE. */
+ * owned by the context.  The per-call point buffers of rsrr_sample and
+ * rsrr_sample_gmres are sized to half of the free device memory, or to the
+ * environment variable RSRR_WS_BUDGET_MB (MiB) when it is set at creation;
+ * larger calls run in chunks of points.
+ * Errors: -1 ctx NULL, -2 bad device, RSRR_EDEVICE. */
 RSRR_API rsrr_status rsrr_create(rsrr_ctx **ctx, int device, void *stream);
 
 /* Release the context and its workspace.  Errors: -1 ctx NULL. */
@@ -159,6 +165,44 @@ RSRR_API rsrr_status rsrr_contour(double gamma_re, double gamma_im, double a, do
 RSRR_API rsrr_status rsrr_sample(rsrr_ctx *ctx, const rsrr_nep *nep, int N, const double *z,
                         const double *U, int L, int ldu, int prec,
                         double *S, int lds, rsrr_point_info *info);
+
+/* Per sampling point diagnostics of rsrr_sample_gmres. */
+typedef struct {
+    int iters;         /* Arnoldi steps, max over the point's columns              */
+    int restarts;      /* restart cycles after the first, max over its columns     */
+    int converged;     /* 1 when every column met tol                               */
+    int ref;           /* the reference point whose factors preconditioned it      */
+    double resid;      /* max over columns of ||u_c - T(z_k) x_c||_2 / ||u_c||_2, FP64 */
+} rsrr_gmres_info;
+
+/* Resolvent sampling with an iterative solver (RSRR Step 2, eq. hatS; Sec. 4.3
+ * leaves the solver of T(z_k)^-1 U to the host software and names iterative
+ * solvers for large boundary-element and finite-element models, as used in
+ * Sec. 6).  Every point k and probe column l is one system T(z_k) x = u_l,
+ * solved by restarted flexible GMRES with right preconditioning.  The
+ * preconditioner of point k is the complex FP32 LU of T(zref[r]) at one of
+ * nref reference points (host, 2*nref doubles): r = ref[k] (host, N ints in
+ * [0, nref)), or the nearest reference when ref is NULL; each used reference
+ * is factored once.  The operator T(z_k), the Krylov vectors and the
+ * residuals are FP64.  A column stops when its FP64 relative residual
+ * ||u - T(z_k) x||_2 / ||u||_2 is at most tol (0 < tol < 1), measured on the
+ * true residual at the end of each restart cycle of at most `restart` steps
+ * (1..64), or after max_iters steps.  z, U, S, lds and ldu are as for
+ * rsrr_sample (S: device, n x N*L, block k in columns k*L .. k*L+L-1).
+ * info: host, N entries (may be NULL).  Phase times (ms) of the last call via
+ * rsrr_last_timings: [reference assembly + LU and per-point FP64 operator
+ * assembly, operator applications, preconditioner applications, Krylov
+ * cycles (all of the iteration), total].
+ * Status: RSRR_ENOTCONV if a column missed tol within max_iters (S still holds
+ * the last iterate; info says which points), RSRR_ESINGULAR / RSRR_ENAN if a
+ * reference matrix had an exact zero / non-finite pivot (nothing solved).
+ * Errors: -2 nep invalid (n > 8192), -3 N < 1, -4 z NULL, -5 nref < 1,
+ * -6 zref NULL, -7 a ref[k] out of range, -8 U NULL, -9 L < 1, -10 ldu < n,
+ * -11 tol, -12 restart, -13 max_iters < 1, -14 S NULL, -15 lds < n. */
+RSRR_API rsrr_status rsrr_sample_gmres(rsrr_ctx *ctx, const rsrr_nep *nep, int N, const double *z,
+                                       int nref, const double *zref, const int *ref,
+                                       const double *U, int L, int ldu, double tol, int restart,
+                                       int max_iters, double *S, int lds, rsrr_gmres_info *info);
 
 /* Basis (RSRR Step 3, Sec. 4.2-4.3).  S (device, n x NL, lds) is normalised
  * in place to unit column norms, then its singular values sigma (host,

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -70,6 +71,7 @@ rsrr_status rsrr_create(rsrr_ctx** ctx, int device, void* stream)
     rsrr_ctx* c = new rsrr_ctx();
     c->device = device;
     c->stream = (hipStream_t)stream;
+    if (const char* e = std::getenv("RSRR_WS_BUDGET_MB")) c->ws_budget = (size_t)std::strtoull(e, nullptr, 10) << 20;
     for (auto& e : c->ev)
         if (hipEventCreate(&e) != hipSuccess) { delete c; return RSRR_EDEVICE; }
     if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||

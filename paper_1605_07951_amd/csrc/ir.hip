@@ -310,8 +310,14 @@ __global__ __launch_bounds__(RW) void resid_skinny_kernel(int n, int L, const do
         __syncthreads();
     }
     if (row >= n) return;
-    const double2* Ub = U + b * sU;
     double2* Rb = R + b * sR;
+    if (!U) {  // R = T X
+#pragma unroll
+        for (int c = 0; c < LC; ++c)
+            if (c < L) Rb[row + (long)c * ldr] = acc[c];
+        return;
+    }
+    const double2* Ub = U + b * sU;
 #pragma unroll
     for (int c = 0; c < LC; ++c)
         if (c < L) {

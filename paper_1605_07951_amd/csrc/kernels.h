@@ -97,7 +97,8 @@ hipError_t bcast_c128(hipStream_t st, int n, int L, const double2* U, int ldu, d
 hipError_t widen(hipStream_t st, int n, int L, const float2* D, int ldd, long sD, double2* X, int ldx, long sX, int B);
 hipError_t colnorms(hipStream_t st, int n, int L, const double2* X, int ldx, long sX, double* out, int B);
 // R_b = U_b - T_b X_b (FP64) for L <= 16 columns, matrices with active[b] == 0
-// skipped (active may be null); resid_skinny_ok(L) tells whether it applies.
+// skipped (active may be null); U null gives R_b = T_b X_b.  resid_skinny_ok(L)
+// tells whether it applies.
 bool resid_skinny_ok(int L);
 // Real FP32 corrections for a real NEP at real points: Tr = (float) Re T;
 // D = (float)(Re R * inv) (inv may be null: 1); X = (D, 0) (scale null) or
@@ -136,6 +137,31 @@ hipError_t gather_scale(hipStream_t st, const double2* A, int lda, int m, const 
 hipError_t gaussian(hipStream_t st, double2* X, int n, int m, int ld, unsigned long long seed);
 hipError_t bcgs2(hipStream_t st, double2* Y, int ld, int n, int m, void* work, double* n0);
 size_t bcgs2_work_bytes(int n, int m);
+
+// ---- flexible GMRES over many columns (gmres.hip) ----
+// C independent systems side by side (column c of an n x C block belongs to
+// point c / L); per-column small arrays are index-major ([i * C + c]).
+int gm_slices(int n);        // row slices of the column kernels (partials per column)
+int gm_max_restart();        // longest restart cycle
+hipError_t gm_point_scale(hipStream_t st, int n, int C, int L, const double2* Z, int ldz, const double2* coef,
+                          double2* Y, int ldy);
+hipError_t gm_narrow(hipStream_t st, int n, int C, const double2* V, int ldv, float2* D, int ldd);
+hipError_t gm_widen(hipStream_t st, int n, int C, const float2* D, int ldd, double2* Z, int ldz);
+hipError_t gm_resid(hipStream_t st, int n, int C, int L, const double2* U, int ldu, double2* V, int ldv);
+hipError_t gm_scale(hipStream_t st, int n, int C, const double* s, double2* X, int ldx);
+hipError_t gm_scatter(hipStream_t st, int n, int C, int L, const double2* X, int ldx, const int* idx, double2* S,
+                      int lds);
+// One classical Gram-Schmidt pass of W against V_0..V_{j1-1}: h = V^H W,
+// W -= V h; Hc = h (first) or Hc += h.  part: gm_slices(n) * j1 * C values.
+hipError_t gm_orth_pass(hipStream_t st, int n, int C, int j1, const double2* V, int ldv, long sV, double2* W, int ldw,
+                        const int* done, double2* part, double2* h, double2* Hc, int first);
+hipError_t gm_givens(hipStream_t st, int C, int j, int M, const double2* Hc, const double* hn, const double* thr,
+                     double* cs, double2* sn, double2* g, double2* Rm, int* done, int* kc, double* inv, int* ndone);
+hipError_t gm_solve(hipStream_t st, int C, int M, int jend, const double2* Rm, const double2* g, const int* active,
+                    const int* kc, double2* y, int* steps);
+hipError_t gm_combine(hipStream_t st, int n, int C, int k, const double2* Z, int ldz, long sZ, const double2* y,
+                      double2* X, int ldx);
+hipError_t gm_g0(hipStream_t st, int C, const double* g0, double2* g);
 
 // ---- SS-FULL helpers (ssfull.hip) ----
 hipError_t hankel(hipStream_t st, const double2* mom, int k, int K, int shift, double2* H, int ldh);

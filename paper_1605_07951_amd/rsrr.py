@@ -40,7 +40,7 @@ STATUS_NAMES = {0: "OK", 1: "ESINGULAR", 2: "WARN_FALLBACK", 3: "WARN_GAP", 4: "
 EXPORTS = ["rsrr_create", "rsrr_destroy", "rsrr_contour", "rsrr_sample", "rsrr_sample_batched", "rsrr_basis",
            "rsrr_project", "rsrr_solve", "rsrr_last_timings", "rsrr_update_stats", "rsrr_version",
            "rsrr_two_stage", "rsrr_moments", "rsrr_server_create", "rsrr_server_submit", "rsrr_server_wait", "rsrr_server_stats",
-           "rsrr_server_destroy"]
+           "rsrr_server_destroy", "rsrr_sample_gmres"]
 RSRR_BATCH_GRAPH = 1
 RSRR_BATCH_AUTOTUNE = 2
 RSRR_SERVE_NO_BATCH = 1
@@ -56,6 +56,11 @@ class RsrrTerm(C.Structure):
 class RsrrNep(C.Structure):
     _fields_ = [("kind", C.c_int), ("n", C.c_int), ("J", C.c_int), ("A", C.c_void_p), ("lda", C.c_int),
                 ("terms", C.POINTER(RsrrTerm)), ("points", C.c_void_p), ("w", C.c_double)]
+
+
+class RsrrGmresInfo(C.Structure):
+    _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("converged", C.c_int), ("ref", C.c_int),
+                ("resid", C.c_double)]
 
 
 class RsrrInstance(C.Structure):
@@ -126,6 +131,8 @@ def lib():
     L.rsrr_contour.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, dp, dp]
     L.rsrr_sample.argtypes = [vp, C.POINTER(RsrrNep), C.c_int, dp, vp, C.c_int, C.c_int, C.c_int, vp, C.c_int,
                               C.POINTER(RsrrPointInfo)]
+    L.rsrr_sample_gmres.argtypes = [vp, C.POINTER(RsrrNep), C.c_int, dp, C.c_int, dp, ip, vp, C.c_int, C.c_int,
+                                    C.c_double, C.c_int, C.c_int, vp, C.c_int, C.POINTER(RsrrGmresInfo)]
     L.rsrr_sample_batched.argtypes = [vp, C.c_int, C.POINTER(RsrrInstance), C.c_int, C.c_int,
                                       C.POINTER(RsrrPointInfo)]
     L.rsrr_basis.argtypes = [vp, C.c_int, C.c_int, vp, C.c_int, C.c_double, vp, C.c_int, C.c_int, ip, dp]
@@ -304,6 +311,36 @@ def rsrr_sample(ctx, dnep, z, U, prec=RSRR_PREC_C64_IR, S=None, ok=(RSRR_OK, RSR
                              info)
     _check("rsrr_sample", code, ok)
     infos = [{"info": i.info, "ir_iters": i.ir_iters, "fallback": i.fallback, "resid": i.resid} for i in info]
+    return S, infos, code
+
+
+def rsrr_sample_gmres(ctx, dnep, z, U, zref, ref=None, tol=1e-10, restart=32, max_iters=300, S=None, ok=(RSRR_OK,)):
+    """S = [T(z_k)^-1 U]_k by flexible GMRES preconditioned with complex FP32 LU factors of T at the
+    reference points zref (point k uses ref[k], or the nearest reference when ref is None).
+
+    Returns (S tensor of shape (N*L, n) = column-major n x N*L, info list, status).
+    """
+    torch = _torch()
+    n = dnep.n
+    if not torch.is_tensor(U):
+        U, _ = colmajor(U)
+    L = U.shape[0]
+    ldu = U.shape[1]
+    zc, zp = _zbuf(z)
+    rc, rp = _zbuf(np.atleast_1d(zref))
+    N = zc.size
+    rarr = None
+    if ref is not None:
+        rarr = (C.c_int * N)(*[int(r) for r in ref])
+    if S is None:
+        S = torch.empty((N * L, n), dtype=torch.complex128, device=U.device)
+    lds = S.shape[1]
+    info = (RsrrGmresInfo * N)()
+    code = lib().rsrr_sample_gmres(ctx.h, C.byref(dnep.desc), N, zp, rc.size, rp, rarr, U.data_ptr(), L, ldu,
+                                   float(tol), int(restart), int(max_iters), S.data_ptr(), lds, info)
+    _check("rsrr_sample_gmres", code, ok)
+    infos = [{"iters": i.iters, "restarts": i.restarts, "converged": i.converged, "ref": i.ref, "resid": i.resid}
+             for i in info]
     return S, infos, code
 
 

@@ -62,6 +62,7 @@ def test_argument_errors_without_device(lib):
     assert lib.rsrr_basis(None, 1, 1, None, 1, 1e-14, None, 1, 1, C.byref(k), None) == -1
     assert lib.rsrr_last_timings(None, None) == -1
     assert lib.rsrr_update_stats(None, 0, 0, None) == -1
+    assert lib.rsrr_sample_gmres(None, None, 1, None, 1, None, None, None, 1, 1, 1e-10, 8, 10, None, 1, None) == -1
     assert b"gfx950" in lib.rsrr_version()
 
 
@@ -90,13 +91,13 @@ def test_server_structs_match_header(lib):
     import subprocess
     import tempfile
     from paper_1605_07951_amd import rsrr
-    src = ('#include <stdio.h>\n#include "rsrr.h"\nint main(void){printf("%zu %zu %zu %zu %zu\\n", '
+    src = ('#include <stdio.h>\n#include "rsrr.h"\nint main(void){printf("%zu %zu %zu %zu %zu %zu\\n", '
            'sizeof(rsrr_request), sizeof(rsrr_result), sizeof(rsrr_server_config), sizeof(rsrr_nep), '
-           'sizeof(rsrr_instance)); return 0;}\n')
+           'sizeof(rsrr_instance), sizeof(rsrr_gmres_info)); return 0;}\n')
     with tempfile.TemporaryDirectory() as d:
         cpath, exe = os.path.join(d, "sz.c"), os.path.join(d, "sz")
         open(cpath, "w").write(src)
         subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), cpath, "-o", exe], check=True)
         got = [int(x) for x in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
     assert got == [C.sizeof(rsrr.RsrrRequest), C.sizeof(rsrr.RsrrResult), C.sizeof(rsrr.RsrrServerConfig),
-                   C.sizeof(rsrr.RsrrNep), C.sizeof(rsrr.RsrrInstance)]
+                   C.sizeof(rsrr.RsrrNep), C.sizeof(rsrr.RsrrInstance), C.sizeof(rsrr.RsrrGmresInfo)]
