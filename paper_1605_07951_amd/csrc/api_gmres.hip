@@ -49,10 +49,23 @@ struct EvPair {
     float ms() { float t = 0.f; (void)hipEventElapsedTime(&t, a, b); return t; }
 };
 
+// Length of the K slices that split a contraction of length K over about 512
+// workgroups when `tiles` output tiles alone would leave the chip idle (K
+// itself: no split).  Slices are multiples of 64.
+static int k_slice(long tiles, int K)
+{
+    const long S = std::max(1L, std::min(16L, (512 + tiles - 1) / tiles));
+    const int Ks = (int)((K + S - 1) / S + 63) / 64 * 64;
+    return std::min(Ks, K);
+}
+static int n_slices(int K, int Ks) { return (K + Ks - 1) / Ks; }
+
 struct GmChunk {
     int B, C;                      // points, columns (B * L)
-    double2 *V, *Z, *Y, *X;        // Krylov vectors, directions, scaled copy, iterate (ld = c.ld)
-    float2* D;                     // complex FP32 preconditioner input/output
+    int ldy, Kop, Kso;             // separable: stacked scaled copies (J*n rows), K-slice of the operator
+    double2* P;                    // split-operator partial products (n_slices(Kop, Kso) blocks)
+    double2 *V, *Z, *Y, *X;        // Krylov vectors, directions, scaled copies, iterate (ld = c.ld)
+    float2 *D, *D2;                // complex FP32 preconditioner input / output
     double2 *part, *h, *Hc, *Rm, *g, *sn, *y, *coef;
     double *cs, *hn, *thr, *inv, *g0;
     int *done, *act, *kc, *steps, *ndone, *pidx;
@@ -68,12 +81,26 @@ static rsrr_status gm_apply(rsrr_ctx* c, const rsrr_nep* nep, int L, int ld, lon
 {
     const int n = nep->n;
     if (nep->kind == RSRR_T_SEPARABLE) {
-        // sum_j A_j (Z diag(f_j(z_point(c)))): one GEMM over all columns per term
-        for (int j = 0; j < nep->J; ++j) {
-            RSRR_HIP(gm_point_scale(c->stream, n, k.C, L, Zin, ld, k.coef + (size_t)j * k.B, k.Y, ld));
-            RSRR_HIP(zgemm(c->stream, 0, 0, n, k.C, n, 1.0, (const double2*)nep->A + (size_t)j * nep->lda * n,
-                           nep->lda, 0, k.Y, ld, 0, j ? 1.0 : 0.0, W, ld, 0, 1));
+        // sum_j A_j (Z diag(f_j(z_point(c)))) = [A_0 .. A_{J-1}] [Z f_0; ..; Z f_{J-1}]: the terms lie
+        // back to back (matrix j at column j*n of one n x J*n matrix), so this is one GEMM of depth
+        // J*n over all columns, split into K slices whose partial products are summed after
+        for (int j = 0; j < nep->J; ++j)
+            RSRR_HIP(gm_point_scale(c->stream, n, k.C, L, Zin, ld, k.coef + (size_t)j * k.B, k.Y + (size_t)j * n,
+                                    k.ldy));
+        const double2* A = (const double2*)nep->A;
+        const int S1 = k.Kop / k.Kso, r1 = k.Kop - S1 * k.Kso;
+        const long sP = (long)ld * k.C;
+        if (S1 == 1 && r1 == 0) {
+            RSRR_HIP(zgemm(c->stream, 0, 0, n, k.C, k.Kop, 1.0, A, nep->lda, 0, k.Y, k.ldy, 0, 0.0, W, ld, 0, 1));
+            return RSRR_OK;
         }
+        if (S1 > 0)
+            RSRR_HIP(zgemm(c->stream, 0, 0, n, k.C, k.Kso, 1.0, A, nep->lda, (long)k.Kso * nep->lda, k.Y, k.ldy,
+                           k.Kso, 0.0, k.P, ld, sP, S1));
+        if (r1 > 0)
+            RSRR_HIP(zgemm(c->stream, 0, 0, n, k.C, r1, 1.0, A + (size_t)S1 * k.Kso * nep->lda, nep->lda, 0,
+                           k.Y + (size_t)S1 * k.Kso, k.ldy, 0, 0.0, k.P + (size_t)S1 * sP, ld, 0, 1));
+        RSRR_HIP(gm_sum_c128(c->stream, n, k.C, k.P, ld, sP, S1 + (r1 > 0), W, ld));
     } else if (resid_skinny_ok(L)) {
         RSRR_HIP(resid_skinny(c->stream, n, L, k.T, ld, sT, Zin, ld, (long)ld * L, nullptr, 0, 0, W, ld, (long)ld * L,
                               nullptr, k.B));
@@ -201,6 +228,22 @@ extern "C" rsrr_status rsrr_sample_gmres(rsrr_ctx* c, const rsrr_nep* nep, int N
             if (hinfo[f] > 0) return RSRR_ESINGULAR;
         }
     }
+    // A reference that serves several points is applied as an explicit inverse
+    // (one complex FP32 GEMM per application instead of a chain of n/nb
+    // triangular steps); the inverse costs about as much as 4n/(3L') solves.
+    const bool use_inv = N >= 4 * nf;
+    float2* Pinv = nullptr;
+    if (use_inv) {
+        EvPair ev;
+        RSRR_HIP(hipEventRecord(ev.a, c->stream));
+        Pinv = (float2*)ws_get(c, WS_GMI, (size_t)nf * sT * 8);
+        if (!Pinv) return RSRR_ENOMEM;
+        RSRR_HIP(gm_eye_c64(c->stream, n, Pinv, ld, sT, nf));
+        RSRR_HIP(getrs_batched<float>(c->stream, Tf, sT, ld, n, nb, w, Pinv, sT, ld, n, nf));
+        RSRR_HIP(hipEventRecord(ev.b, c->stream));
+        RSRR_HIP(hipEventSynchronize(ev.b));
+        c->timings[0] += ev.ms();
+    }
 
     // ---- probe norms ----
     double* unrm = (double*)ws_get(c, WS_NORM, (size_t)L * 8);
@@ -212,9 +255,10 @@ extern "C" rsrr_status rsrr_sample_gmres(rsrr_ctx* c, const rsrr_nep* nep, int N
 
     // ---- chunk size from the memory budget ----
     const int ns = gm_slices(n);
-    const size_t per_col = (size_t)(2 * M + 3) * ld * 16 + (size_t)ld * 8 +
+    const size_t per_col = (size_t)(2 * M + 3) * ld * 16 + (size_t)ld * 16 +
                            ((size_t)ns * (M + 1) * 16 + (size_t)(M + 1) * 16 * 3 + (size_t)M * M * 16 +
-                            (size_t)M * 24 + 64) + (size_t)nb * 8;
+                            (size_t)M * 40 + 64) + (size_t)nb * 8 +
+                           (size_t)(nep->kind == RSRR_T_SEPARABLE ? nep->J * n : 0) * 16 + (size_t)16 * ld * 24;
     const size_t per_pt = (nep->kind == RSRR_T_HELMHOLTZ ? (size_t)sT * 16 + (((size_t)n * n + 255) / 256) * 8 : 0) +
                           (size_t)nb * n * 8 + (size_t)std::max(nep->J, 1) * 16 + 64;
     size_t budget = c->ws_budget;
@@ -252,16 +296,31 @@ extern "C" rsrr_status rsrr_sample_gmres(rsrr_ctx* c, const rsrr_nep* nep, int N
         const long sTmp = (long)nb * std::max(n, maxrun * L);
 
         // Krylov workspace
-        const size_t kbytes = a256((size_t)(M + 1) * vb * 16) + a256((size_t)M * vb * 16) + a256(vb * 16) * 2 +
-                              a256(vb * 8) + a256((size_t)(equal ? nrun : 1) * sTmp * 8);
+        // split contractions: the separable operator (depth J*n) and the explicit-inverse
+        // preconditioner (depth n per reference group)
+        const bool sep = nep->kind == RSRR_T_SEPARABLE;
+        k.ldy = sep ? nep->J * n : ld;
+        k.Kop = sep ? nep->J * n : n;
+        k.Kso = sep ? k_slice((long)((n + 63) / 64) * ((C + 63) / 64), k.Kop) : k.Kop;
+        const int Sop = sep ? n_slices(k.Kop, k.Kso) : 0;
+        const int bn = maxrun * L <= 32 ? 32 : (maxrun * L <= 64 ? 64 : 128);
+        const int Kpc = use_inv ? k_slice((long)((n + 127) / 128) * ((maxrun * L + bn - 1) / bn), n) : n;
+        const int Spc = use_inv ? n_slices(n, Kpc) : 0;
+        const size_t ybytes = sep ? (size_t)k.ldy * C * 16 : vb * 16;
+        const size_t kbytes = a256((size_t)(M + 1) * vb * 16) + a256((size_t)M * vb * 16) + a256(ybytes) +
+                              a256(vb * 16) + a256(vb * 8) * 2 + a256((size_t)(equal ? nrun : 1) * sTmp * 8) +
+                              a256((size_t)(Sop > 1 ? Sop : 0) * vb * 16) + a256((size_t)(Spc > 1 ? Spc : 0) * vb * 8);
         Carve kc{(char*)ws_get(c, WS_GMK, kbytes)};
         if (!kc.base) return RSRR_ENOMEM;
         k.V = kc.take<double2>((size_t)(M + 1) * vb);
         k.Z = kc.take<double2>((size_t)M * vb);
-        k.Y = kc.take<double2>(vb);
+        k.Y = kc.take<double2>(ybytes / 16);
         k.X = kc.take<double2>(vb);
         k.D = kc.take<float2>(vb);
+        k.D2 = kc.take<float2>(vb);
         k.tmp = kc.take<float2>((size_t)(equal ? nrun : 1) * sTmp);
+        k.P = kc.take<double2>((size_t)(Sop > 1 ? Sop : 0) * vb);
+        float2* Pp = kc.take<float2>((size_t)(Spc > 1 ? Spc : 0) * vb);
         const size_t sbytes = a256((size_t)ns * (M + 1) * C * 16) + a256((size_t)(M + 1) * C * 16) * 3 +
                               a256((size_t)M * M * C * 16) + a256((size_t)M * C * 16) * 2 + a256((size_t)M * C * 8) +
                               a256((size_t)C * 8) * 4 + a256((size_t)C * 4) * 4 + a256(64) +
@@ -369,7 +428,40 @@ extern "C" rsrr_status rsrr_sample_gmres(rsrr_ctx* c, const rsrr_nep* nep, int N
                 // Z_j = P^-1 V_j (complex FP32 factors of the point's reference)
                 RSRR_HIP(hipEventRecord(e1.a, c->stream));
                 RSRR_HIP(gm_narrow(c->stream, n, C, Vj, ld, k.D, ld));
-                if (equal) {
+                float2* Dz = k.D;
+                bool widened = false;
+                if (use_inv && Spc > 1) {
+                    // Z_j = P^-1 V_j, each reference group's product split into K slices
+                    const int S1 = n / Kpc, r1 = n - S1 * Kpc;
+                    for (int r = 0; r < nrun; ++r) {
+                        const int cols = (run0[r + 1] - run0[r]) * L;
+                        const size_t o = (size_t)run0[r] * L * ld;
+                        const float2* Pr = Pinv + runf[r] * sT;
+                        if (S1 > 0)
+                            RSRR_HIP(cgemm(c->stream, n, cols, Kpc, 1.f, Pr, ld, (long)Kpc * ld, k.D + o, ld, Kpc, 0.f,
+                                           Pp + o, ld, (long)vb, S1));
+                        if (r1 > 0)
+                            RSRR_HIP(cgemm(c->stream, n, cols, r1, 1.f, Pr + (size_t)S1 * Kpc * ld, ld, 0,
+                                           k.D + o + (size_t)S1 * Kpc, ld, 0, 0.f, Pp + (size_t)S1 * vb + o, ld, 0,
+                                           1));
+                    }
+                    RSRR_HIP(gm_sum_widen(c->stream, n, C, Pp, ld, (long)vb, Spc, Zj, ld));
+                    widened = true;
+                } else if (use_inv) {
+                    Dz = k.D2;
+                    if (equal) {
+                        const int rl = run0[1] - run0[0];
+                        RSRR_HIP(cgemm(c->stream, n, rl * L, n, 1.f, Pinv + runf[0] * sT, ld, sT, k.D, ld,
+                                       (long)ld * rl * L, 0.f, k.D2, ld, (long)ld * rl * L, nrun));
+                    } else {
+                        for (int r = 0; r < nrun; ++r) {
+                            const int rl = run0[r + 1] - run0[r];
+                            const size_t o = (size_t)run0[r] * L * ld;
+                            RSRR_HIP(cgemm(c->stream, n, rl * L, n, 1.f, Pinv + runf[r] * sT, ld, sT, k.D + o, ld, 0,
+                                           0.f, k.D2 + o, ld, 0, 1));
+                        }
+                    }
+                } else if (equal) {
                     const int rl = run0[1] - run0[0];
                     LUWork wr = w;
                     const int f0 = runf[0];
@@ -388,7 +480,7 @@ extern "C" rsrr_status rsrr_sample_gmres(rsrr_ctx* c, const rsrr_nep* nep, int N
                                                       1));
                     }
                 }
-                RSRR_HIP(gm_widen(c->stream, n, C, k.D, ld, Zj, ld));
+                if (!widened) RSRR_HIP(gm_widen(c->stream, n, C, Dz, ld, Zj, ld));
                 RSRR_HIP(hipEventRecord(e1.b, c->stream));
                 // W = T Z_j
                 RSRR_HIP(hipEventRecord(e2.a, c->stream));

@@ -277,6 +277,46 @@ __global__ __launch_bounds__(GM_NT) void gm_combine_kernel(int n, int C, int k, 
     }
 }
 
+// Z = (c128) sum_{s < S} P_s (complex FP32 partial products of a split
+// contraction, slice s at P + s*sP), summed in FP64.
+__global__ __launch_bounds__(GM_NT) void gm_sum_widen_kernel(int n, int C, const float2* __restrict__ P, int ldp,
+                                                              long sP, int S, double2* __restrict__ Z, int ldz)
+{
+    const long e = (long)blockIdx.x * GM_NT + threadIdx.x;
+    if (e >= (long)n * C) return;
+    const int i = (int)(e % n), c = (int)(e / n);
+    const long o = i + (long)c * ldp;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int s = 0; s < S; ++s) {
+        const float2 v = P[s * sP + o];
+        acc.x += (double)v.x;
+        acc.y += (double)v.y;
+    }
+    Z[i + (long)c * ldz] = acc;
+}
+
+// W = sum_{s < S} P_s (complex FP64 partial products).
+__global__ __launch_bounds__(GM_NT) void gm_sum_c128_kernel(int n, int C, const double2* __restrict__ P, int ldp,
+                                                             long sP, int S, double2* __restrict__ W, int ldw)
+{
+    const long e = (long)blockIdx.x * GM_NT + threadIdx.x;
+    if (e >= (long)n * C) return;
+    const int i = (int)(e % n), c = (int)(e / n);
+    const long o = i + (long)c * ldp;
+    double2 acc = P[o];
+    for (int s = 1; s < S; ++s) acc = cadd(acc, P[s * sP + o]);
+    W[i + (long)c * ldw] = acc;
+}
+
+// B identity matrices n x n (complex FP32, leading dimension ld, stride sA).
+__global__ __launch_bounds__(GM_NT) void gm_eye_c64_kernel(int n, float2* __restrict__ A, int ld, long sA)
+{
+    const long e = (long)blockIdx.x * GM_NT + threadIdx.x;
+    if (e >= (long)n * n) return;
+    const int i = (int)(e % n), c = (int)(e / n);
+    A[blockIdx.y * sA + i + (long)c * ld] = make_float2(i == c ? 1.f : 0.f, 0.f);
+}
+
 // g[c] = g0[c] (row 0 of the right-hand side), g rows 1.. untouched.
 __global__ __launch_bounds__(GM_NT) void gm_g0_kernel(int C, const double* __restrict__ g0, double2* __restrict__ g)
 {
@@ -349,6 +389,22 @@ hipError_t gm_combine(hipStream_t st, int n, int C, int k, const double2* Z, int
     if (k <= 0) return hipSuccess;
     hipLaunchKernelGGL(gm_combine_kernel, dim3((unsigned)C, (unsigned)gm_slices(n)), dim3(GM_NT), 0, st, n, C, k, Z,
                        ldz, sZ, y, X, ldx);
+    return hipGetLastError();
+}
+hipError_t gm_sum_widen(hipStream_t st, int n, int C, const float2* P, int ldp, long sP, int S, double2* Z, int ldz)
+{
+    hipLaunchKernelGGL(gm_sum_widen_kernel, flat_grid((long)n * C), dim3(GM_NT), 0, st, n, C, P, ldp, sP, S, Z, ldz);
+    return hipGetLastError();
+}
+hipError_t gm_sum_c128(hipStream_t st, int n, int C, const double2* P, int ldp, long sP, int S, double2* W, int ldw)
+{
+    hipLaunchKernelGGL(gm_sum_c128_kernel, flat_grid((long)n * C), dim3(GM_NT), 0, st, n, C, P, ldp, sP, S, W, ldw);
+    return hipGetLastError();
+}
+hipError_t gm_eye_c64(hipStream_t st, int n, float2* A, int ld, long sA, int B)
+{
+    hipLaunchKernelGGL(gm_eye_c64_kernel, dim3((unsigned)(((long)n * n + GM_NT - 1) / GM_NT), (unsigned)B),
+                       dim3(GM_NT), 0, st, n, A, ld, sA);
     return hipGetLastError();
 }
 hipError_t gm_g0(hipStream_t st, int C, const double* g0, double2* g)

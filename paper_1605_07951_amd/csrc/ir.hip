@@ -418,7 +418,11 @@ hipError_t resid_skinny(hipStream_t st, int n, int L, const double2* T, int ldt,
     hipLaunchKernelGGL((resid_skinny_kernel<LC, RW>), dim3((unsigned)((n + RW - 1) / RW), (unsigned)B), dim3(RW), 0, \
                        st, n, L, T, ldt, sT, X, ldx, sX, U, ldu, sU, R, ldr, sR, active)
     const bool small = n <= 1024;
-    if (L <= 8) {
+    if (L <= 2) {
+        if (small) RS_L(2, 64); else RS_L(2, 256);
+    } else if (L <= 4) {
+        if (small) RS_L(4, 64); else RS_L(4, 256);
+    } else if (L <= 8) {
         if (small) RS_L(8, 64); else RS_L(8, 256);
     } else {
         if (small) RS_L(16, 64); else RS_L(16, 256);

@@ -162,6 +162,10 @@ hipError_t gm_solve(hipStream_t st, int C, int M, int jend, const double2* Rm, c
 hipError_t gm_combine(hipStream_t st, int n, int C, int k, const double2* Z, int ldz, long sZ, const double2* y,
                       double2* X, int ldx);
 hipError_t gm_g0(hipStream_t st, int C, const double* g0, double2* g);
+hipError_t gm_eye_c64(hipStream_t st, int n, float2* A, int ld, long sA, int B);
+// Sums of the S slices of a split contraction (slice s at P + s*sP): Z = (c128) sum P_s, W = sum P_s.
+hipError_t gm_sum_widen(hipStream_t st, int n, int C, const float2* P, int ldp, long sP, int S, double2* Z, int ldz);
+hipError_t gm_sum_c128(hipStream_t st, int n, int C, const double2* P, int ldp, long sP, int S, double2* W, int ldw);
 
 // ---- SS-FULL helpers (ssfull.hip) ----
 hipError_t hankel(hipStream_t st, const double2* mom, int k, int K, int shift, double2* H, int ldh);

@@ -262,6 +262,12 @@ class Context:
         _check("rsrr_last_timings", lib().rsrr_last_timings(self.h, t))
         return {"assemble_ms": t[0], "lu_ms": t[1], "solve_ms": t[2], "residual_ms": t[3], "total_ms": t[4]}
 
+    def raw_timings(self):
+        """The five phase times (ms) of the last call, in the order its entry point documents."""
+        t = (C.c_double * 5)()
+        _check("rsrr_last_timings", lib().rsrr_last_timings(self.h, t))
+        return list(t)
+
 
 def rsrr_update_stats(ctx, enable=True, reset=False):
     """Trailing-update kernel statistics: dict(launches, ms, flops, untimed)."""

@@ -122,3 +122,34 @@ def test_ragged_batch_config_sampled(R):
         nep, U = neps[i]
         _sampled_parity(R, O.Problem(nep), items[i].S, z, U, ks=[0, 11, 23])
     ctx.close()
+
+
+def test_gmres_full_size_sampled_points(R, ctx):
+    """The GMRES workload bench.py times: Helmholtz sphere n=4096 on the headline ellipse, N=64,
+    L=2, one reference factorisation at the centre, tol 1e-10.  Every point converged; at sampled
+    points the residual recomputed with the oracle's T is <= 1.5 tol, and the distance to the
+    oracle's solve is within 2 kappa times it.  kappa: LAPACK's 1-norm estimate (zgecon) on the
+    oracle's LU; T is complex symmetric, so kappa_2 <= kappa_1."""
+    import scipy.linalg as sl
+    from scipy.linalg import lapack
+    nep, C, U = W.cfg_helmholtz(n=4096, N=64, L=2)
+    z, _ = R.rsrr_contour(C.gamma, C.a, C.b, C.N)
+    Ud, _ = R.colmajor(U)
+    S, info, code = R.rsrr_sample_gmres(ctx, R.DeviceNEP(nep), z, Ud, [C.gamma], tol=1e-10, restart=32)
+    torch.cuda.synchronize()
+    assert code == R.RSRR_OK
+    assert all(i["converged"] == 1 and i["resid"] <= 1e-10 for i in info)
+    prob = O.Problem(nep)
+    Sh = R.from_colmajor(S, 4096)
+    for k in (0, 45):
+        T = prob.T(z[k])
+        assert np.allclose(T, T.T)
+        X = Sh[:, 2 * k:2 * k + 2]
+        res = np.linalg.norm(U - T @ X, axis=0) / np.linalg.norm(U, axis=0)
+        assert res.max() <= 1.5e-10
+        lu, piv = sl.lu_factor(T)
+        Xo = sl.lu_solve((lu, piv), U)
+        rcond, inf = lapack.zgecon(lu, np.linalg.norm(T, 1), norm="1")
+        assert inf == 0
+        err = np.linalg.norm(X - Xo, axis=0) / np.linalg.norm(Xo, axis=0)
+        assert np.all(err <= 2.0 * res / rcond + 1e-13), (k, err, res, 1 / rcond)

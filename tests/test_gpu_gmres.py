@@ -113,6 +113,28 @@ def test_gmres_unequal_reference_groups_and_order(R, ctx):
     _check(R, nep, z, U, S, infos, 1e-10)
 
 
+def test_gmres_inverse_preconditioner_unequal_groups(R, ctx):
+    """Enough points per reference to apply the factors as explicit inverses, groups of 8, 5 and 3."""
+    nep, C, U = W.cfg_helmholtz(n=256, N=16, L=2, seed=2600)
+    z, _ = R.rsrr_contour(C.gamma, C.a, C.b, C.N)
+    zref, _ = R.rsrr_contour(C.gamma, 0.5 * C.a, 0.5 * C.b, 3)
+    ref = [0] * 8 + [1] * 5 + [2] * 3
+    ref = ref[5:] + ref[:5]
+    S, infos, code = _run(R, ctx, nep, z, U, zref, ref=ref)
+    assert code == R.RSRR_OK
+    assert [i["ref"] for i in infos] == ref
+    _check(R, nep, z, U, S, infos, 1e-10)
+
+
+def test_gmres_split_products_with_ragged_slices(R, ctx):
+    """n = 300: the split preconditioner product ends in a partial K slice (300 = 4*64 + 44)."""
+    nep, C, U = W.cfg_helmholtz(n=300, N=8, L=2, seed=2700)
+    z, _ = R.rsrr_contour(C.gamma, C.a, C.b, C.N)
+    S, infos, code = _run(R, ctx, nep, z, U, [C.gamma])
+    assert code == R.RSRR_OK
+    _check(R, nep, z, U, S, infos, 1e-10)
+
+
 def test_gmres_short_restart_cycles(R, ctx):
     nep, C, U = W.cfg_helmholtz(n=384, N=6, L=2, seed=2200)
     z, _ = R.rsrr_contour(C.gamma, C.a, C.b, C.N)
