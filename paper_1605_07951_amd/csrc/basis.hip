@@ -72,44 +72,47 @@ __global__ __launch_bounds__(JB_NT) void jacobi_gram_kernel(const double2* __res
     for (int u = 0; u < 4; ++u) G[gp * JB_W + gq0 + u] = acc[u];
 }
 
-// 2. one wave per pair: sum the slices, measure, rotate.  V (JB_W x JB_W, row
-// major, entry [t][s] = V_ts) and skip[pr] go to global memory.
-__global__ __launch_bounds__(64) void jacobi_solve_kernel(const double2* __restrict__ Gp, int slices, int inner_sweeps,
-                                                           double tol, double zthr2, double2* __restrict__ Vout,
-                                                           int* __restrict__ skip, double* __restrict__ offmax)
+// 2. one workgroup of JS_NT threads per pair: sum the slices, measure, rotate.
+// V (JB_W x JB_W, row major, entry [t][s] = V_ts) and skip[pr] go to global memory.
+constexpr int JS_NT = 256;
+__global__ __launch_bounds__(JS_NT) void jacobi_solve_kernel(const double2* __restrict__ Gp, int slices,
+                                                              int inner_sweeps, double tol, double zthr2,
+                                                              double2* __restrict__ Vout, int* __restrict__ skip,
+                                                              double* __restrict__ offmax)
 {
     __shared__ double2 G[JB_W][JB_W + 1];
     __shared__ double2 V[JB_W][JB_W + 1];
     __shared__ double rc[JB_W / 2], rs[JB_W / 2];
     __shared__ double2 re[JB_W / 2];
     __shared__ int rp[JB_W / 2], rq[JB_W / 2], ron[JB_W / 2];
-    const int pr = blockIdx.x, lane = threadIdx.x;
+    __shared__ double wmax[JS_NT / 64];
+    const int pr = blockIdx.x, tid = threadIdx.x;
     const double2* src = Gp + (long)pr * slices * (JB_W * JB_W);
     {
-        // 16 entries per lane, all loads of a slice in flight together; each entry is
-        // summed over the slices in order
-        constexpr int PER = JB_W * JB_W / 64;
+        // JB_W^2 / JS_NT entries per thread, all loads of a slice in flight together; each
+        // entry is summed over the slices in order
+        constexpr int PER = JB_W * JB_W / JS_NT;
         double2 g[PER];
 #pragma unroll
         for (int t = 0; t < PER; ++t) g[t] = make_double2(0.0, 0.0);
         for (int sl = 0; sl < slices; ++sl) {
-            const double2* sp = src + (long)sl * (JB_W * JB_W) + lane;
+            const double2* sp = src + (long)sl * (JB_W * JB_W) + tid;
             double2 v[PER];
 #pragma unroll
-            for (int t = 0; t < PER; ++t) v[t] = sp[64 * t];
+            for (int t = 0; t < PER; ++t) v[t] = sp[JS_NT * t];
 #pragma unroll
             for (int t = 0; t < PER; ++t) g[t] = cadd(g[t], v[t]);
         }
 #pragma unroll
         for (int t = 0; t < PER; ++t) {
-            const int e = lane + 64 * t;
+            const int e = tid + JS_NT * t;
             G[e / JB_W][e % JB_W] = g[t];
             V[e / JB_W][e % JB_W] = make_double2(e / JB_W == e % JB_W ? 1.0 : 0.0, 0.0);
         }
     }
     __syncthreads();
     double off = 0.0;
-    for (int e = lane; e < JB_W * JB_W; e += 64) {
+    for (int e = tid; e < JB_W * JB_W; e += JS_NT) {
         const int i = e / JB_W, q = e % JB_W;
         if (i == q) continue;
         const double dp = G[i][i].x, dq = G[q][q].x;
@@ -119,16 +122,20 @@ __global__ __launch_bounds__(64) void jacobi_solve_kernel(const double2* __restr
         }
     }
     for (int o = 32; o >= 1; o >>= 1) off = fmax(off, __shfl_xor(off, o));
-    if (lane == 0) {
+    if ((tid & 63) == 0) wmax[tid >> 6] = off;
+    __syncthreads();
+    off = wmax[0];
+    for (int w = 1; w < JS_NT / 64; ++w) off = fmax(off, wmax[w]);
+    if (tid == 0) {
         offmax[pr] = off;
         skip[pr] = off <= tol ? 1 : 0;
     }
-    if (off <= tol) return;  // pair already orthogonal: A stays unchanged
+    if (off <= tol) return;  // pair already orthogonal: A stays unchanged (uniform over the workgroup)
 
     for (int sw = 0; sw < inner_sweeps; ++sw) {
         for (int st = 0; st < JB_W - 1; ++st) {
-            if (lane < JB_W / 2) {
-                const int ip = rr_block(lane, st, JB_W), iq = rr_block(JB_W - 1 - lane, st, JB_W);
+            if (tid < JB_W / 2) {
+                const int ip = rr_block(tid, st, JB_W), iq = rr_block(JB_W - 1 - tid, st, JB_W);
                 const int a_ = ip < iq ? ip : iq, b_ = ip < iq ? iq : ip;
                 const double2 g = G[a_][b_];
                 const double h = sqrt(g.x * g.x + g.y * g.y);
@@ -144,11 +151,11 @@ __global__ __launch_bounds__(64) void jacobi_solve_kernel(const double2* __restr
                     e = make_double2(g.x / h, g.y / h);
                     on = 1;
                 }
-                rp[lane] = a_; rq[lane] = b_; rc[lane] = c; rs[lane] = s; re[lane] = e; ron[lane] = on;
+                rp[tid] = a_; rq[tid] = b_; rc[tid] = c; rs[tid] = s; re[tid] = e; ron[tid] = on;
             }
             __syncthreads();
             // columns: [x_p, x_q] <- [c x_p - s conj(e) x_q, s e x_p + c x_q] for G and V
-            for (int task = lane; task < (JB_W / 2) * JB_W * 2; task += 64) {
+            for (int task = tid; task < (JB_W / 2) * JB_W * 2; task += JS_NT) {
                 const int which = task / ((JB_W / 2) * JB_W);  // 0: G, 1: V
                 const int rem = task % ((JB_W / 2) * JB_W);
                 const int k = rem / JB_W, row = rem % JB_W;
@@ -164,7 +171,7 @@ __global__ __launch_bounds__(64) void jacobi_solve_kernel(const double2* __restr
             }
             __syncthreads();
             // rows of G: row_p <- c row_p - s e row_q ; row_q <- s conj(e) row_p + c row_q
-            for (int task = lane; task < (JB_W / 2) * JB_W; task += 64) {
+            for (int task = tid; task < (JB_W / 2) * JB_W; task += JS_NT) {
                 const int k = task / JB_W, col = task % JB_W;
                 if (!ron[k]) continue;
                 const int a_ = rp[k], b_ = rq[k];
@@ -176,8 +183,8 @@ __global__ __launch_bounds__(64) void jacobi_solve_kernel(const double2* __restr
                 G[b_][col] = make_double2(s * cep.x + c * xq.x, s * cep.y + c * xq.y);
             }
             __syncthreads();
-            if (lane < JB_W / 2 && ron[lane]) {
-                const int a_ = rp[lane], b_ = rq[lane];
+            if (tid < JB_W / 2 && ron[tid]) {
+                const int a_ = rp[tid], b_ = rq[tid];
                 G[a_][b_] = make_double2(0.0, 0.0);
                 G[b_][a_] = make_double2(0.0, 0.0);
                 G[a_][a_].y = 0.0;
@@ -187,7 +194,7 @@ __global__ __launch_bounds__(64) void jacobi_solve_kernel(const double2* __restr
         }
     }
     double2* Vo = Vout + (long)pr * (JB_W * JB_W);
-    for (int e = lane; e < JB_W * JB_W; e += 64) Vo[e] = V[e / JB_W][e % JB_W];
+    for (int e = tid; e < JB_W * JB_W; e += JS_NT) Vo[e] = V[e / JB_W][e % JB_W];
 }
 
 // 3. [A_I A_J] <- [A_I A_J] V on rows [slice*JR, min(m_apply, slice*JR + JR)).
@@ -450,7 +457,7 @@ hipError_t jacobi_round(hipStream_t st, double2* A, int lda, int m, int m_apply,
     double2* V = Gp + (size_t)pairs * gs * JB_W * JB_W;
     int* skip = (int*)(V + (size_t)pairs * JB_W * JB_W);
     hipLaunchKernelGGL(jacobi_gram_kernel, dim3(pairs, gs), dim3(JB_NT), 0, st, A, lda, m, p, nb, round, Gp);
-    hipLaunchKernelGGL(jacobi_solve_kernel, dim3(pairs), dim3(64), 0, st, Gp, gs, inner, tol, zthr2, V, skip, offmax);
+    hipLaunchKernelGGL(jacobi_solve_kernel, dim3(pairs), dim3(JS_NT), 0, st, Gp, gs, inner, tol, zthr2, V, skip, offmax);
     hipLaunchKernelGGL(jacobi_apply_kernel, dim3(pairs, as), dim3(JB_NT), 0, st, A, lda, m_apply, p, nb, round, V,
                        skip);
     return hipGetLastError();
