@@ -126,7 +126,7 @@ typedef struct {
     int nbar;          /* eigenvalue count from the gap rule (eq. gap)    */
     int warn_gap;      /* 1 when g_max < tol_gap                          */
     double gmax;       /* largest sigma_j / sigma_{j+1} of H              */
-    int n_sigma;       /* number of singular values of H written         */
+    int n_sigma;       /* number of singular values of H computed (leading) */
     int pad;
 } rsrr_solve_info;
 
@@ -242,7 +242,10 @@ RSRR_API rsrr_status rsrr_project(rsrr_ctx *ctx, const rsrr_nep *nep, const doub
  * residuals resid (host, max_eigs; ||T(lambda)v||_2 / (||T(lambda)||_1 ||v||_2)
  * in FP64 against the full nep; may be NULL only if V is NULL), the level of
  * each eigenvalue is for the caller to compute.  sigma_H (host, KQ*k doubles,
- * may be NULL) receives the singular values of H.  sinfo (host, may be NULL).
+ * may be NULL) receives the singular values of H, descending: all KQ*k of
+ * them, or, when H is numerically of low rank and a range sketch of it shows
+ * a clear gap (g_max >= 10 tol_gap), the sinfo->n_sigma leading ones
+ * followed by zeros.  sinfo (host, may be NULL).
  * Status RSRR_WARN_GAP when g_max < tol_gap (results are best effort).
  * Errors: -2 nep, -3 k < 1, -4 AQ NULL, -5 J_eff < 1, -6 terms NULL,
  * -7 Q NULL, -8 ldq, -9 gamma NULL, -10 a, -11 b, -12 NQ < 2*KQ+1,

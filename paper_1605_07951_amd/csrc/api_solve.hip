@@ -123,35 +123,123 @@ extern "C" rsrr_status rsrr_solve(rsrr_ctx* c, const rsrr_nep* nep, int k, const
     RSRR_HIP(eye(c->stream, Hx, 2 * Kk, Kk, Kk));
     RSRR_HIP(hankel(c->stream, mom, k, KQ, 1, Hs, Kk));
     rsrr_status st = RSRR_OK;
-    const double tol = 4.0 * std::max(1.0, std::sqrt((double)Kk)) * 2.220446049250313e-16;
-    if (jacobi_svd(c, Hx, 2 * Kk, Kk, 2 * Kk, Kk, 80, tol, &st) < 0) return st;
+    const double eps = 2.220446049250313e-16;
+    const double tol = 4.0 * std::max(1.0, std::sqrt((double)Kk)) * eps;
 
-    // ---- singular values, gap rule ----
-    double* nrm = (double*)ws_get(c, WS_B5, (size_t)Kk * 8);
-    if (!nrm) return RSRR_ENOMEM;
-    RSRR_HIP(colnorms(c->stream, Kk, Kk, Hx, 2 * Kk, 0, nrm, 1));
-    std::vector<double> sv(Kk);
-    RSRR_HIP(hipMemcpyAsync(sv.data(), nrm, (size_t)Kk * 8, hipMemcpyDeviceToHost, c->stream));
-    RSRR_HIP(hipStreamSynchronize(c->stream));
-    std::vector<int> ord(Kk);
-    std::iota(ord.begin(), ord.end(), 0);
-    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return sv[x] > sv[y]; });
-    std::vector<double> s(Kk);
-    for (int i = 0; i < Kk; ++i) s[i] = sv[ord[i]];
-    if (sigma_H)
-        for (int i = 0; i < Kk; ++i) sigma_H[i] = s[i];
-    int nbar = 0;
+    // ---- SVD of H and the gap rule (eq. gap) ----
+    // When the contour holds few eigenvalues, H is numerically of low rank: its
+    // leading singular triplets come from a range sketch of H (one power step,
+    // each product orthonormalised by BCGS2) and a one-sided Jacobi SVD of the
+    // small factor.  The sketch is used only when it shows a clear gap inside
+    // what it captured (g >= 10 tol_gap, and larger than any ratio the
+    // uncaptured tail could show); otherwise the Jacobi SVD of the whole H runs.
+    std::vector<double> s;
+    std::vector<int> ord;
+    int nbar = 0, nsig = 0, rS = 0;
     double gmax = 0.0;
-    for (int j = 0; j + 1 < Kk; ++j) {
-        const double r = s[j + 1] == 0.0 ? (s[j] > 0.0 ? INFINITY : 0.0) : s[j] / s[j + 1];
-        if (r > gmax) { gmax = r; nbar = j + 1; }
+    double2 *QY = nullptr, *XS = nullptr;
+    auto gap_rule = [](const std::vector<double>& sv, int cnt, int* nb, double* g) {
+        *nb = 0;
+        *g = 0.0;
+        for (int j = 0; j + 1 < cnt; ++j) {
+            const double r = sv[j + 1] == 0.0 ? (sv[j] > 0.0 ? INFINITY : 0.0) : sv[j] / sv[j + 1];
+            if (r > *g) { *g = r; *nb = j + 1; }
+        }
+    };
+    for (int l = 64; 2 * l <= Kk; l *= 2) {
+        double2* Om = (double2*)ws_get(c, WS_HS0, (size_t)Kk * l * 16);
+        double2* Y = (double2*)ws_get(c, WS_HS1, (size_t)Kk * l * 16);
+        double2* Z = (double2*)ws_get(c, WS_HS2, (size_t)Kk * l * 16);
+        void* wb = ws_get(c, WS_HSW, bcgs2_work_bytes(Kk, l));
+        double* n0 = (double*)ws_get(c, WS_HSD, (size_t)2 * l * 8);
+        int* di = (int*)ws_get(c, WS_HSI, (size_t)l * 4);
+        if (!Om || !Y || !Z || !wb || !n0 || !di) return RSRR_ENOMEM;
+        RSRR_HIP(gaussian(c->stream, Om, Kk, l, Kk, 0x4a4b5eedull + (unsigned long long)l));
+        RSRR_HIP(zgemm(c->stream, 0, 0, Kk, l, Kk, 1.0, Hx, 2 * Kk, 0, Om, Kk, 0, 0.0, Y, Kk, 0, 1));
+        RSRR_HIP(bcgs2(c->stream, Y, Kk, Kk, l, wb, n0));
+        RSRR_HIP(zgemm(c->stream, 1, 0, Kk, l, Kk, 1.0, Hx, 2 * Kk, 0, Y, Kk, 0, 0.0, Z, Kk, 0, 1));
+        RSRR_HIP(bcgs2(c->stream, Z, Kk, Kk, l, wb, n0));
+        RSRR_HIP(zgemm(c->stream, 0, 0, Kk, l, Kk, 1.0, Hx, 2 * Kk, 0, Z, Kk, 0, 0.0, Y, Kk, 0, 1));
+        RSRR_HIP(bcgs2(c->stream, Y, Kk, Kk, l, wb, n0));
+        RSRR_HIP(colnorms(c->stream, Kk, l, Y, Kk, 0, n0, 1));
+        std::vector<double> hq(l);
+        RSRR_HIP(hipMemcpyAsync(hq.data(), n0, (size_t)l * 8, hipMemcpyDeviceToHost, c->stream));
+        RSRR_HIP(hipStreamSynchronize(c->stream));
+        std::vector<int> idx;
+        for (int i = 0; i < l; ++i)
+            if (hq[i] > 0.5) idx.push_back(i);
+        const int r = (int)idx.size();
+        if (r < 2) break;
+        // compacted Q_Y (into Omega's buffer), X = [H^H Q_Y; I_r]
+        std::vector<double> ones(r, 1.0);
+        RSRR_HIP(hipMemcpyAsync(di, idx.data(), (size_t)r * 4, hipMemcpyHostToDevice, c->stream));
+        RSRR_HIP(hipMemcpyAsync(n0 + l, ones.data(), (size_t)r * 8, hipMemcpyHostToDevice, c->stream));
+        RSRR_HIP(gather_scale(c->stream, Y, Kk, Kk, di, n0 + l, Om, Kk, r));
+        double2* X = (double2*)ws_get(c, WS_HSX, (size_t)(Kk + r) * r * 16);
+        if (!X) return RSRR_ENOMEM;
+        RSRR_HIP(zgemm(c->stream, 1, 0, Kk, r, Kk, 1.0, Hx, 2 * Kk, 0, Om, Kk, 0, 0.0, X, Kk + r, 0, 1));
+        RSRR_HIP(eye(c->stream, X, Kk + r, Kk, r));
+        if (jacobi_svd(c, X, Kk + r, Kk, Kk + r, r, 80, tol, &st) < 0) return st;
+        RSRR_HIP(colnorms(c->stream, Kk, r, X, Kk + r, 0, n0, 1));
+        std::vector<double> sv(r);
+        RSRR_HIP(hipMemcpyAsync(sv.data(), n0, (size_t)r * 8, hipMemcpyDeviceToHost, c->stream));
+        RSRR_HIP(hipStreamSynchronize(c->stream));
+        std::vector<int> o(r);
+        std::iota(o.begin(), o.end(), 0);
+        std::stable_sort(o.begin(), o.end(), [&](int x, int y) { return sv[x] > sv[y]; });
+        std::vector<double> ss(r);
+        for (int i = 0; i < r; ++i) ss[i] = sv[o[i]];
+        if (!(ss[0] > 0.0)) break;
+        int nb1 = 0;
+        double g1 = 0.0;
+        bool ok;
+        if (r < l) {
+            // rank-deficient sketch: what it did not capture lies below the BCGS2
+            // dropping level, taken as the next singular value
+            std::vector<double> se(ss);
+            se.push_back(4.0 * eps * std::sqrt((double)Kk * l) * ss[0]);
+            gap_rule(se, r + 1, &nb1, &g1);
+            ok = g1 >= 10.0 * tol_gap;
+        } else {
+            gap_rule(ss, r, &nb1, &g1);
+            ok = g1 >= 10.0 * tol_gap && nb1 <= r - 2 && g1 >= ss[r - 1] / (eps * ss[0]);
+        }
+        if (ok) {
+            s = ss;
+            ord = o;
+            nbar = nb1;
+            gmax = g1;
+            nsig = r;
+            rS = r;
+            QY = Om;
+            XS = X;
+            break;
+        }
     }
+    if (!XS) {
+        if (jacobi_svd(c, Hx, 2 * Kk, Kk, 2 * Kk, Kk, 80, tol, &st) < 0) return st;
+        double* nrm = (double*)ws_get(c, WS_B5, (size_t)Kk * 8);
+        if (!nrm) return RSRR_ENOMEM;
+        RSRR_HIP(colnorms(c->stream, Kk, Kk, Hx, 2 * Kk, 0, nrm, 1));
+        std::vector<double> sv(Kk);
+        RSRR_HIP(hipMemcpyAsync(sv.data(), nrm, (size_t)Kk * 8, hipMemcpyDeviceToHost, c->stream));
+        RSRR_HIP(hipStreamSynchronize(c->stream));
+        ord.resize(Kk);
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return sv[x] > sv[y]; });
+        s.resize(Kk);
+        for (int i = 0; i < Kk; ++i) s[i] = sv[ord[i]];
+        nsig = Kk;
+        gap_rule(s, Kk, &nbar, &gmax);
+    }
+    if (sigma_H)
+        for (int i = 0; i < Kk; ++i) sigma_H[i] = i < nsig ? s[i] : 0.0;
     const int warn = gmax < tol_gap;
     if (sinfo) {
         sinfo->nbar = nbar;
         sinfo->warn_gap = warn;
         sinfo->gmax = gmax;
-        sinfo->n_sigma = Kk;
+        sinfo->n_sigma = nsig;
     }
     if (nbar == 0 || s[0] == 0.0) return RSRR_WARN_GAP;
     const int ne = std::min(std::min(nbar, max_eigs), 256);
@@ -174,8 +262,17 @@ extern "C" rsrr_status rsrr_solve(rsrr_ctx* c, const rsrr_nep* nep, int k, const
     for (int i = 0; i < ne; ++i) { hinv[i] = 1.0 / s[i]; hinv[ne + i] = 1.0; }
     RSRR_HIP(hipMemcpyAsync(dord, ord.data(), (size_t)ne * 4, hipMemcpyHostToDevice, c->stream));
     RSRR_HIP(hipMemcpyAsync(dinv, hinv.data(), (size_t)2 * ne * 8, hipMemcpyHostToDevice, c->stream));
-    RSRR_HIP(gather_scale(c->stream, Hx, 2 * Kk, Kk, dord, dinv, V0, Kk, ne));
-    RSRR_HIP(gather_scale(c->stream, Hx + Kk, 2 * Kk, Kk, dord, dinv + ne, W0, Kk, ne));
+    if (XS) {
+        // sketch: left vectors Q_Y W (W: bottom r rows of X), right vectors (top of X) / sigma
+        double2* Wsm = (double2*)ws_get(c, WS_B2, (size_t)rS * ne * 16);
+        if (!Wsm) return RSRR_ENOMEM;
+        RSRR_HIP(gather_scale(c->stream, XS, Kk + rS, Kk, dord, dinv, W0, Kk, ne));
+        RSRR_HIP(gather_scale(c->stream, XS + Kk, Kk + rS, rS, dord, dinv + ne, Wsm, rS, ne));
+        RSRR_HIP(zgemm(c->stream, 0, 0, Kk, ne, rS, 1.0, QY, Kk, 0, Wsm, rS, 0, 0.0, V0, Kk, 0, 1));
+    } else {
+        RSRR_HIP(gather_scale(c->stream, Hx, 2 * Kk, Kk, dord, dinv, V0, Kk, ne));
+        RSRR_HIP(gather_scale(c->stream, Hx + Kk, 2 * Kk, Kk, dord, dinv + ne, W0, Kk, ne));
+    }
     RSRR_HIP(zgemm(c->stream, 0, 0, Kk, ne, Kk, 1.0, Hs, Kk, 0, W0, Kk, 0, 0.0, T1, Kk, 0, 1));
     RSRR_HIP(zgemm(c->stream, 1, 0, ne, ne, Kk, 1.0, V0, Kk, 0, T1, Kk, 0, 0.0, Ared, ne, 0, 1));
     RSRR_HIP(scale_cols(c->stream, ne, ne, Ared, ne, dinv));
