@@ -120,6 +120,16 @@ def _pipeline(R, ctx, nep, C, U, NQ=500, KQ=2, prec=1):
     return out
 
 
+def _check_hankel_svd(out, ro):
+    """The gap count and the leading singular values of H (from the library's sketch or full
+    Jacobi SVD) agree with the oracle's full SVD of its own H."""
+    so = ro["ss"]["sigma_H"]
+    nb = out["nbar"]
+    assert nb == ro["ss"]["nbar"]
+    assert out["sigma_H"].size >= nb + 1
+    assert np.max(np.abs(out["sigma_H"][:nb] - so[:nb])) <= 1e-9 * so[0]
+
+
 def _match(got, ref):
     return max(np.min(np.abs(ref - g)) / max(1.0, abs(g)) for g in got)
 
@@ -143,6 +153,7 @@ def test_pipeline_qep_closed_form(R, ctx, prec):
     ro = O.rsrr(prob, C, U)
     oin = ro["lam"][ro["level"] < 0.98]
     assert _match(out["lam"][ins], oin) < 1e-9 and _match(oin, out["lam"][ins]) < 1e-9
+    _check_hankel_svd(out, ro)
 
 
 def test_pipeline_delay_lambert_w(R, ctx):
@@ -169,6 +180,7 @@ def test_pipeline_helmholtz_vs_oracle(R, ctx):
     ins = out["level"] < 0.98
     assert ins.sum() == oin.size == 4
     assert _match(out["lam"][ins], oin) < 1e-9 and _match(oin, out["lam"][ins]) < 1e-9
+    _check_hankel_svd(out, ro)
     assert out["resid"][ins].max() <= 1e-10
     for i in np.where(ins)[0]:
         assert O.residual(prob, out["lam"][i], out["V"][:, i]) <= 1e-10
