@@ -91,19 +91,18 @@ def build_workload(args):
 
 def measured_traffic():
     """HBM bytes per trailing-update launch from the committed rocprofv3 counter summary, or
-    None when the kernel source has changed since the counters were taken."""
+    None when the kernel or the LU driver has changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_trailing_update_helmholtz_n4096_N64_L64_mixed.md")
-    src = os.path.join(ROOT, "paper_1605_07951_amd", "csrc", "gemm.hip")
+    srcs = [os.path.join(ROOT, "paper_1605_07951_amd", "csrc", f) for f in ("gemm.hip", "lu.hip")]
     try:
         txt = open(path).read()
         val = int(txt.split("traffic_bytes_per_launch:")[1].split()[0])
-        sha = txt.split("source_sha256_16 (paper_1605_07951_amd/csrc/gemm.hip):")[1].split()[0]
+        sha = txt.split("source_sha256_16 (csrc/gemm.hip + csrc/lu.hip):")[1].split()[0]
+        h = hashlib.sha256(b"".join(open(s, "rb").read() for s in srcs)).hexdigest()[:16]
     except (OSError, IndexError, ValueError):
         return None
-    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != sha:
-        return None
-    return val
+    return val if h == sha else None
 
 
 def cpu_baseline(nep, C, U, npts):

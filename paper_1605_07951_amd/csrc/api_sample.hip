@@ -198,12 +198,14 @@ struct PhaseTimer {
 struct SampleBufs {
     void* Tlu; double2* Tres; int* ipiv; int2* perm; int2* tperm; int* info; double2* coef; double* frobp;
     double* frob; float2* D64; double2* R; double* norms; int* active; double2* zdev; void* inv; void* tmp;
-    int ld, np, nb; long sT, sP, sPerm, sTP, nparts, sInv, sTmp;
+    void* pair;
+    int ld, np, nb; long sT, sP, sPerm, sTP, nparts, sInv, sTmp, sPair;
     LUWork lu(const int* act, UpdateRecorder* rec) const
     {
         LUWork w;
         w.ipiv = ipiv; w.sP = sP; w.perm = perm; w.sPerm = sPerm; w.tperm = tperm; w.sTP = sTP; w.info = info;
         w.inv = inv; w.sInv = sInv; w.tmp = tmp; w.sTmp = sTmp; w.active = act; w.rec = rec;
+        w.pair = pair; w.sPair = sPair; w.ldpair = ld;
         return w;
     }
 };
@@ -221,6 +223,7 @@ static size_t per_point_bytes(int n, int L, int prec)
     if (prec != RSRR_PREC_C128) {
         b += (size_t)np * 2 * 128 * 128 * 8 / 2;          // diagonal-block inverses (nb = 128: n/128 panels)
         b += (size_t)128 * std::max(n, L) * 8;            // scratch rows
+        b += (size_t)lu_pair_elems(n, 128, (int)ld) * 8;  // paired trailing updates
     }
     return b;
 }
@@ -236,7 +239,9 @@ static rsrr_status alloc_bufs(rsrr_ctx* c, int n, int L, int J, int prec, int B,
     s.sTmp = fp32 ? (long)s.nb * std::max(n, L) : 0;
     s.inv = fp32 ? ws_get(c, WS_B0, (size_t)B * s.sInv * 8) : nullptr;
     s.tmp = fp32 ? ws_get(c, WS_B1, (size_t)B * s.sTmp * 8) : nullptr;
-    if (fp32 && (!s.inv || !s.tmp)) return RSRR_ENOMEM;
+    s.sPair = fp32 ? lu_pair_elems(n, max_panel<float>(), s.ld) : 0;  // any panel width the LU clamps to
+    s.pair = fp32 ? ws_get(c, WS_LUP, (size_t)B * s.sPair * 8) : nullptr;
+    if (fp32 && (!s.inv || !s.tmp || !s.pair)) return RSRR_ENOMEM;
     s.sT = (long)s.ld * n;
     s.sP = n;
     s.sPerm = (long)s.np * 2 * MAX_NB;
@@ -326,6 +331,7 @@ static LUWork lu_offset(const LUWork& w, long b0, int esz = 8)
     o.info = w.info + b0;
     if (w.inv) o.inv = (char*)w.inv + b0 * w.sInv * esz;
     if (w.tmp) o.tmp = (char*)w.tmp + b0 * w.sTmp * esz;
+    if (w.pair) o.pair = (char*)w.pair + b0 * w.sPair * esz;
     if (w.active) o.active = w.active + b0;
     return o;
 }

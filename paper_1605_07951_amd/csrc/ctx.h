@@ -17,7 +17,7 @@ enum WsSlot {
     WS_D64, WS_R, WS_NORM, WS_ACTIVE, WS_Z,
     WS_B0, WS_B1, WS_B2, WS_B3, WS_B4, WS_B5, WS_B6, WS_B7, WS_N1, WS_JAC, WS_TSQ, WS_TSAQ, WS_TSV,
     WS_GMF, WS_GMW, WS_GMK, WS_GMS, WS_GMT, WS_GMI,
-    WS_HS0, WS_HS1, WS_HS2, WS_HSW, WS_HSX, WS_HSD, WS_HSI,
+    WS_HS0, WS_HS1, WS_HS2, WS_HSW, WS_HSX, WS_HSD, WS_HSI, WS_LUP,
     WS_COUNT
 };
 

@@ -47,6 +47,8 @@ struct UpdateRecorder {
 //  inv   : complex-FP32 path only: panels*2*nb*nb complex (stride sInv), L11^-1, U11^-1
 //  tmp   : complex-FP32 path only: nb*max(n, nrhs) complex (stride sTmp)
 //  active: optional per-matrix mask; rec: optional trailing-update event recorder
+//  pair  : FP32 paths, optional: (ldpair*2*nb + nb*nb) elements per matrix (stride sPair,
+//          ldpair >= n): two panels then share one trailing update of depth 2nb
 struct LUWork {
     int* ipiv = nullptr; long sP = 0;
     int2* perm = nullptr; long sPerm = 0;
@@ -57,7 +59,10 @@ struct LUWork {
     const int* active = nullptr;
     UpdateRecorder* rec = nullptr;
     hipEvent_t first_panel = nullptr;  // recorded once the first panel and its row block are done
+    void* pair = nullptr; long sPair = 0; int ldpair = 0;
 };
+// Elements per matrix of the pair buffer for n x n matrices and panel width nb.
+inline long lu_pair_elems(int n, int nb, int ldpair) { return (long)ldpair * 2 * nb + (long)nb * nb; }
 
 // Blocked LU with partial pivoting of `batch` n x n matrices (stride sA).
 template <typename R>

@@ -497,6 +497,31 @@ static C* panel_inv(const LUWork& w, int p, int nb, int which)
     return (C*)w.inv + (long)(2 * p + which) * nb * nb;
 }
 
+// D(r0.., 0..cols) = S(r0.., 0..cols): rows r0..n-1 of a column block, per matrix.
+template <typename C>
+__global__ __launch_bounds__(256) void copy_rows_kernel(int r0, int n, int cols, const C* __restrict__ S, int lds,
+                                                         long sS, C* __restrict__ D, int ldd, long sD,
+                                                         const int* __restrict__ active)
+{
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    const long m = n - r0;
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= m * cols) return;
+    const int r = r0 + (int)(e % m), c = (int)(e / m);
+    D[b * sD + r + (long)c * ldd] = S[b * sS + r + (long)c * lds];
+}
+
+template <typename C>
+static void copy_rows(hipStream_t st, int r0, int n, int cols, const C* S, int lds, long sS, C* D, int ldd, long sD,
+                      const int* active, int batch)
+{
+    const long cnt = (long)(n - r0) * cols;
+    if (cnt <= 0) return;
+    hipLaunchKernelGGL(copy_rows_kernel<C>, dim3((unsigned)((cnt + 255) / 256), batch), dim3(256), 0, st, r0, n, cols,
+                       S, lds, sS, D, ldd, sD, active);
+}
+
 template <typename C>
 static hipError_t getrf_impl(hipStream_t st, C* A, long sA, int lda, int n, int nb, const LUWork& w,
                          int batch)
@@ -506,43 +531,90 @@ static hipError_t getrf_impl(hipStream_t st, C* A, long sA, int lda, int n, int 
     if (nb > max_panel<R>()) nb = max_panel<R>();
     if (nb < MIN_NB) nb = MIN_NB;  // perm/inv storage holds perm_panels(n) panels
     UpdateRecorder* rec = w.rec;
-    for (int c0 = 0; c0 < n; c0 += nb) {
-        const int jb = (n - c0 < nb) ? n - c0 : nb;
-        const int p = c0 / nb;
+    auto timed_update = [&](int rest, int kdepth, const C* Aop, int ldaop, long sAop, const C* Bop, C* Cop) {
+        const bool timed = rec && rec->used < rec->cap;
+        if (timed) (void)hipEventRecord(rec->ev[2 * rec->used], st);
+        (void)gemm_sub<C>(st, rest, rest, kdepth, Aop, ldaop, sAop, Bop, lda, sA, Cop, lda, sA, batch, 1);
+        if (timed) {
+            (void)hipEventRecord(rec->ev[2 * rec->used + 1], st);
+            rec->used++;
+            rec->flops += (elem_traits<C>::complex ? 8.0 : 2.0) * rest * (double)rest * kdepth * batch;
+        } else if (rec) {
+            rec->dropped++;
+        }
+    };
+    // panel p: factor, composed interchanges, diagonal-block inverses (FP32 paths)
+    auto panel = [&](int c0, int jb, int p) -> int2* {
         factor_panel<C>(st, A, sA, lda, n, c0, jb, w.ipiv, w.sP, w.info, w.tperm, w.sTP, 0, w.active, batch);
         int2* pm = w.perm + (long)p * 2 * MAX_NB;
-        hipLaunchKernelGGL(perm_build_kernel, dim3(batch), dim3(64), 0, st, w.ipiv, w.sP, c0, jb, pm, w.sPerm, w.active);
-        const int rest = n - c0 - jb;
+        hipLaunchKernelGGL(perm_build_kernel, dim3(batch), dim3(64), 0, st, w.ipiv, w.sP, c0, jb, pm, w.sPerm,
+                           w.active);
         if (use_inv) {
-            // L11^-1 and U11^-1 of this panel (also used by the solves)
             perm_trsm<C>(st, A, sA, lda, (const int2*)nullptr, 0, panel_inv<C>(w, p, nb, 0), w.sInv, nb, c0, jb, jb, 4,
                          w.active, batch, c0);
             perm_trsm<C>(st, A, sA, lda, (const int2*)nullptr, 0, panel_inv<C>(w, p, nb, 1), w.sInv, nb, c0, jb, jb, 5,
                          w.active, batch, c0);
         }
-        if (rest > 0) {
-            C* Ar = A + (long)(c0 + jb) * lda;
+        return pm;
+    };
+    // Two panels may share one trailing update of depth jb0 + jb1 (the deeper
+    // product keeps the matrix cores busier per byte of A22 read and written):
+    // panel p+1's columns get panel p's update first; the rows of L21_p are
+    // copied and interchanged like panel p+1's rows (the stored L21_p keeps
+    // panel p's row order, which the solves expect); the U rows of panel p+1
+    // receive panel p's update from that copy; then A22 -= [L21_p' L21_{p+1}]
+    // [U12_p; U12_{p+1}] in one product.
+    const bool pairing = use_inv && w.pair != nullptr;
+    for (int c0 = 0, p = 0; c0 < n;) {
+        const int jb0 = (n - c0 < nb) ? n - c0 : nb;
+        const int c1 = c0 + jb0;
+        const int jb1 = pairing ? ((n - c1 < nb) ? n - c1 : nb) : 0;
+        const int2* pm0 = panel(c0, jb0, p);
+        const int rest0 = n - c1;
+        if (rest0 > 0) {
+            C* Ar = A + (long)c1 * lda;
             if (use_inv) {
                 // interchanges on the right block (top rows to the scratch), then U12 = L11^-1 A12 on MFMA
-                perm_rows<C>(st, pm, w.sPerm, Ar, sA, lda, (C*)w.tmp, w.sTmp, nb, c0, jb, rest, w.active, batch);
-                (void)gemm_sub<C>(st, jb, rest, jb, panel_inv<C>(w, p, nb, 0), nb, w.sInv, (const C*)w.tmp, nb,
+                perm_rows<C>(st, pm0, w.sPerm, Ar, sA, lda, (C*)w.tmp, w.sTmp, nb, c0, jb0, rest0, w.active, batch);
+                (void)gemm_sub<C>(st, jb0, rest0, jb0, panel_inv<C>(w, p, nb, 0), nb, w.sInv, (const C*)w.tmp, nb,
                                   w.sTmp, Ar + c0, lda, sA, batch, 0, -1.0, 0.0);
             } else {
-                perm_trsm<C>(st, A, sA, lda, pm, w.sPerm, Ar, sA, lda, c0, jb, rest, 1, w.active, batch);
+                perm_trsm<C>(st, A, sA, lda, pm0, w.sPerm, Ar, sA, lda, c0, jb0, rest0, 1, w.active, batch);
             }
             if (c0 == 0 && w.first_panel) (void)hipEventRecord(w.first_panel, st);
-            const bool timed = rec && rec->used < rec->cap;
-            if (timed) (void)hipEventRecord(rec->ev[2 * rec->used], st);
-            (void)gemm_sub<C>(st, rest, rest, jb, A + (c0 + jb) + (long)c0 * lda, lda, sA, Ar + c0, lda, sA,
-                              Ar + c0 + jb, lda, sA, batch, 1);
-            if (timed) {
-                (void)hipEventRecord(rec->ev[2 * rec->used + 1], st);
-                rec->used++;
-                rec->flops += (elem_traits<C>::complex ? 8.0 : 2.0) * rest * (double)rest * jb * batch;
-            } else if (rec) {
-                rec->dropped++;
-            }
         }
+        const int c2 = c1 + jb1, rest2 = n - c2;
+        if (jb1 <= 0 || rest2 <= 0) {
+            if (rest0 > 0)
+                timed_update(rest0, jb0, A + c1 + (long)c0 * lda, lda, sA, A + c0 + (long)c1 * lda,
+                             A + c1 + (long)c1 * lda);
+            c0 = c1;
+            p += 1;
+            continue;
+        }
+        C* Wp = (C*)w.pair;
+        const int ldw = w.ldpair;
+        C* TL = Wp + (long)ldw * 2 * nb;
+        // panel p+1's columns receive panel p's update, then panel p+1
+        (void)gemm_sub<C>(st, rest0, jb1, jb0, A + c1 + (long)c0 * lda, lda, sA, A + c0 + (long)c1 * lda, lda, sA,
+                          A + c1 + (long)c1 * lda, lda, sA, batch);
+        const int2* pm1 = panel(c1, jb1, p + 1);
+        // L21_p rows c1.. into the pair buffer, interchanged like panel p+1 (top rows to TL)
+        copy_rows<C>(st, c1, n, jb0, A + (long)c0 * lda, lda, sA, Wp, ldw, w.sPair, w.active, batch);
+        perm_rows<C>(st, pm1, w.sPerm, Wp, w.sPair, ldw, TL, w.sPair, nb, c1, jb1, jb0, w.active, batch);
+        // panel p+1's interchanges on the trailing columns; its U rows get panel p's update, then L11^-1
+        C* Ar2 = A + (long)c2 * lda;
+        perm_rows<C>(st, pm1, w.sPerm, Ar2, sA, lda, (C*)w.tmp, w.sTmp, nb, c1, jb1, rest2, w.active, batch);
+        (void)gemm_sub<C>(st, jb1, rest2, jb0, TL, nb, w.sPair, A + c0 + (long)c2 * lda, lda, sA, (C*)w.tmp, nb,
+                          w.sTmp, batch);
+        (void)gemm_sub<C>(st, jb1, rest2, jb1, panel_inv<C>(w, p + 1, nb, 0), nb, w.sInv, (const C*)w.tmp, nb,
+                          w.sTmp, Ar2 + c1, lda, sA, batch, 0, -1.0, 0.0);
+        // [L21_p' L21_{p+1}] side by side, one update of depth jb0 + jb1
+        copy_rows<C>(st, c2, n, jb1, A + (long)c1 * lda, lda, sA, Wp + (long)ldw * jb0, ldw, w.sPair, w.active,
+                     batch);
+        timed_update(rest2, jb0 + jb1, Wp + c2, ldw, w.sPair, A + c0 + (long)c2 * lda, A + c2 + (long)c2 * lda);
+        c0 = c2;
+        p += 2;
     }
     return hipGetLastError();
 }
