@@ -28,6 +28,21 @@ namespace rsrr {
 // ----------------------------------------------------------------------------
 constexpr int CG_KT = 16, CG_NT = 256;
 
+// Tile t of a matrix -> (row tile, column tile): groups of TG_ROWS row tiles
+// sweep the columns together, so the workgroups in flight on one XCD share a
+// few row slices of A and column slices of B in its L2 instead of streaming
+// all of A once per column of tiles.
+constexpr int TG_ROWS = 8;
+__device__ __forceinline__ void tile_order(int t, int tilesM, int tilesN, int* ti, int* tj)
+{
+    const int span = TG_ROWS * tilesN;
+    const int g = t / span, first = g * TG_ROWS;
+    const int rows = min(tilesM - first, TG_ROWS);
+    const int in = t - g * span;
+    *ti = first + in % rows;
+    *tj = in / rows;
+}
+
 template <int WR, int WC, int BR, int BC, bool VEC, int TAG>
 __global__ __launch_bounds__(CG_NT, 2) void cgemm_mfma_kernel(
     int M, int N, int K, float alpha,
@@ -50,8 +65,10 @@ __global__ __launch_bounds__(CG_NT, 2) void cgemm_mfma_kernel(
     const long b = tile / per;
     if (b >= batch) return;
     const int t = (int)(tile - b * per);
-    const int i0 = (t % tilesM) * BM;
-    const int j0 = (t / tilesM) * BN;
+    int ti, tj;
+    tile_order(t, tilesM, tilesN, &ti, &tj);
+    const int i0 = ti * BM;
+    const int j0 = tj * BN;
     const float2* Ab = A + b * sA;
     const float2* Bb = B + b * sB;
     float2* Cb = C + b * sC;
@@ -244,8 +261,10 @@ __global__ __launch_bounds__(CG_NT, 2) void sgemm_mfma_kernel(
     const long b = tile / per;
     if (b >= batch) return;
     const int t = (int)(tile - b * per);
-    const int i0 = (t % tilesM) * BM;
-    const int j0 = (t / tilesM) * BN;
+    int ti, tj;
+    tile_order(t, tilesM, tilesN, &ti, &tj);
+    const int i0 = ti * BM;
+    const int j0 = tj * BN;
     const float* Ab = A + b * sA;
     const float* Bb = B + b * sB;
     float* Cb = C + b * sC;
@@ -424,8 +443,10 @@ __global__ __launch_bounds__(ZG_NT, 2) void zgemm_mfma_kernel(
     const long b = tile / per;
     if (b >= batch) return;
     const int t = (int)(tile - b * per);
-    const int i0 = (t % tilesM) * ZG_BM;
-    const int j0 = (t / tilesM) * ZG_BN;
+    int ti, tj;
+    tile_order(t, tilesM, tilesN, &ti, &tj);
+    const int i0 = ti * ZG_BM;
+    const int j0 = tj * ZG_BN;
     const double2* Ab = A + b * sA;
     const double2* Bb = B + b * sB;
     double2* Cb = C + b * sC;
