@@ -125,7 +125,8 @@ struct BucketBufs {
     void* T; double2* T128; double2* Ub; double2* Xb; double2* R; float2* D64; int* ipiv; int2* perm; int2* tperm;
     int* info; void* inv; void* tmp; int* nk; double2* coef; double* frobp; double* frob; double* un; double* rn;
     double* xn; double* inv_s; double* scl; int* active; double* prev; double* resid; int* iters; double* ones;
-    long sT, sU, sP, sPerm, sTP, sInv, sTmp;
+    void* pair;
+    long sT, sU, sP, sPerm, sTP, sInv, sTmp, sPair;
 };
 
 // Everything a bucket does on the device, in stream order (capturable).
@@ -175,6 +176,7 @@ rsrr_status run_bucket(rsrr_ctx* c, hipStream_t sm, const rsrr_instance* inst, c
     LUWork w;
     w.ipiv = b.ipiv; w.sP = b.sP; w.perm = b.perm; w.sPerm = b.sPerm; w.tperm = b.tperm; w.sTP = b.sTP;
     w.info = b.info; w.inv = b.inv; w.sInv = b.sInv; w.tmp = b.tmp; w.sTmp = b.sTmp;
+    w.pair = b.pair; w.sPair = b.sPair; w.ldpair = P;
     if (mixed) RSRR_HIP(getrf_batched<float>(sm, (float2*)b.T, b.sT, P, P, nb, w, (int)M));
     else RSRR_HIP(getrf_batched<double>(sm, (double2*)b.T, b.sT, P, P, nb, w, (int)M));
     RSRR_HIP(ir_init(sm, (int)M, b.info, b.active, b.prev, b.resid, b.iters));
@@ -308,6 +310,7 @@ extern "C" rsrr_status rsrr_sample_batched(rsrr_ctx* c, int count, const rsrr_in
         // ceil(P/nb) panels of 2 nb^2 for any nb <= nbmax: at most 2 nbmax (P + nbmax)
         b.sInv = mixed ? 2L * nbmax * (P + nbmax) : 0;
         b.sTmp = mixed ? (long)nbmax * std::max(P, Lmax) : 0;
+        b.sPair = mixed ? lu_pair_elems(P, nbmax, P) : 0;
         const size_t esz = mixed ? 8 : 16;
         long nparts_max = ((long)maxn * maxn + 255) / 256;
         hipStream_t sm = c->stream;
@@ -340,8 +343,9 @@ extern "C" rsrr_status rsrr_sample_batched(rsrr_ctx* c, int count, const rsrr_in
         b.resid = (double*)bget(S, s++, (size_t)M * 8, sm);
         b.iters = (int*)bget(S, s++, (size_t)M * 4, sm);
         b.ones = (double*)bget(S, s++, (size_t)M * Lmax * 8, sm);
+        b.pair = mixed ? bget(S, s++, (size_t)M * b.sPair * 8, sm) : (void*)(s++, nullptr);
         if (!b.T || !b.T128 || !b.Ub || !b.Xb || !b.R || !b.D64 || !b.ipiv || !b.perm || !b.tperm || !b.info ||
-            (mixed && (!b.inv || !b.tmp)) || !b.nk || !b.coef || !b.frobp || !b.frob || !b.un || !b.rn || !b.xn ||
+            (mixed && (!b.inv || !b.tmp || !b.pair)) || !b.nk || !b.coef || !b.frobp || !b.frob || !b.un || !b.rn || !b.xn ||
             !b.inv_s || !b.scl || !b.active || !b.prev || !b.resid || !b.iters || !b.ones)
             return RSRR_ENOMEM;
         // the first solve narrows U with scale 1: ones in scl
