@@ -53,6 +53,7 @@ def parse():
                     help="skip the comparison run (plain FP64 sampling; for gmres the direct path)")
     ap.add_argument("--sample-only", action="store_true", help="skip the basis/projection/SS-FULL pass")
     ap.add_argument("--nq", type=int, default=500, help="SS-FULL quadrature nodes")
+    ap.add_argument("--latency-runs", type=int, default=5, help="whole-method runs for the NEP latency p50/p99")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy before the timed region (counter calibration)")
     ap.add_argument("--instances", type=int, default=256, help="batched: QEP instances")
@@ -717,6 +718,22 @@ def main():
                                  "nbar": sol["nbar"], "gmax": sol["gmax"], "eigs_inside": int(ins.sum()),
                                  "eig_resid_max_inside": float(sol["resid"][ins].max()) if ins.any() else None,
                                  "lambda_inside": [[float(l.real), float(l.imag)] for l in sol["lam"][ins]]}
+        # latency of the whole method for one NEP (sampling, basis, projection, SS-FULL), repeated
+        lat = []
+        for _ in range(args.latency_runs):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            R.rsrr_sample(ctx, dnep, z, U, prec=prec, S=S)
+            Q, k, _ = R.rsrr_basis(ctx, S, n, 1e-14, kmax=kmax)
+            AQ, terms = R.rsrr_project(ctx, dnep, Q, k, C.gamma, radius)
+            R.rsrr_solve(ctx, dnep, Q, k, AQ, terms, C.gamma, C.a, C.b, NQ=args.nq, KQ=2)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t0)
+        if lat:
+            res["nep_latency_s"] = {"p50": round(_pct(lat, 50), 4), "p99": round(_pct(lat, 99), 4),
+                                    "mean": round(sum(lat) / len(lat), 4), "runs": len(lat),
+                                    "what": "one NEP alone, whole method: rsrr_sample + rsrr_basis + rsrr_project"
+                                            " + rsrr_solve (eigenpairs and residuals on the host)"}
 
     if not args.no_plain and prec == R.RSRR_PREC_C64_IR:
         # plain FP64 path on the same inputs for the mixed/plain speedup
