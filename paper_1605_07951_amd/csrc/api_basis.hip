@@ -245,18 +245,30 @@ extern "C" rsrr_status rsrr_project(rsrr_ctx* c, const rsrr_nep* nep, const doub
         }
         const int d = taylor_degree(radius, 2.0 * rr);
         if (max_terms < d + 1) return -9;
-        double2* Tp = (double2*)ws_get(c, WS_B0, (size_t)n * n * 16);
-        double2* W = (double2*)ws_get(c, WS_B1, (size_t)n * k * 16);
+        // groups of G terms: generated together, then two batched products T_p Q and Q^H (T_p Q)
+        const int P = d + 1;
+        const size_t per = (size_t)n * n * 16 + (size_t)n * k * 16;
+        size_t fr = 0, tot = 0;
+        RSRR_HIP(hipMemGetInfo(&fr, &tot));
+        const size_t budget = std::min<size_t>(fr / 4, (size_t)8 << 30);
+        const int G = (int)std::max<size_t>(1, std::min<size_t>((size_t)P, budget / per));
+        double2* Tp = (double2*)ws_get(c, WS_B0, (size_t)G * n * n * 16);
+        double2* W = (double2*)ws_get(c, WS_B1, (size_t)G * n * k * 16);
         if (!Tp || !W) return RSRR_ENOMEM;
-        for (int p = 0; p <= d; ++p) {
-            RSRR_HIP(helmholtz_taylor(c->stream, n, nep->points, nep->w, gamma[0], gamma[1], p, Tp, n));
-            RSRR_HIP(zgemm(c->stream, 0, 0, n, k, n, 1.0, Tp, n, 0, Q, ldq, 0, 0.0, W, n, 0, 1));
-            RSRR_HIP(zgemm(c->stream, 1, 0, k, k, n, 1.0, Q, ldq, 0, W, n, 0, 0.0, out + (size_t)p * k * k, k, 0, 1));
+        const long nn = (long)n * n, nk = (long)n * k;
+        for (int p0 = 0; p0 < P; p0 += G) {
+            const int g = std::min(G, P - p0);
+            RSRR_HIP(helmholtz_taylor_range(c->stream, n, nep->points, nep->w, gamma[0], gamma[1], p0, g, Tp, n, nn));
+            RSRR_HIP(zgemm(c->stream, 0, 0, n, k, n, 1.0, Tp, n, nn, Q, ldq, 0, 0.0, W, n, nk, g));
+            RSRR_HIP(zgemm(c->stream, 1, 0, k, k, n, 1.0, Q, ldq, 0, W, n, nk, 0.0, out + (size_t)p0 * k * k, k,
+                           (long)k * k, g));
+        }
+        for (int p = 0; p < P; ++p) {
             rsrr_term t = {};
             t.c_re = 1.0; t.p = p; t.z0_re = gamma[0]; t.z0_im = gamma[1];
             terms_out[p] = t;
         }
-        *J_eff = d + 1;
+        *J_eff = P;
     }
     RSRR_HIP(hipStreamSynchronize(c->stream));
     return RSRR_OK;

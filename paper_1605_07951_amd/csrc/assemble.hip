@@ -238,6 +238,63 @@ __global__ __launch_bounds__(AS_NT) void helm_taylor_kernel(int n, const double*
     Tp[i + (long)c * ld] = t;
 }
 
+// Terms p0 .. p0+G-1 at once (term p0+g at Tp + g*sT): the distance, the
+// phase and the decay are evaluated once per entry and the magnitude is
+// carried from one degree to the next (times r/p).
+__global__ __launch_bounds__(AS_NT) void helm_taylor_range_kernel(int n, const double* __restrict__ pts, double w,
+                                                                   double2 gamma, int p0, int G, double inv_p0fact,
+                                                                   double2* __restrict__ Tp, int ld, long sT)
+{
+    const long nn = (long)n * n;
+    const long e = (long)blockIdx.x * AS_NT + threadIdx.x;
+    if (e >= nn) return;
+    const int i = (int)(e % n), c = (int)(e / n);
+    const double inv4pi = 0.25 / M_PI;
+    double2* out = Tp + i + (long)c * ld;
+    if (i == c) {
+        for (int g = 0; g < G; ++g) {
+            const int p = p0 + g;
+            double2 t = make_double2(0.0, 0.0);
+            if (p == 0) t = make_double2(0.5 * sqrt(w / M_PI) - gamma.y * w * inv4pi, gamma.x * w * inv4pi);
+            else if (p == 1) t = make_double2(0.0, w * inv4pi);
+            out[g * sT] = t;
+        }
+        return;
+    }
+    const double dx = pts[3 * i] - pts[3 * c];
+    const double dy = pts[3 * i + 1] - pts[3 * c + 1];
+    const double dz = pts[3 * i + 2] - pts[3 * c + 2];
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    double s, co;
+    sincos(gamma.x * r, &s, &co);
+    double mag = w * inv4pi / r * exp(-gamma.y * r) * pow(r, (double)p0) * inv_p0fact;
+    for (int g = 0; g < G; ++g) {
+        const int p = p0 + g;
+        if (g > 0) mag *= r / p;
+        // i^p rotates by p quarter turns
+        const double re = mag * co, im = mag * s;
+        double2 t;
+        switch (p & 3) {
+            case 0: t = make_double2(re, im); break;
+            case 1: t = make_double2(-im, re); break;
+            case 2: t = make_double2(-re, -im); break;
+            default: t = make_double2(im, -re); break;
+        }
+        out[g * sT] = t;
+    }
+}
+
+hipError_t helmholtz_taylor_range(hipStream_t st, int n, const double* pts, double w, double gre, double gim, int p0,
+                                  int G, double2* Tp, int ld, long sT)
+{
+    double pf = 1.0;
+    for (int q = 2; q <= p0; ++q) pf *= q;
+    const long nn = (long)n * n;
+    hipLaunchKernelGGL(helm_taylor_range_kernel, dim3((unsigned)((nn + AS_NT - 1) / AS_NT)), dim3(AS_NT), 0, st, n,
+                       pts, w, make_double2(gre, gim), p0, G, 1.0 / pf, Tp, ld, sT);
+    return hipGetLastError();
+}
+
 hipError_t helmholtz_taylor(hipStream_t st, int n, const double* pts, double w, double gre, double gim, int p,
                             double2* Tp, int ld)
 {

@@ -95,6 +95,9 @@ hipError_t assemble_helmholtz(hipStream_t st, int n, const double* pts, double w
                               double* frob_part, double* frob);
 hipError_t helmholtz_taylor(hipStream_t st, int n, const double* pts, double w, double gre, double gim, int p,
                             double2* Tp, int ld);
+// Taylor terms p0 .. p0+G-1 of the Helmholtz matrix about gamma, term p0+g at Tp + g*sT.
+hipError_t helmholtz_taylor_range(hipStream_t st, int n, const double* pts, double w, double gre, double gim, int p0,
+                                  int G, double2* Tp, int ld, long sT);
 
 // ---- element-wise helpers (ir.hip) ----
 hipError_t bcast_to_c64(hipStream_t st, int n, int L, const double2* U, int ldu, float2* D, int ldd, long sD, int B);

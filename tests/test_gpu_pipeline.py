@@ -130,6 +130,28 @@ def _check_hankel_svd(out, ro):
     assert np.max(np.abs(out["sigma_H"][:nb] - so[:nb])) <= 1e-9 * so[0]
 
 
+def _check_eigvecs(out, ins, ro, m=0.98):
+    """Eigenvectors against the oracle's: per cluster of eigenvalues (within 1e-3 relative; a
+    simple eigenvalue is a cluster of one), the cosine of the largest principal angle between the
+    two spans is at least 1 - 1e-9."""
+    lam, V = out["lam"][ins], out["V"][:, ins]
+    ko = ro["level"] < m
+    lo, Vo = ro["lam"][ko], ro["V"][:, ko]
+    seen = np.zeros(lo.size, bool)
+    for i in range(lo.size):
+        if seen[i]:
+            continue
+        tol = 1e-3 * max(1.0, abs(lo[i]))
+        cl = np.where(np.abs(lo - lo[i]) <= tol)[0]
+        seen[cl] = True
+        g = np.where(np.abs(lam - lo[i]) <= tol)[0]
+        assert g.size == cl.size, (lo[i], g.size, cl.size)
+        qa = np.linalg.qr(V[:, g])[0]
+        qb = np.linalg.qr(Vo[:, cl])[0]
+        cos = np.linalg.svd(qa.conj().T @ qb, compute_uv=False).min()
+        assert cos >= 1 - 1e-9, (lo[i], cl.size, 1 - cos)
+
+
 def _match(got, ref):
     return max(np.min(np.abs(ref - g)) / max(1.0, abs(g)) for g in got)
 
@@ -154,6 +176,7 @@ def test_pipeline_qep_closed_form(R, ctx, prec):
     oin = ro["lam"][ro["level"] < 0.98]
     assert _match(out["lam"][ins], oin) < 1e-9 and _match(oin, out["lam"][ins]) < 1e-9
     _check_hankel_svd(out, ro)
+    _check_eigvecs(out, ins, ro)
 
 
 def test_pipeline_delay_lambert_w(R, ctx):
@@ -167,6 +190,7 @@ def test_pipeline_delay_lambert_w(R, ctx):
     assert out["resid"][ins].max() <= 1e-10
     # the double eigenvalue: the two eigenvectors span the oracle's 2-dim eigenspace
     prob = O.Problem(nep)
+    _check_eigvecs(out, ins, O.rsrr(prob, C, U))
     for i in np.where(ins)[0]:
         assert O.residual(prob, out["lam"][i], out["V"][:, i]) <= 1e-10
 
@@ -181,6 +205,7 @@ def test_pipeline_helmholtz_vs_oracle(R, ctx):
     assert ins.sum() == oin.size == 4
     assert _match(out["lam"][ins], oin) < 1e-9 and _match(oin, out["lam"][ins]) < 1e-9
     _check_hankel_svd(out, ro)
+    _check_eigvecs(out, ins, ro)
     assert out["resid"][ins].max() <= 1e-10
     for i in np.where(ins)[0]:
         assert O.residual(prob, out["lam"][i], out["V"][:, i]) <= 1e-10
