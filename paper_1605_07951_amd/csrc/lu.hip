@@ -497,6 +497,138 @@ static C* panel_inv(const LUWork& w, int p, int nb, int which)
     return (C*)w.inv + (long)(2 * p + which) * nb * nb;
 }
 
+// Inverses of the two triangles of the jb x jb diagonal block at (c0, c0):
+// L11^-1 (unit lower, which = 0) at inv + (2p) nb^2 and U11^-1 (upper,
+// which = 1) at inv + (2p+1) nb^2, ld nb, the other triangle zero.  By 32 x 32
+// blocks: one workgroup per (block column j, triangle, matrix).  Each needed
+// diagonal block is inverted by one wave, a lane per column (substitution in
+// registers, the triangle read from LDS by broadcast); then block column j of
+// the inverse follows by blocked substitution: for L, X_jj = L_jj^-1 and
+// X_ij = -L_ii^-1 sum_{j<=k<i} L_ik X_kj; for U, upwards from X_jj = U_jj^-1.
+// A zero diagonal entry of U is skipped (as in the solves).  Rows and columns
+// past jb are padded with the identity.
+constexpr int TI_B = 32, TI_MAXB = 4, TI_NT = 256;
+
+template <typename C>
+__global__ __launch_bounds__(TI_NT) void tri_inv_kernel(const C* __restrict__ LU, long sLU, int ldl, int c0, int jb,
+                                                         C* __restrict__ inv, long sInv, int nb,
+                                                         const int* __restrict__ active)
+{
+    const int j = blockIdx.x, b = blockIdx.y, which = blockIdx.z;
+    if (active && !active[b]) return;
+    const int nbk = (jb + TI_B - 1) / TI_B;
+    const C* A = LU + (long)b * sLU + c0 + (long)c0 * ldl;   // the diagonal block, A(r, c) = A[r + c*ldl]
+    C* X = (C*)inv + (long)b * sInv + (long)(2 * (c0 / nb) + which) * nb * nb;
+    __shared__ C D[TI_MAXB][TI_B][TI_B + 1];   // inverted diagonal blocks (slot = block row)
+    __shared__ C Xc[TI_MAXB][TI_B][TI_B + 1];  // block column j of the inverse
+    __shared__ C Tt[TI_B][TI_B + 1];           // an off-diagonal block of the triangle
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    auto entry = [&](int r, int c) -> C {        // padded triangle entry (r, c < nbk * 32)
+        if (r < jb && c < jb) return A[r + (long)c * ldl];
+        return from_real<C>((real_t<C>)(r == c ? 1 : 0));
+    };
+    // 1. diagonal blocks i = j .. nbk-1 (L) or 0 .. j (U), staged in D[i], then inverted by
+    //    wave i (TI_MAXB waves), a lane per column
+    for (int e = tid; e < nbk * TI_B * TI_B; e += TI_NT) {
+        const int i = e / (TI_B * TI_B), r = e % TI_B, c = (e / TI_B) % TI_B;
+        D[i][r][c] = entry(i * TI_B + r, i * TI_B + c);
+    }
+    __syncthreads();
+    C x[TI_B];
+    const int i1 = wave, col = lane;
+    const bool mine = i1 < nbk && (which == 0 ? i1 >= j : i1 <= j) && col < TI_B;
+    if (mine) {
+        if (which == 0) {
+#pragma unroll
+            for (int r = 0; r < TI_B; ++r) {
+                C s = from_real<C>((real_t<C>)(r == col ? 1 : 0));
+#pragma unroll
+                for (int l = 0; l < r; ++l) s = cfms(s, D[i1][r][l], x[l]);
+                x[r] = s;
+            }
+        } else {
+#pragma unroll
+            for (int r = TI_B - 1; r >= 0; --r) {
+                C s = from_real<C>((real_t<C>)(r == col ? 1 : 0));
+#pragma unroll
+                for (int l = r + 1; l < TI_B; ++l) s = cfms(s, D[i1][r][l], x[l]);
+                const C d = D[i1][r][r];
+                x[r] = is_zero(d) ? s : cmul(s, crecip(d));
+            }
+        }
+    }
+    __syncthreads();
+    if (mine) {
+#pragma unroll
+        for (int r = 0; r < TI_B; ++r) D[i1][r][col] = x[r];
+    }
+    __syncthreads();
+    // 2. block column j
+    for (int e = tid; e < TI_B * TI_B; e += TI_NT) {
+        const int r = e % TI_B, c = e / TI_B;
+        Xc[j][r][c] = D[j][r][c];
+    }
+    __syncthreads();
+    const int steps = which == 0 ? nbk - 1 - j : j;
+    for (int s = 1; s <= steps; ++s) {
+        const int i = which == 0 ? j + s : j - s;
+        // acc = sum_k T_ik X_kj over k between i and j (exclusive of i), 4 outputs per thread
+        C acc[TI_B * TI_B / TI_NT];
+#pragma unroll
+        for (int q = 0; q < TI_B * TI_B / TI_NT; ++q) acc[q] = czero<C>();
+        const int k0 = which == 0 ? j : i + 1, k1 = which == 0 ? i - 1 : j;
+        for (int k = k0; k <= k1; ++k) {
+            for (int e = tid; e < TI_B * TI_B; e += TI_NT) {
+                const int r = e % TI_B, c = e / TI_B;
+                Tt[r][c] = entry(i * TI_B + r, k * TI_B + c);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < TI_B * TI_B / TI_NT; ++q) {
+                const int e = tid + TI_NT * q;
+                const int r = e % TI_B, c = e / TI_B;
+                C a = acc[q];
+                for (int l = 0; l < TI_B; ++l) a = cfma(a, Tt[r][l], Xc[k][l][c]);
+                acc[q] = a;
+            }
+            __syncthreads();
+        }
+        // Xc[i] = -D[i] acc  (acc staged through Tt)
+#pragma unroll
+        for (int q = 0; q < TI_B * TI_B / TI_NT; ++q) {
+            const int e = tid + TI_NT * q;
+            Tt[e % TI_B][e / TI_B] = acc[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < TI_B * TI_B / TI_NT; ++q) {
+            const int e = tid + TI_NT * q;
+            const int r = e % TI_B, c = e / TI_B;
+            C a = czero<C>();
+            for (int l = 0; l < TI_B; ++l) a = cfms(a, D[i][r][l], Tt[l][c]);
+            Xc[i][r][c] = a;
+        }
+        __syncthreads();
+    }
+    // 3. write block column j (zeros in the other triangle), rows and columns < jb
+    for (int e = tid; e < nbk * TI_B * TI_B; e += TI_NT) {
+        const int rr = e % (nbk * TI_B), c = e / (nbk * TI_B);
+        const int gc = j * TI_B + c, i = rr / TI_B, r = rr % TI_B;
+        if (rr >= jb || gc >= jb) continue;
+        const bool in = which == 0 ? i >= j : i <= j;
+        X[rr + (long)gc * nb] = in ? Xc[i][r][c] : czero<C>();
+    }
+}
+
+template <typename C>
+static void tri_inv(hipStream_t st, const C* LU, long sLU, int ldl, int c0, int jb, C* inv, long sInv, int nb,
+                    const int* active, int batch)
+{
+    const int nbk = (jb + TI_B - 1) / TI_B;
+    hipLaunchKernelGGL(tri_inv_kernel<C>, dim3(nbk, batch, 2), dim3(TI_NT), 0, st, LU, sLU, ldl, c0, jb, inv, sInv,
+                       nb, active);
+}
+
 // D(r0.., 0..cols) = S(r0.., 0..cols): rows r0..n-1 of a column block, per matrix.
 template <typename C>
 __global__ __launch_bounds__(256) void copy_rows_kernel(int r0, int n, int cols, const C* __restrict__ S, int lds,
@@ -549,12 +681,7 @@ static hipError_t getrf_impl(hipStream_t st, C* A, long sA, int lda, int n, int 
         int2* pm = w.perm + (long)p * 2 * MAX_NB;
         hipLaunchKernelGGL(perm_build_kernel, dim3(batch), dim3(64), 0, st, w.ipiv, w.sP, c0, jb, pm, w.sPerm,
                            w.active);
-        if (use_inv) {
-            perm_trsm<C>(st, A, sA, lda, (const int2*)nullptr, 0, panel_inv<C>(w, p, nb, 0), w.sInv, nb, c0, jb, jb, 4,
-                         w.active, batch, c0);
-            perm_trsm<C>(st, A, sA, lda, (const int2*)nullptr, 0, panel_inv<C>(w, p, nb, 1), w.sInv, nb, c0, jb, jb, 5,
-                         w.active, batch, c0);
-        }
+        if constexpr (use_inv) tri_inv<C>(st, A, sA, lda, c0, jb, (C*)w.inv, w.sInv, nb, w.active, batch);
         return pm;
     };
     // Two panels may share one trailing update of depth jb0 + jb1 (the deeper
