@@ -42,12 +42,16 @@ struct GraphEntry {
     std::vector<int> nk_host;
 };
 
+constexpr int N_BUCKET_STREAMS = 8;  // replayed buckets run side by side on these (default priority)
+
 struct BatchedState {
     std::map<long, int> tuned;                    // (P*2 + prec) -> nb
     std::map<long, std::unique_ptr<GraphEntry>> graphs;  // bucket P*2+prec -> captured graph
     std::vector<void*> bufs;
     std::vector<size_t> sizes;
     bool file_loaded = false;
+    hipStream_t streams[N_BUCKET_STREAMS] = {};
+    hipEvent_t done[N_BUCKET_STREAMS] = {};
 };
 
 std::map<rsrr_ctx*, std::unique_ptr<BatchedState>>& states()
@@ -230,6 +234,10 @@ void batched_release(rsrr_ctx* c)
     if (it == m.end()) return;
     for (auto& g : it->second->graphs)
         if (g.second && g.second->exec) (void)hipGraphExecDestroy(g.second->exec);
+    for (int i = 0; i < N_BUCKET_STREAMS; ++i) {
+        if (it->second->streams[i]) (void)hipStreamDestroy(it->second->streams[i]);
+        if (it->second->done[i]) (void)hipEventDestroy(it->second->done[i]);
+    }
     for (void* p : it->second->bufs)
         if (p) (void)hipFree(p);
     m.erase(it);
@@ -271,6 +279,53 @@ extern "C" rsrr_status rsrr_sample_batched(rsrr_ctx* c, int count, const rsrr_in
     for (int i = 0; i < count; ++i) buckets[(inst[i].nep.n + BUCKET - 1) / BUCKET * BUCKET].push_back(i);
 
     int any_sing = 0, any_fb = 0, any_nan = 0;
+    // Replayed buckets (their own buffers) run side by side on a pool of streams and
+    // report after all of them; eager buckets share buffers and report one by one.
+    struct Pending { std::vector<int> ids; std::vector<long> off; long M; int* info; int* iters; double* resid; };
+    std::vector<Pending> pending;
+    if (use_graph && !S.streams[0]) {
+        for (int i = 0; i < N_BUCKET_STREAMS; ++i) {
+            RSRR_HIP(hipStreamCreateWithFlags(&S.streams[i], hipStreamNonBlocking));
+            RSRR_HIP(hipEventCreateWithFlags(&S.done[i], hipEventDisableTiming));
+        }
+    }
+    int nlaunched = 0;
+    // diagnostics of one bucket back to the host; points above the residual bar are redone in FP64
+    auto report = [&](const std::vector<int>& ids, const std::vector<long>& off, long M, const int* dinfo,
+                      const int* diters, const double* dres) -> rsrr_status {
+        std::vector<int> hinfo(M), hit(M);
+        std::vector<double> hres(M);
+        RSRR_HIP(hipMemcpyAsync(hinfo.data(), dinfo, (size_t)M * 4, hipMemcpyDeviceToHost, c->stream));
+        RSRR_HIP(hipMemcpyAsync(hit.data(), diters, (size_t)M * 4, hipMemcpyDeviceToHost, c->stream));
+        RSRR_HIP(hipMemcpyAsync(hres.data(), dres, (size_t)M * 8, hipMemcpyDeviceToHost, c->stream));
+        RSRR_HIP(hipStreamSynchronize(c->stream));
+        for (size_t q = 0; q < ids.size(); ++q) {
+            const rsrr_instance& in = inst[ids[q]];
+            for (int k = 0; k < in.N; ++k) {
+                const long m = off[q] + k;
+                rsrr_point_info pi{};
+                pi.info = hinfo[m];
+                pi.ir_iters = hit[m];
+                pi.resid = hres[m];
+                if (hinfo[m] > 0) any_sing = 1;
+                if (hinfo[m] < 0) any_nan = 1;
+                if (hinfo[m] == 0 && !(hres[m] <= 1e-10)) {
+                    // redo this point on the FP64 path
+                    rsrr_point_info fpi;
+                    const rsrr_status st = rsrr_sample(c, &in.nep, 1, in.z + 2 * k, in.U, in.L, in.ldu,
+                                                       RSRR_PREC_C128, in.S + 2 * (size_t)k * in.L * in.lds, in.lds,
+                                                       &fpi);
+                    if (st < 0 || st == RSRR_EDEVICE || st == RSRR_ENOMEM) return st;
+                    pi.fallback = 1;
+                    pi.resid = fpi.resid;
+                    pi.info = fpi.info;
+                    any_fb = 1;
+                }
+                if (info) info[pbase[ids[q]] + k] = pi;
+            }
+        }
+        return RSRR_OK;
+    };
     for (auto& kv : buckets) {
         const int P = kv.first;
         const std::vector<int>& ids = kv.second;
@@ -425,50 +480,34 @@ extern "C" rsrr_status rsrr_sample_batched(rsrr_ctx* c, int count, const rsrr_in
                 const hipError_t ie = hipGraphInstantiate(&slot->exec, g, nullptr, nullptr, 0);
                 (void)hipGraphDestroy(g);
                 if (ie != hipSuccess) { slot.reset(); return RSRR_EDEVICE; }
-            } else {
-                RSRR_HIP(hipEventRecord(c->fork, c->stream));
-                RSRR_HIP(hipStreamWaitEvent(c->aux, c->fork, 0));
             }
-            RSRR_HIP(hipGraphLaunch(slot->exec, c->aux));
-            RSRR_HIP(hipEventRecord(c->join, c->aux));
-            RSRR_HIP(hipStreamWaitEvent(c->stream, c->join, 0));
+            // after everything enqueued on the context stream so far
+            hipStream_t ps = S.streams[nlaunched % N_BUCKET_STREAMS];
+            RSRR_HIP(hipEventRecord(c->fork, c->stream));
+            RSRR_HIP(hipStreamWaitEvent(ps, c->fork, 0));
+            RSRR_HIP(hipGraphLaunch(slot->exec, ps));
+            ++nlaunched;
+            pending.push_back(Pending{ids, off, M, b.info, b.iters, b.resid});
+            continue;
         } else {
             rsrr_status st = run_bucket(c, c->stream, inst, ids, off, P, Lmax, M, prec, nb, b, coef.data(), nk.data(),
                                         maxit);
             if (st) return st;
         }
 
-        // diagnostics back to the host
-        std::vector<int> hinfo(M), hit(M);
-        std::vector<double> hres(M);
-        RSRR_HIP(hipMemcpyAsync(hinfo.data(), b.info, (size_t)M * 4, hipMemcpyDeviceToHost, c->stream));
-        RSRR_HIP(hipMemcpyAsync(hit.data(), b.iters, (size_t)M * 4, hipMemcpyDeviceToHost, c->stream));
-        RSRR_HIP(hipMemcpyAsync(hres.data(), b.resid, (size_t)M * 8, hipMemcpyDeviceToHost, c->stream));
-        RSRR_HIP(hipStreamSynchronize(c->stream));
-        for (size_t q = 0; q < ids.size(); ++q) {
-            const rsrr_instance& in = inst[ids[q]];
-            for (int k = 0; k < in.N; ++k) {
-                const long m = off[q] + k;
-                rsrr_point_info pi{};
-                pi.info = hinfo[m];
-                pi.ir_iters = hit[m];
-                pi.resid = hres[m];
-                if (hinfo[m] > 0) any_sing = 1;
-                if (hinfo[m] < 0) any_nan = 1;
-                if (hinfo[m] == 0 && !(hres[m] <= 1e-10)) {
-                    // redo this point on the FP64 path
-                    rsrr_point_info fpi;
-                    const rsrr_status st = rsrr_sample(c, &in.nep, 1, in.z + 2 * k, in.U, in.L, in.ldu,
-                                                       RSRR_PREC_C128, in.S + 2 * (size_t)k * in.L * in.lds, in.lds,
-                                                       &fpi);
-                    if (st < 0 || st == RSRR_EDEVICE || st == RSRR_ENOMEM) return st;
-                    pi.fallback = 1;
-                    pi.resid = fpi.resid;
-                    pi.info = fpi.info;
-                    any_fb = 1;
-                }
-                if (info) info[pbase[ids[q]] + k] = pi;
-            }
+        {
+            const rsrr_status st = report(ids, off, M, b.info, b.iters, b.resid);
+            if (st) return st;
+        }
+    }
+    if (!pending.empty()) {
+        for (int i = 0; i < std::min(nlaunched, N_BUCKET_STREAMS); ++i) {
+            RSRR_HIP(hipEventRecord(S.done[i], S.streams[i]));
+            RSRR_HIP(hipStreamWaitEvent(c->stream, S.done[i], 0));
+        }
+        for (const Pending& pd : pending) {
+            const rsrr_status st = report(pd.ids, pd.off, pd.M, pd.info, pd.iters, pd.resid);
+            if (st) return st;
         }
     }
     if (any_nan) return RSRR_ENAN;
