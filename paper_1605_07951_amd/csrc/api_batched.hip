@@ -279,17 +279,26 @@ extern "C" rsrr_status rsrr_sample_batched(rsrr_ctx* c, int count, const rsrr_in
     for (int i = 0; i < count; ++i) buckets[(inst[i].nep.n + BUCKET - 1) / BUCKET * BUCKET].push_back(i);
 
     int any_sing = 0, any_fb = 0, any_nan = 0;
-    // Replayed buckets (their own buffers) run side by side on a pool of streams and
-    // report after all of them; eager buckets share buffers and report one by one.
-    struct Pending { std::vector<int> ids; std::vector<long> off; long M; int* info; int* iters; double* resid; };
+    // Every bucket has its own buffers; the buckets run side by side on a pool of
+    // streams (replayed graphs or eager launches) and report after all of them.  The
+    // host tables of eager launches stay alive in `pending` until then.
+    struct Pending {
+        std::vector<int> ids; std::vector<long> off; long M; int* info; int* iters; double* resid;
+        std::vector<double2> coef; std::vector<int> nk;
+    };
     std::vector<Pending> pending;
-    if (use_graph && !S.streams[0]) {
+    if (!S.streams[0]) {
         for (int i = 0; i < N_BUCKET_STREAMS; ++i) {
             RSRR_HIP(hipStreamCreateWithFlags(&S.streams[i], hipStreamNonBlocking));
             RSRR_HIP(hipEventCreateWithFlags(&S.done[i], hipEventDisableTiming));
         }
     }
     int nlaunched = 0;
+    // on every return the launched buckets have finished before `pending` (host tables) goes away
+    struct Drain {
+        BatchedState& S; const int& n;
+        ~Drain() { for (int i = 0; i < std::min(n, N_BUCKET_STREAMS); ++i) (void)hipStreamSynchronize(S.streams[i]); }
+    } drain{S, nlaunched};
     // diagnostics of one bucket back to the host; points above the residual bar are redone in FP64
     auto report = [&](const std::vector<int>& ids, const std::vector<long>& off, long M, const int* dinfo,
                       const int* diters, const double* dres) -> rsrr_status {
@@ -371,7 +380,7 @@ extern "C" rsrr_status rsrr_sample_batched(rsrr_ctx* c, int count, const rsrr_in
         hipStream_t sm = c->stream;
         // with graphs every bucket size has its own buffers (the graphs keep pointing at
         // them); otherwise the buckets of a call run one after the other and share them
-        int s = use_graph ? (P / BUCKET) * 32 : 0;
+        int s = (P / BUCKET) * 32;
         b.T = bget(S, s++, (size_t)M * b.sT * esz, sm);
         b.T128 = (double2*)bget(S, s++, (size_t)M * b.sT * 16, sm);
         b.Ub = (double2*)bget(S, s++, (size_t)M * b.sU * 16, sm);
@@ -487,17 +496,17 @@ extern "C" rsrr_status rsrr_sample_batched(rsrr_ctx* c, int count, const rsrr_in
             RSRR_HIP(hipStreamWaitEvent(ps, c->fork, 0));
             RSRR_HIP(hipGraphLaunch(slot->exec, ps));
             ++nlaunched;
-            pending.push_back(Pending{ids, off, M, b.info, b.iters, b.resid});
-            continue;
+            pending.push_back(Pending{ids, off, M, b.info, b.iters, b.resid, {}, {}});
         } else {
-            rsrr_status st = run_bucket(c, c->stream, inst, ids, off, P, Lmax, M, prec, nb, b, coef.data(), nk.data(),
+            hipStream_t ps = S.streams[nlaunched % N_BUCKET_STREAMS];
+            RSRR_HIP(hipEventRecord(c->fork, c->stream));
+            RSRR_HIP(hipStreamWaitEvent(ps, c->fork, 0));
+            pending.push_back(Pending{ids, off, M, b.info, b.iters, b.resid, std::move(coef), std::move(nk)});
+            Pending& pd = pending.back();
+            rsrr_status st = run_bucket(c, ps, inst, ids, off, P, Lmax, M, prec, nb, b, pd.coef.data(), pd.nk.data(),
                                         maxit);
             if (st) return st;
-        }
-
-        {
-            const rsrr_status st = report(ids, off, M, b.info, b.iters, b.resid);
-            if (st) return st;
+            ++nlaunched;
         }
     }
     if (!pending.empty()) {
