@@ -184,7 +184,11 @@ typedef struct {
  * nref reference points (host, 2*nref doubles): r = ref[k] (host, N ints in
  * [0, nref)), or the nearest reference when ref is NULL; each used reference
  * is factored once.  The operator T(z_k), the Krylov vectors and the
- * residuals are FP64.  A column stops when its FP64 relative residual
+ * residuals are FP64.  For a HELMHOLTZ nep the operator uses the points'
+ * assembled FP64 matrices (16 n^2 bytes per point of a chunk), or, with flags
+ * RSRR_GMRES_MATRIX_FREE or when they would take more than half of the
+ * workspace budget, generates the entries inside every application
+ * (matrix-free; flags is otherwise 0).  A column stops when its FP64 relative residual
  * ||u - T(z_k) x||_2 / ||u||_2 is at most tol (0 < tol < 1), measured on the
  * true residual at the end of each restart cycle of at most `restart` steps
  * (1..64), or after max_iters steps.  z, U, S, lds and ldu are as for
@@ -198,11 +202,13 @@ typedef struct {
  * reference matrix had an exact zero / non-finite pivot (nothing solved).
  * Errors: -2 nep invalid (n > 8192), -3 N < 1, -4 z NULL, -5 nref < 1,
  * -6 zref NULL, -7 a ref[k] out of range, -8 U NULL, -9 L < 1, -10 ldu < n,
- * -11 tol, -12 restart, -13 max_iters < 1, -14 S NULL, -15 lds < n. */
+ * -11 tol, -12 restart, -13 max_iters < 1, -14 flags, -15 S NULL, -16 lds < n. */
+enum { RSRR_GMRES_MATRIX_FREE = 1 };
 RSRR_API rsrr_status rsrr_sample_gmres(rsrr_ctx *ctx, const rsrr_nep *nep, int N, const double *z,
                                        int nref, const double *zref, const int *ref,
                                        const double *U, int L, int ldu, double tol, int restart,
-                                       int max_iters, double *S, int lds, rsrr_gmres_info *info);
+                                       int max_iters, int flags, double *S, int lds,
+                                       rsrr_gmres_info *info);
 
 /* Basis (RSRR Step 3, Sec. 4.2-4.3).  S (device, n x NL, lds) is normalised
  * in place to unit column norms, then its singular values sigma (host,

@@ -69,7 +69,8 @@ struct GmChunk {
     double2 *part, *h, *Hc, *Rm, *g, *sn, *y, *coef;
     double *cs, *hn, *thr, *inv, *g0;
     int *done, *act, *kc, *steps, *ndone, *pidx;
-    double2* T;                    // HELMHOLTZ: per-point FP64 matrices
+    double2* T;                    // HELMHOLTZ: per-point FP64 matrices (null: generated on the fly)
+    double2* zc;                   // HELMHOLTZ: the chunk's points (device)
     void* tmp;                     // getrs scratch
 };
 
@@ -101,6 +102,9 @@ static rsrr_status gm_apply(rsrr_ctx* c, const rsrr_nep* nep, int L, int ld, lon
             RSRR_HIP(zgemm(c->stream, 0, 0, n, k.C, r1, 1.0, A + (size_t)S1 * k.Kso * nep->lda, nep->lda, 0,
                            k.Y + (size_t)S1 * k.Kso, k.ldy, 0, 0.0, k.P + (size_t)S1 * sP, ld, 0, 1));
         RSRR_HIP(gm_sum_c128(c->stream, n, k.C, k.P, ld, sP, S1 + (r1 > 0), W, ld));
+    } else if (!k.T) {
+        RSRR_HIP(helm_apply(c->stream, n, L, nep->points, nep->w, k.zc, Zin, ld, (long)ld * L, W, ld, (long)ld * L,
+                            k.B));
     } else if (resid_skinny_ok(L)) {
         RSRR_HIP(resid_skinny(c->stream, n, L, k.T, ld, sT, Zin, ld, (long)ld * L, nullptr, 0, 0, W, ld, (long)ld * L,
                               nullptr, k.B));
@@ -113,7 +117,7 @@ static rsrr_status gm_apply(rsrr_ctx* c, const rsrr_nep* nep, int L, int ld, lon
 
 extern "C" rsrr_status rsrr_sample_gmres(rsrr_ctx* c, const rsrr_nep* nep, int N, const double* z, int nref,
                                          const double* zref, const int* ref, const double* Up, int L, int ldu,
-                                         double tol, int restart, int max_iters, double* Sp, int lds,
+                                         double tol, int restart, int max_iters, int flags, double* Sp, int lds,
                                          rsrr_gmres_info* info)
 {
     if (!c) return -1;
@@ -138,8 +142,9 @@ extern "C" rsrr_status rsrr_sample_gmres(rsrr_ctx* c, const rsrr_nep* nep, int N
     if (!(tol > 0.0 && tol < 1.0)) return -11;
     if (restart < 1 || restart > gm_max_restart()) return -12;
     if (max_iters < 1) return -13;
-    if (!Sp) return -14;
-    if (lds < nep->n) return -15;
+    if (flags & ~RSRR_GMRES_MATRIX_FREE) return -14;
+    if (!Sp) return -15;
+    if (lds < nep->n) return -16;
     RSRR_HIP(hipSetDevice(c->device));
     EvPair all;
     RSRR_HIP(hipEventRecord(all.a, c->stream));
@@ -259,14 +264,19 @@ extern "C" rsrr_status rsrr_sample_gmres(rsrr_ctx* c, const rsrr_nep* nep, int N
                            ((size_t)ns * (M + 1) * 16 + (size_t)(M + 1) * 16 * 3 + (size_t)M * M * 16 +
                             (size_t)M * 40 + 64) + (size_t)nb * 8 +
                            (size_t)(nep->kind == RSRR_T_SEPARABLE ? nep->J * n : 0) * 16 + (size_t)16 * ld * 24;
-    const size_t per_pt = (nep->kind == RSRR_T_HELMHOLTZ ? (size_t)sT * 16 + (((size_t)n * n + 255) / 256) * 8 : 0) +
-                          (size_t)nb * n * 8 + (size_t)std::max(nep->J, 1) * 16 + 64;
     size_t budget = c->ws_budget;
     if (!budget) {
         size_t fr = 0, tot = 0;
         RSRR_HIP(hipMemGetInfo(&fr, &tot));
         budget = fr / 2;
     }
+    // Helmholtz operator: the points' FP64 matrices are assembled once per chunk, unless asked
+    // not to or unless they would take more than half of the budget (then entries are generated
+    // inside every application)
+    const bool helm = nep->kind == RSRR_T_HELMHOLTZ;
+    const bool mfree = helm && ((flags & RSRR_GMRES_MATRIX_FREE) || (size_t)N * sT * 16 > budget / 2);
+    const size_t per_pt = (helm && !mfree ? (size_t)sT * 16 + (((size_t)n * n + 255) / 256) * 8 : 0) +
+                          (size_t)nb * n * 8 + (size_t)std::max(nep->J, 1) * 16 + 64;
     int Bmax = (int)std::min<size_t>((size_t)N, std::max<size_t>(1, budget / (per_col * L + per_pt)));
     Bmax = std::max(1, std::min(Bmax, 65535));  // points per chunk ride on a grid dimension
 
@@ -324,7 +334,8 @@ extern "C" rsrr_status rsrr_sample_gmres(rsrr_ctx* c, const rsrr_nep* nep, int N
         const size_t sbytes = a256((size_t)ns * (M + 1) * C * 16) + a256((size_t)(M + 1) * C * 16) * 3 +
                               a256((size_t)M * M * C * 16) + a256((size_t)M * C * 16) * 2 + a256((size_t)M * C * 8) +
                               a256((size_t)C * 8) * 4 + a256((size_t)C * 4) * 4 + a256(64) +
-                              a256((size_t)k.B * 4) + a256((size_t)std::max(nep->J, 1) * k.B * 16);
+                              a256((size_t)k.B * 4) + a256((size_t)std::max(nep->J, 1) * k.B * 16) +
+                              a256((size_t)k.B * 16);
         Carve sc{(char*)ws_get(c, WS_GMS, sbytes)};
         if (!sc.base) return RSRR_ENOMEM;
         k.part = sc.take<double2>((size_t)ns * (M + 1) * C);
@@ -346,6 +357,7 @@ extern "C" rsrr_status rsrr_sample_gmres(rsrr_ctx* c, const rsrr_nep* nep, int N
         k.ndone = sc.take<int>(16);
         k.pidx = sc.take<int>(k.B);
         k.coef = sc.take<double2>((size_t)std::max(nep->J, 1) * k.B);
+        k.zc = sc.take<double2>(k.B);
         k.T = nullptr;
 
         std::vector<int> hp(k.B);
@@ -362,6 +374,11 @@ extern "C" rsrr_status rsrr_sample_gmres(rsrr_ctx* c, const rsrr_nep* nep, int N
                         cf[(size_t)j * k.B + b] = make_double2(v.real(), v.imag());
                     }
                 RSRR_HIP(hipMemcpyAsync(k.coef, cf.data(), cf.size() * 16, hipMemcpyHostToDevice, c->stream));
+                RSRR_HIP(hipStreamSynchronize(c->stream));
+            } else if (mfree) {
+                std::vector<double2> zz(k.B);
+                for (int b = 0; b < k.B; ++b) zz[b] = make_double2(zp[hp[b]].real(), zp[hp[b]].imag());
+                RSRR_HIP(hipMemcpyAsync(k.zc, zz.data(), (size_t)k.B * 16, hipMemcpyHostToDevice, c->stream));
                 RSRR_HIP(hipStreamSynchronize(c->stream));
             } else {
                 k.T = (double2*)ws_get(c, WS_GMT, (size_t)k.B * sT * 16);

@@ -308,6 +308,85 @@ __global__ __launch_bounds__(GM_NT) void gm_sum_c128_kernel(int n, int C, const 
     W[i + (long)c * ldw] = acc;
 }
 
+// W_b = T(z_b) Z_b for the Helmholtz single-layer matrix without storing it:
+// the entries are generated in FP64 as they are consumed (the same expressions
+// as the assembly kernel), Z_b (n x L, L <= LC) staged through LDS in chunks
+// of KC rows.  Grid: row tiles of RW x points.
+template <int LC, int RW>
+__global__ __launch_bounds__(RW) void helm_apply_kernel(int n, int L, const double* __restrict__ pts, double w,
+                                                         const double2* __restrict__ z,
+                                                         const double2* __restrict__ Z, int ldz, long sZ,
+                                                         double2* __restrict__ W, int ldw, long sW)
+{
+    constexpr int KC = 64;
+    __shared__ double2 zs[KC][LC];
+    __shared__ double pc[KC][3];
+    const int b = blockIdx.y;
+    const int row = blockIdx.x * RW + threadIdx.x;
+    const double2 zb = z[b];
+    const double inv4pi = 0.25 / M_PI;
+    const double diag_re = 0.5 * sqrt(w / M_PI);
+    const double2* Zb = Z + b * sZ;
+    double xi = 0.0, yi = 0.0, zi = 0.0;
+    if (row < n) { xi = pts[3 * row]; yi = pts[3 * row + 1]; zi = pts[3 * row + 2]; }
+    double2 acc[LC];
+#pragma unroll
+    for (int c = 0; c < LC; ++c) acc[c] = make_double2(0.0, 0.0);
+    for (int k0 = 0; k0 < n; k0 += KC) {
+        for (int e = threadIdx.x; e < KC * LC; e += RW) {
+            const int kk = e % KC, c = e / KC;
+            zs[kk][c] = (k0 + kk < n && c < L) ? Zb[(k0 + kk) + (long)c * ldz] : make_double2(0.0, 0.0);
+        }
+        for (int e = threadIdx.x; e < KC * 3; e += RW) {
+            const int kk = e / 3, d = e % 3;
+            pc[kk][d] = k0 + kk < n ? pts[3 * (k0 + kk) + d] : 0.0;
+        }
+        __syncthreads();
+        if (row < n) {
+            const int kend = min(KC, n - k0);
+            for (int kk = 0; kk < kend; ++kk) {
+                const int j = k0 + kk;
+                double2 t;
+                if (j != row) {
+                    const double dx = xi - pc[kk][0], dy = yi - pc[kk][1], dz = zi - pc[kk][2];
+                    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+                    const double scale = w * inv4pi / r;
+                    double s, co;
+                    sincos(zb.x * r, &s, &co);
+                    const double m = scale * exp(-zb.y * r);
+                    t = make_double2(m * co, m * s);
+                } else {
+                    t = make_double2(diag_re - zb.y * w * inv4pi, zb.x * w * inv4pi);
+                }
+#pragma unroll
+                for (int c = 0; c < LC; ++c) acc[c] = cfma(acc[c], t, zs[kk][c]);
+            }
+        }
+        __syncthreads();
+    }
+    if (row >= n) return;
+    double2* Wb = W + b * sW;
+#pragma unroll
+    for (int c = 0; c < LC; ++c)
+        if (c < L) Wb[row + (long)c * ldw] = acc[c];
+}
+
+hipError_t helm_apply(hipStream_t st, int n, int L, const double* pts, double w, const double2* z, const double2* Z,
+                      int ldz, long sZ, double2* W, int ldw, long sW, int B)
+{
+    for (int c0 = 0; c0 < L; c0 += 16) {
+        const int Lc = L - c0 < 16 ? L - c0 : 16;
+        const double2* Zc = Z + (long)c0 * ldz;
+        double2* Wc = W + (long)c0 * ldw;
+#define HA_L(LC)                                                                                                   \
+    hipLaunchKernelGGL((helm_apply_kernel<LC, 256>), dim3((unsigned)((n + 255) / 256), (unsigned)B), dim3(256), 0, \
+                       st, n, Lc, pts, w, z, Zc, ldz, sZ, Wc, ldw, sW)
+        if (Lc <= 2) HA_L(2); else if (Lc <= 4) HA_L(4); else if (Lc <= 8) HA_L(8); else HA_L(16);
+#undef HA_L
+    }
+    return hipGetLastError();
+}
+
 // B identity matrices n x n (complex FP32, leading dimension ld, stride sA).
 __global__ __launch_bounds__(GM_NT) void gm_eye_c64_kernel(int n, float2* __restrict__ A, int ld, long sA)
 {

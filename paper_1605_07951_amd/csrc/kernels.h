@@ -171,6 +171,10 @@ hipError_t gm_combine(hipStream_t st, int n, int C, int k, const double2* Z, int
                       double2* X, int ldx);
 hipError_t gm_g0(hipStream_t st, int C, const double* g0, double2* g);
 hipError_t gm_eye_c64(hipStream_t st, int n, float2* A, int ld, long sA, int B);
+// W_b = T(z_b) Z_b for the Helmholtz single-layer matrix of the points, entries generated in FP64
+// on the fly (matrix-free); any L (columns in groups of 16).
+hipError_t helm_apply(hipStream_t st, int n, int L, const double* pts, double w, const double2* z, const double2* Z,
+                      int ldz, long sZ, double2* W, int ldw, long sW, int B);
 // Sums of the S slices of a split contraction (slice s at P + s*sP): Z = (c128) sum P_s, W = sum P_s.
 hipError_t gm_sum_widen(hipStream_t st, int n, int C, const float2* P, int ldp, long sP, int S, double2* Z, int ldz);
 hipError_t gm_sum_c128(hipStream_t st, int n, int C, const double2* P, int ldp, long sP, int S, double2* W, int ldw);

@@ -132,7 +132,7 @@ def lib():
     L.rsrr_sample.argtypes = [vp, C.POINTER(RsrrNep), C.c_int, dp, vp, C.c_int, C.c_int, C.c_int, vp, C.c_int,
                               C.POINTER(RsrrPointInfo)]
     L.rsrr_sample_gmres.argtypes = [vp, C.POINTER(RsrrNep), C.c_int, dp, C.c_int, dp, ip, vp, C.c_int, C.c_int,
-                                    C.c_double, C.c_int, C.c_int, vp, C.c_int, C.POINTER(RsrrGmresInfo)]
+                                    C.c_double, C.c_int, C.c_int, C.c_int, vp, C.c_int, C.POINTER(RsrrGmresInfo)]
     L.rsrr_sample_batched.argtypes = [vp, C.c_int, C.POINTER(RsrrInstance), C.c_int, C.c_int,
                                       C.POINTER(RsrrPointInfo)]
     L.rsrr_basis.argtypes = [vp, C.c_int, C.c_int, vp, C.c_int, C.c_double, vp, C.c_int, C.c_int, ip, dp]
@@ -320,7 +320,11 @@ def rsrr_sample(ctx, dnep, z, U, prec=RSRR_PREC_C64_IR, S=None, ok=(RSRR_OK, RSR
     return S, infos, code
 
 
-def rsrr_sample_gmres(ctx, dnep, z, U, zref, ref=None, tol=1e-10, restart=32, max_iters=300, S=None, ok=(RSRR_OK,)):
+RSRR_GMRES_MATRIX_FREE = 1
+
+
+def rsrr_sample_gmres(ctx, dnep, z, U, zref, ref=None, tol=1e-10, restart=32, max_iters=300, flags=0, S=None,
+                      ok=(RSRR_OK,)):
     """S = [T(z_k)^-1 U]_k by flexible GMRES preconditioned with complex FP32 LU factors of T at the
     reference points zref (point k uses ref[k], or the nearest reference when ref is None).
 
@@ -343,7 +347,7 @@ def rsrr_sample_gmres(ctx, dnep, z, U, zref, ref=None, tol=1e-10, restart=32, ma
     lds = S.shape[1]
     info = (RsrrGmresInfo * N)()
     code = lib().rsrr_sample_gmres(ctx.h, C.byref(dnep.desc), N, zp, rc.size, rp, rarr, U.data_ptr(), L, ldu,
-                                   float(tol), int(restart), int(max_iters), S.data_ptr(), lds, info)
+                                   float(tol), int(restart), int(max_iters), int(flags), S.data_ptr(), lds, info)
     _check("rsrr_sample_gmres", code, ok)
     infos = [{"iters": i.iters, "restarts": i.restarts, "converged": i.converged, "ref": i.ref, "resid": i.resid}
              for i in info]

@@ -62,7 +62,7 @@ def test_argument_errors_without_device(lib):
     assert lib.rsrr_basis(None, 1, 1, None, 1, 1e-14, None, 1, 1, C.byref(k), None) == -1
     assert lib.rsrr_last_timings(None, None) == -1
     assert lib.rsrr_update_stats(None, 0, 0, None) == -1
-    assert lib.rsrr_sample_gmres(None, None, 1, None, 1, None, None, None, 1, 1, 1e-10, 8, 10, None, 1, None) == -1
+    assert lib.rsrr_sample_gmres(None, None, 1, None, 1, None, None, None, 1, 1, 1e-10, 8, 10, 0, None, 1, None) == -1
     assert b"gfx950" in lib.rsrr_version()
 
 

@@ -60,12 +60,12 @@ def _check(R, nep, z, U, S_dev, infos, tol, kappa=True):
     return worst
 
 
-def _run(R, ctx, nep, z, U, zref, ref=None, tol=1e-10, restart=32, max_iters=300, ok=None):
+def _run(R, ctx, nep, z, U, zref, ref=None, tol=1e-10, restart=32, max_iters=300, ok=None, flags=0):
     dn = R.DeviceNEP(nep)
     Ud, _ = R.colmajor(U)
     kw = {} if ok is None else {"ok": ok}
     S, infos, code = R.rsrr_sample_gmres(ctx, dn, z, Ud, zref, ref=ref, tol=tol, restart=restart,
-                                         max_iters=max_iters, **kw)
+                                         max_iters=max_iters, flags=flags, **kw)
     torch.cuda.synchronize()
     return S, infos, code
 
@@ -135,6 +135,21 @@ def test_gmres_split_products_with_ragged_slices(R, ctx):
     _check(R, nep, z, U, S, infos, 1e-10)
 
 
+@pytest.mark.parametrize("L", [2, 5, 20])
+def test_gmres_helmholtz_matrix_free_operator(R, ctx, L):
+    """Entries generated inside every application (no stored matrices): the same bars, and the
+    iterate agrees with the one from the assembled matrices (same entry formula, same order)."""
+    nep, C, U = W.cfg_helmholtz(n=320, N=6, L=L, seed=2800)
+    z, _ = R.rsrr_contour(C.gamma, C.a, C.b, C.N)
+    S, infos, code = _run(R, ctx, nep, z, U, [C.gamma], flags=R.RSRR_GMRES_MATRIX_FREE)
+    assert code == R.RSRR_OK
+    _check(R, nep, z, U, S, infos, 1e-10)
+    S2, infos2, _ = _run(R, ctx, nep, z, U, [C.gamma])
+    a, b = R.from_colmajor(S, 320), R.from_colmajor(S2, 320)
+    assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(b)
+    assert all(abs(x["iters"] - y["iters"]) <= 1 for x, y in zip(infos, infos2))
+
+
 def test_gmres_short_restart_cycles(R, ctx):
     nep, C, U = W.cfg_helmholtz(n=384, N=6, L=2, seed=2200)
     z, _ = R.rsrr_contour(C.gamma, C.a, C.b, C.N)
@@ -198,16 +213,16 @@ def test_gmres_argument_errors(R, ctx):
     zp = z.view(np.float64).ctypes.data_as(C_.POINTER(C_.c_double))
     rp = zr.view(np.float64).ctypes.data_as(C_.POINTER(C_.c_double))
     f = R.lib().rsrr_sample_gmres
-    good = dict(N=2, nref=1, ref=None, L=1, ldu=64, tol=1e-10, restart=8, it=50, lds=64)
+    good = dict(N=2, nref=1, ref=None, L=1, ldu=64, tol=1e-10, restart=8, it=50, flags=0, lds=64)
 
     def call(**kw):
         a = dict(good, **kw)
         return f(ctx.h, C_.byref(dn.desc), a["N"], kw.get("zp", zp), a["nref"], kw.get("rp", rp), a["ref"],
-                 kw.get("U", Ud.data_ptr()), a["L"], a["ldu"], a["tol"], a["restart"], a["it"],
+                 kw.get("U", Ud.data_ptr()), a["L"], a["ldu"], a["tol"], a["restart"], a["it"], a["flags"],
                  kw.get("S", S.data_ptr()), a["lds"], None)
 
     nullp = C_.cast(None, C_.POINTER(C_.c_double))
-    assert f(None, None, 1, None, 1, None, None, None, 1, 1, 1e-10, 8, 10, None, 1, None) == -1
+    assert f(None, None, 1, None, 1, None, None, None, 1, 1, 1e-10, 8, 10, 0, None, 1, None) == -1
     assert call(N=0) == -3
     assert call(zp=nullp) == -4
     assert call(nref=0) == -5
@@ -221,9 +236,11 @@ def test_gmres_argument_errors(R, ctx):
     assert call(restart=0) == -12
     assert call(restart=65) == -12
     assert call(it=0) == -13
-    assert call(S=None) == -14
-    assert call(lds=63) == -15
+    assert call(flags=2) == -14
+    assert call(S=None) == -15
+    assert call(lds=63) == -16
     assert call() == R.RSRR_OK
+    assert call(flags=R.RSRR_GMRES_MATRIX_FREE) == R.RSRR_OK
 
 
 def test_gmres_chunked_by_memory_budget(R):
