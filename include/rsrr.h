@@ -173,6 +173,8 @@ typedef struct {
     int converged;     /* 1 when every column met tol                               */
     int ref;           /* the reference point whose factors preconditioned it      */
     double resid;      /* max over columns of ||u_c - T(z_k) x_c||_2 / ||u_c||_2, FP64 */
+    int matrix_free;   /* 1 when the operator generated its entries (HELMHOLTZ)     */
+    int pad;
 } rsrr_gmres_info;
 
 /* Resolvent sampling with an iterative solver (RSRR Step 2, eq. hatS; Sec. 4.3

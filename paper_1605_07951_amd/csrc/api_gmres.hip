@@ -569,6 +569,8 @@ extern "C" rsrr_status rsrr_sample_gmres(rsrr_ctx* c, const rsrr_nep* nep, int N
             info[p].converged = pconv[p];
             info[p].ref = rk[p];
             info[p].resid = pres[p];
+            info[p].matrix_free = mfree ? 1 : 0;
+            info[p].pad = 0;
         }
     return any_nconv ? RSRR_ENOTCONV : RSRR_OK;
 }

@@ -60,7 +60,7 @@ class RsrrNep(C.Structure):
 
 class RsrrGmresInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("converged", C.c_int), ("ref", C.c_int),
-                ("resid", C.c_double)]
+                ("resid", C.c_double), ("matrix_free", C.c_int), ("pad", C.c_int)]
 
 
 class RsrrInstance(C.Structure):
@@ -349,8 +349,8 @@ def rsrr_sample_gmres(ctx, dnep, z, U, zref, ref=None, tol=1e-10, restart=32, ma
     code = lib().rsrr_sample_gmres(ctx.h, C.byref(dnep.desc), N, zp, rc.size, rp, rarr, U.data_ptr(), L, ldu,
                                    float(tol), int(restart), int(max_iters), int(flags), S.data_ptr(), lds, info)
     _check("rsrr_sample_gmres", code, ok)
-    infos = [{"iters": i.iters, "restarts": i.restarts, "converged": i.converged, "ref": i.ref, "resid": i.resid}
-             for i in info]
+    infos = [{"iters": i.iters, "restarts": i.restarts, "converged": i.converged, "ref": i.ref, "resid": i.resid,
+              "matrix_free": i.matrix_free} for i in info]
     return S, infos, code
 
 

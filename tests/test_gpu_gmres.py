@@ -143,8 +143,10 @@ def test_gmres_helmholtz_matrix_free_operator(R, ctx, L):
     z, _ = R.rsrr_contour(C.gamma, C.a, C.b, C.N)
     S, infos, code = _run(R, ctx, nep, z, U, [C.gamma], flags=R.RSRR_GMRES_MATRIX_FREE)
     assert code == R.RSRR_OK
+    assert all(i["matrix_free"] == 1 for i in infos)
     _check(R, nep, z, U, S, infos, 1e-10)
     S2, infos2, _ = _run(R, ctx, nep, z, U, [C.gamma])
+    assert all(i["matrix_free"] == 0 for i in infos2)
     a, b = R.from_colmajor(S, 320), R.from_colmajor(S2, 320)
     assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(b)
     assert all(abs(x["iters"] - y["iters"]) <= 1 for x, y in zip(infos, infos2))
