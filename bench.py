@@ -619,7 +619,7 @@ def run_gmres(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU only (the sharding across GPUs is a design, not code); run with --gpus 1",
                           "n_gpus_requested": args.gpus}))
         sys.exit(2)
     if args.workload == "serve":
