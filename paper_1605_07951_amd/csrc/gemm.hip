@@ -20,9 +20,10 @@ namespace rsrr {
 // ----------------------------------------------------------------------------
 // complex FP32: v_mfma_f32_32x32x2f32.  The workgroup has WR x WC waves; each
 // wave owns BR x BC blocks of 32x32 outputs, so the WG tile is
-// (32 WR BR) x (32 WC BC).  Shapes: 128x128 (2x2 waves of 2x2 blocks) for the
-// trailing update, 128x64 and 128x32 for the narrow products of the panel
-// recursion and the solves.  beta*C is loaded into the accumulators before
+// (32 WR BR) x (32 WC BC).  In this 4M form it serves the 128x32 products of
+// the panel recursion; wider products go to the 3M kernel below.  The 4M
+// kernel is kept general (a 128x128 tile of 2x2 waves of 2x2 blocks runs at
+// two waves per SIMD).  beta*C is loaded into the accumulators before
 // the k loop (its latency overlaps the first LDS stage), alpha is folded
 // into the A operand, and the epilogue only stores.
 // ----------------------------------------------------------------------------
@@ -196,7 +197,187 @@ __global__ __launch_bounds__(CG_NT, 2) void cgemm_mfma_kernel(
     }
 }
 
-template <int WR, int WC, int BR, int BC>
+// ----------------------------------------------------------------------------
+// complex FP32, "3M" form (Gauss's three-product trick): with A = Ar + i Ai and
+// B = Br + i Bi, the three real products T1 = Ar Br, T2 = Ai Bi and
+// T3 = (Ar + Ai)(Br + Bi) give Re AB = T1 - T2 and Im AB = T3 - T1 - T2: 3
+// real multiplies per complex multiply-add instead of 4.  Here the MFMA's
+// inner index of 2 runs over two consecutive complex k (lanes 0-31: k, lanes
+// 32-63: k + 1), so one stage of CG_KT complex k takes 3 * CG_KT / 2 MFMAs per
+// 32x32 block against 2 * CG_KT for the 4M kernel.  Staging, tile order and
+// output layout are those of the 4M kernel; the sums Ar + Ai and Br + Bi are
+// formed in registers from the staged values.  beta C enters the
+// accumulators as T1 = beta Re C, T2 = 0, T3 = beta (Re C + Im C).  The error
+// is bounded normwise like that of the 4M form with a slightly larger
+// constant (Higham, "Stability of a method for multiplying complex matrices
+// with three real matrix multiplications", SIMAX 1992), which the FP64
+// refinement downstream absorbs.  Three accumulator sets per block: with
+// 2x2 blocks per wave that is one wave per SIMD, with two blocks two.  The
+// workgroup has 64 WR WC threads.
+// ----------------------------------------------------------------------------
+template <int WR, int WC, int BR, int BC, bool VEC, int TAG>
+__global__ __launch_bounds__(64 * WR * WC, (BR * BC <= 2) ? 512 / (64 * WR * WC) : 1) void cgemm3m_mfma_kernel(
+    int M, int N, int K, float alpha,
+    const float2* __restrict__ A, int lda, long sA,
+    const float2* __restrict__ B, int ldb, long sB,
+    float beta, float2* __restrict__ C, int ldc, long sC,
+    int tilesM, int tilesN, int batch, long total_padded)
+{
+    constexpr int NT = 64 * WR * WC;
+    constexpr int BM = 32 * WR * BR, BN = 32 * WC * BC;
+    constexpr int AQ = BM * CG_KT / 2 / NT;
+    constexpr int BQ = BN * CG_KT / 2 / NT;
+    static_assert(AQ >= 1 && BQ >= 1, "tile too small for the loader");
+    static_assert(CG_KT % 2 == 0, "stages hold pairs of k");
+    __shared__ __attribute__((aligned(16))) float As[2][CG_KT][2 * BM];
+    __shared__ __attribute__((aligned(16))) float2 Bs[2][CG_KT][BN + 4];
+
+    const long tile = xcd_remap(blockIdx.x, total_padded);
+    const long per = (long)tilesM * tilesN;
+    const long b = tile / per;
+    if (b >= batch) return;
+    const int t = (int)(tile - b * per);
+    int ti, tj;
+    tile_order(t, tilesM, tilesN, &ti, &tj);
+    const int i0 = ti * BM;
+    const int j0 = tj * BN;
+    const float2* Ab = A + b * sA;
+    const float2* Bb = B + b * sB;
+    float2* Cb = C + b * sC;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wi = wave % WR, wj = wave / WR;
+    const int li = lane & 31, half = lane >> 5;
+    const int wrow = i0 + wi * BR * 32, wcol = j0 + wj * BC * 32;
+
+    floatx16 t1[BR][BC], t2[BR][BC], t3[BR][BC];
+#pragma unroll
+    for (int x = 0; x < BR; ++x)
+#pragma unroll
+        for (int y = 0; y < BC; ++y) {
+            const int i = wrow + x * 32 + li;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int j = wcol + y * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                float2 c = make_float2(0.f, 0.f);
+                if (beta != 0.f && i < M && j < N) c = Cb[i + (long)j * ldc];
+                t1[x][y][r] = beta * c.x;
+                t2[x][y][r] = 0.f;
+                t3[x][y][r] = beta * (c.x + c.y);
+            }
+        }
+
+    floatx4 ra[AQ], rb[BQ];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < AQ; ++q) {
+            const int p = tid + NT * q;
+            const int k = p / (BM / 2), ip = (p % (BM / 2)) * 2;
+            const int gi = i0 + ip, gk = k0 + k;
+            floatx4 v = {0.f, 0.f, 0.f, 0.f};
+            if (gk < K) {
+                const float2* src = Ab + gi + (long)gk * lda;
+                if (VEC && gi + 1 < M) {
+                    v = *reinterpret_cast<const floatx4*>(src);
+                } else {
+                    if (gi < M) { float2 e = src[0]; v[0] = e.x; v[1] = e.y; }
+                    if (gi + 1 < M) { float2 e = src[1]; v[2] = e.x; v[3] = e.y; }
+                }
+            }
+            ra[q] = v;
+        }
+#pragma unroll
+        for (int q = 0; q < BQ; ++q) {
+            const int p = tid + NT * q;
+            const int j = p / (CG_KT / 2), kp = (p % (CG_KT / 2)) * 2;
+            const int gj = j0 + j, gk = k0 + kp;
+            floatx4 v = {0.f, 0.f, 0.f, 0.f};
+            if (gj < N) {
+                const float2* src = Bb + gk + (long)gj * ldb;
+                if (VEC && gk + 1 < K) {
+                    v = *reinterpret_cast<const floatx4*>(src);
+                } else {
+                    if (gk < K) { float2 e = src[0]; v[0] = e.x; v[1] = e.y; }
+                    if (gk + 1 < K) { float2 e = src[1]; v[2] = e.x; v[3] = e.y; }
+                }
+            }
+            rb[q] = v;
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < AQ; ++q) {
+            const int p = tid + NT * q;
+            const int k = p / (BM / 2), ip = (p % (BM / 2)) * 2;
+            *reinterpret_cast<floatx4*>(&As[buf][k][2 * ip]) = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < BQ; ++q) {
+            const int p = tid + NT * q;
+            const int j = p / (CG_KT / 2), kp = (p % (CG_KT / 2)) * 2;
+            Bs[buf][kp][j] = make_float2(rb[q][0], rb[q][1]);
+            Bs[buf][kp + 1][j] = make_float2(rb[q][2], rb[q][3]);
+        }
+    };
+
+    const int nst = (K + CG_KT - 1) / CG_KT;
+    if (nst > 0) {
+        gload(0);
+        sstore(0);
+        __syncthreads();
+    }
+    for (int s = 0; s < nst; ++s) {
+        const int buf = s & 1;
+        if (s + 1 < nst) gload((s + 1) * CG_KT);
+#pragma unroll 2
+        for (int kk = 0; kk < CG_KT; kk += 2) {
+            const int k = kk + half;
+            float ar[BR], ai[BR], as[BR], br[BC], bi[BC], bs[BC];
+#pragma unroll
+            for (int x = 0; x < BR; ++x) {
+                const float2 av = *reinterpret_cast<const float2*>(&As[buf][k][2 * (wi * BR * 32 + x * 32 + li)]);
+                ar[x] = alpha * av.x;
+                ai[x] = alpha * av.y;
+                as[x] = alpha * (av.x + av.y);
+            }
+#pragma unroll
+            for (int y = 0; y < BC; ++y) {
+                const float2 bv = Bs[buf][k][wj * BC * 32 + y * 32 + li];
+                br[y] = bv.x;
+                bi[y] = bv.y;
+                bs[y] = bv.x + bv.y;
+            }
+#pragma unroll
+            for (int x = 0; x < BR; ++x)
+#pragma unroll
+                for (int y = 0; y < BC; ++y) {
+                    t1[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(br[y], ar[x], t1[x][y], 0, 0, 0);
+                    t2[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(bi[y], ai[x], t2[x][y], 0, 0, 0);
+                    t3[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(bs[y], as[x], t3[x][y], 0, 0, 0);
+                }
+        }
+        if (s + 1 < nst) sstore(buf ^ 1);
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int x = 0; x < BR; ++x) {
+        const int i = wrow + x * 32 + li;
+        if (i >= M) continue;
+#pragma unroll
+        for (int y = 0; y < BC; ++y)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int j = wcol + y * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                if (j < N)
+                    Cb[i + (long)j * ldc] =
+                        make_float2(t1[x][y][r] - t2[x][y][r], t3[x][y][r] - t1[x][y][r] - t2[x][y][r]);
+            }
+    }
+}
+
+template <int WR, int WC, int BR, int BC, bool M3 = false>
 static void cgemm_launch(hipStream_t st, int M, int N, int K, float alpha, const float2* A, int lda, long sA,
                          const float2* B, int ldb, long sB, float beta, float2* C, int ldc, long sC, int batch,
                          int tag, bool vec)
@@ -205,8 +386,15 @@ static void cgemm_launch(hipStream_t st, int M, int N, int K, float alpha, const
     const int tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
     const long total = round_up_l((long)tm * tn * batch, 8);
 #define CG_L(V, T)                                                                                                    \
-    hipLaunchKernelGGL((cgemm_mfma_kernel<WR, WC, BR, BC, V, T>), dim3((unsigned)total), dim3(CG_NT), 0, st, M, N, K, \
-                       alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, tm, tn, batch, total)
+    do {                                                                                                              \
+        if constexpr (M3)                                                                                             \
+            hipLaunchKernelGGL((cgemm3m_mfma_kernel<WR, WC, BR, BC, V, T>), dim3((unsigned)total), dim3(64 * WR * WC), \
+                               0, st,                                                                                 \
+                               M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, tm, tn, batch, total);       \
+        else                                                                                                          \
+            hipLaunchKernelGGL((cgemm_mfma_kernel<WR, WC, BR, BC, V, T>), dim3((unsigned)total), dim3(CG_NT), 0, st,   \
+                               M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, tm, tn, batch, total);       \
+    } while (0)
     if (vec) {
         if (tag == 1) CG_L(true, 1); else CG_L(true, 0);
     } else {
@@ -222,12 +410,15 @@ hipError_t cgemm(hipStream_t st, int M, int N, int K, float alpha,
     if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
     const bool vec = ((((uintptr_t)A) | ((uintptr_t)B)) & 15) == 0 && (lda % 2 == 0) && (ldb % 2 == 0)
                      && (sA % 2 == 0) && (sB % 2 == 0);
+    // 128x32 tiles in the 4M form for the narrow products of the panel
+    // recursion; 128x64 tiles in the 3M form for everything wider (trailing
+    // updates, U12 products, solves): with two 32x32 blocks per wave the three
+    // accumulator sets still leave two waves per SIMD, which measured faster
+    // than 128x128 tiles in either form.
     if (N <= 32)
         cgemm_launch<4, 1, 1, 1>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tag, vec);
-    else if (N <= 64)
-        cgemm_launch<4, 1, 1, 2>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tag, vec);
     else
-        cgemm_launch<2, 2, 2, 2>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tag, vec);
+        cgemm_launch<4, 1, 1, 2, true>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tag, vec);
     return hipGetLastError();
 }
 

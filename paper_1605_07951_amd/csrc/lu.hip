@@ -770,7 +770,11 @@ static hipError_t getrs_impl(hipStream_t st, const C* LU, long sLU, int lda, int
             (void)gemm_sub<C>(st, rest, nrhs, jb, LU + (c0 + jb) + (long)c0 * lda, lda, sLU, X + c0, ldx, sX,
                               X + c0 + jb, ldx, sX, batch);
     }
-    for (int p = np - 1; p >= 0; --p) {
+    // Backward sweep with U11.  Panels are taken in pairs (p, p-1): after both
+    // diagonal solves (the second preceded by the small coupling product with
+    // U[p-1, p]) the rows above are updated once with depth jb(p-1) + jb(p);
+    // the columns of U above a pair are contiguous, so no copy is needed.
+    auto diag_solve = [&](int p) {
         const int c0 = p * nb, jb = (n - c0 < nb) ? n - c0 : nb;
         if (use_inv) {
             perm_rows<C>(st, nullptr, 0, X, sX, ldx, (C*)w.tmp, w.sTmp, nb, c0, jb, nrhs, w.active, batch);
@@ -779,8 +783,22 @@ static hipError_t getrs_impl(hipStream_t st, const C* LU, long sLU, int lda, int
         } else {
             perm_trsm<C>(st, LU, sLU, lda, nullptr, 0, X, sX, ldx, c0, jb, nrhs, 2, w.active, batch);
         }
-        if (c0 > 0)
-            (void)gemm_sub<C>(st, c0, nrhs, jb, LU + (long)c0 * lda, lda, sLU, X + c0, ldx, sX, X, ldx, sX, batch);
+    };
+    for (int p = np - 1; p >= 0;) {
+        const int c0 = p * nb, jb = (n - c0 < nb) ? n - c0 : nb;
+        diag_solve(p);
+        if (p >= 1) {
+            const int c1 = c0 - nb;  // panel p-1 is a full panel of width nb
+            (void)gemm_sub<C>(st, nb, nrhs, jb, LU + c1 + (long)c0 * lda, lda, sLU, X + c0, ldx, sX, X + c1, ldx, sX,
+                              batch);
+            diag_solve(p - 1);
+            if (c1 > 0)
+                (void)gemm_sub<C>(st, c1, nrhs, nb + jb, LU + (long)c1 * lda, lda, sLU, X + c1, ldx, sX, X, ldx, sX,
+                                  batch);
+            p -= 2;
+        } else {
+            p -= 1;
+        }
     }
     return hipGetLastError();
 }
