@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "resolvent solves/sec (n=4096, L=64) & % MFMA peak; p50/p99 NEP latency"
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_FP64_MFMA_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
 
 
 def parse():
@@ -90,20 +91,71 @@ def build_workload(args):
     return nep, C, U, desc
 
 
-def measured_traffic():
-    """HBM bytes per trailing-update launch from the committed rocprofv3 counter summary, or
-    None when the kernel or the LU driver has changed since the counters were taken."""
+def _profile_figure(name, key, conv):
+    """A figure from a committed rocprofv3 counter summary under profiles/, or None when the
+    kernel or the LU driver has changed since the counters were taken (hash of both files)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_trailing_update_helmholtz_n4096_N64_L64_mixed.md")
+    path = os.path.join(ROOT, "profiles", name)
     srcs = [os.path.join(ROOT, "paper_1605_07951_amd", "csrc", f) for f in ("gemm.hip", "lu.hip")]
     try:
         txt = open(path).read()
-        val = int(txt.split("traffic_bytes_per_launch:")[1].split()[0])
+        val = conv(txt.split(key + ":")[1].split()[0])
         sha = txt.split("source_sha256_16 (csrc/gemm.hip + csrc/lu.hip):")[1].split()[0]
         h = hashlib.sha256(b"".join(open(s, "rb").read() for s in srcs)).hexdigest()[:16]
     except (OSError, IndexError, ValueError):
         return None
     return val if h == sha else None
+
+
+def measured_traffic():
+    """HBM bytes per trailing-update launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)."""
+    return _profile_figure("traffic_trailing_update_helmholtz_n4096_N64_L64_mixed.md",
+                           "traffic_bytes_per_launch", int)
+
+
+def measured_mfma_util():
+    """rocprofv3's MfmaUtil of the trailing update (mean over one step's launches)."""
+    return _profile_figure("mfma_util_trailing_update_helmholtz_n4096_N64_L64_mixed.md",
+                           "rocprof_mfma_util_update", float)
+
+
+def phase_rooflines(n, N, L, tm, iters):
+    """Achieved rates of the sampling phases other than the LU, from the last step's phase times.
+
+    Work per step (all N points are processed by every launch of a pass, converged points
+    included): the Helmholtz assembly writes a c64 copy of T for the LU and a c128 copy for the
+    residual (24 n^2 bytes per point; the entries are generated, nothing n^2-sized is read);
+    the solve and the FP64 residual each run once before refinement and once per correction
+    (iters + 1 passes).  A solve pass reads the c64 factors (8 n^2 bytes) and does 8 n^2 L
+    flops (standard complex count) per point; a residual pass reads T in c128 (16 n^2 bytes)
+    and does 8 n^2 L FP64 flops per point.  With L = 64 both passes sit above the ridge of
+    their matrix peak (8 L flops per 8-byte factor entry against 157.3 / 8 = 19.7; 8 L per
+    16-byte entry against 78.6 / 8 = 9.8), so their flop rate is the one that bounds them."""
+    n2 = float(n) * n
+    passes = iters + 1
+    out = {}
+    a_ms = tm.get("assemble_ms", 0.0)
+    if a_ms > 0:
+        b = N * 24.0 * n2
+        out["assembly"] = {"ms": round(a_ms, 3), "bytes": b, "GB_s": round(b / (a_ms * 1e-3) / 1e9, 1),
+                           "hbm_frac": round(b / (a_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+    s_ms = tm.get("solve_ms", 0.0)
+    if s_ms > 0:
+        f = passes * N * 8.0 * n2 * L
+        b = passes * N * 8.0 * n2
+        out["solves"] = {"ms": round(s_ms, 3), "passes": passes, "flops": f, "bytes": b,
+                         "TFLOP_s": round(f / (s_ms * 1e-3) / 1e12, 2),
+                         "fp32_mfma_frac": round(f / (s_ms * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS, 4),
+                         "GB_s": round(b / (s_ms * 1e-3) / 1e9, 1)}
+    r_ms = tm.get("residual_ms", 0.0)
+    if r_ms > 0:
+        f = passes * N * 8.0 * n2 * L
+        b = passes * N * 16.0 * n2
+        out["residual"] = {"ms": round(r_ms, 3), "passes": passes, "flops": f, "bytes": b,
+                           "TFLOP_s": round(f / (r_ms * 1e-3) / 1e12, 2),
+                           "fp64_mfma_frac": round(f / (r_ms * 1e-3) / 1e12 / PEAK_FP64_MFMA_TFLOPS, 4),
+                           "GB_s": round(b / (r_ms * 1e-3) / 1e9, 1)}
+    return out
 
 
 def cpu_baseline(nep, C, U, npts):
@@ -714,14 +766,19 @@ def main():
                      "flops_per_launch": st["flops"] / max(1, st["launches"]),
                      **({"form": "3M: three real MFMA products per complex multiply-add; achieved counts the "
                                  "standard 8 real flops per complex multiply-add, the matrix cores execute 6",
-                         "mfma_executed_frac": round(0.75 * achieved / peak, 4)}
+                         "mfma_executed_frac": round(0.75 * achieved / peak, 4),
+                         "rocprof_mfma_util": (measured_mfma_util() if (args.workload == "helmholtz" and n == 4096
+                                                                        and N == 64 and L == 64) else None)}
                         if prec == R.RSRR_PREC_C64_IR else {})},
         "sample_solves_per_s": round(N * args.steps / (sample_ms * 1e-3), 3) if sample_ms > 0 else None,
+        "rhs_columns_per_s": round(L * value, 1),
         "phase_ms_last_step": {k: round(v, 3) for k, v in tm.items()},
         "ir_iters_max": max(i["ir_iters"] for i in info),
         "resid_max": max(i["resid"] for i in info),
         "fallbacks": sum(i["fallback"] for i in info),
     }
+    if prec == R.RSRR_PREC_C64_IR and args.workload == "helmholtz":
+        res["phase_rooflines"] = phase_rooflines(n, N, L, tm, res["ir_iters_max"])
     if not args.sample_only:
         # the rest of the method on the sampled S: basis, projection, SS-FULL (timed once, reported)
         torch.cuda.synchronize()
