@@ -269,12 +269,16 @@ __global__ __launch_bounds__(EW_NT) void ir_decide_kernel(int M, int Lmax, const
 
 // R_b = U_b - T_b X_b in FP64 for at most RS_LC right-hand sides: the product is
 // skinny, so it is a stream over T (HBM bound) rather than an MFMA GEMM.  One
-// workgroup per 256 rows of one matrix; a chunk of 64 rows of X is staged in LDS
-// and read by broadcast; each thread keeps its row's L sums in registers and
-// walks k in order (deterministic).  Matrices with active[b] == 0 are skipped.
-// RW rows (= threads) per workgroup: 64 for small matrices, so that there are
-// enough workgroups, 256 otherwise.
-template <int LC, int RW>
+// workgroup per RW * RPT rows of one matrix; a chunk of 64 rows of X is staged
+// in LDS and read by broadcast; each thread keeps the L sums of its RPT rows
+// (rows threadIdx.x + r RW, so every load of T stays coalesced) in registers
+// and walks k in order (deterministic).  With RPT rows per thread one
+// broadcast read of X(k, c) serves RPT loads of T: at L = 8 and above the
+// broadcast reads would otherwise use as much LDS bandwidth as the stream
+// over T uses HBM.  Matrices with active[b] == 0 are skipped.  RW rows
+// (= threads) per workgroup: 64 for small matrices, so that there are enough
+// workgroups, 256 otherwise.
+template <int LC, int RW, int RPT>
 __global__ __launch_bounds__(RW) void resid_skinny_kernel(int n, int L, const double2* __restrict__ T, int ldt,
                                                             long sT, const double2* __restrict__ X, int ldx, long sX,
                                                             const double2* __restrict__ U, int ldu, long sU,
@@ -285,45 +289,59 @@ __global__ __launch_bounds__(RW) void resid_skinny_kernel(int n, int L, const do
     __shared__ double2 xs[KC][LC];
     const int b = blockIdx.y;
     if (active && !active[b]) return;
-    const int row = blockIdx.x * RW + threadIdx.x;
+    const int row0 = blockIdx.x * RW * RPT + threadIdx.x;
     const double2* Tb = T + b * sT;
     const double2* Xb = X + b * sX;
-    double2 acc[LC];
+    bool ok[RPT];
 #pragma unroll
-    for (int c = 0; c < LC; ++c) acc[c] = make_double2(0.0, 0.0);
+    for (int r = 0; r < RPT; ++r) ok[r] = row0 + r * RW < n;
+    double2 acc[RPT][LC];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r)
+#pragma unroll
+        for (int c = 0; c < LC; ++c) acc[r][c] = make_double2(0.0, 0.0);
     for (int k0 = 0; k0 < n; k0 += KC) {
         for (int e = threadIdx.x; e < KC * LC; e += RW) {
             const int kk = e % KC, c = e / KC;
             xs[kk][c] = (k0 + kk < n && c < L) ? Xb[(k0 + kk) + (long)c * ldx] : make_double2(0.0, 0.0);
         }
         __syncthreads();
-        if (row < n) {
+        if (ok[0]) {
             const int kend = min(KC, n - k0);
-            const double2* tp = Tb + row + (long)k0 * ldt;
-#pragma unroll 8
+            const double2* tp = Tb + row0 + (long)k0 * ldt;
+#pragma unroll 2
             for (int kk = 0; kk < kend; ++kk) {
-                const double2 t = tp[(long)kk * ldt];
+                double2 t[RPT];
 #pragma unroll
-                for (int c = 0; c < LC; ++c) acc[c] = cfma(acc[c], t, xs[kk][c]);
+                for (int r = 0; r < RPT; ++r)
+                    t[r] = ok[r] ? tp[r * RW + (long)kk * ldt] : make_double2(0.0, 0.0);
+#pragma unroll
+                for (int c = 0; c < LC; ++c) {
+                    const double2 x = xs[kk][c];
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) acc[r][c] = cfma(acc[r][c], t[r], x);
+                }
             }
         }
         __syncthreads();
     }
-    if (row >= n) return;
     double2* Rb = R + b * sR;
-    if (!U) {  // R = T X
+    const double2* Ub = U ? U + b * sU : nullptr;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        if (!ok[r]) continue;
+        const int row = row0 + r * RW;
 #pragma unroll
         for (int c = 0; c < LC; ++c)
-            if (c < L) Rb[row + (long)c * ldr] = acc[c];
-        return;
+            if (c < L) {
+                if (!Ub) {  // R = T X
+                    Rb[row + (long)c * ldr] = acc[r][c];
+                } else {
+                    const double2 u = Ub[row + (long)c * ldu];
+                    Rb[row + (long)c * ldr] = make_double2(u.x - acc[r][c].x, u.y - acc[r][c].y);
+                }
+            }
     }
-    const double2* Ub = U + b * sU;
-#pragma unroll
-    for (int c = 0; c < LC; ++c)
-        if (c < L) {
-            const double2 u = Ub[row + (long)c * ldu];
-            Rb[row + (long)c * ldr] = make_double2(u.x - acc[c].x, u.y - acc[c].y);
-        }
 }
 
 static dim3 ew_grid(long elems, int B) { return dim3((unsigned)((elems + EW_NT - 1) / EW_NT), B); }
@@ -414,9 +432,13 @@ hipError_t resid_skinny(hipStream_t st, int n, int L, const double2* T, int ldt,
                         long sX, const double2* U, int ldu, long sU, double2* R, int ldr, long sR, const int* active,
                         int B)
 {
-#define RS_L(LC, RW)                                                                                                 \
-    hipLaunchKernelGGL((resid_skinny_kernel<LC, RW>), dim3((unsigned)((n + RW - 1) / RW), (unsigned)B), dim3(RW), 0, \
-                       st, n, L, T, ldt, sT, X, ldx, sX, U, ldu, sU, R, ldr, sR, active)
+#define RS_L(LC, RW)                                                                                             \
+    do {                                                                                                         \
+        constexpr int RPT = (LC >= 8) ? 2 : 1;                                                                   \
+        hipLaunchKernelGGL((resid_skinny_kernel<LC, RW, RPT>), dim3((unsigned)((n + RW * RPT - 1) / (RW * RPT)), \
+                                                                    (unsigned)B),                               \
+                           dim3(RW), 0, st, n, L, T, ldt, sT, X, ldx, sX, U, ldu, sU, R, ldr, sR, active);      \
+    } while (0)
     const bool small = n <= 1024;
     if (L <= 2) {
         if (small) RS_L(2, 64); else RS_L(2, 256);
