@@ -377,6 +377,149 @@ __global__ __launch_bounds__(64 * WR * WC, (BR * BC <= 2) ? 512 / (64 * WR * WC)
     }
 }
 
+// ----------------------------------------------------------------------------
+// complex FP32 with at most 16 output columns (the solves of narrow probe
+// blocks and the lowest levels of the panel recursion): v_mfma_f32_16x16x4f32,
+// whose inner index of 4 covers two complex k in the 4M split k' = 2k + c
+// (lane group g = lane / 16: complex k = k0 + g / 2, part c = g % 2).  A
+// 32-wide instruction would leave three quarters of its columns empty at
+// N = 8; this one leaves at most half.  With the operands swapped as in the
+// kernels above, lane l and register r of a 16x16 block hold row l % 16 and
+// column 4 (l / 16) + r.  Four waves of BR 16x16 blocks stacked in rows: the
+// workgroup tile is (64 BR) x 16.
+// ----------------------------------------------------------------------------
+template <int BR, bool VEC, int TAG>
+__global__ __launch_bounds__(CG_NT) void cgemm_narrow_kernel(
+    int M, int N, int K, float alpha,
+    const float2* __restrict__ A, int lda, long sA,
+    const float2* __restrict__ B, int ldb, long sB,
+    float beta, float2* __restrict__ C, int ldc, long sC,
+    int tilesM, int batch, long total_padded)
+{
+    constexpr int BM = 64 * BR, BN = 16;
+    constexpr int AQ = BM * CG_KT / 2 / CG_NT;   // float4 (2 complex) A loads per thread per stage
+    constexpr int BLD = BN * CG_KT / 2;          // float4 B loads per stage (fewer than the threads)
+    static_assert(AQ >= 1 && AQ * 2 * CG_NT == BM * CG_KT, "A tile must split evenly over the threads");
+    static_assert(BLD <= CG_NT, "one B load per thread at most");
+    __shared__ __attribute__((aligned(16))) float As[2][CG_KT][2 * BM];
+    __shared__ __attribute__((aligned(16))) float2 Bs[2][CG_KT][BN + 4];
+
+    const long tile = xcd_remap(blockIdx.x, total_padded);
+    const long b = tile / tilesM;
+    if (b >= batch) return;
+    const int i0 = (int)(tile - b * tilesM) * BM;
+    const float2* Ab = A + b * sA;
+    const float2* Bb = B + b * sB;
+    float2* Cb = C + b * sC;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, g = lane >> 4;
+    const int kc = g >> 1, part = g & 1;
+    const int wrow = i0 + wave * BR * 16;
+
+    floatx4 accR[BR], accI[BR];
+#pragma unroll
+    for (int x = 0; x < BR; ++x) {
+        const int i = wrow + x * 16 + li;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = 4 * g + r;
+            float2 c = make_float2(0.f, 0.f);
+            if (beta != 0.f && i < M && j < N) c = Cb[i + (long)j * ldc];
+            accR[x][r] = beta * c.x;
+            accI[x][r] = beta * c.y;
+        }
+    }
+
+    floatx4 ra[AQ], rb;
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < AQ; ++q) {
+            const int p = tid + CG_NT * q;
+            const int k = p / (BM / 2), ip = (p % (BM / 2)) * 2;
+            const int gi = i0 + ip, gk = k0 + k;
+            floatx4 v = {0.f, 0.f, 0.f, 0.f};
+            if (gk < K) {
+                const float2* src = Ab + gi + (long)gk * lda;
+                if (VEC && gi + 1 < M) {
+                    v = *reinterpret_cast<const floatx4*>(src);
+                } else {
+                    if (gi < M) { float2 e = src[0]; v[0] = e.x; v[1] = e.y; }
+                    if (gi + 1 < M) { float2 e = src[1]; v[2] = e.x; v[3] = e.y; }
+                }
+            }
+            ra[q] = v;
+        }
+        rb = floatx4{0.f, 0.f, 0.f, 0.f};
+        if (tid < BLD) {
+            const int j = tid / (CG_KT / 2), kp = (tid % (CG_KT / 2)) * 2;
+            const int gk = k0 + kp;
+            if (j < N) {
+                const float2* src = Bb + gk + (long)j * ldb;
+                if (VEC && gk + 1 < K) {
+                    rb = *reinterpret_cast<const floatx4*>(src);
+                } else {
+                    if (gk < K) { float2 e = src[0]; rb[0] = e.x; rb[1] = e.y; }
+                    if (gk + 1 < K) { float2 e = src[1]; rb[2] = e.x; rb[3] = e.y; }
+                }
+            }
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < AQ; ++q) {
+            const int p = tid + CG_NT * q;
+            const int k = p / (BM / 2), ip = (p % (BM / 2)) * 2;
+            *reinterpret_cast<floatx4*>(&As[buf][k][2 * ip]) = ra[q];
+        }
+        if (tid < BLD) {
+            const int j = tid / (CG_KT / 2), kp = (tid % (CG_KT / 2)) * 2;
+            Bs[buf][kp][j] = make_float2(rb[0], rb[1]);
+            Bs[buf][kp + 1][j] = make_float2(rb[2], rb[3]);
+        }
+    };
+
+    const int nst = (K + CG_KT - 1) / CG_KT;
+    if (nst > 0) {
+        gload(0);
+        sstore(0);
+        __syncthreads();
+    }
+    for (int s = 0; s < nst; ++s) {
+        const int buf = s & 1;
+        if (s + 1 < nst) gload((s + 1) * CG_KT);
+#pragma unroll 4
+        for (int kk = 0; kk < CG_KT; kk += 2) {
+            const int k = kk + kc;
+            float a[BR];
+#pragma unroll
+            for (int x = 0; x < BR; ++x) a[x] = alpha * As[buf][k][2 * (wave * BR * 16 + x * 16 + li) + part];
+            const float2 bv = Bs[buf][k][li];
+            const float br = part ? -bv.y : bv.x;
+            const float bi = part ? bv.x : bv.y;
+#pragma unroll
+            for (int x = 0; x < BR; ++x) {
+                accR[x] = __builtin_amdgcn_mfma_f32_16x16x4f32(br, a[x], accR[x], 0, 0, 0);
+                accI[x] = __builtin_amdgcn_mfma_f32_16x16x4f32(bi, a[x], accI[x], 0, 0, 0);
+            }
+        }
+        if (s + 1 < nst) sstore(buf ^ 1);
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int x = 0; x < BR; ++x) {
+        const int i = wrow + x * 16 + li;
+        if (i >= M) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = 4 * g + r;
+            if (j < N) Cb[i + (long)j * ldc] = make_float2(accR[x][r], accI[x][r]);
+        }
+    }
+}
+
 template <int WR, int WC, int BR, int BC, bool M3 = false>
 static void cgemm_launch(hipStream_t st, int M, int N, int K, float alpha, const float2* A, int lda, long sA,
                          const float2* B, int ldb, long sB, float beta, float2* C, int ldc, long sC, int batch,
@@ -410,12 +553,26 @@ hipError_t cgemm(hipStream_t st, int M, int N, int K, float alpha,
     if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
     const bool vec = ((((uintptr_t)A) | ((uintptr_t)B)) & 15) == 0 && (lda % 2 == 0) && (ldb % 2 == 0)
                      && (sA % 2 == 0) && (sB % 2 == 0);
-    // 128x32 tiles in the 4M form for the narrow products of the panel
-    // recursion; 128x64 tiles in the 3M form for everything wider (trailing
+    // 128x16 tiles of 16x16 blocks for at most 16 columns, 128x32 tiles in the
+    // 4M form up to 32 columns (the narrow products of the panel recursion and
+    // of narrow probe blocks); 128x64 tiles in the 3M form for everything wider (trailing
     // updates, U12 products, solves): with two 32x32 blocks per wave the three
     // accumulator sets still leave two waves per SIMD, which measured faster
     // than 128x128 tiles in either form.
-    if (N <= 32)
+    if (N <= 16) {
+        constexpr int BR = 2, BM = 64 * BR;
+        const int tm = (M + BM - 1) / BM;
+        const long total = round_up_l((long)tm * batch, 8);
+#define CN_L(V, T)                                                                                                 \
+    hipLaunchKernelGGL((cgemm_narrow_kernel<BR, V, T>), dim3((unsigned)total), dim3(CG_NT), 0, st, M, N, K, alpha, \
+                       A, lda, sA, B, ldb, sB, beta, C, ldc, sC, tm, batch, total)
+        if (vec) {
+            if (tag == 1) CN_L(true, 1); else CN_L(true, 0);
+        } else {
+            if (tag == 1) CN_L(false, 1); else CN_L(false, 0);
+        }
+#undef CN_L
+    } else if (N <= 32)
         cgemm_launch<4, 1, 1, 1>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tag, vec);
     else
         cgemm_launch<4, 1, 1, 2, true>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tag, vec);

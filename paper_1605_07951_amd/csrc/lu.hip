@@ -519,8 +519,9 @@ __global__ __launch_bounds__(TI_NT) void tri_inv_kernel(const C* __restrict__ LU
     const int nbk = (jb + TI_B - 1) / TI_B;
     const C* A = LU + (long)b * sLU + c0 + (long)c0 * ldl;   // the diagonal block, A(r, c) = A[r + c*ldl]
     C* X = (C*)inv + (long)b * sInv + (long)(2 * (c0 / nb) + which) * nb * nb;
-    __shared__ C D[TI_MAXB][TI_B][TI_B + 1];   // inverted diagonal blocks (slot = block row)
-    __shared__ C Xc[TI_MAXB][TI_B][TI_B + 1];  // block column j of the inverse
+    // D[i]: inverted diagonal block i until block i of column j of the inverse is
+    // known, then that block (its last use as a diagonal inverse is in computing it)
+    __shared__ C D[TI_MAXB][TI_B][TI_B + 1];
     __shared__ C Tt[TI_B][TI_B + 1];           // an off-diagonal block of the triangle
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     auto entry = [&](int r, int c) -> C {        // padded triangle entry (r, c < nbk * 32)
@@ -563,12 +564,7 @@ __global__ __launch_bounds__(TI_NT) void tri_inv_kernel(const C* __restrict__ LU
         for (int r = 0; r < TI_B; ++r) D[i1][r][col] = x[r];
     }
     __syncthreads();
-    // 2. block column j
-    for (int e = tid; e < TI_B * TI_B; e += TI_NT) {
-        const int r = e % TI_B, c = e / TI_B;
-        Xc[j][r][c] = D[j][r][c];
-    }
-    __syncthreads();
+    // 2. block column j: X_jj = D[j] already; X_ij replaces D[i] in order of i
     const int steps = which == 0 ? nbk - 1 - j : j;
     for (int s = 1; s <= steps; ++s) {
         const int i = which == 0 ? j + s : j - s;
@@ -588,12 +584,13 @@ __global__ __launch_bounds__(TI_NT) void tri_inv_kernel(const C* __restrict__ LU
                 const int e = tid + TI_NT * q;
                 const int r = e % TI_B, c = e / TI_B;
                 C a = acc[q];
-                for (int l = 0; l < TI_B; ++l) a = cfma(a, Tt[r][l], Xc[k][l][c]);
+                for (int l = 0; l < TI_B; ++l) a = cfma(a, Tt[r][l], D[k][l][c]);
                 acc[q] = a;
             }
             __syncthreads();
         }
-        // Xc[i] = -D[i] acc  (acc staged through Tt)
+        // X_ij = -D[i] acc (acc staged through Tt), computed in registers, then
+        // written over D[i] once every thread has read it
 #pragma unroll
         for (int q = 0; q < TI_B * TI_B / TI_NT; ++q) {
             const int e = tid + TI_NT * q;
@@ -606,7 +603,13 @@ __global__ __launch_bounds__(TI_NT) void tri_inv_kernel(const C* __restrict__ LU
             const int r = e % TI_B, c = e / TI_B;
             C a = czero<C>();
             for (int l = 0; l < TI_B; ++l) a = cfms(a, D[i][r][l], Tt[l][c]);
-            Xc[i][r][c] = a;
+            acc[q] = a;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < TI_B * TI_B / TI_NT; ++q) {
+            const int e = tid + TI_NT * q;
+            D[i][e % TI_B][e / TI_B] = acc[q];
         }
         __syncthreads();
     }
@@ -616,7 +619,7 @@ __global__ __launch_bounds__(TI_NT) void tri_inv_kernel(const C* __restrict__ LU
         const int gc = j * TI_B + c, i = rr / TI_B, r = rr % TI_B;
         if (rr >= jb || gc >= jb) continue;
         const bool in = which == 0 ? i >= j : i <= j;
-        X[rr + (long)gc * nb] = in ? Xc[i][r][c] : czero<C>();
+        X[rr + (long)gc * nb] = in ? D[i][r][c] : czero<C>();
     }
 }
 
