@@ -275,7 +275,8 @@ __global__ __launch_bounds__(EW_NT) void ir_decide_kernel(int M, int Lmax, const
 // and walks k in order (deterministic).  With RPT rows per thread one
 // broadcast read of X(k, c) serves RPT loads of T: at L = 8 and above the
 // broadcast reads would otherwise use as much LDS bandwidth as the stream
-// over T uses HBM.  Matrices with active[b] == 0 are skipped.  RW rows
+// over T uses HBM.  At L <= 2 (the GMRES operator) four rows per thread keep
+// more loads of T in flight.  Matrices with active[b] == 0 are skipped.  RW rows
 // (= threads) per workgroup: 64 for small matrices, so that there are enough
 // workgroups, 256 otherwise.
 template <int LC, int RW, int RPT>
@@ -434,7 +435,7 @@ hipError_t resid_skinny(hipStream_t st, int n, int L, const double2* T, int ldt,
 {
 #define RS_L(LC, RW)                                                                                             \
     do {                                                                                                         \
-        constexpr int RPT = (LC >= 8) ? 2 : 1;                                                                   \
+        constexpr int RPT = (LC >= 8) ? 2 : (LC <= 2 ? 4 : 1);                                                                  \
         hipLaunchKernelGGL((resid_skinny_kernel<LC, RW, RPT>), dim3((unsigned)((n + RW * RPT - 1) / (RW * RPT)), \
                                                                     (unsigned)B),                               \
                            dim3(RW), 0, st, n, L, T, ldt, sT, X, ldx, sX, U, ldu, sU, R, ldr, sR, active);      \
