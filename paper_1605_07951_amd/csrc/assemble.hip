@@ -19,7 +19,7 @@
 namespace rsrr {
 
 constexpr int AS_NT = 256;
-constexpr int AS_PG = 8;      // points per thread pass
+constexpr int AS_PG = 24;     // points per thread pass
 constexpr int AS_MAXJ = 64;   // separable terms held in LDS
 
 // element e of a column-major n x n matrix: (e % n, e / n)
