@@ -13,7 +13,7 @@
  *   rsrr_solve    Step 4, second half, and Step 5: SS-FULL (Sec. 3.3) on the
  *                 projected NEP, lift v = Q g, residuals
  *   rsrr_moments  the moment matrix M = S Z of the moment scheme (Sec. 4.1)
- *   rsrr_two_stage        the two-stage strategy of Sec. 5.2-5.3: stage-1
+ *   rsrr_two_stage        the two-stage strategy of Sec. 5.4 and Sec. 6: stage-1
  *                 eigenvalue estimates become extra sampling points
  *   rsrr_sample_batched   Step 2 for a ragged batch of NEP instances
  *   rsrr_sample_gmres     Step 2 with an iterative solver: flexible GMRES,
@@ -312,7 +312,7 @@ RSRR_API rsrr_status rsrr_sample_batched(rsrr_ctx *ctx, int count, const rsrr_in
  * block i of S (columns i L .. i L + L - 1), zeta_i = (z_i - gamma)/rho and
  * omega_i = 1 / prod_{j != i} ((zeta_i - zeta_j)/C) are the barycentric
  * weights (eq. bary-wt) with every factor divided by the capacity C
- * (Sec. 3.4; for an ellipse of semi-axes a, b and rho = max(a, b):
+ * (Sec. 3.3, item 3; for an ellipse of semi-axes a, b and rho = max(a, b):
  * C = (a + b) / (2 rho)).  Block alpha of M is columns alpha L .. alpha L + L - 1.
  * S: device, n x N L, lds; z: host, 2N doubles (the points of S's blocks);
  * gamma: host, 2 doubles; M: device, n x K L, ldm (caller-owned).  The moment
@@ -330,7 +330,7 @@ typedef struct {
     double resid1_max;       /* largest stage-1 eigen-residual inside C                   */
 } rsrr_two_stage_info;
 
-/* Two-stage sampling (Sec. 5.2, Example 2; Sec. 5.3).  Stage 1: RSRR (Steps
+/* Two-stage sampling (Sec. 5.4, Example 2; Sec. 6, Example 3).  Stage 1: RSRR (Steps
  * 2-5) with N1 points on the ellipse (gamma, a, b).  The distinct stage-1
  * eigenvalue estimates inside the ellipse (elliptic level < 1; estimates within
  * 1e-6 max(1, |lambda|) of an earlier one are dropped; at most max_new) become

@@ -28,7 +28,7 @@ Steps and the passages they follow
 * ``rsrr``             the five steps of Sec. 4.3 chained together.
 * ``barycentric_weights``, ``chebyshev_points``, ``chebyshev_weights``
                        eq. bary-wt (with each factor divided by a capacity C, the
-                       scaling Sec. 3.4 suggests against under- and overflow),
+                       scaling Sec. 3.3 suggests against under- and overflow),
                        eq. Chebyshev-pts and eq. Chebyshev-wts.
 * ``moments``          the resolvent moment scheme, Sec. 4.1: M_alpha =
                        sum_i omega_i zeta_i^alpha T(z_i)^-1 U (eq. Malpha) for
@@ -36,8 +36,8 @@ Steps and the passages they follow
                        i.e. M = S Z (eq. MS).
 * ``rsrr_moment``      SS-RR with M in place of S (the variant Sec. 4.3 describes
                        in its closing remark).
-* ``two_stage``        the two-stage strategy of Sec. 5.2 (Example 2) and
-                       Sec. 5.3: RSRR on a few contour points, then the
+* ``two_stage``        the two-stage strategy of Sec. 5.4 (Example 2, the gun
+                       cavity) and Sec. 6 (Example 3): RSRR on a few contour points, then the
                        distinct eigenvalue estimates inside the contour become
                        extra sampling points; the first-stage columns of S are
                        kept and RSRR runs again on all of them.
@@ -332,18 +332,6 @@ def residual(prob, lam, v):
     return float(np.linalg.norm(T @ v) / (np.linalg.norm(T, 1) * np.linalg.norm(v)))
 
 
-def solve_residuals(prob, z, U, S):
-    """Per point, per column ||u - T(z_k) x||_2 / ||u||_2 for the blocks of S."""
-    L = U.shape[1]
-    out = np.zeros((len(z), L))
-    un = np.linalg.norm(U, axis=0)
-    for k, zk in enumerate(z):
-        X = S[:, k * L:(k + 1) * L]
-        R = U - prob.T(zk) @ X
-        out[k] = np.linalg.norm(R, axis=0) / un
-    return out
-
-
 def rsrr(prob, contour, U, delta=1e-14, NQ=500, KQ=2, tol_gap=1e3, S=None):
     """RSRR (Sec. 4.3): sample, normalise, truncate, project, SS-FULL, lift.
 
@@ -376,7 +364,7 @@ def distinct_inside(lam, gamma, a, b, rel=1e-6):
 
 
 def two_stage(prob, contour, U, delta=1e-14, NQ=500, KQ=2, tol_gap=1e3):
-    """Two-stage RSRR (Sec. 5.2, Example 2; Sec. 5.3): stage 1 on contour.N points,
+    """Two-stage RSRR (Sec. 5.4, Example 2; Sec. 6, Example 3): stage 1 on contour.N points,
     stage 2 with the stage-1 estimates inside the contour appended as sampling points
     (their T(z)^-1 U appended to the stage-1 S, which is reused)."""
     r1 = rsrr(prob, contour, U, delta=delta, NQ=NQ, KQ=KQ, tol_gap=tol_gap)

@@ -1,4 +1,4 @@
-// C ABI: two-stage sampling (Sec. 5.2, Example 2, and Sec. 5.3).
+// C ABI: two-stage sampling (Sec. 5.4, Example 2, and Sec. 6, Example 3).
 //
 // Stage 1 runs RSRR on N1 points of the ellipse.  The distinct eigenvalue
 // estimates inside the contour then become extra sampling points: their

@@ -4,7 +4,7 @@
 // M_alpha = sum_i c_{alpha,i} X_i with X_i the i-th L-column block of S and
 // c_{alpha,i} = omega_i zeta_i^alpha (eq. Malpha), zeta_i = (z_i - gamma)/rho,
 // omega_i the barycentric weights of the zeta_i (eq. bary-wt) with every
-// factor divided by the capacity C (the scaling Sec. 3.4 recommends against
+// factor divided by the capacity C (the scaling Sec. 3.3 recommends against
 // under- and overflow).  For a fixed probe column l the blocks form an
 // n x N matrix (stride L lds between points) and M's columns alpha L + l an
 // n x K matrix, so M is one batched FP64 MFMA GEMM over the L probe columns

@@ -1,4 +1,4 @@
-"""GPU parity of rsrr_two_stage (Sec. 5.2-5.3) against the oracle's two-stage RSRR:
+"""GPU parity of rsrr_two_stage (Sec. 5.4 and Sec. 6) against the oracle's two-stage RSRR:
 the added points equal the oracle's (1e-8 relative), the stage-2 eigenvalues inside
 the contour match the oracle and the closed form within 1e-9, and the eigen-residuals
 match the oracle's (they are set by the stage-2 subspace)."""

@@ -67,6 +67,46 @@ def test_helmholtz_single_layer_of_constant_density():
         assert np.allclose(T, T.T)  # complex symmetric
 
 
+def _self_patch_ratio(T, z, w):
+    """Largest |T_ii - D(z)| over the diagonal in units of |z|^2 a^3 / 12, where
+    D(z) = (e^{i z a} - 1)/(2 i z) is the single-layer integral of e^{i z r}/(4 pi r)
+    over a flat disk of radius a = sqrt(w/pi) about its centre (the self patch of the
+    Nystrom rule), and |z|^2 a^3 / 12 is the size of its first term past second order."""
+    a = math.sqrt(w / math.pi)
+    disk = (np.exp(1j * z * a) - 1.0) / (2j * z)
+    return float(np.max(np.abs(np.diag(T) - disk)) / (abs(z) ** 2 * a ** 3 / 12.0))
+
+
+def test_helmholtz_self_patch_is_the_disk_integral():
+    """The diagonal sqrt(w/pi)/2 + i z w/(4 pi) is the disk integral (e^{iza} - 1)/(2iz) up to
+    its third-order term -z^2 a^3/12: both terms of the diagonal are fixed by it."""
+    for n in (1024, 2048):
+        nep = W.helmholtz_sphere(n)
+        for z in (1.0, 3.8, 2.5 + 0.2j, 4.9 - 0.1j):
+            T = O.T_helmholtz(nep.points[:16], nep.w, z)
+            assert _self_patch_ratio(T, z, nep.w) < 1.25
+
+
+def test_helmholtz_derivative_is_the_difference_quotient():
+    """dT/dz against a central difference of T (step 1e-5): off the diagonal and on it."""
+    nep = W.helmholtz_sphere(300)
+    for z in (3.8, 2.5 + 0.2j):
+        h = 1e-5
+        fd = (O.T_helmholtz(nep.points, nep.w, z + h) - O.T_helmholtz(nep.points, nep.w, z - h)) / (2 * h)
+        D = O.dT_helmholtz(nep.points, nep.w, z)
+        assert np.max(np.abs(fd - D)) <= 1e-8 * np.max(np.abs(D))
+        assert np.max(np.abs(np.diag(fd) - np.diag(D))) <= 1e-8 * np.max(np.abs(np.diag(D)))
+
+
+def test_helmholtz_argument_count_inside_the_headline_ellipse():
+    """Argument principle with T and dT/dz: the ellipse (3.8; 1.4, 0.3) holds 4 eigenvalues of the
+    sphere's single-layer matrix (pi, and the l = 1 triple near 4.493 split by the lattice)."""
+    nep = W.helmholtz_sphere(256)
+    prob = O.Problem(nep)
+    cnt = P.argument_count(prob.T, prob.dT, 3.8, 1.4, 0.3, M=128)
+    assert abs(cnt - 4) < 1e-6
+
+
 # --------------------------------------------------------------- Step 2 ----
 
 def test_sample_matches_high_precision_solve():
@@ -304,6 +344,70 @@ def test_planted_slips_are_caught(monkeypatch):
     assert bad.size == 0 or _match(bad, lam) > 1e-6 or res["warn_gap"]
 
 
+def _moments_closed_form(lam, U, z, gamma, rho, capacity, K):
+    """eq. fa1 for T(z) = diag(z - l_m): with mu = (l - gamma)/rho and l(x) = prod_j (x - zeta_j),
+    sum_i omega_i zeta_i^alpha / (z_i - l_m) = -C^(N-1) mu_m^alpha / (rho l(mu_m)) for alpha <= N-1."""
+    zeta = (np.asarray(z) - gamma) / rho
+    mu = (lam - gamma) / rho
+    node_poly = np.array([np.prod(m - zeta) for m in mu])
+    L = U.shape[1]
+    M = np.zeros((lam.size, K * L), dtype=np.complex128)
+    for a in range(K):
+        f = -capacity ** (zeta.size - 1) * mu ** a / (rho * node_poly)
+        M[:, a * L:(a + 1) * L] = f[:, None] * U
+    return M
+
+
+def _diag_moment_case():
+    lam = np.array([0.2 + 0.1j, -0.5 + 0.3j, 0.9 - 0.2j, 3.0 + 0j, -2.5j, 0.05j, 1.7 + 0.6j])
+    A = [np.diag(-lam).astype(complex), np.eye(lam.size, dtype=complex)]
+    nep = W.SeparableNEP("diag", A, [W.term(1.0, 0), W.term(1.0, 1)])
+    C = W.Contour(0.3 + 0.1j, 1.5, 0.8, 12)
+    U = W.probes(lam.size, 3, 31)
+    z, _ = O.ellipse(C.gamma, C.a, C.b, C.N)
+    S = O.sample(O.Problem(nep), z, U)
+    rho = max(C.a, C.b)
+    return lam, U, z, S, C.gamma, rho, (C.a + C.b) / (2 * rho), C.N
+
+
+def test_moments_match_the_closed_form_of_a_diagonal_nep():
+    """Sec. 4.1, eq. Malpha with the capacity-scaled weights of eq. bary-wt: every moment order
+    alpha = 0..N-1 against the closed form that eq. fa1 gives for T(z) = diag(z - l_m)."""
+    lam, U, z, S, gamma, rho, cap, N = _diag_moment_case()
+    M = O.moments(S, z, U.shape[1], N, gamma, rho, cap)
+    ref = _moments_closed_form(lam, U, z, gamma, rho, cap, N)
+    assert np.linalg.norm(M - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_planted_moment_and_self_patch_slips_are_caught(monkeypatch):
+    """A moment order off by one (zeta^(alpha+1) for zeta^alpha, planted through the weights),
+    a dropped or sign-flipped self-patch term i z w/(4 pi), and a conjugated phase in the
+    off-diagonal kernel each fail a pin."""
+    lam, U, z, S, gamma, rho, cap, N = _diag_moment_case()
+    ref = _moments_closed_form(lam, U, z, gamma, rho, cap, N)
+    orig = O.barycentric_weights
+    monkeypatch.setattr(O, "barycentric_weights", lambda zz, capacity=1.0: orig(zz, capacity) * np.asarray(zz))
+    bad = O.moments(S, z, U.shape[1], N, gamma, rho, cap)
+    monkeypatch.undo()
+    assert np.linalg.norm(bad - ref) > 1e-3 * np.linalg.norm(ref)
+
+    nep = W.helmholtz_sphere(2048)
+    w = nep.w
+    for zz in (3.8, 2.5 + 0.2j):
+        T = O.T_helmholtz(nep.points[:16], w, zz)
+        term = 1j * zz * w / (4.0 * math.pi)
+        dropped = T - np.diag(np.full(16, term))
+        flipped = T - np.diag(np.full(16, 2 * term))
+        assert _self_patch_ratio(dropped, zz, w) > 5.0
+        assert _self_patch_ratio(flipped, zz, w) > 5.0
+    prob = O.Problem(nep)
+    T = prob.T(3.8)
+    conj = T.real - 1j * T.imag
+    np.fill_diagonal(conj, np.diag(T))
+    exact = np.exp(1j * 3.8) * np.sin(3.8) / 3.8
+    assert np.max(np.abs(conj.sum(axis=1) - exact)) > 3e-2 * abs(exact) + 5e-3
+
+
 def test_distinct_inside_keeps_first_of_close_estimates():
     lam = np.array([1.0 + 0.1j, 1.0 + 0.1j + 5e-7, 3.0 + 0j, 0.2 - 0.05j, 1.0 + 0.1j + 2e-6])
     got = O.distinct_inside(lam, 1.0 + 0j, 1.5, 0.5)  # 3.0 lies outside (level 1.78)
@@ -311,7 +415,7 @@ def test_distinct_inside_keeps_first_of_close_estimates():
 
 
 def test_two_stage_points_at_estimates_sharpen_the_eigenvalues():
-    """Sec. 5.2-5.3: stage 1 on six contour points is rough; adding its estimates inside as
+    """Sec. 5.4 and Sec. 6: stage 1 on six contour points is rough; adding its estimates inside as
     sampling points gives every eigenvalue inside to 1e-9 of the closed form and cuts the
     eigen-residuals by orders of magnitude."""
     nep, C, U = W.cfg_qep(n=60, N=6, L=4)
