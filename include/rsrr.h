@@ -66,7 +66,10 @@ enum {
     RSRR_EDEVICE = 5,        /* a HIP runtime call failed                                      */
     RSRR_ENOTCONV = 6,       /* an iterative eigen/singular-value solve did not converge        */
     RSRR_ENAN = 7,           /* a NaN or Inf reached a pivot                                   */
-    RSRR_ETIMEOUT = 8        /* rsrr_server_wait: the request had not finished in time          */
+    RSRR_ETIMEOUT = 8,       /* rsrr_server_wait: the request had not finished in time          */
+    RSRR_ELIMIT = 9,         /* a size beyond a documented limit of the library (see the call)   */
+    RSRR_WARN_MORE = 10      /* rsrr_solve: more eigenpairs than max_eigs; those of lowest
+                                elliptic level were returned                                     */
 };
 
 /* Kinds of T(z).  SEPARABLE: T(z) = sum_j f_j(z) A_j (the form of every
@@ -127,7 +130,7 @@ typedef struct {
     int warn_gap;      /* 1 when g_max < tol_gap                          */
     double gmax;       /* largest sigma_j / sigma_{j+1} of H              */
     int n_sigma;       /* number of singular values of H computed (leading) */
-    int pad;
+    int truncated;     /* 1 when nbar > max_eigs and only max_eigs eigenpairs were returned */
 } rsrr_solve_info;
 
 typedef struct rsrr_ctx rsrr_ctx;
@@ -140,6 +143,56 @@ typedef struct rsrr_ctx rsrr_ctx;
  * larger calls run in chunks of points.
  * Errors: -1 ctx NULL, -2 bad device, RSRR_EDEVICE. */
 RSRR_API rsrr_status rsrr_create(rsrr_ctx **ctx, int device, void *stream);
+
+/* Versioned options of a context (the knobs the library otherwise fixes).
+ * `size` comes first: the library reads only the fields that lie inside the
+ * caller's `size` bytes and keeps its defaults for the rest, so a caller built
+ * against an older, shorter struct stays valid.  Initialise with
+ * rsrr_options_init, change fields, then rsrr_set_options.
+ *   ir_max_iters          rsrr_sample (C64_IR, R32_IR): most refinement
+ *                         corrections per point (default 10; 0..100; 0 = no
+ *                         correction: a point whose first solve is above
+ *                         fallback_resid is redone on the C128 path).
+ *   ir_max_iters_batched  the same for rsrr_sample_batched and the server's
+ *                         sampling launches, whose refinement runs on the
+ *                         device (default 3; 0..16).
+ *   basis_sketch_max      rsrr_basis: columns of the first range sketch of S
+ *                         (default 1024; >= 8); it doubles until it resolves
+ *                         the range (see rsrr_basis).
+ *   ir_tol                refinement stops when a point's normwise backward
+ *                         error max_c ||r_c|| / (||T||_F ||x_c|| + ||u_c||) is at
+ *                         most ir_tol * u * sqrt(n), u = 2^-53 (default 4; > 0).
+ *   fallback_resid        a refined point whose relative residual
+ *                         max_c ||u_c - T x_c||_2 / ||u_c||_2 is above this is
+ *                         redone on the C128 path (default 1e-10; (0, 1)).
+ *   delta, tol_gap        rank truncation (Sec. 4.3, Step 3) and gap threshold
+ *                         (eq. gap) where the library chooses them: server
+ *                         requests with delta = 0, and the server's SS-FULL
+ *                         (defaults 1e-14 and 1e3).
+ * Errors of rsrr_set_options: -1 ctx NULL, -2 opt NULL or size too small to
+ * hold `version`, -3 .. -9 the fields in the order above out of range. */
+#define RSRR_OPTIONS_VERSION 1
+typedef struct {
+    unsigned long long size;   /* sizeof(rsrr_options) as the caller compiled it */
+    int version;               /* RSRR_OPTIONS_VERSION as the caller compiled it */
+    int ir_max_iters;
+    int ir_max_iters_batched;
+    int basis_sketch_max;
+    double ir_tol;
+    double fallback_resid;
+    double delta;
+    double tol_gap;
+} rsrr_options;
+
+/* Fill *opt with the defaults, its size and version.  Errors: -1 opt NULL. */
+RSRR_API rsrr_status rsrr_options_init(rsrr_options *opt);
+
+/* Apply options to a context (later calls on it use them). */
+RSRR_API rsrr_status rsrr_set_options(rsrr_ctx *ctx, const rsrr_options *opt);
+
+/* Read a context's options (opt->size set by the caller, as for rsrr_set_options).
+ * Errors: -1 ctx NULL, -2 opt NULL or size too small. */
+RSRR_API rsrr_status rsrr_get_options(rsrr_ctx *ctx, rsrr_options *opt);
 
 /* Release the context and its workspace.  Errors: -1 ctx NULL. */
 RSRR_API rsrr_status rsrr_destroy(rsrr_ctx *ctx);
@@ -213,11 +266,22 @@ RSRR_API rsrr_status rsrr_sample_gmres(rsrr_ctx *ctx, const rsrr_nep *nep, int N
                                        rsrr_gmres_info *info);
 
 /* Basis (RSRR Step 3, Sec. 4.2-4.3).  S (device, n x NL, lds) is normalised
- * in place to unit column norms, then its singular values sigma (host,
- * min(n, NL) doubles, descending; may be NULL) and the number k of them above
- * delta*sigma_1 are computed in FP64; the first min(k, kmax) left singular
- * vectors are written to Q (device, n x kmax, ldq >= n).  *k (host) receives
- * k even when k > kmax.
+ * in place to unit column norms; then the number k of singular values above
+ * delta*sigma_1 and the first min(k, kmax) left singular vectors (Q: device,
+ * n x kmax, ldq >= n) are computed in FP64.  *k (host) receives k even when
+ * k > kmax.  The range of S is found by a seeded Gaussian sketch S Omega of
+ * basis_sketch_max columns (rsrr_options, default 1024; S itself when NL is
+ * no wider), orthonormalised by block CGS2 with numerically dependent columns
+ * dropped; the sketch width doubles (up to min(n, NL)) until the sketch comes
+ * out rank deficient or its smallest singular value is at the rounding floor
+ * (<= 1e-15 sigma_1).  The SVD of S restricted to that range (one-sided
+ * Jacobi) gives r <= min(n, NL) singular values.  sigma (host, min(n, NL)
+ * doubles, may be NULL) receives those r values, descending, followed by
+ * zeros for the values the sketch did not resolve.  Those lie at the rounding
+ * level of S: below 1e-15 sigma_1 when the sketch stopped at that floor, or
+ * below the block CGS2 dropping level (4 u sqrt(n) of a sketch column's norm,
+ * u = 2^-53) when it came out rank deficient; a count k near delta*sigma_1
+ * can therefore differ from a full SVD's by the values within that level.
  * Errors: -2 n < 1, -3 NL < 1, -4 S NULL, -5 lds < n, -6 delta not in (0,1),
  * -7 Q NULL, -8 ldq < n, -9 kmax < 1, -10 k NULL.  RSRR_ENOTCONV if the
  * one-sided Jacobi SVD did not converge. */
@@ -243,18 +307,25 @@ RSRR_API rsrr_status rsrr_project(rsrr_ctx *ctx, const rsrr_nep *nep, const doub
  * sum_j f_j(z) AQ_j (device AQ, J_eff matrices k x k; host terms).  SS-FULL
  * on the ellipse (gamma, a, b) with NQ trapezoid nodes and KQ moment blocks:
  * moments of T_Q^-1 in zeta = (z - gamma)/max(a, b), block Hankel H and H^<
- * (eq. HH), SVD of H, count by the largest gap (eq. gap), reduced matrix
- * (eq. A), its eigenpairs, lift g = M W0 Sigma0^-1 b and v = Q g.
+ * (eq. HH), SVD of H, count nbar by the largest gap (eq. gap), reduced matrix
+ * A = V0^H H^< W0 Sigma0^-1 of order nbar (eq. A, every retained singular
+ * triplet), its nbar eigenpairs, lift g = M W0 Sigma0^-1 b and v = Q g.
+ * Of the nbar eigenpairs, the min(nbar, max_eigs) of lowest elliptic level
+ * |Re(lambda-gamma)/a|^2 + |Im(lambda-gamma)/b|^2 are returned, in increasing
+ * level; max_eigs never changes the arithmetic, only how many are copied out.
  * Outputs: count (host) eigenvalues lambda (host, 2*max_eigs doubles),
  * eigenvectors V (device, n x max_eigs, ldv >= n, unit 2-norm; may be NULL),
  * residuals resid (host, max_eigs; ||T(lambda)v||_2 / (||T(lambda)||_1 ||v||_2)
- * in FP64 against the full nep; may be NULL only if V is NULL), the level of
- * each eigenvalue is for the caller to compute.  sigma_H (host, KQ*k doubles,
- * may be NULL) receives the singular values of H, descending: all KQ*k of
- * them, or, when H is numerically of low rank and a range sketch of it shows
- * a clear gap (g_max >= 10 tol_gap), the sinfo->n_sigma leading ones
- * followed by zeros.  sinfo (host, may be NULL).
- * Status RSRR_WARN_GAP when g_max < tol_gap (results are best effort).
+ * in FP64 against the full nep; may be NULL only if V is NULL).  sigma_H
+ * (host, KQ*k doubles, may be NULL) receives the singular values of H,
+ * descending: all KQ*k of them, or, when H is numerically of low rank and a
+ * range sketch of it shows a clear gap (g_max >= 10 tol_gap), the
+ * sinfo->n_sigma leading ones followed by zeros.  sinfo (host, may be NULL):
+ * nbar, g_max, the gap warning and whether the output was truncated.
+ * Status RSRR_WARN_GAP when g_max < tol_gap (results are best effort; takes
+ * precedence over RSRR_WARN_MORE), RSRR_WARN_MORE when nbar > max_eigs,
+ * RSRR_ELIMIT when nbar > 1024 (the reduced eigenproblem's size limit;
+ * nothing is returned, sinfo->nbar tells the count).
  * Errors: -2 nep, -3 k < 1, -4 AQ NULL, -5 J_eff < 1, -6 terms NULL,
  * -7 Q NULL, -8 ldq, -9 gamma NULL, -10 a, -11 b, -12 NQ < 2*KQ+1,
  * -13 KQ < 1, -14 tol_gap, -15 max_eigs < 1, -16 lambda NULL, -17 ldv,
@@ -295,7 +366,8 @@ enum {
  * for many NEPs at once).  Instances are grouped by n rounded up to 64; each
  * group runs as one batch of padded matrices diag(T(z_k), I) (the padded
  * solve returns T(z_k)^-1 U exactly).  With C64_IR the refinement runs on the
- * device with at most 3 corrections; points above 1e-10 relative residual
+ * device with at most ir_max_iters_batched corrections (rsrr_options,
+ * default 3); points above fallback_resid (default 1e-10) relative residual
  * are redone on the FP64 path.  info: host, sum of N entries in instance
  * order (may be NULL).  The library keeps per-bucket buffers (and graphs) in
  * the context until rsrr_destroy.  Panel widths chosen by the autotuner are
@@ -381,6 +453,8 @@ typedef struct {
     int pad;
     unsigned long long arena_bytes;  /* HBM for the admitted requests' S blocks            */
     unsigned long long batch_bytes;  /* HBM cap of one sampling launch's LU workspace      */
+    const rsrr_options *options;     /* options of every context of the server (NULL: defaults);
+                                        read at creation                                     */
 } rsrr_server_config;
 
 enum {

@@ -22,7 +22,7 @@ namespace {
 constexpr int MAX_TERMS = 64;
 constexpr double DISTINCT_REL = 1e-6;
 
-bool bad(rsrr_status s) { return s < 0 || s == RSRR_ENOMEM || s == RSRR_EDEVICE || s == RSRR_ENOTCONV || s == RSRR_ENAN; }
+bool bad(rsrr_status s) { return s < 0 || s == RSRR_ENOMEM || s == RSRR_EDEVICE || s == RSRR_ENOTCONV || s == RSRR_ENAN || s == RSRR_ELIMIT; }
 
 void keep_first(rsrr_status& acc, rsrr_status s)
 {

@@ -104,7 +104,7 @@ extern "C" rsrr_status rsrr_basis(rsrr_ctx* c, int n, int NL, double* S, int lds
     // smallest singular value is at the rounding floor (<= 1e-15 sigma_1);
     // otherwise l doubles.
     const int m = std::min(n, NL);
-    int l = std::min(m, 1024);
+    int l = std::min(m, c->basis_sketch_max);
     const double tol = 4.0 * std::max(1.0, std::sqrt((double)NL)) * 2.220446049250313e-16;
     rsrr_status st = RSRR_OK;
     std::vector<int> o, idx;

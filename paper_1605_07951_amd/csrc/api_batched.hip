@@ -33,7 +33,6 @@ using namespace rsrr;
 namespace {
 
 constexpr int BUCKET = 64;
-constexpr int MAXIT_BATCHED = 3;
 
 struct GraphEntry {
     std::vector<unsigned long long> key;
@@ -195,7 +194,7 @@ rsrr_status run_bucket(rsrr_ctx* c, hipStream_t sm, const rsrr_instance* inst, c
         RSRR_HIP(getrs_batched<double>(sm, (const double2*)b.T, b.sT, P, P, nb, w, b.Xb, b.sU, P, Lmax, (int)M));
     }
     // refinement with FP64 residuals, decisions on the device
-    const double tol_be = 4.0 * 1.1102230246251565e-16 * std::sqrt((double)P);
+    const double tol_be = c->ir_tol * 1.1102230246251565e-16 * std::sqrt((double)P);
     const int iters = mixed ? maxit : 0;
     for (int it = 0; it <= iters; ++it) {
         if (resid_skinny_ok(Lmax)) {
@@ -318,7 +317,7 @@ extern "C" rsrr_status rsrr_sample_batched(rsrr_ctx* c, int count, const rsrr_in
                 pi.resid = hres[m];
                 if (hinfo[m] > 0) any_sing = 1;
                 if (hinfo[m] < 0) any_nan = 1;
-                if (hinfo[m] == 0 && !(hres[m] <= 1e-10)) {
+                if (hinfo[m] == 0 && !(hres[m] <= c->fallback_resid)) {
                     // redo this point on the FP64 path
                     rsrr_point_info fpi;
                     const rsrr_status st = rsrr_sample(c, &in.nep, 1, in.z + 2 * k, in.U, in.L, in.ldu,
@@ -451,7 +450,7 @@ extern "C" rsrr_status rsrr_sample_batched(rsrr_ctx* c, int count, const rsrr_in
             save_tune_file(S);
         }
 
-        const int maxit = MAXIT_BATCHED;
+        const int maxit = c->ir_max_iters_batched;
         if (use_graph) {
             // key: everything the captured work depends on
             std::vector<unsigned long long> key;
@@ -459,6 +458,10 @@ extern "C" rsrr_status rsrr_sample_batched(rsrr_ctx* c, int count, const rsrr_in
             key.push_back((unsigned long long)prec);
             key.push_back((unsigned long long)nb);
             key.push_back((unsigned long long)M);
+            key.push_back((unsigned long long)maxit);
+            unsigned long long tolbits;
+            std::memcpy(&tolbits, &c->ir_tol, 8);
+            key.push_back(tolbits);
             for (int id : ids) {
                 const rsrr_instance& in = inst[id];
                 key.push_back((unsigned long long)(uintptr_t)in.nep.A);

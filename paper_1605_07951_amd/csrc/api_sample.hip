@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -82,6 +83,75 @@ rsrr_status rsrr_create(rsrr_ctx** ctx, int device, void* stream)
         return RSRR_EDEVICE;
     }
     *ctx = c;
+    return RSRR_OK;
+}
+
+rsrr_status rsrr_options_init(rsrr_options* opt)
+{
+    if (!opt) return -1;
+    const rsrr_ctx d;
+    *opt = rsrr_options{};
+    opt->size = sizeof(rsrr_options);
+    opt->version = RSRR_OPTIONS_VERSION;
+    opt->ir_max_iters = d.ir_max_iters;
+    opt->ir_max_iters_batched = d.ir_max_iters_batched;
+    opt->basis_sketch_max = d.basis_sketch_max;
+    opt->ir_tol = d.ir_tol;
+    opt->fallback_resid = d.fallback_resid;
+    opt->delta = d.delta;
+    opt->tol_gap = d.tol_gap;
+    return RSRR_OK;
+}
+
+// A field is read when it lies wholly inside the caller's `size` bytes.
+#define RSRR_OPT_HAS(opt, f) ((opt)->size >= offsetof(rsrr_options, f) + sizeof((opt)->f))
+
+rsrr_status rsrr_set_options(rsrr_ctx* c, const rsrr_options* opt)
+{
+    if (!c) return -1;
+    if (!opt || !RSRR_OPT_HAS(opt, version)) return -2;
+    rsrr_ctx n;  // validated copy of the option fields
+    n.ir_max_iters = RSRR_OPT_HAS(opt, ir_max_iters) ? opt->ir_max_iters : c->ir_max_iters;
+    n.ir_max_iters_batched = RSRR_OPT_HAS(opt, ir_max_iters_batched) ? opt->ir_max_iters_batched : c->ir_max_iters_batched;
+    n.basis_sketch_max = RSRR_OPT_HAS(opt, basis_sketch_max) ? opt->basis_sketch_max : c->basis_sketch_max;
+    n.ir_tol = RSRR_OPT_HAS(opt, ir_tol) ? opt->ir_tol : c->ir_tol;
+    n.fallback_resid = RSRR_OPT_HAS(opt, fallback_resid) ? opt->fallback_resid : c->fallback_resid;
+    n.delta = RSRR_OPT_HAS(opt, delta) ? opt->delta : c->delta;
+    n.tol_gap = RSRR_OPT_HAS(opt, tol_gap) ? opt->tol_gap : c->tol_gap;
+    if (n.ir_max_iters < 0 || n.ir_max_iters > 100) return -3;
+    if (n.ir_max_iters_batched < 0 || n.ir_max_iters_batched > 16) return -4;
+    if (n.basis_sketch_max < 8) return -5;
+    if (!(n.ir_tol > 0)) return -6;
+    if (!(n.fallback_resid > 0 && n.fallback_resid < 1)) return -7;
+    if (!(n.delta > 0 && n.delta < 1)) return -8;
+    if (!(n.tol_gap > 0)) return -9;
+    c->ir_max_iters = n.ir_max_iters;
+    c->ir_max_iters_batched = n.ir_max_iters_batched;
+    c->basis_sketch_max = n.basis_sketch_max;
+    c->ir_tol = n.ir_tol;
+    c->fallback_resid = n.fallback_resid;
+    c->delta = n.delta;
+    c->tol_gap = n.tol_gap;
+    return RSRR_OK;
+}
+
+rsrr_status rsrr_get_options(rsrr_ctx* c, rsrr_options* opt)
+{
+    if (!c) return -1;
+    if (!opt || !RSRR_OPT_HAS(opt, version)) return -2;
+    rsrr_options full;
+    rsrr_options_init(&full);
+    full.ir_max_iters = c->ir_max_iters;
+    full.ir_max_iters_batched = c->ir_max_iters_batched;
+    full.basis_sketch_max = c->basis_sketch_max;
+    full.ir_tol = c->ir_tol;
+    full.fallback_resid = c->fallback_resid;
+    full.delta = c->delta;
+    full.tol_gap = c->tol_gap;
+    const size_t bytes = std::min<size_t>((size_t)opt->size, sizeof(rsrr_options));
+    const unsigned long long keep = opt->size;
+    std::memcpy(opt, &full, bytes);
+    opt->size = keep;
     return RSRR_OK;
 }
 
@@ -473,7 +543,7 @@ static rsrr_status sample_batch(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, i
         t.stop();
     }
     const double eps = 1.1102230246251565e-16;
-    const double tol_be = 4.0 * eps * std::sqrt((double)n);
+    const double tol_be = c->ir_tol * eps * std::sqrt((double)n);
     std::vector<double> prev(B, 1e300), resid(B, 0.0), scl((size_t)B * L), inv((size_t)B * L);
     std::vector<int> done(B, 0), iters(B, 0);
     for (int k = 0; k < B; ++k) done[k] = act[k] ? 0 : 1;
@@ -551,10 +621,10 @@ static rsrr_status sample_batch(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, i
             info[k].resid = resid[k];
         }
     }
-    // fallback: points whose refinement did not reach 1e-10 are redone in FP64
+    // fallback: points whose refinement did not reach fallback_resid are redone in FP64
     for (int k = 0; k < B; ++k) {
         if (hinfo[k] != 0) continue;
-        if (resid[k] <= 1e-10) continue;
+        if (resid[k] <= c->fallback_resid) continue;
         rsrr_point_info pi;
         int sing = 0, fb = 0, nan = 0;
         st = sample_batch(c, nep, z + k, 1, U, L, ldu, un, RSRR_PREC_C128, S + (size_t)k * sX, lds, &pi, &sing, &fb,

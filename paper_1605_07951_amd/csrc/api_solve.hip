@@ -240,61 +240,83 @@ extern "C" rsrr_status rsrr_solve(rsrr_ctx* c, const rsrr_nep* nep, int k, const
         sinfo->warn_gap = warn;
         sinfo->gmax = gmax;
         sinfo->n_sigma = nsig;
+        sinfo->truncated = 0;
     }
     if (nbar == 0 || s[0] == 0.0) return RSRR_WARN_GAP;
-    const int ne = std::min(std::min(nbar, max_eigs), 256);
+    // eq. A uses every retained singular triplet: the reduced matrix and its
+    // eigenpairs are formed at the full count nbar; max_eigs only bounds how many
+    // eigenpairs are copied out (those of lowest elliptic level first).
+    if (nbar > small_eig_max()) return RSRR_ELIMIT;
+    const int na = nbar;
+    const int ne = std::min(na, max_eigs);
+    if (sinfo) sinfo->truncated = ne < na;
 
     // ---- V0, W0, reduced matrix A = V0^H H^< W0 Sigma0^-1 ----
-    int* dord = (int*)ws_get(c, WS_ACTIVE, (size_t)ne * 4);
-    double* dinv = (double*)ws_get(c, WS_NORM, (size_t)2 * ne * 8);
-    double2* V0 = (double2*)ws_get(c, WS_D64, (size_t)Kk * ne * 16);
-    double2* W0 = (double2*)ws_get(c, WS_R, (size_t)Kk * ne * 16);
-    double2* T1 = (double2*)ws_get(c, WS_B6, (size_t)Kk * ne * 16 + (size_t)3 * ne * ne * 16 + (size_t)ne * 16 + 64);
+    int* dord = (int*)ws_get(c, WS_ACTIVE, (size_t)na * 4);
+    double* dinv = (double*)ws_get(c, WS_NORM, (size_t)2 * na * 8);
+    double2* V0 = (double2*)ws_get(c, WS_D64, (size_t)Kk * na * 16);
+    double2* W0 = (double2*)ws_get(c, WS_R, (size_t)Kk * na * 16);
+    double2* T1 = (double2*)ws_get(c, WS_B6, (size_t)Kk * na * 16 + (size_t)4 * na * na * 16 + (size_t)na * 16 + 64);
     double2* G = (double2*)ws_get(c, WS_B7, (size_t)k * ne * 16 + (size_t)Kk * ne * 16);
     if (!dord || !dinv || !V0 || !W0 || !T1 || !G) return RSRR_ENOMEM;
-    double2* Ared = T1 + (size_t)Kk * ne;
-    double2* Hw = Ared + (size_t)ne * ne;
-    double2* Zw = Hw + (size_t)ne * ne;
-    double2* mu = Zw + (size_t)ne * ne;
+    double2* Ared = T1 + (size_t)Kk * na;
+    double2* Hw = Ared + (size_t)na * na;
+    double2* Zw = Hw + (size_t)na * na;
+    double2* Bsel = Zw + (size_t)na * na;
+    double2* mu = Bsel + (size_t)na * na;
     double2* Bv = V0;  // V0 is no longer needed once Ared is formed; reuse for the eigenvectors
     double2* Y = G + (size_t)k * ne;
-    std::vector<double> hinv(2 * ne);
-    for (int i = 0; i < ne; ++i) { hinv[i] = 1.0 / s[i]; hinv[ne + i] = 1.0; }
-    RSRR_HIP(hipMemcpyAsync(dord, ord.data(), (size_t)ne * 4, hipMemcpyHostToDevice, c->stream));
-    RSRR_HIP(hipMemcpyAsync(dinv, hinv.data(), (size_t)2 * ne * 8, hipMemcpyHostToDevice, c->stream));
+    std::vector<double> hinv(2 * na);
+    for (int i = 0; i < na; ++i) { hinv[i] = 1.0 / s[i]; hinv[na + i] = 1.0; }
+    RSRR_HIP(hipMemcpyAsync(dord, ord.data(), (size_t)na * 4, hipMemcpyHostToDevice, c->stream));
+    RSRR_HIP(hipMemcpyAsync(dinv, hinv.data(), (size_t)2 * na * 8, hipMemcpyHostToDevice, c->stream));
     if (XS) {
         // sketch: left vectors Q_Y W (W: bottom r rows of X), right vectors (top of X) / sigma
-        double2* Wsm = (double2*)ws_get(c, WS_B2, (size_t)rS * ne * 16);
+        double2* Wsm = (double2*)ws_get(c, WS_B2, (size_t)rS * na * 16);
         if (!Wsm) return RSRR_ENOMEM;
-        RSRR_HIP(gather_scale(c->stream, XS, Kk + rS, Kk, dord, dinv, W0, Kk, ne));
-        RSRR_HIP(gather_scale(c->stream, XS + Kk, Kk + rS, rS, dord, dinv + ne, Wsm, rS, ne));
-        RSRR_HIP(zgemm(c->stream, 0, 0, Kk, ne, rS, 1.0, QY, Kk, 0, Wsm, rS, 0, 0.0, V0, Kk, 0, 1));
+        RSRR_HIP(gather_scale(c->stream, XS, Kk + rS, Kk, dord, dinv, W0, Kk, na));
+        RSRR_HIP(gather_scale(c->stream, XS + Kk, Kk + rS, rS, dord, dinv + na, Wsm, rS, na));
+        RSRR_HIP(zgemm(c->stream, 0, 0, Kk, na, rS, 1.0, QY, Kk, 0, Wsm, rS, 0, 0.0, V0, Kk, 0, 1));
     } else {
-        RSRR_HIP(gather_scale(c->stream, Hx, 2 * Kk, Kk, dord, dinv, V0, Kk, ne));
-        RSRR_HIP(gather_scale(c->stream, Hx + Kk, 2 * Kk, Kk, dord, dinv + ne, W0, Kk, ne));
+        RSRR_HIP(gather_scale(c->stream, Hx, 2 * Kk, Kk, dord, dinv, V0, Kk, na));
+        RSRR_HIP(gather_scale(c->stream, Hx + Kk, 2 * Kk, Kk, dord, dinv + na, W0, Kk, na));
     }
-    RSRR_HIP(zgemm(c->stream, 0, 0, Kk, ne, Kk, 1.0, Hs, Kk, 0, W0, Kk, 0, 0.0, T1, Kk, 0, 1));
-    RSRR_HIP(zgemm(c->stream, 1, 0, ne, ne, Kk, 1.0, V0, Kk, 0, T1, Kk, 0, 0.0, Ared, ne, 0, 1));
-    RSRR_HIP(scale_cols(c->stream, ne, ne, Ared, ne, dinv));
+    RSRR_HIP(zgemm(c->stream, 0, 0, Kk, na, Kk, 1.0, Hs, Kk, 0, W0, Kk, 0, 0.0, T1, Kk, 0, 1));
+    RSRR_HIP(zgemm(c->stream, 1, 0, na, na, Kk, 1.0, V0, Kk, 0, T1, Kk, 0, 0.0, Ared, na, 0, 1));
+    RSRR_HIP(scale_cols(c->stream, na, na, Ared, na, dinv));
     int* dstat = (int*)ws_get(c, WS_INFO, 64);
     if (!dstat) return RSRR_ENOMEM;
-    RSRR_HIP(small_eig(c->stream, Ared, ne, Hw, Zw, mu, Bv, dstat));
+    RSRR_HIP(small_eig(c->stream, Ared, na, Hw, Zw, mu, Bv, dstat));
     int hstat = 0;
+    std::vector<double2> hmu(na);
     RSRR_HIP(hipMemcpyAsync(&hstat, dstat, 4, hipMemcpyDeviceToHost, c->stream));
-    // ---- lift: Y = W0 Sigma0^-1 B, g = M Y, v = Q g (unit columns) ----
-    RSRR_HIP(scale_cols(c->stream, Kk, ne, W0, Kk, dinv));
-    RSRR_HIP(zgemm(c->stream, 0, 0, Kk, ne, ne, 1.0, W0, Kk, 0, Bv, ne, 0, 0.0, Y, Kk, 0, 1));
-    RSRR_HIP(zgemm(c->stream, 0, 0, k, ne, Kk, 1.0, mom, k, 0, Y, Kk, 0, 0.0, G, k, 0, 1));
-    std::vector<double2> hmu(ne);
-    RSRR_HIP(hipMemcpyAsync(hmu.data(), mu, (size_t)ne * 16, hipMemcpyDeviceToHost, c->stream));
+    RSRR_HIP(hipMemcpyAsync(hmu.data(), mu, (size_t)na * 16, hipMemcpyDeviceToHost, c->stream));
     RSRR_HIP(hipStreamSynchronize(c->stream));
     if (hstat) return RSRR_ENOTCONV;
+    // ---- the ne eigenpairs of lowest elliptic level (stable: ties keep the Schur order) ----
+    std::vector<zd> lall(na);
+    std::vector<double> lev(na);
+    for (int i = 0; i < na; ++i) {
+        lall[i] = g + rho * zd(hmu[i].x, hmu[i].y);
+        const zd dz = lall[i] - g;
+        lev[i] = (dz.real() / a) * (dz.real() / a) + (dz.imag() / b) * (dz.imag() / b);
+    }
+    std::vector<int> sel(na);
+    std::iota(sel.begin(), sel.end(), 0);
+    std::stable_sort(sel.begin(), sel.end(), [&](int x, int y) { return lev[x] < lev[y]; });
+    sel.resize(ne);
     std::vector<zd> lam(ne);
     for (int i = 0; i < ne; ++i) {
-        lam[i] = g + rho * zd(hmu[i].x, hmu[i].y);
+        lam[i] = lall[sel[i]];
         lambda[2 * i] = lam[i].real();
         lambda[2 * i + 1] = lam[i].imag();
     }
+    RSRR_HIP(hipMemcpyAsync(dord, sel.data(), (size_t)ne * 4, hipMemcpyHostToDevice, c->stream));
+    RSRR_HIP(gather_scale(c->stream, Bv, na, na, dord, dinv + na, Bsel, na, ne));
+    // ---- lift: Y = W0 Sigma0^-1 B, g = M Y, v = Q g (unit columns) ----
+    RSRR_HIP(scale_cols(c->stream, Kk, na, W0, Kk, dinv));
+    RSRR_HIP(zgemm(c->stream, 0, 0, Kk, ne, na, 1.0, W0, Kk, 0, Bsel, na, 0, 0.0, Y, Kk, 0, 1));
+    RSRR_HIP(zgemm(c->stream, 0, 0, k, ne, Kk, 1.0, mom, k, 0, Y, Kk, 0, 0.0, G, k, 0, 1));
     *count = ne;
     if (Vp) {
         double2* V = (double2*)Vp;
@@ -333,5 +355,6 @@ extern "C" rsrr_status rsrr_solve(rsrr_ctx* c, const rsrr_nep* nep, int k, const
         }
     }
     RSRR_HIP(hipStreamSynchronize(c->stream));
-    return warn ? RSRR_WARN_GAP : RSRR_OK;
+    if (warn) return RSRR_WARN_GAP;
+    return ne < na ? RSRR_WARN_MORE : RSRR_OK;
 }

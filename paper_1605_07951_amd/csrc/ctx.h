@@ -33,7 +33,14 @@ struct rsrr_ctx {
     double timings[5] = {0, 0, 0, 0, 0};
     int nb_c64 = 128;      // outer LU panel width, complex FP32 path
     int nb_c128 = 64;      // outer LU panel width, complex FP64 path
-    int ir_max_iters = 10;
+    // options (rsrr_set_options)
+    int ir_max_iters = 10;          // host refinement loop of rsrr_sample
+    int ir_max_iters_batched = 3;   // device refinement of rsrr_sample_batched / the server
+    int basis_sketch_max = 1024;    // first range-sketch width of rsrr_basis
+    double ir_tol = 4.0;            // backward-error stop: ir_tol * u * sqrt(n)
+    double fallback_resid = 1e-10;  // refined points above this are redone in FP64
+    double delta = 1e-14;           // library-chosen rank truncation (server)
+    double tol_gap = 1e3;           // library-chosen gap threshold (server)
     size_t ws_budget = 0;  // bytes for the per-point sampling buffers (0 = half of free memory)
     // trailing-update statistics (rsrr_update_stats)
     bool rec_on = false;

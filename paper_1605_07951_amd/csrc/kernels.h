@@ -184,7 +184,9 @@ hipError_t hankel(hipStream_t st, const double2* mom, int k, int K, int shift, d
 hipError_t eye(hipStream_t st, double2* X, int ldx, int r0, int p);
 hipError_t norm1(hipStream_t st, const double2* T, int ld, long sT, int n, double* out, int B, double* part);
 int norm1_parts(int n);  // doubles of `part` per matrix
+// Eigenpairs of an n x n complex matrix, n <= small_eig_max().
 hipError_t small_eig(hipStream_t st, const double2* A, int n, double2* H, double2* Z, double2* lam, double2* Bv,
                      int* status);
+int small_eig_max();
 
 }  // namespace rsrr

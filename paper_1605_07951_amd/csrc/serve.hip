@@ -37,8 +37,6 @@ namespace {
 
 constexpr int DEFAULT_NQ = 500;
 constexpr int DEFAULT_KQ = 2;
-constexpr double DEFAULT_DELTA = 1e-14;
-constexpr double TOL_GAP = 1e3;
 constexpr int MAX_TERMS = 64;
 constexpr size_t ALIGN = 256;
 
@@ -112,7 +110,7 @@ double now_s(std::chrono::steady_clock::time_point t0)
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
-bool is_error(rsrr_status s) { return s < 0 || s == RSRR_ENOMEM || s == RSRR_EDEVICE || s == RSRR_ENOTCONV || s == RSRR_ENAN || s == RSRR_ESINGULAR; }
+bool is_error(rsrr_status s) { return s < 0 || s == RSRR_ENOMEM || s == RSRR_EDEVICE || s == RSRR_ENOTCONV || s == RSRR_ENAN || s == RSRR_ESINGULAR || s == RSRR_ELIMIT; }
 
 // LU workspace of one point in a sampling launch (the bucket buffers of
 // rsrr_sample_batched), bytes.
@@ -205,7 +203,7 @@ void finish_request(Worker* w, Req* q)
     double2* Q = (double2*)grow(w->q_buf, w->q_cap, (size_t)n * kmax * 16);
     if (!Q) { note_status(res, RSRR_ENOMEM); return; }
     int k = 0;
-    rsrr_status e = rsrr_basis(c, n, NL, q->S, n, r.delta > 0 ? r.delta : DEFAULT_DELTA, (double*)Q, n, kmax, &k,
+    rsrr_status e = rsrr_basis(c, n, NL, q->S, n, r.delta > 0 ? r.delta : c->delta, (double*)Q, n, kmax, &k,
                                nullptr);
     note_status(res, e);
     if (is_error(e)) return;
@@ -227,7 +225,7 @@ void finish_request(Worker* w, Req* q)
     rsrr_solve_info si{};
     std::vector<double> resid(r.max_eigs, 0.0);
     e = rsrr_solve(c, &r.nep, k, (const double*)AQ, J_eff, tout.data(), (const double*)Q, n, gam, r.a, r.b,
-                   r.NQ > 0 ? r.NQ : DEFAULT_NQ, r.KQ > 0 ? r.KQ : DEFAULT_KQ, TOL_GAP, r.max_eigs, r.lambda,
+                   r.NQ > 0 ? r.NQ : DEFAULT_NQ, r.KQ > 0 ? r.KQ : DEFAULT_KQ, c->tol_gap, r.max_eigs, r.lambda,
                    (double*)V, n, r.resid ? r.resid : resid.data(), &count, nullptr, &si);
     note_status(res, e);
     if (is_error(e)) return;
@@ -424,14 +422,18 @@ void solver_main(rsrr_server* s, Worker* w)
 
 }  // namespace
 
-static rsrr_status worker_init(Worker* w, int device)
+static rsrr_status worker_init(Worker* w, int device, const rsrr_options* opt)
 {
     if (hipStreamCreateWithFlags(&w->st, hipStreamNonBlocking) != hipSuccess) {
         w->st = nullptr;
         return RSRR_EDEVICE;
     }
-    const rsrr_status e = rsrr_create(&w->c, device, w->st);
-    if (e) w->c = nullptr;
+    rsrr_status e = rsrr_create(&w->c, device, w->st);
+    if (e) {
+        w->c = nullptr;
+        return e;
+    }
+    if (opt) e = rsrr_set_options(w->c, opt) ? -2 : RSRR_OK;
     return e;
 }
 
@@ -468,11 +470,12 @@ extern "C" rsrr_status rsrr_server_create(rsrr_server** out, const rsrr_server_c
     s->cfg = *cfg;
     if (s->cfg.solvers == 0) s->cfg.solvers = 2;
     s->t0 = std::chrono::steady_clock::now();
-    rsrr_status e = worker_init(&s->ws, cfg->device);
+    s->cfg.options = nullptr;  // read here only
+    rsrr_status e = worker_init(&s->ws, cfg->device, cfg->options);
     const int nsolve = (cfg->flags & RSRR_SERVE_SERIAL) ? 0 : s->cfg.solvers;
     for (int i = 0; i < nsolve && !e; ++i) {
         s->wp.emplace_back(new Worker());
-        e = worker_init(s->wp.back().get(), cfg->device);
+        e = worker_init(s->wp.back().get(), cfg->device, cfg->options);
     }
     if (!e && hipMalloc(&s->arena_base, cfg->arena_bytes) != hipSuccess) {
         (void)hipGetLastError();

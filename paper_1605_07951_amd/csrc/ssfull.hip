@@ -93,14 +93,23 @@ hipError_t norm1(hipStream_t st, const double2* T, int ld, long sT, int n, doubl
 int norm1_parts(int n) { return (n + N1_COLS - 1) / N1_COLS; }
 
 // ---------------------------------------------------------------------------
-// Eigenpairs of a small general complex matrix (n x n, column-major, ld n):
-// Householder reduction to Hessenberg form, single-shift QR with Wilkinson
-// shifts to the Schur form T = Z^H A Z, then eigenvectors of T by back
-// substitution, b = Z y (unit 2-norm).  One workgroup; the reduction and the
-// QR sweeps run on lane 0, the wide row/column updates on all lanes.
+// Eigenpairs of a small general complex matrix (n x n, column-major, ld n,
+// n <= SMALL_EIG_MAX): Householder reduction to Hessenberg form, single-shift
+// QR with Wilkinson shifts to the Schur form T = Z^H A Z, then eigenvectors of
+// T by back substitution, b = Z y (unit 2-norm).  One workgroup of one wave.
+// The Householder vector is formed on lane 0; every other step is spread over
+// the 64 lanes: row and column updates of the reflections, and in each QR step
+// the row pair (left rotation) and column pair (right rotation) of every Givens
+// rotation.  The rotations of one QR step depend on each other and are applied
+// in order, one barrier apart; all lanes compute the same rotation from the
+// same entries, so the control flow is uniform.
 // Work arrays (device): H (n*n), Z (n*n).  Outputs: lam (n), Bv (n*n).
+// Dynamic LDS: n complex (reflector) + n complex + n real (rotations).
 // status[0]: 0 ok, 1 QR did not converge.
 // ---------------------------------------------------------------------------
+constexpr int SMALL_EIG_MAX = 1024;
+int small_eig_max() { return SMALL_EIG_MAX; }
+
 RSRR_DEV double cabs_(double2 a) { return hypot(a.x, a.y); }
 RSRR_DEV double2 cdiv_(double2 a, double2 b) { return cmul(a, crecip(b)); }
 RSRR_DEV double2 csqrt_(double2 a)
@@ -113,10 +122,29 @@ RSRR_DEV double2 csqrt_(double2 a)
     return make_double2(x, y);
 }
 
+// Givens rotation [c s; -conj(s) c] (c real) that zeroes y below x.
+RSRR_DEV void givens_(double2 x, double2 y, double* cc, double2* ss)
+{
+    const double ax = cabs_(x), ay = cabs_(y);
+    const double r = hypot(ax, ay);
+    if (r == 0.0) { *cc = 1.0; *ss = make_double2(0.0, 0.0); }
+    else if (ax == 0.0) { *cc = 0.0; *ss = make_double2(y.x / ay, -y.y / ay); }
+    else {
+        *cc = ax / r;
+        const double2 ph = make_double2(x.x / ax, x.y / ax);
+        *ss = cmul(ph, make_double2(y.x / r, -y.y / r));
+    }
+}
+
 __global__ __launch_bounds__(64) void small_eig_kernel(const double2* __restrict__ A, int n, double2* __restrict__ H,
                                                         double2* __restrict__ Z, double2* __restrict__ lam,
                                                         double2* __restrict__ Bv, int* __restrict__ status)
 {
+    extern __shared__ double2 s_dyn[];
+    double2* s_v = s_dyn;                      // n: Householder vector
+    double2* s_sn = s_dyn + n;                 // n: rotation sines of one QR step
+    double* s_cs = (double*)(s_dyn + 2 * n);   // n: rotation cosines
+    __shared__ double s_beta;
     const int t = threadIdx.x;
 #define HH(i, j) H[(i) + (long)(j) * n]
 #define ZZ(i, j) Z[(i) + (long)(j) * n]
@@ -125,9 +153,7 @@ __global__ __launch_bounds__(64) void small_eig_kernel(const double2* __restrict
         Z[e] = make_double2((e % n) == (e / n) ? 1.0 : 0.0, 0.0);
     }
     __syncthreads();
-    __shared__ double2 s_v[256];
-    __shared__ double s_beta;
-    // ---- Hessenberg reduction (n <= 256 for the LDS reflector) ----
+    // ---- Hessenberg reduction ----
     for (int kcol = 0; kcol + 2 < n; ++kcol) {
         if (t == 0) {
             double alpha2 = 0.0;
@@ -175,87 +201,82 @@ __global__ __launch_bounds__(64) void small_eig_kernel(const double2* __restrict
             }
         }
         __syncthreads();
-        if (t == 0)
-            for (int i = kcol + 2; i < n; ++i) HH(i, kcol) = make_double2(0.0, 0.0);
+        for (int i = kcol + 2 + t; i < n; i += 64) HH(i, kcol) = make_double2(0.0, 0.0);
         __syncthreads();
     }
-    // ---- shifted QR to Schur form (lane 0) ----
-    if (t == 0) {
-        const double eps = 2.220446049250313e-16;
-        int hi = n - 1, iter = 0, total = 0, bad = 0;
-        while (hi > 0) {
-            // deflation search
-            int lo = hi;
-            while (lo > 0) {
-                const double s = cabs_(HH(lo, lo)) + cabs_(HH(lo - 1, lo - 1));
-                if (cabs_(HH(lo, lo - 1)) <= eps * (s > 0 ? s : 1.0)) { HH(lo, lo - 1) = make_double2(0.0, 0.0); break; }
-                --lo;
-            }
-            if (lo == hi) { --hi; iter = 0; continue; }
-            if (++total > 100 * n) { bad = 1; break; }
-            ++iter;
-            // Wilkinson shift from the trailing 2x2 of the active block
-            const double2 a = HH(hi - 1, hi - 1), b = HH(hi - 1, hi), c = HH(hi, hi - 1), d = HH(hi, hi);
-            double2 mu;
-            if (iter % 11 == 10) {
-                mu = make_double2(d.x + 0.75 * cabs_(c), d.y);  // exceptional shift
-            } else {
-                const double2 hd = make_double2(0.5 * (a.x - d.x), 0.5 * (a.y - d.y));
-                const double2 disc = csqrt_(cadd(cmul(hd, hd), cmul(b, c)));
-                const double2 m1 = cadd(make_double2(0.5 * (a.x + d.x), 0.5 * (a.y + d.y)), disc);
-                const double2 m2 = csub(make_double2(0.5 * (a.x + d.x), 0.5 * (a.y + d.y)), disc);
-                mu = cabs_(csub(m1, d)) < cabs_(csub(m2, d)) ? m1 : m2;
-            }
-            // explicit shifted QR step on rows/cols lo..hi (full rows/cols for the Schur form)
-            for (int i = lo; i <= hi; ++i) HH(i, i) = csub(HH(i, i), mu);
-            double cs[256];
-            double2 sn[256];
-            for (int i = lo; i < hi; ++i) {
-                const double2 x = HH(i, i), y = HH(i + 1, i);
-                const double ax = cabs_(x), ay = cabs_(y);
-                const double r = hypot(ax, ay);
-                double cc;
-                double2 ss;
-                if (r == 0.0) { cc = 1.0; ss = make_double2(0.0, 0.0); }
-                else if (ax == 0.0) { cc = 0.0; ss = make_double2(y.x / ay, -y.y / ay); }
-                else {
-                    cc = ax / r;
-                    const double2 ph = make_double2(x.x / ax, x.y / ax);
-                    ss = cmul(ph, make_double2(y.x / r, -y.y / r));
-                }
-                cs[i - lo] = cc; sn[i - lo] = ss;
-                // rows i, i+1: [r_i; r_{i+1}] <- [c s; -conj(s) c] [r_i; r_{i+1}]
-                for (int j = i; j < n; ++j) {
-                    const double2 u = HH(i, j), v = HH(i + 1, j);
-                    HH(i, j) = cadd(make_double2(cc * u.x, cc * u.y), cmul(ss, v));
-                    HH(i + 1, j) = csub(make_double2(cc * v.x, cc * v.y), cmul(cconj(ss), u));
-                }
-            }
-            for (int i = lo; i < hi; ++i) {
-                const double cc = cs[i - lo];
-                const double2 ss = sn[i - lo];
-                // columns i, i+1 <- columns * G^H : [c_i c_{i+1}] [c -s; conj(s) c]
-                const int rmax = (i + 2 <= hi) ? i + 2 : hi;
-                for (int r = 0; r <= rmax; ++r) {
-                    const double2 u = HH(r, i), v = HH(r, i + 1);
-                    HH(r, i) = cadd(make_double2(cc * u.x, cc * u.y), cmul(cconj(ss), v));
-                    HH(r, i + 1) = csub(make_double2(cc * v.x, cc * v.y), cmul(ss, u));
-                }
-                for (int r = 0; r < n; ++r) {
-                    const double2 u = ZZ(r, i), v = ZZ(r, i + 1);
-                    ZZ(r, i) = cadd(make_double2(cc * u.x, cc * u.y), cmul(cconj(ss), v));
-                    ZZ(r, i + 1) = csub(make_double2(cc * v.x, cc * v.y), cmul(ss, u));
-                }
-            }
-            for (int i = lo; i <= hi; ++i) HH(i, i) = cadd(HH(i, i), mu);
+    // ---- shifted QR to Schur form ----
+    const double eps = 2.220446049250313e-16;
+    int hi = n - 1, iter = 0, total = 0, bad = 0;
+    while (hi > 0) {
+        __syncthreads();
+        // deflation search (every lane, same entries, same answer)
+        int lo = hi;
+        while (lo > 0) {
+            const double s = cabs_(HH(lo, lo)) + cabs_(HH(lo - 1, lo - 1));
+            if (cabs_(HH(lo, lo - 1)) <= eps * (s > 0 ? s : 1.0)) break;
+            --lo;
         }
-        status[0] = bad;
-        for (int i = 0; i < n; ++i) lam[i] = HH(i, i);
+        __syncthreads();
+        if (lo > 0 && t == 0) HH(lo, lo - 1) = make_double2(0.0, 0.0);
+        if (lo == hi) { --hi; iter = 0; continue; }
+        if (++total > 100 * n) { bad = 1; break; }
+        ++iter;
+        // Wilkinson shift from the trailing 2x2 of the active block
+        const double2 a = HH(hi - 1, hi - 1), b = HH(hi - 1, hi), c = HH(hi, hi - 1), d = HH(hi, hi);
+        double2 mu;
+        if (iter % 11 == 10) {
+            mu = make_double2(d.x + 0.75 * cabs_(c), d.y);  // exceptional shift
+        } else {
+            const double2 hd = make_double2(0.5 * (a.x - d.x), 0.5 * (a.y - d.y));
+            const double2 disc = csqrt_(cadd(cmul(hd, hd), cmul(b, c)));
+            const double2 m1 = cadd(make_double2(0.5 * (a.x + d.x), 0.5 * (a.y + d.y)), disc);
+            const double2 m2 = csub(make_double2(0.5 * (a.x + d.x), 0.5 * (a.y + d.y)), disc);
+            mu = cabs_(csub(m1, d)) < cabs_(csub(m2, d)) ? m1 : m2;
+        }
+        __syncthreads();
+        // explicit shifted QR step on the active block (full rows/columns for the Schur form)
+        for (int i = lo + t; i <= hi; i += 64) HH(i, i) = csub(HH(i, i), mu);
+        __syncthreads();
+        for (int i = lo; i < hi; ++i) {
+            double cc;
+            double2 ss;
+            givens_(HH(i, i), HH(i + 1, i), &cc, &ss);
+            if (t == 0) { s_cs[i - lo] = cc; s_sn[i - lo] = ss; }
+            __syncthreads();
+            // rows i, i+1: [r_i; r_{i+1}] <- [c s; -conj(s) c] [r_i; r_{i+1}]
+            for (int j = i + t; j < n; j += 64) {
+                const double2 u = HH(i, j), v = HH(i + 1, j);
+                HH(i, j) = cadd(make_double2(cc * u.x, cc * u.y), cmul(ss, v));
+                HH(i + 1, j) = csub(make_double2(cc * v.x, cc * v.y), cmul(cconj(ss), u));
+            }
+            __syncthreads();
+        }
+        for (int i = lo; i < hi; ++i) {
+            const double cc = s_cs[i - lo];
+            const double2 ss = s_sn[i - lo];
+            // columns i, i+1 <- columns * G^H : [c_i c_{i+1}] [c -s; conj(s) c]
+            const int rmax = (i + 2 <= hi) ? i + 2 : hi;
+            for (int r = t; r <= rmax; r += 64) {
+                const double2 u = HH(r, i), v = HH(r, i + 1);
+                HH(r, i) = cadd(make_double2(cc * u.x, cc * u.y), cmul(cconj(ss), v));
+                HH(r, i + 1) = csub(make_double2(cc * v.x, cc * v.y), cmul(ss, u));
+            }
+            for (int r = t; r < n; r += 64) {
+                const double2 u = ZZ(r, i), v = ZZ(r, i + 1);
+                ZZ(r, i) = cadd(make_double2(cc * u.x, cc * u.y), cmul(cconj(ss), v));
+                ZZ(r, i + 1) = csub(make_double2(cc * v.x, cc * v.y), cmul(ss, u));
+            }
+            __syncthreads();
+        }
+        for (int i = lo + t; i <= hi; i += 64) HH(i, i) = cadd(HH(i, i), mu);
     }
     __syncthreads();
+    if (t == 0) status[0] = bad;
+    for (int i = t; i < n; i += 64) lam[i] = HH(i, i);
     // ---- eigenvectors of T (back substitution), b_i = Z y, unit norm ----
     double tn = 0.0;
-    for (long e = 0; e < (long)n * n; ++e) tn = fmax(tn, cabs_(H[e]));
+    for (long e = t; e < (long)n * n; e += 64) tn = fmax(tn, cabs_(H[e]));
+    for (int o = 32; o >= 1; o >>= 1) tn = fmax(tn, __shfl_xor(tn, o));
     const double small = fmax(tn, 1e-300) * 2.220446049250313e-16;
     for (int i = t; i < n; i += 64) {
         double2* y = Bv + (long)i * n;  // use the output column as scratch for y
@@ -274,8 +295,8 @@ __global__ __launch_bounds__(64) void small_eig_kernel(const double2* __restrict
     __syncthreads();
     for (int i = t; i < n; i += 64) {
         double2* y = Bv + (long)i * n;
-        // b = Z y, computed in place from the top (y_j = 0 for j > i)
-        // write into H's column i (T no longer needed) then copy back
+        // b = Z y, computed from the top (y_j = 0 for j > i), written into H's
+        // column i (T is no longer needed) and copied back scaled
         double nn = 0.0;
         for (int r = 0; r < n; ++r) {
             double2 s = make_double2(0.0, 0.0);
@@ -296,8 +317,9 @@ __global__ __launch_bounds__(64) void small_eig_kernel(const double2* __restrict
 hipError_t small_eig(hipStream_t st, const double2* A, int n, double2* H, double2* Z, double2* lam, double2* Bv,
                      int* status)
 {
-    if (n > 256) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(small_eig_kernel, dim3(1), dim3(64), 0, st, A, n, H, Z, lam, Bv, status);
+    if (n < 1 || n > SMALL_EIG_MAX) return hipErrorInvalidValue;
+    const size_t lds = (size_t)n * (2 * sizeof(double2) + sizeof(double));
+    hipLaunchKernelGGL(small_eig_kernel, dim3(1), dim3(64), lds, st, A, n, H, Z, lam, Bv, status);
     return hipGetLastError();
 }
 

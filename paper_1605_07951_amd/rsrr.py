@@ -28,6 +28,8 @@ RSRR_EDEVICE = 5
 RSRR_ENOTCONV = 6
 RSRR_ENAN = 7
 RSRR_ETIMEOUT = 8
+RSRR_ELIMIT = 9
+RSRR_WARN_MORE = 10
 RSRR_T_SEPARABLE = 0
 RSRR_T_HELMHOLTZ = 1
 RSRR_PREC_C128 = 0
@@ -35,12 +37,12 @@ RSRR_PREC_C64_IR = 1
 RSRR_PREC_R32_IR = 2
 
 STATUS_NAMES = {0: "OK", 1: "ESINGULAR", 2: "WARN_FALLBACK", 3: "WARN_GAP", 4: "ENOMEM", 5: "EDEVICE",
-                6: "ENOTCONV", 7: "ENAN", 8: "ETIMEOUT"}
+                6: "ENOTCONV", 7: "ENAN", 8: "ETIMEOUT", 9: "ELIMIT", 10: "WARN_MORE"}
 
 EXPORTS = ["rsrr_create", "rsrr_destroy", "rsrr_contour", "rsrr_sample", "rsrr_sample_batched", "rsrr_basis",
            "rsrr_project", "rsrr_solve", "rsrr_last_timings", "rsrr_update_stats", "rsrr_version",
            "rsrr_two_stage", "rsrr_moments", "rsrr_server_create", "rsrr_server_submit", "rsrr_server_wait", "rsrr_server_stats",
-           "rsrr_server_destroy", "rsrr_sample_gmres"]
+           "rsrr_server_destroy", "rsrr_sample_gmres", "rsrr_options_init", "rsrr_set_options", "rsrr_get_options"]
 RSRR_BATCH_GRAPH = 1
 RSRR_BATCH_AUTOTUNE = 2
 RSRR_SERVE_NO_BATCH = 1
@@ -75,7 +77,7 @@ class RsrrPointInfo(C.Structure):
 
 class RsrrSolveInfo(C.Structure):
     _fields_ = [("nbar", C.c_int), ("warn_gap", C.c_int), ("gmax", C.c_double), ("n_sigma", C.c_int),
-                ("pad", C.c_int)]
+                ("truncated", C.c_int)]
 
 
 class RsrrTwoStageInfo(C.Structure):
@@ -83,10 +85,19 @@ class RsrrTwoStageInfo(C.Structure):
                 ("nbar2", C.c_int), ("resid1_max", C.c_double)]
 
 
+class RsrrOptions(C.Structure):
+    _fields_ = [("size", C.c_ulonglong), ("version", C.c_int), ("ir_max_iters", C.c_int),
+                ("ir_max_iters_batched", C.c_int), ("basis_sketch_max", C.c_int), ("ir_tol", C.c_double),
+                ("fallback_resid", C.c_double), ("delta", C.c_double), ("tol_gap", C.c_double)]
+
+
+OPTION_FIELDS = [f for f, _ in RsrrOptions._fields_ if f not in ("size", "version")]
+
+
 class RsrrServerConfig(C.Structure):
     _fields_ = [("device", C.c_int), ("prec", C.c_int), ("max_slots", C.c_int), ("flags", C.c_int),
                 ("solvers", C.c_int), ("pad", C.c_int), ("arena_bytes", C.c_ulonglong),
-                ("batch_bytes", C.c_ulonglong)]
+                ("batch_bytes", C.c_ulonglong), ("options", C.POINTER(RsrrOptions))]
 
 
 class RsrrRequest(C.Structure):
@@ -153,6 +164,9 @@ def lib():
     L.rsrr_server_wait.argtypes = [vp, C.c_int, C.c_double, C.POINTER(RsrrResult)]
     L.rsrr_server_stats.argtypes = [vp, dp]
     L.rsrr_server_destroy.argtypes = [vp]
+    L.rsrr_options_init.argtypes = [C.POINTER(RsrrOptions)]
+    L.rsrr_set_options.argtypes = [vp, C.POINTER(RsrrOptions)]
+    L.rsrr_get_options.argtypes = [vp, C.POINTER(RsrrOptions)]
     L.rsrr_version.restype = C.c_char_p
     for f in EXPORTS:
         if f != "rsrr_version":
@@ -267,6 +281,35 @@ class Context:
         t = (C.c_double * 5)()
         _check("rsrr_last_timings", lib().rsrr_last_timings(self.h, t))
         return list(t)
+
+
+def rsrr_options(**kw):
+    """An rsrr_options struct: the library's defaults with the given fields changed."""
+    o = RsrrOptions()
+    _check("rsrr_options_init", lib().rsrr_options_init(C.byref(o)))
+    for f, v in kw.items():
+        if f not in OPTION_FIELDS:
+            raise KeyError(f)
+        setattr(o, f, v)
+    return o
+
+
+def rsrr_set_options(ctx, **kw):
+    """Change a context's options (rsrr_set_options); returns the options now in force."""
+    o = rsrr_get_options(ctx)
+    for f, v in kw.items():
+        if f not in OPTION_FIELDS:
+            raise KeyError(f)
+        setattr(o, f, v)
+    _check("rsrr_set_options", lib().rsrr_set_options(ctx.h, C.byref(o)))
+    return rsrr_get_options(ctx)
+
+
+def rsrr_get_options(ctx):
+    o = RsrrOptions()
+    o.size = C.sizeof(RsrrOptions)
+    _check("rsrr_get_options", lib().rsrr_get_options(ctx.h, C.byref(o)))
+    return o
 
 
 def rsrr_update_stats(ctx, enable=True, reset=False):
@@ -422,12 +465,12 @@ def rsrr_project(ctx, dnep, Q, k, gamma, radius, max_terms=64):
 
 
 def rsrr_solve(ctx, dnep, Q, k, AQ, terms, gamma, a, b, NQ=500, KQ=2, tol_gap=1e3, max_eigs=None,
-               ok=(RSRR_OK, RSRR_WARN_GAP)):
+               ok=(RSRR_OK, RSRR_WARN_GAP, RSRR_WARN_MORE)):
     """SS-FULL on the projected NEP and lift.  Returns dict with lam, V (host), resid, info, status."""
     torch = _torch()
     n = dnep.n
     ldq = Q.shape[1]
-    max_eigs = max_eigs or min(k * KQ, 512)
+    max_eigs = max_eigs or min(k * KQ, 1024)
     lam = (C.c_double * (2 * max_eigs))()
     V = torch.zeros((max_eigs, n), dtype=torch.complex128, device=Q.device)
     res = (C.c_double * max_eigs)()
@@ -445,6 +488,7 @@ def rsrr_solve(ctx, dnep, Q, k, AQ, terms, gamma, a, b, NQ=500, KQ=2, tol_gap=1e
     lam_np = np.frombuffer(lam, dtype=np.float64).view(np.complex128)[:m].copy()
     return {"lam": lam_np, "V": from_colmajor(V[:m], n), "resid": np.frombuffer(res, dtype=np.float64)[:m].copy(),
             "nbar": sinfo.nbar, "warn_gap": bool(sinfo.warn_gap), "gmax": sinfo.gmax,
+            "truncated": bool(sinfo.truncated),
             "sigma_H": np.frombuffer(sigH, dtype=np.float64)[:sinfo.n_sigma].copy(), "status": code}
 
 
@@ -505,10 +549,12 @@ class Server:
     buffer of a request alive until wait() has returned it."""
 
     def __init__(self, device=0, prec=RSRR_PREC_C64_IR, max_slots=8, arena_bytes=16 << 30,
-                 batch_bytes=24 << 30, flags=0, solvers=0):
+                 batch_bytes=24 << 30, flags=0, solvers=0, options=None):
         L = lib()
+        self._opt = options
         self.cfg = RsrrServerConfig(device, int(prec), int(max_slots), int(flags), int(solvers), 0,
-                                    int(arena_bytes), int(batch_bytes))
+                                    int(arena_bytes), int(batch_bytes),
+                                    C.pointer(options) if options is not None else None)
         self.h = C.c_void_p()
         _check("rsrr_server_create", L.rsrr_server_create(C.byref(self.h), C.byref(self.cfg)))
         self._live = {}

@@ -68,7 +68,7 @@ def test_argument_errors_without_device(lib):
 
 def test_server_argument_errors_without_device(lib):
     from paper_1605_07951_amd import rsrr
-    cfg = rsrr.RsrrServerConfig(0, 1, 0, 0, 0, 0, 1 << 20, 1 << 20)  # max_slots = 0
+    cfg = rsrr.RsrrServerConfig(0, 1, 0, 0, 0, 0, 1 << 20, 1 << 20, None)  # max_slots = 0
     h = C.c_void_p()
     assert lib.rsrr_server_create(None, C.byref(cfg)) == -1
     assert lib.rsrr_server_create(C.byref(h), None) == -2
@@ -91,13 +91,41 @@ def test_server_structs_match_header(lib):
     import subprocess
     import tempfile
     from paper_1605_07951_amd import rsrr
-    src = ('#include <stdio.h>\n#include "rsrr.h"\nint main(void){printf("%zu %zu %zu %zu %zu %zu\\n", '
+    src = ('#include <stdio.h>\n#include "rsrr.h"\nint main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", '
            'sizeof(rsrr_request), sizeof(rsrr_result), sizeof(rsrr_server_config), sizeof(rsrr_nep), '
-           'sizeof(rsrr_instance), sizeof(rsrr_gmres_info)); return 0;}\n')
+           'sizeof(rsrr_instance), sizeof(rsrr_gmres_info), sizeof(rsrr_options), sizeof(rsrr_solve_info), '
+           'sizeof(rsrr_point_info)); return 0;}\n')
     with tempfile.TemporaryDirectory() as d:
         cpath, exe = os.path.join(d, "sz.c"), os.path.join(d, "sz")
         open(cpath, "w").write(src)
         subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), cpath, "-o", exe], check=True)
         got = [int(x) for x in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
     assert got == [C.sizeof(rsrr.RsrrRequest), C.sizeof(rsrr.RsrrResult), C.sizeof(rsrr.RsrrServerConfig),
-                   C.sizeof(rsrr.RsrrNep), C.sizeof(rsrr.RsrrInstance), C.sizeof(rsrr.RsrrGmresInfo)]
+                   C.sizeof(rsrr.RsrrNep), C.sizeof(rsrr.RsrrInstance), C.sizeof(rsrr.RsrrGmresInfo),
+                   C.sizeof(rsrr.RsrrOptions), C.sizeof(rsrr.RsrrSolveInfo), C.sizeof(rsrr.RsrrPointInfo)]
+
+
+def test_options_struct_layout_and_defaults(lib):
+    """rsrr_options: every field at the offset the header gives it, size first, and the defaults
+    that rsrr_options_init writes; a NULL struct is refused."""
+    import subprocess
+    import tempfile
+    from paper_1605_07951_amd import rsrr
+    fields = [f for f, _ in rsrr.RsrrOptions._fields_]
+    body = " ".join(f'printf("%zu ", offsetof(rsrr_options, {f}));' for f in fields)
+    src = ('#include <stdio.h>\n#include <stddef.h>\n#include "rsrr.h"\n'
+           'int main(void){' + body + ' printf("%d\\n", RSRR_OPTIONS_VERSION); return 0;}\n')
+    with tempfile.TemporaryDirectory() as d:
+        cpath, exe = os.path.join(d, "off.c"), os.path.join(d, "off")
+        open(cpath, "w").write(src)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), cpath, "-o", exe], check=True)
+        got = [int(x) for x in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
+    assert got[:-1] == [getattr(rsrr.RsrrOptions, f).offset for f in fields]
+    assert fields[0] == "size"
+    o = rsrr.rsrr_options()
+    assert o.size == C.sizeof(rsrr.RsrrOptions) and o.version == got[-1] == 1
+    assert (o.ir_max_iters, o.ir_max_iters_batched, o.basis_sketch_max) == (10, 3, 1024)
+    assert (o.ir_tol, o.fallback_resid, o.delta, o.tol_gap) == (4.0, 1e-10, 1e-14, 1e3)
+    assert lib.rsrr_options_init(None) == -1
+    assert lib.rsrr_set_options(None, C.byref(o)) == -1
+    assert lib.rsrr_get_options(None, C.byref(o)) == -1

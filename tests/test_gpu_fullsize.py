@@ -153,3 +153,104 @@ def test_gmres_full_size_sampled_points(R, ctx):
         assert inf == 0
         err = np.linalg.norm(X - Xo, axis=0) / np.linalg.norm(Xo, axis=0)
         assert np.all(err <= 2.0 * res / rcond + 1e-13), (k, err, res, 1 / rcond)
+
+
+def _clusters(lo, tol_rel=1e-3):
+    out, seen = [], np.zeros(lo.size, bool)
+    for i in range(lo.size):
+        if seen[i]:
+            continue
+        cl = np.where(np.abs(lo - lo[i]) <= tol_rel * max(1.0, abs(lo[i])))[0]
+        seen[cl] = True
+        out.append(cl)
+    return out
+
+
+def test_headline_eigenpairs_match_the_oracle(R, ctx, headline):
+    """Helmholtz n = 4096, N = 64, L = 64 (mixed precision, the bench's launch), Steps 3-5 against
+    the oracle's RSRR on the same inputs (tests/golden/helmholtz_n4096_N64_L64.json, written by
+    make_helmholtz_n4096.py from oracle/ only): eigenvalues inside within 1e-9 (relative), the
+    gap count, k within the rounding band at delta (reading: counts near delta*sigma_1 may move),
+    singular values of S within 1e-13 sigma_1 where the sketch resolved them, eigenvector cosines
+    (per cluster of eigenvalues within 1e-3) >= 1 - 1e-9, residuals <= 1e-10."""
+    import json
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    g = json.load(open(os.path.join(here, "helmholtz_n4096_N64_L64.json")))
+    Vo = np.load(os.path.join(here, "helmholtz_n4096_N64_L64_V.npz"))["V"]
+    lo = np.array([complex(a, b) for a, b in g["lam_inside"]])
+    nep, C, U, dnep, z, S, info, code = headline
+    n = nep.points.shape[0]
+    Q, k, sig = R.rsrr_basis(ctx, S.clone(), n, 1e-14)
+    so = np.array(g["sigma_S_leading"])
+    assert abs(k - g["k"]) <= 8
+    r = min(int(np.sum(sig > 0)), k - 8)
+    assert np.max(np.abs(sig[:r] - so[:r])) <= 1e-13 * so[0]
+    AQ, terms = R.rsrr_project(ctx, dnep, Q, k, C.gamma, max(C.a, C.b))
+    out = R.rsrr_solve(ctx, dnep, Q, k, AQ, terms, C.gamma, C.a, C.b)
+    assert out["nbar"] == g["nbar"]
+    ins = O.level(out["lam"], C.gamma, C.a, C.b) < 1
+    lam, V = out["lam"][ins], out["V"][:, ins]
+    assert lam.size == lo.size == 4
+    assert _match_rel(lam, lo) < 1e-9 and _match_rel(lo, lam) < 1e-9
+    for cl in _clusters(lo):
+        gsel = np.array([int(np.argmin(np.abs(lam - lo[i]))) for i in cl])
+        assert np.unique(gsel).size == cl.size
+        qa = np.linalg.qr(V[:, gsel])[0]
+        qb = np.linalg.qr(Vo[:, cl])[0]
+        cos = np.linalg.svd(qa.conj().T @ qb, compute_uv=False).min()
+        assert cos >= 1 - 1e-9, (lo[cl], 1 - cos)
+    assert out["resid"][ins].max() <= 1e-10
+
+
+def _match_rel(got, ref):
+    return max(np.min(np.abs(ref - x)) / max(1.0, abs(x)) for x in got)
+
+
+def test_delay_parity_config_32x32(R, ctx):
+    """Config 1' at its stated size: delay Laplacian 32 x 32 (n = 1024), parity circle (-4, 0.75),
+    N = 48, L = 32, mixed precision; the three eigenvalues inside against Lambert W to 1e-9 and
+    eigen-residuals recomputed on the CPU."""
+    from oracle import pins as P
+    nep, C, U = W.cfg_delay(nx=32, N=48, L=32)
+    dnep = R.DeviceNEP(nep)
+    z, _ = R.rsrr_contour(C.gamma, C.a, C.b, C.N)
+    S, info, code = R.rsrr_sample(ctx, dnep, z, U, prec=1)
+    assert code == R.RSRR_OK and all(i["resid"] <= 1e-10 for i in info)
+    Q, k, _ = R.rsrr_basis(ctx, S, 1024, 1e-14)
+    AQ, terms = R.rsrr_project(ctx, dnep, Q, k, C.gamma, max(C.a, C.b))
+    out = R.rsrr_solve(ctx, dnep, Q, k, AQ, terms, C.gamma, C.a, C.b)
+    ex = P.delay_eigs(W.laplacian_modes(32, 32))
+    exin = ex[O.level(ex, C.gamma, C.a, C.b) < 1]
+    ins = O.level(out["lam"], C.gamma, C.a, C.b) < 0.98
+    assert exin.size == 3 and ins.sum() == 3
+    assert _match_rel(out["lam"][ins], exin) < 1e-9 and _match_rel(exin, out["lam"][ins]) < 1e-9
+    prob = O.Problem(nep)
+    for i in np.where(ins)[0]:
+        assert O.residual(prob, out["lam"][i], out["V"][:, i]) <= 1e-10
+
+
+def test_sketch_narrower_than_S_matches_full_svd(R, ctx):
+    """Helmholtz n = 2048, N = 48, L = 32: NL = 1536 is wider than the first sketch (1024
+    columns).  Singular values of the normalised S within 1e-13 sigma_1 of the oracle's full SVD
+    where resolved, k within the rounding band, and the leading subspace (to the largest gap)
+    within 100x Wedin's bound of the oracle's."""
+    nep, C, U = W.cfg_helmholtz(n=2048, N=48, L=32)
+    dnep = R.DeviceNEP(nep)
+    z, _ = R.rsrr_contour(C.gamma, C.a, C.b, C.N)
+    S, info, code = R.rsrr_sample(ctx, dnep, z, U, prec=1)
+    assert code == R.RSRR_OK
+    Sh = R.from_colmajor(S, 2048)
+    Q, k, sig = R.rsrr_basis(ctx, S, 2048, 1e-14)
+    Qo, sigo, ko = O.basis(O.normalize(Sh), 1e-14)
+    assert abs(k - ko) <= 8
+    r = min(int(np.sum(sig > 0)), k - 8)
+    assert np.max(np.abs(sig[:r] - sigo[:r])) <= 1e-13 * sigo[0]
+    # leading subspace up to the largest relative gap among sigma > 1e-6 sigma_1, against 100x
+    # Wedin's bound eps sigma_1 / gap (the subspace is fixed only to that accuracy)
+    cand = np.where(sigo[:k] > 1e-6 * sigo[0])[0]
+    j = int(cand[np.argmax(sigo[cand] / sigo[cand + 1])])
+    bound = 100 * 2.22e-16 * sigo[0] / (sigo[j] - sigo[j + 1])
+    Qh = R.from_colmajor(Q[:k], 2048)
+    A = Qo[:, :j + 1]
+    assert np.linalg.norm(A - Qh @ (Qh.conj().T @ A), 2) <= max(bound, 1e-13)

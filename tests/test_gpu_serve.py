@@ -53,11 +53,20 @@ def test_serve_requests_meet_parity(R):
         nep, C, U = W.cfg_delay(nx=16, N=48, L=32)
         reqs.append(("delay", nep, C, srv.submit(R.DeviceNEP(nep), R.colmajor(U)[0], C.gamma, C.a, C.b, C.N,
                                                  max_eigs=32, want_V=True)))
+        hn, hC, hU = W.cfg_helmholtz(n=300, N=32, L=16)
+        reqs.append(("helmholtz", hn, hC, srv.submit(R.DeviceNEP(hn), R.colmajor(hU)[0], hC.gamma, hC.a, hC.b,
+                                                     hC.N, max_eigs=32, NQ=200, want_V=True)))
         for kind, nep, C, rid in reqs:
             res = srv.wait(rid, timeout=120.0)
             prob = O.Problem(nep)
             if kind == "qep":
                 _check_qep(res, nep, C)
+            elif kind == "helmholtz":
+                ro = O.rsrr(prob, C, hU, NQ=200)
+                oin = ro["lam"][ro["level"] < 0.98]
+                ins = O.level(res["lam"], C.gamma, C.a, C.b) < 0.98
+                assert res["status"] == 0 and ins.sum() == oin.size == 4
+                assert _match(res["lam"][ins], oin) < 1e-9 and _match(oin, res["lam"][ins]) < 1e-9
             else:
                 ex = P.delay_eigs(W.laplacian_modes(16, 16))
                 exin = ex[O.level(ex, C.gamma, C.a, C.b) < 1]
@@ -70,7 +79,7 @@ def test_serve_requests_meet_parity(R):
                 assert O.residual(prob, res["lam"][i], res["V"][:, i]) <= 1e-10
             assert res["t_submit"] <= res["t_admit"] <= res["t_sampled"] <= res["t_done"]
         st = srv.stats()
-        assert st["finished"] == 3 and st["points"] == 32 + 32 + 48
+        assert st["finished"] == 4 and st["points"] == 32 + 32 + 48 + 32
     finally:
         srv.close()
 
