@@ -394,6 +394,20 @@ RSRR_API rsrr_status rsrr_sample_batched(rsrr_ctx *ctx, int count, const rsrr_in
 RSRR_API rsrr_status rsrr_moments(rsrr_ctx *ctx, int n, int N, int L, const double *S, int lds, const double *z,
                                   const double *gamma, double rho, double capacity, int K, double *M, int ldm);
 
+/* rsrr_moments without any device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and errors as
+ * rsrr_moments; the points and the N x K coefficient table live in a static
+ * per-GPU scratch array of 65536 complex entries (1 MiB, held by each GPU the
+ * library runs on until the process ends) instead of context workspace.
+ * Limit: N + N*K <= 65536, else RSRR_ELIMIT with nothing enqueued.  Every
+ * call on one GPU shares that GPU's array: calls that overlap on one GPU (two
+ * contexts or streams at once) race; a call has finished with it when it
+ * returns (the call synchronises its stream). */
+RSRR_API rsrr_status rsrr_moments_noalloc(rsrr_ctx *ctx, int n, int N, int L, const double *S, int lds,
+                                          const double *z, const double *gamma, double rho, double capacity,
+                                          int K, double *M, int ldm);
+
 /* Diagnostics of rsrr_two_stage. */
 typedef struct {
     int k1, count1, nbar1;   /* stage 1: rank of S, eigenvalues returned, SS-FULL count   */

@@ -82,6 +82,10 @@ rsrr_status rsrr_create(rsrr_ctx** ctx, int device, void* stream)
         delete c;
         return RSRR_EDEVICE;
     }
+    if (noalloc_scratch_setup(device, &c->noalloc_scratch) != RSRR_OK) {
+        rsrr_destroy(c);
+        return RSRR_EDEVICE;
+    }
     *ctx = c;
     return RSRR_OK;
 }

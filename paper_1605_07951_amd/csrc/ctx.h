@@ -42,6 +42,7 @@ struct rsrr_ctx {
     double delta = 1e-14;           // library-chosen rank truncation (server)
     double tol_gap = 1e3;           // library-chosen gap threshold (server)
     size_t ws_budget = 0;  // bytes for the per-point sampling buffers (0 = half of free memory)
+    void* noalloc_scratch = nullptr;  // this device's address of the no-allocation scratch array
     // trailing-update statistics (rsrr_update_stats)
     bool rec_on = false;
     rsrr::UpdateRecorder rec;
@@ -67,6 +68,10 @@ rsrr_status assemble_c128(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, int B, 
 // One-sided Jacobi SVD (api_basis): see jacobi_round.  Returns sweeps or -1.
 int jacobi_svd(rsrr_ctx* c, double2* A, int lda, int m, int m_apply, int p, int max_sweeps, double tol,
                rsrr_status* st);
+
+// Device address of the no-allocation scratch array on `device` (the current
+// device), looked up once per device.
+rsrr_status noalloc_scratch_setup(int device, void** out);
 
 // f(z) = c (z - z0)^p exp(-tau z) / (z - s)^q
 zd term_eval(const rsrr_term& t, zd z);

@@ -42,7 +42,8 @@ STATUS_NAMES = {0: "OK", 1: "ESINGULAR", 2: "WARN_FALLBACK", 3: "WARN_GAP", 4: "
 EXPORTS = ["rsrr_create", "rsrr_destroy", "rsrr_contour", "rsrr_sample", "rsrr_sample_batched", "rsrr_basis",
            "rsrr_project", "rsrr_solve", "rsrr_last_timings", "rsrr_update_stats", "rsrr_version",
            "rsrr_two_stage", "rsrr_moments", "rsrr_server_create", "rsrr_server_submit", "rsrr_server_wait", "rsrr_server_stats",
-           "rsrr_server_destroy", "rsrr_sample_gmres", "rsrr_options_init", "rsrr_set_options", "rsrr_get_options"]
+           "rsrr_server_destroy", "rsrr_sample_gmres", "rsrr_options_init", "rsrr_set_options", "rsrr_get_options",
+           "rsrr_moments_noalloc"]
 RSRR_BATCH_GRAPH = 1
 RSRR_BATCH_AUTOTUNE = 2
 RSRR_SERVE_NO_BATCH = 1
@@ -159,6 +160,7 @@ def lib():
                                  dp, vp, C.c_int, dp, ip, dp, C.POINTER(RsrrTwoStageInfo)]
     L.rsrr_moments.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp, C.c_int, dp, dp, C.c_double, C.c_double, C.c_int,
                                vp, C.c_int]
+    L.rsrr_moments_noalloc.argtypes = L.rsrr_moments.argtypes
     L.rsrr_server_create.argtypes = [C.POINTER(vp), C.POINTER(RsrrServerConfig)]
     L.rsrr_server_submit.argtypes = [vp, C.POINTER(RsrrRequest), ip]
     L.rsrr_server_wait.argtypes = [vp, C.c_int, C.c_double, C.POINTER(RsrrResult)]
@@ -533,6 +535,17 @@ def rsrr_moments(ctx, S, n, z, L, K, gamma, rho, capacity):
     g = (C.c_double * 2)(complex(gamma).real, complex(gamma).imag)
     _check("rsrr_moments", lib().rsrr_moments(ctx.h, n, N, L, S.data_ptr(), S.shape[1], zp, g, float(rho),
                                               float(capacity), int(K), M.data_ptr(), n))
+    return M
+
+
+def rsrr_moments_noalloc(ctx, S, n, z, L, K, gamma, rho, capacity, M):
+    """rsrr_moments into a caller-provided device tensor M ((K*L, n), column-major n x K*L),
+    with no device allocation by the library."""
+    zc, zp = _zbuf(z)
+    g = (C.c_double * 2)(complex(gamma).real, complex(gamma).imag)
+    _check("rsrr_moments_noalloc", lib().rsrr_moments_noalloc(ctx.h, n, zc.size, L, S.data_ptr(), S.shape[1], zp, g,
+                                                              float(rho), float(capacity), int(K), M.data_ptr(),
+                                                              M.shape[1]))
     return M
 
 
