@@ -442,16 +442,37 @@ RSRR_API rsrr_status rsrr_two_stage(rsrr_ctx *ctx, const rsrr_nep *nep, const do
  *
  * Each request is the whole method of Sec. 4.3 for one NEP: contour nodes
  * (eq. ellip-contour-xw), resolvent sampling (Step 2), basis (Step 3),
- * projection and SS-FULL (Steps 4-5).  A request is admitted when a slot is
- * free and its S block (16 n N L bytes) fits in the server's HBM arena
- * (first come, first served).  The sampling points of every admitted request
- * are batched together: each sampling launch takes points from all admitted
+ * projection and SS-FULL (Steps 4-5).
+ *
+ * Admission by footprint.  A request is admitted when a slot is free and its
+ * whole per-request device footprint fits in the server's HBM arena (first
+ * come, first served): S (16 n N (L + L_extra) bytes), its LU factors kept on
+ * the device (complex FP32 or FP64 factors of every point, P x P with P = n
+ * rounded up to 64, plus interchanges and diagonal-block inverses), the basis
+ * Q (16 n min(n, N (L + L_extra)) bytes) and the eigenvectors V (16 n max_eigs
+ * bytes); rsrr_server_footprint gives the figure.  What is not per request is
+ * fixed at creation: the sampling launches' buffers (batch_bytes, trimmed back
+ * after a launch that needed more) and each solve thread's budget solve_bytes
+ * (projected matrices, the chunked phases of Steps 3-5 and the solves of a
+ * re-probe), so device use is bounded by arena_bytes + batch_bytes +
+ * solvers * solve_bytes plus the caller's own inputs.
+ *
+ * Continuous batching.  The sampling points of every admitted request are
+ * batched together: each sampling launch takes points from all admitted
  * requests in admission order, up to batch_bytes of LU workspace, grouped by
  * (n rounded up to 64, L), so points that arrive while others are on the GPU
  * join the next launch.  Solve threads, each with its own stream, run basis,
  * projection and SS-FULL of requests whose sampling has finished, overlapping
- * each other and the next sampling launches on the device.  The factors of a launch stay in
- * HBM from factorisation through refinement and the FP64 fallback.
+ * each other and the next sampling launches on the device.
+ *
+ * Kept factors and re-probes.  A request's factors stay in its arena block
+ * from factorisation until it finishes.  When SS-FULL's gap test fails
+ * (g_max < tol_gap, eq. gap) or an eigenpair inside the contour has residual
+ * above 1e-10, the paper's remedy is more probe columns (Sec. 3.3): the
+ * request's L_extra reserve columns of U are then solved with the kept
+ * factors (triangular solves and refinement only, no refactorisation),
+ * appended to S, and Steps 3-5 run again on all N (L + L_extra) columns.
+ *
  * Per-point work (tile shapes, panel width, refinement) depends only on
  * (n, L, precision), never on what else is in the launch, so a request's
  * results do not depend on the mix it ran in.
@@ -465,8 +486,9 @@ typedef struct {
     int flags;                /* RSRR_SERVE_*                                               */
     int solvers;              /* solve threads, each with its own stream (0: 2; at most 8)  */
     int pad;
-    unsigned long long arena_bytes;  /* HBM for the admitted requests' S blocks            */
-    unsigned long long batch_bytes;  /* HBM cap of one sampling launch's LU workspace      */
+    unsigned long long arena_bytes;  /* HBM for the admitted requests' footprints           */
+    unsigned long long batch_bytes;  /* HBM cap of one sampling launch's LU workspace       */
+    unsigned long long solve_bytes;  /* HBM budget of each solve thread (0: 4 GiB)          */
     const rsrr_options *options;     /* options of every context of the server (NULL: defaults);
                                         read at creation                                     */
 } rsrr_server_config;
@@ -477,12 +499,13 @@ enum {
                                  sampling launches, on the sampling stream                */
 };
 
-/* One request.  nep device data, U (device, n x L, ldu >= n) and the host
- * output arrays stay owned by the caller and must stay valid until
+/* One request.  nep device data, U (device, n x (L + L_extra), ldu >= n) and
+ * the host output arrays stay owned by the caller and must stay valid until
  * rsrr_server_wait has returned this request.  Outputs: lambda (host,
  * 2*max_eigs doubles), resid (host, max_eigs; ||T(lambda)v|| / (||T(lambda)||_1
  * ||v||)), V (host, n x max_eigs column-major with ld n, unit 2-norm columns;
- * may be NULL). */
+ * may be NULL).  The first L columns of U are the probes; the L_extra after
+ * them are solved only on a re-probe. */
 typedef struct {
     rsrr_nep nep;
     double gamma_re, gamma_im;   /* ellipse centre */
@@ -493,11 +516,13 @@ typedef struct {
     int ldu;
     int NQ;                      /* SS-FULL quadrature nodes (0: 500)  */
     int KQ;                      /* SS-FULL moment blocks (0: 2)       */
-    double delta;                /* rank truncation (0: 1e-14)         */
+    double delta;                /* rank truncation (0: the options' delta, 1e-14) */
     int max_eigs;
     double *lambda;
     double *resid;
     double *V;
+    int L_extra;                 /* reserve probe columns for a re-probe (>= 0) */
+    int pad;
 } rsrr_request;
 
 /* Result of one request; times are seconds on the server's steady clock
@@ -513,16 +538,26 @@ typedef struct {
     int launches;                /* sampling launches that carried this request's points */
     double sample_resid_max;     /* max relative residual of the refined solves          */
     double t_submit, t_admit, t_sampled, t_done;
+    int reprobes;                /* re-probes (0 or 1) solved from the kept factors      */
+    int L_used;                  /* probe columns in the final S (L or L + L_extra)      */
+    unsigned long long footprint;  /* bytes of the request's arena block                  */
 } rsrr_result;
 
+/* Per-request device footprint (bytes) that admission charges against the
+ * arena for request req on a server configured by cfg (host computation).
+ * Errors: -1 cfg NULL, -2 req NULL or invalid, -3 bytes NULL. */
+RSRR_API rsrr_status rsrr_server_footprint(const rsrr_server_config *cfg, const rsrr_request *req,
+                                           unsigned long long *bytes);
+
 /* Create a server (a sampling thread and cfg->solvers solve threads, each on
- * its own non-blocking stream on cfg->device) and allocate its arena.  Errors: -1 srv NULL, -2 cfg invalid,
+ * its own non-blocking stream on cfg->device) and allocate its arena.  Errors:
+ * -1 srv NULL, -2 cfg invalid (or its options refused by rsrr_set_options),
  * RSRR_ENOMEM, RSRR_EDEVICE. */
 RSRR_API rsrr_status rsrr_server_create(rsrr_server **srv, const rsrr_server_config *cfg);
 
 /* Queue a request (thread safe, does not block on the GPU).  *id receives its
- * id.  Errors: -1 srv, -2 request invalid, -3 id NULL; RSRR_ENOMEM when its S
- * block alone exceeds the arena. */
+ * id.  Errors: -1 srv, -2 request invalid, -3 id NULL; RSRR_ENOMEM when its
+ * footprint alone exceeds the arena. */
 RSRR_API rsrr_status rsrr_server_submit(rsrr_server *srv, const rsrr_request *req, int *id);
 
 /* Wait until request id has finished (timeout_s < 0: no limit) and fill out.
@@ -530,11 +565,12 @@ RSRR_API rsrr_status rsrr_server_submit(rsrr_server *srv, const rsrr_request *re
  * RSRR_ETIMEOUT. */
 RSRR_API rsrr_status rsrr_server_wait(rsrr_server *srv, int id, double timeout_s, rsrr_result *out);
 
-/* Server counters (host, 10 doubles): requests finished, points sampled,
+/* Server counters (host, 12 doubles): requests finished, points factored,
  * sampling launches, arena bytes in use at peak, largest launch (points),
- * seconds the sampling thread was busy, seconds the solve thread was busy,
- * peak device memory in use (bytes, from hipMemGetInfo), current server
- * time, requests waiting for admission.  Errors: -1 srv, -2 out NULL. */
+ * seconds the sampling thread was busy, seconds the solve threads were busy,
+ * peak device memory in use (bytes, from hipMemGetInfo), current server time,
+ * requests waiting for admission, points solved again from kept factors
+ * (re-probes), re-probes.  Errors: -1 srv, -2 out NULL. */
 RSRR_API rsrr_status rsrr_server_stats(rsrr_server *srv, double *out);
 
 /* Finish every submitted request, stop the threads and free the server.

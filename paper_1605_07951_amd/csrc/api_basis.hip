@@ -250,7 +250,8 @@ extern "C" rsrr_status rsrr_project(rsrr_ctx* c, const rsrr_nep* nep, const doub
         const size_t per = (size_t)n * n * 16 + (size_t)n * k * 16;
         size_t fr = 0, tot = 0;
         RSRR_HIP(hipMemGetInfo(&fr, &tot));
-        const size_t budget = std::min<size_t>(fr / 4, (size_t)8 << 30);
+        size_t budget = std::min<size_t>(fr / 4, (size_t)8 << 30);
+        if (c->ws_budget) budget = std::min(budget, c->ws_budget);
         const int G = (int)std::max<size_t>(1, std::min<size_t>((size_t)P, budget / per));
         double2* Tp = (double2*)ws_get(c, WS_B0, (size_t)G * n * n * 16);
         double2* W = (double2*)ws_get(c, WS_B1, (size_t)G * n * k * 16);

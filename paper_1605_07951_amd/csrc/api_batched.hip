@@ -132,16 +132,32 @@ struct BucketBufs {
     long sT, sU, sP, sPerm, sTP, sInv, sTmp, sPair;
 };
 
+// Strides of one point's factor data in the bucket buffers and in a FactorStore.
+long bucket_sPerm(int P) { return (long)perm_panels(P) * 2 * MAX_NB; }
+long bucket_sInv(int P, bool mixed) { return mixed ? 2L * max_panel<float>() * (P + max_panel<float>()) : 0; }
+
 // Everything a bucket does on the device, in stream order (capturable).
+// keep (may be null): per entry of ids, the store that receives that instance's
+// factors (null: none) at point keep_k0[q].  from (may be null): the bucket is one
+// instance whose factors are already in this store from point from_k0: no
+// complex FP32 assembly and no factorisation.
 rsrr_status run_bucket(rsrr_ctx* c, hipStream_t sm, const rsrr_instance* inst, const std::vector<int>& ids,
                        const std::vector<long>& off, int P, int Lmax, long M, int prec, int nb, BucketBufs& b,
-                       const double2* coef_host, const int* nk_host, int maxit)
+                       const double2* coef_host, const int* nk_host, int maxit, FactorStore* const* keep = nullptr,
+                       const int* keep_k0 = nullptr, const FactorStore* from = nullptr, int from_k0 = 0)
 {
     const bool mixed = prec == RSRR_PREC_C64_IR;
+    const size_t esz = mixed ? 8 : 16;
+    if (from) {
+        // the kept factors stand in for the bucket's factor buffers
+        b.T = (char*)from->T + (size_t)from_k0 * from->sT * esz;
+        b.perm = from->perm + (size_t)from_k0 * from->sPerm;
+        b.inv = mixed ? (void*)((char*)from->inv + (size_t)from_k0 * from->sInv * 8) : nullptr;
+    }
     // per-matrix sizes and the identity padding
     RSRR_HIP(hipMemcpyAsync(b.nk, nk_host, (size_t)M * 4, hipMemcpyHostToDevice, sm));
-    RSRR_HIP(pad_identity(sm, mixed ? (float2*)b.T : nullptr, b.T128, P, b.sT, P, b.nk, (int)M));
-    if (!mixed) RSRR_HIP(pad_identity(sm, nullptr, (double2*)b.T, P, b.sT, P, b.nk, (int)M));
+    RSRR_HIP(pad_identity(sm, mixed && !from ? (float2*)b.T : nullptr, b.T128, P, b.sT, P, b.nk, (int)M));
+    if (!mixed && !from) RSRR_HIP(pad_identity(sm, nullptr, (double2*)b.T, P, b.sT, P, b.nk, (int)M));
     // assembly of every instance's points (FP64 sums, c64 and c128 copies)
     long coff = 0;
     for (size_t q = 0; q < ids.size(); ++q) {
@@ -152,18 +168,18 @@ rsrr_status run_bucket(rsrr_ctx* c, hipStream_t sm, const rsrr_instance* inst, c
             const long cnt = (long)in.nep.J * in.N;
             RSRR_HIP(hipMemcpyAsync(b.coef + coff, coef_host + coff, (size_t)cnt * 16, hipMemcpyHostToDevice, sm));
             RSRR_HIP(assemble_separable(sm, n, in.nep.J, (const double2*)in.nep.A, in.nep.lda, b.coef + coff, in.N,
-                                        mixed ? (float2*)b.T + off[q] * b.sT : nullptr, P, b.sT,
+                                        mixed && !from ? (float2*)b.T + off[q] * b.sT : nullptr, P, b.sT,
                                         b.T128 + off[q] * b.sT, P, b.sT, b.frobp + off[q] * nparts, b.frob + off[q]));
             coff += cnt;
         } else {
             const long cnt = in.N;
             RSRR_HIP(hipMemcpyAsync(b.coef + coff, coef_host + coff, (size_t)cnt * 16, hipMemcpyHostToDevice, sm));
             RSRR_HIP(assemble_helmholtz(sm, n, in.nep.points, in.nep.w, b.coef + coff, in.N,
-                                        mixed ? (float2*)b.T + off[q] * b.sT : nullptr, P, b.sT,
+                                        mixed && !from ? (float2*)b.T + off[q] * b.sT : nullptr, P, b.sT,
                                         b.T128 + off[q] * b.sT, P, b.sT, b.frobp + off[q] * nparts, b.frob + off[q]));
             coff += cnt;
         }
-        if (!mixed)
+        if (!mixed && !from)
             RSRR_HIP(copy_c128(sm, n, n, b.T128 + off[q] * b.sT, P, b.sT, (double2*)b.T + off[q] * b.sT, P, b.sT,
                                in.N));
     }
@@ -180,8 +196,10 @@ rsrr_status run_bucket(rsrr_ctx* c, hipStream_t sm, const rsrr_instance* inst, c
     w.ipiv = b.ipiv; w.sP = b.sP; w.perm = b.perm; w.sPerm = b.sPerm; w.tperm = b.tperm; w.sTP = b.sTP;
     w.info = b.info; w.inv = b.inv; w.sInv = b.sInv; w.tmp = b.tmp; w.sTmp = b.sTmp;
     w.pair = b.pair; w.sPair = b.sPair; w.ldpair = P;
-    if (mixed) RSRR_HIP(getrf_batched<float>(sm, (float2*)b.T, b.sT, P, P, nb, w, (int)M));
-    else RSRR_HIP(getrf_batched<double>(sm, (double2*)b.T, b.sT, P, P, nb, w, (int)M));
+    if (!from) {
+        if (mixed) RSRR_HIP(getrf_batched<float>(sm, (float2*)b.T, b.sT, P, P, nb, w, (int)M));
+        else RSRR_HIP(getrf_batched<double>(sm, (double2*)b.T, b.sT, P, P, nb, w, (int)M));
+    }
     RSRR_HIP(ir_init(sm, (int)M, b.info, b.active, b.prev, b.resid, b.iters));
     w.active = b.active;
     // first solve
@@ -220,6 +238,21 @@ rsrr_status run_bucket(rsrr_ctx* c, hipStream_t sm, const rsrr_instance* inst, c
         RSRR_HIP(copy_c128(sm, in.nep.n, in.L, b.Xb + off[q] * b.sU, P, b.sU, (double2*)in.S, in.lds,
                            (long)in.L * in.lds, in.N));
     }
+    // factors kept on the device for later solves (same strides in the store)
+    for (size_t q = 0; keep && q < ids.size(); ++q) {
+        FactorStore* fs = keep[q];
+        if (!fs) continue;
+        const long cnt = off[q + 1] - off[q];
+        const size_t k0 = (size_t)keep_k0[q];
+        RSRR_HIP(hipMemcpyAsync((char*)fs->T + k0 * fs->sT * esz, (const char*)b.T + (size_t)off[q] * b.sT * esz,
+                                (size_t)cnt * b.sT * esz, hipMemcpyDeviceToDevice, sm));
+        RSRR_HIP(hipMemcpyAsync(fs->perm + k0 * fs->sPerm, b.perm + (size_t)off[q] * b.sPerm,
+                                (size_t)cnt * b.sPerm * 8, hipMemcpyDeviceToDevice, sm));
+        if (mixed)
+            RSRR_HIP(hipMemcpyAsync((char*)fs->inv + k0 * fs->sInv * 8, (const char*)b.inv + (size_t)off[q] * b.sInv * 8,
+                                    (size_t)cnt * b.sInv * 8, hipMemcpyDeviceToDevice, sm));
+        fs->nb = nb;
+    }
     return RSRR_OK;
 }
 
@@ -242,13 +275,132 @@ void batched_release(rsrr_ctx* c)
     m.erase(it);
 }
 
-extern "C" rsrr_status rsrr_sample_batched(rsrr_ctx* c, int count, const rsrr_instance* inst, int prec, int flags,
-                                           rsrr_point_info* info)
+namespace {
+
+// Host tables of one bucket: per-matrix n and the coefficient (separable) or point
+// (Helmholtz) table of every instance, in bucket order.
+void bucket_tables(const rsrr_instance* inst, const std::vector<int>& ids, const std::vector<long>& off,
+                   std::vector<int>& nk, std::vector<double2>& coef)
 {
-    if (!c) return -1;
-    if (count < 1) return -2;
-    if (!inst) return -3;
-    if (prec != RSRR_PREC_C128 && prec != RSRR_PREC_C64_IR) return -4;
+    nk.assign(off.back(), 0);
+    coef.clear();
+    for (size_t q = 0; q < ids.size(); ++q) {
+        const rsrr_instance& in = inst[ids[q]];
+        for (long k = off[q]; k < off[q + 1]; ++k) nk[k] = in.nep.n;
+        if (in.nep.kind == RSRR_T_SEPARABLE) {
+            for (int j = 0; j < in.nep.J; ++j)
+                for (int k = 0; k < in.N; ++k) {
+                    const zd f = term_eval(in.nep.terms[j], zd(in.z[2 * k], in.z[2 * k + 1]));
+                    coef.push_back(make_double2(f.real(), f.imag()));
+                }
+        } else {
+            for (int k = 0; k < in.N; ++k) coef.push_back(make_double2(in.z[2 * k], in.z[2 * k + 1]));
+        }
+    }
+}
+
+// The buffers of one bucket of M padded P x P matrices with Lmax right-hand sides,
+// from the context's slots of bucket size P (with `from`, no factor buffers).
+rsrr_status bucket_bufs(BatchedState& S, hipStream_t sm, int P, int Lmax, long M, int maxn, size_t ncoef, bool mixed,
+                        bool from, BucketBufs& b)
+{
+    const int nbmax = mixed ? max_panel<float>() : max_panel<double>();
+    b = BucketBufs{};
+    b.sT = (long)P * P;
+    b.sU = (long)P * Lmax;
+    b.sP = P;
+    b.sPerm = bucket_sPerm(P);
+    b.sTP = 8L * 2 * MAX_NB;
+    // ceil(P/nb) panels of 2 nb^2 for any nb <= nbmax: at most 2 nbmax (P + nbmax)
+    b.sInv = bucket_sInv(P, mixed);
+    b.sTmp = mixed ? (long)nbmax * std::max(P, Lmax) : 0;
+    b.sPair = mixed ? lu_pair_elems(P, nbmax, P) : 0;
+    const size_t esz = mixed ? 8 : 16;
+    const long nparts_max = ((long)maxn * maxn + 255) / 256;
+    // every bucket size has its own buffers (graphs keep pointing at them, and the
+    // buckets of one call run side by side)
+    int s = (P / BUCKET) * 32;
+    b.T = from ? (void*)(s++, nullptr) : bget(S, s++, (size_t)M * b.sT * esz, sm);
+    b.T128 = (double2*)bget(S, s++, (size_t)M * b.sT * 16, sm);
+    b.Ub = (double2*)bget(S, s++, (size_t)M * b.sU * 16, sm);
+    b.Xb = (double2*)bget(S, s++, (size_t)M * b.sU * 16, sm);
+    b.R = (double2*)bget(S, s++, (size_t)M * b.sU * 16, sm);
+    b.D64 = (float2*)bget(S, s++, (size_t)M * b.sU * 8, sm);
+    b.ipiv = (int*)bget(S, s++, (size_t)M * b.sP * 4, sm);
+    b.perm = from ? (int2*)(s++, nullptr) : (int2*)bget(S, s++, (size_t)M * b.sPerm * 8, sm);
+    b.tperm = (int2*)bget(S, s++, (size_t)M * b.sTP * 8, sm);
+    b.info = (int*)bget(S, s++, (size_t)M * 4, sm);
+    b.inv = mixed && !from ? bget(S, s++, (size_t)M * b.sInv * 8, sm) : (void*)(s++, nullptr);
+    b.tmp = mixed ? bget(S, s++, (size_t)M * b.sTmp * 8, sm) : (void*)(s++, nullptr);
+    b.nk = (int*)bget(S, s++, (size_t)M * 4, sm);
+    b.coef = (double2*)bget(S, s++, ncoef * 16, sm);
+    b.frobp = (double*)bget(S, s++, (size_t)M * nparts_max * 8, sm);
+    b.frob = (double*)bget(S, s++, (size_t)M * 8, sm);
+    b.un = (double*)bget(S, s++, (size_t)M * Lmax * 8, sm);
+    b.rn = (double*)bget(S, s++, (size_t)M * Lmax * 8, sm);
+    b.xn = (double*)bget(S, s++, (size_t)M * Lmax * 8, sm);
+    b.inv_s = (double*)bget(S, s++, (size_t)M * Lmax * 8, sm);
+    b.scl = (double*)bget(S, s++, (size_t)M * Lmax * 8, sm);
+    b.active = (int*)bget(S, s++, (size_t)M * 4, sm);
+    b.prev = (double*)bget(S, s++, (size_t)M * 8, sm);
+    b.resid = (double*)bget(S, s++, (size_t)M * 8, sm);
+    b.iters = (int*)bget(S, s++, (size_t)M * 4, sm);
+    b.ones = (double*)bget(S, s++, (size_t)M * Lmax * 8, sm);
+    b.pair = mixed && !from ? bget(S, s++, (size_t)M * b.sPair * 8, sm) : (void*)(s++, nullptr);
+    if ((!from && (!b.T || !b.perm || (mixed && (!b.inv || !b.pair)))) || !b.T128 || !b.Ub || !b.Xb || !b.R ||
+        !b.D64 || !b.ipiv || !b.tperm || !b.info || (mixed && !b.tmp) || !b.nk || !b.coef || !b.frobp || !b.frob ||
+        !b.un || !b.rn || !b.xn || !b.inv_s || !b.scl || !b.active || !b.prev || !b.resid || !b.iters || !b.ones)
+        return RSRR_ENOMEM;
+    // the first solve narrows U with scale 1: ones in scl
+    std::vector<double> ones((size_t)M * Lmax, 1.0);
+    RSRR_HIP(hipMemcpyAsync(b.ones, ones.data(), ones.size() * 8, hipMemcpyHostToDevice, sm));
+    RSRR_HIP(hipStreamSynchronize(sm));
+    return RSRR_OK;
+}
+
+struct Flags { int sing = 0, fb = 0, nan = 0; };
+
+// Diagnostics of one bucket back to the host; points above the residual bar are
+// redone in FP64.  info (may be null) is indexed by pbase[ids[q]] + k.
+rsrr_status report_bucket(rsrr_ctx* c, const rsrr_instance* inst, const std::vector<int>& ids,
+                          const std::vector<long>& off, long M, const int* dinfo, const int* diters,
+                          const double* dres, const std::vector<long>& pbase, rsrr_point_info* info, Flags& f)
+{
+    std::vector<int> hinfo(M), hit(M);
+    std::vector<double> hres(M);
+    RSRR_HIP(hipMemcpyAsync(hinfo.data(), dinfo, (size_t)M * 4, hipMemcpyDeviceToHost, c->stream));
+    RSRR_HIP(hipMemcpyAsync(hit.data(), diters, (size_t)M * 4, hipMemcpyDeviceToHost, c->stream));
+    RSRR_HIP(hipMemcpyAsync(hres.data(), dres, (size_t)M * 8, hipMemcpyDeviceToHost, c->stream));
+    RSRR_HIP(hipStreamSynchronize(c->stream));
+    for (size_t q = 0; q < ids.size(); ++q) {
+        const rsrr_instance& in = inst[ids[q]];
+        for (int k = 0; k < in.N; ++k) {
+            const long m = off[q] + k;
+            rsrr_point_info pi{};
+            pi.info = hinfo[m];
+            pi.ir_iters = hit[m];
+            pi.resid = hres[m];
+            if (hinfo[m] > 0) f.sing = 1;
+            if (hinfo[m] < 0) f.nan = 1;
+            if (hinfo[m] == 0 && !(hres[m] <= c->fallback_resid)) {
+                // redo this point on the FP64 path
+                rsrr_point_info fpi;
+                const rsrr_status st = rsrr_sample(c, &in.nep, 1, in.z + 2 * k, in.U, in.L, in.ldu, RSRR_PREC_C128,
+                                                   in.S + 2 * (size_t)k * in.L * in.lds, in.lds, &fpi);
+                if (st < 0 || st == RSRR_EDEVICE || st == RSRR_ENOMEM) return st;
+                pi.fallback = 1;
+                pi.resid = fpi.resid;
+                pi.info = fpi.info;
+                f.fb = 1;
+            }
+            if (info) info[pbase[ids[q]] + k] = pi;
+        }
+    }
+    return RSRR_OK;
+}
+
+rsrr_status validate(int count, const rsrr_instance* inst)
+{
     for (int i = 0; i < count; ++i) {
         const rsrr_instance& in = inst[i];
         const rsrr_nep& e = in.nep;
@@ -262,10 +414,16 @@ extern "C" rsrr_status rsrr_sample_batched(rsrr_ctx* c, int count, const rsrr_in
         }
         if (in.N < 1 || !in.z || !in.U || in.L < 1 || in.ldu < e.n || !in.S || in.lds < e.n) return -3;
     }
+    return RSRR_OK;
+}
+
+rsrr_status batched_impl(rsrr_ctx* c, int count, const rsrr_instance* inst, int prec, int flags,
+                         rsrr_point_info* info, FactorStore* const* keep, const int* keep_k0)
+{
     RSRR_HIP(hipSetDevice(c->device));
     BatchedState& S = state_of(c);
     load_tune_file(S);
-    const bool use_graph = (flags & RSRR_BATCH_GRAPH) != 0;
+    const bool use_graph = (flags & RSRR_BATCH_GRAPH) != 0 && !keep;
     const bool autotune = (flags & RSRR_BATCH_AUTOTUNE) != 0;
     const bool mixed = prec == RSRR_PREC_C64_IR;
 
@@ -277,13 +435,13 @@ extern "C" rsrr_status rsrr_sample_batched(rsrr_ctx* c, int count, const rsrr_in
     std::map<int, std::vector<int>> buckets;
     for (int i = 0; i < count; ++i) buckets[(inst[i].nep.n + BUCKET - 1) / BUCKET * BUCKET].push_back(i);
 
-    int any_sing = 0, any_fb = 0, any_nan = 0;
+    Flags fl;
     // Every bucket has its own buffers; the buckets run side by side on a pool of
     // streams (replayed graphs or eager launches) and report after all of them.  The
     // host tables of eager launches stay alive in `pending` until then.
     struct Pending {
         std::vector<int> ids; std::vector<long> off; long M; int* info; int* iters; double* resid;
-        std::vector<double2> coef; std::vector<int> nk;
+        std::vector<double2> coef; std::vector<int> nk; std::vector<FactorStore*> keep; std::vector<int> k0;
     };
     std::vector<Pending> pending;
     if (!S.streams[0]) {
@@ -298,42 +456,6 @@ extern "C" rsrr_status rsrr_sample_batched(rsrr_ctx* c, int count, const rsrr_in
         BatchedState& S; const int& n;
         ~Drain() { for (int i = 0; i < std::min(n, N_BUCKET_STREAMS); ++i) (void)hipStreamSynchronize(S.streams[i]); }
     } drain{S, nlaunched};
-    // diagnostics of one bucket back to the host; points above the residual bar are redone in FP64
-    auto report = [&](const std::vector<int>& ids, const std::vector<long>& off, long M, const int* dinfo,
-                      const int* diters, const double* dres) -> rsrr_status {
-        std::vector<int> hinfo(M), hit(M);
-        std::vector<double> hres(M);
-        RSRR_HIP(hipMemcpyAsync(hinfo.data(), dinfo, (size_t)M * 4, hipMemcpyDeviceToHost, c->stream));
-        RSRR_HIP(hipMemcpyAsync(hit.data(), diters, (size_t)M * 4, hipMemcpyDeviceToHost, c->stream));
-        RSRR_HIP(hipMemcpyAsync(hres.data(), dres, (size_t)M * 8, hipMemcpyDeviceToHost, c->stream));
-        RSRR_HIP(hipStreamSynchronize(c->stream));
-        for (size_t q = 0; q < ids.size(); ++q) {
-            const rsrr_instance& in = inst[ids[q]];
-            for (int k = 0; k < in.N; ++k) {
-                const long m = off[q] + k;
-                rsrr_point_info pi{};
-                pi.info = hinfo[m];
-                pi.ir_iters = hit[m];
-                pi.resid = hres[m];
-                if (hinfo[m] > 0) any_sing = 1;
-                if (hinfo[m] < 0) any_nan = 1;
-                if (hinfo[m] == 0 && !(hres[m] <= c->fallback_resid)) {
-                    // redo this point on the FP64 path
-                    rsrr_point_info fpi;
-                    const rsrr_status st = rsrr_sample(c, &in.nep, 1, in.z + 2 * k, in.U, in.L, in.ldu,
-                                                       RSRR_PREC_C128, in.S + 2 * (size_t)k * in.L * in.lds, in.lds,
-                                                       &fpi);
-                    if (st < 0 || st == RSRR_EDEVICE || st == RSRR_ENOMEM) return st;
-                    pi.fallback = 1;
-                    pi.resid = fpi.resid;
-                    pi.info = fpi.info;
-                    any_fb = 1;
-                }
-                if (info) info[pbase[ids[q]] + k] = pi;
-            }
-        }
-        return RSRR_OK;
-    };
     for (auto& kv : buckets) {
         const int P = kv.first;
         const std::vector<int>& ids = kv.second;
@@ -345,78 +467,14 @@ extern "C" rsrr_status rsrr_sample_batched(rsrr_ctx* c, int count, const rsrr_in
             maxn = std::max(maxn, inst[ids[q]].nep.n);
         }
         const long M = off.back();
-        // host tables: per-matrix n and the coefficient / point tables
-        std::vector<int> nk(M);
+        std::vector<int> nk;
         std::vector<double2> coef;
-        for (size_t q = 0; q < ids.size(); ++q) {
-            const rsrr_instance& in = inst[ids[q]];
-            for (long k = off[q]; k < off[q + 1]; ++k) nk[k] = in.nep.n;
-            if (in.nep.kind == RSRR_T_SEPARABLE) {
-                for (int j = 0; j < in.nep.J; ++j)
-                    for (int k = 0; k < in.N; ++k) {
-                        const zd f = term_eval(in.nep.terms[j], zd(in.z[2 * k], in.z[2 * k + 1]));
-                        coef.push_back(make_double2(f.real(), f.imag()));
-                    }
-            } else {
-                for (int k = 0; k < in.N; ++k) coef.push_back(make_double2(in.z[2 * k], in.z[2 * k + 1]));
-            }
-        }
-        // buffers
-        const int npan = perm_panels(P);
+        bucket_tables(inst, ids, off, nk, coef);
         const int nbmax = mixed ? max_panel<float>() : max_panel<double>();
         BucketBufs b{};
-        b.sT = (long)P * P;
-        b.sU = (long)P * Lmax;
-        b.sP = P;
-        b.sPerm = (long)npan * 2 * MAX_NB;
-        b.sTP = 8L * 2 * MAX_NB;
-        // ceil(P/nb) panels of 2 nb^2 for any nb <= nbmax: at most 2 nbmax (P + nbmax)
-        b.sInv = mixed ? 2L * nbmax * (P + nbmax) : 0;
-        b.sTmp = mixed ? (long)nbmax * std::max(P, Lmax) : 0;
-        b.sPair = mixed ? lu_pair_elems(P, nbmax, P) : 0;
-        const size_t esz = mixed ? 8 : 16;
-        long nparts_max = ((long)maxn * maxn + 255) / 256;
         hipStream_t sm = c->stream;
-        // with graphs every bucket size has its own buffers (the graphs keep pointing at
-        // them); otherwise the buckets of a call run one after the other and share them
-        int s = (P / BUCKET) * 32;
-        b.T = bget(S, s++, (size_t)M * b.sT * esz, sm);
-        b.T128 = (double2*)bget(S, s++, (size_t)M * b.sT * 16, sm);
-        b.Ub = (double2*)bget(S, s++, (size_t)M * b.sU * 16, sm);
-        b.Xb = (double2*)bget(S, s++, (size_t)M * b.sU * 16, sm);
-        b.R = (double2*)bget(S, s++, (size_t)M * b.sU * 16, sm);
-        b.D64 = (float2*)bget(S, s++, (size_t)M * b.sU * 8, sm);
-        b.ipiv = (int*)bget(S, s++, (size_t)M * b.sP * 4, sm);
-        b.perm = (int2*)bget(S, s++, (size_t)M * b.sPerm * 8, sm);
-        b.tperm = (int2*)bget(S, s++, (size_t)M * b.sTP * 8, sm);
-        b.info = (int*)bget(S, s++, (size_t)M * 4, sm);
-        b.inv = mixed ? bget(S, s++, (size_t)M * b.sInv * 8, sm) : (void*)(s++, nullptr);
-        b.tmp = mixed ? bget(S, s++, (size_t)M * b.sTmp * 8, sm) : (void*)(s++, nullptr);
-        b.nk = (int*)bget(S, s++, (size_t)M * 4, sm);
-        b.coef = (double2*)bget(S, s++, coef.size() * 16, sm);
-        b.frobp = (double*)bget(S, s++, (size_t)M * nparts_max * 8, sm);
-        b.frob = (double*)bget(S, s++, (size_t)M * 8, sm);
-        b.un = (double*)bget(S, s++, (size_t)M * Lmax * 8, sm);
-        b.rn = (double*)bget(S, s++, (size_t)M * Lmax * 8, sm);
-        b.xn = (double*)bget(S, s++, (size_t)M * Lmax * 8, sm);
-        b.inv_s = (double*)bget(S, s++, (size_t)M * Lmax * 8, sm);
-        b.scl = (double*)bget(S, s++, (size_t)M * Lmax * 8, sm);
-        b.active = (int*)bget(S, s++, (size_t)M * 4, sm);
-        b.prev = (double*)bget(S, s++, (size_t)M * 8, sm);
-        b.resid = (double*)bget(S, s++, (size_t)M * 8, sm);
-        b.iters = (int*)bget(S, s++, (size_t)M * 4, sm);
-        b.ones = (double*)bget(S, s++, (size_t)M * Lmax * 8, sm);
-        b.pair = mixed ? bget(S, s++, (size_t)M * b.sPair * 8, sm) : (void*)(s++, nullptr);
-        if (!b.T || !b.T128 || !b.Ub || !b.Xb || !b.R || !b.D64 || !b.ipiv || !b.perm || !b.tperm || !b.info ||
-            (mixed && (!b.inv || !b.tmp || !b.pair)) || !b.nk || !b.coef || !b.frobp || !b.frob || !b.un || !b.rn || !b.xn ||
-            !b.inv_s || !b.scl || !b.active || !b.prev || !b.resid || !b.iters || !b.ones)
-            return RSRR_ENOMEM;
-        // the first solve narrows U with scale 1: ones in scl
-        {
-            std::vector<double> ones((size_t)M * Lmax, 1.0);
-            RSRR_HIP(hipMemcpyAsync(b.ones, ones.data(), ones.size() * 8, hipMemcpyHostToDevice, sm));
-            RSRR_HIP(hipStreamSynchronize(sm));
-        }
+        rsrr_status bs = bucket_bufs(S, sm, P, Lmax, M, maxn, coef.size(), mixed, false, b);
+        if (bs) return bs;
 
         // panel width: tuned (timed over the candidates on this bucket) or default
         const long tkey = (long)P * 2 + (mixed ? 1 : 0);
@@ -499,15 +557,20 @@ extern "C" rsrr_status rsrr_sample_batched(rsrr_ctx* c, int count, const rsrr_in
             RSRR_HIP(hipStreamWaitEvent(ps, c->fork, 0));
             RSRR_HIP(hipGraphLaunch(slot->exec, ps));
             ++nlaunched;
-            pending.push_back(Pending{ids, off, M, b.info, b.iters, b.resid, {}, {}});
+            pending.push_back(Pending{ids, off, M, b.info, b.iters, b.resid, {}, {}, {}, {}});
         } else {
             hipStream_t ps = S.streams[nlaunched % N_BUCKET_STREAMS];
             RSRR_HIP(hipEventRecord(c->fork, c->stream));
             RSRR_HIP(hipStreamWaitEvent(ps, c->fork, 0));
-            pending.push_back(Pending{ids, off, M, b.info, b.iters, b.resid, std::move(coef), std::move(nk)});
+            std::vector<FactorStore*> kq;
+            std::vector<int> k0q;
+            if (keep)
+                for (int id : ids) { kq.push_back(keep[id]); k0q.push_back(keep_k0[id]); }
+            pending.push_back(Pending{ids, off, M, b.info, b.iters, b.resid, std::move(coef), std::move(nk),
+                                      std::move(kq), std::move(k0q)});
             Pending& pd = pending.back();
             rsrr_status st = run_bucket(c, ps, inst, ids, off, P, Lmax, M, prec, nb, b, pd.coef.data(), pd.nk.data(),
-                                        maxit);
+                                        maxit, keep ? pd.keep.data() : nullptr, keep ? pd.k0.data() : nullptr);
             if (st) return st;
             ++nlaunched;
         }
@@ -518,12 +581,116 @@ extern "C" rsrr_status rsrr_sample_batched(rsrr_ctx* c, int count, const rsrr_in
             RSRR_HIP(hipStreamWaitEvent(c->stream, S.done[i], 0));
         }
         for (const Pending& pd : pending) {
-            const rsrr_status st = report(pd.ids, pd.off, pd.M, pd.info, pd.iters, pd.resid);
+            const rsrr_status st = report_bucket(c, inst, pd.ids, pd.off, pd.M, pd.info, pd.iters, pd.resid, pbase,
+                                                 info, fl);
             if (st) return st;
         }
     }
-    if (any_nan) return RSRR_ENAN;
-    if (any_sing) return RSRR_ESINGULAR;
-    if (any_fb) return RSRR_WARN_FALLBACK;
+    if (fl.nan) return RSRR_ENAN;
+    if (fl.sing) return RSRR_ESINGULAR;
+    if (fl.fb) return RSRR_WARN_FALLBACK;
     return RSRR_OK;
+}
+
+}  // namespace
+
+extern "C" rsrr_status rsrr_sample_batched(rsrr_ctx* c, int count, const rsrr_instance* inst, int prec, int flags,
+                                           rsrr_point_info* info)
+{
+    if (!c) return -1;
+    if (count < 1) return -2;
+    if (!inst) return -3;
+    if (prec != RSRR_PREC_C128 && prec != RSRR_PREC_C64_IR) return -4;
+    const rsrr_status v = validate(count, inst);
+    if (v) return v;
+    return batched_impl(c, count, inst, prec, flags, info, nullptr, nullptr);
+}
+
+rsrr_status sample_batched_keep(rsrr_ctx* c, int count, const rsrr_instance* inst, int prec, rsrr_point_info* info,
+                                FactorStore* const* keep, const int* k0)
+{
+    if (!c || count < 1 || !inst || !keep || !k0) return -1;
+    const rsrr_status v = validate(count, inst);
+    if (v) return v;
+    for (int i = 0; i < count; ++i)
+        if (keep[i] && (keep[i]->P != (inst[i].nep.n + BUCKET - 1) / BUCKET * BUCKET || keep[i]->prec != prec ||
+                        k0[i] < 0 || k0[i] + inst[i].N > keep[i]->N))
+            return -3;
+    return batched_impl(c, count, inst, prec, 0, info, keep, k0);
+}
+
+rsrr_status solve_from_store(rsrr_ctx* c, const rsrr_instance& in, const FactorStore& fs, int k0,
+                             rsrr_point_info* info)
+{
+    if (!c) return -1;
+    if (validate(1, &in)) return -2;
+    const int P = (in.nep.n + BUCKET - 1) / BUCKET * BUCKET;
+    if (fs.P != P || fs.nb < MIN_NB || k0 < 0 || k0 + in.N > fs.N) return -3;
+    RSRR_HIP(hipSetDevice(c->device));
+    BatchedState& S = state_of(c);
+    const bool mixed = fs.prec == RSRR_PREC_C64_IR;
+    std::vector<int> ids{0};
+    std::vector<long> off{0, in.N};
+    std::vector<int> nk;
+    std::vector<double2> coef;
+    bucket_tables(&in, ids, off, nk, coef);
+    BucketBufs b{};
+    rsrr_status st = bucket_bufs(S, c->stream, P, in.L, in.N, in.nep.n, coef.size(), mixed, true, b);
+    if (st) return st;
+    st = run_bucket(c, c->stream, &in, ids, off, P, in.L, in.N, fs.prec, fs.nb, b, coef.data(), nk.data(),
+                    c->ir_max_iters_batched, nullptr, nullptr, &fs, k0);
+    if (st) return st;
+    Flags fl;
+    std::vector<long> pbase{0, in.N};
+    st = report_bucket(c, &in, ids, off, in.N, b.info, b.iters, b.resid, pbase, info, fl);
+    if (st) return st;
+    if (fl.nan) return RSRR_ENAN;
+    if (fl.sing) return RSRR_ESINGULAR;
+    if (fl.fb) return RSRR_WARN_FALLBACK;
+    return RSRR_OK;
+}
+
+size_t factor_store_bytes(int n, int N, int prec)
+{
+    const int P = (n + BUCKET - 1) / BUCKET * BUCKET;
+    const bool mixed = prec == RSRR_PREC_C64_IR;
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    return al((size_t)N * P * P * (mixed ? 8 : 16)) + al((size_t)N * bucket_sPerm(P) * 8) +
+           al((size_t)N * bucket_sInv(P, mixed) * 8);
+}
+
+FactorStore factor_store_at(void* base, int n, int N, int prec)
+{
+    const int P = (n + BUCKET - 1) / BUCKET * BUCKET;
+    const bool mixed = prec == RSRR_PREC_C64_IR;
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    FactorStore f;
+    f.P = P;
+    f.N = N;
+    f.prec = prec;
+    f.sT = (long)P * P;
+    f.sPerm = bucket_sPerm(P);
+    f.sInv = bucket_sInv(P, mixed);
+    char* p = (char*)base;
+    f.T = p;
+    p += al((size_t)N * f.sT * (mixed ? 8 : 16));
+    f.perm = (int2*)p;
+    p += al((size_t)N * f.sPerm * 8);
+    f.inv = mixed ? (void*)p : nullptr;
+    return f;
+}
+
+void batched_trim(rsrr_ctx* c, size_t keep_bytes)
+{
+    size_t tot = 0;
+    {
+        std::lock_guard<std::mutex> lk(states_mu());
+        auto it = states().find(c);
+        if (it == states().end()) return;
+        for (size_t x : it->second->sizes) tot += x;
+    }
+    if (tot > keep_bytes) {
+        (void)hipStreamSynchronize(c->stream);
+        batched_release(c);
+    }
 }

@@ -58,7 +58,9 @@ extern "C" rsrr_status rsrr_solve(rsrr_ctx* c, const rsrr_nep* nep, int k, const
     if (!mom) return RSRR_ENOMEM;
     RSRR_HIP(hipMemsetAsync(mom, 0, (size_t)twoK * kk * 16, c->stream));
     const size_t per_pt = (size_t)kk * 16 * 2 + (size_t)k * 4 + 64 * 1024;
-    const int Mc = (int)std::max<size_t>(1, std::min<size_t>((size_t)std::min(NQ, 256), (size_t)(8ull << 30) / per_pt));
+    // points per batched LU: 8 GiB of buffers, or the context's workspace budget when set
+    const size_t mom_budget = c->ws_budget ? std::min<size_t>(c->ws_budget, (size_t)8 << 30) : (size_t)8 << 30;
+    const int Mc = (int)std::max<size_t>(1, std::min<size_t>((size_t)std::min(NQ, 256), mom_budget / per_pt));
     const int nb = 64;
     const int np = perm_panels(k);
     double2* T = (double2*)ws_get(c, WS_TLU, (size_t)Mc * kk * 16);
@@ -331,7 +333,7 @@ extern "C" rsrr_status rsrr_solve(rsrr_ctx* c, const rsrr_nep* nep, int k, const
         RSRR_HIP(scale_cols(c->stream, n, ne, V, ldv, vn));
         if (resid) {
             // ||T(lambda_i) v_i||_2 / ||T(lambda_i)||_1 in FP64 against the full T
-            const size_t budget = (size_t)4 << 30;
+            const size_t budget = c->ws_budget ? std::min<size_t>(c->ws_budget, (size_t)4 << 30) : (size_t)4 << 30;
             const int Bc = (int)std::max<size_t>(1, std::min<size_t>((size_t)ne, budget / ((size_t)n * n * 16)));
             double2* Tb = (double2*)ws_get(c, WS_TLU, (size_t)Bc * n * n * 16);
             double2* Rv = (double2*)ws_get(c, WS_R, (size_t)Bc * n * 16);

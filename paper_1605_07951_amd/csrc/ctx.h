@@ -73,6 +73,38 @@ int jacobi_svd(rsrr_ctx* c, double2* A, int lda, int m, int m_apply, int p, int 
 // device), looked up once per device.
 rsrr_status noalloc_scratch_setup(int device, void** out);
 
+// Device-resident LU factors of one NEP's sampling points (serving: kept from
+// factorisation until the request finishes, so more probe columns can be solved
+// without refactoring).  Layout in one caller-provided block, each part
+// 256-byte aligned: factors T (N matrices P x P, P = n rounded up to 64, stride
+// sT; complex FP32 or FP64 by prec), composed row interchanges perm (stride
+// sPerm) and, for complex FP32, the diagonal-block inverses inv (stride sInv),
+// with the panel width nb they were made with (set by the sampling call).
+struct FactorStore {
+    void* T = nullptr;
+    int2* perm = nullptr;
+    void* inv = nullptr;
+    long sT = 0, sPerm = 0, sInv = 0;
+    int P = 0, N = 0, prec = 0, nb = 0;
+};
+size_t factor_store_bytes(int n, int N, int prec);
+FactorStore factor_store_at(void* base, int n, int N, int prec);
+
+// rsrr_sample_batched (eager launches) that also copies every instance's
+// factors into keep[i] at points k0[i] .. k0[i] + N_i - 1 (keep[i] may be null).
+rsrr_status sample_batched_keep(rsrr_ctx* c, int count, const rsrr_instance* inst, int prec, rsrr_point_info* info,
+                                FactorStore* const* keep, const int* k0);
+
+// X = T(z_k)^-1 U for points k0 .. k0 + in.N - 1 of a store: triangular solves with
+// the kept factors and refinement against FP64 residuals (T(z_k) regenerated), no
+// factorisation.  Points that do not reach fallback_resid are redone in FP64.
+rsrr_status solve_from_store(rsrr_ctx* c, const rsrr_instance& in, const FactorStore& fs, int k0,
+                             rsrr_point_info* info);
+
+// Free the ragged-batch buffers (and graphs) of a context when they hold more than
+// keep_bytes (after its streams have drained).
+void batched_trim(rsrr_ctx* c, size_t keep_bytes);
+
 // f(z) = c (z - z0)^p exp(-tau z) / (z - s)^q
 zd term_eval(const rsrr_term& t, zd z);
 

@@ -3,16 +3,21 @@
 //
 // Two host threads, each with its own rsrr_ctx on its own non-blocking
 // stream:
-//   sampler  admits queued requests (free slot + room for S in the arena, first
-//            come first served), then repeatedly takes sampling points from all
+//   sampler  admits queued requests (free slot + room for the request's whole
+//            footprint in the arena: S, kept LU factors, Q, V; first come,
+//            first served), then repeatedly takes sampling points from all
 //            admitted requests in admission order, up to batch_bytes of LU
-//            workspace, and runs them as one rsrr_sample_batched call per
-//            probe count L (inside it, one uniform batch per size bucket).
-//            Requests that arrive meanwhile join the next launch.
+//            workspace, and runs them as one batched sampling call per probe
+//            count L (inside it, one uniform batch per size bucket), which also
+//            copies each point's factors into its request's block.  Requests
+//            that arrive meanwhile join the next launch.
 //   solver   runs basis, projection and SS-FULL of each request whose points
-//            are all sampled, copies the eigenpairs to the caller's host
-//            arrays and frees the request's arena block (which may admit the
-//            next request).  Its kernels overlap the next sampling launches.
+//            are all sampled; when the gap test fails or an eigenpair inside
+//            has a large residual, solves the request's reserve probe columns
+//            with the kept factors (no refactorisation) and runs Steps 3-5
+//            again; copies the eigenpairs to the caller's host arrays and frees
+//            the request's arena block (which may admit the next request).
+//            Its kernels overlap the next sampling launches.
 // The arena is one hipMalloc'd block sub-allocated first-fit, so admission
 // decides on real HBM and the loop never calls hipMalloc/hipFree per request.
 #include <hip/hip_runtime.h>
@@ -39,6 +44,26 @@ constexpr int DEFAULT_NQ = 500;
 constexpr int DEFAULT_KQ = 2;
 constexpr int MAX_TERMS = 64;
 constexpr size_t ALIGN = 256;
+constexpr double REPROBE_RESID = 1e-10;   // eigen-residual bar inside the contour
+constexpr size_t DEFAULT_SOLVE_BYTES = (size_t)4 << 30;
+
+size_t al(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+// The request's arena block: S | factors | Q | V.
+struct Layout {
+    size_t s, fac, q, v, total;
+};
+Layout layout_of(const rsrr_request& r, int prec)
+{
+    const size_t n = (size_t)r.nep.n, NL = (size_t)r.N * (r.L + r.L_extra);
+    Layout l;
+    l.s = al(n * NL * 16);
+    l.fac = al(factor_store_bytes(r.nep.n, r.N, prec));
+    l.q = al(n * std::min(n, NL) * 16);
+    l.v = al(n * (size_t)r.max_eigs * 16);
+    l.total = l.s + l.fac + l.q + l.v;
+    return l;
+}
 
 // First-fit sub-allocator over [0, size).
 struct Arena {
@@ -91,8 +116,12 @@ struct Req {
     rsrr_request r{};
     std::vector<rsrr_term> terms;  // copy of the caller's term table
     std::vector<double> z;         // contour nodes (2N)
-    size_t s_off = 0, s_bytes = 0;
-    double* S = nullptr;           // n x N*L in the arena
+    Layout lay{};
+    size_t s_off = 0, s_bytes = 0; // the whole arena block
+    double* S = nullptr;           // n x N*(L + L_extra) in the arena: N*L initial columns, then N*L_extra
+    FactorStore fs;                // kept factors of the N points
+    double* Q = nullptr;           // n x min(n, N*(L + L_extra))
+    double* V = nullptr;           // n x max_eigs
     int next = 0;                  // first point not yet handed to a launch
     int sampled = 0;               // points finished
     int last_launch = -1;
@@ -111,6 +140,23 @@ double now_s(std::chrono::steady_clock::time_point t0)
 }
 
 bool is_error(rsrr_status s) { return s < 0 || s == RSRR_ENOMEM || s == RSRR_EDEVICE || s == RSRR_ENOTCONV || s == RSRR_ENAN || s == RSRR_ESINGULAR || s == RSRR_ELIMIT; }
+
+// Request checks shared by rsrr_server_submit and rsrr_server_footprint.
+bool request_ok(const rsrr_request* r)
+{
+    const rsrr_nep& e = r->nep;
+    if (e.n < 1 || e.n > 8192) return false;
+    if (e.kind == RSRR_T_SEPARABLE) {
+        if (e.J < 1 || e.J > MAX_TERMS || !e.A || e.lda < e.n || !e.terms) return false;
+    } else if (e.kind == RSRR_T_HELMHOLTZ) {
+        if (!e.points || !(e.w > 0)) return false;
+    } else {
+        return false;
+    }
+    return r->a > 0 && r->b > 0 && r->N >= 1 && r->L >= 1 && r->L_extra >= 0 && r->U && r->ldu >= e.n &&
+           r->max_eigs >= 1 && r->lambda && r->NQ >= 0 && r->KQ >= 0 &&
+           !(r->NQ > 0 && r->NQ < 2 * std::max(r->KQ, 1) + 1) && r->delta >= 0 && r->delta < 1;
+}
 
 // LU workspace of one point in a sampling launch (the bucket buffers of
 // rsrr_sample_batched), bytes.
@@ -133,9 +179,7 @@ size_t point_bytes(int n, int L, bool mixed)
 struct Worker {
     hipStream_t st = nullptr;
     rsrr_ctx* c = nullptr;
-    void* q_buf = nullptr;  size_t q_cap = 0;
-    void* aq_buf = nullptr; size_t aq_cap = 0;
-    void* v_buf = nullptr;  size_t v_cap = 0;
+    void* aq_buf = nullptr; size_t aq_cap = 0;  // projected matrices (within solve_bytes)
     std::thread th;
 };
 
@@ -161,7 +205,7 @@ struct rsrr_server {
     int posting = 0;                  // requests inside the solve step
 
     // counters
-    long finished = 0, points = 0, launches = 0, max_launch = 0;
+    long finished = 0, points = 0, launches = 0, max_launch = 0, repoints = 0, reprobes = 0;
     double busy_s = 0.0, busy_p = 0.0;
     size_t mem_peak = 0;
 
@@ -190,49 +234,109 @@ void note_status(rsrr_result& r, rsrr_status s)
     if (r.status == RSRR_OK || (!is_error(r.status) && is_error(s))) r.status = s;
 }
 
+// Solve the reserve probe columns of every point from the kept factors into the
+// columns N*L .. N*(L + L_extra) - 1 of S, in chunks of points sized to the
+// solve thread's budget; the chunk buffers are released afterwards.
+rsrr_status reprobe(rsrr_server* s, Worker* w, Req* q)
+{
+    const rsrr_request& r = q->r;
+    const int n = r.nep.n, Lx = r.L_extra;
+    const bool mixed = s->cfg.prec == RSRR_PREC_C64_IR;
+    const size_t per = point_bytes(n, Lx, mixed);
+    const int chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)r.N, s->cfg.solve_bytes / per));
+    rsrr_status st = RSRR_OK;
+    std::vector<rsrr_point_info> pi(chunk);
+    for (int k0 = 0; k0 < r.N; k0 += chunk) {
+        rsrr_instance in{};
+        in.nep = r.nep;
+        in.nep.terms = q->terms.empty() ? nullptr : q->terms.data();
+        in.N = std::min(chunk, r.N - k0);
+        in.z = q->z.data() + 2 * (size_t)k0;
+        in.U = r.U + 2 * (size_t)r.L * r.ldu;
+        in.L = Lx;
+        in.ldu = r.ldu;
+        in.S = q->S + 2 * ((size_t)r.N * r.L + (size_t)k0 * Lx) * n;
+        in.lds = n;
+        const rsrr_status e = solve_from_store(w->c, in, q->fs, k0, pi.data());
+        if (e && (st == RSRR_OK || is_error(e))) st = e;
+        if (is_error(e)) break;
+        for (int k = 0; k < in.N; ++k) {
+            q->res.fallbacks += pi[k].fallback;
+            q->res.ir_iters_max = std::max(q->res.ir_iters_max, pi[k].ir_iters);
+            if (pi[k].resid > q->res.sample_resid_max) q->res.sample_resid_max = pi[k].resid;
+        }
+    }
+    batched_trim(w->c, 0);
+    return st;
+}
+
 // Basis, projection, SS-FULL and the copy of the eigenpairs to the host (RSRR
-// Steps 3-5) for one sampled request, on context c.
-void finish_request(Worker* w, Req* q)
+// Steps 3-5) for one sampled request, on context c; a re-probe from the kept
+// factors when the first pass fails its checks.
+void finish_request(rsrr_server* s, Worker* w, Req* q)
 {
     rsrr_ctx* c = w->c;
     hipStream_t st = w->st;
     rsrr_result& res = q->res;
     if (is_error(res.status) && res.status != RSRR_ESINGULAR) return;
     const rsrr_request& r = q->r;
-    const int n = r.nep.n, NL = r.N * r.L, kmax = std::min(n, NL);
-    double2* Q = (double2*)grow(w->q_buf, w->q_cap, (size_t)n * kmax * 16);
-    if (!Q) { note_status(res, RSRR_ENOMEM); return; }
-    int k = 0;
-    rsrr_status e = rsrr_basis(c, n, NL, q->S, n, r.delta > 0 ? r.delta : c->delta, (double*)Q, n, kmax, &k,
-                               nullptr);
-    note_status(res, e);
-    if (is_error(e)) return;
-    res.k = k;
-    if (k < 1) return;
-    const int maxt = r.nep.kind == RSRR_T_SEPARABLE ? r.nep.J : MAX_TERMS;
-    double2* AQ = (double2*)grow(w->aq_buf, w->aq_cap, (size_t)maxt * k * k * 16);
-    // eigenvectors are always lifted on the device: the residuals need them
-    double2* V = (double2*)grow(w->v_buf, w->v_cap, (size_t)n * r.max_eigs * 16);
-    if (!AQ || !V) { note_status(res, RSRR_ENOMEM); return; }
-    std::vector<rsrr_term> tout(maxt);
-    int J_eff = 0;
+    const int n = r.nep.n;
+    const int kmax = (int)std::min<long>(n, (long)r.N * (r.L + r.L_extra));
     const double gam[2] = {r.gamma_re, r.gamma_im};
-    e = rsrr_project(c, &r.nep, (const double*)Q, n, k, gam, std::max(r.a, r.b), (double*)AQ, maxt, &J_eff,
-                     tout.data());
-    note_status(res, e);
-    if (is_error(e)) return;
-    int count = 0;
-    rsrr_solve_info si{};
+    const double rho = std::max(r.a, r.b);
     std::vector<double> resid(r.max_eigs, 0.0);
-    e = rsrr_solve(c, &r.nep, k, (const double*)AQ, J_eff, tout.data(), (const double*)Q, n, gam, r.a, r.b,
-                   r.NQ > 0 ? r.NQ : DEFAULT_NQ, r.KQ > 0 ? r.KQ : DEFAULT_KQ, c->tol_gap, r.max_eigs, r.lambda,
-                   (double*)V, n, r.resid ? r.resid : resid.data(), &count, nullptr, &si);
-    note_status(res, e);
-    if (is_error(e)) return;
-    res.count = count;
-    res.nbar = si.nbar;
-    if (r.V && count > 0) {
-        if (hipMemcpyAsync(r.V, V, (size_t)n * count * 16, hipMemcpyDeviceToHost, st) != hipSuccess ||
+    double* rout = r.resid ? r.resid : resid.data();
+    res.L_used = r.L;
+    for (;;) {
+        const int NL = r.N * res.L_used;
+        int k = 0;
+        rsrr_status e = rsrr_basis(c, n, NL, q->S, n, r.delta > 0 ? r.delta : c->delta, q->Q, n, kmax, &k, nullptr);
+        note_status(res, e);
+        if (is_error(e)) return;
+        res.k = k;
+        if (k < 1) return;
+        const int maxt = r.nep.kind == RSRR_T_SEPARABLE ? r.nep.J : MAX_TERMS;
+        const size_t aq_bytes = (size_t)maxt * k * k * 16;
+        if (aq_bytes > s->cfg.solve_bytes) { note_status(res, RSRR_ENOMEM); return; }
+        double2* AQ = (double2*)grow(w->aq_buf, w->aq_cap, aq_bytes);
+        if (!AQ) { note_status(res, RSRR_ENOMEM); return; }
+        std::vector<rsrr_term> tout(maxt);
+        int J_eff = 0;
+        e = rsrr_project(c, &r.nep, q->Q, n, k, gam, rho, (double*)AQ, maxt, &J_eff, tout.data());
+        note_status(res, e);
+        if (is_error(e)) return;
+        int count = 0;
+        rsrr_solve_info si{};
+        e = rsrr_solve(c, &r.nep, k, (const double*)AQ, J_eff, tout.data(), q->Q, n, gam, r.a, r.b,
+                       r.NQ > 0 ? r.NQ : DEFAULT_NQ, r.KQ > 0 ? r.KQ : DEFAULT_KQ, c->tol_gap, r.max_eigs, r.lambda,
+                       q->V, n, rout, &count, nullptr, &si);
+        if (is_error(e)) { note_status(res, e); return; }
+        res.count = count;
+        res.nbar = si.nbar;
+        // the paper's remedy for a failed gap test or inaccurate pairs: more probe columns
+        bool bad_pair = false;
+        for (int i = 0; i < count; ++i) {
+            const double dx = (r.lambda[2 * i] - r.gamma_re) / r.a, dy = (r.lambda[2 * i + 1] - r.gamma_im) / r.b;
+            if (dx * dx + dy * dy < 1.0 && !(rout[i] <= REPROBE_RESID)) bad_pair = true;
+        }
+        if ((si.warn_gap || bad_pair) && r.L_extra > 0 && res.L_used == r.L) {
+            const rsrr_status pe = reprobe(s, w, q);
+            if (is_error(pe)) { note_status(res, pe); return; }
+            if (pe == RSRR_WARN_FALLBACK) note_status(res, pe);
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->repoints += r.N;
+                ++s->reprobes;
+            }
+            res.reprobes = 1;
+            res.L_used = r.L + r.L_extra;
+            continue;
+        }
+        note_status(res, e);
+        break;
+    }
+    if (r.V && res.count > 0) {
+        if (hipMemcpyAsync(r.V, q->V, (size_t)n * res.count * 16, hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess)
             note_status(res, RSRR_EDEVICE);
     }
@@ -247,7 +351,11 @@ void admit_locked(rsrr_server* s)
         if (off < 0) break;  // first come first served: wait for room
         s->queue.pop_front();
         q->s_off = (size_t)off;
-        q->S = (double*)((char*)s->arena_base + off);
+        char* base = (char*)s->arena_base + off;
+        q->S = (double*)base;
+        q->fs = factor_store_at(base + q->lay.s, q->r.nep.n, q->r.N, s->cfg.prec);
+        q->Q = (double*)(base + q->lay.s + q->lay.fac);
+        q->V = (double*)(base + q->lay.s + q->lay.fac + q->lay.q);
         q->state = ADMITTED;
         q->res.t_admit = now_s(s->t0);
         s->admitted.push_back(q);
@@ -288,6 +396,8 @@ void run_launch(rsrr_server* s, const std::vector<Chunk>& ch, std::vector<std::v
     for (size_t i = 0; i < ch.size(); ++i) byL[ch[i].q->r.L].push_back((int)i);
     for (auto& kv : byL) {
         std::vector<rsrr_instance> inst;
+        std::vector<FactorStore*> keep;
+        std::vector<int> k0;
         long tot = 0;
         for (int i : kv.second) {
             const Chunk& c = ch[i];
@@ -303,10 +413,13 @@ void run_launch(rsrr_server* s, const std::vector<Chunk>& ch, std::vector<std::v
             in.S = c.q->S + 2 * (size_t)c.k0 * r.L * r.nep.n;
             in.lds = r.nep.n;
             inst.push_back(in);
+            keep.push_back(&c.q->fs);
+            k0.push_back(c.k0);
             tot += c.cnt;
         }
         std::vector<rsrr_point_info> pi(tot);
-        const rsrr_status e = rsrr_sample_batched(s->ws.c, (int)inst.size(), inst.data(), s->cfg.prec, 0, pi.data());
+        const rsrr_status e = sample_batched_keep(s->ws.c, (int)inst.size(), inst.data(), s->cfg.prec, pi.data(),
+                                                  keep.data(), k0.data());
         long p = 0;
         for (int i : kv.second) {
             infos[i].assign(pi.begin() + p, pi.begin() + p + ch[i].cnt);
@@ -343,7 +456,7 @@ void post_one(rsrr_server* s, Worker* w, std::unique_lock<std::mutex>& lk)
     ++s->posting;
     lk.unlock();
     const auto t = std::chrono::steady_clock::now();
-    finish_request(w, q);
+    finish_request(s, w, q);
     const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t).count();
     lk.lock();
     s->busy_p += dt;
@@ -379,6 +492,7 @@ void sampler_main(rsrr_server* s)
         run_launch(s, ch, infos, codes);
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) != hipSuccess) { (void)hipGetLastError(); fr = tot; }
+        batched_trim(s->ws.c, s->cfg.batch_bytes);  // bucket buffers of earlier sizes stay within the cap
         const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t).count();
         lk.lock();
         s->busy_s += dt;
@@ -422,7 +536,7 @@ void solver_main(rsrr_server* s, Worker* w)
 
 }  // namespace
 
-static rsrr_status worker_init(Worker* w, int device, const rsrr_options* opt)
+static rsrr_status worker_init(Worker* w, int device, const rsrr_options* opt, size_t ws_budget)
 {
     if (hipStreamCreateWithFlags(&w->st, hipStreamNonBlocking) != hipSuccess) {
         w->st = nullptr;
@@ -434,15 +548,14 @@ static rsrr_status worker_init(Worker* w, int device, const rsrr_options* opt)
         return e;
     }
     if (opt) e = rsrr_set_options(w->c, opt) ? -2 : RSRR_OK;
+    if (ws_budget) w->c->ws_budget = ws_budget;
     return e;
 }
 
 static void worker_free(Worker* w)
 {
     if (w->c) rsrr_destroy(w->c);
-    if (w->q_buf) (void)hipFree(w->q_buf);
     if (w->aq_buf) (void)hipFree(w->aq_buf);
-    if (w->v_buf) (void)hipFree(w->v_buf);
     if (w->st) (void)hipStreamDestroy(w->st);
     *w = Worker();
 }
@@ -471,11 +584,14 @@ extern "C" rsrr_status rsrr_server_create(rsrr_server** out, const rsrr_server_c
     if (s->cfg.solvers == 0) s->cfg.solvers = 2;
     s->t0 = std::chrono::steady_clock::now();
     s->cfg.options = nullptr;  // read here only
-    rsrr_status e = worker_init(&s->ws, cfg->device, cfg->options);
-    const int nsolve = (cfg->flags & RSRR_SERVE_SERIAL) ? 0 : s->cfg.solvers;
+    if (s->cfg.solve_bytes == 0) s->cfg.solve_bytes = DEFAULT_SOLVE_BYTES;
+    const bool serial = (cfg->flags & RSRR_SERVE_SERIAL) != 0;
+    // the sampling context also runs Steps 3-5 in serial mode
+    rsrr_status e = worker_init(&s->ws, cfg->device, cfg->options, serial ? s->cfg.solve_bytes : 0);
+    const int nsolve = serial ? 0 : s->cfg.solvers;
     for (int i = 0; i < nsolve && !e; ++i) {
         s->wp.emplace_back(new Worker());
-        e = worker_init(s->wp.back().get(), cfg->device, cfg->options);
+        e = worker_init(s->wp.back().get(), cfg->device, cfg->options, s->cfg.solve_bytes);
     }
     if (!e && hipMalloc(&s->arena_base, cfg->arena_bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -493,24 +609,23 @@ extern "C" rsrr_status rsrr_server_create(rsrr_server** out, const rsrr_server_c
     return RSRR_OK;
 }
 
+extern "C" rsrr_status rsrr_server_footprint(const rsrr_server_config* cfg, const rsrr_request* req,
+                                             unsigned long long* bytes)
+{
+    if (!cfg) return -1;
+    if (!req || !request_ok(req)) return -2;
+    if (!bytes) return -3;
+    *bytes = layout_of(*req, cfg->prec).total;
+    return RSRR_OK;
+}
+
 extern "C" rsrr_status rsrr_server_submit(rsrr_server* s, const rsrr_request* r, int* id)
 {
     if (!s) return -1;
     if (!r) return -2;
     if (!id) return -3;
+    if (!request_ok(r)) return -2;
     const rsrr_nep& e = r->nep;
-    if (e.n < 1 || e.n > 8192) return -2;
-    if (e.kind == RSRR_T_SEPARABLE) {
-        if (e.J < 1 || e.J > MAX_TERMS || !e.A || e.lda < e.n || !e.terms) return -2;
-    } else if (e.kind == RSRR_T_HELMHOLTZ) {
-        if (!e.points || !(e.w > 0)) return -2;
-    } else {
-        return -2;
-    }
-    if (!(r->a > 0) || !(r->b > 0) || r->N < 1 || r->L < 1 || !r->U || r->ldu < e.n || r->max_eigs < 1 ||
-        !r->lambda || r->NQ < 0 || r->KQ < 0 || (r->NQ > 0 && r->NQ < 2 * std::max(r->KQ, 1) + 1) ||
-        !(r->delta >= 0 && r->delta < 1))
-        return -2;
     std::unique_ptr<Req> q(new Req());
     q->r = *r;
     if (e.kind == RSRR_T_SEPARABLE) q->terms.assign(e.terms, e.terms + e.J);
@@ -518,8 +633,11 @@ extern "C" rsrr_status rsrr_server_submit(rsrr_server* s, const rsrr_request* r,
     q->z.resize(2 * (size_t)r->N);
     const rsrr_status ce = rsrr_contour(r->gamma_re, r->gamma_im, r->a, r->b, r->N, q->z.data(), nullptr);
     if (ce) return -2;
-    q->s_bytes = (size_t)e.n * r->N * r->L * 16;
-    if ((q->s_bytes + ALIGN - 1) / ALIGN * ALIGN > s->cfg.arena_bytes) return RSRR_ENOMEM;
+    q->lay = layout_of(*r, s->cfg.prec);
+    q->s_bytes = q->lay.total;
+    q->res.footprint = q->lay.total;
+    q->res.L_used = r->L;
+    if (q->s_bytes > s->cfg.arena_bytes) return RSRR_ENOMEM;
     std::lock_guard<std::mutex> lk(s->mu);
     q->id = s->next_id++;
     q->res.id = q->id;
@@ -565,6 +683,8 @@ extern "C" rsrr_status rsrr_server_stats(rsrr_server* s, double* out)
     out[7] = (double)s->mem_peak;
     out[8] = now_s(s->t0);
     out[9] = (double)s->queue.size();
+    out[10] = (double)s->repoints;
+    out[11] = (double)s->reprobes;
     return RSRR_OK;
 }
 

@@ -43,7 +43,7 @@ EXPORTS = ["rsrr_create", "rsrr_destroy", "rsrr_contour", "rsrr_sample", "rsrr_s
            "rsrr_project", "rsrr_solve", "rsrr_last_timings", "rsrr_update_stats", "rsrr_version",
            "rsrr_two_stage", "rsrr_moments", "rsrr_server_create", "rsrr_server_submit", "rsrr_server_wait", "rsrr_server_stats",
            "rsrr_server_destroy", "rsrr_sample_gmres", "rsrr_options_init", "rsrr_set_options", "rsrr_get_options",
-           "rsrr_moments_noalloc"]
+           "rsrr_moments_noalloc", "rsrr_server_footprint"]
 RSRR_BATCH_GRAPH = 1
 RSRR_BATCH_AUTOTUNE = 2
 RSRR_SERVE_NO_BATCH = 1
@@ -98,7 +98,7 @@ OPTION_FIELDS = [f for f, _ in RsrrOptions._fields_ if f not in ("size", "versio
 class RsrrServerConfig(C.Structure):
     _fields_ = [("device", C.c_int), ("prec", C.c_int), ("max_slots", C.c_int), ("flags", C.c_int),
                 ("solvers", C.c_int), ("pad", C.c_int), ("arena_bytes", C.c_ulonglong),
-                ("batch_bytes", C.c_ulonglong), ("options", C.POINTER(RsrrOptions))]
+                ("batch_bytes", C.c_ulonglong), ("solve_bytes", C.c_ulonglong), ("options", C.POINTER(RsrrOptions))]
 
 
 class RsrrRequest(C.Structure):
@@ -106,14 +106,15 @@ class RsrrRequest(C.Structure):
                 ("b", C.c_double), ("N", C.c_int), ("L", C.c_int), ("U", C.c_void_p), ("ldu", C.c_int),
                 ("NQ", C.c_int), ("KQ", C.c_int), ("delta", C.c_double), ("max_eigs", C.c_int),
                 ("lambda_", C.POINTER(C.c_double)), ("resid", C.POINTER(C.c_double)),
-                ("V", C.POINTER(C.c_double))]
+                ("V", C.POINTER(C.c_double)), ("L_extra", C.c_int), ("pad", C.c_int)]
 
 
 class RsrrResult(C.Structure):
     _fields_ = [("id", C.c_int), ("status", C.c_int), ("count", C.c_int), ("k", C.c_int), ("nbar", C.c_int),
                 ("fallbacks", C.c_int), ("ir_iters_max", C.c_int), ("launches", C.c_int),
                 ("sample_resid_max", C.c_double), ("t_submit", C.c_double), ("t_admit", C.c_double),
-                ("t_sampled", C.c_double), ("t_done", C.c_double)]
+                ("t_sampled", C.c_double), ("t_done", C.c_double), ("reprobes", C.c_int), ("L_used", C.c_int),
+                ("footprint", C.c_ulonglong)]
 
 
 class RsrrError(RuntimeError):
@@ -163,6 +164,8 @@ def lib():
     L.rsrr_moments_noalloc.argtypes = L.rsrr_moments.argtypes
     L.rsrr_server_create.argtypes = [C.POINTER(vp), C.POINTER(RsrrServerConfig)]
     L.rsrr_server_submit.argtypes = [vp, C.POINTER(RsrrRequest), ip]
+    L.rsrr_server_footprint.argtypes = [C.POINTER(RsrrServerConfig), C.POINTER(RsrrRequest),
+                                        C.POINTER(C.c_ulonglong)]
     L.rsrr_server_wait.argtypes = [vp, C.c_int, C.c_double, C.POINTER(RsrrResult)]
     L.rsrr_server_stats.argtypes = [vp, dp]
     L.rsrr_server_destroy.argtypes = [vp]
@@ -562,20 +565,18 @@ class Server:
     buffer of a request alive until wait() has returned it."""
 
     def __init__(self, device=0, prec=RSRR_PREC_C64_IR, max_slots=8, arena_bytes=16 << 30,
-                 batch_bytes=24 << 30, flags=0, solvers=0, options=None):
+                 batch_bytes=24 << 30, flags=0, solvers=0, options=None, solve_bytes=0):
         L = lib()
         self._opt = options
         self.cfg = RsrrServerConfig(device, int(prec), int(max_slots), int(flags), int(solvers), 0,
-                                    int(arena_bytes), int(batch_bytes),
+                                    int(arena_bytes), int(batch_bytes), int(solve_bytes),
                                     C.pointer(options) if options is not None else None)
         self.h = C.c_void_p()
         _check("rsrr_server_create", L.rsrr_server_create(C.byref(self.h), C.byref(self.cfg)))
         self._live = {}
 
-    def submit(self, dnep, U, gamma, a, b, N, max_eigs=64, NQ=0, KQ=0, delta=0.0, want_V=False):
-        """U: device tensor (L, n) holding the n x L probes column-major.  Returns the request id."""
+    def _request(self, dnep, U, gamma, a, b, N, max_eigs, NQ, KQ, delta, L, L_extra, want_V):
         n = dnep.n
-        L = U.shape[0]
         lam = (C.c_double * (2 * max_eigs))()
         res = (C.c_double * max_eigs)()
         V = np.zeros((max_eigs, n), dtype=np.complex128) if want_V else None
@@ -583,11 +584,27 @@ class Server:
         g = complex(gamma)
         req = RsrrRequest(dnep.desc, g.real, g.imag, float(a), float(b), int(N), int(L), U.data_ptr(),
                           U.shape[1], int(NQ), int(KQ), float(delta), int(max_eigs),
-                          C.cast(lam, C.POINTER(C.c_double)), C.cast(res, C.POINTER(C.c_double)), vptr)
+                          C.cast(lam, C.POINTER(C.c_double)), C.cast(res, C.POINTER(C.c_double)), vptr,
+                          int(L_extra), 0)
+        return req, lam, res, V
+
+    def submit(self, dnep, U, gamma, a, b, N, max_eigs=64, NQ=0, KQ=0, delta=0.0, want_V=False, L_extra=0):
+        """U: device tensor (L + L_extra, n) holding the n x (L + L_extra) probes column-major; the
+        last L_extra columns are solved only on a re-probe.  Returns the request id."""
+        L = U.shape[0] - int(L_extra)
+        req, lam, res, V = self._request(dnep, U, gamma, a, b, N, max_eigs, NQ, KQ, delta, L, L_extra, want_V)
         rid = C.c_int(0)
         _check("rsrr_server_submit", lib().rsrr_server_submit(self.h, C.byref(req), C.byref(rid)))
         self._live[rid.value] = (dnep, U, lam, res, V, req)
         return rid.value
+
+    def footprint(self, dnep, U, gamma, a, b, N, max_eigs=64, L_extra=0):
+        """Bytes of the arena block that admission charges for this request."""
+        L = U.shape[0] - int(L_extra)
+        req, _, _, _ = self._request(dnep, U, gamma, a, b, N, max_eigs, 0, 0, 0.0, L, L_extra, False)
+        out = C.c_ulonglong(0)
+        _check("rsrr_server_footprint", lib().rsrr_server_footprint(C.byref(self.cfg), C.byref(req), C.byref(out)))
+        return out.value
 
     def wait(self, rid, timeout=-1.0):
         """Block until request rid has finished; returns its eigenpairs and timings."""
@@ -602,10 +619,10 @@ class Server:
         return r
 
     def stats(self):
-        out = (C.c_double * 10)()
+        out = (C.c_double * 12)()
         _check("rsrr_server_stats", lib().rsrr_server_stats(self.h, out))
         keys = ["finished", "points", "launches", "arena_peak_bytes", "max_launch_points", "sampler_busy_s",
-                "solver_busy_s", "device_mem_peak_bytes", "now_s", "queued"]
+                "solver_busy_s", "device_mem_peak_bytes", "now_s", "queued", "reprobe_points", "reprobes"]
         return dict(zip(keys, list(out)))
 
     def close(self):

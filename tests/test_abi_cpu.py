@@ -68,7 +68,7 @@ def test_argument_errors_without_device(lib):
 
 def test_server_argument_errors_without_device(lib):
     from paper_1605_07951_amd import rsrr
-    cfg = rsrr.RsrrServerConfig(0, 1, 0, 0, 0, 0, 1 << 20, 1 << 20, None)  # max_slots = 0
+    cfg = rsrr.RsrrServerConfig(0, 1, 0, 0, 0, 0, 1 << 20, 1 << 20, 0, None)  # max_slots = 0
     h = C.c_void_p()
     assert lib.rsrr_server_create(None, C.byref(cfg)) == -1
     assert lib.rsrr_server_create(C.byref(h), None) == -2
@@ -84,6 +84,32 @@ def test_server_argument_errors_without_device(lib):
     assert lib.rsrr_server_wait(None, 1, 0.0, None) == -1
     assert lib.rsrr_server_stats(None, None) == -1
     assert lib.rsrr_server_destroy(None) == -1
+    b = C.c_ulonglong(0)
+    assert lib.rsrr_server_footprint(None, None, C.byref(b)) == -1
+    cfg = rsrr.RsrrServerConfig(0, 1, 1, 0, 0, 0, 1 << 30, 1 << 30)
+    assert lib.rsrr_server_footprint(C.byref(cfg), None, C.byref(b)) == -2
+
+
+def test_server_footprint_is_the_documented_sum(lib):
+    """rsrr_server_footprint (host only): S with the reserve columns + kept complex FP32 factors
+    (P x P, interchanges, diagonal-block inverses) + Q + V, each rounded up to 256 bytes."""
+    from paper_1605_07951_amd import rsrr
+    n, N, L, Lx, me = 200, 32, 4, 12, 64
+    dummy = (C.c_double * 2)()
+    nep = rsrr.RsrrNep(0, n, 3, C.cast(dummy, C.c_void_p), n, C.cast(C.pointer(rsrr.RsrrTerm()), C.POINTER(rsrr.RsrrTerm)),
+                       None, 0.0)
+    req = rsrr.RsrrRequest(nep, 0.0, 5.0, 4.0, 1.0, N, L, C.cast(dummy, C.c_void_p), n, 0, 0, 0.0, me,
+                           C.cast(dummy, C.POINTER(C.c_double)), C.cast(dummy, C.POINTER(C.c_double)), None, Lx, 0)
+    al = lambda x: (x + 255) // 256 * 256
+    P = 256
+    npan = (P + 31) // 32
+    for prec, esz, inv in ((1, 8, 2 * 128 * (P + 128) * 8), (0, 16, 0)):
+        cfg = rsrr.RsrrServerConfig(0, prec, 1, 0, 0, 0, 1 << 30, 1 << 30)
+        b = C.c_ulonglong(0)
+        assert lib.rsrr_server_footprint(C.byref(cfg), C.byref(req), C.byref(b)) == 0
+        fac = al(N * P * P * esz) + al(N * npan * 2 * 128 * 8) + al(N * inv)
+        want = al(n * N * (L + Lx) * 16) + fac + al(n * min(n, N * (L + Lx)) * 16) + al(n * me * 16)
+        assert b.value == want
 
 
 def test_server_structs_match_header(lib):

@@ -125,10 +125,17 @@ def test_serve_alone_equals_mix(R):
 
 
 def test_serve_admission_by_arena(R):
-    """An arena that holds one request's S at a time admits the next only after the first is done."""
+    """An arena that holds one request's footprint (S, kept factors, Q, V) at a time admits the next
+    only after the first is done; the reported footprint is rsrr_server_footprint's."""
     nep, C, dn, U = _qep(R, 0, n=128)
+    probe = R.Server(max_slots=1, arena_bytes=1 << 30, batch_bytes=1 << 30)
+    try:
+        fp = probe.footprint(dn, U, C.gamma, C.a, C.b, C.N, max_eigs=64)
+    finally:
+        probe.close()
     s_bytes = 128 * C.N * 16 * 16
-    srv = R.Server(max_slots=4, arena_bytes=s_bytes + 1024, batch_bytes=1 << 30)
+    assert fp > 3 * s_bytes        # the factors are kept: S is the small part
+    srv = R.Server(max_slots=4, arena_bytes=fp + 1024, batch_bytes=1 << 30)
     try:
         ids = [srv.submit(dn, U, C.gamma, C.a, C.b, C.N, max_eigs=64) for _ in range(3)]
         res = [srv.wait(i, 120.0) for i in ids]
@@ -138,21 +145,53 @@ def test_serve_admission_by_arena(R):
     for a, b in zip(res, res[1:]):
         assert b["t_admit"] >= a["t_done"]
         assert np.array_equal(a["lam"], b["lam"])
-    assert st["arena_peak_bytes"] <= s_bytes + 1024
+    assert all(r["footprint"] == fp for r in res)
+    assert st["arena_peak_bytes"] <= fp + 1024
 
 
 def test_serve_rejects_oversized_and_unknown(R):
     nep, C, dn, U = _qep(R, 0, n=128)
-    srv = R.Server(max_slots=1, arena_bytes=(1 << 20) - 4096, batch_bytes=1 << 30)
+    srv = R.Server(max_slots=1, arena_bytes=1 << 20, batch_bytes=1 << 30)
     try:
+        assert srv.footprint(dn, U, C.gamma, C.a, C.b, C.N) > (1 << 20)
         with pytest.raises(R.RsrrError) as e:
-            srv.submit(dn, U, C.gamma, C.a, C.b, C.N)   # S is 128*32*16*16 B = 1 MiB
+            srv.submit(dn, U, C.gamma, C.a, C.b, C.N)
         assert e.value.code == R.RSRR_ENOMEM
         with pytest.raises(R.RsrrError) as e:
             srv.wait(12345, 0.0)
         assert e.value.code == -2
     finally:
         srv.close()
+
+
+def test_serve_reprobe_from_kept_factors(R):
+    """QEP n = 200, N = 32, centre 5i (34 roots inside): one probe column (32 directions) cannot
+    resolve them, the residual check fails, and the 15 reserve columns are solved from the kept
+    factors (no new factorisation: the server factored 32 points, and solved 32 again); the result
+    then matches the closed form and the oracle's RSRR with 16 probes, and equals a request that
+    used all 16 columns from the start."""
+    nep, C, U16 = W.cfg_qep(n=200, N=32, L=16)
+    dn = R.DeviceNEP(nep)
+    Ud = R.colmajor(U16)[0]
+    srv = R.Server(max_slots=2, arena_bytes=4 << 30, batch_bytes=1 << 30)
+    try:
+        res = srv.wait(srv.submit(dn, Ud, C.gamma, C.a, C.b, C.N, max_eigs=64, want_V=True, L_extra=15), 120.0)
+        st = srv.stats()
+        full = srv.wait(srv.submit(dn, Ud, C.gamma, C.a, C.b, C.N, max_eigs=64), 120.0)
+    finally:
+        srv.close()
+    assert res["reprobes"] == 1 and res["L_used"] == 16
+    assert st["points"] == 32 and st["reprobe_points"] == 32 and st["reprobes"] == 1
+    _check_qep(res, nep, C)
+    prob = O.Problem(nep)
+    ro = O.rsrr(prob, C, U16)
+    oin = ro["lam"][ro["level"] < 0.98]
+    ins = O.level(res["lam"], C.gamma, C.a, C.b) < 0.98
+    assert _match(res["lam"][ins], oin) < 1e-9 and _match(oin, res["lam"][ins]) < 1e-9
+    for i in np.where(ins)[0]:
+        assert O.residual(prob, res["lam"][i], res["V"][:, i]) <= 1e-10
+    assert full["reprobes"] == 0 and full["k"] == res["k"]
+    assert _match(full["lam"][O.level(full["lam"], C.gamma, C.a, C.b) < 0.98], res["lam"][ins]) < 1e-9
 
 
 def test_serve_sequential_plain_fp64_matches(R):
