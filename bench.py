@@ -69,9 +69,14 @@ def parse():
     ap.add_argument("--requests", type=int, default=24, help="serve: requests taken from the stream")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: Poisson arrival rate (1/s)")
     ap.add_argument("--slots", type=int, default=8, help="serve: requests admitted at once")
-    ap.add_argument("--arena-gb", type=int, default=32, help="serve: HBM arena for S blocks (GiB)")
+    ap.add_argument("--arena-gb", type=int, default=150,
+                    help="serve: HBM arena for the requests' footprints (S, kept factors, Q, V) (GiB)")
     ap.add_argument("--batch-gb", type=int, default=48, help="serve: LU workspace cap per launch (GiB)")
     ap.add_argument("--solvers", type=int, default=0, help="serve: solve threads (0: library default)")
+    ap.add_argument("--serve-leg", type=int, default=24,
+                    help="default workload: requests of the serving leg run after the headline (0: none)")
+    ap.add_argument("--serve-slow-rate", type=float, default=1.5,
+                    help="default workload: the serving leg's second, sustainable arrival rate (1/s)")
     return ap.parse_args()
 
 
@@ -158,15 +163,37 @@ def phase_rooflines(n, N, L, tm, iters):
     return out
 
 
+def cpu_model():
+    """CPU model name and logical CPUs this process may run on (Linux)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, avail
+
+
 def cpu_baseline(nep, C, U, npts):
-    """Time the CPU oracle's sampling on npts points of the same workload."""
+    """Time the CPU oracle's sampling on npts points of the same workload.  `cores` is the
+    BLAS thread count the oracle's LAPACK calls ran with (threadpoolctl), never more than the
+    CPUs available to the process."""
     from oracle import rsrr_oracle as O
-    threads = os.cpu_count() or 1
+    model, avail = cpu_model()
+    threads = avail
+    blas = None
     try:
         from threadpoolctl import threadpool_info
-        info = threadpool_info()
+        info = [i for i in threadpool_info() if i.get("user_api") == "blas"] or threadpool_info()
         if info:
-            threads = max(int(i.get("num_threads", 1)) for i in info)
+            threads = min(avail, max(int(i.get("num_threads", 1)) for i in info))
+            blas = f"{info[0].get('internal_api')} {info[0].get('version')}"
     except Exception:
         pass
     prob = O.Problem(nep)
@@ -176,6 +203,7 @@ def cpu_baseline(nep, C, U, npts):
     O.sample(prob, pts, U)
     dt = time.perf_counter() - t0
     return {"value": npts / dt, "unit": "resolvent solves/s", "cores": threads, "kind": "oracle",
+            "cpu_model": model, "cpus_available": avail, "blas": blas,
             "sample": f"{npts} of {C.N} sampling points of the same workload (assembly + zgetrf + zgetrs, "
                       f"FP64, NumPy/SciPy LAPACK), {dt:.2f} s"}
 
@@ -185,76 +213,95 @@ def _pct(x, q):
     return float(np.percentile(np.asarray(x), q)) if len(x) else None
 
 
+def serving_items(requests, rate):
+    """The first `requests` entries of the seeded serving stream with their device inputs: one
+    DeviceNEP per (kind, n) (the NEP depends only on those), probes per request."""
+    import torch
+    import workloads as W
+    from paper_1605_07951_amd import rsrr as R
+
+    stream = W.cfg_serving_stream(count=requests, rate=rate)
+    neps, items = {}, []
+    for q in stream:
+        key = (q["kind"], q["n"])
+        if key not in neps:
+            neps[key] = R.DeviceNEP(W.serving_nep(q))
+        items.append((q, neps[key], R.colmajor(W.probes(q["n"], q["L"], q["seed"]))[0]))
+    torch.cuda.synchronize()
+    return items
+
+
+def serve_stream(items, label, prec, flags, slots, arena_gb, batch_gb, solvers=0, rate_scale=1.0):
+    """Submit the items at their arrival times (scaled by rate_scale: times are divided by it)
+    to a fresh server and wait for all; latency = result on the host minus submission."""
+    import threading
+    from paper_1605_07951_amd import rsrr as R
+
+    srv = R.Server(prec=prec, max_slots=slots, arena_bytes=arena_gb << 30, batch_bytes=batch_gb << 30,
+                   flags=flags, solvers=solvers)
+    ids = [None] * len(items)
+    t0 = time.perf_counter()
+
+    def feeder():
+        for i, (q, dn, U) in enumerate(items):
+            dt = q["t"] / rate_scale - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            ids[i] = srv.submit(dn, U, q["gamma"], q["a"], q["b"], q["N"], max_eigs=64)
+
+    th = threading.Thread(target=feeder)
+    th.start()
+    th.join()
+    res = []
+    for i in range(len(items)):
+        res.append(srv.wait(ids[i]))
+        r = res[-1]
+        print(f"[serve {label}] {i + 1}/{len(items)} {items[i][0]['kind']} n={items[i][0]['n']} "
+              f"latency {r['t_done'] - r['t_submit']:.3f}s status {r['status']}", file=sys.stderr, flush=True)
+    elapsed = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    lat = [r["t_done"] - r["t_submit"] for r in res]
+    t_first = min(r["t_submit"] for r in res)
+    makespan = max(r["t_done"] for r in res) - t_first
+    solves = sum(q["N"] for q, _, _ in items)
+    worst, n_inside = 0.0, 0
+    for (q, _, _), r in zip(items, res):
+        d = r["lam"] - complex(q["gamma"])
+        ins = (d.real / q["a"]) ** 2 + (d.imag / q["b"]) ** 2 < 0.98
+        n_inside += int(ins.sum())
+        if ins.any():
+            worst = max(worst, float(r["resid"][ins].max()))
+    span = items[-1][0]["t"] / rate_scale
+    out = {"requests": len(items), "offered_rate_per_s": round(len(items) / span, 3) if span > 0 else None,
+           "p50_latency_s": round(_pct(lat, 50), 4), "p99_latency_s": round(_pct(lat, 99), 4),
+           "mean_latency_s": round(float(np.mean(lat)), 4), "makespan_s": round(makespan, 3),
+           "mean_wait_admit_s": round(float(np.mean([r["t_admit"] - r["t_submit"] for r in res])), 4),
+           "mean_sampling_s": round(float(np.mean([r["t_sampled"] - r["t_admit"] for r in res])), 4),
+           "mean_post_s": round(float(np.mean([r["t_done"] - r["t_sampled"] for r in res])), 4),
+           "req_per_s": round(len(items) / makespan, 3), "solves_per_s": round(solves / makespan, 3),
+           "wall_s": round(elapsed, 3), "launches": int(st["launches"]),
+           "max_launch_points": int(st["max_launch_points"]), "sampler_busy_s": round(st["sampler_busy_s"], 3),
+           "solver_busy_s": round(st["solver_busy_s"], 3), "arena_peak_gb": round(st["arena_peak_bytes"] / 2**30, 3),
+           "device_mem_peak_gb": round(st["device_mem_peak_bytes"] / 2**30, 2),
+           "statuses": {str(k): int(v) for k, v in zip(*np.unique([r["status"] for r in res], return_counts=True))},
+           "eigs_inside": n_inside, "reprobes": int(st["reprobes"]),
+           "eig_resid_max_inside": worst, "fallback_points": int(sum(r["fallbacks"] for r in res))}
+    return out, solves
+
+
 def run_serve(args):
     """Serving stream: requests arrive (Poisson), the server batches their sampling points.
 
     Latency = result on the host minus submission (at the arrival time).  The
     same stream is then replayed through a sequential plain-FP64 server (one
     slot, no batching, no overlap) for comparison."""
-    import threading
-    import torch
-    import workloads as W
     from paper_1605_07951_amd import rsrr as R
 
-    stream = W.cfg_serving_stream(count=args.requests, rate=args.rate)
-    items = []
-    for q in stream:
-        items.append((q, R.DeviceNEP(W.serving_nep(q)), R.colmajor(W.probes(q["n"], q["L"], q["seed"]))[0]))
-    torch.cuda.synchronize()
+    items = serving_items(args.requests, args.rate)
     print(f"[serve] {len(items)} requests ready", file=sys.stderr, flush=True)
-
-    def run(label, prec, flags, slots):
-        srv = R.Server(prec=prec, max_slots=slots, arena_bytes=args.arena_gb << 30,
-                       batch_bytes=args.batch_gb << 30, flags=flags, solvers=args.solvers)
-        ids = [None] * len(items)
-        t0 = time.perf_counter()
-
-        def feeder():
-            for i, (q, dn, U) in enumerate(items):
-                dt = q["t"] - (time.perf_counter() - t0)
-                if dt > 0:
-                    time.sleep(dt)
-                ids[i] = srv.submit(dn, U, q["gamma"], q["a"], q["b"], q["N"], max_eigs=64)
-
-        th = threading.Thread(target=feeder)
-        th.start()
-        th.join()
-        res = []
-        for i in range(len(items)):
-            res.append(srv.wait(ids[i]))
-            r = res[-1]
-            print(f"[serve {label}] {i + 1}/{len(items)} {items[i][0]['kind']} n={items[i][0]['n']} "
-                  f"latency {r['t_done'] - r['t_submit']:.3f}s status {r['status']}", file=sys.stderr, flush=True)
-        elapsed = time.perf_counter() - t0
-        st = srv.stats()
-        srv.close()
-        lat = [r["t_done"] - r["t_submit"] for r in res]
-        t_first = min(r["t_submit"] for r in res)
-        makespan = max(r["t_done"] for r in res) - t_first
-        solves = sum(q["N"] for q, _, _ in items)
-        worst, n_inside = 0.0, 0
-        for (q, _, _), r in zip(items, res):
-            d = r["lam"] - complex(q["gamma"])
-            ins = (d.real / q["a"]) ** 2 + (d.imag / q["b"]) ** 2 < 0.98
-            n_inside += int(ins.sum())
-            if ins.any():
-                worst = max(worst, float(r["resid"][ins].max()))
-        out = {"p50_latency_s": round(_pct(lat, 50), 4), "p99_latency_s": round(_pct(lat, 99), 4),
-               "mean_latency_s": round(float(np.mean(lat)), 4), "makespan_s": round(makespan, 3),
-               "mean_wait_admit_s": round(float(np.mean([r["t_admit"] - r["t_submit"] for r in res])), 4),
-               "mean_sampling_s": round(float(np.mean([r["t_sampled"] - r["t_admit"] for r in res])), 4),
-               "mean_post_s": round(float(np.mean([r["t_done"] - r["t_sampled"] for r in res])), 4),
-               "req_per_s": round(len(items) / makespan, 3), "solves_per_s": round(solves / makespan, 3),
-               "wall_s": round(elapsed, 3), "launches": int(st["launches"]),
-               "max_launch_points": int(st["max_launch_points"]), "sampler_busy_s": round(st["sampler_busy_s"], 3),
-               "solver_busy_s": round(st["solver_busy_s"], 3), "arena_peak_gb": round(st["arena_peak_bytes"] / 2**30, 3),
-               "device_mem_peak_gb": round(st["device_mem_peak_bytes"] / 2**30, 2),
-               "statuses": {str(k): int(v) for k, v in zip(*np.unique([r["status"] for r in res], return_counts=True))},
-               "eigs_inside": n_inside,
-               "eig_resid_max_inside": worst, "fallback_points": int(sum(r["fallbacks"] for r in res))}
-        return out, solves
-
-    served, solves = run("mixed", R.RSRR_PREC_C64_IR, 0, args.slots)
+    served, solves = serve_stream(items, "mixed", R.RSRR_PREC_C64_IR, 0, args.slots, args.arena_gb, args.batch_gb,
+                                  args.solvers)
     res = {
         "metric": METRIC,
         "value": served["solves_per_s"],
@@ -277,7 +324,8 @@ def run_serve(args):
         "serving": served,
     }
     if not args.no_plain:
-        seq, _ = run("fp64-seq", R.RSRR_PREC_C128, R.RSRR_SERVE_NO_BATCH | R.RSRR_SERVE_SERIAL, 1)
+        seq, _ = serve_stream(items, "fp64-seq", R.RSRR_PREC_C128, R.RSRR_SERVE_NO_BATCH | R.RSRR_SERVE_SERIAL, 1,
+                              args.arena_gb, args.batch_gb)
         res["sequential_plain_fp64"] = seq
         res["speedup_vs_sequential_fp64"] = {
             "solves_per_s": round(served["solves_per_s"] / seq["solves_per_s"], 3),
@@ -818,16 +866,49 @@ def main():
                                             " + rsrr_solve (eigenpairs and residuals on the host)"}
 
     if not args.no_plain and prec == R.RSRR_PREC_C64_IR:
-        # plain FP64 path on the same inputs for the mixed/plain speedup
+        # plain FP64 path on the same inputs for the mixed/plain speedup, with the roofline of its
+        # trailing update (FP64 MFMA, 4M form: 8 m^2 k flops per complex update, all on the matrix cores)
         R.rsrr_sample(ctx, dnep, z, U, prec=R.RSRR_PREC_C128, S=S)
         torch.cuda.synchronize()
+        R.rsrr_update_stats(ctx, enable=True, reset=True)
         t1 = time.perf_counter()
         R.rsrr_sample(ctx, dnep, z, U, prec=R.RSRR_PREC_C128, S=S)
         torch.cuda.synchronize()
         dtp = time.perf_counter() - t1
+        pst = R.rsrr_update_stats(ctx, enable=False)
+        ptm = ctx.timings()
         res["plain_c128_sample_solves_per_s"] = round(N / dtp, 3)
         if res["sample_solves_per_s"]:
             res["mixed_over_plain_speedup"] = round(res["sample_solves_per_s"] / (N / dtp), 3)
+        if pst["ms"] > 0:
+            pach = pst["flops"] / (pst["ms"] * 1e-3) / 1e12
+            lu_all = N * (8.0 / 3.0) * float(n) ** 3
+            res["plain_c128_roofline"] = {
+                "bound": "mfma", "kernel": "LU trailing update, complex FP64 (zgemm_mfma_kernel<0,0,1>)",
+                "achieved": round(pach, 3), "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(pach / PEAK_FP64_MFMA_TFLOPS, 4), "launches": pst["launches"],
+                "avg_launch_ms": round(pst["ms"] / max(1, pst["launches"]), 4),
+                "flops_per_launch": pst["flops"] / max(1, pst["launches"]),
+                "lu_phase_ms": round(ptm["lu_ms"], 3),
+                "lu_phase_TFLOP_s": round(lu_all / (ptm["lu_ms"] * 1e-3) / 1e12, 3) if ptm["lu_ms"] > 0 else None,
+                "phase_ms": {k: round(v, 3) for k, v in ptm.items()}}
+
+    if args.serve_leg > 0 and args.workload == "helmholtz" and prec == R.RSRR_PREC_C64_IR:
+        # p50/p99 under load: the first requests of the seeded serving stream at the stated 20/s
+        # (over capacity: backlog) and at a sustainable rate
+        del S
+        ctx.close()
+        torch.cuda.empty_cache()
+        items = serving_items(args.serve_leg, args.rate)
+        fast, _ = serve_stream(items, "20/s", R.RSRR_PREC_C64_IR, 0, args.slots, args.arena_gb, args.batch_gb,
+                               args.solvers)
+        slow, _ = serve_stream(items, "sustainable", R.RSRR_PREC_C64_IR, 0, args.slots, args.arena_gb,
+                               args.batch_gb, args.solvers, rate_scale=args.serve_slow_rate / args.rate)
+        res["serving"] = {"what": f"first {len(items)} requests of the seeded serving stream (50/50 delay n "
+                                  f"512/1024/2048 N=48 L=32 / Helmholtz n 2048/4096/8192 N=64 L=64), whole "
+                                  f"method per request, latency = submission to eigenpairs on the host",
+                          "rate_20_per_s": fast, f"rate_{args.serve_slow_rate:g}_per_s": slow}
+        del items
 
     if not args.no_cpu:
         npts = args.cpu_points or (4 if n >= 2048 else min(N, 16))

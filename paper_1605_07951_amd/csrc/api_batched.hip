@@ -44,6 +44,8 @@ struct GraphEntry {
 constexpr int N_BUCKET_STREAMS = 8;  // replayed buckets run side by side on these (default priority)
 
 struct BatchedState {
+    std::map<int, long> last_use;                 // bucket size P -> call counter of its last use
+    long calls = 0;
     std::map<long, int> tuned;                    // (P*2 + prec) -> nb
     std::map<long, std::unique_ptr<GraphEntry>> graphs;  // bucket P*2+prec -> captured graph
     std::vector<void*> bufs;
@@ -319,6 +321,7 @@ rsrr_status bucket_bufs(BatchedState& S, hipStream_t sm, int P, int Lmax, long M
     const long nparts_max = ((long)maxn * maxn + 255) / 256;
     // every bucket size has its own buffers (graphs keep pointing at them, and the
     // buckets of one call run side by side)
+    S.last_use[P] = S.calls;
     int s = (P / BUCKET) * 32;
     b.T = from ? (void*)(s++, nullptr) : bget(S, s++, (size_t)M * b.sT * esz, sm);
     b.T128 = (double2*)bget(S, s++, (size_t)M * b.sT * 16, sm);
@@ -422,6 +425,7 @@ rsrr_status batched_impl(rsrr_ctx* c, int count, const rsrr_instance* inst, int 
 {
     RSRR_HIP(hipSetDevice(c->device));
     BatchedState& S = state_of(c);
+    ++S.calls;
     load_tune_file(S);
     const bool use_graph = (flags & RSRR_BATCH_GRAPH) != 0 && !keep;
     const bool autotune = (flags & RSRR_BATCH_AUTOTUNE) != 0;
@@ -628,6 +632,7 @@ rsrr_status solve_from_store(rsrr_ctx* c, const rsrr_instance& in, const FactorS
     if (fs.P != P || fs.nb < MIN_NB || k0 < 0 || k0 + in.N > fs.N) return -3;
     RSRR_HIP(hipSetDevice(c->device));
     BatchedState& S = state_of(c);
+    ++S.calls;
     const bool mixed = fs.prec == RSRR_PREC_C64_IR;
     std::vector<int> ids{0};
     std::vector<long> off{0, in.N};
@@ -682,15 +687,41 @@ FactorStore factor_store_at(void* base, int n, int N, int prec)
 
 void batched_trim(rsrr_ctx* c, size_t keep_bytes)
 {
+    std::lock_guard<std::mutex> lk(states_mu());
+    auto it = states().find(c);
+    if (it == states().end()) return;
+    BatchedState& S = *it->second;
     size_t tot = 0;
-    {
-        std::lock_guard<std::mutex> lk(states_mu());
-        auto it = states().find(c);
-        if (it == states().end()) return;
-        for (size_t x : it->second->sizes) tot += x;
-    }
-    if (tot > keep_bytes) {
-        (void)hipStreamSynchronize(c->stream);
-        batched_release(c);
+    for (size_t x : S.sizes) tot += x;
+    if (tot <= keep_bytes) return;
+    // free whole bucket sizes, least recently used first; the sizes of the last call stay
+    // unless nothing else is left to free
+    std::vector<std::pair<long, int>> order;  // (last use, P)
+    for (auto& kv : S.last_use) order.push_back({kv.second, kv.first});
+    std::sort(order.begin(), order.end());
+    (void)hipStreamSynchronize(c->stream);
+    for (int i = 0; i < N_BUCKET_STREAMS; ++i)
+        if (S.streams[i]) (void)hipStreamSynchronize(S.streams[i]);
+    for (int pass = 0; pass < 2 && tot > keep_bytes; ++pass) {
+        for (auto& u : order) {
+            if (tot <= keep_bytes) break;
+            if (pass == 0 && u.first == S.calls) continue;
+            const int P = u.second;
+            const long tkey0 = (long)P * 2, tkey1 = tkey0 + 1;
+            for (long tk : {tkey0, tkey1}) {
+                auto g = S.graphs.find(tk);
+                if (g != S.graphs.end()) {
+                    if (g->second && g->second->exec) (void)hipGraphExecDestroy(g->second->exec);
+                    S.graphs.erase(g);
+                }
+            }
+            const int s0 = (P / BUCKET) * 32;
+            for (int sl = s0; sl < s0 + 32 && sl < (int)S.bufs.size(); ++sl) {
+                if (S.bufs[sl]) (void)hipFree(S.bufs[sl]);
+                tot -= S.sizes[sl];
+                S.bufs[sl] = nullptr;
+                S.sizes[sl] = 0;
+            }
+        }
     }
 }
