@@ -75,7 +75,28 @@ rsrr_status rsrr_create(rsrr_ctx** ctx, int device, void* stream)
     if (const char* e = std::getenv("RSRR_WS_BUDGET_MB")) c->ws_budget = (size_t)std::strtoull(e, nullptr, 10) << 20;
     for (auto& e : c->ev)
         if (hipEventCreate(&e) != hipSuccess) { delete c; return RSRR_EDEVICE; }
+    if (const char* e = std::getenv("RSRR_LOOKAHEAD")) c->lookahead = std::atoi(e) != 0;
+    if (const char* e = std::getenv("RSRR_LA_CUS")) c->la_cus = std::atoi(e);
+    if (const char* e = std::getenv("RSRR_LA_COLS")) c->la_cols = std::atoi(e);
+    {
+        // the overlapped updates run on every CU but the first la_cus, which stay free for
+        // the look-ahead's panel kernels
+        hipDeviceProp_t prop;
+        const int ncu = hipGetDeviceProperties(&prop, device) == hipSuccess ? prop.multiProcessorCount : 0;
+        if (c->la_cus > 0 && c->la_cus < ncu) {
+            std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
+            for (int i = c->la_cus; i < ncu; ++i) mask[i / 32] |= 1u << (i % 32);
+            if (hipExtStreamCreateWithCUMask(&c->upd, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
+                (void)hipGetLastError();
+                c->upd = nullptr;
+            }
+        }
+    }
     if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->la, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->la_a, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->la_b, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->la_c, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->join, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->offset, hipEventDisableTiming) != hipSuccess) {
@@ -170,6 +191,11 @@ rsrr_status rsrr_destroy(rsrr_ctx* c)
         if (c->ws[s]) (void)hipFree(c->ws[s]);
     for (auto& e : c->ev) (void)hipEventDestroy(e);
     if (c->aux) (void)hipStreamDestroy(c->aux);
+    if (c->la) (void)hipStreamSynchronize(c->la), (void)hipStreamDestroy(c->la);
+    if (c->la_a) (void)hipEventDestroy(c->la_a);
+    if (c->la_b) (void)hipEventDestroy(c->la_b);
+    if (c->la_c) (void)hipEventDestroy(c->la_c);
+    if (c->upd) (void)hipStreamSynchronize(c->upd), (void)hipStreamDestroy(c->upd);
     if (c->fork) (void)hipEventDestroy(c->fork);
     if (c->join) (void)hipEventDestroy(c->join);
     if (c->offset) (void)hipEventDestroy(c->offset);
@@ -272,7 +298,9 @@ struct PhaseTimer {
 struct SampleBufs {
     void* Tlu; double2* Tres; int* ipiv; int2* perm; int2* tperm; int* info; double2* coef; double* frobp;
     double* frob; float2* D64; double2* R; double* norms; int* active; double2* zdev; void* inv; void* tmp;
-    void* pair;
+    void* pair; void* pair2;
+    hipStream_t la, upd; hipEvent_t la_a, la_b, la_c;
+    int la_cols;
     int ld, np, nb; long sT, sP, sPerm, sTP, nparts, sInv, sTmp, sPair;
     LUWork lu(const int* act, UpdateRecorder* rec) const
     {
@@ -280,6 +308,8 @@ struct SampleBufs {
         w.ipiv = ipiv; w.sP = sP; w.perm = perm; w.sPerm = sPerm; w.tperm = tperm; w.sTP = sTP; w.info = info;
         w.inv = inv; w.sInv = sInv; w.tmp = tmp; w.sTmp = sTmp; w.active = act; w.rec = rec;
         w.pair = pair; w.sPair = sPair; w.ldpair = ld;
+        w.pair2 = pair2; w.side = la; w.ev_a = la_a; w.ev_b = la_b; w.upd = upd; w.ev_c = la_c;
+        w.la_cols = la_cols;
         return w;
     }
 };
@@ -297,7 +327,7 @@ static size_t per_point_bytes(int n, int L, int prec)
     if (prec != RSRR_PREC_C128) {
         b += (size_t)np * 2 * 128 * 128 * 8 / 2;          // diagonal-block inverses (nb = 128: n/128 panels)
         b += (size_t)128 * std::max(n, L) * 8;            // scratch rows
-        b += (size_t)lu_pair_elems(n, 128, (int)ld) * 8;  // paired trailing updates
+        b += (size_t)lu_pair_elems(n, 128, (int)ld) * 8 * 2;  // paired trailing updates (two for the look-ahead)
     }
     return b;
 }
@@ -314,8 +344,16 @@ static rsrr_status alloc_bufs(rsrr_ctx* c, int n, int L, int J, int prec, int B,
     s.inv = fp32 ? ws_get(c, WS_B0, (size_t)B * s.sInv * 8) : nullptr;
     s.tmp = fp32 ? ws_get(c, WS_B1, (size_t)B * s.sTmp * 8) : nullptr;
     s.sPair = fp32 ? lu_pair_elems(n, max_panel<float>(), s.ld) : 0;  // any panel width the LU clamps to
-    s.pair = fp32 ? ws_get(c, WS_LUP, (size_t)B * s.sPair * 8) : nullptr;
+    const bool la = fp32 && c->lookahead;
+    s.pair = fp32 ? ws_get(c, WS_LUP, (size_t)B * s.sPair * 8 * (la ? 2 : 1)) : nullptr;
     if (fp32 && (!s.inv || !s.tmp || !s.pair)) return RSRR_ENOMEM;
+    s.pair2 = la ? (char*)s.pair + (size_t)B * s.sPair * 8 : nullptr;
+    s.la = la ? c->la : nullptr;
+    s.la_a = c->la_a;
+    s.la_b = c->la_b;
+    s.la_c = c->la_c;
+    s.upd = la ? c->upd : nullptr;
+    s.la_cols = c->la_cols;
     s.sT = (long)s.ld * n;
     s.sP = n;
     s.sPerm = (long)s.np * 2 * MAX_NB;
@@ -406,6 +444,7 @@ static LUWork lu_offset(const LUWork& w, long b0, int esz = 8)
     if (w.inv) o.inv = (char*)w.inv + b0 * w.sInv * esz;
     if (w.tmp) o.tmp = (char*)w.tmp + b0 * w.sTmp * esz;
     if (w.pair) o.pair = (char*)w.pair + b0 * w.sPair * esz;
+    if (w.pair2) o.pair2 = (char*)w.pair2 + b0 * w.sPair * esz;
     if (w.active) o.active = w.active + b0;
     return o;
 }

@@ -27,6 +27,12 @@ struct rsrr_ctx {
     hipStream_t aux = nullptr;       // second stream (default priority) for the second point group
     hipEvent_t fork = nullptr, join = nullptr, offset = nullptr;
     int groups = 1;                  // point groups factored on separate streams (1 = off; measured no overlap)
+    hipStream_t la = nullptr;        // look-ahead stream of the LU (default priority): next panels beside the update
+    hipEvent_t la_a = nullptr, la_b = nullptr, la_c = nullptr;
+    hipStream_t upd = nullptr;       // CU-masked stream for the overlapped updates (null: no mask)
+    bool lookahead = true;           // RSRR_LOOKAHEAD=0 at creation turns it off
+    int la_cus = 32;                 // CUs the overlapped updates leave to the look-ahead (RSRR_LA_CUS)
+    int la_cols = 0;                 // columns of each overlapped update on the masked stream (RSRR_LA_COLS)
     void* ws[WS_COUNT] = {};
     size_t ws_size[WS_COUNT] = {};
     hipEvent_t ev[2] = {};

@@ -60,6 +60,17 @@ struct LUWork {
     UpdateRecorder* rec = nullptr;
     hipEvent_t first_panel = nullptr;  // recorded once the first panel and its row block are done
     void* pair = nullptr; long sPair = 0; int ldpair = 0;
+    // look-ahead (FP32 paths with pairs): a second pair buffer (same stride), a side
+    // stream and two events; the next pair's panels are then factored on `side`
+    // while the trailing update of the current pair runs on the main stream.
+    void* pair2 = nullptr;
+    hipStream_t side = nullptr;
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;
+    // optional: a stream whose CU mask leaves some CUs to `side`; the bulk of each
+    // overlapped update runs on it (event ev_c joins it back)
+    hipStream_t upd = nullptr;
+    hipEvent_t ev_c = nullptr;
+    int la_cols = 0;                   // columns of each overlapped update on `upd` (0: all)
 };
 // Elements per matrix of the pair buffer for n x n matrices and panel width nb.
 inline long lu_pair_elems(int n, int nb, int ldpair) { return (long)ldpair * 2 * nb + (long)nb * nb; }

@@ -17,6 +17,7 @@
 // Pivot: largest |Re| + |Im| in the column, lowest row index on ties
 // (LAPACK's choice).  info = first column (1-based) whose pivot is exactly
 // zero; the factorisation continues past it, as getrf does.
+#include <algorithm>
 #include <climits>
 
 #include "common.h"
@@ -666,25 +667,30 @@ static hipError_t getrf_impl(hipStream_t st, C* A, long sA, int lda, int n, int 
     if (nb > max_panel<R>()) nb = max_panel<R>();
     if (nb < MIN_NB) nb = MIN_NB;  // perm/inv storage holds perm_panels(n) panels
     UpdateRecorder* rec = w.rec;
-    auto timed_update = [&](int rest, int kdepth, const C* Aop, int ldaop, long sAop, const C* Bop, C* Cop) {
+    // trailing update C(M x N) -= Aop(M x kdepth) Bop(kdepth x N) on `st`, event-timed
+    auto timed_update_on = [&](hipStream_t s, int M, int N, int kdepth, const C* Aop, int ldaop, long sAop,
+                               const C* Bop, C* Cop) {
         const bool timed = rec && rec->used < rec->cap;
-        if (timed) (void)hipEventRecord(rec->ev[2 * rec->used], st);
-        (void)gemm_sub<C>(st, rest, rest, kdepth, Aop, ldaop, sAop, Bop, lda, sA, Cop, lda, sA, batch, 1);
+        if (timed) (void)hipEventRecord(rec->ev[2 * rec->used], s);
+        (void)gemm_sub<C>(s, M, N, kdepth, Aop, ldaop, sAop, Bop, lda, sA, Cop, lda, sA, batch, 1);
         if (timed) {
-            (void)hipEventRecord(rec->ev[2 * rec->used + 1], st);
+            (void)hipEventRecord(rec->ev[2 * rec->used + 1], s);
             rec->used++;
-            rec->flops += (elem_traits<C>::complex ? 8.0 : 2.0) * rest * (double)rest * kdepth * batch;
+            rec->flops += (elem_traits<C>::complex ? 8.0 : 2.0) * M * (double)N * kdepth * batch;
         } else if (rec) {
             rec->dropped++;
         }
     };
-    // panel p: factor, composed interchanges, diagonal-block inverses (FP32 paths)
-    auto panel = [&](int c0, int jb, int p) -> int2* {
-        factor_panel<C>(st, A, sA, lda, n, c0, jb, w.ipiv, w.sP, w.info, w.tperm, w.sTP, 0, w.active, batch);
+    auto timed_update = [&](int M, int N, int kdepth, const C* Aop, int ldaop, long sAop, const C* Bop, C* Cop) {
+        timed_update_on(st, M, N, kdepth, Aop, ldaop, sAop, Bop, Cop);
+    };
+    // panel p on stream s: factor, composed interchanges, diagonal-block inverses (FP32 paths)
+    auto panel = [&](hipStream_t s, int c0, int jb, int p) -> int2* {
+        factor_panel<C>(s, A, sA, lda, n, c0, jb, w.ipiv, w.sP, w.info, w.tperm, w.sTP, 0, w.active, batch);
         int2* pm = w.perm + (long)p * 2 * MAX_NB;
-        hipLaunchKernelGGL(perm_build_kernel, dim3(batch), dim3(64), 0, st, w.ipiv, w.sP, c0, jb, pm, w.sPerm,
+        hipLaunchKernelGGL(perm_build_kernel, dim3(batch), dim3(64), 0, s, w.ipiv, w.sP, c0, jb, pm, w.sPerm,
                            w.active);
-        if constexpr (use_inv) tri_inv<C>(st, A, sA, lda, c0, jb, (C*)w.inv, w.sInv, nb, w.active, batch);
+        if constexpr (use_inv) tri_inv<C>(s, A, sA, lda, c0, jb, (C*)w.inv, w.sInv, nb, w.active, batch);
         return pm;
     };
     // Two panels may share one trailing update of depth jb0 + jb1 (the deeper
@@ -695,11 +701,97 @@ static hipError_t getrf_impl(hipStream_t st, C* A, long sA, int lda, int n, int 
     // receive panel p's update from that copy; then A22 -= [L21_p' L21_{p+1}]
     // [U12_p; U12_{p+1}] in one product.
     const bool pairing = use_inv && w.pair != nullptr;
-    for (int c0 = 0, p = 0; c0 < n;) {
+    int c0 = 0, p = 0;
+    // Look-ahead over full pairs (two nb-wide panels with a trailing block after
+    // them).  A pair's work splits into a front part that touches only its own
+    // 2 nb columns (panel p, its interchanges and U rows on panel p+1's columns,
+    // panel p+1's columns update, panel p+1, the interchanged copy of L21_p) and
+    // a back part on the trailing columns (the interchanges and U rows of both
+    // panels there, the copy of L21_{p+1}).  After the back part of pair i, the
+    // trailing update is split: first the 2 nb columns of pair i+1, then, while
+    // the rest of the update runs on `st`, pair i+1's front part runs on the side
+    // stream (its own pair buffer); the next back part waits for both.
+    if (pairing && w.side && w.pair2 && w.ev_a && w.ev_b && n > 2 * nb) {
+        C* Wb[2] = {(C*)w.pair, (C*)w.pair2};
+        const int ldw = w.ldpair;
+        auto front = [&](hipStream_t s, int q0, int pp, C* Wp) {
+            const int q1 = q0 + nb;
+            C* TL = Wp + (long)ldw * 2 * nb;
+            const int2* pm0 = panel(s, q0, nb, pp);
+            perm_rows<C>(s, pm0, w.sPerm, A + (long)q1 * lda, sA, lda, (C*)w.tmp, w.sTmp, nb, q0, nb, nb, w.active,
+                         batch);
+            (void)gemm_sub<C>(s, nb, nb, nb, panel_inv<C>(w, pp, nb, 0), nb, w.sInv, (const C*)w.tmp, nb, w.sTmp,
+                              A + q0 + (long)q1 * lda, lda, sA, batch, 0, -1.0, 0.0);
+            (void)gemm_sub<C>(s, n - q1, nb, nb, A + q1 + (long)q0 * lda, lda, sA, A + q0 + (long)q1 * lda, lda, sA,
+                              A + q1 + (long)q1 * lda, lda, sA, batch);
+            const int2* pm1 = panel(s, q1, nb, pp + 1);
+            copy_rows<C>(s, q1, n, nb, A + (long)q0 * lda, lda, sA, Wp, ldw, w.sPair, w.active, batch);
+            perm_rows<C>(s, pm1, w.sPerm, Wp, w.sPair, ldw, TL, w.sPair, nb, q1, nb, nb, w.active, batch);
+        };
+        auto back = [&](int q0, int pp, C* Wp) {
+            const int q1 = q0 + nb, q2 = q1 + nb, rest = n - q2;
+            C* TL = Wp + (long)ldw * 2 * nb;
+            const int2* pm0 = w.perm + (long)pp * 2 * MAX_NB;
+            const int2* pm1 = w.perm + (long)(pp + 1) * 2 * MAX_NB;
+            C* Ar2 = A + (long)q2 * lda;
+            perm_rows<C>(st, pm0, w.sPerm, Ar2, sA, lda, (C*)w.tmp, w.sTmp, nb, q0, nb, rest, w.active, batch);
+            (void)gemm_sub<C>(st, nb, rest, nb, panel_inv<C>(w, pp, nb, 0), nb, w.sInv, (const C*)w.tmp, nb, w.sTmp,
+                              Ar2 + q0, lda, sA, batch, 0, -1.0, 0.0);
+            perm_rows<C>(st, pm1, w.sPerm, Ar2, sA, lda, (C*)w.tmp, w.sTmp, nb, q1, nb, rest, w.active, batch);
+            (void)gemm_sub<C>(st, nb, rest, nb, TL, nb, w.sPair, Ar2 + q0, lda, sA, (C*)w.tmp, nb, w.sTmp, batch);
+            (void)gemm_sub<C>(st, nb, rest, nb, panel_inv<C>(w, pp + 1, nb, 0), nb, w.sInv, (const C*)w.tmp, nb,
+                              w.sTmp, Ar2 + q1, lda, sA, batch, 0, -1.0, 0.0);
+            copy_rows<C>(st, q2, n, nb, A + (long)q1 * lda, lda, sA, Wp + (long)ldw * nb, ldw, w.sPair, w.active,
+                         batch);
+        };
+        int buf = 0;
+        front(st, 0, 0, Wb[0]);
+        if (w.first_panel) (void)hipEventRecord(w.first_panel, st);
+        for (;;) {
+            const int c2 = c0 + 2 * nb, rest = n - c2;
+            back(c0, p, Wb[buf]);
+            C* Aop = Wb[buf] + c2;
+            const C* Bop = A + c0 + (long)c2 * lda;
+            C* Cop = A + c2 + (long)c2 * lda;
+            if (rest <= 2 * nb) {
+                // no full pair follows: one update, the loop below finishes the tail
+                timed_update(rest, rest, 2 * nb, Aop, ldw, w.sPair, Bop, Cop);
+                c0 = c2;
+                p += 2;
+                break;
+            }
+            const int wn = 2 * nb;
+            timed_update(rest, wn, 2 * nb, Aop, ldw, w.sPair, Bop, Cop);
+            (void)hipEventRecord(w.ev_a, st);
+            (void)hipStreamWaitEvent(w.side, w.ev_a, 0);
+            front(w.side, c2, p + 2, Wb[buf ^ 1]);
+            (void)hipEventRecord(w.ev_b, w.side);
+            if (w.upd && w.ev_c) {
+                // the first la_cols columns of the update on the CUs the side stream does not
+                // use (while the next panels are factored), the rest on every CU
+                const int n1 = w.la_cols > 0 ? std::min(rest - wn, w.la_cols) : rest - wn;
+                (void)hipStreamWaitEvent(w.upd, w.ev_a, 0);
+                timed_update_on(w.upd, rest, n1, 2 * nb, Aop, ldw, w.sPair, Bop + (long)wn * lda,
+                                Cop + (long)wn * lda);
+                (void)hipEventRecord(w.ev_c, w.upd);
+                (void)hipStreamWaitEvent(st, w.ev_c, 0);
+                if (n1 < rest - wn)
+                    timed_update(rest, rest - wn - n1, 2 * nb, Aop, ldw, w.sPair, Bop + (long)(wn + n1) * lda,
+                                 Cop + (long)(wn + n1) * lda);
+            } else {
+                timed_update(rest, rest - wn, 2 * nb, Aop, ldw, w.sPair, Bop + (long)wn * lda, Cop + (long)wn * lda);
+            }
+            (void)hipStreamWaitEvent(st, w.ev_b, 0);
+            c0 = c2;
+            p += 2;
+            buf ^= 1;
+        }
+    }
+    while (c0 < n) {
         const int jb0 = (n - c0 < nb) ? n - c0 : nb;
         const int c1 = c0 + jb0;
         const int jb1 = pairing ? ((n - c1 < nb) ? n - c1 : nb) : 0;
-        const int2* pm0 = panel(c0, jb0, p);
+        const int2* pm0 = panel(st, c0, jb0, p);
         const int rest0 = n - c1;
         if (rest0 > 0) {
             C* Ar = A + (long)c1 * lda;
@@ -716,7 +808,7 @@ static hipError_t getrf_impl(hipStream_t st, C* A, long sA, int lda, int n, int 
         const int c2 = c1 + jb1, rest2 = n - c2;
         if (jb1 <= 0 || rest2 <= 0) {
             if (rest0 > 0)
-                timed_update(rest0, jb0, A + c1 + (long)c0 * lda, lda, sA, A + c0 + (long)c1 * lda,
+                timed_update(rest0, rest0, jb0, A + c1 + (long)c0 * lda, lda, sA, A + c0 + (long)c1 * lda,
                              A + c1 + (long)c1 * lda);
             c0 = c1;
             p += 1;
@@ -728,7 +820,7 @@ static hipError_t getrf_impl(hipStream_t st, C* A, long sA, int lda, int n, int 
         // panel p+1's columns receive panel p's update, then panel p+1
         (void)gemm_sub<C>(st, rest0, jb1, jb0, A + c1 + (long)c0 * lda, lda, sA, A + c0 + (long)c1 * lda, lda, sA,
                           A + c1 + (long)c1 * lda, lda, sA, batch);
-        const int2* pm1 = panel(c1, jb1, p + 1);
+        const int2* pm1 = panel(st, c1, jb1, p + 1);
         // L21_p rows c1.. into the pair buffer, interchanged like panel p+1 (top rows to TL)
         copy_rows<C>(st, c1, n, jb0, A + (long)c0 * lda, lda, sA, Wp, ldw, w.sPair, w.active, batch);
         perm_rows<C>(st, pm1, w.sPerm, Wp, w.sPair, ldw, TL, w.sPair, nb, c1, jb1, jb0, w.active, batch);
@@ -742,7 +834,8 @@ static hipError_t getrf_impl(hipStream_t st, C* A, long sA, int lda, int n, int 
         // [L21_p' L21_{p+1}] side by side, one update of depth jb0 + jb1
         copy_rows<C>(st, c2, n, jb1, A + (long)c1 * lda, lda, sA, Wp + (long)ldw * jb0, ldw, w.sPair, w.active,
                      batch);
-        timed_update(rest2, jb0 + jb1, Wp + c2, ldw, w.sPair, A + c0 + (long)c2 * lda, A + c2 + (long)c2 * lda);
+        timed_update(rest2, rest2, jb0 + jb1, Wp + c2, ldw, w.sPair, A + c0 + (long)c2 * lda,
+                     A + c2 + (long)c2 * lda);
         c0 = c2;
         p += 2;
     }
