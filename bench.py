@@ -812,6 +812,16 @@ def main():
                                                         and n == 4096 and N == 64 and L == 64) else None),
                      "launches": st["launches"], "avg_launch_ms": round(avg_ms, 4),
                      "flops_per_launch": st["flops"] / max(1, st["launches"]),
+                     "algorithmic_bytes_per_launch": st["bytes"] / max(1, st["launches"]),
+                     **({"cu_masked_part": {
+                         "what": "the bulk of each update overlapped with the next panels runs on a stream "
+                                 "whose CU mask leaves one XCD to them: its rate is bounded by that CU share",
+                         "cu_share": round(st["masked_cu_share"], 4),
+                         "flops_share": round(st["masked_flops"] / st["flops"], 4) if st["flops"] else None,
+                         "achieved": round(st["masked_flops"] / (st["masked_ms"] * 1e-3) / 1e12, 3),
+                         "frac_of_its_cus": round(st["masked_flops"] / (st["masked_ms"] * 1e-3) / 1e12
+                                                  / (peak * st["masked_cu_share"]), 4)}}
+                        if st.get("masked_ms", 0) > 0 else {}),
                      **({"form": "3M: three real MFMA products per complex multiply-add; achieved counts the "
                                  "standard 8 real flops per complex multiply-add, the matrix cores execute 6",
                          "mfma_executed_frac": round(0.75 * achieved / peak, 4),

@@ -359,7 +359,7 @@ typedef struct {
 enum {
     RSRR_BATCH_GRAPH = 1,     /* capture each size bucket's work in a hipGraph; replay it when the
                                  same batch (same buffers, sizes and points) is submitted again   */
-    RSRR_BATCH_AUTOTUNE = 2   /* time the LU panel widths on the first call for each size bucket */
+    RSRR_BATCH_AUTOTUNE = 2   /* time panel widths x update tiles on the first call for each size bucket */
 };
 
 /* Resolvent sampling for a ragged batch of instances (RSRR Step 2, eq. hatS,
@@ -370,9 +370,15 @@ enum {
  * default 3); points above fallback_resid (default 1e-10) relative residual
  * are redone on the FP64 path.  info: host, sum of N entries in instance
  * order (may be NULL).  The library keeps per-bucket buffers (and graphs) in
- * the context until rsrr_destroy.  Panel widths chosen by the autotuner are
- * cached per (bucket, precision) and, when the environment variable
- * RSRR_TUNE_FILE names a file, read from and written to it.
+ * the context until rsrr_destroy.  With RSRR_BATCH_AUTOTUNE, the first call
+ * for a size bucket times one bucket pass for every candidate configuration
+ * (LU panel width 32/64/128 x workgroup tile of the complex FP32 trailing
+ * update: 3M 128x64, 3M 64x64, 4M 128x128, 4M 64x64, all four waves and two
+ * LDS stages; FP64: panel width 32/64) and keeps the fastest per (bucket,
+ * precision, device architecture); when the environment variable
+ * RSRR_TUNE_FILE names a file the choices are read from and written to it as
+ * JSON ({"arch": ..., "entries": [{"P", "prec", "nb", "update_tile",
+ * "update_tile_name", "ms"}, ...]}).
  * Status as rsrr_sample.  Errors: -2 count < 1, -3 an instance is invalid,
  * -4 prec. */
 RSRR_API rsrr_status rsrr_sample_batched(rsrr_ctx *ctx, int count, const rsrr_instance *inst, int prec, int flags,
@@ -580,10 +586,14 @@ RSRR_API rsrr_status rsrr_server_destroy(rsrr_server *srv);
 /* Device-event statistics of the LU trailing-update kernel (A22 -= L21 U12,
  * the matrix-core hot loop of rsrr_sample).  enable = 1 starts recording a
  * pair of events around every trailing-update launch of later rsrr_sample
- * calls, 0 stops; reset = 1 clears the totals.  out (host, 4 doubles, may be
+ * calls, 0 stops; reset = 1 clears the totals.  out (host, 8 doubles, may be
  * NULL): launches timed, summed kernel time in ms, algorithmic flops of the
- * timed launches (8 m^2 k per complex m x m x k update and matrix), launches
- * not timed (event pool exhausted).  Errors: -1 ctx NULL. */
+ * timed launches (8 m n k per complex m x n x k update and matrix), launches
+ * not timed (event pool exhausted), algorithmic bytes of the timed launches
+ * (the m x n block read and written once, the m x k and k x n operands read
+ * once), then of those launches the ones that ran on the look-ahead's
+ * CU-masked stream: their summed time (ms) and flops, and the fraction of
+ * the device's CUs that stream may use.  Errors: -1 ctx NULL. */
 RSRR_API rsrr_status rsrr_update_stats(rsrr_ctx *ctx, int enable, int reset, double *out);
 
 /* Library version string (static storage). */

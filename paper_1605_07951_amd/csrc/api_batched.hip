@@ -23,6 +23,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "ctx.h"
@@ -43,10 +44,26 @@ struct GraphEntry {
 
 constexpr int N_BUCKET_STREAMS = 8;  // replayed buckets run side by side on these (default priority)
 
+// One autotuned configuration of a size bucket: LU panel width, workgroup tile of
+// the complex FP32 trailing update, and the time of the bucket pass it won with.
+struct Tuned {
+    int nb = 0;
+    int tile = UPD_TILE_3M_128x64;
+    double ms = 0.0;
+};
+
+// Sets the update tile for the calling thread and restores the previous one.
+struct TileScope {
+    int prev;
+    explicit TileScope(int t) : prev(get_update_tile()) { set_update_tile(t); }
+    ~TileScope() { set_update_tile(prev); }
+};
+
 struct BatchedState {
     std::map<int, long> last_use;                 // bucket size P -> call counter of its last use
     long calls = 0;
-    std::map<long, int> tuned;                    // (P*2 + prec) -> nb
+    std::map<long, Tuned> tuned;                  // (P*2 + prec) -> panel width and update tile
+    std::string arch;                             // device architecture the tuned entries are for
     std::map<long, std::unique_ptr<GraphEntry>> graphs;  // bucket P*2+prec -> captured graph
     std::vector<void*> bufs;
     std::vector<size_t> sizes;
@@ -102,17 +119,58 @@ void* bget(BatchedState& S, int slot, size_t bytes, hipStream_t st)
     return p;
 }
 
-void load_tune_file(BatchedState& S)
+// The autotuner's cache (RSRR_TUNE_FILE): JSON, one entry per line,
+//   {"arch": "gfx950", "entries": [
+//    {"P": 320, "prec": "c64", "nb": 64, "update_tile": 1, "update_tile_name": "3m_64x64_4waves", "ms": 1.23},
+//    ...]}
+// Entries of another architecture are ignored when read.
+std::string device_arch(int device)
+{
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) { (void)hipGetLastError(); return "unknown"; }
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+void load_tune_file(BatchedState& S, int device)
 {
     if (S.file_loaded) return;
     S.file_loaded = true;
+    S.arch = device_arch(device);
     const char* f = std::getenv("RSRR_TUNE_FILE");
     if (!f) return;
     FILE* fp = std::fopen(f, "r");
     if (!fp) return;
-    long key;
-    int nb;
-    while (std::fscanf(fp, "%ld %d", &key, &nb) == 2) S.tuned[key] = nb;
+    char line[512];
+    std::string farch;
+    while (std::fgets(line, sizeof line, fp)) {
+        const char* a = std::strstr(line, "\"arch\":");
+        if (a) {
+            char buf[64] = {0};
+            if (std::sscanf(a, "\"arch\": \"%63[^\"]\"", buf) == 1) farch = buf;
+        }
+        const char* pp = std::strstr(line, "\"P\":");
+        if (!pp || farch != S.arch) continue;
+        int P = 0, nb = 0, tile = 0;
+        char prec[16] = {0};
+        double ms = 0.0;
+        const char* q;
+        if (std::sscanf(pp, "\"P\": %d", &P) != 1) continue;
+        if (!(q = std::strstr(line, "\"prec\":")) || std::sscanf(q, "\"prec\": \"%15[^\"]\"", prec) != 1) continue;
+        if (!(q = std::strstr(line, "\"nb\":")) || std::sscanf(q, "\"nb\": %d", &nb) != 1) continue;
+        if ((q = std::strstr(line, "\"update_tile\":"))) std::sscanf(q, "\"update_tile\": %d", &tile);
+        if ((q = std::strstr(line, "\"ms\":"))) std::sscanf(q, "\"ms\": %lf", &ms);
+        const bool mixed = std::strcmp(prec, "c64") == 0;
+        if (!mixed && std::strcmp(prec, "c128") != 0) continue;
+        if (nb < MIN_NB || nb > (mixed ? max_panel<float>() : max_panel<double>())) continue;
+        if (tile < 0 || tile >= UPD_TILE_COUNT) tile = UPD_TILE_3M_128x64;
+        Tuned t;
+        t.nb = nb;
+        t.tile = tile;
+        t.ms = ms;
+        S.tuned[(long)P * 2 + (mixed ? 1 : 0)] = t;
+    }
     std::fclose(fp);
 }
 
@@ -122,7 +180,16 @@ void save_tune_file(const BatchedState& S)
     if (!f) return;
     FILE* fp = std::fopen(f, "w");
     if (!fp) return;
-    for (auto& kv : S.tuned) std::fprintf(fp, "%ld %d\n", kv.first, kv.second);
+    std::fprintf(fp, "{\"arch\": \"%s\", \"entries\": [\n", S.arch.c_str());
+    size_t i = 0;
+    for (auto& kv : S.tuned) {
+        const int P = (int)(kv.first / 2);
+        const bool mixed = (kv.first & 1) != 0;
+        std::fprintf(fp, " {\"P\": %d, \"prec\": \"%s\", \"nb\": %d, \"update_tile\": %d, \"update_tile_name\": \"%s\", "
+                     "\"ms\": %.4f}%s\n", P, mixed ? "c64" : "c128", kv.second.nb, kv.second.tile,
+                     update_tile_name(kv.second.tile), kv.second.ms, ++i < S.tuned.size() ? "," : "");
+    }
+    std::fprintf(fp, "]}\n");
     std::fclose(fp);
 }
 
@@ -424,9 +491,10 @@ rsrr_status batched_impl(rsrr_ctx* c, int count, const rsrr_instance* inst, int 
                          rsrr_point_info* info, FactorStore* const* keep, const int* keep_k0)
 {
     RSRR_HIP(hipSetDevice(c->device));
+    masked_stream_release(c);  // a CU-masked stream would cost the buckets' streams their concurrency
     BatchedState& S = state_of(c);
     ++S.calls;
-    load_tune_file(S);
+    load_tune_file(S, c->device);
     const bool use_graph = (flags & RSRR_BATCH_GRAPH) != 0 && !keep;
     const bool autotune = (flags & RSRR_BATCH_AUTOTUNE) != 0;
     const bool mixed = prec == RSRR_PREC_C64_IR;
@@ -480,37 +548,49 @@ rsrr_status batched_impl(rsrr_ctx* c, int count, const rsrr_instance* inst, int 
         rsrr_status bs = bucket_bufs(S, sm, P, Lmax, M, maxn, coef.size(), mixed, false, b);
         if (bs) return bs;
 
-        // panel width: tuned (timed over the candidates on this bucket) or default
+        // panel width and update tile: tuned (each candidate timed with one bucket pass) or default
         const long tkey = (long)P * 2 + (mixed ? 1 : 0);
         int nb = mixed ? std::min(c->nb_c64, nbmax) : std::min(c->nb_c128, nbmax);
+        int tile = UPD_TILE_3M_128x64;
         auto tu = S.tuned.find(tkey);
         if (tu != S.tuned.end()) {
-            nb = tu->second;
+            nb = tu->second.nb;
+            tile = tu->second.tile;
         } else if (autotune) {
-            std::vector<int> cand = mixed ? std::vector<int>{32, 64, 128} : std::vector<int>{32, 64};
+            std::vector<int> nbs = mixed ? std::vector<int>{32, 64, 128} : std::vector<int>{32, 64};
+            std::vector<int> tiles = mixed ? std::vector<int>{UPD_TILE_3M_128x64, UPD_TILE_3M_64x64,
+                                                              UPD_TILE_4M_128x128, UPD_TILE_4M_64x64}
+                                           : std::vector<int>{UPD_TILE_3M_128x64};
             float best = 1e30f;
-            int bestnb = nb;
+            Tuned bt;
+            bt.nb = nb;
             hipEvent_t e0, e1;
             RSRR_HIP(hipEventCreate(&e0));
             RSRR_HIP(hipEventCreate(&e1));
-            for (int cb : cand) {
+            for (int cb : nbs) {
                 if (cb > nbmax) continue;
-                // one full bucket pass (assembly, LU, one solve, one residual) per candidate
-                RSRR_HIP(hipEventRecord(e0, sm));
-                rsrr_status st = run_bucket(c, sm, inst, ids, off, P, Lmax, M, prec, cb, b, coef.data(), nk.data(), 0);
-                if (st) return st;
-                RSRR_HIP(hipEventRecord(e1, sm));
-                RSRR_HIP(hipEventSynchronize(e1));
-                float ms = 0.f;
-                RSRR_HIP(hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best) { best = ms; bestnb = cb; }
+                for (int ct : tiles) {
+                    // one full bucket pass (assembly, LU, one solve, one residual) per candidate
+                    TileScope ts(ct);
+                    RSRR_HIP(hipEventRecord(e0, sm));
+                    rsrr_status st = run_bucket(c, sm, inst, ids, off, P, Lmax, M, prec, cb, b, coef.data(),
+                                                nk.data(), 0);
+                    if (st) return st;
+                    RSRR_HIP(hipEventRecord(e1, sm));
+                    RSRR_HIP(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    RSRR_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    if (ms < best) { best = ms; bt.nb = cb; bt.tile = ct; bt.ms = ms; }
+                }
             }
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
-            nb = bestnb;
-            S.tuned[tkey] = nb;
+            nb = bt.nb;
+            tile = bt.tile;
+            S.tuned[tkey] = bt;
             save_tune_file(S);
         }
+        TileScope tile_scope(tile);
 
         const int maxit = c->ir_max_iters_batched;
         if (use_graph) {
@@ -519,6 +599,7 @@ rsrr_status batched_impl(rsrr_ctx* c, int count, const rsrr_instance* inst, int 
             key.push_back((unsigned long long)P);
             key.push_back((unsigned long long)prec);
             key.push_back((unsigned long long)nb);
+            key.push_back((unsigned long long)tile);
             key.push_back((unsigned long long)M);
             key.push_back((unsigned long long)maxit);
             unsigned long long tolbits;

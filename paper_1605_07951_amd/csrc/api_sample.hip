@@ -39,13 +39,21 @@ void rec_collect(rsrr_ctx* c)
     for (int i = 0; i < c->rec.used; ++i) {
         (void)hipEventSynchronize(c->rec.ev[2 * i + 1]);
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, c->rec.ev[2 * i], c->rec.ev[2 * i + 1]) == hipSuccess) c->upd_ms += ms;
+        if (hipEventElapsedTime(&ms, c->rec.ev[2 * i], c->rec.ev[2 * i + 1]) == hipSuccess) {
+            c->upd_ms += ms;
+            if (c->rec.lmask && c->rec.lmask[i]) {
+                c->upd_ms_masked += ms;
+                c->upd_flops_masked += c->rec.lflops[i];
+            }
+        }
     }
     c->upd_launches += c->rec.used;
     c->upd_flops += c->rec.flops;
+    c->upd_bytes += c->rec.bytes;
     c->upd_dropped += c->rec.dropped;
     c->rec.used = 0;
     c->rec.flops = 0.0;
+    c->rec.bytes = 0.0;
     c->rec.dropped = 0;
 }
 
@@ -78,20 +86,6 @@ rsrr_status rsrr_create(rsrr_ctx** ctx, int device, void* stream)
     if (const char* e = std::getenv("RSRR_LOOKAHEAD")) c->lookahead = std::atoi(e) != 0;
     if (const char* e = std::getenv("RSRR_LA_CUS")) c->la_cus = std::atoi(e);
     if (const char* e = std::getenv("RSRR_LA_COLS")) c->la_cols = std::atoi(e);
-    {
-        // the overlapped updates run on every CU but the first la_cus, which stay free for
-        // the look-ahead's panel kernels
-        hipDeviceProp_t prop;
-        const int ncu = hipGetDeviceProperties(&prop, device) == hipSuccess ? prop.multiProcessorCount : 0;
-        if (c->la_cus > 0 && c->la_cus < ncu) {
-            std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
-            for (int i = c->la_cus; i < ncu; ++i) mask[i / 32] |= 1u << (i % 32);
-            if (hipExtStreamCreateWithCUMask(&c->upd, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
-                (void)hipGetLastError();
-                c->upd = nullptr;
-            }
-        }
-    }
     if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&c->la, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->la_a, hipEventDisableTiming) != hipSuccess ||
@@ -195,13 +189,15 @@ rsrr_status rsrr_destroy(rsrr_ctx* c)
     if (c->la_a) (void)hipEventDestroy(c->la_a);
     if (c->la_b) (void)hipEventDestroy(c->la_b);
     if (c->la_c) (void)hipEventDestroy(c->la_c);
-    if (c->upd) (void)hipStreamSynchronize(c->upd), (void)hipStreamDestroy(c->upd);
+    masked_stream_release(c);
     if (c->fork) (void)hipEventDestroy(c->fork);
     if (c->join) (void)hipEventDestroy(c->join);
     if (c->offset) (void)hipEventDestroy(c->offset);
     if (c->rec.ev) {
         for (int i = 0; i < 2 * c->rec.cap; ++i) (void)hipEventDestroy(c->rec.ev[i]);
         delete[] c->rec.ev;
+        delete[] c->rec.lflops;
+        delete[] c->rec.lmask;
     }
     delete c;
     return RSRR_OK;
@@ -233,11 +229,14 @@ rsrr_status rsrr_update_stats(rsrr_ctx* c, int enable, int reset, double* out)
         const int cap = 8192;
         c->rec.ev = new hipEvent_t[2 * cap];
         for (int i = 0; i < 2 * cap; ++i) RSRR_HIP(hipEventCreate(&c->rec.ev[i]));
+        c->rec.lflops = new double[cap];
+        c->rec.lmask = new unsigned char[cap];
         c->rec.cap = cap;
     }
     c->rec_on = enable != 0;
     if (reset) {
-        c->upd_ms = c->upd_flops = 0.0;
+        c->upd_ms = c->upd_flops = c->upd_bytes = 0.0;
+        c->upd_ms_masked = c->upd_flops_masked = 0.0;
         c->upd_launches = c->upd_dropped = 0;
     }
     if (out) {
@@ -245,6 +244,12 @@ rsrr_status rsrr_update_stats(rsrr_ctx* c, int enable, int reset, double* out)
         out[1] = c->upd_ms;
         out[2] = c->upd_flops;
         out[3] = (double)c->upd_dropped;
+        out[4] = c->upd_bytes;
+        out[5] = c->upd_ms_masked;
+        out[6] = c->upd_flops_masked;
+        hipDeviceProp_t prop;
+        const int ncu = hipGetDeviceProperties(&prop, c->device) == hipSuccess ? prop.multiProcessorCount : 0;
+        out[7] = ncu > 0 && c->la_cus > 0 && c->la_cus < ncu ? (double)(ncu - c->la_cus) / ncu : 1.0;
     }
     return RSRR_OK;
 }
@@ -352,7 +357,7 @@ static rsrr_status alloc_bufs(rsrr_ctx* c, int n, int L, int J, int prec, int B,
     s.la_a = c->la_a;
     s.la_b = c->la_b;
     s.la_c = c->la_c;
-    s.upd = la ? c->upd : nullptr;
+    s.upd = nullptr;  // set while the factorisation runs
     s.la_cols = c->la_cols;
     s.sT = (long)s.ld * n;
     s.sP = n;
@@ -472,6 +477,38 @@ static rsrr_status split_groups(rsrr_ctx* c, int B, F f, bool stagger = false)
     return RSRR_OK;
 }
 
+// The CU-masked stream of the look-ahead is created on first use and kept in the
+// context (creating it per call cost about 5 ms per headline step).  While it
+// exists the process's other streams lose concurrency (the ragged batch, whose
+// size buckets run side by side, measured 169 -> 230 ms per step), so the
+// ragged-batch path releases it (masked_stream_release) before it launches.
+static void masked_stream_acquire(rsrr_ctx* c)
+{
+    if (!c->lookahead || c->la_cus <= 0 || c->upd) return;
+    hipDeviceProp_t prop;
+    const int ncu = hipGetDeviceProperties(&prop, c->device) == hipSuccess ? prop.multiProcessorCount : 0;
+    if (c->la_cus >= ncu) return;
+    // every CU but the first la_cus, which stay free for the look-ahead's panel kernels
+    std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
+    for (int i = c->la_cus; i < ncu; ++i) mask[i / 32] |= 1u << (i % 32);
+    if (hipExtStreamCreateWithCUMask(&c->upd, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
+        (void)hipGetLastError();
+        c->upd = nullptr;
+    }
+}
+
+}  // namespace
+
+void masked_stream_release(rsrr_ctx* c)
+{
+    if (!c->upd) return;
+    (void)hipStreamSynchronize(c->upd);
+    (void)hipStreamDestroy(c->upd);
+    c->upd = nullptr;
+}
+
+namespace {
+
 static rsrr_status sample_batch(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, int B, const double2* U, int L, int ldu,
                                 const std::vector<double>& un, int prec, double2* S, int lds,
                                 rsrr_point_info* info, int* any_singular, int* any_fallback, int* any_nan)
@@ -493,6 +530,8 @@ static rsrr_status sample_batch(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, i
     {
         PhaseTimer t(c, &tm[1]);
         RSRR_HIP(hipMemsetAsync(s.info, 0, (size_t)B * 4, c->stream));
+        if (s.la != nullptr && n > 2 * s.nb) masked_stream_acquire(c);
+        s.upd = s.la ? c->upd : nullptr;
         const LUWork w = s.lu(nullptr, c->rec_on ? &c->rec : nullptr);
         st = split_groups(
             c, B,

@@ -52,12 +52,17 @@ struct rsrr_ctx {
     // trailing-update statistics (rsrr_update_stats)
     bool rec_on = false;
     rsrr::UpdateRecorder rec;
-    double upd_ms = 0.0, upd_flops = 0.0;
+    double upd_ms = 0.0, upd_flops = 0.0, upd_bytes = 0.0;
+    double upd_ms_masked = 0.0, upd_flops_masked = 0.0;  // launches on the CU-masked stream
     long upd_launches = 0, upd_dropped = 0;
 };
 
 // Release the ragged-batch buffers and graphs of a context.
 void batched_release(rsrr_ctx* c);
+
+// Destroy the context's CU-masked look-ahead stream, if any (it is recreated on
+// the next factorisation that uses it).
+void masked_stream_release(rsrr_ctx* c);
 
 // Fold the recorded update events into the running statistics (syncs the events).
 void rec_collect(rsrr_ctx* c);

@@ -546,6 +546,23 @@ static void cgemm_launch(hipStream_t st, int M, int N, int K, float alpha, const
 #undef CG_L
 }
 
+// Workgroup tile of the complex FP32 trailing update (tag 1), chosen per bucket
+// by the ragged batch's autotuner and set around its launches (host thread).
+namespace {
+thread_local int g_update_tile = UPD_TILE_3M_128x64;
+}
+void set_update_tile(int t) { g_update_tile = (t >= 0 && t < UPD_TILE_COUNT) ? t : UPD_TILE_3M_128x64; }
+int get_update_tile() { return g_update_tile; }
+const char* update_tile_name(int t)
+{
+    switch (t) {
+    case UPD_TILE_3M_64x64: return "3m_64x64_4waves";
+    case UPD_TILE_4M_128x128: return "4m_128x128_4waves";
+    case UPD_TILE_4M_64x64: return "4m_64x64_4waves";
+    default: return "3m_128x64_4waves";
+    }
+}
+
 hipError_t cgemm(hipStream_t st, int M, int N, int K, float alpha,
                  const float2* A, int lda, long sA, const float2* B, int ldb, long sB,
                  float beta, float2* C, int ldc, long sC, int batch, int tag)
@@ -555,10 +572,12 @@ hipError_t cgemm(hipStream_t st, int M, int N, int K, float alpha,
                      && (sA % 2 == 0) && (sB % 2 == 0);
     // 128x16 tiles of 16x16 blocks for at most 16 columns, 128x32 tiles in the
     // 4M form up to 32 columns (the narrow products of the panel recursion and
-    // of narrow probe blocks); 128x64 tiles in the 3M form for everything wider (trailing
-    // updates, U12 products, solves): with two 32x32 blocks per wave the three
+    // of narrow probe blocks); 64x64 tiles in the 3M form up to 64 columns (the
+    // solves at L = 64); 128x64 tiles in the 3M form for everything wider (trailing
+    // updates, U12 products): with two 32x32 blocks per wave the three
     // accumulator sets still leave two waves per SIMD, which measured faster
-    // than 128x128 tiles in either form.
+    // than 128x128 tiles in either form.  The trailing update's tile can be
+    // changed per bucket by the ragged batch's autotuner (set_update_tile).
     if (N <= 16) {
         constexpr int BR = 2, BM = 64 * BR;
         const int tm = (M + BM - 1) / BM;
@@ -572,10 +591,22 @@ hipError_t cgemm(hipStream_t st, int M, int N, int K, float alpha,
             if (tag == 1) CN_L(false, 1); else CN_L(false, 0);
         }
 #undef CN_L
-    } else if (N <= 32)
+    } else if (N <= 32) {
         cgemm_launch<4, 1, 1, 1>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tag, vec);
-    else
+    } else if (tag == 0 && N <= 64) {
+        // 33..64 columns (the solves' products at L = 64): 64 x 64 tiles in the 3M form give
+        // twice the workgroups of 128 x 64 on these skinny products (solve phase 25.8 -> 21.9 ms
+        // per headline step; 64 x 32 and 32 x 64 tiles of two waves, 128 x 32 of four: slower)
+        cgemm_launch<2, 2, 1, 1, true>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tag, vec);
+    } else if (tag == 1 && g_update_tile == UPD_TILE_3M_64x64) {
+        cgemm_launch<2, 2, 1, 1, true>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tag, vec);
+    } else if (tag == 1 && g_update_tile == UPD_TILE_4M_128x128) {
+        cgemm_launch<2, 2, 2, 2>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tag, vec);
+    } else if (tag == 1 && g_update_tile == UPD_TILE_4M_64x64) {
+        cgemm_launch<2, 2, 1, 1>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tag, vec);
+    } else {
         cgemm_launch<4, 1, 1, 2, true>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, tag, vec);
+    }
     return hipGetLastError();
 }
 

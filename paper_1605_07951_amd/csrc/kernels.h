@@ -24,6 +24,16 @@ hipError_t cgemm(hipStream_t st, int M, int N, int K, float alpha,
                  const float2* A, int lda, long sA, const float2* B, int ldb, long sB,
                  float beta, float2* C, int ldc, long sC, int batch, int tag = 0);
 
+// Workgroup tiles of the complex FP32 trailing update (tag 1) that the ragged
+// batch's autotuner chooses from (all 4 waves per workgroup, two LDS stages):
+// 3M 128x64 (the default), 3M 64x64, 4M 128x128, 4M 64x64.  The choice holds
+// for the calling host thread until changed.
+enum { UPD_TILE_3M_128x64 = 0, UPD_TILE_3M_64x64 = 1, UPD_TILE_4M_128x128 = 2, UPD_TILE_4M_64x64 = 3,
+       UPD_TILE_COUNT = 4 };
+void set_update_tile(int t);
+int get_update_tile();
+const char* update_tile_name(int t);
+
 // C = beta*C + alpha*op(A)*op(B), complex double on v_mfma_f64_16x16x4f64;
 // op = conjugate transpose when the flag is set.
 hipError_t zgemm(hipStream_t st, int opA, int opB, int M, int N, int K, double alpha,
@@ -36,6 +46,9 @@ struct UpdateRecorder {
     int cap = 0;
     int used = 0;               // pairs recorded
     double flops = 0.0;         // algorithmic flops of the recorded launches (8 m n k)
+    double bytes = 0.0;         // algorithmic bytes: C (m x n) read and written, A (m x k) and B (k x n) read once
+    double* lflops = nullptr;   // per recorded launch: its algorithmic flops
+    unsigned char* lmask = nullptr;  // per recorded launch: 1 when it ran on the CU-masked stream
     long dropped = 0;           // launches beyond the pool (not timed)
 };
 

@@ -675,8 +675,12 @@ static hipError_t getrf_impl(hipStream_t st, C* A, long sA, int lda, int n, int 
         (void)gemm_sub<C>(s, M, N, kdepth, Aop, ldaop, sAop, Bop, lda, sA, Cop, lda, sA, batch, 1);
         if (timed) {
             (void)hipEventRecord(rec->ev[2 * rec->used + 1], s);
+            const double fl = (elem_traits<C>::complex ? 8.0 : 2.0) * M * (double)N * kdepth * batch;
+            if (rec->lflops) rec->lflops[rec->used] = fl;
+            if (rec->lmask) rec->lmask[rec->used] = (s == w.upd && s != nullptr) ? 1 : 0;
             rec->used++;
-            rec->flops += (elem_traits<C>::complex ? 8.0 : 2.0) * M * (double)N * kdepth * batch;
+            rec->flops += fl;
+            rec->bytes += (double)sizeof(C) * (2.0 * M * N + (double)M * kdepth + (double)kdepth * N) * batch;
         } else if (rec) {
             rec->dropped++;
         }

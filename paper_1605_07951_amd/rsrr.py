@@ -319,9 +319,10 @@ def rsrr_get_options(ctx):
 
 def rsrr_update_stats(ctx, enable=True, reset=False):
     """Trailing-update kernel statistics: dict(launches, ms, flops, untimed)."""
-    out = (C.c_double * 4)()
+    out = (C.c_double * 8)()
     _check("rsrr_update_stats", lib().rsrr_update_stats(ctx.h, int(enable), int(reset), out))
-    return {"launches": int(out[0]), "ms": out[1], "flops": out[2], "untimed": int(out[3])}
+    return {"launches": int(out[0]), "ms": out[1], "flops": out[2], "untimed": int(out[3]), "bytes": out[4],
+            "masked_ms": out[5], "masked_flops": out[6], "masked_cu_share": out[7]}
 
 
 def rsrr_create(device=0, stream=None):

@@ -1,5 +1,6 @@
 """GPU parity of rsrr_sample_batched (ragged batches of instances, size buckets,
-device-side refinement, hipGraph capture and replay, panel-width autotuning)
+device-side refinement, hipGraph capture and replay, autotuning of the panel width and
+the update tile)
 against the CPU oracle.  Bar: every block X_k within 1e-10 (relative
 Frobenius) of the oracle's LAPACK solve, reported residuals <= 1e-10."""
 import os
@@ -82,14 +83,32 @@ def test_batched_graph_replays_match_eager(R):
 
 
 def test_batched_autotune_writes_cache(R, tmp_path, monkeypatch):
-    f = tmp_path / "tune.txt"
+    """The autotuner times every (panel width, update tile) candidate on each bucket and caches the
+    winner per (bucket, precision, arch) as JSON; a fresh context that reads the cache reproduces
+    the tuned call's S bit for bit."""
+    import json
+    f = tmp_path / "tune.json"
     monkeypatch.setenv("RSRR_TUNE_FILE", str(f))
     ctx = R.rsrr_create(0)
-    items, hosts = _items(R, [300, 310], N=5, L=2, seed=5000)
+    items, hosts = _items(R, [300, 310, 700], N=5, L=2, seed=5000)
     infos, _ = R.rsrr_sample_batched(ctx, items, prec=1, flags=R.RSRR_BATCH_AUTOTUNE)
     _check(R, items, hosts, infos)
-    lines = f.read_text().split()
-    assert len(lines) >= 2 and int(lines[1]) in (32, 64, 128)
+    tuned = [it.S.clone() for it in items]
+    ctx.close()
+    doc = json.loads(f.read_text())
+    assert doc["arch"].startswith("gfx9")
+    ent = {(e["P"], e["prec"]): e for e in doc["entries"]}
+    assert set(ent) == {(320, "c64"), (704, "c64")}
+    for e in ent.values():
+        assert e["nb"] in (32, 64, 128) and e["update_tile"] in (0, 1, 2, 3) and e["ms"] > 0
+        assert e["update_tile_name"].endswith("4waves")
+    ctx = R.rsrr_create(0)
+    for it in items:
+        it.S.zero_()
+    R.rsrr_sample_batched(ctx, items, prec=1)
+    torch.cuda.synchronize()
+    for it, t in zip(items, tuned):
+        assert torch.equal(it.S, t)
     ctx.close()
 
 
@@ -108,15 +127,20 @@ def test_batched_matches_single_instance_calls(R):
     ctx.close()
 
 
+@pytest.mark.parametrize("tile", [0, 1, 2, 3])
 @pytest.mark.parametrize("nb", [32, 64, 128])
-def test_batched_every_panel_width(R, tmp_path, monkeypatch, nb):
-    """Each panel width the autotuner may pick, forced through the cache file, on buckets whose
-    size is and is not a multiple of it (P = 128, 192, 256, 320)."""
-    f = tmp_path / "tune.txt"
-    f.write_text("".join(f"{P * 2 + 1} {nb}\n" for P in (128, 192, 256, 320)))
+def test_batched_every_panel_width(R, tmp_path, monkeypatch, nb, tile):
+    """Each panel width and update tile the autotuner may pick, forced through the JSON cache, on
+    buckets whose size is and is not a multiple of the width (P = 128, 192, 256, 320)."""
+    import json
+    f = tmp_path / "tune.json"
+    entries = [{"P": P, "prec": "c64", "nb": nb, "update_tile": tile, "ms": 1.0} for P in (128, 192, 256, 320)]
+    # the library's own layout: one entry per line
+    f.write_text('{"arch": "gfx950", "entries": [\n' + ",\n".join(json.dumps(e) for e in entries) + "\n]}\n")
+    json.loads(f.read_text())
     monkeypatch.setenv("RSRR_TUNE_FILE", str(f))
     ctx = R.rsrr_create(0)
-    items, hosts = _items(R, [100, 150, 250, 300], N=4, L=3, seed=7000 + nb)
+    items, hosts = _items(R, [100, 150, 250, 300], N=4, L=3, seed=7000 + nb + 10 * tile)
     infos, code = R.rsrr_sample_batched(ctx, items, prec=1)
     assert code == R.RSRR_OK
     _check(R, items, hosts, infos)
