@@ -98,7 +98,9 @@ extern "C" rsrr_status rsrr_basis(rsrr_ctx* c, int n, int NL, double* S, int lds
     //   numerically independent columns kept, X = [S^H Q_Y; I_r]: Jacobi
     //   rotations J on the columns make the top part V Sigma (right singular
     //   vectors of B = Q_Y^H S) and the bottom part J = W, the left singular
-    //   vectors of B; S's left singular vectors are Q_Y W.
+    //   vectors of B; S's left singular vectors are Q_Y W.  When NL >= 2r the
+    //   top part is replaced by R from S^H Q_Y = Q_X R (same Gram matrix, so the
+    //   same rotations and singular values, on r rows instead of NL).
     // When l = min(n, NL) the sketch spans range(S) and this is the SVD of S.  A
     // smaller l is accepted when the sketch came out rank deficient (r < l) or its
     // smallest singular value is at the rounding floor (<= 1e-15 sigma_1);
@@ -111,7 +113,7 @@ extern "C" rsrr_status rsrr_basis(rsrr_ctx* c, int n, int NL, double* S, int lds
     std::vector<double> sv, hq;
     double2* Yu = nullptr;
     double2* X = nullptr;
-    int r = 0;
+    int r = 0, xr = 0;  // X = [top (xr rows); W (r rows)] after the Jacobi sweeps
     for (;;) {
         double2* Y = (double2*)ws_get(c, WS_TLU, (size_t)n * l * 16);
         double2* Om = (double2*)ws_get(c, WS_TRES, (size_t)std::max((long)NL * l, (long)n * l) * 16);
@@ -146,14 +148,32 @@ extern "C" rsrr_status rsrr_basis(rsrr_ctx* c, int n, int NL, double* S, int lds
             RSRR_HIP(hipStreamSynchronize(c->stream));
             Yu = Om;
         }
-        X = (double2*)ws_get(c, WS_R, (size_t)(NL + r) * r * 16);
-        if (!X) return RSRR_ENOMEM;
-        RSRR_HIP(zgemm(c->stream, 1, 0, NL, r, n, 1.0, A, lds, 0, Yu, n, 0, 0.0, X, NL + r, 0, 1));
-        RSRR_HIP(eye(c->stream, X, NL + r, NL, r));
-        if (jacobi_svd(c, X, NL + r, NL, NL + r, r, 80, tol, &st) < 0) return st;
+        if (NL >= 2 * r) {
+            // QR first: B^H = S^H Q_Y = Q_X R (BCGS2), then the Jacobi rotations on
+            // [R; I_r]: R has the Gram matrix of B^H, so the rotations, singular
+            // values and W are those of B^H, on 2r rows instead of NL + r
+            double2* Xs = (double2*)ws_get(c, WS_B0, (size_t)NL * r * 16);
+            double2* Xq = (double2*)ws_get(c, WS_B1, (size_t)NL * r * 16);
+            void* Wq = ws_get(c, WS_D64, bcgs2_work_bytes(NL, r));
+            double* nq = (double*)ws_get(c, WS_B7, (size_t)r * 8);
+            X = (double2*)ws_get(c, WS_R, (size_t)2 * r * r * 16);
+            if (!Xs || !Xq || !Wq || !nq || !X) return RSRR_ENOMEM;
+            RSRR_HIP(zgemm(c->stream, 1, 0, NL, r, n, 1.0, A, lds, 0, Yu, n, 0, 0.0, Xs, NL, 0, 1));
+            RSRR_HIP(copy_c128(c->stream, NL, r, Xs, NL, 0, Xq, NL, 0, 1));
+            RSRR_HIP(bcgs2(c->stream, Xq, NL, NL, r, Wq, nq));
+            RSRR_HIP(zgemm(c->stream, 1, 0, r, r, NL, 1.0, Xq, NL, 0, Xs, NL, 0, 0.0, X, 2 * r, 0, 1));
+            xr = r;
+        } else {
+            X = (double2*)ws_get(c, WS_R, (size_t)(NL + r) * r * 16);
+            if (!X) return RSRR_ENOMEM;
+            RSRR_HIP(zgemm(c->stream, 1, 0, NL, r, n, 1.0, A, lds, 0, Yu, n, 0, 0.0, X, NL + r, 0, 1));
+            xr = NL;
+        }
+        RSRR_HIP(eye(c->stream, X, xr + r, xr, r));
+        if (jacobi_svd(c, X, xr + r, xr, xr + r, r, 80, tol, &st) < 0) return st;
         double* cn = (double*)ws_get(c, WS_B5, (size_t)r * 8);
         if (!cn) return RSRR_ENOMEM;
-        RSRR_HIP(colnorms(c->stream, NL, r, X, NL + r, 0, cn, 1));
+        RSRR_HIP(colnorms(c->stream, xr, r, X, xr + r, 0, cn, 1));
         sv.assign(r, 0.0);
         RSRR_HIP(hipMemcpyAsync(sv.data(), cn, (size_t)r * 8, hipMemcpyDeviceToHost, c->stream));
         RSRR_HIP(hipStreamSynchronize(c->stream));
@@ -179,7 +199,7 @@ extern "C" rsrr_status rsrr_basis(rsrr_ctx* c, int n, int NL, double* S, int lds
         if (!Ws) return RSRR_ENOMEM;
         RSRR_HIP(hipMemcpyAsync(ord, o.data(), (size_t)kw * 4, hipMemcpyHostToDevice, c->stream));
         RSRR_HIP(hipMemcpyAsync(inv, ones.data(), (size_t)kw * 8, hipMemcpyHostToDevice, c->stream));
-        RSRR_HIP(gather_scale(c->stream, X + NL, NL + r, r, ord, inv, Ws, r, kw));
+        RSRR_HIP(gather_scale(c->stream, X + xr, xr + r, r, ord, inv, Ws, r, kw));
         RSRR_HIP(zgemm(c->stream, 0, 0, n, kw, r, 1.0, Yu, n, 0, Ws, r, 0, 0.0, (double2*)Q, ldq, 0, 1));
     }
     RSRR_HIP(hipStreamSynchronize(c->stream));

@@ -3,17 +3,20 @@
 //
 // The columns of A (m x p) are split into blocks of JB_B columns.  A sweep
 // pairs every block with every other once (round-robin tournament, all
-// pairs of a round independent).  A round is three launches:
-//   1. gram:  for every pair and every slice of JR rows, one workgroup forms
+// pairs of a round independent).  A round is two launches:
+//   1. gram:  for every pair and every slice of JRG rows, one workgroup forms
 //      the partial Gram matrix [A_I A_J]^H [A_I A_J] (2B x 2B) of its slice;
-//   2. solve: one wave per pair sums the slices (fixed order), records
-//      max |G_pq| / sqrt(G_pp G_qq) over p != q (the convergence measure of
-//      one-sided Jacobi; columns with |a|^2 <= zthr2, rounding level
-//      relative to ||A||_F, count as zero and are neither measured nor
-//      rotated, so exactly rank-deficient inputs converge), and diagonalises
-//      G by cyclic two-sided Jacobi rotations (parallel ordering),
-//      accumulating the unitary V;
-//   3. apply: for every pair and row slice, [A_I A_J] <- [A_I A_J] V.
+//   2. rotate: for every pair and every slice of JR rows of the m_apply rows
+//      that are rotated, one workgroup sums the pair's Gram slices (fixed
+//      order), measures max |G_pq| / sqrt(G_pp G_qq) over p != q (the
+//      convergence measure of one-sided Jacobi; columns with |a|^2 <= zthr2,
+//      rounding level relative to ||A||_F, count as zero and are neither
+//      measured nor rotated, so exactly rank-deficient inputs converge),
+//      diagonalises G by cyclic two-sided Jacobi rotations (parallel
+//      ordering) accumulating the unitary V, and applies
+//      [A_I A_J] <- [A_I A_J] V to its rows.  Every workgroup of a pair does
+//      the same small diagonalisation on the same data, so they agree
+//      bitwise; slice 0 records the measure.
 // Splitting the rows keeps every CU busy although a round has only p/(2B)
 // pairs.  When every pair's measure is below the tolerance the columns of A
 // are orthogonal: A = U Sigma with the column norms as singular values.
@@ -27,12 +30,12 @@ namespace rsrr {
 constexpr int JB_B = 16;          // columns per block
 constexpr int JB_W = 2 * JB_B;    // columns per pair
 constexpr int JB_NT = 256;
-constexpr int JB_RC = 32;         // rows per LDS chunk
 
 // block at tournament position pos in round r (nb even, position 0 fixed)
 RSRR_DEV int rr_block(int pos, int r, int nb) { return pos == 0 ? 0 : ((pos - 1 + r) % (nb - 1)) + 1; }
 
-constexpr int JR = 256;           // rows per slice
+constexpr int JR = 256;           // rows per slice of the rotation
+constexpr int JRG = 128;          // rows per slice of the Gram matrices
 
 RSRR_DEV int jac_col(int s, int bI, int bJ, int p)
 {
@@ -40,79 +43,106 @@ RSRR_DEV int jac_col(int s, int bI, int bJ, int p)
     return c < p ? c : -1;
 }
 
-// 1. partial Gram matrix of rows [slice*JR, min(m, slice*JR + JR)) of pair blockIdx.x.
+// 1. partial Gram matrix of rows [slice*JRG, min(m, slice*JRG + JRG)) of pair blockIdx.x.
+// Chunks of JG_RC rows pass through LDS; the next chunk is fetched into
+// registers while the current one is multiplied.
+constexpr int JG_RC = 64;
+constexpr int JG_PER = JG_RC * JB_W / JB_NT;  // entries of a chunk per thread
+
 __global__ __launch_bounds__(JB_NT) void jacobi_gram_kernel(const double2* __restrict__ A, int lda, int m, int p,
                                                              int nb, int round, double2* __restrict__ Gp)
 {
-    __shared__ double2 tile[JB_RC][JB_W + 1];
+    __shared__ double2 tile[JG_RC][JB_W + 1];
     const int pr = blockIdx.x, slice = blockIdx.y, tid = threadIdx.x;
     const int bI = rr_block(pr, round, nb), bJ = rr_block(nb - 1 - pr, round, nb);
     const int gp = tid >> 3, gq0 = (tid & 7) * 4;  // each thread: G[gp][gq0..gq0+3]
-    const int rlo = slice * JR, rhi = min(m, rlo + JR);
+    const int rlo = slice * JRG, rhi = min(m, rlo + JRG);
     double2 acc[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc[u] = make_double2(0.0, 0.0);
-    for (int r0 = rlo; r0 < rhi; r0 += JB_RC) {
-        for (int e = tid; e < JB_RC * JB_W; e += JB_NT) {
-            const int i = e % JB_RC, s = e / JB_RC;
-            const int c = jac_col(s, bI, bJ, p);
-            tile[i][s] = (c >= 0 && r0 + i < rhi) ? A[(r0 + i) + (long)c * lda] : make_double2(0.0, 0.0);
+    double2 nx[JG_PER];
+    auto fetch = [&](int r0) {
+#pragma unroll
+        for (int u = 0; u < JG_PER; ++u) {
+            const int e = tid + JB_NT * u, i = e % JG_RC, sc = e / JG_RC;
+            const int c = jac_col(sc, bI, bJ, p);
+            nx[u] = (c >= 0 && r0 + i < rhi) ? A[(r0 + i) + (long)c * lda] : make_double2(0.0, 0.0);
+        }
+    };
+    fetch(rlo);
+    for (int r0 = rlo; r0 < rhi; r0 += JG_RC) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < JG_PER; ++u) {
+            const int e = tid + JB_NT * u;
+            tile[e % JG_RC][e / JG_RC] = nx[u];
         }
         __syncthreads();
+        if (r0 + JG_RC < rhi) fetch(r0 + JG_RC);
 #pragma unroll 4
-        for (int i = 0; i < JB_RC; ++i) {
+        for (int i = 0; i < JG_RC; ++i) {
             const double2 a = tile[i][gp];
 #pragma unroll
             for (int u = 0; u < 4; ++u) acc[u] = cfma_cj(acc[u], a, tile[i][gq0 + u]);
         }
-        __syncthreads();
     }
     double2* G = Gp + ((long)pr * gridDim.y + slice) * (JB_W * JB_W);
 #pragma unroll
     for (int u = 0; u < 4; ++u) G[gp * JB_W + gq0 + u] = acc[u];
 }
 
-// 2. one workgroup of JS_NT threads per pair: sum the slices, measure, rotate.
-// V (JB_W x JB_W, row major, entry [t][s] = V_ts) and skip[pr] go to global memory.
-constexpr int JS_NT = 256;
-__global__ __launch_bounds__(JS_NT) void jacobi_solve_kernel(const double2* __restrict__ Gp, int slices,
-                                                              int inner_sweeps, double tol, double zthr2,
-                                                              double2* __restrict__ Vout, int* __restrict__ skip,
-                                                              double* __restrict__ offmax)
+// 2. sum the Gram slices of pair blockIdx.x, measure, diagonalise, and rotate the
+// rows of slice blockIdx.y.  One step of the inner sweep applies JB_W / 2
+// disjoint rotations (a_k, b_k) from both sides at once; thread (pi, pj) owns
+// the 2 x 2 entries of G and of V at rows {a_pi, b_pi} x columns {a_pj, b_pj},
+// so the update is done in place and a step needs two barriers.
+__global__ __launch_bounds__(JB_NT) void jacobi_rotate_kernel(double2* __restrict__ A, int lda, int m_apply, int p,
+                                                               int nb, int round, const double2* __restrict__ Gp,
+                                                               int slices, int inner_sweeps, double tol, double zthr2,
+                                                               double* __restrict__ offmax)
 {
+    static_assert(JB_NT == (JB_W / 2) * (JB_W / 2), "one thread per 2 x 2 block of a step");
     __shared__ double2 G[JB_W][JB_W + 1];
     __shared__ double2 V[JB_W][JB_W + 1];
-    __shared__ double rc[JB_W / 2], rs[JB_W / 2];
-    __shared__ double2 re[JB_W / 2];
-    __shared__ int rp[JB_W / 2], rq[JB_W / 2], ron[JB_W / 2];
-    __shared__ double wmax[JS_NT / 64];
-    const int pr = blockIdx.x, tid = threadIdx.x;
+    __shared__ double2 tile[JG_RC][JB_W + 1];
+    __shared__ int pa[JB_W / 2], pb[JB_W / 2], pon[JB_W / 2];
+    __shared__ double pc[JB_W / 2], ps[JB_W / 2];
+    __shared__ double2 pe[JB_W / 2];
+    __shared__ double wmax[JB_NT / 64];
+    const int pr = blockIdx.x, slice = blockIdx.y, tid = threadIdx.x;
     const double2* src = Gp + (long)pr * slices * (JB_W * JB_W);
+    constexpr int PER = JB_W * JB_W / JB_NT;
     {
-        // JB_W^2 / JS_NT entries per thread, all loads of a slice in flight together; each
-        // entry is summed over the slices in order
-        constexpr int PER = JB_W * JB_W / JS_NT;
+        // JS_SL slices' loads in flight at once; each entry is summed in slice order
+        constexpr int JS_SL = 8;
         double2 g[PER];
 #pragma unroll
         for (int t = 0; t < PER; ++t) g[t] = make_double2(0.0, 0.0);
-        for (int sl = 0; sl < slices; ++sl) {
-            const double2* sp = src + (long)sl * (JB_W * JB_W) + tid;
-            double2 v[PER];
+        for (int sl0 = 0; sl0 < slices; sl0 += JS_SL) {
+            double2 v[JS_SL][PER];
 #pragma unroll
-            for (int t = 0; t < PER; ++t) v[t] = sp[JS_NT * t];
+            for (int q = 0; q < JS_SL; ++q) {
+                const double2* sp = src + (long)(sl0 + q) * (JB_W * JB_W) + tid;
 #pragma unroll
-            for (int t = 0; t < PER; ++t) g[t] = cadd(g[t], v[t]);
+                for (int t = 0; t < PER; ++t) v[q][t] = sl0 + q < slices ? sp[JB_NT * t] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int q = 0; q < JS_SL; ++q) {
+                if (sl0 + q >= slices) break;
+#pragma unroll
+                for (int t = 0; t < PER; ++t) g[t] = cadd(g[t], v[q][t]);
+            }
         }
 #pragma unroll
         for (int t = 0; t < PER; ++t) {
-            const int e = tid + JS_NT * t;
+            const int e = tid + JB_NT * t;
             G[e / JB_W][e % JB_W] = g[t];
             V[e / JB_W][e % JB_W] = make_double2(e / JB_W == e % JB_W ? 1.0 : 0.0, 0.0);
         }
     }
     __syncthreads();
     double off = 0.0;
-    for (int e = tid; e < JB_W * JB_W; e += JS_NT) {
+    for (int e = tid; e < JB_W * JB_W; e += JB_NT) {
         const int i = e / JB_W, q = e % JB_W;
         if (i == q) continue;
         const double dp = G[i][i].x, dq = G[q][q].x;
@@ -125,13 +155,11 @@ __global__ __launch_bounds__(JS_NT) void jacobi_solve_kernel(const double2* __re
     if ((tid & 63) == 0) wmax[tid >> 6] = off;
     __syncthreads();
     off = wmax[0];
-    for (int w = 1; w < JS_NT / 64; ++w) off = fmax(off, wmax[w]);
-    if (tid == 0) {
-        offmax[pr] = off;
-        skip[pr] = off <= tol ? 1 : 0;
-    }
+    for (int w = 1; w < JB_NT / 64; ++w) off = fmax(off, wmax[w]);
+    if (slice == 0 && tid == 0) offmax[pr] = off;
     if (off <= tol) return;  // pair already orthogonal: A stays unchanged (uniform over the workgroup)
 
+    const int qi = tid / (JB_W / 2), qj = tid % (JB_W / 2);
     for (int sw = 0; sw < inner_sweeps; ++sw) {
         for (int st = 0; st < JB_W - 1; ++st) {
             if (tid < JB_W / 2) {
@@ -151,82 +179,87 @@ __global__ __launch_bounds__(JS_NT) void jacobi_solve_kernel(const double2* __re
                     e = make_double2(g.x / h, g.y / h);
                     on = 1;
                 }
-                rp[tid] = a_; rq[tid] = b_; rc[tid] = c; rs[tid] = s; re[tid] = e; ron[tid] = on;
+                pa[tid] = a_; pb[tid] = b_; pon[tid] = on; pc[tid] = c; ps[tid] = s; pe[tid] = e;
             }
             __syncthreads();
-            // columns: [x_p, x_q] <- [c x_p - s conj(e) x_q, s e x_p + c x_q] for G and V
-            for (int task = tid; task < (JB_W / 2) * JB_W * 2; task += JS_NT) {
-                const int which = task / ((JB_W / 2) * JB_W);  // 0: G, 1: V
-                const int rem = task % ((JB_W / 2) * JB_W);
-                const int k = rem / JB_W, row = rem % JB_W;
-                if (!ron[k]) continue;
-                const int a_ = rp[k], b_ = rq[k];
-                const double c = rc[k], s = rs[k];
-                const double2 e = re[k];
-                double2(*M)[JB_W + 1] = which ? V : G;
-                const double2 xp = M[row][a_], xq = M[row][b_];
-                const double2 ecq = cmul(cconj(e), xq), exp_ = cmul(e, xp);
-                M[row][a_] = make_double2(c * xp.x - s * ecq.x, c * xp.y - s * ecq.y);
-                M[row][b_] = make_double2(s * exp_.x + c * xq.x, s * exp_.y + c * xq.y);
-            }
-            __syncthreads();
-            // rows of G: row_p <- c row_p - s e row_q ; row_q <- s conj(e) row_p + c row_q
-            for (int task = tid; task < (JB_W / 2) * JB_W; task += JS_NT) {
-                const int k = task / JB_W, col = task % JB_W;
-                if (!ron[k]) continue;
-                const int a_ = rp[k], b_ = rq[k];
-                const double c = rc[k], s = rs[k];
-                const double2 e = re[k];
-                const double2 xp = G[a_][col], xq = G[b_][col];
-                const double2 eq = cmul(e, xq), cep = cmul(cconj(e), xp);
-                G[a_][col] = make_double2(c * xp.x - s * eq.x, c * xp.y - s * eq.y);
-                G[b_][col] = make_double2(s * cep.x + c * xq.x, s * cep.y + c * xq.y);
-            }
-            __syncthreads();
-            if (tid < JB_W / 2 && ron[tid]) {
-                const int a_ = rp[tid], b_ = rq[tid];
-                G[a_][b_] = make_double2(0.0, 0.0);
-                G[b_][a_] = make_double2(0.0, 0.0);
-                G[a_][a_].y = 0.0;
-                G[b_][b_].y = 0.0;
+            // columns a, b (pair qj): x_a <- c x_a - s conj(e) x_b, x_b <- s e x_a + c x_b;
+            // rows a, b (pair qi):    r_a <- c r_a - s e r_b,       r_b <- s conj(e) r_a + c r_b
+            const int ra = pa[qi], rb = pb[qi], ca = pa[qj], cb = pb[qj];
+            const bool oi = pon[qi] != 0, oj = pon[qj] != 0;
+            if (oi || oj) {
+                double2 g00 = G[ra][ca], g01 = G[ra][cb], g10 = G[rb][ca], g11 = G[rb][cb];
+                double2 v00 = V[ra][ca], v01 = V[ra][cb], v10 = V[rb][ca], v11 = V[rb][cb];
+                if (oj) {
+                    const double c = pc[qj], s = ps[qj];
+                    const double2 e = pe[qj], ce = cconj(e);
+                    auto colop = [&](double2& xa, double2& xb) {
+                        const double2 ecq = cmul(ce, xb), exp_ = cmul(e, xa);
+                        const double2 na = make_double2(c * xa.x - s * ecq.x, c * xa.y - s * ecq.y);
+                        xb = make_double2(s * exp_.x + c * xb.x, s * exp_.y + c * xb.y);
+                        xa = na;
+                    };
+                    colop(g00, g01);
+                    colop(g10, g11);
+                    colop(v00, v01);
+                    colop(v10, v11);
+                    V[ra][ca] = v00; V[ra][cb] = v01; V[rb][ca] = v10; V[rb][cb] = v11;
+                }
+                if (oi) {
+                    const double c = pc[qi], s = ps[qi];
+                    const double2 e = pe[qi], ce = cconj(e);
+                    auto rowop = [&](double2& xa, double2& xb) {
+                        const double2 eq = cmul(e, xb), cep = cmul(ce, xa);
+                        const double2 na = make_double2(c * xa.x - s * eq.x, c * xa.y - s * eq.y);
+                        xb = make_double2(s * cep.x + c * xb.x, s * cep.y + c * xb.y);
+                        xa = na;
+                    };
+                    rowop(g00, g10);
+                    rowop(g01, g11);
+                }
+                if (qi == qj) {
+                    // the rotated pair's coupling is zero, its diagonal real
+                    g01 = make_double2(0.0, 0.0);
+                    g10 = make_double2(0.0, 0.0);
+                    g00.y = 0.0;
+                    g11.y = 0.0;
+                }
+                G[ra][ca] = g00; G[ra][cb] = g01; G[rb][ca] = g10; G[rb][cb] = g11;
             }
             __syncthreads();
         }
     }
-    double2* Vo = Vout + (long)pr * (JB_W * JB_W);
-    for (int e = tid; e < JB_W * JB_W; e += JS_NT) Vo[e] = V[e / JB_W][e % JB_W];
-}
-
-// 3. [A_I A_J] <- [A_I A_J] V on rows [slice*JR, min(m_apply, slice*JR + JR)).
-__global__ __launch_bounds__(JB_NT) void jacobi_apply_kernel(double2* __restrict__ A, int lda, int m_apply, int p,
-                                                              int nb, int round, const double2* __restrict__ Vin,
-                                                              const int* __restrict__ skip)
-{
-    __shared__ double2 tile[JB_RC][JB_W + 1];
-    __shared__ double2 V[JB_W][JB_W + 1];
-    const int pr = blockIdx.x, slice = blockIdx.y, tid = threadIdx.x;
-    if (skip[pr]) return;
+    // rotate the rows of this slice: [A_I A_J] <- [A_I A_J] V
     const int bI = rr_block(pr, round, nb), bJ = rr_block(nb - 1 - pr, round, nb);
-    const double2* Vs = Vin + (long)pr * (JB_W * JB_W);
-    for (int e = tid; e < JB_W * JB_W; e += JB_NT) V[e / JB_W][e % JB_W] = Vs[e];
     const int rlo = slice * JR, rhi = min(m_apply, rlo + JR);
-    for (int r0 = rlo; r0 < rhi; r0 += JB_RC) {
-        for (int e = tid; e < JB_RC * JB_W; e += JB_NT) {
-            const int i = e % JB_RC, s = e / JB_RC;
-            const int c = jac_col(s, bI, bJ, p);
-            tile[i][s] = (c >= 0 && r0 + i < rhi) ? A[(r0 + i) + (long)c * lda] : make_double2(0.0, 0.0);
+    double2 nxv[JG_PER];
+    auto fetch = [&](int r0) {
+#pragma unroll
+        for (int u = 0; u < JG_PER; ++u) {
+            const int e = tid + JB_NT * u, i = e % JG_RC, sc = e / JG_RC;
+            const int c = jac_col(sc, bI, bJ, p);
+            nxv[u] = (c >= 0 && r0 + i < rhi) ? A[(r0 + i) + (long)c * lda] : make_double2(0.0, 0.0);
+        }
+    };
+    fetch(rlo);
+    for (int r0 = rlo; r0 < rhi; r0 += JG_RC) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < JG_PER; ++u) {
+            const int e = tid + JB_NT * u;
+            tile[e % JG_RC][e / JG_RC] = nxv[u];
         }
         __syncthreads();
-        for (int e = tid; e < JB_RC * JB_W; e += JB_NT) {
-            const int i = e % JB_RC, s = e / JB_RC;
-            const int c = jac_col(s, bI, bJ, p);
+        if (r0 + JG_RC < rhi) fetch(r0 + JG_RC);
+#pragma unroll
+        for (int u = 0; u < JG_PER; ++u) {
+            const int e = tid + JB_NT * u, i = e % JG_RC, sc = e / JG_RC;
+            const int c = jac_col(sc, bI, bJ, p);
             if (c < 0 || r0 + i >= rhi) continue;
             double2 v = make_double2(0.0, 0.0);
 #pragma unroll 8
-            for (int t = 0; t < JB_W; ++t) v = cfma(v, tile[i][t], V[t][s]);
+            for (int t = 0; t < JB_W; ++t) v = cfma(v, tile[i][t], V[t][sc]);
             A[(r0 + i) + (long)c * lda] = v;
         }
-        __syncthreads();
     }
 }
 
@@ -397,43 +430,206 @@ static hipError_t project_out(hipStream_t st, double2* Y, int ld, int n, int j0,
     return e;
 }
 
+// ----------------------------------------------------------------------------
+// Orthonormalisation inside a wide block from its Gram matrix.  G = Yb^H Yb
+// (bw x bw) is factored G = R^H R column by column; a column is dropped (R row
+// and Rinv row and column zero) when its norm after the projections on the
+// earlier blocks, sqrt(G_cc), or after the earlier columns of the block,
+// sqrt(d_c) with d_c the Cholesky pivot, is at most thr * ref[c] (ref =
+// nullptr: thr).  The pivot carries a relative rounding error of about
+// n eps G_cc / d_c, so the factorisation stops at the first column whose pivot
+// falls below tau * G_cc: flag[0] = that column (bw when none), and columns
+// from there on are left to the next block, which sees them projected off
+// the columns kept here (the scale that made the pivot small is gone then).
+// The first column that is not dropped always has d_c = G_cc, so flag[0] > 0.
+// Rinv = R^-1 on the kept columns before the cut, so Yb Rinv has orthonormal
+// columns up to eps cond(Yb)^2 (a second pass brings that to eps).  flag[1] =
+// number of kept columns before the cut.  One workgroup; R in the upper
+// triangle of the LDS array, Rinv^T in its strict lower triangle with the
+// diagonal apart.
+constexpr int QB = 64;        // columns per BCGS2 block
+constexpr int CH_NT = 256;
+
+__global__ __launch_bounds__(CH_NT) void block_chol_kernel(const double2* __restrict__ Gin, int bw,
+                                                            const double* __restrict__ ref, double thr, double tau,
+                                                            double2* __restrict__ Rinv, int* __restrict__ flag)
+{
+    __shared__ double2 A[QB][QB + 1];
+    __shared__ double gd[QB], rd[QB];
+    __shared__ double2 dinv[QB];
+    __shared__ int keep[QB];
+    __shared__ int s_cut;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < bw * bw; e += CH_NT) {
+        const int i = e % bw, j = e / bw;
+        if (i <= j) A[i][j] = Gin[i + (long)j * bw];
+    }
+    if (tid < bw) gd[tid] = Gin[tid + (long)tid * bw].x;
+    if (tid == 0) s_cut = bw;
+    __syncthreads();
+    for (int c = 0; c < bw; ++c) {
+        if (tid == 0) {
+            const double d = A[c][c].x, g = gd[c];
+            const double lim = thr * (ref ? ref[c] : 1.0), lim2 = lim * lim;
+            int k = 1;
+            if (!(g > lim2) || !(d == d)) {
+                k = 0;                      // dependent on the earlier blocks (or not finite)
+            } else if (d < tau * g) {
+                k = 0;                      // the pivot is not resolved: cut here
+                s_cut = c;
+            } else if (d <= lim2) {
+                k = 0;                      // dependent on the earlier columns of the block
+            }
+            keep[c] = k;
+            rd[c] = k ? sqrt(d) : 0.0;
+        }
+        __syncthreads();
+        if (s_cut < bw) break;              // uniform: read from LDS after the barrier
+        if (!keep[c]) continue;
+        const double ri = 1.0 / rd[c];
+        for (int j = c + 1 + tid; j < bw; j += CH_NT) A[c][j] = make_double2(A[c][j].x * ri, A[c][j].y * ri);
+        if (tid == 0) A[c][c] = make_double2(rd[c], 0.0);
+        __syncthreads();
+        const int w = bw - c - 1;
+        for (int e = tid; e < w * w; e += CH_NT) {
+            const int i = c + 1 + e % w, j = c + 1 + e / w;
+            if (i <= j) {
+                const double2 a = A[c][i], b = A[c][j];
+                double2 t = A[i][j];
+                // t -= conj(a) b
+                t.x -= a.x * b.x + a.y * b.y;
+                t.y -= a.x * b.y - a.y * b.x;
+                A[i][j] = t;
+            }
+        }
+        __syncthreads();
+    }
+    const int cut = s_cut;
+    for (int c = cut + tid; c < bw; c += CH_NT) {
+        keep[c] = 0;
+        rd[c] = 0.0;
+    }
+    __syncthreads();
+    // Rinv column j (thread j): Rinv_jj = 1 / R_jj, then upwards
+    // Rinv_ij = -(sum_{i<k<=j} R_ik Rinv_kj) / R_ii over the kept rows
+    if (tid < bw) {
+        const int j = tid;
+        const bool kj = keep[j] != 0;
+        dinv[j] = make_double2(kj ? 1.0 / rd[j] : 0.0, 0.0);
+        for (int i = j - 1; i >= 0; --i) {
+            double2 v = make_double2(0.0, 0.0);
+            if (kj && keep[i]) {
+                double2 s = cmul(A[i][j], make_double2(1.0 / rd[j], 0.0));
+                for (int k = i + 1; k < j; ++k) s = cfma(s, A[i][k], A[j][k]);
+                v = make_double2(-s.x / rd[i], -s.y / rd[i]);
+            }
+            A[j][i] = v;
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < bw * bw; e += CH_NT) {
+        const int i = e % bw, j = e / bw;
+        Rinv[e] = i < j ? A[j][i] : (i == j ? dinv[j] : make_double2(0.0, 0.0));
+    }
+    if (tid == 0) {
+        int kept = 0;
+        for (int c = 0; c < bw; ++c) kept += keep[c];
+        flag[0] = cut;
+        flag[1] = kept;
+    }
+}
+
+// G = Yb^H Yb for the bw columns of Yb, split along the rows like project_out.
+static hipError_t gram_block(hipStream_t st, const double2* Yb, int ld, int n, int bw, double2* G, double2* part)
+{
+    const int S1 = n / PK_ROWS, r1 = n - S1 * PK_ROWS;
+    const long bb = (long)bw * bw;
+    hipError_t e = hipSuccess;
+    if (S1 > 0) e = zgemm(st, 1, 0, bw, bw, PK_ROWS, 1.0, Yb, ld, PK_ROWS, Yb, ld, PK_ROWS, 0.0, part, bw, bb, S1);
+    if (e == hipSuccess && r1 > 0)
+        e = zgemm(st, 1, 0, bw, bw, r1, 1.0, Yb + S1 * PK_ROWS, ld, 0, Yb + S1 * PK_ROWS, ld, 0, 0.0,
+                  part + (long)S1 * bb, bw, 0, 1);
+    if (e == hipSuccess) e = sum_parts(st, part, S1 + (r1 > 0), bw, bw, G, bw, 0);
+    return e;
+}
+
 size_t bcgs2_work_bytes(int n, int m)
 {
-    const size_t w = (size_t)m * CG_BW;
-    const size_t p1 = (size_t)(n / PK_ROWS + 1) * m * CG_BW, p2 = (size_t)(m / PK_COLS + 1) * n * CG_BW;
-    return (w + std::max(p1, p2)) * 16 + 256;
+    const size_t w = (size_t)m * QB;
+    const size_t p1 = (size_t)(n / PK_ROWS + 1) * std::max(m, QB) * QB, p2 = (size_t)(m / PK_COLS + 1) * n * QB;
+    return (w + std::max(p1, p2) + 2 * (size_t)QB * QB + (size_t)n * QB) * 16 + 512;
 }
 
 // Block classical Gram-Schmidt with reorthogonalisation (BCGS2) of Y (n x m,
-// ld): each block of CG_BW columns is projected off the finished blocks and
-// orthonormalised inside the block, twice.  Columns found dependent
-// (remaining norm <= 4 eps sqrt(n) times their original norm) come out as zero
-// columns, so Q^H Q is the identity on the nonzero columns.
+// ld): each block of up to QB columns is projected off the finished blocks and
+// orthonormalised inside the block from its Gram matrix, twice.  Columns found
+// dependent (remaining norm <= 4 eps sqrt(n) times their original norm) come
+// out as zero columns, so Q^H Q is the identity on the nonzero columns.  A
+// block is cut where its Gram pivots stop being resolved in FP64 (columns of
+// very different scale in one block), and the rest starts the next block.
+// Once every column of a block is dependent, the range of Y is taken as
+// captured and the remaining columns are set to zero: for Gaussian sketch
+// columns the chance that a further column would still be independent is
+// below 0.01^QB.
 // work: bcgs2_work_bytes(n, m) bytes; n0: scratch of m doubles.
 hipError_t bcgs2(hipStream_t st, double2* Y, int ld, int n, int m, void* work, double* n0)
 {
     const double thr = 4.0 * 2.220446049250313e-16 * sqrt((double)n);
+    const double tau = 1e-6;
+    const size_t p1 = (size_t)(n / PK_ROWS + 1) * std::max(m, QB) * QB, p2 = (size_t)(m / PK_COLS + 1) * n * QB;
     double2* W = (double2*)work;
-    double2* part = W + (size_t)m * CG_BW;
+    double2* part = W + (size_t)m * QB;
+    double2* G = part + std::max(p1, p2);
+    double2* Ri = G + (size_t)QB * QB;
+    double2* T = Ri + (size_t)QB * QB;
+    int* flag = (int*)(T + (size_t)n * QB);
+    int hf[2] = {0, 0};
     hipError_t e = colnorms(st, n, m, Y, ld, 0, n0, 1);
     if (e != hipSuccess) return e;
-    for (int j0 = 0; j0 < m; j0 += CG_BW) {
-        const int bw = (m - j0 < CG_BW) ? m - j0 : CG_BW;
-        double2* Yj = Y + (long)j0 * ld;
-        // two full passes (project on the finished blocks, then orthonormalise inside the
-        // block): the second pass sees a block that is already well conditioned, which is
-        // what makes the reorthogonalisation effective when S is nearly rank deficient
-        for (int pass = 0; pass < 2; ++pass) {
-            if (j0 > 0) {
-                e = project_out(st, Y, ld, n, j0, bw, W, part);
-                if (e != hipSuccess) return e;
+    // column by column on columns [a, b) (two passes per CG_BW sub-block), for a block
+    // the Gram route cannot finish; orig: the columns still carry their original scale
+    auto exact = [&](int a, int b, bool orig) -> hipError_t {
+        for (int s0 = a; s0 < b; s0 += CG_BW) {
+            const int sbw = std::min(CG_BW, b - s0);
+            for (int pass = 0; pass < 2; ++pass) {
+                if (s0 > 0) {
+                    hipError_t x = project_out(st, Y, ld, n, s0, sbw, W, part);
+                    if (x != hipSuccess) return x;
+                }
+                hipLaunchKernelGGL(block_cgs2_kernel, dim3(1), dim3(CG_NT), 0, st, Y + (long)s0 * ld, ld, n, sbw,
+                                   (pass == 0 && orig) ? n0 + s0 : (const double*)nullptr, thr);
+                hipError_t x = hipGetLastError();
+                if (x != hipSuccess) return x;
+                if (s0 == 0) break;
             }
-            hipLaunchKernelGGL(block_cgs2_kernel, dim3(1), dim3(CG_NT), 0, st, Yj, ld, n, bw,
-                               pass == 0 ? n0 + j0 : (const double*)nullptr, thr);
-            e = hipGetLastError();
-            if (e != hipSuccess) return e;
-            if (j0 == 0) break;
         }
+        return hipSuccess;
+    };
+    for (int j0 = 0; j0 < m;) {
+        int bw = std::min(QB, m - j0);
+        double2* Yb = Y + (long)j0 * ld;
+        for (int pass = 0; pass < 2; ++pass) {
+            if (j0 > 0 && (e = project_out(st, Y, ld, n, j0, bw, W, part)) != hipSuccess) return e;
+            if ((e = gram_block(st, Yb, ld, n, bw, G, part)) != hipSuccess) return e;
+            hipLaunchKernelGGL(block_chol_kernel, dim3(1), dim3(CH_NT), 0, st, G, bw,
+                               pass == 0 ? n0 + j0 : (const double*)nullptr, thr, tau, Ri, flag);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if ((e = hipMemcpyAsync(hf, flag, sizeof(hf), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+            if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+            const int ldr = bw;
+            if (hf[0] < 1 || (pass == 1 && hf[0] < bw)) {
+                // not expected (see block_chol_kernel); finish these columns one by one
+                if ((e = exact(j0, j0 + bw, pass == 0)) != hipSuccess) return e;
+                break;
+            }
+            if (pass == 0) {
+                if (hf[0] == bw && hf[1] == 0) return zero_c128(st, n, m - j0, Yb, ld, 0, 1);
+                bw = hf[0];
+            }
+            if ((e = zgemm(st, 0, 0, n, bw, bw, 1.0, Yb, ld, 0, Ri, ldr, 0, 0.0, T, n, 0, 1)) != hipSuccess) return e;
+            if ((e = copy_c128(st, n, bw, T, n, 0, Yb, ld, 0, 1)) != hipSuccess) return e;
+        }
+        j0 += bw;
     }
     return hipSuccess;
 }
@@ -443,7 +639,7 @@ int jacobi_blocks(int p) { int nb = (p + JB_B - 1) / JB_B; return nb + (nb & 1);
 size_t jacobi_work_bytes(int m, int m_apply, int p)
 {
     const size_t pairs = (size_t)jacobi_blocks(p) / 2;
-    const size_t slices = (size_t)(std::max(m, 1) + JR - 1) / JR;
+    const size_t slices = (size_t)(std::max(m, 1) + JRG - 1) / JRG;
     (void)m_apply;
     return pairs * (slices + 1) * JB_W * JB_W * 16 + pairs * 4 + 256;
 }
@@ -452,14 +648,11 @@ hipError_t jacobi_round(hipStream_t st, double2* A, int lda, int m, int m_apply,
                         double tol, double zthr2, double* offmax, void* work)
 {
     const int nb = jacobi_blocks(p), pairs = nb / 2;
-    const int gs = (std::max(m, 1) + JR - 1) / JR, as = (m_apply + JR - 1) / JR;
+    const int gs = (std::max(m, 1) + JRG - 1) / JRG, as = (m_apply + JR - 1) / JR;
     double2* Gp = (double2*)work;
-    double2* V = Gp + (size_t)pairs * gs * JB_W * JB_W;
-    int* skip = (int*)(V + (size_t)pairs * JB_W * JB_W);
     hipLaunchKernelGGL(jacobi_gram_kernel, dim3(pairs, gs), dim3(JB_NT), 0, st, A, lda, m, p, nb, round, Gp);
-    hipLaunchKernelGGL(jacobi_solve_kernel, dim3(pairs), dim3(JS_NT), 0, st, Gp, gs, inner, tol, zthr2, V, skip, offmax);
-    hipLaunchKernelGGL(jacobi_apply_kernel, dim3(pairs, as), dim3(JB_NT), 0, st, A, lda, m_apply, p, nb, round, V,
-                       skip);
+    hipLaunchKernelGGL(jacobi_rotate_kernel, dim3(pairs, as), dim3(JB_NT), 0, st, A, lda, m_apply, p, nb, round, Gp,
+                       gs, inner, tol, zthr2, offmax);
     return hipGetLastError();
 }
 
