@@ -528,9 +528,31 @@ rsrr_status batched_impl(rsrr_ctx* c, int count, const rsrr_instance* inst, int 
         BatchedState& S; const int& n;
         ~Drain() { for (int i = 0; i < std::min(n, N_BUCKET_STREAMS); ++i) (void)hipStreamSynchronize(S.streams[i]); }
     } drain{S, nlaunched};
+    // Longest processing time first: buckets in decreasing order of their LU work
+    // (matrices x P^3), each on the stream with the least work assigned so far, so
+    // the largest bucket's long chain starts first instead of running alone at the end.
+    int nstreams = N_BUCKET_STREAMS;
+    if (const char* e = std::getenv("RSRR_BUCKET_STREAMS")) nstreams = std::max(1, std::min(N_BUCKET_STREAMS, std::atoi(e)));
+    std::vector<std::pair<double, int>> order;  // (work, P)
     for (auto& kv : buckets) {
-        const int P = kv.first;
-        const std::vector<int>& ids = kv.second;
+        long pts = 0;
+        for (int id : kv.second) pts += inst[id].N;
+        order.push_back({(double)pts * kv.first * (double)kv.first * kv.first, kv.first});
+    }
+    std::stable_sort(order.begin(), order.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+        return a.first > b.first;
+    });
+    std::vector<double> load(nstreams, 0.0);
+    auto next_stream = [&](double work) {
+        int s = 0;
+        for (int i = 1; i < nstreams; ++i)
+            if (load[i] < load[s]) s = i;
+        load[s] += work;
+        return S.streams[s];
+    };
+    for (auto& ow : order) {
+        const int P = ow.second;
+        const std::vector<int>& ids = buckets[P];
         std::vector<long> off(ids.size() + 1, 0);
         int Lmax = 0, maxn = 0;
         for (size_t q = 0; q < ids.size(); ++q) {
@@ -637,14 +659,14 @@ rsrr_status batched_impl(rsrr_ctx* c, int count, const rsrr_instance* inst, int 
                 if (ie != hipSuccess) { slot.reset(); return RSRR_EDEVICE; }
             }
             // after everything enqueued on the context stream so far
-            hipStream_t ps = S.streams[nlaunched % N_BUCKET_STREAMS];
+            hipStream_t ps = next_stream(ow.first);
             RSRR_HIP(hipEventRecord(c->fork, c->stream));
             RSRR_HIP(hipStreamWaitEvent(ps, c->fork, 0));
             RSRR_HIP(hipGraphLaunch(slot->exec, ps));
             ++nlaunched;
             pending.push_back(Pending{ids, off, M, b.info, b.iters, b.resid, {}, {}, {}, {}});
         } else {
-            hipStream_t ps = S.streams[nlaunched % N_BUCKET_STREAMS];
+            hipStream_t ps = next_stream(ow.first);
             RSRR_HIP(hipEventRecord(c->fork, c->stream));
             RSRR_HIP(hipStreamWaitEvent(ps, c->fork, 0));
             std::vector<FactorStore*> kq;

@@ -57,12 +57,15 @@ extern "C" rsrr_status rsrr_solve(rsrr_ctx* c, const rsrr_nep* nep, int k, const
     double2* mom = (double2*)ws_get(c, WS_B0, (size_t)twoK * kk * 16);
     if (!mom) return RSRR_ENOMEM;
     RSRR_HIP(hipMemsetAsync(mom, 0, (size_t)twoK * kk * 16, c->stream));
-    const size_t per_pt = (size_t)kk * 16 * 2 + (size_t)k * 4 + 64 * 1024;
+    const int nb = 64;
+    const int np = perm_panels(k);
+    // the diagonal blocks of the FP64 LU are inverted once per panel, so the solves
+    // with the k columns of I are products on the matrix cores
+    const long sInv = 2L * ((k + nb - 1) / nb) * nb * nb, sTmp = (long)nb * k;
+    const size_t per_pt = (size_t)kk * 16 * 2 + (size_t)k * 4 + 64 * 1024 + (size_t)(sInv + sTmp) * 16;
     // points per batched LU: 8 GiB of buffers, or the context's workspace budget when set
     const size_t mom_budget = c->ws_budget ? std::min<size_t>(c->ws_budget, (size_t)8 << 30) : (size_t)8 << 30;
     const int Mc = (int)std::max<size_t>(1, std::min<size_t>((size_t)std::min(NQ, 256), mom_budget / per_pt));
-    const int nb = 64;
-    const int np = perm_panels(k);
     double2* T = (double2*)ws_get(c, WS_TLU, (size_t)Mc * kk * 16);
     double2* X = (double2*)ws_get(c, WS_TRES, (size_t)Mc * kk * 16);
     int* ipiv = (int*)ws_get(c, WS_IPIV, (size_t)Mc * k * 4);
@@ -75,7 +78,10 @@ extern "C" rsrr_status rsrr_solve(rsrr_ctx* c, const rsrr_nep* nep, int k, const
     double* frob = (double*)ws_get(c, WS_FROB, (size_t)Mc * 8);
     const long nparts = (kk + 255) / 256;
     double* frobp = (double*)ws_get(c, WS_FROBP, (size_t)Mc * nparts * 8);
-    if (!T || !X || !ipiv || !perm || !tperm || !info || !coef || !cw || !I || !frob || !frobp) return RSRR_ENOMEM;
+    double2* inv = (double2*)ws_get(c, WS_B5, (size_t)Mc * sInv * 16);
+    double2* tmp = (double2*)ws_get(c, WS_B6, (size_t)Mc * sTmp * 16);
+    if (!T || !X || !ipiv || !perm || !tperm || !info || !coef || !cw || !I || !frob || !frobp || !inv || !tmp)
+        return RSRR_ENOMEM;
     RSRR_HIP(eye(c->stream, I, k, 0, k));
     int singular = 0;
     std::vector<double2> hcoef((size_t)J_eff * Mc), hcw((size_t)Mc * twoK);
@@ -104,6 +110,7 @@ extern "C" rsrr_status rsrr_solve(rsrr_ctx* c, const rsrr_nep* nep, int k, const
         LUWork w;
         w.ipiv = ipiv; w.sP = k; w.perm = perm; w.sPerm = (long)np * 2 * MAX_NB; w.tperm = tperm;
         w.sTP = 8L * 2 * MAX_NB; w.info = info;
+        w.inv = inv; w.sInv = sInv; w.tmp = tmp; w.sTmp = sTmp;
         RSRR_HIP(getrf_batched<double>(c->stream, T, kk, k, k, nb, w, B));
         RSRR_HIP(bcast_c128(c->stream, k, k, I, k, X, k, kk, B));
         RSRR_HIP(getrs_batched<double>(c->stream, T, kk, k, k, nb, w, X, kk, k, k, B));

@@ -57,8 +57,10 @@ struct UpdateRecorder {
 //  perm  : perm_panels(n)*2*MAX_NB int2     (stride sPerm), composed interchanges per panel
 //  tperm : 8*2*MAX_NB int2                 (stride sTP), recursion scratch
 //  info  : 1 int, zero on entry            (getrf semantics; < 0: NaN/Inf pivot)
-//  inv   : complex-FP32 path only: panels*2*nb*nb complex (stride sInv), L11^-1, U11^-1
-//  tmp   : complex-FP32 path only: nb*max(n, nrhs) complex (stride sTmp)
+//  inv   : FP32 paths, and FP64 when given together with tmp (the diagonal blocks are
+//          then solved by products with their inverses, as in FP32):
+//          panels*2*nb*nb elements (stride sInv), L11^-1, U11^-1
+//  tmp   : with inv: nb*max(n, nrhs) elements (stride sTmp)
 //  active: optional per-matrix mask; rec: optional trailing-update event recorder
 //  pair  : FP32 paths, optional: (ldpair*2*nb + nb*nb) elements per matrix (stride sPair,
 //          ldpair >= n): two panels then share one trailing update of depth 2nb

@@ -663,7 +663,9 @@ static hipError_t getrf_impl(hipStream_t st, C* A, long sA, int lda, int n, int 
                          int batch)
 {
     typedef real_t<C> R;
-    constexpr bool use_inv = sizeof(R) == 4;
+    // diagonal-block inverses and products on the matrix cores: always in FP32, in
+    // FP64 when the caller gives the inverse and scratch buffers
+    const bool use_inv = sizeof(R) == 4 || (w.inv != nullptr && w.tmp != nullptr);
     if (nb > max_panel<R>()) nb = max_panel<R>();
     if (nb < MIN_NB) nb = MIN_NB;  // perm/inv storage holds perm_panels(n) panels
     UpdateRecorder* rec = w.rec;
@@ -694,7 +696,7 @@ static hipError_t getrf_impl(hipStream_t st, C* A, long sA, int lda, int n, int 
         int2* pm = w.perm + (long)p * 2 * MAX_NB;
         hipLaunchKernelGGL(perm_build_kernel, dim3(batch), dim3(64), 0, s, w.ipiv, w.sP, c0, jb, pm, w.sPerm,
                            w.active);
-        if constexpr (use_inv) tri_inv<C>(s, A, sA, lda, c0, jb, (C*)w.inv, w.sInv, nb, w.active, batch);
+        if (use_inv) tri_inv<C>(s, A, sA, lda, c0, jb, (C*)w.inv, w.sInv, nb, w.active, batch);
         return pm;
     };
     // Two panels may share one trailing update of depth jb0 + jb1 (the deeper
@@ -851,7 +853,7 @@ static hipError_t getrs_impl(hipStream_t st, const C* LU, long sLU, int lda, int
                          const LUWork& w, C* X, long sX, int ldx, int nrhs, int batch)
 {
     typedef real_t<C> R;
-    constexpr bool use_inv = sizeof(R) == 4;
+    const bool use_inv = sizeof(R) == 4 || (w.inv != nullptr && w.tmp != nullptr);
     if (nb > max_panel<R>()) nb = max_panel<R>();
     if (nb < MIN_NB) nb = MIN_NB;
     const int np = (n + nb - 1) / nb;
