@@ -769,9 +769,8 @@ static hipError_t getrf_impl(hipStream_t st, C* A, long sA, int lda, int n, int 
             const int wn = 2 * nb;
             timed_update(rest, wn, 2 * nb, Aop, ldw, w.sPair, Bop, Cop);
             (void)hipEventRecord(w.ev_a, st);
-            (void)hipStreamWaitEvent(w.side, w.ev_a, 0);
-            front(w.side, c2, p + 2, Wb[buf ^ 1]);
-            (void)hipEventRecord(w.ev_b, w.side);
+            // the rest of the update is enqueued before the next pair's panels (a chain of
+            // small launches), so the host never holds it back behind them
             if (w.upd && w.ev_c) {
                 // the first la_cols columns of the update on the CUs the side stream does not
                 // use (while the next panels are factored), the rest on every CU
@@ -787,6 +786,9 @@ static hipError_t getrf_impl(hipStream_t st, C* A, long sA, int lda, int n, int 
             } else {
                 timed_update(rest, rest - wn, 2 * nb, Aop, ldw, w.sPair, Bop + (long)wn * lda, Cop + (long)wn * lda);
             }
+            (void)hipStreamWaitEvent(w.side, w.ev_a, 0);
+            front(w.side, c2, p + 2, Wb[buf ^ 1]);
+            (void)hipEventRecord(w.ev_b, w.side);
             (void)hipStreamWaitEvent(st, w.ev_b, 0);
             c0 = c2;
             p += 2;
