@@ -357,8 +357,10 @@ typedef struct {
 
 /* Flags of rsrr_sample_batched. */
 enum {
-    RSRR_BATCH_GRAPH = 1,     /* capture each size bucket's work in a hipGraph; replay it when the
-                                 same batch (same buffers, sizes and points) is submitted again   */
+    RSRR_BATCH_GRAPH = 1,     /* capture the whole call in one hipGraph (every size bucket an
+                                 independent branch, spread over the bucket streams) and replay it
+                                 with one launch when the same batch (same buffers, sizes and
+                                 points) is submitted again                                        */
     RSRR_BATCH_AUTOTUNE = 2   /* time panel widths x update tiles on the first call for each size bucket */
 };
 
@@ -369,8 +371,8 @@ enum {
  * device with at most ir_max_iters_batched corrections (rsrr_options,
  * default 3); points above fallback_resid (default 1e-10) relative residual
  * are redone on the FP64 path.  info: host, sum of N entries in instance
- * order (may be NULL).  The library keeps per-bucket buffers (and graphs) in
- * the context until rsrr_destroy.  With RSRR_BATCH_AUTOTUNE, the first call
+ * order (may be NULL).  The library keeps per-bucket buffers (and the last
+ * call's graph) in the context until rsrr_destroy.  With RSRR_BATCH_AUTOTUNE, the first call
  * for a size bucket times one bucket pass for every candidate configuration
  * (LU panel width 32/64/128 x workgroup tile of the complex FP32 trailing
  * update: 3M 128x64, 3M 64x64, 4M 128x128, 4M 64x64, all four waves and two

@@ -35,11 +35,14 @@ namespace {
 
 constexpr int BUCKET = 64;
 
+// One captured graph for a whole batched call: every bucket's work as an
+// independent branch (forked from the capture stream onto the bucket streams and
+// joined back), replayed with one launch.
 struct GraphEntry {
     std::vector<unsigned long long> key;
     hipGraphExec_t exec = nullptr;
-    std::vector<double2> coef_host;   // host staging referenced by the captured copies
-    std::vector<int> nk_host;
+    std::vector<std::vector<double2>> coef_host;   // host staging referenced by the captured copies
+    std::vector<std::vector<int>> nk_host;
 };
 
 constexpr int N_BUCKET_STREAMS = 8;  // replayed buckets run side by side on these (default priority)
@@ -64,7 +67,8 @@ struct BatchedState {
     long calls = 0;
     std::map<long, Tuned> tuned;                  // (P*2 + prec) -> panel width and update tile
     std::string arch;                             // device architecture the tuned entries are for
-    std::map<long, std::unique_ptr<GraphEntry>> graphs;  // bucket P*2+prec -> captured graph
+    std::unique_ptr<GraphEntry> graph;            // the last call's captured graph
+    hipEvent_t cap_fork = nullptr;                // fork point inside a capture
     std::vector<void*> bufs;
     std::vector<size_t> sizes;
     bool file_loaded = false;
@@ -333,8 +337,8 @@ void batched_release(rsrr_ctx* c)
     auto& m = states();
     auto it = m.find(c);
     if (it == m.end()) return;
-    for (auto& g : it->second->graphs)
-        if (g.second && g.second->exec) (void)hipGraphExecDestroy(g.second->exec);
+    if (it->second->graph && it->second->graph->exec) (void)hipGraphExecDestroy(it->second->graph->exec);
+    if (it->second->cap_fork) (void)hipEventDestroy(it->second->cap_fork);
     for (int i = 0; i < N_BUCKET_STREAMS; ++i) {
         if (it->second->streams[i]) (void)hipStreamDestroy(it->second->streams[i]);
         if (it->second->done[i]) (void)hipEventDestroy(it->second->done[i]);
@@ -521,6 +525,7 @@ rsrr_status batched_impl(rsrr_ctx* c, int count, const rsrr_instance* inst, int 
             RSRR_HIP(hipStreamCreateWithFlags(&S.streams[i], hipStreamNonBlocking));
             RSRR_HIP(hipEventCreateWithFlags(&S.done[i], hipEventDisableTiming));
         }
+        RSRR_HIP(hipEventCreateWithFlags(&S.cap_fork, hipEventDisableTiming));
     }
     int nlaunched = 0;
     // on every return the launched buckets have finished before `pending` (host tables) goes away
@@ -548,8 +553,16 @@ rsrr_status batched_impl(rsrr_ctx* c, int count, const rsrr_instance* inst, int 
         for (int i = 1; i < nstreams; ++i)
             if (load[i] < load[s]) s = i;
         load[s] += work;
-        return S.streams[s];
+        return s;
     };
+    // graph mode: the buckets' plans, captured together after the loop
+    struct Plan {
+        std::vector<int> ids; std::vector<long> off; long M; int P, Lmax, nb, tile, sidx; BucketBufs b;
+        std::vector<double2> coef; std::vector<int> nk;
+    };
+    std::vector<Plan> plans;
+    std::vector<unsigned long long> gkey;
+    const int maxit = c->ir_max_iters_batched;
     for (auto& ow : order) {
         const int P = ow.second;
         const std::vector<int>& ids = buckets[P];
@@ -614,59 +627,30 @@ rsrr_status batched_impl(rsrr_ctx* c, int count, const rsrr_instance* inst, int 
         }
         TileScope tile_scope(tile);
 
-        const int maxit = c->ir_max_iters_batched;
         if (use_graph) {
             // key: everything the captured work depends on
-            std::vector<unsigned long long> key;
-            key.push_back((unsigned long long)P);
-            key.push_back((unsigned long long)prec);
-            key.push_back((unsigned long long)nb);
-            key.push_back((unsigned long long)tile);
-            key.push_back((unsigned long long)M);
-            key.push_back((unsigned long long)maxit);
+            gkey.push_back((unsigned long long)P);
+            gkey.push_back((unsigned long long)prec);
+            gkey.push_back((unsigned long long)nb);
+            gkey.push_back((unsigned long long)tile);
+            gkey.push_back((unsigned long long)M);
+            gkey.push_back((unsigned long long)maxit);
             unsigned long long tolbits;
             std::memcpy(&tolbits, &c->ir_tol, 8);
-            key.push_back(tolbits);
+            gkey.push_back(tolbits);
             for (int id : ids) {
                 const rsrr_instance& in = inst[id];
-                key.push_back((unsigned long long)(uintptr_t)in.nep.A);
-                key.push_back((unsigned long long)(uintptr_t)in.nep.points);
-                key.push_back((unsigned long long)(uintptr_t)in.U);
-                key.push_back((unsigned long long)(uintptr_t)in.S);
-                key.push_back(((unsigned long long)in.nep.n << 32) | (unsigned)in.N);
-                key.push_back(((unsigned long long)in.L << 32) | (unsigned)in.lds);
+                gkey.push_back((unsigned long long)(uintptr_t)in.nep.A);
+                gkey.push_back((unsigned long long)(uintptr_t)in.nep.points);
+                gkey.push_back((unsigned long long)(uintptr_t)in.U);
+                gkey.push_back((unsigned long long)(uintptr_t)in.S);
+                gkey.push_back(((unsigned long long)in.nep.n << 32) | (unsigned)in.N);
+                gkey.push_back(((unsigned long long)in.L << 32) | (unsigned)in.lds);
             }
-            auto& slot = S.graphs[tkey];
-            const bool hit = slot && slot->key == key && slot->coef_host.size() == coef.size() &&
-                             std::memcmp(slot->coef_host.data(), coef.data(), coef.size() * 16) == 0;
-            if (!hit) {
-                if (slot && slot->exec) (void)hipGraphExecDestroy(slot->exec);
-                slot = std::make_unique<GraphEntry>();
-                slot->key = key;
-                slot->coef_host = coef;
-                slot->nk_host = nk;
-                RSRR_HIP(hipEventRecord(c->fork, c->stream));
-                RSRR_HIP(hipStreamWaitEvent(c->aux, c->fork, 0));
-                RSRR_HIP(hipStreamBeginCapture(c->aux, hipStreamCaptureModeThreadLocal));
-                rsrr_status st = run_bucket(c, c->aux, inst, ids, off, P, Lmax, M, prec, nb, b,
-                                            slot->coef_host.data(), slot->nk_host.data(), maxit);
-                hipGraph_t g = nullptr;
-                const hipError_t ce = hipStreamEndCapture(c->aux, &g);
-                if (st) { if (g) (void)hipGraphDestroy(g); slot.reset(); return st; }
-                if (ce != hipSuccess || !g) { slot.reset(); return RSRR_EDEVICE; }
-                const hipError_t ie = hipGraphInstantiate(&slot->exec, g, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(g);
-                if (ie != hipSuccess) { slot.reset(); return RSRR_EDEVICE; }
-            }
-            // after everything enqueued on the context stream so far
-            hipStream_t ps = next_stream(ow.first);
-            RSRR_HIP(hipEventRecord(c->fork, c->stream));
-            RSRR_HIP(hipStreamWaitEvent(ps, c->fork, 0));
-            RSRR_HIP(hipGraphLaunch(slot->exec, ps));
-            ++nlaunched;
-            pending.push_back(Pending{ids, off, M, b.info, b.iters, b.resid, {}, {}, {}, {}});
+            plans.push_back(Plan{ids, off, M, P, Lmax, nb, tile, next_stream(ow.first), b, std::move(coef),
+                                 std::move(nk)});
         } else {
-            hipStream_t ps = next_stream(ow.first);
+            hipStream_t ps = S.streams[next_stream(ow.first)];
             RSRR_HIP(hipEventRecord(c->fork, c->stream));
             RSRR_HIP(hipStreamWaitEvent(ps, c->fork, 0));
             std::vector<FactorStore*> kq;
@@ -680,6 +664,69 @@ rsrr_status batched_impl(rsrr_ctx* c, int count, const rsrr_instance* inst, int 
                                         maxit, keep ? pd.keep.data() : nullptr, keep ? pd.k0.data() : nullptr);
             if (st) return st;
             ++nlaunched;
+        }
+    }
+    if (use_graph && !plans.empty()) {
+        bool hit = S.graph && S.graph->key == gkey && S.graph->coef_host.size() == plans.size();
+        for (size_t i = 0; hit && i < plans.size(); ++i)
+            hit = S.graph->coef_host[i].size() == plans[i].coef.size() &&
+                  std::memcmp(S.graph->coef_host[i].data(), plans[i].coef.data(), plans[i].coef.size() * 16) == 0;
+        if (!hit) {
+            if (S.graph && S.graph->exec) (void)hipGraphExecDestroy(S.graph->exec);
+            S.graph = std::make_unique<GraphEntry>();
+            GraphEntry& ge = *S.graph;
+            ge.key = gkey;
+            for (Plan& pl : plans) {
+                ge.coef_host.push_back(pl.coef);
+                ge.nk_host.push_back(pl.nk);
+            }
+            // capture: fork from the capture stream onto the bucket streams, every bucket
+            // on its stream, join back
+            RSRR_HIP(hipEventRecord(c->fork, c->stream));
+            RSRR_HIP(hipStreamWaitEvent(c->aux, c->fork, 0));
+            RSRR_HIP(hipStreamBeginCapture(c->aux, hipStreamCaptureModeThreadLocal));
+            rsrr_status st = RSRR_OK;
+            hipError_t ce = hipEventRecord(S.cap_fork, c->aux);
+            std::vector<char> used(N_BUCKET_STREAMS, 0);
+            for (size_t i = 0; i < plans.size() && st == RSRR_OK && ce == hipSuccess; ++i) {
+                Plan& pl = plans[i];
+                hipStream_t ps = S.streams[pl.sidx];
+                if (!used[pl.sidx]) {
+                    ce = hipStreamWaitEvent(ps, S.cap_fork, 0);
+                    used[pl.sidx] = 1;
+                    if (ce != hipSuccess) break;
+                }
+                TileScope ts(pl.tile);
+                st = run_bucket(c, ps, inst, pl.ids, pl.off, pl.P, pl.Lmax, pl.M, prec, pl.nb, pl.b,
+                                ge.coef_host[i].data(), ge.nk_host[i].data(), maxit);
+            }
+            for (int i = 0; i < N_BUCKET_STREAMS; ++i) {
+                if (!used[i]) continue;
+                // every forked stream is joined back, also after an error, so the capture ends
+                (void)hipEventRecord(S.done[i], S.streams[i]);
+                (void)hipStreamWaitEvent(c->aux, S.done[i], 0);
+            }
+            hipGraph_t g = nullptr;
+            const hipError_t ee = hipStreamEndCapture(c->aux, &g);
+            if (st || ce != hipSuccess || ee != hipSuccess || !g) {
+                if (g) (void)hipGraphDestroy(g);
+                S.graph.reset();
+                return st ? st : RSRR_EDEVICE;
+            }
+            const hipError_t ie = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ie != hipSuccess) { S.graph.reset(); return RSRR_EDEVICE; }
+        }
+        // one launch for the whole call, after everything enqueued on the context stream so far
+        RSRR_HIP(hipEventRecord(c->fork, c->stream));
+        RSRR_HIP(hipStreamWaitEvent(c->aux, c->fork, 0));
+        RSRR_HIP(hipGraphLaunch(S.graph->exec, c->aux));
+        RSRR_HIP(hipEventRecord(c->join, c->aux));
+        RSRR_HIP(hipStreamWaitEvent(c->stream, c->join, 0));
+        for (const Plan& pl : plans) {
+            const rsrr_status st = report_bucket(c, inst, pl.ids, pl.off, pl.M, pl.b.info, pl.b.iters, pl.b.resid,
+                                                 pbase, info, fl);
+            if (st) return st;
         }
     }
     if (!pending.empty()) {
@@ -810,13 +857,10 @@ void batched_trim(rsrr_ctx* c, size_t keep_bytes)
             if (tot <= keep_bytes) break;
             if (pass == 0 && u.first == S.calls) continue;
             const int P = u.second;
-            const long tkey0 = (long)P * 2, tkey1 = tkey0 + 1;
-            for (long tk : {tkey0, tkey1}) {
-                auto g = S.graphs.find(tk);
-                if (g != S.graphs.end()) {
-                    if (g->second && g->second->exec) (void)hipGraphExecDestroy(g->second->exec);
-                    S.graphs.erase(g);
-                }
+            // the captured graph points at every bucket's buffers
+            if (S.graph) {
+                if (S.graph->exec) (void)hipGraphExecDestroy(S.graph->exec);
+                S.graph.reset();
             }
             const int s0 = (P / BUCKET) * 32;
             for (int sl = s0; sl < s0 + 32 && sl < (int)S.bufs.size(); ++sl) {
