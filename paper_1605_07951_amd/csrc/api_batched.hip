@@ -35,14 +35,24 @@ namespace {
 
 constexpr int BUCKET = 64;
 
+// Host tables of one bucket: per-matrix order, coefficient (separable) or point
+// (Helmholtz) table of every instance in bucket order, and the instance tables of
+// the bucket-wide launches (sep empty unless every instance is separable).
+struct BucketHost {
+    std::vector<int> nk;
+    std::vector<double2> coef;
+    std::vector<SepInstance> sep;
+    std::vector<RhsInstance> rhs;
+    int nmax = 0, Nmax = 0;
+};
+
 // One captured graph for a whole batched call: every bucket's work as an
 // independent branch (forked from the capture stream onto the bucket streams and
 // joined back), replayed with one launch.
 struct GraphEntry {
     std::vector<unsigned long long> key;
     hipGraphExec_t exec = nullptr;
-    std::vector<std::vector<double2>> coef_host;   // host staging referenced by the captured copies
-    std::vector<std::vector<int>> nk_host;
+    std::vector<BucketHost> host;   // the captured buckets' host tables (uploaded before every replay)
 };
 
 constexpr int N_BUCKET_STREAMS = 8;  // replayed buckets run side by side on these (default priority)
@@ -201,7 +211,7 @@ struct BucketBufs {
     void* T; double2* T128; double2* Ub; double2* Xb; double2* R; float2* D64; int* ipiv; int2* perm; int2* tperm;
     int* info; void* inv; void* tmp; int* nk; double2* coef; double* frobp; double* frob; double* un; double* rn;
     double* xn; double* inv_s; double* scl; int* active; double* prev; double* resid; int* iters; double* ones;
-    void* pair;
+    void* pair; SepInstance* sep; RhsInstance* rhs;
     long sT, sU, sP, sPerm, sTP, sInv, sTmp, sPair;
 };
 
@@ -209,15 +219,29 @@ struct BucketBufs {
 long bucket_sPerm(int P) { return (long)perm_panels(P) * 2 * MAX_NB; }
 long bucket_sInv(int P, bool mixed) { return mixed ? 2L * max_panel<float>() * (P + max_panel<float>()) : 0; }
 
-// Everything a bucket does on the device, in stream order (capturable).
+// The bucket's host tables into its device buffers.
+hipError_t upload_tables(hipStream_t sm, const BucketHost& h, BucketBufs& b)
+{
+    hipError_t e = hipMemcpyAsync(b.nk, h.nk.data(), h.nk.size() * 4, hipMemcpyHostToDevice, sm);
+    if (e == hipSuccess) e = hipMemcpyAsync(b.coef, h.coef.data(), h.coef.size() * 16, hipMemcpyHostToDevice, sm);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b.rhs, h.rhs.data(), h.rhs.size() * sizeof(RhsInstance), hipMemcpyHostToDevice, sm);
+    if (e == hipSuccess && !h.sep.empty())
+        e = hipMemcpyAsync(b.sep, h.sep.data(), h.sep.size() * sizeof(SepInstance), hipMemcpyHostToDevice, sm);
+    return e;
+}
+
+// Everything a bucket does on the device, in stream order (capturable with
+// upload = false once the tables are on the device).
 // keep (may be null): per entry of ids, the store that receives that instance's
 // factors (null: none) at point keep_k0[q].  from (may be null): the bucket is one
 // instance whose factors are already in this store from point from_k0: no
 // complex FP32 assembly and no factorisation.
 rsrr_status run_bucket(rsrr_ctx* c, hipStream_t sm, const rsrr_instance* inst, const std::vector<int>& ids,
                        const std::vector<long>& off, int P, int Lmax, long M, int prec, int nb, BucketBufs& b,
-                       const double2* coef_host, const int* nk_host, int maxit, FactorStore* const* keep = nullptr,
-                       const int* keep_k0 = nullptr, const FactorStore* from = nullptr, int from_k0 = 0)
+                       const BucketHost& h, int maxit, FactorStore* const* keep = nullptr,
+                       const int* keep_k0 = nullptr, const FactorStore* from = nullptr, int from_k0 = 0,
+                       bool upload = true)
 {
     const bool mixed = prec == RSRR_PREC_C64_IR;
     const size_t esz = mixed ? 8 : 16;
@@ -227,41 +251,49 @@ rsrr_status run_bucket(rsrr_ctx* c, hipStream_t sm, const rsrr_instance* inst, c
         b.perm = from->perm + (size_t)from_k0 * from->sPerm;
         b.inv = mixed ? (void*)((char*)from->inv + (size_t)from_k0 * from->sInv * 8) : nullptr;
     }
-    // per-matrix sizes and the identity padding
-    RSRR_HIP(hipMemcpyAsync(b.nk, nk_host, (size_t)M * 4, hipMemcpyHostToDevice, sm));
+    // host tables (unless the caller uploaded them: a captured graph holds kernels only),
+    // then the per-matrix identity padding
+    const int nins = (int)ids.size();
+    if (upload) RSRR_HIP(upload_tables(sm, h, b));
     RSRR_HIP(pad_identity(sm, mixed && !from ? (float2*)b.T : nullptr, b.T128, P, b.sT, P, b.nk, (int)M));
     if (!mixed && !from) RSRR_HIP(pad_identity(sm, nullptr, (double2*)b.T, P, b.sT, P, b.nk, (int)M));
-    // assembly of every instance's points (FP64 sums, c64 and c128 copies)
-    long coff = 0;
-    for (size_t q = 0; q < ids.size(); ++q) {
-        const rsrr_instance& in = inst[ids[q]];
-        const int n = in.nep.n;
-        const long nparts = ((long)n * n + 255) / 256;
-        if (in.nep.kind == RSRR_T_SEPARABLE) {
-            const long cnt = (long)in.nep.J * in.N;
-            RSRR_HIP(hipMemcpyAsync(b.coef + coff, coef_host + coff, (size_t)cnt * 16, hipMemcpyHostToDevice, sm));
-            RSRR_HIP(assemble_separable(sm, n, in.nep.J, (const double2*)in.nep.A, in.nep.lda, b.coef + coff, in.N,
-                                        mixed && !from ? (float2*)b.T + off[q] * b.sT : nullptr, P, b.sT,
-                                        b.T128 + off[q] * b.sT, P, b.sT, b.frobp + off[q] * nparts, b.frob + off[q]));
-            coff += cnt;
-        } else {
-            const long cnt = in.N;
-            RSRR_HIP(hipMemcpyAsync(b.coef + coff, coef_host + coff, (size_t)cnt * 16, hipMemcpyHostToDevice, sm));
-            RSRR_HIP(assemble_helmholtz(sm, n, in.nep.points, in.nep.w, b.coef + coff, in.N,
-                                        mixed && !from ? (float2*)b.T + off[q] * b.sT : nullptr, P, b.sT,
-                                        b.T128 + off[q] * b.sT, P, b.sT, b.frobp + off[q] * nparts, b.frob + off[q]));
-            coff += cnt;
+    if (!h.sep.empty()) {
+        // every instance separable: the whole bucket's assembly in one launch (FP64 sums,
+        // c64 and c128 copies) and one for the norms
+        RSRR_HIP(assemble_separable_group(sm, b.sep, nins, h.nmax, h.Nmax, b.coef, P, (int)M, b.nk,
+                                          mixed && !from ? (float2*)b.T : nullptr, b.sT, b.T128, b.sT, b.frobp,
+                                          b.frob));
+        if (!mixed && !from) RSRR_HIP(copy_c128(sm, P, P, b.T128, P, b.sT, (double2*)b.T, P, b.sT, (int)M));
+    } else {
+        // assembly of every instance's points (FP64 sums, c64 and c128 copies)
+        long coff = 0;
+        for (size_t q = 0; q < ids.size(); ++q) {
+            const rsrr_instance& in = inst[ids[q]];
+            const int n = in.nep.n;
+            const long nparts = ((long)n * n + 255) / 256;
+            if (in.nep.kind == RSRR_T_SEPARABLE) {
+                const long cnt = (long)in.nep.J * in.N;
+                RSRR_HIP(assemble_separable(sm, n, in.nep.J, (const double2*)in.nep.A, in.nep.lda, b.coef + coff,
+                                            in.N, mixed && !from ? (float2*)b.T + off[q] * b.sT : nullptr, P, b.sT,
+                                            b.T128 + off[q] * b.sT, P, b.sT, b.frobp + off[q] * nparts,
+                                            b.frob + off[q]));
+                coff += cnt;
+            } else {
+                const long cnt = in.N;
+                RSRR_HIP(assemble_helmholtz(sm, n, in.nep.points, in.nep.w, b.coef + coff, in.N,
+                                            mixed && !from ? (float2*)b.T + off[q] * b.sT : nullptr, P, b.sT,
+                                            b.T128 + off[q] * b.sT, P, b.sT, b.frobp + off[q] * nparts,
+                                            b.frob + off[q]));
+                coff += cnt;
+            }
+            if (!mixed && !from)
+                RSRR_HIP(copy_c128(sm, n, n, b.T128 + off[q] * b.sT, P, b.sT, (double2*)b.T + off[q] * b.sT, P,
+                                   b.sT, in.N));
         }
-        if (!mixed && !from)
-            RSRR_HIP(copy_c128(sm, n, n, b.T128 + off[q] * b.sT, P, b.sT, (double2*)b.T + off[q] * b.sT, P, b.sT,
-                               in.N));
     }
-    // padded right-hand sides [U; 0]
+    // padded right-hand sides [U; 0], all instances in one launch
     RSRR_HIP(zero_c128(sm, P, Lmax, b.Ub, P, b.sU, (int)M));
-    for (size_t q = 0; q < ids.size(); ++q) {
-        const rsrr_instance& in = inst[ids[q]];
-        RSRR_HIP(bcast_c128(sm, in.nep.n, in.L, (const double2*)in.U, in.ldu, b.Ub + off[q] * b.sU, P, b.sU, in.N));
-    }
+    RSRR_HIP(bcast_group(sm, b.rhs, nins, h.nmax, Lmax, h.Nmax, b.Ub, P, b.sU));
     RSRR_HIP(colnorms(sm, P, Lmax, b.Ub, P, b.sU, b.un, (int)M));
     // factorisation
     RSRR_HIP(zero_int(sm, b.info, (int)M));
@@ -305,12 +337,8 @@ rsrr_status run_bucket(rsrr_ctx* c, hipStream_t sm, const rsrr_instance* inst, c
         RSRR_HIP(getrs_batched<float>(sm, (const float2*)b.T, b.sT, P, P, nb, w, b.D64, b.sU, P, Lmax, (int)M));
         RSRR_HIP(axpy_widen(sm, P, Lmax, b.D64, P, b.sU, b.scl, b.Xb, P, b.sU, b.active, (int)M));
     }
-    // results into each instance's S
-    for (size_t q = 0; q < ids.size(); ++q) {
-        const rsrr_instance& in = inst[ids[q]];
-        RSRR_HIP(copy_c128(sm, in.nep.n, in.L, b.Xb + off[q] * b.sU, P, b.sU, (double2*)in.S, in.lds,
-                           (long)in.L * in.lds, in.N));
-    }
+    // results into each instance's S, all instances in one launch
+    RSRR_HIP(copy_out_group(sm, b.rhs, nins, h.nmax, Lmax, h.Nmax, b.Xb, P, b.sU));
     // factors kept on the device for later solves (same strides in the store)
     for (size_t q = 0; keep && q < ids.size(); ++q) {
         FactorStore* fs = keep[q];
@@ -350,32 +378,48 @@ void batched_release(rsrr_ctx* c)
 
 namespace {
 
-// Host tables of one bucket: per-matrix n and the coefficient (separable) or point
-// (Helmholtz) table of every instance, in bucket order.
+// Host tables of one bucket (see BucketHost).
 void bucket_tables(const rsrr_instance* inst, const std::vector<int>& ids, const std::vector<long>& off,
-                   std::vector<int>& nk, std::vector<double2>& coef)
+                   BucketHost& h)
 {
-    nk.assign(off.back(), 0);
-    coef.clear();
+    h.nk.assign(off.back(), 0);
+    h.coef.clear();
+    h.sep.clear();
+    h.rhs.clear();
+    h.nmax = h.Nmax = 0;
+    bool all_sep = true;
     for (size_t q = 0; q < ids.size(); ++q) {
         const rsrr_instance& in = inst[ids[q]];
-        for (long k = off[q]; k < off[q + 1]; ++k) nk[k] = in.nep.n;
+        for (long k = off[q]; k < off[q + 1]; ++k) h.nk[k] = in.nep.n;
+        h.nmax = std::max(h.nmax, in.nep.n);
+        h.Nmax = std::max(h.Nmax, in.N);
+        RhsInstance r{};
+        r.U = (const double2*)in.U; r.S = (double2*)in.S; r.koff = off[q];
+        r.ldu = in.ldu; r.lds = in.lds; r.n = in.nep.n; r.L = in.L; r.N = in.N;
+        h.rhs.push_back(r);
         if (in.nep.kind == RSRR_T_SEPARABLE) {
+            SepInstance e{};
+            e.A = (const double2*)in.nep.A; e.coff = (long)h.coef.size(); e.koff = off[q];
+            e.lda = in.nep.lda; e.J = in.nep.J; e.n = in.nep.n; e.N = in.N;
+            if (e.J > assemble_max_terms()) all_sep = false;
+            h.sep.push_back(e);
             for (int j = 0; j < in.nep.J; ++j)
                 for (int k = 0; k < in.N; ++k) {
                     const zd f = term_eval(in.nep.terms[j], zd(in.z[2 * k], in.z[2 * k + 1]));
-                    coef.push_back(make_double2(f.real(), f.imag()));
+                    h.coef.push_back(make_double2(f.real(), f.imag()));
                 }
         } else {
-            for (int k = 0; k < in.N; ++k) coef.push_back(make_double2(in.z[2 * k], in.z[2 * k + 1]));
+            all_sep = false;
+            for (int k = 0; k < in.N; ++k) h.coef.push_back(make_double2(in.z[2 * k], in.z[2 * k + 1]));
         }
     }
+    if (!all_sep) h.sep.clear();
 }
 
 // The buffers of one bucket of M padded P x P matrices with Lmax right-hand sides,
 // from the context's slots of bucket size P (with `from`, no factor buffers).
-rsrr_status bucket_bufs(BatchedState& S, hipStream_t sm, int P, int Lmax, long M, int maxn, size_t ncoef, bool mixed,
-                        bool from, BucketBufs& b)
+rsrr_status bucket_bufs(BatchedState& S, hipStream_t sm, int P, int Lmax, long M, int maxn, size_t ncoef, int nins,
+                        bool mixed, bool from, BucketBufs& b)
 {
     const int nbmax = mixed ? max_panel<float>() : max_panel<double>();
     b = BucketBufs{};
@@ -421,9 +465,12 @@ rsrr_status bucket_bufs(BatchedState& S, hipStream_t sm, int P, int Lmax, long M
     b.iters = (int*)bget(S, s++, (size_t)M * 4, sm);
     b.ones = (double*)bget(S, s++, (size_t)M * Lmax * 8, sm);
     b.pair = mixed && !from ? bget(S, s++, (size_t)M * b.sPair * 8, sm) : (void*)(s++, nullptr);
+    b.sep = (SepInstance*)bget(S, s++, (size_t)nins * sizeof(SepInstance), sm);
+    b.rhs = (RhsInstance*)bget(S, s++, (size_t)nins * sizeof(RhsInstance), sm);
     if ((!from && (!b.T || !b.perm || (mixed && (!b.inv || !b.pair)))) || !b.T128 || !b.Ub || !b.Xb || !b.R ||
         !b.D64 || !b.ipiv || !b.tperm || !b.info || (mixed && !b.tmp) || !b.nk || !b.coef || !b.frobp || !b.frob ||
-        !b.un || !b.rn || !b.xn || !b.inv_s || !b.scl || !b.active || !b.prev || !b.resid || !b.iters || !b.ones)
+        !b.un || !b.rn || !b.xn || !b.inv_s || !b.scl || !b.active || !b.prev || !b.resid || !b.iters || !b.ones ||
+        !b.sep || !b.rhs)
         return RSRR_ENOMEM;
     // the first solve narrows U with scale 1: ones in scl
     std::vector<double> ones((size_t)M * Lmax, 1.0);
@@ -517,7 +564,7 @@ rsrr_status batched_impl(rsrr_ctx* c, int count, const rsrr_instance* inst, int 
     // host tables of eager launches stay alive in `pending` until then.
     struct Pending {
         std::vector<int> ids; std::vector<long> off; long M; int* info; int* iters; double* resid;
-        std::vector<double2> coef; std::vector<int> nk; std::vector<FactorStore*> keep; std::vector<int> k0;
+        BucketHost h; std::vector<FactorStore*> keep; std::vector<int> k0;
     };
     std::vector<Pending> pending;
     if (!S.streams[0]) {
@@ -558,7 +605,7 @@ rsrr_status batched_impl(rsrr_ctx* c, int count, const rsrr_instance* inst, int 
     // graph mode: the buckets' plans, captured together after the loop
     struct Plan {
         std::vector<int> ids; std::vector<long> off; long M; int P, Lmax, nb, tile, sidx; BucketBufs b;
-        std::vector<double2> coef; std::vector<int> nk;
+        BucketHost h;
     };
     std::vector<Plan> plans;
     std::vector<unsigned long long> gkey;
@@ -574,13 +621,12 @@ rsrr_status batched_impl(rsrr_ctx* c, int count, const rsrr_instance* inst, int 
             maxn = std::max(maxn, inst[ids[q]].nep.n);
         }
         const long M = off.back();
-        std::vector<int> nk;
-        std::vector<double2> coef;
-        bucket_tables(inst, ids, off, nk, coef);
+        BucketHost h;
+        bucket_tables(inst, ids, off, h);
         const int nbmax = mixed ? max_panel<float>() : max_panel<double>();
         BucketBufs b{};
         hipStream_t sm = c->stream;
-        rsrr_status bs = bucket_bufs(S, sm, P, Lmax, M, maxn, coef.size(), mixed, false, b);
+        rsrr_status bs = bucket_bufs(S, sm, P, Lmax, M, maxn, h.coef.size(), (int)ids.size(), mixed, false, b);
         if (bs) return bs;
 
         // panel width and update tile: tuned (each candidate timed with one bucket pass) or default
@@ -608,8 +654,7 @@ rsrr_status batched_impl(rsrr_ctx* c, int count, const rsrr_instance* inst, int 
                     // one full bucket pass (assembly, LU, one solve, one residual) per candidate
                     TileScope ts(ct);
                     RSRR_HIP(hipEventRecord(e0, sm));
-                    rsrr_status st = run_bucket(c, sm, inst, ids, off, P, Lmax, M, prec, cb, b, coef.data(),
-                                                nk.data(), 0);
+                    rsrr_status st = run_bucket(c, sm, inst, ids, off, P, Lmax, M, prec, cb, b, h, 0);
                     if (st) return st;
                     RSRR_HIP(hipEventRecord(e1, sm));
                     RSRR_HIP(hipEventSynchronize(e1));
@@ -647,8 +692,7 @@ rsrr_status batched_impl(rsrr_ctx* c, int count, const rsrr_instance* inst, int 
                 gkey.push_back(((unsigned long long)in.nep.n << 32) | (unsigned)in.N);
                 gkey.push_back(((unsigned long long)in.L << 32) | (unsigned)in.lds);
             }
-            plans.push_back(Plan{ids, off, M, P, Lmax, nb, tile, next_stream(ow.first), b, std::move(coef),
-                                 std::move(nk)});
+            plans.push_back(Plan{ids, off, M, P, Lmax, nb, tile, next_stream(ow.first), b, std::move(h)});
         } else {
             hipStream_t ps = S.streams[next_stream(ow.first)];
             RSRR_HIP(hipEventRecord(c->fork, c->stream));
@@ -657,29 +701,33 @@ rsrr_status batched_impl(rsrr_ctx* c, int count, const rsrr_instance* inst, int 
             std::vector<int> k0q;
             if (keep)
                 for (int id : ids) { kq.push_back(keep[id]); k0q.push_back(keep_k0[id]); }
-            pending.push_back(Pending{ids, off, M, b.info, b.iters, b.resid, std::move(coef), std::move(nk),
-                                      std::move(kq), std::move(k0q)});
+            pending.push_back(Pending{ids, off, M, b.info, b.iters, b.resid, std::move(h), std::move(kq),
+                                      std::move(k0q)});
             Pending& pd = pending.back();
-            rsrr_status st = run_bucket(c, ps, inst, ids, off, P, Lmax, M, prec, nb, b, pd.coef.data(), pd.nk.data(),
-                                        maxit, keep ? pd.keep.data() : nullptr, keep ? pd.k0.data() : nullptr);
+            rsrr_status st = run_bucket(c, ps, inst, ids, off, P, Lmax, M, prec, nb, b, pd.h, maxit,
+                                        keep ? pd.keep.data() : nullptr, keep ? pd.k0.data() : nullptr);
             if (st) return st;
             ++nlaunched;
         }
     }
     if (use_graph && !plans.empty()) {
-        bool hit = S.graph && S.graph->key == gkey && S.graph->coef_host.size() == plans.size();
-        for (size_t i = 0; hit && i < plans.size(); ++i)
-            hit = S.graph->coef_host[i].size() == plans[i].coef.size() &&
-                  std::memcmp(S.graph->coef_host[i].data(), plans[i].coef.data(), plans[i].coef.size() * 16) == 0;
+        auto same = [](const auto& x, const auto& y) {
+            return x.size() == y.size() && std::memcmp(x.data(), y.data(), x.size() * sizeof(x[0])) == 0;
+        };
+        bool hit = S.graph && S.graph->key == gkey && S.graph->host.size() == plans.size();
+        for (size_t i = 0; hit && i < plans.size(); ++i) {
+            const BucketHost &x = S.graph->host[i], &y = plans[i].h;
+            hit = same(x.coef, y.coef) && same(x.nk, y.nk) && same(x.sep, y.sep) && same(x.rhs, y.rhs);
+        }
+        // the tables go to the device outside the graph, before every replay (another call
+        // may have used the same bucket buffers since the capture)
+        for (Plan& pl : plans) RSRR_HIP(upload_tables(c->stream, pl.h, pl.b));
         if (!hit) {
             if (S.graph && S.graph->exec) (void)hipGraphExecDestroy(S.graph->exec);
             S.graph = std::make_unique<GraphEntry>();
             GraphEntry& ge = *S.graph;
             ge.key = gkey;
-            for (Plan& pl : plans) {
-                ge.coef_host.push_back(pl.coef);
-                ge.nk_host.push_back(pl.nk);
-            }
+            for (Plan& pl : plans) ge.host.push_back(pl.h);
             // capture: fork from the capture stream onto the bucket streams, every bucket
             // on its stream, join back
             RSRR_HIP(hipEventRecord(c->fork, c->stream));
@@ -697,8 +745,8 @@ rsrr_status batched_impl(rsrr_ctx* c, int count, const rsrr_instance* inst, int 
                     if (ce != hipSuccess) break;
                 }
                 TileScope ts(pl.tile);
-                st = run_bucket(c, ps, inst, pl.ids, pl.off, pl.P, pl.Lmax, pl.M, prec, pl.nb, pl.b,
-                                ge.coef_host[i].data(), ge.nk_host[i].data(), maxit);
+                st = run_bucket(c, ps, inst, pl.ids, pl.off, pl.P, pl.Lmax, pl.M, prec, pl.nb, pl.b, ge.host[i],
+                                maxit, nullptr, nullptr, nullptr, 0, false);
             }
             for (int i = 0; i < N_BUCKET_STREAMS; ++i) {
                 if (!used[i]) continue;
@@ -786,14 +834,13 @@ rsrr_status solve_from_store(rsrr_ctx* c, const rsrr_instance& in, const FactorS
     const bool mixed = fs.prec == RSRR_PREC_C64_IR;
     std::vector<int> ids{0};
     std::vector<long> off{0, in.N};
-    std::vector<int> nk;
-    std::vector<double2> coef;
-    bucket_tables(&in, ids, off, nk, coef);
+    BucketHost h;
+    bucket_tables(&in, ids, off, h);
     BucketBufs b{};
-    rsrr_status st = bucket_bufs(S, c->stream, P, in.L, in.N, in.nep.n, coef.size(), mixed, true, b);
+    rsrr_status st = bucket_bufs(S, c->stream, P, in.L, in.N, in.nep.n, h.coef.size(), 1, mixed, true, b);
     if (st) return st;
-    st = run_bucket(c, c->stream, &in, ids, off, P, in.L, in.N, fs.prec, fs.nb, b, coef.data(), nk.data(),
-                    c->ir_max_iters_batched, nullptr, nullptr, &fs, k0);
+    st = run_bucket(c, c->stream, &in, ids, off, P, in.L, in.N, fs.prec, fs.nb, b, h, c->ir_max_iters_batched,
+                    nullptr, nullptr, &fs, k0);
     if (st) return st;
     Flags fl;
     std::vector<long> pbase{0, in.N};

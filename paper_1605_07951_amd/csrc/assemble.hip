@@ -157,6 +157,107 @@ __global__ __launch_bounds__(64) void frob_finish_kernel(const double* __restric
     if (lane == 0) out[k] = sqrt(v);
 }
 
+// ----------------------------------------------------------------------------
+// One size bucket of a ragged batch in one launch: instance q = blockIdx.y with
+// its own n, terms A_j and coefficient rows (coef + coff, [J][N] point-fastest),
+// point group blockIdx.z; its points are bucket matrices koff .. koff+N-1 (ld P,
+// strides s64/s128), its partial sums at frob_part + k nparts_max.
+// ----------------------------------------------------------------------------
+template <bool O64, bool O128>
+__global__ __launch_bounds__(AS_NT) void assemble_sep_group_kernel(
+    const SepInstance* __restrict__ ins, const double2* __restrict__ coef, int P,
+    float2* __restrict__ T64, long s64, double2* __restrict__ T128, long s128,
+    double* __restrict__ frob_part, int nparts_max)
+{
+    __shared__ double2 f[AS_MAXJ][AS_PG];
+    __shared__ double red[AS_NT / 64][AS_PG];
+    const SepInstance in = ins[blockIdx.y];
+    const int n = in.n, J = in.J, B = in.N;
+    const int k0 = blockIdx.z * AS_PG;
+    const long nn = (long)n * n;
+    const int nparts = (int)((nn + AS_NT - 1) / AS_NT);
+    if (k0 >= B || (int)blockIdx.x >= nparts) return;   // uniform over the workgroup
+    const int tid = threadIdx.x;
+    const int npts = min(AS_PG, B - k0);
+    for (int e = tid; e < J * AS_PG; e += AS_NT) {
+        const int j = e / AS_PG, p = e % AS_PG;
+        f[j][p] = (p < npts) ? coef[in.coff + (long)j * B + k0 + p] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const long e = (long)blockIdx.x * AS_NT + tid;
+    double acc[AS_PG];
+#pragma unroll
+    for (int p = 0; p < AS_PG; ++p) acc[p] = 0.0;
+    if (e < nn) {
+        const int i = (int)(e % n), c = (int)(e / n);
+        double2 t[AS_PG];
+#pragma unroll
+        for (int p = 0; p < AS_PG; ++p) t[p] = make_double2(0.0, 0.0);
+        for (int j = 0; j < J; ++j) {
+            const double2 a = in.A[(long)j * in.lda * n + i + (long)c * in.lda];
+#pragma unroll
+            for (int p = 0; p < AS_PG; ++p) t[p] = cfma(t[p], f[j][p], a);
+        }
+#pragma unroll
+        for (int p = 0; p < AS_PG; ++p) {
+            if (p < npts) {
+                const long k = in.koff + k0 + p;
+                if (O64) T64[k * s64 + i + (long)c * P] = to_c64(t[p]);
+                if (O128) T128[k * s128 + i + (long)c * P] = t[p];
+                acc[p] = t[p].x * t[p].x + t[p].y * t[p].y;
+            }
+        }
+    }
+    const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int p = 0; p < AS_PG; ++p) {
+        double v = acc[p];
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) red[wave][p] = v;
+    }
+    __syncthreads();
+    if (tid < AS_PG && tid < npts)  {
+        double v = 0.0;
+        for (int w = 0; w < AS_NT / 64; ++w) v += red[w][tid];
+        frob_part[(in.koff + k0 + tid) * (long)nparts_max + blockIdx.x] = v;
+    }
+}
+
+// ||T_k||_F of every matrix of the bucket: matrix k of order nk[k] has
+// ceil(nk^2 / AS_NT) partial sums at part + k nparts_max.
+__global__ __launch_bounds__(64) void frob_finish_group_kernel(const double* __restrict__ part, int nparts_max,
+                                                                const int* __restrict__ nk, double* __restrict__ out)
+{
+    const int k = blockIdx.x, lane = threadIdx.x;
+    const long nn = (long)nk[k] * nk[k];
+    const int nparts = (int)((nn + AS_NT - 1) / AS_NT);
+    double v = 0.0;
+    for (int t = lane; t < nparts; t += 64) v += part[(long)k * nparts_max + t];
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) out[k] = sqrt(v);
+}
+
+hipError_t assemble_separable_group(hipStream_t st, const SepInstance* ins, int nins, int nmax, int Nmax,
+                                    const double2* coef, int P, int M, const int* nk, float2* T64, long s64,
+                                    double2* T128, long s128, double* frob_part, double* frob)
+{
+    const int nparts_max = (int)(((long)nmax * nmax + AS_NT - 1) / AS_NT);
+    const dim3 g((unsigned)nparts_max, (unsigned)nins, (unsigned)((Nmax + AS_PG - 1) / AS_PG));
+    if (T64 && T128)
+        hipLaunchKernelGGL((assemble_sep_group_kernel<true, true>), g, dim3(AS_NT), 0, st, ins, coef, P, T64, s64, T128,
+                           s128, frob_part, nparts_max);
+    else if (T64)
+        hipLaunchKernelGGL((assemble_sep_group_kernel<true, false>), g, dim3(AS_NT), 0, st, ins, coef, P, T64, s64,
+                           T128, s128, frob_part, nparts_max);
+    else
+        hipLaunchKernelGGL((assemble_sep_group_kernel<false, true>), g, dim3(AS_NT), 0, st, ins, coef, P, T64, s64,
+                           T128, s128, frob_part, nparts_max);
+    hipLaunchKernelGGL(frob_finish_group_kernel, dim3(M), dim3(64), 0, st, frob_part, nparts_max, nk, frob);
+    return hipGetLastError();
+}
+
+int assemble_max_terms() { return AS_MAXJ; }
+
 hipError_t assemble_separable(hipStream_t st, int n, int J, const double2* A, int lda, const double2* coef, int B,
                               float2* T64, int ld64, long s64, double2* T128, int ld128, long s128,
                               double* frob_part, double* frob)

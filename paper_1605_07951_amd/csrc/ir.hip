@@ -346,6 +346,46 @@ __global__ __launch_bounds__(RW) void resid_skinny_kernel(int n, int L, const do
 }
 
 static dim3 ew_grid(long elems, int B) { return dim3((unsigned)((elems + EW_NT - 1) / EW_NT), B); }
+// Ub_k (rows < n, columns < L) = U_q for point k = koff + blockIdx.y of instance blockIdx.z.
+__global__ __launch_bounds__(EW_NT) void bcast_group_kernel(const RhsInstance* __restrict__ ins,
+                                                             double2* __restrict__ Ub, int ldb, long sB)
+{
+    const RhsInstance in = ins[blockIdx.z];
+    const int k = blockIdx.y;
+    const long e = (long)blockIdx.x * EW_NT + threadIdx.x;
+    if (k >= in.N || e >= (long)in.n * in.L) return;
+    const int i = (int)(e % in.n), c = (int)(e / in.n);
+    Ub[(in.koff + k) * sB + i + (long)c * ldb] = in.U[i + (long)c * in.ldu];
+}
+
+// S_q columns k L .. k L + L - 1 (rows < n) = X_(koff + k) for point k = blockIdx.y of instance blockIdx.z.
+__global__ __launch_bounds__(EW_NT) void copy_out_group_kernel(const RhsInstance* __restrict__ ins,
+                                                                const double2* __restrict__ Xb, int ldb, long sB)
+{
+    const RhsInstance in = ins[blockIdx.z];
+    const int k = blockIdx.y;
+    const long e = (long)blockIdx.x * EW_NT + threadIdx.x;
+    if (k >= in.N || e >= (long)in.n * in.L) return;
+    const int i = (int)(e % in.n), c = (int)(e / in.n);
+    in.S[i + ((long)k * in.L + c) * in.lds] = Xb[(in.koff + k) * sB + i + (long)c * ldb];
+}
+
+hipError_t bcast_group(hipStream_t st, const RhsInstance* ins, int nins, int nmax, int Lmax, int Nmax,
+                       double2* Ub, int ldb, long sB)
+{
+    const dim3 g((unsigned)(((long)nmax * Lmax + EW_NT - 1) / EW_NT), (unsigned)Nmax, (unsigned)nins);
+    hipLaunchKernelGGL(bcast_group_kernel, g, dim3(EW_NT), 0, st, ins, Ub, ldb, sB);
+    return hipGetLastError();
+}
+
+hipError_t copy_out_group(hipStream_t st, const RhsInstance* ins, int nins, int nmax, int Lmax, int Nmax,
+                          const double2* Xb, int ldb, long sB)
+{
+    const dim3 g((unsigned)(((long)nmax * Lmax + EW_NT - 1) / EW_NT), (unsigned)Nmax, (unsigned)nins);
+    hipLaunchKernelGGL(copy_out_group_kernel, g, dim3(EW_NT), 0, st, ins, Xb, ldb, sB);
+    return hipGetLastError();
+}
+
 
 hipError_t pad_identity(hipStream_t st, float2* T64, double2* T128, int ld, long sT, int P, const int* nk, int M)
 {

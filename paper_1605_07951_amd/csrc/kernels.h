@@ -125,6 +125,29 @@ hipError_t helmholtz_taylor(hipStream_t st, int n, const double* pts, double w, 
 hipError_t helmholtz_taylor_range(hipStream_t st, int n, const double* pts, double w, double gre, double gim, int p0,
                                   int G, double2* Tp, int ld, long sT);
 
+// One separable instance of a ragged batch's size bucket (device table entry):
+// terms A (J matrices n x n, ld lda, consecutive), coefficient rows at
+// coef + coff ([J][N], point-fastest), points = bucket matrices koff .. koff+N-1.
+struct SepInstance {
+    const double2* A; long coff; long koff; int lda, J, n, N;
+};
+// The whole bucket (all instances separable, J <= assemble_max_terms()) in one
+// launch plus one launch for the norms; nk: per-matrix order (M matrices),
+// frob_part: M * ceil(nmax^2/256) doubles.
+hipError_t assemble_separable_group(hipStream_t st, const SepInstance* ins, int nins, int nmax, int Nmax,
+                                    const double2* coef, int P, int M, const int* nk, float2* T64, long s64,
+                                    double2* T128, long s128, double* frob_part, double* frob);
+int assemble_max_terms();
+// Right-hand sides and results of a bucket's instances in one launch each:
+// Ub_k = [U_q; 0] for the points k of instance q, and S_q columns from X_k.
+struct RhsInstance {
+    const double2* U; double2* S; long koff; int ldu, lds, n, L, N;
+};
+hipError_t bcast_group(hipStream_t st, const RhsInstance* ins, int nins, int nmax, int Lmax, int Nmax,
+                       double2* Ub, int ldb, long sB);
+hipError_t copy_out_group(hipStream_t st, const RhsInstance* ins, int nins, int nmax, int Lmax, int Nmax,
+                          const double2* Xb, int ldb, long sB);
+
 // ---- element-wise helpers (ir.hip) ----
 hipError_t bcast_to_c64(hipStream_t st, int n, int L, const double2* U, int ldu, float2* D, int ldd, long sD, int B);
 hipError_t bcast_c128(hipStream_t st, int n, int L, const double2* U, int ldu, double2* R, int ldr, long sR, int B);
