@@ -208,11 +208,11 @@ void save_tune_file(const BatchedState& S)
 }
 
 struct BucketBufs {
-    void* T; double2* T128; double2* Ub; double2* Xb; double2* R; float2* D64; int* ipiv; int2* perm; int2* tperm;
+    void* T; double2* T128; double2* Ub; double2* Xb; double2* R; float2* D64; int* ipiv; int2* perm;
     int* info; void* inv; void* tmp; int* nk; double2* coef; double* frobp; double* frob; double* un; double* rn;
     double* xn; double* inv_s; double* scl; int* active; double* prev; double* resid; int* iters; double* ones;
     void* pair; SepInstance* sep; RhsInstance* rhs;
-    long sT, sU, sP, sPerm, sTP, sInv, sTmp, sPair;
+    long sT, sU, sP, sPerm, sInv, sTmp, sPair;
 };
 
 // Strides of one point's factor data in the bucket buffers and in a FactorStore.
@@ -298,7 +298,7 @@ rsrr_status run_bucket(rsrr_ctx* c, hipStream_t sm, const rsrr_instance* inst, c
     // factorisation
     RSRR_HIP(zero_int(sm, b.info, (int)M));
     LUWork w;
-    w.ipiv = b.ipiv; w.sP = b.sP; w.perm = b.perm; w.sPerm = b.sPerm; w.tperm = b.tperm; w.sTP = b.sTP;
+    w.ipiv = b.ipiv; w.sP = b.sP; w.perm = b.perm; w.sPerm = b.sPerm;
     w.info = b.info; w.inv = b.inv; w.sInv = b.sInv; w.tmp = b.tmp; w.sTmp = b.sTmp;
     w.pair = b.pair; w.sPair = b.sPair; w.ldpair = P;
     if (!from) {
@@ -427,7 +427,6 @@ rsrr_status bucket_bufs(BatchedState& S, hipStream_t sm, int P, int Lmax, long M
     b.sU = (long)P * Lmax;
     b.sP = P;
     b.sPerm = bucket_sPerm(P);
-    b.sTP = 8L * 2 * MAX_NB;
     // ceil(P/nb) panels of 2 nb^2 for any nb <= nbmax: at most 2 nbmax (P + nbmax)
     b.sInv = bucket_sInv(P, mixed);
     b.sTmp = mixed ? (long)nbmax * std::max(P, Lmax) : 0;
@@ -446,7 +445,6 @@ rsrr_status bucket_bufs(BatchedState& S, hipStream_t sm, int P, int Lmax, long M
     b.D64 = (float2*)bget(S, s++, (size_t)M * b.sU * 8, sm);
     b.ipiv = (int*)bget(S, s++, (size_t)M * b.sP * 4, sm);
     b.perm = from ? (int2*)(s++, nullptr) : (int2*)bget(S, s++, (size_t)M * b.sPerm * 8, sm);
-    b.tperm = (int2*)bget(S, s++, (size_t)M * b.sTP * 8, sm);
     b.info = (int*)bget(S, s++, (size_t)M * 4, sm);
     b.inv = mixed && !from ? bget(S, s++, (size_t)M * b.sInv * 8, sm) : (void*)(s++, nullptr);
     b.tmp = mixed ? bget(S, s++, (size_t)M * b.sTmp * 8, sm) : (void*)(s++, nullptr);
@@ -468,7 +466,7 @@ rsrr_status bucket_bufs(BatchedState& S, hipStream_t sm, int P, int Lmax, long M
     b.sep = (SepInstance*)bget(S, s++, (size_t)nins * sizeof(SepInstance), sm);
     b.rhs = (RhsInstance*)bget(S, s++, (size_t)nins * sizeof(RhsInstance), sm);
     if ((!from && (!b.T || !b.perm || (mixed && (!b.inv || !b.pair)))) || !b.T128 || !b.Ub || !b.Xb || !b.R ||
-        !b.D64 || !b.ipiv || !b.tperm || !b.info || (mixed && !b.tmp) || !b.nk || !b.coef || !b.frobp || !b.frob ||
+        !b.D64 || !b.ipiv || !b.info || (mixed && !b.tmp) || !b.nk || !b.coef || !b.frobp || !b.frob ||
         !b.un || !b.rn || !b.xn || !b.inv_s || !b.scl || !b.active || !b.prev || !b.resid || !b.iters || !b.ones ||
         !b.sep || !b.rhs)
         return RSRR_ENOMEM;

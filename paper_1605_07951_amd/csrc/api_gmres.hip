@@ -180,16 +180,15 @@ extern "C" rsrr_status rsrr_sample_gmres(rsrr_ctx* c, const rsrr_nep* nep, int N
     const int nb = std::min(std::max(c->nb_c64, MIN_NB), max_panel<float>());
     const int np = perm_panels(n);
     const long sInv = (long)((n + nb - 1) / nb) * 2 * nb * nb;
-    const long sPerm = (long)np * 2 * MAX_NB, sTP = 8L * 2 * MAX_NB;
+    const long sPerm = (long)np * 2 * MAX_NB;
     float2* Tf = (float2*)ws_get(c, WS_GMF, (size_t)nf * sT * 8);
-    size_t fw = a256((size_t)nf * n * 4) + a256((size_t)nf * sPerm * 8) + a256((size_t)nf * sTP * 8) +
+    size_t fw = a256((size_t)nf * n * 4) + a256((size_t)nf * sPerm * 8) +
                 a256((size_t)nf * 4) + a256((size_t)nf * sInv * 8) + a256((size_t)nf * nb * n * 8);
     Carve fc{(char*)ws_get(c, WS_GMW, fw)};
     if (!Tf || !fc.base) return RSRR_ENOMEM;
     LUWork w;
     w.ipiv = fc.take<int>((size_t)nf * n); w.sP = n;
     w.perm = fc.take<int2>((size_t)nf * sPerm); w.sPerm = sPerm;
-    w.tperm = fc.take<int2>((size_t)nf * sTP); w.sTP = sTP;
     w.info = fc.take<int>(nf);
     w.inv = fc.take<float2>((size_t)nf * sInv); w.sInv = sInv;
     w.tmp = fc.take<float2>((size_t)nf * nb * n); w.sTmp = (long)nb * n;
@@ -482,7 +481,7 @@ extern "C" rsrr_status rsrr_sample_gmres(rsrr_ctx* c, const rsrr_nep* nep, int N
                     const int rl = run0[1] - run0[0];
                     LUWork wr = w;
                     const int f0 = runf[0];
-                    wr.ipiv = w.ipiv + (long)f0 * n; wr.perm = w.perm + f0 * sPerm; wr.tperm = w.tperm + f0 * sTP;
+                    wr.ipiv = w.ipiv + (long)f0 * n; wr.perm = w.perm + f0 * sPerm;
                     wr.info = w.info + f0; wr.inv = (float2*)w.inv + f0 * sInv; wr.tmp = k.tmp; wr.sTmp = sTmp;
                     RSRR_HIP(getrs_batched<float>(c->stream, Tf + f0 * sT, sT, ld, n, nb, wr, k.D, (long)ld * rl * L,
                                                   ld, rl * L, nrun));
@@ -490,7 +489,7 @@ extern "C" rsrr_status rsrr_sample_gmres(rsrr_ctx* c, const rsrr_nep* nep, int N
                     for (int r = 0; r < nrun; ++r) {
                         const int rl = run0[r + 1] - run0[r], f = runf[r];
                         LUWork wr = w;
-                        wr.ipiv = w.ipiv + (long)f * n; wr.perm = w.perm + f * sPerm; wr.tperm = w.tperm + f * sTP;
+                        wr.ipiv = w.ipiv + (long)f * n; wr.perm = w.perm + f * sPerm;
                         wr.info = w.info + f; wr.inv = (float2*)w.inv + f * sInv; wr.tmp = k.tmp; wr.sTmp = sTmp;
                         RSRR_HIP(getrs_batched<float>(c->stream, Tf + f * sT, sT, ld, n, nb, wr,
                                                       k.D + (size_t)run0[r] * L * ld, (long)ld * rl * L, ld, rl * L,

@@ -301,16 +301,16 @@ struct PhaseTimer {
 };
 
 struct SampleBufs {
-    void* Tlu; double2* Tres; int* ipiv; int2* perm; int2* tperm; int* info; double2* coef; double* frobp;
+    void* Tlu; double2* Tres; int* ipiv; int2* perm; int* info; double2* coef; double* frobp;
     double* frob; float2* D64; double2* R; double* norms; int* active; double2* zdev; void* inv; void* tmp;
     void* pair; void* pair2;
     hipStream_t la, upd; hipEvent_t la_a, la_b, la_c;
     int la_cols;
-    int ld, np, nb; long sT, sP, sPerm, sTP, nparts, sInv, sTmp, sPair;
+    int ld, np, nb; long sT, sP, sPerm, nparts, sInv, sTmp, sPair;
     LUWork lu(const int* act, UpdateRecorder* rec) const
     {
         LUWork w;
-        w.ipiv = ipiv; w.sP = sP; w.perm = perm; w.sPerm = sPerm; w.tperm = tperm; w.sTP = sTP; w.info = info;
+        w.ipiv = ipiv; w.sP = sP; w.perm = perm; w.sPerm = sPerm; w.info = info;
         w.inv = inv; w.sInv = sInv; w.tmp = tmp; w.sTmp = sTmp; w.active = act; w.rec = rec;
         w.pair = pair; w.sPair = sPair; w.ldpair = ld;
         w.pair2 = pair2; w.side = la; w.ev_a = la_a; w.ev_b = la_b; w.upd = upd; w.ev_c = la_c;
@@ -326,7 +326,7 @@ static size_t per_point_bytes(int n, int L, int prec)
     const size_t np = perm_panels(n);
     size_t b = ld * n * 16;                         // FP64 copy for residuals
     b += ld * n * (prec == RSRR_PREC_C128 ? 16 : 8);  // LU input
-    b += (size_t)n * 4 + np * 2 * MAX_NB * 8 + 8 * 2 * MAX_NB * 8 + 16;
+    b += (size_t)n * 4 + np * 2 * MAX_NB * 8 + 16;
     b += ((size_t)n * n + 255) / 256 * 8 + 8;
     b += (size_t)ld * L * (8 + 16) + (size_t)L * 16;
     if (prec != RSRR_PREC_C128) {
@@ -362,14 +362,12 @@ static rsrr_status alloc_bufs(rsrr_ctx* c, int n, int L, int J, int prec, int B,
     s.sT = (long)s.ld * n;
     s.sP = n;
     s.sPerm = (long)s.np * 2 * MAX_NB;
-    s.sTP = 8L * 2 * MAX_NB;
     s.nparts = ((long)n * n + 255) / 256;
     const size_t esz = prec == RSRR_PREC_C128 ? 16 : 8;
     s.Tlu = ws_get(c, WS_TLU, (size_t)B * s.sT * esz);
     s.Tres = (double2*)ws_get(c, WS_TRES, (size_t)B * s.sT * 16);
     s.ipiv = (int*)ws_get(c, WS_IPIV, (size_t)B * s.sP * 4);
     s.perm = (int2*)ws_get(c, WS_PERM, (size_t)B * s.sPerm * 8);
-    s.tperm = (int2*)ws_get(c, WS_TPERM, (size_t)B * s.sTP * 8);
     s.info = (int*)ws_get(c, WS_INFO, (size_t)B * 4);
     s.coef = (double2*)ws_get(c, WS_COEF, (size_t)std::max(J, 1) * B * 16);
     s.frobp = (double*)ws_get(c, WS_FROBP, (size_t)B * s.nparts * 8);
@@ -379,7 +377,7 @@ static rsrr_status alloc_bufs(rsrr_ctx* c, int n, int L, int J, int prec, int B,
     s.norms = (double*)ws_get(c, WS_NORM, (size_t)3 * B * L * 8);
     s.active = (int*)ws_get(c, WS_ACTIVE, (size_t)B * 4);
     s.zdev = (double2*)ws_get(c, WS_Z, (size_t)B * 16);
-    if (!s.Tlu || !s.Tres || !s.ipiv || !s.perm || !s.tperm || !s.info || !s.coef || !s.frobp || !s.frob ||
+    if (!s.Tlu || !s.Tres || !s.ipiv || !s.perm || !s.info || !s.coef || !s.frobp || !s.frob ||
         !s.D64 || !s.R || !s.norms || !s.active || !s.zdev)
         return RSRR_ENOMEM;
     return RSRR_OK;
@@ -444,7 +442,6 @@ static LUWork lu_offset(const LUWork& w, long b0, int esz = 8)
     LUWork o = w;
     o.ipiv = w.ipiv + b0 * w.sP;
     o.perm = w.perm + b0 * w.sPerm;
-    o.tperm = w.tperm + b0 * w.sTP;
     o.info = w.info + b0;
     if (w.inv) o.inv = (char*)w.inv + b0 * w.sInv * esz;
     if (w.tmp) o.tmp = (char*)w.tmp + b0 * w.sTmp * esz;

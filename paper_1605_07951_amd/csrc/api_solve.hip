@@ -70,7 +70,6 @@ extern "C" rsrr_status rsrr_solve(rsrr_ctx* c, const rsrr_nep* nep, int k, const
     double2* X = (double2*)ws_get(c, WS_TRES, (size_t)Mc * kk * 16);
     int* ipiv = (int*)ws_get(c, WS_IPIV, (size_t)Mc * k * 4);
     int2* perm = (int2*)ws_get(c, WS_PERM, (size_t)Mc * np * 2 * MAX_NB * 8);
-    int2* tperm = (int2*)ws_get(c, WS_TPERM, (size_t)Mc * 8 * 2 * MAX_NB * 8);
     int* info = (int*)ws_get(c, WS_INFO, (size_t)Mc * 4);
     double2* coef = (double2*)ws_get(c, WS_COEF, (size_t)J_eff * Mc * 16);
     double2* cw = (double2*)ws_get(c, WS_B1, (size_t)Mc * twoK * 16);
@@ -80,7 +79,7 @@ extern "C" rsrr_status rsrr_solve(rsrr_ctx* c, const rsrr_nep* nep, int k, const
     double* frobp = (double*)ws_get(c, WS_FROBP, (size_t)Mc * nparts * 8);
     double2* inv = (double2*)ws_get(c, WS_B5, (size_t)Mc * sInv * 16);
     double2* tmp = (double2*)ws_get(c, WS_B6, (size_t)Mc * sTmp * 16);
-    if (!T || !X || !ipiv || !perm || !tperm || !info || !coef || !cw || !I || !frob || !frobp || !inv || !tmp)
+    if (!T || !X || !ipiv || !perm || !info || !coef || !cw || !I || !frob || !frobp || !inv || !tmp)
         return RSRR_ENOMEM;
     RSRR_HIP(eye(c->stream, I, k, 0, k));
     int singular = 0;
@@ -108,8 +107,8 @@ extern "C" rsrr_status rsrr_solve(rsrr_ctx* c, const rsrr_nep* nep, int k, const
         RSRR_HIP(assemble_separable(c->stream, k, J_eff, AQ, k, coef, B, nullptr, 0, 0, T, k, kk, frobp, frob));
         RSRR_HIP(hipMemsetAsync(info, 0, (size_t)B * 4, c->stream));
         LUWork w;
-        w.ipiv = ipiv; w.sP = k; w.perm = perm; w.sPerm = (long)np * 2 * MAX_NB; w.tperm = tperm;
-        w.sTP = 8L * 2 * MAX_NB; w.info = info;
+        w.ipiv = ipiv; w.sP = k; w.perm = perm; w.sPerm = (long)np * 2 * MAX_NB;
+        w.info = info;
         w.inv = inv; w.sInv = sInv; w.tmp = tmp; w.sTmp = sTmp;
         RSRR_HIP(getrf_batched<double>(c->stream, T, kk, k, k, nb, w, B));
         RSRR_HIP(bcast_c128(c->stream, k, k, I, k, X, k, kk, B));

@@ -13,7 +13,7 @@ typedef std::complex<double> zd;
 
 // Workspace slots (each a grow-only device allocation owned by the context).
 enum WsSlot {
-    WS_TLU = 0, WS_TRES, WS_IPIV, WS_PERM, WS_TPERM, WS_INFO, WS_COEF, WS_FROBP, WS_FROB,
+    WS_TLU = 0, WS_TRES, WS_IPIV, WS_PERM, WS_INFO, WS_COEF, WS_FROBP, WS_FROB,
     WS_D64, WS_R, WS_NORM, WS_ACTIVE, WS_Z,
     WS_B0, WS_B1, WS_B2, WS_B3, WS_B4, WS_B5, WS_B6, WS_B7, WS_N1, WS_JAC, WS_TSQ, WS_TSAQ, WS_TSV,
     WS_GMF, WS_GMW, WS_GMK, WS_GMS, WS_GMT, WS_GMI,

@@ -55,7 +55,6 @@ struct UpdateRecorder {
 // Workspace of the batched LU (per-matrix strides in elements).
 //  ipiv  : n ints                          (stride sP)
 //  perm  : perm_panels(n)*2*MAX_NB int2     (stride sPerm), composed interchanges per panel
-//  tperm : 8*2*MAX_NB int2                 (stride sTP), recursion scratch
 //  info  : 1 int, zero on entry            (getrf semantics; < 0: NaN/Inf pivot)
 //  inv   : FP32 paths, and FP64 when given together with tmp (the diagonal blocks are
 //          then solved by products with their inverses, as in FP32):
@@ -67,7 +66,6 @@ struct UpdateRecorder {
 struct LUWork {
     int* ipiv = nullptr; long sP = 0;
     int2* perm = nullptr; long sPerm = 0;
-    int2* tperm = nullptr; long sTP = 0;
     int* info = nullptr;
     void* inv = nullptr; long sInv = 0;
     void* tmp = nullptr; long sTmp = 0;

@@ -217,6 +217,55 @@ __global__ __launch_bounds__(64) void perm_build_kernel(const int* __restrict__ 
     for (int s = lane; s < 2 * jb; s += 64) pm[s] = make_int2(rowid[s], content[s]);
 }
 
+// Wave-level ordering of LDS accesses (one wavefront, no workgroup barrier).
+RSRR_DEV void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The composition of perm_build_kernel done by the first wavefront of a
+// workgroup into pm (2 jb slots, LDS): after the interchanges pv[k1 .. k1+jb),
+// row pm[s].x holds the old row pm[s].y.  The caller synchronises the workgroup
+// afterwards.
+RSRR_DEV void compose_perm_wave(const int* __restrict__ pv, int k1, int jb, int2* pm)
+{
+    const int lane = threadIdx.x & 63;
+    for (int s = lane; s < 2 * jb; s += 64) pm[s] = s < jb ? make_int2(k1 + s, k1 + s) : make_int2(-1, -1);
+    wave_sync();
+    int nout = 0;
+    for (int i = 0; i < jb; ++i) {
+        const int p = pv[k1 + i];
+        int slot;
+        if (p < k1 + jb) {
+            slot = p - k1;
+        } else {
+            int found = INT_MAX;
+            for (int base = 0; base < nout; base += 64) {
+                const int s = base + lane;
+                const bool hit = (s < nout) && pm[jb + s].x == p;
+                const unsigned long long m = __ballot(hit);
+                if (m) { found = base + __ffsll((long long)m) - 1; break; }
+            }
+            if (found == INT_MAX) {
+                slot = jb + nout;
+                if (lane == 0) pm[slot] = make_int2(p, p);
+                ++nout;
+            } else {
+                slot = jb + found;
+            }
+        }
+        wave_sync();
+        if (lane == 0 && slot != i) {
+            const int t = pm[i].y;
+            pm[i].y = pm[slot].y;
+            pm[slot].y = t;
+        }
+        wave_sync();
+    }
+}
+
 // ----------------------------------------------------------------------------
 // Row permutation + triangular solve on a block of columns.
 // X: rows indexed like the factored matrix (row r at X[r - xr0]); columns [0, ncols).
@@ -231,7 +280,7 @@ constexpr int TS_NT = 256;
 template <typename C, int MJB, int TC>
 __global__ __launch_bounds__(TS_NT) void perm_trsm_kernel(
     const C* __restrict__ LU, long sLU, int ldl,
-    const int2* __restrict__ perm, long sPerm,
+    const int2* __restrict__ perm, long sPerm, const int* __restrict__ ipiv, long sP,
     C* __restrict__ X, long sX, int ldx, int xr0,
     int c0, int jb, int ncols, int mode, const int* __restrict__ active)
 {
@@ -252,8 +301,13 @@ __global__ __launch_bounds__(TS_NT) void perm_trsm_kernel(
 
     const bool permute = mode == 0 || mode == 1;
     if (permute) {
-        const int2* pb = perm + (long)b * sPerm;
-        for (int s = tid; s < 2 * jb; s += TS_NT) pm[s] = pb[s];
+        if (ipiv) {
+            // composed here from the interchanges ipiv[c0 .. c0+jb) (uniform branch)
+            if (tid < 64) compose_perm_wave(ipiv + (long)b * sP, c0, jb, pm);
+        } else {
+            const int2* pb = perm + (long)b * sPerm;
+            for (int s = tid; s < 2 * jb; s += TS_NT) pm[s] = pb[s];
+        }
     }
     if (mode != 0) {
         // triangle into LDS (column-major read, coalesced along rows)
@@ -400,24 +454,26 @@ static void panel_base(hipStream_t st, C* A, long sA, int lda, int n, int c0, in
 #undef PB
 }
 
+// perm: composed interchanges of rows c0 .. c0+jb (perm_build), or nullptr with ipiv
+// given: composed inside the kernel from ipiv[c0 .. c0+jb).
 template <typename C>
 static void perm_trsm(hipStream_t st, const C* LU, long sLU, int ldl, const int2* perm, long sPerm,
                       C* X, long sX, int ldx, int c0, int jb, int ncols, int mode,
-                      const int* active, int batch, int xr0 = 0)
+                      const int* active, int batch, int xr0 = 0, const int* ipiv = nullptr, long sP = 0)
 {
     typedef real_t<C> R;
     if (ncols <= 0 || jb <= 0) return;
     if (jb <= 64) {
         constexpr int TC = 32;
         dim3 g((ncols + TC - 1) / TC, batch);
-        hipLaunchKernelGGL((perm_trsm_kernel<C, 64, TC>), g, dim3(TS_NT), 0, st, LU, sLU, ldl, perm, sPerm, X, sX, ldx,
-                           xr0, c0, jb, ncols, mode, active);
+        hipLaunchKernelGGL((perm_trsm_kernel<C, 64, TC>), g, dim3(TS_NT), 0, st, LU, sLU, ldl, perm, sPerm, ipiv, sP,
+                           X, sX, ldx, xr0, c0, jb, ncols, mode, active);
     } else {
         constexpr int MJB = max_panel<R>();
         constexpr int TC = 16;
         dim3 g((ncols + TC - 1) / TC, batch);
-        hipLaunchKernelGGL((perm_trsm_kernel<C, MJB, TC>), g, dim3(TS_NT), 0, st, LU, sLU, ldl, perm, sPerm, X, sX,
-                           ldx, xr0, c0, jb, ncols, mode, active);
+        hipLaunchKernelGGL((perm_trsm_kernel<C, MJB, TC>), g, dim3(TS_NT), 0, st, LU, sLU, ldl, perm, sPerm, ipiv, sP,
+                           X, sX, ldx, xr0, c0, jb, ncols, mode, active);
     }
 }
 
@@ -463,7 +519,7 @@ hipError_t gemm_sub<float>(hipStream_t st, int M, int N, int K, const float* A, 
 // Recursive panel factorisation of columns [c0, c0+w) (rows c0..n-1).
 template <typename C>
 static void factor_panel(hipStream_t st, C* A, long sA, int lda, int n, int c0, int w,
-                         int* ipiv, long sP, int* info, int2* tperm, long sTP, int depth, const int* active,
+                         int* ipiv, long sP, int* info, const int* active,
                          int batch)
 {
     typedef real_t<C> R;
@@ -476,18 +532,17 @@ static void factor_panel(hipStream_t st, C* A, long sA, int lda, int n, int c0, 
     int w1 = (w / 2) / jbase * jbase;
     if (w1 < jbase) w1 = jbase;
     const int w2 = w - w1;
-    int2* pm = tperm + (long)depth * 2 * MAX_NB;
-    factor_panel<C>(st, A, sA, lda, n, c0, w1, ipiv, sP, info, tperm, sTP, depth + 1, active, batch);
-    // right half: interchanges of the left half, U12 = L11^-1 A12, A22 -= L21 U12
-    hipLaunchKernelGGL(perm_build_kernel, dim3(batch), dim3(64), 0, st, ipiv, sP, c0, w1, pm, sTP, active);
+    factor_panel<C>(st, A, sA, lda, n, c0, w1, ipiv, sP, info, active, batch);
+    // right half: interchanges of the left half (composed inside the solve kernel),
+    // U12 = L11^-1 A12, A22 -= L21 U12
     C* Ar = A + (long)(c0 + w1) * lda;
-    perm_trsm<C>(st, A, sA, lda, pm, sTP, Ar, sA, lda, c0, w1, w2, 1, active, batch);
+    perm_trsm<C>(st, A, sA, lda, nullptr, 0, Ar, sA, lda, c0, w1, w2, 1, active, batch, 0, ipiv, sP);
     (void)gemm_sub<C>(st, m - w1, w2, w1, A + (c0 + w1) + (long)c0 * lda, lda, sA, A + c0 + (long)(c0 + w1) * lda, lda, sA,
                 A + (c0 + w1) + (long)(c0 + w1) * lda, lda, sA, batch);
-    factor_panel<C>(st, A, sA, lda, n, c0 + w1, w2, ipiv, sP, info, tperm, sTP, depth + 1, active, batch);
+    factor_panel<C>(st, A, sA, lda, n, c0 + w1, w2, ipiv, sP, info, active, batch);
     // left half receives the interchanges of the right half
-    hipLaunchKernelGGL(perm_build_kernel, dim3(batch), dim3(64), 0, st, ipiv, sP, c0 + w1, w2, pm, sTP, active);
-    perm_trsm<C>(st, A, sA, lda, pm, sTP, A + (long)c0 * lda, sA, lda, c0 + w1, w2, w1, 0, active, batch);
+    perm_trsm<C>(st, A, sA, lda, nullptr, 0, A + (long)c0 * lda, sA, lda, c0 + w1, w2, w1, 0, active, batch, 0, ipiv,
+                 sP);
 }
 
 // Diagonal-block inverses of panel p (complex-FP32 path): L11^-1 at
@@ -692,7 +747,7 @@ static hipError_t getrf_impl(hipStream_t st, C* A, long sA, int lda, int n, int 
     };
     // panel p on stream s: factor, composed interchanges, diagonal-block inverses (FP32 paths)
     auto panel = [&](hipStream_t s, int c0, int jb, int p) -> int2* {
-        factor_panel<C>(s, A, sA, lda, n, c0, jb, w.ipiv, w.sP, w.info, w.tperm, w.sTP, 0, w.active, batch);
+        factor_panel<C>(s, A, sA, lda, n, c0, jb, w.ipiv, w.sP, w.info, w.active, batch);
         int2* pm = w.perm + (long)p * 2 * MAX_NB;
         hipLaunchKernelGGL(perm_build_kernel, dim3(batch), dim3(64), 0, s, w.ipiv, w.sP, c0, jb, pm, w.sPerm,
                            w.active);

@@ -166,7 +166,7 @@ size_t point_bytes(int n, int L, bool mixed)
     const size_t npan = (size_t)perm_panels((int)P);
     size_t b = P * P * (mixed ? 8 + 16 : 16 + 16);           // T and its FP64 copy
     b += P * (size_t)L * (3 * 16 + 8) + P * 4;               // U, X, R, narrow RHS, pivots
-    b += npan * 2 * MAX_NB * 8 + 8 * 2 * MAX_NB * 8;         // permutations
+    b += npan * 2 * MAX_NB * 8;                               // permutations
     if (mixed) b += 2 * MAX_NB * (P + MAX_NB) * 8 + MAX_NB * std::max(P, (size_t)L) * 8;  // inverses, scratch
     b += (P * P + 255) / 256 * 8 + (size_t)L * 6 * 8 + 64;   // norms and refinement state
     return b;
