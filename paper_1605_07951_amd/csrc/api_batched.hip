@@ -219,6 +219,15 @@ struct BucketBufs {
 long bucket_sPerm(int P) { return (long)perm_panels(P) * 2 * MAX_NB; }
 long bucket_sInv(int P, bool mixed) { return mixed ? 2L * max_panel<float>() * (P + max_panel<float>()) : 0; }
 
+// The complex FP32 solves of a bucket: the whole sweep per matrix in one launch when its
+// right-hand sides fit in LDS, else one launch per panel step.
+hipError_t solve_c64(hipStream_t sm, const BucketBufs& b, int P, int nb, const LUWork& w, int Lmax, long M)
+{
+    if (getrs_lds_ok(P, Lmax))
+        return getrs_lds_batched(sm, (const float2*)b.T, b.sT, P, P, nb, w, b.D64, b.sU, P, Lmax, (int)M);
+    return getrs_batched<float>(sm, (const float2*)b.T, b.sT, P, P, nb, w, b.D64, b.sU, P, Lmax, (int)M);
+}
+
 // The bucket's host tables into its device buffers.
 hipError_t upload_tables(hipStream_t sm, const BucketHost& h, BucketBufs& b)
 {
@@ -310,7 +319,7 @@ rsrr_status run_bucket(rsrr_ctx* c, hipStream_t sm, const rsrr_instance* inst, c
     // first solve
     if (mixed) {
         RSRR_HIP(scale_narrow(sm, P, Lmax, b.Ub, P, b.sU, b.ones, b.D64, P, b.sU, nullptr, (int)M));
-        RSRR_HIP(getrs_batched<float>(sm, (const float2*)b.T, b.sT, P, P, nb, w, b.D64, b.sU, P, Lmax, (int)M));
+        RSRR_HIP(solve_c64(sm, b, P, nb, w, Lmax, M));
         RSRR_HIP(widen(sm, P, Lmax, b.D64, P, b.sU, b.Xb, P, b.sU, (int)M));
     } else {
         RSRR_HIP(copy_c128(sm, P, Lmax, b.Ub, P, b.sU, b.Xb, P, b.sU, (int)M));
@@ -334,7 +343,7 @@ rsrr_status run_bucket(rsrr_ctx* c, hipStream_t sm, const rsrr_instance* inst, c
                            b.iters, b.inv_s, b.scl));
         if (it == iters) break;
         RSRR_HIP(scale_narrow(sm, P, Lmax, b.R, P, b.sU, b.inv_s, b.D64, P, b.sU, b.active, (int)M));
-        RSRR_HIP(getrs_batched<float>(sm, (const float2*)b.T, b.sT, P, P, nb, w, b.D64, b.sU, P, Lmax, (int)M));
+        RSRR_HIP(solve_c64(sm, b, P, nb, w, Lmax, M));
         RSRR_HIP(axpy_widen(sm, P, Lmax, b.D64, P, b.sU, b.scl, b.Xb, P, b.sU, b.active, (int)M));
     }
     // results into each instance's S, all instances in one launch

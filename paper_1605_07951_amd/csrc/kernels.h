@@ -98,6 +98,14 @@ template <typename R>
 hipError_t getrs_batched(hipStream_t st, const typename cpx<R>::T* LU, long sLU, int lda, int n, int nb,
                          const LUWork& w, typename cpx<R>::T* X, long sX, int ldx, int nrhs, int batch);
 
+// getrs_batched<float> for right-hand-side blocks that fit in LDS (n * nrhs * 8 B
+// <= 128 KB, nrhs <= 16): one workgroup per matrix runs every panel's forward and
+// backward step out of LDS (the factor columns stream from memory once).  The
+// factors are those of getrf_batched<float> (same nb and workspace).
+bool getrs_lds_ok(int n, int nrhs);
+hipError_t getrs_lds_batched(hipStream_t st, const float2* LU, long sLU, int lda, int n, int nb, const LUWork& w,
+                             float2* X, long sX, int ldx, int nrhs, int batch);
+
 // The same for real FP32 matrices (a real NEP at real points); workspace as
 // for complex FP32 (inv/tmp hold real values, half the bytes used).
 hipError_t getrf_real_batched(hipStream_t st, float* A, long sA, int lda, int n, int nb, const LUWork& w, int batch);

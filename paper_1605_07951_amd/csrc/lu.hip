@@ -962,6 +962,155 @@ static hipError_t getrs_impl(hipStream_t st, const C* LU, long sLU, int lda, int
     return hipGetLastError();
 }
 
+// ----------------------------------------------------------------------------
+// The whole solve of getrs_impl (complex FP32, diagonal blocks by their
+// inverses) for one matrix per workgroup, for right-hand-side blocks that fit
+// in LDS: X (n x L, held row by row) is read once, every panel's forward step
+// (interchanges, X_p = L11^-1 X_p, rows below -= L21 X_p) and backward step
+// (X_p = U11^-1 X_p, rows above -= U12 X_p) runs out of LDS while the factor
+// columns stream from memory once, and X is written back at the end.  The
+// same operations as the launch-per-step chain, so the same result up to the
+// order of the sums; a matrix with active[b] == 0 is left as it is.
+// ----------------------------------------------------------------------------
+constexpr int GS_NT = 512;
+constexpr int GS_KC = 32;    // columns of a diagonal-block inverse staged in LDS at a time
+constexpr int GS_KU = 16;    // factor entries of one row in flight per thread
+
+template <int LT>
+__global__ __launch_bounds__(GS_NT) void getrs_lds_kernel(const float2* __restrict__ LU, long sLU, int lda, int n,
+                                                          int nb, const int2* __restrict__ perm, long sPerm,
+                                                          const float2* __restrict__ inv, long sInv,
+                                                          float2* __restrict__ X, long sX, int ldx, int L,
+                                                          const int* __restrict__ active)
+{
+    extern __shared__ float2 lds[];
+    float2* xs = lds;                      // n x LT, row r at xs + r LT (columns >= L stay zero)
+    float2* ds = lds + (size_t)n * LT;     // a jb x GS_KC slice of a diagonal-block inverse
+    const int b = blockIdx.x, tid = threadIdx.x;
+    if (active && !active[b]) return;
+    const float2* A = LU + (long)b * sLU;
+    float2* Xb = X + (long)b * sX;
+    for (long e = tid; e < (long)n * LT; e += GS_NT) {
+        const int r = (int)(e / LT), l = (int)(e % LT);
+        xs[e] = l < L ? Xb[r + (long)l * ldx] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    const int np = (n + nb - 1) / nb;
+    // X_p = D X_p for the jb x jb block D (ld nb) and rows c0 .. c0+jb
+    auto diag = [&](const float2* D, int c0, int jb) {
+        constexpr int PER = (MAX_NB * LT + GS_NT - 1) / GS_NT;
+        float2 out[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) out[q] = make_float2(0.f, 0.f);
+        for (int k0 = 0; k0 < jb; k0 += GS_KC) {
+            const int kc = min(GS_KC, jb - k0);
+            for (int e = tid; e < jb * GS_KC; e += GS_NT) {
+                const int i = e % jb, k = e / jb;
+                ds[e] = k < kc ? D[i + (long)(k0 + k) * nb] : make_float2(0.f, 0.f);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int e = tid + GS_NT * q;
+                if (e < jb * LT) {
+                    const int i = e / LT, l = e % LT;
+                    float2 acc = out[q];
+                    for (int k = 0; k < kc; ++k) acc = cfma(acc, ds[i + k * jb], xs[(c0 + k0 + k) * LT + l]);
+                    out[q] = acc;
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + GS_NT * q;
+            if (e < jb * LT) xs[(c0 + e / LT) * LT + e % LT] = out[q];
+        }
+        __syncthreads();
+    };
+    // rows [r0, r1) -= F X_p, F the column block of the factor at (r, c0 .. c0+jb)
+    auto update = [&](int r0, int r1, int c0, int jb) {
+        for (int r = r0 + tid; r < r1; r += GS_NT) {
+            float2 acc[LT];
+#pragma unroll
+            for (int l = 0; l < LT; ++l) acc[l] = xs[r * LT + l];
+            for (int k0 = 0; k0 < jb; k0 += GS_KU) {
+                float2 a[GS_KU];
+#pragma unroll
+                for (int u = 0; u < GS_KU; ++u)
+                    a[u] = k0 + u < jb ? A[r + (long)(c0 + k0 + u) * lda] : make_float2(0.f, 0.f);
+#pragma unroll
+                for (int u = 0; u < GS_KU; ++u) {
+                    if (k0 + u < jb) {
+#pragma unroll
+                        for (int l = 0; l < LT; ++l) acc[l] = cfms(acc[l], a[u], xs[(c0 + k0 + u) * LT + l]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int l = 0; l < LT; ++l) xs[r * LT + l] = acc[l];
+        }
+        __syncthreads();
+    };
+    for (int p = 0; p < np; ++p) {
+        const int c0 = p * nb, jb = min(nb, n - c0);
+        // this panel's interchanges: row pm[s].x receives old row pm[s].y
+        const int2* pm = perm + (long)b * sPerm + (long)p * 2 * MAX_NB;
+        constexpr int PQ = (2 * MAX_NB * LT + GS_NT - 1) / GS_NT;
+        float2 v[PQ];
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) {
+            const int e = tid + GS_NT * q;
+            v[q] = make_float2(0.f, 0.f);
+            if (e < 2 * jb * LT) {
+                const int src = pm[e / LT].y;
+                if (src >= 0) v[q] = xs[src * LT + e % LT];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) {
+            const int e = tid + GS_NT * q;
+            if (e < 2 * jb * LT) {
+                const int2 m = pm[e / LT];
+                if (m.y >= 0 && m.x >= 0) xs[m.x * LT + e % LT] = v[q];
+            }
+        }
+        __syncthreads();
+        diag(inv + (long)b * sInv + (long)(2 * p) * nb * nb, c0, jb);
+        update(c0 + jb, n, c0, jb);
+    }
+    for (int p = np - 1; p >= 0; --p) {
+        const int c0 = p * nb, jb = min(nb, n - c0);
+        diag(inv + (long)b * sInv + (long)(2 * p + 1) * nb * nb, c0, jb);
+        update(0, c0, c0, jb);
+    }
+    for (long e = tid; e < (long)n * L; e += GS_NT) {
+        const int r = (int)(e % n), l = (int)(e / n);
+        Xb[r + (long)l * ldx] = xs[r * LT + l];
+    }
+}
+
+static int gs_width(int nrhs) { return nrhs <= 8 ? 8 : 16; }
+static size_t gs_lds(int n, int nrhs) { return ((size_t)n * gs_width(nrhs) + (size_t)MAX_NB * GS_KC) * 8; }
+bool getrs_lds_ok(int n, int nrhs) { return nrhs >= 1 && nrhs <= 16 && gs_lds(n, nrhs) <= (size_t)128 << 10; }
+
+hipError_t getrs_lds_batched(hipStream_t st, const float2* LU, long sLU, int lda, int n, int nb, const LUWork& w,
+                             float2* X, long sX, int ldx, int nrhs, int batch)
+{
+    if (!getrs_lds_ok(n, nrhs)) return hipErrorInvalidValue;
+    if (nb > max_panel<float>()) nb = max_panel<float>();
+    if (nb < MIN_NB) nb = MIN_NB;
+    const size_t lds = gs_lds(n, nrhs);
+    if (gs_width(nrhs) == 8)
+        hipLaunchKernelGGL(getrs_lds_kernel<8>, dim3(batch), dim3(GS_NT), lds, st, LU, sLU, lda, n, nb, w.perm,
+                           w.sPerm, (const float2*)w.inv, w.sInv, X, sX, ldx, nrhs, w.active);
+    else
+        hipLaunchKernelGGL(getrs_lds_kernel<16>, dim3(batch), dim3(GS_NT), lds, st, LU, sLU, lda, n, nb, w.perm,
+                           w.sPerm, (const float2*)w.inv, w.sInv, X, sX, ldx, nrhs, w.active);
+    return hipGetLastError();
+}
+
 template <>
 hipError_t getrf_batched<float>(hipStream_t st, float2* A, long sA, int lda, int n, int nb, const LUWork& w, int batch)
 {
