@@ -279,6 +279,7 @@ __global__ __launch_bounds__(EW_NT) void ir_decide_kernel(int M, int Lmax, const
 // more loads of T in flight.  Matrices with active[b] == 0 are skipped.  RW rows
 // (= threads) per workgroup: 64 for small matrices, so that there are enough
 // workgroups, 256 otherwise.
+constexpr int RS_KD = 4;
 template <int LC, int RW, int RPT>
 __global__ __launch_bounds__(RW) void resid_skinny_kernel(int n, int L, const double2* __restrict__ T, int ldt,
                                                             long sT, const double2* __restrict__ X, int ldx, long sX,
@@ -310,17 +311,27 @@ __global__ __launch_bounds__(RW) void resid_skinny_kernel(int n, int L, const do
         if (ok[0]) {
             const int kend = min(KC, n - k0);
             const double2* tp = Tb + row0 + (long)k0 * ldt;
-#pragma unroll 2
-            for (int kk = 0; kk < kend; ++kk) {
-                double2 t[RPT];
+            // RS_KD columns of T in flight per thread; past kend the last
+            // column is loaded again and multiplied by the zero rows of xs
+            for (int kk0 = 0; kk0 < kend; kk0 += RS_KD) {
+                double2 t[RS_KD][RPT];
 #pragma unroll
-                for (int r = 0; r < RPT; ++r)
-                    t[r] = ok[r] ? tp[r * RW + (long)kk * ldt] : make_double2(0.0, 0.0);
+                for (int u = 0; u < RS_KD; ++u) {
+                    const long kc = min(kk0 + u, kend - 1);
 #pragma unroll
-                for (int c = 0; c < LC; ++c) {
-                    const double2 x = xs[kk][c];
+                    for (int r = 0; r < RPT; ++r)
+                        t[u][r] = ok[r] ? tp[r * RW + kc * ldt] : make_double2(0.0, 0.0);
+                }
 #pragma unroll
-                    for (int r = 0; r < RPT; ++r) acc[r][c] = cfma(acc[r][c], t[r], x);
+                for (int u = 0; u < RS_KD; ++u) {
+                    if (kk0 + u < kend) {
+#pragma unroll
+                        for (int c = 0; c < LC; ++c) {
+                            const double2 x = xs[kk0 + u][c];
+#pragma unroll
+                            for (int r = 0; r < RPT; ++r) acc[r][c] = cfma(acc[r][c], t[u][r], x);
+                        }
+                    }
                 }
             }
         }

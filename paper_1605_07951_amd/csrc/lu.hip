@@ -971,21 +971,94 @@ static hipError_t getrs_impl(hipStream_t st, const C* LU, long sLU, int lda, int
 // columns stream from memory once, and X is written back at the end.  The
 // same operations as the launch-per-step chain, so the same result up to the
 // order of the sums; a matrix with active[b] == 0 is left as it is.
+//
+// Work split: a product row is summed by kg adjacent lanes (lane g of the
+// group takes the columns k = g, g + kg, ...) whose partial sums are combined
+// by butterfly shuffles in a fixed order.  The diagonal blocks (at most 128
+// rows) use kg = 4, so every lane has its share of the block's columns in
+// flight at once; the off-diagonal updates use kg = 1, 2 or 4 as the number
+// of rows left shrinks, so the late panels of a sweep keep every lane busy.
+// The factor and the inverses are read straight from memory (no staging),
+// which leaves the LDS to X alone: n = 1024 with 8 right-hand sides takes
+// 64 KB, two workgroups per compute unit.
 // ----------------------------------------------------------------------------
 constexpr int GS_NT = 512;
-constexpr int GS_KC = 32;    // columns of a diagonal-block inverse staged in LDS at a time
-constexpr int GS_KU = 16;    // factor entries of one row in flight per thread
+constexpr int GS_KU = 16;           // factor entries of one row in flight per lane
+constexpr int GS_DK = MAX_NB / 4;   // diagonal-block entries per lane (4 lanes per row)
+
+// sum of v over the kg adjacent lanes of a group (kg a power of two <= 4; every
+// lane of the wave takes part)
+template <int LT>
+RSRR_DEV void group_sum(float2 (&v)[LT], int kg)
+{
+    for (int off = 1; off < kg; off <<= 1) {
+#pragma unroll
+        for (int l = 0; l < LT; ++l) {
+            v[l].x += __shfl_xor(v[l].x, off);
+            v[l].y += __shfl_xor(v[l].y, off);
+        }
+    }
+}
+
+// p[off] for a uniform base p and a 32-bit element offset (the byte offset
+// fits in 32 bits), so that the load takes the scalar-base form
+RSRR_DEV float2 ldg_off(const float2* __restrict__ p, unsigned off)
+{
+    return *(const float2*)((const char*)p + (size_t)(off * 8u));
+}
+
+// rows [r0, r1) of X (in LDS, LT per row) -= A(r0:r1, c0:c0+jb) X(c0:c0+jb),
+// KG lanes per row; the factor offsets fit in 32 bits (n <= 2048)
+template <int LT, int KG>
+RSRR_DEV void getrs_lds_update(const float2* __restrict__ A, int lda, float2* xs, int r0, int r1, int c0, int jb,
+                               int tid)
+{
+    constexpr int ROWS = GS_NT / KG;
+    const int i = tid / KG, g = tid % KG;
+    for (int rb = r0; rb < r1; rb += ROWS) {
+        const int r = rb + i;
+        const bool on = r < r1;
+        float2 acc[LT];
+#pragma unroll
+        for (int l = 0; l < LT; ++l) acc[l] = make_float2(0.f, 0.f);
+        for (int kb = 0; kb < jb; kb += GS_KU * KG) {
+            const unsigned rc = (unsigned)min(r, r1 - 1);
+            float2 a[GS_KU];
+#pragma unroll
+            for (int u = 0; u < GS_KU; ++u) {
+                const int k = kb + g + u * KG;
+                const float2 v = ldg_off(A, rc + (unsigned)(c0 + min(k, jb - 1)) * (unsigned)lda);
+                a[u] = (on && k < jb) ? v : make_float2(0.f, 0.f);
+            }
+#pragma unroll
+            for (int u = 0; u < GS_KU; ++u) {
+                const int k = kb + g + u * KG;
+                if (k < jb) {
+#pragma unroll
+                    for (int l = 0; l < LT; ++l) acc[l] = cfma(acc[l], a[u], xs[(c0 + k) * LT + l]);
+                }
+            }
+        }
+        group_sum<LT>(acc, KG);
+        if (on) {
+#pragma unroll
+            for (int l = 0; l < LT; ++l)
+                if (l % KG == g) {
+                    const float2 x = xs[r * LT + l];
+                    xs[r * LT + l] = make_float2(x.x - acc[l].x, x.y - acc[l].y);
+                }
+        }
+    }
+}
 
 template <int LT>
-__global__ __launch_bounds__(GS_NT) void getrs_lds_kernel(const float2* __restrict__ LU, long sLU, int lda, int n,
+__global__ __launch_bounds__(GS_NT) __attribute__((amdgpu_waves_per_eu(4))) void getrs_lds_kernel(const float2* __restrict__ LU, long sLU, int lda, int n,
                                                           int nb, const int2* __restrict__ perm, long sPerm,
                                                           const float2* __restrict__ inv, long sInv,
                                                           float2* __restrict__ X, long sX, int ldx, int L,
                                                           const int* __restrict__ active)
 {
-    extern __shared__ float2 lds[];
-    float2* xs = lds;                      // n x LT, row r at xs + r LT (columns >= L stay zero)
-    float2* ds = lds + (size_t)n * LT;     // a jb x GS_KC slice of a diagonal-block inverse
+    extern __shared__ float2 xs[];   // n x LT, row r at xs + r LT (columns >= L stay zero)
     const int b = blockIdx.x, tid = threadIdx.x;
     if (active && !active[b]) return;
     const float2* A = LU + (long)b * sLU;
@@ -997,59 +1070,47 @@ __global__ __launch_bounds__(GS_NT) void getrs_lds_kernel(const float2* __restri
     __syncthreads();
     const int np = (n + nb - 1) / nb;
     // X_p = D X_p for the jb x jb block D (ld nb) and rows c0 .. c0+jb
-    auto diag = [&](const float2* D, int c0, int jb) {
-        constexpr int PER = (MAX_NB * LT + GS_NT - 1) / GS_NT;
-        float2 out[PER];
+    auto diag = [=](const float2* D, int c0, int jb) {
+        const int i = tid >> 2, g = tid & 3;
+        const bool on = i < jb;
+        const unsigned ic = (unsigned)min(i, jb - 1);
+        float2 acc[LT];
 #pragma unroll
-        for (int q = 0; q < PER; ++q) out[q] = make_float2(0.f, 0.f);
-        for (int k0 = 0; k0 < jb; k0 += GS_KC) {
-            const int kc = min(GS_KC, jb - k0);
-            for (int e = tid; e < jb * GS_KC; e += GS_NT) {
-                const int i = e % jb, k = e / jb;
-                ds[e] = k < kc ? D[i + (long)(k0 + k) * nb] : make_float2(0.f, 0.f);
+        for (int l = 0; l < LT; ++l) acc[l] = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int h = 0; h < GS_DK; h += GS_DK / 2) {
+            float2 d[GS_DK / 2];
+#pragma unroll
+            for (int m = 0; m < GS_DK / 2; ++m) {
+                const int k = g + 4 * (h + m);
+                const unsigned kc = (unsigned)min(k, jb - 1);
+                const float2 v = ldg_off(D, ic + kc * (unsigned)nb);
+                d[m] = (on && k < jb) ? v : make_float2(0.f, 0.f);
             }
-            __syncthreads();
 #pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                const int e = tid + GS_NT * q;
-                if (e < jb * LT) {
-                    const int i = e / LT, l = e % LT;
-                    float2 acc = out[q];
-                    for (int k = 0; k < kc; ++k) acc = cfma(acc, ds[i + k * jb], xs[(c0 + k0 + k) * LT + l]);
-                    out[q] = acc;
+            for (int m = 0; m < GS_DK / 2; ++m) {
+                const int k = g + 4 * (h + m);
+                if (k < jb) {
+#pragma unroll
+                    for (int l = 0; l < LT; ++l) acc[l] = cfma(acc[l], d[m], xs[(c0 + k) * LT + l]);
                 }
             }
-            __syncthreads();
         }
+        group_sum<LT>(acc, 4);
+        __syncthreads();   // every read of X_p precedes the first write
+        if (on) {
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int e = tid + GS_NT * q;
-            if (e < jb * LT) xs[(c0 + e / LT) * LT + e % LT] = out[q];
+            for (int l = 0; l < LT; ++l)
+                if ((l & 3) == g) xs[(c0 + i) * LT + l] = acc[l];
         }
         __syncthreads();
     };
     // rows [r0, r1) -= F X_p, F the column block of the factor at (r, c0 .. c0+jb)
-    auto update = [&](int r0, int r1, int c0, int jb) {
-        for (int r = r0 + tid; r < r1; r += GS_NT) {
-            float2 acc[LT];
-#pragma unroll
-            for (int l = 0; l < LT; ++l) acc[l] = xs[r * LT + l];
-            for (int k0 = 0; k0 < jb; k0 += GS_KU) {
-                float2 a[GS_KU];
-#pragma unroll
-                for (int u = 0; u < GS_KU; ++u)
-                    a[u] = k0 + u < jb ? A[r + (long)(c0 + k0 + u) * lda] : make_float2(0.f, 0.f);
-#pragma unroll
-                for (int u = 0; u < GS_KU; ++u) {
-                    if (k0 + u < jb) {
-#pragma unroll
-                        for (int l = 0; l < LT; ++l) acc[l] = cfms(acc[l], a[u], xs[(c0 + k0 + u) * LT + l]);
-                    }
-                }
-            }
-#pragma unroll
-            for (int l = 0; l < LT; ++l) xs[r * LT + l] = acc[l];
-        }
+    auto update = [=](int r0, int r1, int c0, int jb) {
+        const int R = r1 - r0;
+        if (R <= GS_NT / 4) getrs_lds_update<LT, 4>(A, lda, xs, r0, r1, c0, jb, tid);
+        else if (R <= GS_NT / 2) getrs_lds_update<LT, 2>(A, lda, xs, r0, r1, c0, jb, tid);
+        else getrs_lds_update<LT, 1>(A, lda, xs, r0, r1, c0, jb, tid);
         __syncthreads();
     };
     for (int p = 0; p < np; ++p) {
@@ -1092,7 +1153,7 @@ __global__ __launch_bounds__(GS_NT) void getrs_lds_kernel(const float2* __restri
 }
 
 static int gs_width(int nrhs) { return nrhs <= 8 ? 8 : 16; }
-static size_t gs_lds(int n, int nrhs) { return ((size_t)n * gs_width(nrhs) + (size_t)MAX_NB * GS_KC) * 8; }
+static size_t gs_lds(int n, int nrhs) { return (size_t)n * gs_width(nrhs) * 8; }
 bool getrs_lds_ok(int n, int nrhs) { return nrhs >= 1 && nrhs <= 16 && gs_lds(n, nrhs) <= (size_t)128 << 10; }
 
 hipError_t getrs_lds_batched(hipStream_t st, const float2* LU, long sLU, int lda, int n, int nb, const LUWork& w,
