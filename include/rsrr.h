@@ -75,8 +75,31 @@ enum {
 /* Kinds of T(z).  SEPARABLE: T(z) = sum_j f_j(z) A_j (the form of every
  * example of Sec. 2.1 except the boundary-element kernels).  HELMHOLTZ: the
  * single-layer Nystrom matrix of a point set on a surface (kernel G of
- * eq. nyes): T_ij = w e^{i z r_ij} / (4 pi r_ij), T_ii = sqrt(w/pi)/2 + i z w/(4 pi). */
-enum { RSRR_T_SEPARABLE = 0, RSRR_T_HELMHOLTZ = 1 };
+ * eq. nyes): T_ij = w e^{i z r_ij} / (4 pi r_ij), T_ii = sqrt(w/pi)/2 + i z w/(4 pi).
+ * SPARSE: the separable form with every A_j in compressed sparse row storage
+ * (rsrr_csr), the storage of the finite-element models that Sec. 4.3 and
+ * Sec. 6 solve with sparse direct and iterative solvers.  rsrr_sample forms
+ * dense T(z_k) from it; rsrr_sample_gmres applies T(z_k) from the sparse
+ * rows (the preconditioner is still a dense factorisation at the reference
+ * points); rsrr_project forms A_j Q from the sparse rows; rsrr_solve and
+ * rsrr_two_stage accept it; rsrr_sample_batched and the server refuse it. */
+enum { RSRR_T_SEPARABLE = 0, RSRR_T_HELMHOLTZ = 1, RSRR_T_SPARSE = 2 };
+
+/* One coefficient matrix of a SPARSE nep (n x n, compressed sparse rows, all
+ * arrays on the device and owned by the caller): row i holds the entries
+ * rowptr[i] .. rowptr[i+1]-1 (rowptr: n+1 ints, rowptr[0] = 0, rowptr[n] =
+ * nnz); entry e lies in column col[e] (0-based) with the value
+ * val[2e] + i val[2e+1].  The entries of a row may come in any order and a
+ * repeated (row, column) pair is summed.  The device kernels check every row
+ * range against [0, nnz] and every column against [0, n): an entry outside
+ * is skipped and the call returns -2 (S or AQ then hold partial results). */
+typedef struct {
+    int nnz;
+    int pad;
+    const int *rowptr;
+    const int *col;
+    const double *val;
+} rsrr_csr;
 
 /* Arithmetic of the sampling step.  C128: complex FP64 LU and solves.
  * C64_IR: complex FP32 LU on the matrix cores, then iterative refinement
@@ -103,7 +126,9 @@ typedef struct {
  * SEPARABLE: n, J, A (device, J matrices n x n, matrix j at A + 2*j*lda*n
  *            doubles), lda >= n, terms (host, J entries).
  * HELMHOLTZ: n, points (device, n x 3 doubles, x y z of point i at
- *            points + 3*i), w (quadrature weight per point). */
+ *            points + 3*i), w (quadrature weight per point).
+ * SPARSE:    n, J (1..64), terms (host, J entries), csr (host, J
+ *            descriptors; matrix j is csr[j]). */
 typedef struct {
     int kind;
     int n;
@@ -113,6 +138,7 @@ typedef struct {
     const rsrr_term *terms;
     const double *points;
     double w;
+    const rsrr_csr *csr;
 } rsrr_nep;
 
 /* Per sampling point diagnostics of rsrr_sample. */
@@ -212,7 +238,8 @@ RSRR_API rsrr_status rsrr_contour(double gamma_re, double gamma_im, double a, do
  * prec: RSRR_PREC_C128 or RSRR_PREC_C64_IR.
  * Status: RSRR_ESINGULAR if any point had an exact zero pivot (its block of S
  * is then not meaningful), RSRR_WARN_FALLBACK if any point was redone in FP64.
- * Errors: -2 nep invalid (or not SEPARABLE with R32_IR), -3 N < 1, -4 z NULL
+ * Errors: -2 nep invalid (or not SEPARABLE with R32_IR; or a SPARSE entry out of
+ * bounds, found on the device), -3 N < 1, -4 z NULL
  * (or a point off the real axis with R32_IR), -5 U NULL, -6 L < 1, -7 ldu < n,
  * -8 prec, -9 S NULL, -10 lds < n. */
 RSRR_API rsrr_status rsrr_sample(rsrr_ctx *ctx, const rsrr_nep *nep, int N, const double *z,
@@ -239,7 +266,9 @@ typedef struct {
  * nref reference points (host, 2*nref doubles): r = ref[k] (host, N ints in
  * [0, nref)), or the nearest reference when ref is NULL; each used reference
  * is factored once.  The operator T(z_k), the Krylov vectors and the
- * residuals are FP64.  For a HELMHOLTZ nep the operator uses the points'
+ * residuals are FP64.  For a SPARSE nep the operator walks the sparse rows
+ * (no n x n matrix per point; the references are formed densely for their
+ * factorisation, which checks every row's bounds first).  For a HELMHOLTZ nep the operator uses the points'
  * assembled FP64 matrices (16 n^2 bytes per point of a chunk), or, with flags
  * RSRR_GMRES_MATRIX_FREE or when they would take more than half of the
  * workspace budget, generates the entries inside every application
@@ -255,7 +284,8 @@ typedef struct {
  * Status: RSRR_ENOTCONV if a column missed tol within max_iters (S still holds
  * the last iterate; info says which points), RSRR_ESINGULAR / RSRR_ENAN if a
  * reference matrix had an exact zero / non-finite pivot (nothing solved).
- * Errors: -2 nep invalid (n > 8192), -3 N < 1, -4 z NULL, -5 nref < 1,
+ * Errors: -2 nep invalid (n > 8192; or a SPARSE entry out of bounds), -3 N < 1,
+ * -4 z NULL, -5 nref < 1,
  * -6 zref NULL, -7 a ref[k] out of range, -8 U NULL, -9 L < 1, -10 ldu < n,
  * -11 tol, -12 restart, -13 max_iters < 1, -14 flags, -15 S NULL, -16 lds < n. */
 enum { RSRR_GMRES_MATRIX_FREE = 1 };
@@ -289,7 +319,8 @@ RSRR_API rsrr_status rsrr_basis(rsrr_ctx *ctx, int n, int NL, double *S, int lds
                        double *Q, int ldq, int kmax, int *k, double *sigma);
 
 /* Projection (RSRR Step 4, eq. Ts-NEP): T_Q(z) = Q^H T(z) Q with Q (device,
- * n x k, ldq).  SEPARABLE: AQ_j = Q^H A_j Q for each j and the same terms.
+ * n x k, ldq).  SEPARABLE: AQ_j = Q^H A_j Q for each j and the same terms
+ * (SPARSE: the same, with A_j Q formed from the sparse rows).
  * HELMHOLTZ: T(z) is expanded about gamma (host, 2 doubles) in powers of
  * (z - gamma), with the degree chosen so that the remainder is below 1e-17
  * relative for |z - gamma| <= radius; AQ_p = Q^H T_p Q, term p = (z-gamma)^p.

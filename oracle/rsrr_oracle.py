@@ -13,6 +13,10 @@ Steps and the passages they follow
 * ``T_separable``, ``T_helmholtz``
                        T(z) for the two families (eq. QEP / eq. REP-string /
                        the delay form; the single-layer kernel of eq. nyes).
+* ``csr_dense``        the dense matrix of a compressed-sparse-row matrix (the
+                       storage of the finite-element models of Sec. 4.3 and
+                       Sec. 6); a sparse NEP is the separable form with its
+                       A_j given that way and is evaluated densely here.
 * ``sample``           RSRR Step 2 and eq. hatS: S = [T(z_0)^-1 U, ...].
                        This is a plain definition (the unique solution of
                        each linear system), computed by zgetrf/zgetrs.
@@ -152,6 +156,17 @@ def dT_separable(A, terms, z):
     return T
 
 
+def csr_dense(indptr, indices, data, n):
+    """The dense n x n matrix of a compressed-sparse-row matrix: row i holds the
+    entries indptr[i] .. indptr[i+1]-1, entry e at column indices[e] with value
+    data[e]; a repeated (row, column) pair is summed."""
+    A = np.zeros((n, n), dtype=np.complex128)
+    for i in range(n):
+        for e in range(int(indptr[i]), int(indptr[i + 1])):
+            A[i, int(indices[e])] += data[e]
+    return A
+
+
 def _distances(points):
     diff = points[:, None, :] - points[None, :, :]
     return np.sqrt(np.sum(diff * diff, axis=2))
@@ -192,6 +207,12 @@ class Problem:
         if hasattr(nep, "A"):
             self.kind = "separable"
             self.n = nep.A[0].shape[0]
+            self._A = nep.A
+        elif hasattr(nep, "csr"):
+            # the sparse form is the separable one with its matrices stored by rows
+            self.kind = "separable"
+            self.n = nep.n
+            self._A = [csr_dense(ip, ix, d, nep.n) for ip, ix, d in nep.csr]
         else:
             self.kind = "helmholtz"
             self.n = nep.points.shape[0]
@@ -199,12 +220,12 @@ class Problem:
 
     def T(self, z):
         if self.kind == "separable":
-            return T_separable(self.nep.A, self.nep.terms, z)
+            return T_separable(self._A, self.nep.terms, z)
         return T_helmholtz(self.nep.points, self.nep.w, z, self._r)
 
     def dT(self, z):
         if self.kind == "separable":
-            return dT_separable(self.nep.A, self.nep.terms, z)
+            return dT_separable(self._A, self.nep.terms, z)
         return dT_helmholtz(self.nep.points, self.nep.w, z, self._r)
 
 
@@ -259,7 +280,7 @@ def project(prob, Q):
     """
     QH = Q.conj().T
     if prob.kind == "separable":
-        AQ = [QH @ Aj @ Q for Aj in prob.nep.A]
+        AQ = [QH @ Aj @ Q for Aj in prob._A]
         terms = prob.nep.terms
 
         def TQ(z):

@@ -45,7 +45,7 @@ rsrr_status steps_3_to_5(rsrr_ctx* c, const rsrr_nep* nep, double* S, int lds, i
     *k_out = k;
     *count = 0;
     if (k < 1) return st;
-    const int maxt = nep->kind == RSRR_T_SEPARABLE ? nep->J : MAX_TERMS;
+    const int maxt = nep->kind == RSRR_T_HELMHOLTZ ? MAX_TERMS : nep->J;
     double2* AQ = (double2*)ws_get(c, WS_TSAQ, (size_t)maxt * k * k * 16);
     if (!AQ) return RSRR_ENOMEM;
     std::vector<rsrr_term> tout(maxt);

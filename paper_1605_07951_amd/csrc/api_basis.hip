@@ -227,6 +227,8 @@ extern "C" rsrr_status rsrr_project(rsrr_ctx* c, const rsrr_nep* nep, const doub
     if (!nep || nep->n < 1) return -2;
     if (nep->kind == RSRR_T_SEPARABLE && (nep->J < 1 || !nep->A || nep->lda < nep->n || !nep->terms)) return -2;
     if (nep->kind == RSRR_T_HELMHOLTZ && (!nep->points || !(nep->w > 0))) return -2;
+    if (nep->kind == RSRR_T_SPARSE && !csr_nep_ok(nep)) return -2;
+    if (nep->kind != RSRR_T_SEPARABLE && nep->kind != RSRR_T_HELMHOLTZ && nep->kind != RSRR_T_SPARSE) return -2;
     if (!Qp) return -3;
     if (ldq < nep->n) return -4;
     if (k < 1 || k > nep->n) return -5;
@@ -248,6 +250,23 @@ extern "C" rsrr_status rsrr_project(rsrr_ctx* c, const rsrr_nep* nep, const doub
         RSRR_HIP(zgemm(c->stream, 0, 0, n, k, n, 1.0, (const double2*)nep->A, nep->lda, (long)nep->lda * n, Q, ldq, 0,
                        0.0, W, n, (long)n * k, J));
         RSRR_HIP(zgemm(c->stream, 1, 0, k, k, n, 1.0, Q, ldq, 0, W, n, (long)n * k, 0.0, out, k, (long)k * k, J));
+        for (int j = 0; j < J; ++j) terms_out[j] = nep->terms[j];
+        *J_eff = J;
+    } else if (nep->kind == RSRR_T_SPARSE) {
+        const int J = nep->J;
+        if (max_terms < J) return -9;
+        double2* W = (double2*)ws_get(c, WS_B0, (size_t)J * n * k * 16);
+        double2* one = (double2*)ws_get(c, WS_COEF, 16);
+        if (!W || !one) return RSRR_ENOMEM;
+        const double2 h1 = make_double2(1.0, 0.0);
+        RSRR_HIP(hipMemcpyAsync(one, &h1, 16, hipMemcpyHostToDevice, c->stream));
+        CsrDev d;
+        RSRR_TRY(csr_upload(c, nep, d));
+        // W_j = A_j Q from the sparse rows, then AQ_j = Q^H W_j (one batched launch)
+        for (int j = 0; j < J; ++j)
+            RSRR_HIP(csr_apply(c->stream, n, 1, d.terms + j, one, 1, k, Q, ldq, W + (size_t)j * n * k, n, d.bad));
+        RSRR_HIP(zgemm(c->stream, 1, 0, k, k, n, 1.0, Q, ldq, 0, W, n, (long)n * k, 0.0, out, k, (long)k * k, J));
+        RSRR_TRY(csr_check(c, d));
         for (int j = 0; j < J; ++j) terms_out[j] = nep->terms[j];
         *J_eff = J;
     } else {

@@ -71,6 +71,8 @@ struct GmChunk {
     int *done, *act, *kc, *steps, *ndone, *pidx;
     double2* T;                    // HELMHOLTZ: per-point FP64 matrices (null: generated on the fly)
     double2* zc;                   // HELMHOLTZ: the chunk's points (device)
+    const CsrTerm* csr;            // SPARSE: device table of the term matrices
+    int* bad;                      // SPARSE: bounds flag of that table
     void* tmp;                     // getrs scratch
 };
 
@@ -81,6 +83,11 @@ static rsrr_status gm_apply(rsrr_ctx* c, const rsrr_nep* nep, int L, int ld, lon
                             const double2* Zin, double2* W)
 {
     const int n = nep->n;
+    if (nep->kind == RSRR_T_SPARSE) {
+        // sum_j f_j(z_point(c)) A_j Z(:, c), straight from the sparse rows
+        RSRR_HIP(csr_apply(c->stream, n, nep->J, k.csr, k.coef, k.B, L, Zin, ld, W, ld, k.bad));
+        return RSRR_OK;
+    }
     if (nep->kind == RSRR_T_SEPARABLE) {
         // sum_j A_j (Z diag(f_j(z_point(c)))) = [A_0 .. A_{J-1}] [Z f_0; ..; Z f_{J-1}]: the terms lie
         // back to back (matrix j at column j*n of one n x J*n matrix), so this is one GEMM of depth
@@ -126,6 +133,8 @@ extern "C" rsrr_status rsrr_sample_gmres(rsrr_ctx* c, const rsrr_nep* nep, int N
         if (nep->J < 1 || nep->J > 64 || !nep->A || nep->lda < nep->n || !nep->terms) return -2;
     } else if (nep->kind == RSRR_T_HELMHOLTZ) {
         if (!nep->points || !(nep->w > 0)) return -2;
+    } else if (nep->kind == RSRR_T_SPARSE) {
+        if (!csr_nep_ok(nep)) return -2;
     } else {
         return -2;
     }
@@ -176,6 +185,7 @@ extern "C" rsrr_status rsrr_sample_gmres(rsrr_ctx* c, const rsrr_nep* nep, int N
         if (slot[rk[k]] < 0) { slot[rk[k]] = (int)used.size(); used.push_back(rk[k]); }
     const int nf = (int)used.size();
 
+    CsrDev csrd;  // SPARSE: the term table on the device (uploaded with the references)
     // ---- complex FP32 LU of T at the used references ----
     const int nb = std::min(std::max(c->nb_c64, MIN_NB), max_panel<float>());
     const int np = perm_panels(n);
@@ -199,7 +209,7 @@ extern "C" rsrr_status rsrr_sample_gmres(rsrr_ctx* c, const rsrr_nep* nep, int N
         double* frobp = (double*)ws_get(c, WS_FROBP, (size_t)nf * nparts * 8);
         double* frob = (double*)ws_get(c, WS_FROB, (size_t)nf * 8);
         if (!frobp || !frob) return RSRR_ENOMEM;
-        if (nep->kind == RSRR_T_SEPARABLE) {
+        if (nep->kind == RSRR_T_SEPARABLE || nep->kind == RSRR_T_SPARSE) {
             double2* coef = (double2*)ws_get(c, WS_COEF, (size_t)nep->J * nf * 16);
             if (!coef) return RSRR_ENOMEM;
             std::vector<double2> cf((size_t)nep->J * nf);
@@ -209,8 +219,19 @@ extern "C" rsrr_status rsrr_sample_gmres(rsrr_ctx* c, const rsrr_nep* nep, int N
                     cf[(size_t)j * nf + f] = make_double2(v.real(), v.imag());
                 }
             RSRR_HIP(hipMemcpyAsync(coef, cf.data(), cf.size() * 16, hipMemcpyHostToDevice, c->stream));
-            RSRR_HIP(assemble_separable(c->stream, n, nep->J, (const double2*)nep->A, nep->lda, coef, nf, Tf, ld, sT,
-                                        nullptr, 0, 0, frobp, frob));
+            if (nep->kind == RSRR_T_SEPARABLE) {
+                RSRR_HIP(assemble_separable(c->stream, n, nep->J, (const double2*)nep->A, nep->lda, coef, nf, Tf, ld,
+                                            sT, nullptr, 0, 0, frobp, frob));
+            } else {
+                // the references' FP64 matrices from the sparse rows (scratch), narrowed into the LU input;
+                // the bounds of every row are checked here, before any operator application
+                double2* T128 = (double2*)ws_get(c, WS_GMT, (size_t)nf * sT * 16);
+                if (!T128) return RSRR_ENOMEM;
+                RSRR_TRY(csr_upload(c, nep, csrd));
+                RSRR_HIP(assemble_sparse(c->stream, n, nep->J, csrd.terms, coef, nf, Tf, ld, sT, T128, ld, sT, frobp,
+                                         frob, csrd.bad));
+                RSRR_TRY(csr_check(c, csrd));
+            }
         } else {
             double2* zdev = (double2*)ws_get(c, WS_Z, (size_t)nf * 16);
             if (!zdev) return RSRR_ENOMEM;
@@ -358,6 +379,8 @@ extern "C" rsrr_status rsrr_sample_gmres(rsrr_ctx* c, const rsrr_nep* nep, int N
         k.coef = sc.take<double2>((size_t)std::max(nep->J, 1) * k.B);
         k.zc = sc.take<double2>(k.B);
         k.T = nullptr;
+        k.csr = csrd.terms;
+        k.bad = csrd.bad;
 
         std::vector<int> hp(k.B);
         for (int b = 0; b < k.B; ++b) hp[b] = order[p0 + b];
@@ -365,7 +388,7 @@ extern "C" rsrr_status rsrr_sample_gmres(rsrr_ctx* c, const rsrr_nep* nep, int N
         {
             EvPair ev;
             RSRR_HIP(hipEventRecord(ev.a, c->stream));
-            if (nep->kind == RSRR_T_SEPARABLE) {
+            if (nep->kind != RSRR_T_HELMHOLTZ) {
                 std::vector<double2> cf((size_t)nep->J * k.B);
                 for (int j = 0; j < nep->J; ++j)
                     for (int b = 0; b < k.B; ++b) {

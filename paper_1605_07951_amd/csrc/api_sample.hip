@@ -383,6 +383,21 @@ static rsrr_status alloc_bufs(rsrr_ctx* c, int n, int L, int J, int prec, int B,
     return RSRR_OK;
 }
 
+// f_j(z_k) of a separable or sparse nep for B host points into coef (device,
+// [J][B], point-fastest); the upload is complete on return.
+static rsrr_status upload_coef(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, int B, double2* coef)
+{
+    std::vector<double2> cf((size_t)nep->J * B);
+    for (int j = 0; j < nep->J; ++j)
+        for (int k = 0; k < B; ++k) {
+            const zd f = term_eval(nep->terms[j], z[k]);
+            cf[(size_t)j * B + k] = make_double2(f.real(), f.imag());
+        }
+    RSRR_HIP(hipMemcpyAsync(coef, cf.data(), cf.size() * 16, hipMemcpyHostToDevice, c->stream));
+    RSRR_HIP(hipStreamSynchronize(c->stream));
+    return RSRR_OK;
+}
+
 // Assemble T(z_k) for the batch into the LU buffer (c64 or c128) and the FP64 copy.
 static rsrr_status assemble_batch(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, int B, int prec, SampleBufs& s)
 {
@@ -390,18 +405,20 @@ static rsrr_status assemble_batch(rsrr_ctx* c, const rsrr_nep* nep, const zd* z,
     float2* T64 = prec == RSRR_PREC_C64_IR ? (float2*)s.Tlu : nullptr;
     double2* Tlu128 = prec == RSRR_PREC_C128 ? (double2*)s.Tlu : nullptr;
     if (nep->kind == RSRR_T_SEPARABLE) {
-        std::vector<double2> cf((size_t)nep->J * B);
-        for (int j = 0; j < nep->J; ++j)
-            for (int k = 0; k < B; ++k) {
-                zd f = term_eval(nep->terms[j], z[k]);
-                cf[(size_t)j * B + k] = make_double2(f.real(), f.imag());
-            }
-        RSRR_HIP(hipMemcpyAsync(s.coef, cf.data(), cf.size() * 16, hipMemcpyHostToDevice, c->stream));
-        RSRR_HIP(hipStreamSynchronize(c->stream));
+        RSRR_TRY(upload_coef(c, nep, z, B, s.coef));
         RSRR_HIP(assemble_separable(c->stream, n, nep->J, (const double2*)nep->A, nep->lda, s.coef, B, T64, s.ld,
                                     s.sT, s.Tres, s.ld, s.sT, s.frobp, s.frob));
         if (Tlu128) RSRR_HIP(copy_c128(c->stream, n, n, s.Tres, s.ld, s.sT, Tlu128, s.ld, s.sT, B));
         if (prec == RSRR_PREC_R32_IR) RSRR_HIP(narrow_real(c->stream, n, s.Tres, s.ld, s.sT, (float*)s.Tlu, s.ld, s.sT, B));
+    } else if (nep->kind == RSRR_T_SPARSE) {
+        // the FP64 copy is formed from the sparse rows, the LU input from it
+        RSRR_TRY(upload_coef(c, nep, z, B, s.coef));
+        CsrDev d;
+        RSRR_TRY(csr_upload(c, nep, d));
+        RSRR_HIP(assemble_sparse(c->stream, n, nep->J, d.terms, s.coef, B, T64, s.ld, s.sT, s.Tres, s.ld, s.sT,
+                                 s.frobp, s.frob, d.bad));
+        RSRR_TRY(csr_check(c, d));
+        if (Tlu128) RSRR_HIP(copy_c128(c->stream, n, n, s.Tres, s.ld, s.sT, Tlu128, s.ld, s.sT, B));
     } else {
         std::vector<double2> zz(B);
         for (int k = 0; k < B; ++k) zz[k] = make_double2(z[k].real(), z[k].imag());
@@ -723,6 +740,42 @@ static rsrr_status sample_batch(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, i
 
 }  // namespace
 
+bool csr_nep_ok(const rsrr_nep* nep)
+{
+    if (nep->J < 1 || nep->J > 64 || !nep->terms || !nep->csr) return false;
+    for (int j = 0; j < nep->J; ++j) {
+        const rsrr_csr& m = nep->csr[j];
+        if (m.nnz < 0 || !m.rowptr || (m.nnz > 0 && (!m.col || !m.val))) return false;
+    }
+    return true;
+}
+
+rsrr_status csr_upload(rsrr_ctx* c, const rsrr_nep* nep, CsrDev& d)
+{
+    const size_t tb = ((size_t)nep->J * sizeof(CsrTerm) + 255) / 256 * 256;
+    char* p = (char*)ws_get(c, WS_CSR, tb + 256);
+    if (!p) return RSRR_ENOMEM;
+    std::vector<CsrTerm> h(nep->J);
+    for (int j = 0; j < nep->J; ++j) {
+        const rsrr_csr& m = nep->csr[j];
+        h[j] = CsrTerm{m.rowptr, m.col, (const double2*)m.val, m.nnz, 0};
+    }
+    RSRR_HIP(hipMemcpyAsync(p, h.data(), h.size() * sizeof(CsrTerm), hipMemcpyHostToDevice, c->stream));
+    RSRR_HIP(hipMemsetAsync(p + tb, 0, 4, c->stream));
+    RSRR_HIP(hipStreamSynchronize(c->stream));
+    d.terms = (CsrTerm*)p;
+    d.bad = (int*)(p + tb);
+    return RSRR_OK;
+}
+
+rsrr_status csr_check(rsrr_ctx* c, const CsrDev& d)
+{
+    int h = 0;
+    RSRR_HIP(hipMemcpyAsync(&h, d.bad, 4, hipMemcpyDeviceToHost, c->stream));
+    RSRR_HIP(hipStreamSynchronize(c->stream));
+    return h ? -2 : RSRR_OK;
+}
+
 rsrr_status assemble_c128(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, int B, double2* T, int ld, long sT,
                           double* frob)
 {
@@ -730,19 +783,20 @@ rsrr_status assemble_c128(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, int B, 
     const long nparts = ((long)n * n + 255) / 256;
     double* frobp = (double*)ws_get(c, WS_FROBP, (size_t)B * nparts * 8);
     if (!frobp) return RSRR_ENOMEM;
-    if (nep->kind == RSRR_T_SEPARABLE) {
+    if (nep->kind == RSRR_T_SEPARABLE || nep->kind == RSRR_T_SPARSE) {
         double2* coef = (double2*)ws_get(c, WS_COEF, (size_t)nep->J * B * 16);
         if (!coef) return RSRR_ENOMEM;
-        std::vector<double2> cf((size_t)nep->J * B);
-        for (int j = 0; j < nep->J; ++j)
-            for (int k = 0; k < B; ++k) {
-                zd f = term_eval(nep->terms[j], z[k]);
-                cf[(size_t)j * B + k] = make_double2(f.real(), f.imag());
-            }
-        RSRR_HIP(hipMemcpyAsync(coef, cf.data(), cf.size() * 16, hipMemcpyHostToDevice, c->stream));
-        RSRR_HIP(hipStreamSynchronize(c->stream));
-        RSRR_HIP(assemble_separable(c->stream, n, nep->J, (const double2*)nep->A, nep->lda, coef, B, nullptr, 0, 0, T,
-                                    ld, sT, frobp, frob));
+        RSRR_TRY(upload_coef(c, nep, z, B, coef));
+        if (nep->kind == RSRR_T_SEPARABLE) {
+            RSRR_HIP(assemble_separable(c->stream, n, nep->J, (const double2*)nep->A, nep->lda, coef, B, nullptr, 0,
+                                        0, T, ld, sT, frobp, frob));
+        } else {
+            CsrDev d;
+            RSRR_TRY(csr_upload(c, nep, d));
+            RSRR_HIP(assemble_sparse(c->stream, n, nep->J, d.terms, coef, B, nullptr, 0, 0, T, ld, sT, frobp, frob,
+                                     d.bad));
+            RSRR_TRY(csr_check(c, d));
+        }
     } else {
         double2* zdev = (double2*)ws_get(c, WS_Z, (size_t)B * 16);
         if (!zdev) return RSRR_ENOMEM;
@@ -764,6 +818,8 @@ extern "C" rsrr_status rsrr_sample(rsrr_ctx* c, const rsrr_nep* nep, int N, cons
         if (nep->J < 1 || nep->J > 64 || !nep->A || nep->lda < nep->n || !nep->terms) return -2;
     } else if (nep->kind == RSRR_T_HELMHOLTZ) {
         if (!nep->points || !(nep->w > 0)) return -2;
+    } else if (nep->kind == RSRR_T_SPARSE) {
+        if (!csr_nep_ok(nep)) return -2;
     } else {
         return -2;
     }

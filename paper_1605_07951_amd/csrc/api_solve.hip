@@ -27,6 +27,8 @@ extern "C" rsrr_status rsrr_solve(rsrr_ctx* c, const rsrr_nep* nep, int k, const
     if (!nep || nep->n < 1) return -2;
     if (nep->kind == RSRR_T_SEPARABLE && (nep->J < 1 || !nep->A || nep->lda < nep->n || !nep->terms)) return -2;
     if (nep->kind == RSRR_T_HELMHOLTZ && (!nep->points || !(nep->w > 0))) return -2;
+    if (nep->kind == RSRR_T_SPARSE && !csr_nep_ok(nep)) return -2;
+    if (nep->kind != RSRR_T_SEPARABLE && nep->kind != RSRR_T_HELMHOLTZ && nep->kind != RSRR_T_SPARSE) return -2;
     if (k < 1 || k > nep->n) return -3;
     if (!AQp) return -4;
     if (J_eff < 1 || J_eff > 64) return -5;

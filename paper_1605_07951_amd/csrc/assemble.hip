@@ -281,6 +281,60 @@ hipError_t assemble_separable(hipStream_t st, int n, int J, const double2* A, in
     return hipGetLastError();
 }
 
+// Norm partials (and the complex FP32 copy) of dense FP64 matrices formed by
+// another kernel, with the partial layout of the assembly kernels above.
+template <bool O64>
+__global__ __launch_bounds__(AS_NT) void finish_dense_kernel(int n, const double2* __restrict__ T128, int ld128,
+                                                             long s128, float2* __restrict__ T64, int ld64, long s64,
+                                                             double* __restrict__ frob_part, int nparts)
+{
+    __shared__ double red[AS_NT / 64];
+    const int tid = threadIdx.x, k = blockIdx.y;
+    const long nn = (long)n * n;
+    const long e = (long)blockIdx.x * AS_NT + tid;
+    double v = 0.0;
+    if (e < nn) {
+        const int i = (int)(e % n), c = (int)(e / n);
+        const double2 t = T128[(long)k * s128 + i + (long)c * ld128];
+        if (O64) T64[(long)k * s64 + i + (long)c * ld64] = to_c64(t);
+        v = t.x * t.x + t.y * t.y;
+    }
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) {
+        double s = 0.0;
+        for (int w = 0; w < AS_NT / 64; ++w) s += red[w];
+        frob_part[(long)k * nparts + blockIdx.x] = s;
+    }
+}
+
+hipError_t assemble_sparse(hipStream_t st, int n, int J, const CsrTerm* terms, const double2* coef, int B,
+                           float2* T64, int ld64, long s64, double2* T128, int ld128, long s128,
+                           double* frob_part, double* frob, int* bad)
+{
+    if (!T128) return hipErrorInvalidValue;
+    const long nn = (long)n * n;
+    const int nparts = (int)((nn + AS_NT - 1) / AS_NT);
+    hipError_t e = zero_c128(st, n, n, T128, ld128, s128, B);
+    if (e != hipSuccess) return e;
+    e = csr_scatter(st, n, J, terms, coef, B, T128, ld128, s128, bad);
+    if (e != hipSuccess) return e;
+    for (int k0 = 0; k0 < B; k0 += 65535) {
+        const int nb = std::min(65535, B - k0);
+        if (T64)
+            hipLaunchKernelGGL(finish_dense_kernel<true>, dim3(nparts, nb), dim3(AS_NT), 0, st, n,
+                               T128 + (long)k0 * s128, ld128, s128, T64 + (long)k0 * s64, ld64, s64,
+                               frob_part + (long)k0 * nparts, nparts);
+        else
+            hipLaunchKernelGGL(finish_dense_kernel<false>, dim3(nparts, nb), dim3(AS_NT), 0, st, n,
+                               T128 + (long)k0 * s128, ld128, s128, T64, ld64, s64, frob_part + (long)k0 * nparts,
+                               nparts);
+    }
+    hipLaunchKernelGGL(frob_finish_kernel, dim3(B), dim3(64), 0, st, frob_part, nparts, frob);
+    return hipGetLastError();
+}
+
 hipError_t assemble_helmholtz(hipStream_t st, int n, const double* pts, double w, const double2* z, int B,
                               float2* T64, int ld64, long s64, double2* T128, int ld128, long s128,
                               double* frob_part, double* frob)

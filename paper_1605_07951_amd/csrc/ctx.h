@@ -17,7 +17,7 @@ enum WsSlot {
     WS_D64, WS_R, WS_NORM, WS_ACTIVE, WS_Z,
     WS_B0, WS_B1, WS_B2, WS_B3, WS_B4, WS_B5, WS_B6, WS_B7, WS_N1, WS_JAC, WS_TSQ, WS_TSAQ, WS_TSV,
     WS_GMF, WS_GMW, WS_GMK, WS_GMS, WS_GMT, WS_GMI,
-    WS_HS0, WS_HS1, WS_HS2, WS_HSW, WS_HSX, WS_HSD, WS_HSI, WS_LUP,
+    WS_HS0, WS_HS1, WS_HS2, WS_HSW, WS_HSX, WS_HSD, WS_HSI, WS_LUP, WS_CSR,
     WS_COUNT
 };
 
@@ -72,9 +72,23 @@ void* ws_get(rsrr_ctx* c, int s, size_t bytes);
 
 // Assemble T(z_k) in complex FP64 for B host points into T (ld, stride sT);
 // frob (device, B doubles) receives ||T(z_k)||_F.  Uses workspace slots
-// WS_COEF, WS_Z and WS_FROBP.
+// WS_COEF, WS_Z, WS_FROBP (and WS_CSR for a SPARSE nep, whose bounds it
+// checks: -2 when an entry lies out of bounds).
 rsrr_status assemble_c128(rsrr_ctx* c, const rsrr_nep* nep, const zd* z, int B, double2* T, int ld, long sT,
                           double* frob);
+
+// SPARSE nep: descriptor checks on the host (J in 1..64, terms and csr given,
+// every matrix with rowptr, and col and val when nnz > 0).
+bool csr_nep_ok(const rsrr_nep* nep);
+// The J descriptors of a SPARSE nep as a device table in slot WS_CSR, with the
+// device bounds flag (zeroed) after it; csr_check syncs the stream and returns
+// -2 when a kernel found an entry out of bounds since the upload.
+struct CsrDev {
+    rsrr::CsrTerm* terms = nullptr;
+    int* bad = nullptr;
+};
+rsrr_status csr_upload(rsrr_ctx* c, const rsrr_nep* nep, CsrDev& d);
+rsrr_status csr_check(rsrr_ctx* c, const CsrDev& d);
 
 // One-sided Jacobi SVD (api_basis): see jacobi_round.  Returns sweeps or -1.
 int jacobi_svd(rsrr_ctx* c, double2* A, int lda, int m, int m_apply, int p, int max_sweeps, double tol,
@@ -123,4 +137,10 @@ zd term_eval(const rsrr_term& t, zd z);
     do {                                                \
         hipError_t _e = (call);                         \
         if (_e != hipSuccess) return RSRR_EDEVICE;      \
+    } while (0)
+// return the status of a library step unless it is RSRR_OK
+#define RSRR_TRY(call)                                  \
+    do {                                                \
+        rsrr_status _s = (call);                        \
+        if (_s != RSRR_OK) return _s;                   \
     } while (0)

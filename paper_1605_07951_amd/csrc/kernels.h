@@ -131,6 +131,27 @@ hipError_t helmholtz_taylor(hipStream_t st, int n, const double* pts, double w, 
 hipError_t helmholtz_taylor_range(hipStream_t st, int n, const double* pts, double w, double gre, double gim, int p0,
                                   int G, double2* Tp, int ld, long sT);
 
+// A sparse term matrix (compressed sparse rows, device arrays; device table
+// entry): row i holds entries rp[i] .. rp[i+1]-1, entry e at column ci[e].
+struct CsrTerm {
+    const int* rp; const int* ci; const double2* v; int nnz; int pad;
+};
+// T_k = sum_j coef[j B + k] A_j for B points, A_j = terms[j] sparse (J terms):
+// T128 (required) is formed in FP64 (zeroed, then each row's entries summed in
+// by the thread that owns the row), then T64 (may be null) and the norms are
+// taken from it.  *bad (device int) is set when a row range or column index is
+// out of bounds (that entry is skipped).
+hipError_t assemble_sparse(hipStream_t st, int n, int J, const CsrTerm* terms, const double2* coef, int B,
+                           float2* T64, int ld64, long s64, double2* T128, int ld128, long s128,
+                           double* frob_part, double* frob, int* bad);
+// T_k += sum_j coef[j B + k] A_j into dense T_k (sparse.hip)
+hipError_t csr_scatter(hipStream_t st, int n, int J, const CsrTerm* terms, const double2* coef, int B, double2* T,
+                       int ld, long sT, int* bad);
+// Y(:, c) = sum_j coef[j B + c / L] A_j X(:, c) for the C = B L columns (FP64);
+// entries out of bounds are skipped and set *bad.
+hipError_t csr_apply(hipStream_t st, int n, int J, const CsrTerm* terms, const double2* coef, int B, int L,
+                     const double2* X, int ldx, double2* Y, int ldy, int* bad);
+
 // One separable instance of a ragged batch's size bucket (device table entry):
 // terms A (J matrices n x n, ld lda, consecutive), coefficient rows at
 // coef + coff ([J][N], point-fastest), points = bucket matrices koff .. koff+N-1.

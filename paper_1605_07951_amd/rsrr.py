@@ -32,6 +32,7 @@ RSRR_ELIMIT = 9
 RSRR_WARN_MORE = 10
 RSRR_T_SEPARABLE = 0
 RSRR_T_HELMHOLTZ = 1
+RSRR_T_SPARSE = 2
 RSRR_PREC_C128 = 0
 RSRR_PREC_C64_IR = 1
 RSRR_PREC_R32_IR = 2
@@ -56,9 +57,15 @@ class RsrrTerm(C.Structure):
                 ("q", C.c_int)]
 
 
+class RsrrCsr(C.Structure):
+    _fields_ = [("nnz", C.c_int), ("pad", C.c_int), ("rowptr", C.c_void_p), ("col", C.c_void_p),
+                ("val", C.c_void_p)]
+
+
 class RsrrNep(C.Structure):
     _fields_ = [("kind", C.c_int), ("n", C.c_int), ("J", C.c_int), ("A", C.c_void_p), ("lda", C.c_int),
-                ("terms", C.POINTER(RsrrTerm)), ("points", C.c_void_p), ("w", C.c_double)]
+                ("terms", C.POINTER(RsrrTerm)), ("points", C.c_void_p), ("w", C.c_double),
+                ("csr", C.POINTER(RsrrCsr))]
 
 
 class RsrrGmresInfo(C.Structure):
@@ -243,6 +250,22 @@ class DeviceNEP:
             self._terms = terms_array(self.terms)
             self.desc = RsrrNep(RSRR_T_SEPARABLE, self.n, len(nep.A), self.A.data_ptr(), self.n,
                                 C.cast(self._terms, C.POINTER(RsrrTerm)), None, 0.0)
+        elif hasattr(nep, "csr"):
+            self.kind = RSRR_T_SPARSE
+            self.n = int(nep.n)
+            self.mats = []
+            for ip, ix, d in nep.csr:
+                self.mats.append((torch.from_numpy(np.ascontiguousarray(ip, dtype=np.int32)).to(device),
+                                  torch.from_numpy(np.ascontiguousarray(ix, dtype=np.int32)).to(device),
+                                  torch.from_numpy(np.ascontiguousarray(d, dtype=np.complex128)).to(device)))
+            self._csr = (RsrrCsr * len(self.mats))()
+            for j, (ip, ix, d) in enumerate(self.mats):
+                self._csr[j] = RsrrCsr(int(ix.numel()), 0, ip.data_ptr(), ix.data_ptr(), d.data_ptr())
+            self.terms = list(nep.terms)
+            self._terms = terms_array(self.terms)
+            self.desc = RsrrNep(RSRR_T_SPARSE, self.n, len(self.mats), None, self.n,
+                                C.cast(self._terms, C.POINTER(RsrrTerm)), None, 0.0,
+                                C.cast(self._csr, C.POINTER(RsrrCsr)))
         else:
             self.kind = RSRR_T_HELMHOLTZ
             self.n = nep.points.shape[0]

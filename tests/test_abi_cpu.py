@@ -120,7 +120,7 @@ def test_server_structs_match_header(lib):
     src = ('#include <stdio.h>\n#include "rsrr.h"\nint main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", '
            'sizeof(rsrr_request), sizeof(rsrr_result), sizeof(rsrr_server_config), sizeof(rsrr_nep), '
            'sizeof(rsrr_instance), sizeof(rsrr_gmres_info), sizeof(rsrr_options), sizeof(rsrr_solve_info), '
-           'sizeof(rsrr_point_info)); return 0;}\n')
+           'sizeof(rsrr_point_info)); printf("%zu\\n", sizeof(rsrr_csr)); return 0;}\n')
     with tempfile.TemporaryDirectory() as d:
         cpath, exe = os.path.join(d, "sz.c"), os.path.join(d, "sz")
         open(cpath, "w").write(src)
@@ -128,7 +128,8 @@ def test_server_structs_match_header(lib):
         got = [int(x) for x in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
     assert got == [C.sizeof(rsrr.RsrrRequest), C.sizeof(rsrr.RsrrResult), C.sizeof(rsrr.RsrrServerConfig),
                    C.sizeof(rsrr.RsrrNep), C.sizeof(rsrr.RsrrInstance), C.sizeof(rsrr.RsrrGmresInfo),
-                   C.sizeof(rsrr.RsrrOptions), C.sizeof(rsrr.RsrrSolveInfo), C.sizeof(rsrr.RsrrPointInfo)]
+                   C.sizeof(rsrr.RsrrOptions), C.sizeof(rsrr.RsrrSolveInfo), C.sizeof(rsrr.RsrrPointInfo),
+                   C.sizeof(rsrr.RsrrCsr)]
 
 
 def test_options_struct_layout_and_defaults(lib):

@@ -1,0 +1,202 @@
+"""GPU parity of the sparse (compressed sparse row) form of T(z) = sum_j f_j(z) A_j,
+the storage of the finite-element models that Sec. 4.3 and Sec. 6 solve with
+sparse direct and iterative solvers, against the CPU FP64 oracle.
+
+Workload: the delay Laplacian -z I + A0 + 0.5 e^{-z} I on 2D and 3D grids, its
+matrices in CSR (the oracle forms the dense matrices from the same arrays).
+Bars (written below):
+* direct sampling (rsrr_sample, both precisions): every block within 1e-10
+  relative of the oracle's LAPACK solve, FP64 residuals <= 1e-10; the same NEP
+  stored densely gives the same blocks within 1e-11;
+* iterative sampling (rsrr_sample_gmres with the operator applied from the
+  sparse rows): every column's residual, recomputed on the CPU, <= 1.5 tol, and
+  its distance to the oracle's solve <= 2 kappa_2 times that residual + 1e-13;
+* projection: Q^H A_j Q within 1e-12 relative of the oracle's dense product;
+* the whole method on the 3D grid: the four eigenvalues inside the circle equal
+  the closed form mu + W(0.5 e^-mu) within 1e-9, residuals <= 1e-10;
+* a row range or column index out of bounds is reported (-2), not followed.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import pins as P
+from oracle import rsrr_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1605_07951_amd import rsrr
+    rsrr.lib()
+    return rsrr
+
+
+@pytest.fixture(scope="module")
+def ctx(R):
+    return R.rsrr_create(0)
+
+
+def _match(got, ref):
+    return max(np.min(np.abs(ref - g)) / max(1.0, abs(g)) for g in got)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sparse_sample_matches_oracle_and_dense_form(R, ctx, prec):
+    nep = W.delay_laplacian_sparse((16, 16))
+    dense = W.delay_laplacian(16, 16)
+    U = W.probes(nep.n, 4, 5100)
+    z, _ = O.ellipse(-4.0, 0.75, 0.75, 8)
+    prob = O.Problem(nep)
+    S, info, code = R.rsrr_sample(ctx, R.DeviceNEP(nep), z, U, prec=prec)
+    Sd, _, _ = R.rsrr_sample(ctx, R.DeviceNEP(dense), z, U, prec=prec)
+    torch.cuda.synchronize()
+    assert code == R.RSRR_OK
+    n, L = U.shape
+    Sh, Sdh = R.from_colmajor(S, n), R.from_colmajor(Sd, n)
+    for k, zk in enumerate(z):
+        X = Sh[:, k * L:(k + 1) * L]
+        Xo = O.solve_point(prob.T(zk), U)
+        assert np.linalg.norm(X - Xo) <= 1e-10 * np.linalg.norm(Xo), k
+        res = np.linalg.norm(U - prob.T(zk) @ X, axis=0) / np.linalg.norm(U, axis=0)
+        assert res.max() <= 1e-10 and info[k]["resid"] <= 1e-10, (k, res.max())
+        Xd = Sdh[:, k * L:(k + 1) * L]
+        assert np.linalg.norm(X - Xd) <= 1e-11 * np.linalg.norm(Xd), k
+
+
+def test_sparse_gmres_operator_matches_oracle(R, ctx):
+    nep = W.delay_laplacian_sparse((16, 32))
+    U = W.probes(nep.n, 3, 5200)
+    z, _ = R.rsrr_contour(-4.0, 0.75, 0.75, 12)
+    zref, _ = R.rsrr_contour(-4.0, 0.375, 0.375, 4)
+    Ud, _ = R.colmajor(U)
+    tol = 1e-10
+    S, infos, code = R.rsrr_sample_gmres(ctx, R.DeviceNEP(nep), z, Ud, zref, tol=tol)
+    torch.cuda.synchronize()
+    assert code == R.RSRR_OK
+    assert [i["ref"] for i in infos] == [int(np.argmin(np.abs(zref - zk))) for zk in z]
+    prob = O.Problem(nep)
+    n, L = U.shape
+    Sh = R.from_colmajor(S, n)
+    for k, zk in enumerate(z):
+        T = prob.T(zk)
+        X = Sh[:, k * L:(k + 1) * L]
+        res = np.linalg.norm(U - T @ X, axis=0) / np.linalg.norm(U, axis=0)
+        assert infos[k]["converged"] == 1 and res.max() <= 1.5 * tol, (k, res.max())
+        assert abs(infos[k]["resid"] - res.max()) <= 0.05 * tol + 0.05 * res.max()
+        Xo = O.solve_point(T, U)
+        err = np.linalg.norm(X - Xo, axis=0) / np.linalg.norm(Xo, axis=0)
+        assert np.all(err <= 2.0 * np.linalg.cond(T) * res + 1e-13), k
+
+
+def test_sparse_gmres_agrees_with_dense_operator(R, ctx):
+    """The same NEP through the dense separable operator: both iterates meet the same bar and
+    agree within the two residuals' reach."""
+    sp = W.delay_laplacian_sparse((12, 10))
+    de = W.delay_laplacian(12, 10)
+    U = W.probes(sp.n, 2, 5300)
+    z, _ = R.rsrr_contour(-4.0, 0.75, 0.75, 6)
+    Ud, _ = R.colmajor(U)
+    S1, i1, c1 = R.rsrr_sample_gmres(ctx, R.DeviceNEP(sp), z, Ud, [-4.0])
+    S2, i2, c2 = R.rsrr_sample_gmres(ctx, R.DeviceNEP(de), z, Ud, [-4.0])
+    torch.cuda.synchronize()
+    assert c1 == c2 == R.RSRR_OK
+    a, b = R.from_colmajor(S1, sp.n), R.from_colmajor(S2, sp.n)
+    prob = O.Problem(sp)
+    kap = max(np.linalg.cond(prob.T(zk)) for zk in z)
+    assert np.linalg.norm(a - b) <= 4.0 * kap * 1e-10 * np.linalg.norm(b)
+    assert all(abs(x["iters"] - y["iters"]) <= 1 for x, y in zip(i1, i2))
+
+
+def test_sparse_project_matches_oracle(R, ctx):
+    nep = W.delay_laplacian_sparse((6, 5, 4))
+    n, k = nep.n, 37
+    rng = np.random.default_rng(5400)
+    Qh = np.linalg.qr(W.complex_gaussian(rng, (n, k)))[0]
+    Qd, _ = R.colmajor(Qh)
+    AQ, terms = R.rsrr_project(ctx, R.DeviceNEP(nep), Qd, k, -4.0, 0.75)
+    torch.cuda.synchronize()
+    assert len(terms) == 3
+    prob = O.Problem(nep)
+    ref = O.project(prob, Qh).AQ
+    for j in range(3):
+        got = AQ[j].cpu().numpy().T
+        assert np.linalg.norm(got - ref[j]) <= 1e-12 * np.linalg.norm(ref[j]), j
+
+
+def test_sparse_method_3d_lambert_w(R, ctx):
+    nep, C, U = W.cfg_sparse(dims=(8, 8, 8), N=48, L=16, seed=5500)
+    dn = R.DeviceNEP(nep)
+    z, _ = R.rsrr_contour(C.gamma, C.a, C.b, C.N)
+    S, info, code = R.rsrr_sample(ctx, dn, z, U, prec=1)
+    assert code == R.RSRR_OK
+    Q, k, _ = R.rsrr_basis(ctx, S, nep.n, 1e-14)
+    AQ, terms = R.rsrr_project(ctx, dn, Q, k, C.gamma, max(C.a, C.b))
+    out = R.rsrr_solve(ctx, dn, Q, k, AQ, terms, C.gamma, C.a, C.b)
+    torch.cuda.synchronize()
+    ex = P.delay_eigs(W.laplacian_modes_nd((8, 8, 8)))
+    exin = ex[O.level(ex, C.gamma, C.a, C.b) < 1]
+    ins = O.level(out["lam"], C.gamma, C.a, C.b) < 0.98
+    assert exin.size == 4 and ins.sum() == 4
+    assert _match(out["lam"][ins], exin) < 1e-9 and _match(exin, out["lam"][ins]) < 1e-9
+    assert out["resid"][ins].max() <= 1e-10
+    prob = O.Problem(nep)
+    for i in np.where(ins)[0]:
+        assert O.residual(prob, out["lam"][i], out["V"][:, i]) <= 1e-10
+
+
+@pytest.mark.parametrize("fault", ["column", "rowptr"])
+def test_sparse_out_of_bounds_entry_is_reported(R, ctx, fault):
+    """A column index of n, or a last row pointer past nnz: the kernels skip the entry (their
+    own bounds checks), raise the flag, and the call returns -2."""
+    nep = W.delay_laplacian_sparse((8, 8))
+    ip, ix, d = (a.copy() for a in nep.csr[0])
+    if fault == "column":
+        ix[5] = nep.n
+    else:
+        ip[-1] = ix.size + 3
+    bad = W.SparseNEP(nep.name, nep.n, [(ip, ix, d)] + nep.csr[1:], nep.terms)
+    U = W.probes(nep.n, 2, 5600)
+    z, _ = O.ellipse(-4.0, 0.75, 0.75, 3)
+    _, _, code = R.rsrr_sample(ctx, R.DeviceNEP(bad), z, U, prec=1, ok=(-2,))
+    torch.cuda.synchronize()
+    assert code == -2
+    Ud, _ = R.colmajor(U)
+    _, _, code = R.rsrr_sample_gmres(ctx, R.DeviceNEP(bad), z, Ud, [-4.0], ok=(-2,))
+    torch.cuda.synchronize()
+    assert code == -2
+    # the context still works afterwards
+    S, info, code = R.rsrr_sample(ctx, R.DeviceNEP(nep), z, U, prec=1)
+    torch.cuda.synchronize()
+    assert code == R.RSRR_OK and max(i["resid"] for i in info) <= 1e-10
+
+
+def test_sparse_refused_where_not_supported(R, ctx):
+    """Descriptor checks on the host: a missing csr table, a matrix without rows, and the batched
+    call (which takes dense or Helmholtz instances only)."""
+    nep = W.delay_laplacian_sparse((6, 6))
+    dn = R.DeviceNEP(nep)
+    U = W.probes(nep.n, 2, 5700)
+    z, _ = O.ellipse(-4.0, 0.75, 0.75, 3)
+    saved = dn.desc.csr
+    dn.desc.csr = C.cast(None, C.POINTER(R.RsrrCsr))
+    _, _, code = R.rsrr_sample(ctx, dn, z, U, prec=1, ok=(-2,))
+    assert code == -2
+    dn.desc.csr = saved
+    row0 = dn._csr[1].rowptr
+    dn._csr[1].rowptr = None
+    _, _, code = R.rsrr_sample(ctx, dn, z, U, prec=1, ok=(-2,))
+    assert code == -2
+    dn._csr[1].rowptr = row0
+    _, _, code = R.rsrr_sample(ctx, dn, z, U, prec=2, ok=(-2,))
+    assert code == -2
+    item = R.BatchItem(dn, z, W.probes(nep.n, 2, 5701))
+    _, code = R.rsrr_sample_batched(ctx, [item], ok=(-3,))
+    assert code == -3

@@ -493,3 +493,59 @@ def test_real_sampling_on_chebyshev_points_finds_the_string_eigenvalues():
     lam = r["lam"]
     sel = (lam.real >= lo) & (lam.real <= hi) & (r["level"] < 1) & (r["res"] < 1e-10)
     assert int(sel.sum()) == g["count"]
+
+
+# -------------------------------------------------------- sparse storage ----
+
+def _random_csr(seed, n=40):
+    """A CSR matrix with unsorted columns and repeated (row, column) pairs."""
+    rng = np.random.default_rng(seed)
+    counts = rng.integers(0, 8, n)
+    indptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    indices = rng.integers(0, n // 4, indptr[-1]).astype(np.int32)
+    data = W.complex_gaussian(rng, indptr[-1])
+    return indptr, indices, data
+
+
+def test_csr_dense_sums_repeated_entries_like_scipy():
+    """csr_dense against SciPy's own CSR-to-dense conversion (which sums repeats)."""
+    from scipy import sparse
+    ip, ix, d = _random_csr(77)
+    n = ip.size - 1
+    rows = np.repeat(np.arange(n), np.diff(ip))
+    assert np.unique(np.stack([rows, ix]), axis=1).shape[1] < ix.size  # repeats are present
+    ref = sparse.csr_matrix((d, ix, ip), shape=(n, n)).toarray()
+    got = O.csr_dense(ip, ix, d, n)
+    assert np.abs(got - ref).max() <= 1e-15 * np.abs(ref).max()
+    # a slip: later repeats overwrite instead of adding
+    slip = np.zeros((n, n), dtype=np.complex128)
+    for i in range(n):
+        for e in range(ip[i], ip[i + 1]):
+            slip[i, ix[e]] = d[e]
+    assert np.abs(slip - ref).max() > 1e-3
+
+
+def test_sparse_delay_nep_is_the_dense_one():
+    """The CSR generators give the matrices of the dense delay NEP (SciPy conversion), and the
+    oracle's T(z) of the two forms agree."""
+    from scipy import sparse
+    sp, de = W.delay_laplacian_sparse((16, 32)), W.delay_laplacian(16, 32)
+    for (ip, ix, d), A in zip(sp.csr, de.A):
+        B = sparse.csr_matrix((d, ix, ip), shape=A.shape).toarray()
+        assert np.abs(B - A).max() <= 1e-12 * np.abs(A).max()
+    ps, pd = O.Problem(sp), O.Problem(de)
+    for z in (-4.2 + 0.3j, -3.5 - 0.1j):
+        assert np.abs(ps.T(z) - pd.T(z)).max() <= 1e-12 * np.abs(pd.T(z)).max()
+        assert np.abs(ps.dT(z) - pd.dT(z)).max() <= 1e-12 * np.abs(pd.dT(z)).max()
+
+
+def test_laplacian_3d_csr_spectrum_closed_form():
+    """7-point Dirichlet Laplacian on a 6 x 5 x 4 grid: symmetric, with the eigenvalues
+    sum_d -(4/h_d^2) sin^2(p pi h_d / 2)."""
+    from scipy import sparse
+    ip, ix, d = W.laplacian_csr((6, 5, 4))
+    A = sparse.csr_matrix((d, ix, ip), shape=(120, 120)).toarray().real
+    assert np.array_equal(A, A.T)
+    ex = np.sort(W.laplacian_modes_nd((6, 5, 4)))
+    assert np.abs(np.linalg.eigvalsh(A) - ex).max() <= 1e-10 * np.abs(ex).max()
+    assert np.all(np.diff(ip) <= 7) and np.all(np.diff(ip) >= 4)

@@ -69,6 +69,25 @@ class HelmholtzNEP:
         return self.points.shape[0]
 
 
+@dataclass
+class SparseNEP:
+    """T(z) = sum_j f_j(z) A_j with every A_j in compressed sparse row form.
+
+    ``csr[j] = (indptr, indices, data)``: int32 row pointers (n+1), int32
+    column indices and complex128 values (nnz each); row i holds the entries
+    indptr[i] .. indptr[i+1]-1.
+    """
+    name: str
+    n: int
+    csr: list
+    terms: list
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def J(self):
+        return len(self.csr)
+
+
 def complex_gaussian(rng, shape):
     """(N(0,1) + i N(0,1)) / sqrt(2) entries."""
     return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / math.sqrt(2.0)
@@ -148,6 +167,70 @@ def laplacian_modes(nx, ny):
     mx = -(4.0 / hx**2) * np.sin(p * math.pi * hx / 2) ** 2
     my = -(4.0 / hy**2) * np.sin(q * math.pi * hy / 2) ** 2
     return (my[:, None] + mx[None, :]).ravel()
+
+
+def laplacian_csr(dims):
+    """Dirichlet Laplacian on the interior grid of the unit square (2 dims, 5 points)
+    or cube (3 dims, 7 points), 1/h^2 scaled, in CSR.
+
+    Lexicographic order with the first dimension fastest (the order of
+    ``dirichlet_laplacian_2d``); each row lists its entries in increasing column
+    order.  Returns (indptr, indices, data) with complex128 data.
+    """
+    dims = tuple(int(d) for d in dims)
+    h2 = [1.0 / (d + 1) ** 2 for d in dims]
+    strides = [1]
+    for d in dims[:-1]:
+        strides.append(strides[-1] * d)
+    n = int(np.prod(dims))
+    indptr = np.zeros(n + 1, dtype=np.int32)
+    indices, data = [], []
+    diag = -2.0 * sum(1.0 / h for h in h2)
+    for i in range(n):
+        rem, coord = i, []
+        for d in dims:
+            coord.append(rem % d)
+            rem //= d
+        row = [(i, diag)]
+        for a, d in enumerate(dims):
+            if coord[a] > 0:
+                row.append((i - strides[a], 1.0 / h2[a]))
+            if coord[a] < d - 1:
+                row.append((i + strides[a], 1.0 / h2[a]))
+        row.sort()
+        indices.extend(c for c, _ in row)
+        data.extend(v for _, v in row)
+        indptr[i + 1] = len(indices)
+    return indptr, np.asarray(indices, dtype=np.int32), np.asarray(data, dtype=np.complex128)
+
+
+def identity_csr(n, scale=1.0):
+    return (np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32),
+            np.full(n, scale, dtype=np.complex128))
+
+
+def delay_laplacian_sparse(dims, a1=0.5):
+    """The delay NEP of ``delay_laplacian`` (-z I + A0 + a1 e^{-z} I) on a 2D or 3D
+    grid, its three matrices in CSR (the storage of a finite-element model)."""
+    dims = tuple(int(d) for d in dims)
+    n = int(np.prod(dims))
+    return SparseNEP(
+        name="delay_lap_sparse_" + "x".join(str(d) for d in dims),
+        n=n,
+        csr=[laplacian_csr(dims), identity_csr(n), identity_csr(n, a1)],
+        terms=[term(1.0, 0), term(-1.0, 1), term(1.0, 0, tau=1.0)],
+        extra={"dims": dims, "a1": a1},
+    )
+
+
+def laplacian_modes_nd(dims):
+    """Eigenvalues of the scaled Dirichlet Laplacian on a grid of any dimension (closed form)."""
+    vals = np.zeros(1)
+    for d in dims:
+        h = 1.0 / (d + 1)
+        m = -(4.0 / h**2) * np.sin(np.arange(1, d + 1) * math.pi * h / 2) ** 2
+        vals = (vals[:, None] + m[None, :]).ravel()
+    return vals
 
 
 def fibonacci_sphere(n):
@@ -230,6 +313,15 @@ def cfg_delay(nx=32, ny=None, N=48, L=32, seed=1000, parity=True):
     U = probes(nep.n, L, seed)
     C = Contour(-4.0 + 0j, 0.75, 0.75, N) if parity else Contour(-20.0 + 0j, 15.0, 15.0, N)
     return nep, C, U
+
+
+def cfg_sparse(dims=(20, 20, 20), N=32, L=8, seed=5000):
+    """Sparse delay NEP on a 3D grid (n = 8000 at 20^3), circle (-4, 0.75): the
+    eigenvalues mu + W(a1 e^-mu) of the four lowest modes lie inside (one simple,
+    one triple)."""
+    nep = delay_laplacian_sparse(dims)
+    U = probes(nep.n, L, seed)
+    return nep, Contour(-4.0 + 0j, 0.75, 0.75, N), U
 
 
 def cfg_helmholtz(n=4096, N=64, L=64, seed=2000):
