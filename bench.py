@@ -62,7 +62,8 @@ def parse():
     ap.add_argument("--K", type=str, default="4,16", help="moments: moment counts K to compare")
     ap.add_argument("--real-nep", default="delay", choices=["delay", "string"], help="real: the real NEP")
     ap.add_argument("--interval", type=str, default=None, help="real: sampling interval lo,hi")
-    ap.add_argument("--gmres-nep", default="helmholtz", choices=["helmholtz", "delay"], help="gmres: the NEP")
+    ap.add_argument("--gmres-nep", default="helmholtz", choices=["helmholtz", "delay", "sparse"],
+                    help="gmres: the NEP (sparse: the delay Laplacian on a 3D grid, matrices in CSR)")
     ap.add_argument("--nref", type=int, default=1, help="gmres: reference points (factorisations)")
     ap.add_argument("--restart", type=int, default=32, help="gmres: restart cycle length")
     ap.add_argument("--tol", type=float, default=1e-10, help="gmres: relative residual per column")
@@ -606,7 +607,10 @@ def run_gmres(args):
     Default: the Helmholtz sphere NEP (n=4096) on the headline ellipse with N=64 points and L=2
     probes (the probe count of the paper's large boundary-element runs), one reference at the
     contour centre, tol 1e-10.  --gmres-nep delay: the delay Laplacian (64x64 grid) on its
-    parity circle (centre -4, radius 0.75).  The direct mixed-precision path runs on the same inputs for comparison.
+    parity circle (centre -4, radius 0.75).  --gmres-nep sparse: the delay Laplacian on a 3D grid
+    (20^3, n = 8000) with its matrices in CSR, the operator applied from the sparse rows; the same
+    NEP with dense matrices (the dense separable operator) runs beside it.  The direct
+    mixed-precision path runs on the same inputs for comparison.
     value = resolvent solves/s (points per second) of the GMRES path."""
     import torch
     import workloads as W
@@ -617,6 +621,10 @@ def run_gmres(args):
     n = args.n or 4096
     if args.gmres_nep == "helmholtz":
         nep, C, Uh = W.cfg_helmholtz(n=n, N=N, L=L)
+    elif args.gmres_nep == "sparse":
+        side = int(round((args.n or 8000) ** (1.0 / 3.0)))
+        nep, C, Uh = W.cfg_sparse(dims=(side, side, side), N=N, L=L)
+        n = nep.n
     else:
         nep, C, Uh = W.cfg_delay(nx=int(round(math.sqrt(n))), N=N, L=L)
         n = nep.n
@@ -643,7 +651,19 @@ def run_gmres(args):
     cycles = max(i["restarts"] for i in info) + 1
     applies = max(iters) + cycles           # Arnoldi steps in lockstep + one true residual per cycle
     op_ms = tm[1] / applies
-    if not hasattr(nep, "A") and info[0]["matrix_free"]:
+    sparse = hasattr(nep, "csr")
+    if sparse:
+        # each apply reads every term's rows once (row pointers, columns, values) and the n x N L
+        # block in, and writes the block out
+        csr_bytes = sum(4.0 * ip.size + 20.0 * ix.size for ip, ix, _ in nep.csr)
+        bytes_apply = csr_bytes + 2 * 16.0 * n * N * L
+        achieved = bytes_apply / (op_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": "operator sum_j f_j A_j Z from the sparse rows, FP64 (csr_apply_kernel)",
+                "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                "frac": round(achieved / 8000.0, 4), "traffic": None,
+                "bytes_per_apply": bytes_apply, "avg_apply_ms": round(op_ms, 4), "applies": applies,
+                "nnz": int(sum(ix.size for _, ix, _ in nep.csr))}
+    elif not hasattr(nep, "A") and info[0]["matrix_free"]:
         # entries generated inside every application: transcendental FP64 work, no stored matrices
         roof = None
     elif not hasattr(nep, "A"):
@@ -663,7 +683,28 @@ def run_gmres(args):
                 "frac": round(achieved / PEAK_FP64_MFMA_TFLOPS, 4), "traffic": None,
                 "flops_per_apply": flops_apply, "avg_apply_ms": round(op_ms, 4), "applies": applies}
     mfree = None
-    if not hasattr(nep, "A"):
+    dense_op = None
+    if sparse and not args.no_plain:
+        # the same NEP with its matrices stored densely: the dense separable operator
+        from scipy import sparse as sps
+        dn = R.DeviceNEP(W.SeparableNEP(nep.name + "_dense",
+                                        [sps.csr_matrix((d, ix, ip), shape=(n, n)).toarray() for ip, ix, d in nep.csr],
+                                        nep.terms))
+        R.rsrr_sample_gmres(ctx, dn, z, U, zref, tol=args.tol, restart=args.restart, S=S)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, dinfo, _ = R.rsrr_sample_gmres(ctx, dn, z, U, zref, tol=args.tol, restart=args.restart, S=S)
+        torch.cuda.synchronize()
+        dg = (time.perf_counter() - t0) / args.steps
+        tmd = ctx.raw_timings()
+        dense_op = {"solves_per_s": round(N / dg, 3), "ms_per_step": round(1e3 * dg, 3),
+                    "operator_ms": round(tmd[1], 3),
+                    "iters_max": max(i["iters"] for i in dinfo),
+                    "resid_max": max(i["resid"] for i in dinfo), "converged": all(i["converged"] for i in dinfo)}
+        del dn
+        torch.cuda.empty_cache()
+    if not hasattr(nep, "A") and not sparse:
         # the same solves with the matrix entries generated inside every operator application
         R.rsrr_sample_gmres(ctx, dnep, z, U, zref, tol=args.tol, restart=args.restart, S=S,
                             flags=R.RSRR_GMRES_MATRIX_FREE)
@@ -710,6 +751,7 @@ def run_gmres(args):
         "roofline": roof,
         "gmres": gres,
         "gmres_matrix_free": mfree,
+        "gmres_dense_operator": dense_op,
         "direct_mixed": direct,
         "gmres_over_direct": round(gres["solves_per_s"] / direct["solves_per_s"], 3) if direct else None,
     }
