@@ -854,8 +854,11 @@ __global__ __launch_bounds__(ZG_NT, 2) void zgemm_mfma_kernel(
             }
         }
 
-    double2 ra[4], rb[4];
-    auto gload = [&](int k0) {
+    // global tiles are fetched two K-tiles ahead into one of two register sets
+    // (tile t into set t & 1), so a fetch has two tiles of matrix-core work to
+    // arrive in before it is stored to LDS
+    double2 ra0[4], rb0[4], ra1[4], rb1[4];
+    auto gload = [&](int k0, double2 (&ra)[4], double2 (&rb)[4]) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             int p = tid + ZG_NT * q;   // 0..1023
@@ -883,7 +886,7 @@ __global__ __launch_bounds__(ZG_NT, 2) void zgemm_mfma_kernel(
             rb[q] = w;
         }
     };
-    auto sstore = [&](int buf) {
+    auto sstore = [&](int buf, const double2 (&ra)[4], const double2 (&rb)[4]) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             int p = tid + ZG_NT * q;
@@ -893,16 +896,7 @@ __global__ __launch_bounds__(ZG_NT, 2) void zgemm_mfma_kernel(
             else Bs[buf][p >> 6][p & 63] = rb[q];
         }
     };
-
-    const int nst = (K + ZG_KT - 1) / ZG_KT;
-    if (nst > 0) {
-        gload(0);
-        sstore(0);
-        __syncthreads();
-    }
-    for (int s = 0; s < nst; ++s) {
-        const int buf = s & 1;
-        if (s + 1 < nst) gload((s + 1) * ZG_KT);
+    auto compute = [&](int buf) {
 #pragma unroll 2
         for (int kk = 0; kk < ZG_KT; kk += 2) {
             double a[2], br[2], bi[2];
@@ -925,7 +919,27 @@ __global__ __launch_bounds__(ZG_NT, 2) void zgemm_mfma_kernel(
                     accI[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(bi[y], a[x], accI[x][y], 0, 0, 0);
                 }
         }
-        if (s + 1 < nst) sstore(buf ^ 1);
+    };
+
+    const int nst = (K + ZG_KT - 1) / ZG_KT;
+    if (nst > 0) {
+        gload(0, ra0, rb0);
+        sstore(0, ra0, rb0);
+        if (nst > 1) gload(ZG_KT, ra1, rb1);
+        __syncthreads();
+    }
+    // tiles in pairs so that the register set of every step is fixed at compile time
+    for (int s = 0; s < nst; s += 2) {
+        // even tile s: LDS buffer 0; tile s+1 waits in set 1, tile s+2 is fetched into set 0
+        if (s + 2 < nst) gload((s + 2) * ZG_KT, ra0, rb0);
+        compute(0);
+        if (s + 1 < nst) sstore(1, ra1, rb1);
+        __syncthreads();
+        if (s + 1 >= nst) break;
+        // odd tile s+1: LDS buffer 1; tile s+2 waits in set 0, tile s+3 is fetched into set 1
+        if (s + 3 < nst) gload((s + 3) * ZG_KT, ra1, rb1);
+        compute(1);
+        if (s + 2 < nst) sstore(0, ra0, rb0);
         __syncthreads();
     }
 
