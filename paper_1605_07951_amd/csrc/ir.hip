@@ -181,21 +181,32 @@ __global__ __launch_bounds__(EW_NT) void scale_cols_kernel(int n, int m, double2
 // ---- ragged-batch helpers ----
 
 // Identity outside the leading nk x nk block of each P x P matrix (both copies
-// may be null); the leading block is written by the assembly afterwards.
+// may be null); the leading block is written by the assembly afterwards.  Only
+// the padding is visited (grid-stride): with p = P - n, element e < n p lies in
+// column e / p of the rows below the block (zero), the rest in the last p
+// columns (identity).
 template <typename C>
 __global__ __launch_bounds__(EW_NT) void pad_identity_kernel(C* __restrict__ T, int ld, long sT, int P,
                                                               const int* __restrict__ nk)
 {
     const int k = blockIdx.y;
-    const long e = (long)blockIdx.x * EW_NT + threadIdx.x;
-    if (e >= (long)P * P) return;
-    const int i = (int)(e % P), j = (int)(e / P);
-    const int n = nk[k];
-    if (i < n && j < n) return;
-    C v;
-    v.x = (i == j) ? 1 : 0;
-    v.y = 0;
-    T[k * sT + i + (long)j * ld] = v;
+    const int n = nk[k], p = P - n;
+    const long total = p > 0 ? (long)p * (n + P) : 0;
+    for (long e = (long)blockIdx.x * EW_NT + threadIdx.x; e < total; e += (long)gridDim.x * EW_NT) {
+        int i, j;
+        if (e < (long)n * p) {
+            j = (int)(e / p);
+            i = n + (int)(e % p);
+        } else {
+            const long f = e - (long)n * p;
+            j = n + (int)(f / P);
+            i = (int)(f % P);
+        }
+        C v;
+        v.x = (i == j) ? 1 : 0;
+        v.y = 0;
+        T[k * sT + i + (long)j * ld] = v;
+    }
 }
 
 // Fill n x m (c128) blocks with zeros (graph-safe replacement of a memset).
@@ -400,9 +411,11 @@ hipError_t copy_out_group(hipStream_t st, const RhsInstance* ins, int nins, int 
 
 hipError_t pad_identity(hipStream_t st, float2* T64, double2* T128, int ld, long sT, int P, const int* nk, int M)
 {
-    if (T64) hipLaunchKernelGGL(pad_identity_kernel<float2>, ew_grid((long)P * P, M), dim3(EW_NT), 0, st, T64, ld, sT,
+    // one thread per padding element of a matrix of a 64-wide size bucket (P - n < 64)
+    const long cover = std::min((long)P * P, 128L * P);
+    if (T64) hipLaunchKernelGGL(pad_identity_kernel<float2>, ew_grid(cover, M), dim3(EW_NT), 0, st, T64, ld, sT,
                                 P, nk);
-    if (T128) hipLaunchKernelGGL(pad_identity_kernel<double2>, ew_grid((long)P * P, M), dim3(EW_NT), 0, st, T128, ld,
+    if (T128) hipLaunchKernelGGL(pad_identity_kernel<double2>, ew_grid(cover, M), dim3(EW_NT), 0, st, T128, ld,
                                  sT, P, nk);
     return hipGetLastError();
 }
