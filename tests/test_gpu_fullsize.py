@@ -155,6 +155,39 @@ def test_gmres_full_size_sampled_points(R, ctx):
         assert np.all(err <= 2.0 * res / rcond + 1e-13), (k, err, res, 1 / rcond)
 
 
+def test_sparse_gmres_full_size_sampled_points(R, ctx):
+    """The sparse workload bench.py times (--workload gmres --gmres-nep sparse --N 32 --L 8): the
+    delay Laplacian on a 20^3 grid (n = 8000) with its matrices in CSR, 32 points on the circle
+    (-4, 0.75), 8 probes, one reference factorisation at the centre, the operator applied from
+    the sparse rows.  Every point converged; at sampled points the residual recomputed with the
+    oracle's dense T is <= 1.5 tol and the distance to the oracle's solve is within 2 kappa
+    times it (T is complex symmetric: kappa_2 <= kappa_1, LAPACK's estimate)."""
+    import scipy.linalg as sl
+    from scipy.linalg import lapack
+    nep, C, U = W.cfg_sparse(dims=(20, 20, 20), N=32, L=8)
+    z, _ = R.rsrr_contour(C.gamma, C.a, C.b, C.N)
+    Ud, _ = R.colmajor(U)
+    S, info, code = R.rsrr_sample_gmres(ctx, R.DeviceNEP(nep), z, Ud, [C.gamma], tol=1e-10, restart=32)
+    torch.cuda.synchronize()
+    assert code == R.RSRR_OK
+    assert all(i["converged"] == 1 and i["resid"] <= 1e-10 for i in info)
+    prob = O.Problem(nep)
+    n, L = U.shape
+    Sh = R.from_colmajor(S, n)
+    for k in (3, 20):
+        T = prob.T(z[k])
+        assert np.array_equal(T, T.T)
+        X = Sh[:, k * L:(k + 1) * L]
+        res = np.linalg.norm(U - T @ X, axis=0) / np.linalg.norm(U, axis=0)
+        assert res.max() <= 1.5e-10
+        lu, piv = sl.lu_factor(T)
+        Xo = sl.lu_solve((lu, piv), U)
+        rcond, inf = lapack.zgecon(lu, np.linalg.norm(T, 1), norm="1")
+        assert inf == 0
+        err = np.linalg.norm(X - Xo, axis=0) / np.linalg.norm(Xo, axis=0)
+        assert np.all(err <= 2.0 * res / rcond + 1e-13), (k, err, res, 1 / rcond)
+
+
 def _clusters(lo, tol_rel=1e-3):
     out, seen = [], np.zeros(lo.size, bool)
     for i in range(lo.size):
