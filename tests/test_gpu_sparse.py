@@ -14,7 +14,9 @@ Bars (written below):
 * projection: Q^H A_j Q within 1e-12 relative of the oracle's dense product;
 * the whole method on the 3D grid: the four eigenvalues inside the circle equal
   the closed form mu + W(0.5 e^-mu) within 1e-9, residuals <= 1e-10;
-* a row range or column index out of bounds is reported (-2), not followed.
+* a row range or column index out of bounds is reported (-2), not followed;
+* two-stage sampling on the CSR NEP equals the dense form: added points within 1e-8,
+  eigenvalues inside within 1e-9 of each other and of the closed form.
 """
 import ctypes as C
 
@@ -200,3 +202,23 @@ def test_sparse_refused_where_not_supported(R, ctx):
     item = R.BatchItem(dn, z, W.probes(nep.n, 2, 5701))
     _, code = R.rsrr_sample_batched(ctx, [item], ok=(-3,))
     assert code == -3
+
+
+def test_sparse_two_stage_equals_dense_form(R, ctx):
+    """rsrr_two_stage on the CSR NEP and on the same NEP stored densely: the same added points
+    (1e-8), the same eigenvalues inside the circle (1e-9), equal to mu + W(0.5 e^-mu) (1e-9)."""
+    sp, de = W.delay_laplacian_sparse((10, 10)), W.delay_laplacian(10, 10)
+    U = W.probes(sp.n, 8, 5800)
+    outs = [R.rsrr_two_stage(ctx, R.DeviceNEP(nep), -4.0, 0.75, 0.75, 6, U, prec=1, NQ=300, max_new=32,
+                             max_eigs=64) for nep in (sp, de)]
+    torch.cuda.synchronize()
+    a, b = outs
+    assert a["n_new"] == b["n_new"] > 0
+    assert _match(a["z_new"], b["z_new"]) < 1e-8 and _match(b["z_new"], a["z_new"]) < 1e-8
+    ins = [O.level(o["lam"], -4.0, 0.75, 0.75) < 0.98 for o in outs]
+    assert ins[0].sum() == ins[1].sum() == 3
+    la, lb = a["lam"][ins[0]], b["lam"][ins[1]]
+    assert _match(la, lb) < 1e-9 and _match(lb, la) < 1e-9
+    ex = P.delay_eigs(W.laplacian_modes_nd((10, 10)))
+    assert _match(la, ex) < 1e-9
+    assert a["resid"][ins[0]].max() <= 1e-10
