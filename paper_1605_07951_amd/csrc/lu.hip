@@ -376,9 +376,10 @@ __global__ __launch_bounds__(TS_NT) void perm_trsm_kernel(
 
 // ----------------------------------------------------------------------------
 // Row permutation of a block of columns without a solve (LDS only for the
-// permutation).  Column by column, 2*jb threads gather the affected rows and
-// then scatter them; rows c0..c0+jb-1 go to T (jb x ncols, ldt) when T is
-// given, otherwise back into X.  perm == nullptr: identity (copy the block
+// permutation).  A workgroup takes PR_TC columns: 2*jb threads gather the
+// affected rows of all of them (the loads in flight together), then scatter
+// them; rows c0..c0+jb-1 go to T (jb x ncols, ldt) when T is given, otherwise
+// back into X.  perm == nullptr: identity (copy the block
 // rows to T).
 // ----------------------------------------------------------------------------
 constexpr int PR_TC = 32;
@@ -399,17 +400,26 @@ __global__ __launch_bounds__(2 * MAX_NB) void perm_rows_kernel(
         if (perm) e = perm[(long)b * sPerm + s];
         else if (s < jb) e = make_int2(c0 + s, c0 + s);
     }
+    // every column's source row first (all loads in flight), one barrier, then the stores
+    const int cbase = blockIdx.x * PR_TC;
+    C v[PR_TC];
+#pragma unroll
     for (int cc = 0; cc < PR_TC; ++cc) {
-        const int gcol = blockIdx.x * PR_TC + cc;
-        if (gcol >= ncols) break;
-        C v = czero<C>();
-        if (e.y >= 0) v = Xb[e.y + (long)gcol * ldx];
-        __syncthreads();
-        if (s < jb) {
-            if (Tb) Tb[s + (long)gcol * ldt] = v;
-            else Xb[(c0 + s) + (long)gcol * ldx] = v;
-        } else if (e.x >= 0) {
-            Xb[e.x + (long)gcol * ldx] = v;
+        const int gcol = cbase + cc;
+        v[cc] = czero<C>();
+        if (gcol < ncols && e.y >= 0) v[cc] = Xb[e.y + (long)gcol * ldx];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int cc = 0; cc < PR_TC; ++cc) {
+        const int gcol = cbase + cc;
+        if (gcol < ncols) {
+            if (s < jb) {
+                if (Tb) Tb[s + (long)gcol * ldt] = v[cc];
+                else Xb[(c0 + s) + (long)gcol * ldx] = v[cc];
+            } else if (e.x >= 0) {
+                Xb[e.x + (long)gcol * ldx] = v[cc];
+            }
         }
     }
 }
