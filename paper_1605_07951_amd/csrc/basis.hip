@@ -449,6 +449,7 @@ static hipError_t project_out(hipStream_t st, double2* Y, int ld, int n, int j0,
 // diagonal apart.
 constexpr int QB = 64;        // columns per BCGS2 block
 constexpr int CH_NT = 256;
+constexpr int CH_EPT = (QB * (QB + 1) / 2 + CH_NT - 1) / CH_NT;   // triangle entries per thread
 
 __global__ __launch_bounds__(CH_NT) void block_chol_kernel(const double2* __restrict__ Gin, int bw,
                                                             const double* __restrict__ ref, double thr, double tau,
@@ -460,9 +461,18 @@ __global__ __launch_bounds__(CH_NT) void block_chol_kernel(const double2* __rest
     __shared__ int keep[QB];
     __shared__ int s_cut;
     const int tid = threadIdx.x;
-    for (int e = tid; e < bw * bw; e += CH_NT) {
-        const int i = e % bw, j = e / bw;
-        if (i <= j) A[i][j] = Gin[i + (long)j * bw];
+    // entries of the upper triangle owned by this thread: t = j (j + 1) / 2 + i (i <= j),
+    // t = tid, tid + CH_NT, ...; (-1, -1) past the end
+    int2 own[CH_EPT];
+#pragma unroll
+    for (int q = 0; q < CH_EPT; ++q) {
+        const int t = tid + CH_NT * q;
+        int j = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+        while (j * (j + 1) / 2 > t) --j;
+        while ((j + 1) * (j + 2) / 2 <= t) ++j;
+        const int i = t - j * (j + 1) / 2;
+        own[q] = j < bw ? make_int2(i, j) : make_int2(-1, -1);
+        if (j < bw) A[i][j] = Gin[i + (long)j * bw];
     }
     if (tid < bw) gd[tid] = Gin[tid + (long)tid * bw].x;
     if (tid == 0) s_cut = bw;
@@ -490,10 +500,11 @@ __global__ __launch_bounds__(CH_NT) void block_chol_kernel(const double2* __rest
         for (int j = c + 1 + tid; j < bw; j += CH_NT) A[c][j] = make_double2(A[c][j].x * ri, A[c][j].y * ri);
         if (tid == 0) A[c][c] = make_double2(rd[c], 0.0);
         __syncthreads();
-        const int w = bw - c - 1;
-        for (int e = tid; e < w * w; e += CH_NT) {
-            const int i = c + 1 + e % w, j = c + 1 + e / w;
-            if (i <= j) {
+        // the trailing triangle: each thread updates the entries it owns below row c
+#pragma unroll
+        for (int q = 0; q < CH_EPT; ++q) {
+            const int i = own[q].x, j = own[q].y;
+            if (i > c) {
                 const double2 a = A[c][i], b = A[c][j];
                 double2 t = A[i][j];
                 // t -= conj(a) b
