@@ -16,7 +16,9 @@ Bars (written below):
   the closed form mu + W(0.5 e^-mu) within 1e-9, residuals <= 1e-10;
 * a row range or column index out of bounds is reported (-2), not followed;
 * two-stage sampling on the CSR NEP equals the dense form: added points within 1e-8,
-  eigenvalues inside within 1e-9 of each other and of the closed form.
+  eigenvalues inside within 1e-9 of each other and of the closed form;
+* rows with unsorted and repeated entries (summed) and a term without entries: the
+  same bars for direct and iterative sampling.
 """
 import ctypes as C
 
@@ -222,3 +224,52 @@ def test_sparse_two_stage_equals_dense_form(R, ctx):
     ex = P.delay_eigs(W.laplacian_modes_nd((10, 10)))
     assert _match(la, ex) < 1e-9
     assert a["resid"][ins[0]].max() <= 1e-10
+
+
+def _shuffled_with_repeats(ip, ix, d, seed):
+    """The same matrix with every row's entries in a random order and each entry split into
+    two repeated (row, column) entries whose values add up to it."""
+    rng = np.random.default_rng(seed)
+    nip, nix, nd = [0], [], []
+    for i in range(ip.size - 1):
+        cols, vals = ix[ip[i]:ip[i + 1]], d[ip[i]:ip[i + 1]]
+        w = rng.uniform(0.2, 0.8, cols.size)
+        c2 = np.concatenate([cols, cols])
+        v2 = np.concatenate([vals * w, vals * (1.0 - w)])
+        order = rng.permutation(c2.size)
+        nix.extend(c2[order])
+        nd.extend(v2[order])
+        nip.append(len(nix))
+    return (np.asarray(nip, dtype=np.int32), np.asarray(nix, dtype=np.int32), np.asarray(nd, dtype=np.complex128))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sparse_repeated_unsorted_entries_and_empty_term(R, ctx, prec):
+    """Rows with unsorted, repeated entries (summed) and a term with no entries at all (nnz = 0):
+    direct and iterative sampling match the oracle, whose dense matrices sum the repeats."""
+    base = W.delay_laplacian_sparse((12, 12))
+    n = base.n
+    lap = _shuffled_with_repeats(*base.csr[0], seed=5900)
+    empty = (np.zeros(n + 1, dtype=np.int32), np.zeros(0, dtype=np.int32), np.zeros(0, dtype=np.complex128))
+    nep = W.SparseNEP("delay_lap_repeats", n, [lap, base.csr[1], base.csr[2], empty],
+                      base.terms + [W.term(3.0, 2)])
+    U = W.probes(n, 3, 5901)
+    z, _ = O.ellipse(-4.0, 0.75, 0.75, 6)
+    prob = O.Problem(nep)
+    assert np.array_equal(prob.T(z[0]), O.Problem(base).T(z[0])) or \
+        np.abs(prob.T(z[0]) - O.Problem(base).T(z[0])).max() <= 1e-12 * np.abs(O.Problem(base).T(z[0])).max()
+    dn = R.DeviceNEP(nep)
+    S, info, code = R.rsrr_sample(ctx, dn, z, U, prec=prec)
+    Ud, _ = R.colmajor(U)
+    Sg, ginfo, gcode = R.rsrr_sample_gmres(ctx, dn, z, Ud, [-4.0])
+    torch.cuda.synchronize()
+    assert code == R.RSRR_OK and gcode == R.RSRR_OK
+    Sh, Sgh = R.from_colmajor(S, n), R.from_colmajor(Sg, n)
+    for k, zk in enumerate(z):
+        Xo = O.solve_point(prob.T(zk), U)
+        X = Sh[:, 3 * k:3 * k + 3]
+        assert np.linalg.norm(X - Xo) <= 1e-10 * np.linalg.norm(Xo), k
+        T = prob.T(zk)
+        Xg = Sgh[:, 3 * k:3 * k + 3]
+        res = np.linalg.norm(U - T @ Xg, axis=0) / np.linalg.norm(U, axis=0)
+        assert ginfo[k]["converged"] == 1 and res.max() <= 1.5e-10, (k, res.max())
