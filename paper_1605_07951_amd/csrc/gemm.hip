@@ -251,6 +251,10 @@ __global__ __launch_bounds__(64 * WR * WC, (BR * BC <= 2) ? 512 / (64 * WR * WC)
     const int li = lane & 31, half = lane >> 5;
     const int wrow = i0 + wi * BR * 32, wcol = j0 + wj * BC * 32;
 
+    // alpha leaves the inner loop: the accumulators hold (beta / alpha) C + A B and
+    // are scaled by alpha once at the end (bitwise the same for alpha = +-1)
+    const bool prod = alpha != 0.f;
+    const float cs = prod ? beta / alpha : beta, os = prod ? alpha : 1.f;
     floatx16 t1[BR][BC], t2[BR][BC], t3[BR][BC];
 #pragma unroll
     for (int x = 0; x < BR; ++x)
@@ -262,9 +266,9 @@ __global__ __launch_bounds__(64 * WR * WC, (BR * BC <= 2) ? 512 / (64 * WR * WC)
                 const int j = wcol + y * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
                 float2 c = make_float2(0.f, 0.f);
                 if (beta != 0.f && i < M && j < N) c = Cb[i + (long)j * ldc];
-                t1[x][y][r] = beta * c.x;
+                t1[x][y][r] = cs * c.x;
                 t2[x][y][r] = 0.f;
-                t3[x][y][r] = beta * (c.x + c.y);
+                t3[x][y][r] = cs * (c.x + c.y);
             }
         }
 
@@ -321,7 +325,7 @@ __global__ __launch_bounds__(64 * WR * WC, (BR * BC <= 2) ? 512 / (64 * WR * WC)
         }
     };
 
-    const int nst = (K + CG_KT - 1) / CG_KT;
+    const int nst = prod ? (K + CG_KT - 1) / CG_KT : 0;
     if (nst > 0) {
         gload(0);
         sstore(0);
@@ -337,9 +341,9 @@ __global__ __launch_bounds__(64 * WR * WC, (BR * BC <= 2) ? 512 / (64 * WR * WC)
 #pragma unroll
             for (int x = 0; x < BR; ++x) {
                 const float2 av = *reinterpret_cast<const float2*>(&As[buf][k][2 * (wi * BR * 32 + x * 32 + li)]);
-                ar[x] = alpha * av.x;
-                ai[x] = alpha * av.y;
-                as[x] = alpha * (av.x + av.y);
+                ar[x] = av.x;
+                ai[x] = av.y;
+                as[x] = av.x + av.y;
             }
 #pragma unroll
             for (int y = 0; y < BC; ++y) {
@@ -371,8 +375,8 @@ __global__ __launch_bounds__(64 * WR * WC, (BR * BC <= 2) ? 512 / (64 * WR * WC)
             for (int r = 0; r < 16; ++r) {
                 const int j = wcol + y * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
                 if (j < N)
-                    Cb[i + (long)j * ldc] =
-                        make_float2(t1[x][y][r] - t2[x][y][r], t3[x][y][r] - t1[x][y][r] - t2[x][y][r]);
+                    Cb[i + (long)j * ldc] = make_float2(os * (t1[x][y][r] - t2[x][y][r]),
+                                                        os * (t3[x][y][r] - t1[x][y][r] - t2[x][y][r]));
             }
     }
 }
