@@ -80,7 +80,10 @@ __global__ __launch_bounds__(CG_NT, 2) void cgemm_mfma_kernel(
     const int li = lane & 31, half = lane >> 5;
     const int wrow = i0 + wi * BR * 32, wcol = j0 + wj * BC * 32;
 
-    // ---- prologue: acc = beta * C (output layout: lane li = row, reg r = column 8(r/4)+4 half+r%4) ----
+    // ---- prologue: acc = (beta / alpha) C, scaled by alpha once at the end (bitwise the same
+    // for alpha = +-1); output layout: lane li = row, reg r = column 8(r/4)+4 half+r%4 ----
+    const bool prod = alpha != 0.f;
+    const float cs = prod ? beta / alpha : beta, os = prod ? alpha : 1.f;
     floatx16 accR[BR][BC], accI[BR][BC];
 #pragma unroll
     for (int x = 0; x < BR; ++x)
@@ -92,8 +95,8 @@ __global__ __launch_bounds__(CG_NT, 2) void cgemm_mfma_kernel(
                 const int j = wcol + y * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
                 float2 c = make_float2(0.f, 0.f);
                 if (beta != 0.f && i < M && j < N) c = Cb[i + (long)j * ldc];
-                accR[x][y][r] = beta * c.x;
-                accI[x][y][r] = beta * c.y;
+                accR[x][y][r] = cs * c.x;
+                accI[x][y][r] = cs * c.y;
             }
         }
 
@@ -150,7 +153,7 @@ __global__ __launch_bounds__(CG_NT, 2) void cgemm_mfma_kernel(
         }
     };
 
-    const int nst = (K + CG_KT - 1) / CG_KT;
+    const int nst = prod ? (K + CG_KT - 1) / CG_KT : 0;
     if (nst > 0) {
         gload(0);
         sstore(0);
@@ -163,7 +166,7 @@ __global__ __launch_bounds__(CG_NT, 2) void cgemm_mfma_kernel(
         for (int k = 0; k < CG_KT; ++k) {
             float a[BR], br[BC], bi[BC];
 #pragma unroll
-            for (int x = 0; x < BR; ++x) a[x] = alpha * As[buf][k][2 * (wi * BR * 32 + x * 32 + li) + half];
+            for (int x = 0; x < BR; ++x) a[x] = As[buf][k][2 * (wi * BR * 32 + x * 32 + li) + half];
 #pragma unroll
             for (int y = 0; y < BC; ++y) {
                 const float2 bv = Bs[buf][k][wj * BC * 32 + y * 32 + li];
@@ -192,7 +195,7 @@ __global__ __launch_bounds__(CG_NT, 2) void cgemm_mfma_kernel(
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int j = wcol + y * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-                if (j < N) Cb[i + (long)j * ldc] = make_float2(accR[x][y][r], accI[x][y][r]);
+                if (j < N) Cb[i + (long)j * ldc] = make_float2(os * accR[x][y][r], os * accI[x][y][r]);
             }
     }
 }
@@ -422,6 +425,8 @@ __global__ __launch_bounds__(CG_NT) void cgemm_narrow_kernel(
     const int kc = g >> 1, part = g & 1;
     const int wrow = i0 + wave * BR * 16;
 
+    const bool prod = alpha != 0.f;   // alpha applied once at the end, as in the kernels above
+    const float cs = prod ? beta / alpha : beta, os = prod ? alpha : 1.f;
     floatx4 accR[BR], accI[BR];
 #pragma unroll
     for (int x = 0; x < BR; ++x) {
@@ -431,8 +436,8 @@ __global__ __launch_bounds__(CG_NT) void cgemm_narrow_kernel(
             const int j = 4 * g + r;
             float2 c = make_float2(0.f, 0.f);
             if (beta != 0.f && i < M && j < N) c = Cb[i + (long)j * ldc];
-            accR[x][r] = beta * c.x;
-            accI[x][r] = beta * c.y;
+            accR[x][r] = cs * c.x;
+            accI[x][r] = cs * c.y;
         }
     }
 
@@ -484,7 +489,7 @@ __global__ __launch_bounds__(CG_NT) void cgemm_narrow_kernel(
         }
     };
 
-    const int nst = (K + CG_KT - 1) / CG_KT;
+    const int nst = prod ? (K + CG_KT - 1) / CG_KT : 0;
     if (nst > 0) {
         gload(0);
         sstore(0);
@@ -498,7 +503,7 @@ __global__ __launch_bounds__(CG_NT) void cgemm_narrow_kernel(
             const int k = kk + kc;
             float a[BR];
 #pragma unroll
-            for (int x = 0; x < BR; ++x) a[x] = alpha * As[buf][k][2 * (wave * BR * 16 + x * 16 + li) + part];
+            for (int x = 0; x < BR; ++x) a[x] = As[buf][k][2 * (wave * BR * 16 + x * 16 + li) + part];
             const float2 bv = Bs[buf][k][li];
             const float br = part ? -bv.y : bv.x;
             const float bi = part ? bv.x : bv.y;
@@ -519,7 +524,7 @@ __global__ __launch_bounds__(CG_NT) void cgemm_narrow_kernel(
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int j = 4 * g + r;
-            if (j < N) Cb[i + (long)j * ldc] = make_float2(accR[x][r], accI[x][r]);
+            if (j < N) Cb[i + (long)j * ldc] = make_float2(os * accR[x][r], os * accI[x][r]);
         }
     }
 }
@@ -840,8 +845,11 @@ __global__ __launch_bounds__(ZG_NT, 2) void zgemm_mfma_kernel(
     const int li = lane & 15, kq = lane >> 4;       // kq = 2*kc + part
     const int kc = kq >> 1, part = kq & 1;
 
-    // acc = beta * C; lane li holds row i, register r holds column lane/16 + 4*r
+    // acc = (beta / alpha) C, scaled by alpha once at the end (bitwise the same for
+    // alpha = +-1); lane li holds row i, register r holds column lane/16 + 4*r
     // (the f64 MFMA interleaves its four output groups by register)
+    const bool prod = alpha != 0.0;
+    const double cs = prod ? beta / alpha : beta, os = prod ? alpha : 1.0;
     doublex4 accR[2][2], accI[2][2];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
@@ -853,8 +861,8 @@ __global__ __launch_bounds__(ZG_NT, 2) void zgemm_mfma_kernel(
                 const int j = j0 + wj * 32 + y * 16 + kq + 4 * r;
                 double2 c = make_double2(0.0, 0.0);
                 if (beta != 0.0 && i < M && j < N) c = Cb[i + (long)j * ldc];
-                accR[x][y][r] = beta * c.x;
-                accI[x][y][r] = beta * c.y;
+                accR[x][y][r] = cs * c.x;
+                accI[x][y][r] = cs * c.y;
             }
         }
 
@@ -907,7 +915,7 @@ __global__ __launch_bounds__(ZG_NT, 2) void zgemm_mfma_kernel(
 #pragma unroll
             for (int x = 0; x < 2; ++x) {
                 double2 av = As[buf][kk + kc][wi * 32 + x * 16 + li];
-                a[x] = alpha * (part ? av.y : av.x);
+                a[x] = part ? av.y : av.x;
             }
 #pragma unroll
             for (int y = 0; y < 2; ++y) {
@@ -925,7 +933,7 @@ __global__ __launch_bounds__(ZG_NT, 2) void zgemm_mfma_kernel(
         }
     };
 
-    const int nst = (K + ZG_KT - 1) / ZG_KT;
+    const int nst = prod ? (K + ZG_KT - 1) / ZG_KT : 0;
     if (nst > 0) {
         gload(0, ra0, rb0);
         sstore(0, ra0, rb0);
@@ -957,7 +965,7 @@ __global__ __launch_bounds__(ZG_NT, 2) void zgemm_mfma_kernel(
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int j = j0 + wj * 32 + y * 16 + kq + 4 * r;
-                if (j < N) Cb[i + (long)j * ldc] = make_double2(accR[x][y][r], accI[x][y][r]);
+                if (j < N) Cb[i + (long)j * ldc] = make_double2(os * accR[x][y][r], os * accI[x][y][r]);
             }
     }
 }
